@@ -1,0 +1,183 @@
+"""FP64 CPU oracle — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The product library never loads it, and it
+shares no code with the HIP path.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, single thread, no FP
+contraction); this module only marshals numpy arrays.  Every function states
+the definition it follows in ``oracle.c``: the CSR SpMV definition (the
+operator apply of Section 4.2 / the SpMV benchmark of Section 6.1), textbook
+Hestenes-Stiefel CG (the CG solver benchmarked in Section 6.2) with the
+Iteration / ResidualNorm(rhs_norm) criteria of the Section 3.5 configuration
+example, the nnz-balanced row partition and the Gershgorin condition bound.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# Stop reasons and CSR verdicts, as numbered in oracle.c.
+RUNNING, CONVERGED, MAX_ITERS, BREAKDOWN, NON_FINITE = 0, 1, 2, 3, 4
+CSR_OK, CSR_BAD_SIZE, CSR_BAD_FIRST, CSR_DECREASING, CSR_BAD_LAST, CSR_BAD_COLUMN = range(6)
+
+CFLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = False, src: str = _SRC, out: str = _LIB, extra=()) -> str:
+    """Compile oracle.c with gcc.  ``src``/``out``/``extra`` let tests build variants."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, *extra, src, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+class CGResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("stop_reason", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rhs_norm", ctypes.c_double),
+                ("implicit_resnorm", ctypes.c_double), ("true_resnorm", ctypes.c_double)]
+
+
+def load(path: str = _LIB):
+    vp, i64, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    lib = ctypes.CDLL(path)
+    lib.orc_csr_validate.restype = ctypes.c_int
+    lib.orc_csr_validate.argtypes = [i64, i64, i64, vp, vp]
+    lib.orc_spmv.restype = None
+    lib.orc_spmv.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.orc_spmv_abs.restype = None
+    lib.orc_spmv_abs.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.orc_residual.restype = None
+    lib.orc_residual.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    lib.orc_cg.restype = ctypes.c_int
+    lib.orc_cg.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_partition.restype = None
+    lib.orc_partition.argtypes = [i64, vp, i64, vp]
+    lib.orc_gershgorin_kappa.restype = f64
+    lib.orc_gershgorin_kappa.argtypes = [i64, vp, vp, vp]
+    return lib
+
+
+def _get():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = load(_LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr64(A):
+    return (np.ascontiguousarray(A.row_ptr, np.int64), np.ascontiguousarray(A.col, np.int64),
+            np.ascontiguousarray(A.val, np.float64))
+
+
+class Oracle:
+    """Bound oracle functions; ``lib`` may be a variant build (tests plant mistakes there)."""
+
+    def __init__(self, lib=None):
+        self.lib = lib if lib is not None else _get()
+
+    def csr_validate(self, n_rows, n_cols, nnz, row_ptr, col) -> int:
+        rp = np.ascontiguousarray(row_ptr, np.int64)
+        ci = np.ascontiguousarray(col, np.int64)
+        if rp.size < max(n_rows, 0) + 1:
+            raise ValueError("row_ptr must hold n_rows + 1 entries")
+        return int(self.lib.orc_csr_validate(n_rows, n_cols, nnz, _p(rp), _p(ci)))
+
+    def spmv(self, A, x) -> np.ndarray:
+        rp, ci, va = _csr64(A)
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.empty(A.n_rows, np.float64)
+        self.lib.orc_spmv(A.n_rows, _p(rp), _p(ci), _p(va), _p(x), _p(y))
+        return y
+
+    def spmv_abs(self, A, x) -> np.ndarray:
+        rp, ci, va = _csr64(A)
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.empty(A.n_rows, np.float64)
+        self.lib.orc_spmv_abs(A.n_rows, _p(rp), _p(ci), _p(va), _p(x), _p(y))
+        return y
+
+    def residual(self, A, b, x) -> np.ndarray:
+        rp, ci, va = _csr64(A)
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.ascontiguousarray(x, np.float64)
+        r = np.empty(A.n_rows, np.float64)
+        self.lib.orc_residual(A.n_rows, _p(rp), _p(ci), _p(va), _p(b), _p(x), _p(r))
+        return r
+
+    def cg(self, A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+        """Returns (x, CGResult, hist or None)."""
+        rp, ci, va = _csr64(A)
+        n = A.n_rows
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
+        res = CGResult()
+        hist = np.full(max_iters + 1, np.nan) if history else None
+        self.lib.orc_cg(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tau), int(max_iters),
+                        ctypes.byref(res), _p(hist))
+        if hist is not None:
+            hist = hist[: res.iterations + 1]
+        return x, res, hist
+
+    def partition(self, row_ptr, parts: int) -> np.ndarray:
+        rp = np.ascontiguousarray(row_ptr, np.int64)
+        split = np.empty(parts + 1, np.int64)
+        self.lib.orc_partition(rp.size - 1, _p(rp), parts, _p(split))
+        return split
+
+    def gershgorin_kappa(self, A) -> float:
+        rp, ci, va = _csr64(A)
+        return float(self.lib.orc_gershgorin_kappa(A.n_rows, _p(rp), _p(ci), _p(va)))
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default
+
+
+def spmv(A, x):
+    return default().spmv(A, x)
+
+
+def spmv_abs(A, x):
+    return default().spmv_abs(A, x)
+
+
+def residual(A, b, x):
+    return default().residual(A, b, x)
+
+
+def cg(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+    return default().cg(A, b, x0, tau, max_iters, history)
+
+
+def csr_validate(n_rows, n_cols, nnz, row_ptr, col):
+    return default().csr_validate(n_rows, n_cols, nnz, row_ptr, col)
+
+
+def partition(row_ptr, parts):
+    return default().partition(row_ptr, parts)
+
+
+def gershgorin_kappa(A):
+    return default().gershgorin_kappa(A)

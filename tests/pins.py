@@ -1,0 +1,297 @@
+"""Pins of the FP64 oracle to things other than itself.
+
+Every pin checks the oracle against mathematics or an independent library
+routine (dense numpy algebra, scipy.sparse, scipy's CG, numpy's
+searchsorted), never against a retyping of the oracle's own formula.  The
+pins are chosen so that a plausible mistake anywhere in the oracle (a dropped
+term, a wrong sign or index, a transposed quotient, an off-by-one in the
+iteration count or in a validation check) fails at least one of them;
+``test_oracle_mutants.py`` plants such mistakes in copies of the oracle and
+checks that.
+
+Each pin is a function ``pin_*(orc)`` that raises AssertionError on failure.
+Sizes are small so the whole battery runs in a couple of seconds.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import inputs
+
+U64 = 2.0 ** -53
+
+
+def gamma(m, u=U64):
+    """gamma_m = m u / (1 - m u) (Higham, Accuracy and Stability, Sec. 3.1)."""
+    mu = np.asarray(m, np.float64) * u
+    return mu / (1.0 - mu)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ----------------------------------------------------------------- SpMV
+def pin_spmv_dense_bruteforce(orc):
+    """Random rectangular CSR (n <= 64) vs dense numpy A @ x, within 2*gamma_m*(|A||x|)."""
+    for seed, (nr, nc) in enumerate([(17, 17), (40, 23), (64, 64), (5, 60)]):
+        A = inputs.dyadic_random(nr, nc, 7, seed)
+        A.val = A.val * np.array([inputs.unif(seed, 11, k) for k in range(A.val.size)])
+        x = np.array([inputs.unif(seed, 12, j) for j in range(nc)])
+        D = A.to_dense()
+        y = orc.spmv(A, x)
+        ref = D @ x
+        m = np.diff(A.row_ptr)
+        bound = 2 * gamma(np.maximum(m, 1)) * (np.abs(D) @ np.abs(x))
+        assert np.all(np.abs(y - ref) <= bound), "SpMV differs from dense brute force"
+        # the |A||x| helper is pinned too, against dense |A| @ |x|
+        sa = orc.spmv_abs(A, x)
+        assert np.all(np.abs(sa - np.abs(D) @ np.abs(x)) <= bound)
+
+
+def pin_spmv_dyadic_exact(orc):
+    """Dyadic values and small-integer x: every partial sum is exact, so bit-exact."""
+    A = inputs.dyadic_random(50, 37, 9, 3)
+    x = np.array([float((inputs.hash64(3, 13, j) % 17) - 8) for j in range(37)])
+    y = orc.spmv(A, x)
+    assert np.array_equal(y, A.to_dense() @ x)
+
+
+def pin_spmv_identity_permutation(orc):
+    x = np.array([inputs.unif(5, 14, j) for j in range(33)])
+    assert np.array_equal(orc.spmv(inputs.diagonal(np.ones(33)), x), x)
+    P = inputs.permutation(33, 2)
+    assert np.array_equal(orc.spmv(P, x), x[P.col.astype(np.int64)])
+
+
+def pin_spmv_duplicates_unsorted(orc):
+    """Unsorted columns and duplicate entries: duplicates are summed."""
+    A = inputs.CSR(3, 4, np.array([0, 3, 3, 6], np.int64), np.array([2, 0, 2, 3, 1, 0], np.int32),
+                   np.array([1.5, -2.0, 0.25, 4.0, 8.0, -1.0]))
+    x = np.array([1.0, 2.0, 4.0, -8.0])
+    assert np.array_equal(orc.spmv(A, x), np.array([1.5 * 4 - 2 + 0.25 * 4, 0.0, -32 + 16 - 1]))
+
+
+def pin_spmv_scipy_stencil(orc):
+    """stencil7 N=12 vs scipy.sparse csr_matrix @ x (independent code) within the gamma bound."""
+    import scipy.sparse as sp
+    A = inputs.stencil7(12, 0)
+    x = inputs.vec(A.n_rows, 0, 5)
+    S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n_rows, A.n_cols))
+    ref = S @ x
+    y = orc.spmv(A, x)
+    bound = 2 * gamma(np.diff(A.row_ptr)) * (abs(S) @ np.abs(x))
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+# ----------------------------------------------------------------- validation
+def pin_csr_validate(orc):
+    rp = np.array([0, 2, 3, 5], np.int64)
+    ci = np.array([0, 2, 1, 0, 2], np.int64)
+    assert orc.csr_validate(3, 3, 5, rp, ci) == 0
+    assert orc.csr_validate(-1, 3, 5, rp, ci) == 1
+    assert orc.csr_validate(3, 3, -5, rp, ci) == 1
+    assert orc.csr_validate(3, 3, 5, np.array([1, 2, 3, 5]), ci) == 2
+    assert orc.csr_validate(3, 3, 5, np.array([0, 3, 2, 5]), ci) == 3
+    assert orc.csr_validate(3, 3, 5, np.array([0, 2, 2, 5]), ci) == 0   # empty row is fine
+    assert orc.csr_validate(3, 3, 5, np.array([0, 2, 3, 4]), ci) == 4
+    assert orc.csr_validate(3, 3, 5, rp, np.array([0, 3, 1, 0, 2])) == 5  # col == n_cols
+    assert orc.csr_validate(3, 3, 5, rp, np.array([0, 2, -1, 0, 2])) == 5
+    assert orc.csr_validate(3, 3, 5, rp, np.array([0, 2, 1, 0, 2])) == 0
+    assert orc.csr_validate(0, 0, 0, np.array([0]), np.array([], np.int64)) == 0
+    # first failing check wins: decreasing AND bad column -> decreasing
+    assert orc.csr_validate(3, 3, 5, np.array([0, 3, 2, 5]), np.array([9, 9, 9, 9, 9])) == 3
+
+
+# ----------------------------------------------------------------- CG closed forms
+def pin_cg_identity(orc):
+    b = np.array([1.0, -2.0, 0.5, 3.0, -0.25])
+    x, r, _ = orc.cg(inputs.diagonal(np.ones(5)), b, tau=1e-14)
+    assert r.stop_reason == 1 and r.iterations == 1 and np.array_equal(x, b)
+
+
+def pin_cg_scaled_identity(orc):
+    b = np.array([inputs.unif(1, 15, i) for i in range(20)])
+    x, r, _ = orc.cg(inputs.diagonal(np.full(20, 4.0)), b, tau=1e-14)
+    assert r.iterations == 1 and r.stop_reason == 1 and np.array_equal(x, b / 4.0)
+    assert r.implicit_resnorm == 0.0 and r.rhs_norm == np.linalg.norm(b)
+
+
+def pin_cg_diag_distinct(orc):
+    """m distinct eigenvalues: exact Krylov termination after m iterations, not before."""
+    d = np.repeat(np.array([1.0, 2.0, 3.5, 5.0, 9.0]), 4)
+    b = np.array([1.0 + (i % 3) for i in range(d.size)])
+    _, r5, _ = orc.cg(inputs.diagonal(d), b, tau=0.0, max_iters=5)
+    assert r5.true_resnorm <= 1e-12 * np.linalg.norm(b)
+    _, r4, _ = orc.cg(inputs.diagonal(d), b, tau=0.0, max_iters=4)
+    assert r4.iterations == 4 and r4.true_resnorm > 1e-6
+
+
+def pin_cg_laplacian1d(orc):
+    """tridiag(-1,2,-1) x = 1 has x_i = i(n+1-i)/2 (i = 1..n)."""
+    n = 31
+    i = np.arange(1, n + 1, dtype=np.float64)
+    xs = i * (n + 1 - i) / 2
+    x, r, _ = orc.cg(inputs.laplacian1d(n), np.ones(n), tau=1e-15, max_iters=n)
+    assert r.stop_reason == 1 and r.iterations <= n
+    assert _rel(x, xs) <= 1e-13
+
+
+def pin_cg_dense_solve(orc):
+    """Tiny random SPD systems vs dense numpy.linalg.solve, within kappa * 1e-14."""
+    for seed in range(3):
+        A = inputs.randsym(40, seed, delta=0.05)
+        b = inputs.rhs(40, seed)
+        D = A.to_dense()
+        xs = np.linalg.solve(D, b)
+        kappa = np.linalg.cond(D)
+        x, r, _ = orc.cg(A, b, tau=1e-15, max_iters=400)
+        assert r.stop_reason == 1
+        assert _rel(x, xs) <= max(kappa, 1.0) * 1e-14
+
+
+def pin_cg_krylov_minimiser(orc):
+    """x_k (x0 = 0) minimises ||x - x*||_A over K_k(A, b): checks every iterate, not just the end."""
+    A = inputs.randsym(24, 7, delta=0.3)
+    D = A.to_dense()
+    b = inputs.rhs(24, 7)
+    K = np.empty((24, 6))
+    v = b.copy()
+    for k in range(6):
+        K[:, k] = v
+        v = D @ v
+    for k in range(1, 7):
+        Q, _ = np.linalg.qr(K[:, :k])
+        y = np.linalg.solve(Q.T @ D @ Q, Q.T @ b)
+        xk_ref = Q @ y
+        xk, r, _ = orc.cg(A, b, tau=0.0, max_iters=k)
+        assert r.iterations == k
+        assert _rel(xk, xk_ref) <= 1e-10, "iterate %d off the Krylov minimiser" % k
+
+
+def pin_cg_history_true_residual(orc):
+    """Recorded ||r_k|| tracks ||b - A x_k|| (recomputed densely) at every early k."""
+    A = inputs.randsym(30, 9, delta=0.5)
+    D = A.to_dense()
+    b = inputs.rhs(30, 9)
+    _, _, hist = orc.cg(A, b, tau=0.0, max_iters=8, history=True)
+    assert hist.size == 9 and hist[0] == np.linalg.norm(b)
+    for k in range(1, 9):
+        xk, _, _ = orc.cg(A, b, tau=0.0, max_iters=k)
+        assert abs(hist[k] - np.linalg.norm(b - D @ xk)) <= 1e-12 * np.linalg.norm(b)
+
+
+def pin_cg_scipy(orc):
+    """scipy.sparse.linalg.cg (independent code, same ||r|| <= tau ||b|| criterion)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    for A in (inputs.stencil7(10, 0), inputs.randsym(2000, 3)):
+        b = inputs.rhs(A.n_rows, 0)
+        S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n_rows, A.n_cols))
+        count = [0]
+
+        def cb(_xk):
+            count[0] += 1
+        tau = 1e-10
+        xs, info = spla.cg(S, b, rtol=tau, atol=0.0, maxiter=2000, callback=cb)
+        assert info == 0
+        x, r, _ = orc.cg(A, b, tau=tau, max_iters=2000)
+        kappa_g = orc.gershgorin_kappa(A)
+        assert r.stop_reason == 1 and abs(r.iterations - count[0]) <= 2
+        assert _rel(x, xs) <= 2 * kappa_g * tau
+
+
+def pin_cg_energy_monotone_chebyshev(orc):
+    """||x_k - x*||_A is non-increasing and within the Chebyshev bound with kappa_G."""
+    A = inputs.randsym(60, 11, delta=0.5)
+    D = A.to_dense()
+    b = inputs.rhs(60, 11)
+    xs = np.linalg.solve(D, b)
+    kappa = orc.gershgorin_kappa(A)
+    rate = (math.sqrt(kappa) - 1) / (math.sqrt(kappa) + 1)
+    e0 = math.sqrt(xs @ D @ xs)
+    prev = e0
+    for k in range(1, 16):
+        xk, _, _ = orc.cg(A, b, tau=0.0, max_iters=k)
+        e = xk - xs
+        ek = math.sqrt(max(e @ D @ e, 0.0))
+        assert ek <= prev * (1 + 1e-9) + 1e-14 * e0
+        assert ek <= 2 * rate ** k * e0 * (1 + 1e-9) + 1e-14 * e0
+        prev = ek
+
+
+# ----------------------------------------------------------------- stop semantics
+def pin_cg_stop_semantics(orc):
+    A = inputs.diagonal(np.array([2.0, 3.0, 5.0]))
+    b = np.array([1.0, 1.0, 1.0])
+    x0 = np.array([0.5, -1.0, 7.0])
+    x, r, h = orc.cg(A, b, x0=x0, tau=1e-12, max_iters=0, history=True)
+    assert r.stop_reason == 2 and r.iterations == 0 and np.array_equal(x, x0)
+    assert h.size == 1 and h[0] == np.linalg.norm(b - A.to_dense() @ x0)
+    # b = 0: x = 0, converged, no iteration (even with a nonzero guess)
+    x, r, _ = orc.cg(A, np.zeros(3), x0=x0, tau=1e-12, max_iters=10)
+    assert r.stop_reason == 1 and r.iterations == 0 and np.array_equal(x, np.zeros(3))
+    # exact initial guess: converged before the first iteration
+    xs = np.array([0.5, 1.0 / 3.0, 0.2])
+    x, r, _ = orc.cg(A, b, x0=xs, tau=1e-12, max_iters=10)
+    assert r.stop_reason == 1 and r.iterations == 0
+    # iteration cap reached exactly
+    x, r, _ = orc.cg(inputs.laplacian1d(20), np.ones(20), tau=1e-15, max_iters=3)
+    assert r.stop_reason == 2 and r.iterations == 3
+    # the relative criterion uses ||b||: scaling b scales nothing else
+    _, r1, _ = orc.cg(inputs.laplacian1d(20), np.ones(20), tau=1e-6, max_iters=100)
+    _, r2, _ = orc.cg(inputs.laplacian1d(20), 1024.0 * np.ones(20), tau=1e-6, max_iters=100)
+    assert r1.iterations == r2.iterations and r1.stop_reason == 1
+    # a loose tolerance stops early: the test compares against tau * ||b||, not tau
+    R = inputs.randsym(200, 5, delta=0.2)
+    bb = 1e6 * inputs.rhs(200, 5)
+    _, r3, _ = orc.cg(R, bb, tau=1e-3, max_iters=500)
+    _, r4, _ = orc.cg(R, bb, tau=1e-9, max_iters=500)
+    assert r3.stop_reason == 1 and r4.stop_reason == 1 and r3.iterations < r4.iterations
+    assert r3.implicit_resnorm <= 1e-3 * np.linalg.norm(bb) < r3.implicit_resnorm * 1e4
+
+
+def pin_cg_breakdown_nonfinite(orc):
+    # indefinite: p.q = 1 - 2 < 0 on the first step
+    _, r, _ = orc.cg(inputs.diagonal(np.array([1.0, -2.0])), np.array([1.0, 1.0]), tau=1e-12)
+    assert r.stop_reason == 3 and r.iterations == 0
+    # p.q == 0 exactly
+    _, r, _ = orc.cg(inputs.diagonal(np.array([1.0, -1.0])), np.array([1.0, 1.0]), tau=1e-12)
+    assert r.stop_reason == 3
+    b = np.ones(4)
+    b[2] = np.nan
+    _, r, _ = orc.cg(inputs.diagonal(np.ones(4)), b, tau=1e-12)
+    assert r.stop_reason == 4
+    A = inputs.diagonal(np.array([1.0, np.inf, 1.0]))
+    _, r, _ = orc.cg(A, np.ones(3), tau=1e-12)
+    assert r.stop_reason == 4
+
+
+# ----------------------------------------------------------------- partition, kappa
+def pin_partition(orc):
+    for rp in (inputs.stencil7(5, 0).row_ptr, inputs.randsym(300, 2).row_ptr,
+               np.array([0, 0, 0, 5, 5, 9, 9, 9, 20, 20, 20], np.int64),
+               np.array([0, 0, 0], np.int64)):
+        n = rp.size - 1
+        nnz = int(rp[-1])
+        for P in (1, 2, 3, 7, 64, 1000):
+            s = orc.partition(rp, P)
+            targets = np.array([(j * nnz) // P for j in range(P)], np.int64)
+            ref = np.searchsorted(rp, targets, side="left")
+            assert np.array_equal(s[:P], ref) and s[P] == n
+
+
+def pin_gershgorin(orc):
+    d = np.array([2.0, 8.0, 0.5, 3.0])
+    assert orc.gershgorin_kappa(inputs.diagonal(d)) == 16.0
+    for seed in range(3):
+        A = inputs.randsym(30, seed, delta=0.2)
+        ev = np.linalg.eigvalsh(A.to_dense())
+        kg = orc.gershgorin_kappa(A)
+        assert ev[0] > 0 and ev[-1] / ev[0] <= kg * (1 + 1e-12)
+    assert math.isinf(orc.gershgorin_kappa(inputs.laplacian1d(5)))   # only weakly dominant
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
