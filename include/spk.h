@@ -1,0 +1,212 @@
+/*
+ * spk — sparse Krylov solves on one MI355X (gfx950), C ABI.
+ *
+ * The operation: a CSR sparse matrix A applied to a vector (SpMV, y = A x;
+ * the operator apply of the paper's Section 4.2, benchmarked as a matrix
+ * times a random vector in Section 6.1), and an unpreconditioned conjugate
+ * gradient solve of A x = b (the CG solver of Section 6.2), stopped by an
+ * iteration cap or by ||r|| <= reduction_factor * ||b|| (the "Iteration" and
+ * "ResidualNorm" criteria with baseline rhs_norm of the configuration example
+ * in Section 3.5, Listing 2).  The solution overwrites the initial guess and
+ * a log reports convergence (Section 3.5, around Listing 1).  Value types
+ * half/float/double and index types int32/int64 follow Table 1.
+ *
+ * Conventions for every entry point:
+ *  - All matrix and vector pointers are DEVICE pointers owned by the caller.
+ *    A plan borrows the CSR arrays until spk_free; the caller must not free
+ *    or modify them meanwhile.  A plan owns only what it derives (workspace,
+ *    low-precision value copies, tuning results).
+ *  - Work is enqueued on the context's HIP stream.  spk_execute_* return
+ *    after the work has finished (the log is then valid) unless stated.
+ *  - Functions never abort and never throw; they return a status.  On error
+ *    spk_last_error(ctx) gives a message.  Non-convergence is NOT an error:
+ *    it is reported in spk_log.stop_reason.
+ *  - Handles are not thread-safe: one host thread per context at a time.
+ */
+#ifndef SPK_H
+#define SPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPK_OK = 0,
+    SPK_ERR_INVALID_ARG = 1,   /* null pointer, bad size, malformed CSR, dtype mismatch */
+    SPK_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+    SPK_ERR_OUT_OF_MEMORY = 3, /* device or pinned-host allocation failed */
+    SPK_ERR_BUDGET = 4,        /* request exceeds a configured memory budget */
+    SPK_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+    SPK_ERR_INTERNAL = 6
+} spk_status;
+
+/* Value types (Table 1 plus bfloat16 storage). */
+typedef enum { SPK_F64 = 0, SPK_F32 = 1, SPK_F16 = 2, SPK_BF16 = 3 } spk_dtype;
+/* Index types (Table 1).  row_ptr and col_idx types are independent. */
+typedef enum { SPK_I32 = 0, SPK_I64 = 1 } spk_itype;
+
+/* CSR well-formedness verdicts, in the order the checks are applied; the
+ * first failing check is reported. */
+typedef enum {
+    SPK_CSR_OK = 0,
+    SPK_CSR_BAD_SIZE = 1,    /* negative n_rows, n_cols or nnz */
+    SPK_CSR_BAD_FIRST = 2,   /* row_ptr[0] != 0 */
+    SPK_CSR_DECREASING = 3,  /* row_ptr[i+1] < row_ptr[i] for some i */
+    SPK_CSR_BAD_LAST = 4,    /* row_ptr[n_rows] != nnz */
+    SPK_CSR_BAD_COLUMN = 5   /* some col_idx outside [0, n_cols) */
+} spk_csr_verdict;
+
+/* Why a solve stopped (spk_log.stop_reason). */
+typedef enum {
+    SPK_STOP_RUNNING = 0,
+    SPK_STOP_CONVERGED = 1,   /* ||r_k|| <= reduction_factor * ||b||, or b = 0 (then x = 0) */
+    SPK_STOP_MAX_ITERS = 2,   /* k == max_iters */
+    SPK_STOP_BREAKDOWN = 3,   /* p.Ap <= 0: A is not positive definite along p */
+    SPK_STOP_NON_FINITE = 4   /* a NaN or Inf appeared in a norm or inner product */
+} spk_stop_reason;
+
+typedef enum { SPK_SOLVER_CG = 0 } spk_solver;
+typedef enum {
+    SPK_PREC_FP64 = 0,        /* FP64 values, vectors and reductions */
+    SPK_PREC_MIXED_FP32 = 1,  /* FP32 inner CG (FP64 reductions) + FP64 iterative refinement */
+    SPK_PREC_MIXED_BF16 = 2   /* BF16 matrix values in the inner CG, otherwise as MIXED_FP32 */
+} spk_precision;
+typedef enum { SPK_BASELINE_RHS_NORM = 0 } spk_baseline;
+typedef enum { SPK_PRECOND_NONE = 0 } spk_precond;
+typedef enum {
+    SPK_EXEC_AUTO = 0,        /* the plan's autotuner picks */
+    SPK_EXEC_HOST_LOOP = 1,   /* kernels launched from a host loop, status polled per chunk */
+    SPK_EXEC_GRAPH = 2        /* chunks of iterations replayed from a captured HIP graph */
+} spk_exec_mode;
+
+typedef struct spk_ctx_s *spk_ctx;
+typedef struct spk_plan_s *spk_plan;
+
+/* A CSR matrix in device memory.  row_ptr has n_rows + 1 entries of
+ * ptr_type; col_idx and values have nnz entries of idx_type / val_type.
+ * Columns within a row may be unsorted; duplicate entries are summed. */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    int32_t ptr_type, idx_type, val_type, reserved;
+    const void *row_ptr;
+    const void *col_idx;
+    const void *values;
+} spk_csr;
+
+/* Solver configuration; spk_solver_cfg_default fills the defaults noted. */
+typedef struct {
+    int32_t solver;            /* SPK_SOLVER_CG */
+    int32_t precision;         /* SPK_PREC_FP64 */
+    int32_t baseline;          /* SPK_BASELINE_RHS_NORM */
+    int32_t precond;           /* SPK_PRECOND_NONE */
+    int64_t max_iters;         /* "Iteration" criterion; 1000 (Listings 1-2) */
+    double reduction_factor;   /* "ResidualNorm" criterion; 1e-6 (Listings 1-2) */
+    int32_t exec_mode;         /* SPK_EXEC_AUTO */
+    int32_t chunk_iters;       /* iterations per status poll / graph replay; 0 = auto */
+    int32_t record_history;    /* 1: keep ||r_k|| for k = 0..iterations */
+    int32_t true_residual;     /* 1: recompute ||b - A x|| at exit (default 1) */
+    double inner_reduction;    /* mixed: inner CG reduction factor (default 1e-4) */
+    int64_t max_outer;         /* mixed: refinement step cap (default 50) */
+    int64_t reserved[4];
+} spk_solver_cfg;
+
+/* What a solve did (the paper's logger). */
+typedef struct {
+    int64_t iterations;        /* CG updates performed (inner updates summed for mixed) */
+    int64_t outer_iterations;  /* refinement steps (mixed), else 0 */
+    double implicit_resnorm;   /* ||r_k|| of the recurrence residual at exit */
+    double true_resnorm;       /* ||b - A x|| recomputed in FP64 at exit (NaN if not computed) */
+    double rhs_norm;           /* ||b|| */
+    int32_t converged;         /* stop_reason == SPK_STOP_CONVERGED */
+    int32_t stop_reason;       /* spk_stop_reason */
+    double elapsed_ms;         /* device time of the execute call (HIP events) */
+} spk_log;
+
+/* Tuning decisions a plan made (for reports and tests). */
+typedef struct {
+    int32_t spmv_kernel;       /* 0 = LDS-staged row tiles, 1 = lanes-per-row vector kernel */
+    int32_t lanes;             /* lanes per row of the vector kernel */
+    int32_t grid;              /* SpMV workgroups */
+    int32_t xcd_remap;         /* 1 = tiles grouped per XCD */
+    int32_t exec_mode;         /* resolved spk_exec_mode */
+    int32_t chunk_iters;       /* resolved chunk size */
+    int32_t tuned;             /* 1 = chosen by timing candidates, 0 = heuristic/cached */
+    int32_t reserved;
+    double spmv_ms;            /* measured time of the chosen SpMV (0 if not tuned) */
+} spk_plan_info;
+
+/* Fill cfg with the defaults documented in spk_solver_cfg. */
+void spk_solver_cfg_default(spk_solver_cfg *cfg);
+
+/* Create a context on HIP device device_id that enqueues on hip_stream
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * handle.  Errors: INVALID_ARG (out NULL, bad device), DEVICE. */
+spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out);
+
+/* Destroy a context.  All its plans must have been freed.  NULL is a no-op. */
+spk_status spk_finalize(spk_ctx ctx);
+
+/* Message for the last error on this context (never NULL). */
+const char *spk_last_error(spk_ctx ctx);
+
+/* Static name of a status code. */
+const char *spk_status_string(spk_status s);
+
+/* Validate a device CSR matrix (row_ptr, col_idx) on the GPU.  *verdict
+ * receives an spk_csr_verdict.  Returns OK whatever the verdict; INVALID_ARG
+ * only for null handle/pointers or unknown index types. */
+spk_status spk_csr_check(spk_ctx ctx, const spk_csr *A, int32_t *verdict);
+
+/* nnz-balanced row partition into parts pieces, computed on the GPU:
+ *   split[j] = min { i : row_ptr[i] >= floor(j * nnz / parts) } (j < parts),
+ *   split[parts] = n_rows.
+ * split_dev is a device array of parts + 1 int64.  A must be valid. */
+spk_status spk_partition(spk_ctx ctx, const spk_csr *A, int64_t parts, int64_t *split_dev);
+
+/* Plan y = A x.  Validates A (INVALID_ARG if malformed) and picks the SpMV
+ * kernel.  x and y have val_type F64 -> FP64, else FP32 (F16/BF16 values are
+ * widened to FP32; accumulation is in the vector type). */
+spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out);
+
+/* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
+ * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
+ * an FP32/BF16 copy for the inner solve) or F32 values (taken as exact).
+ * Errors: INVALID_ARG, UNSUPPORTED (options this build lacks), OUT_OF_MEMORY. */
+spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg, spk_plan *out);
+
+/* y = A x with the plan's matrix; x has n_cols entries, y has n_rows. */
+spk_status spk_execute_spmv(spk_plan plan, const void *x, void *y);
+
+/* Solve A x = b.  b (n entries, FP64) is read; x (n entries, FP64) holds the
+ * initial guess on entry and the last iterate on exit.  log may be NULL. */
+spk_status spk_execute_solve(spk_plan plan, const void *b, void *x, spk_log *log);
+
+/* Copy the residual-norm history of the last solve (needs record_history):
+ * up to cap values into host array out; *count receives iterations + 1. */
+spk_status spk_plan_history(spk_plan plan, double *out, int64_t cap, int64_t *count);
+
+/* Report the plan's tuning decisions. */
+spk_status spk_plan_get_info(spk_plan plan, spk_plan_info *info);
+
+/* Per-kernel timing: when on, every launch of the plan's dominant SpMV
+ * kernel is bracketed by HIP events on the context stream; stats return the
+ * summed device time (ms) and launch count since the last reset. */
+spk_status spk_plan_set_profiling(spk_plan plan, int32_t on);
+spk_status spk_plan_kernel_stats(spk_plan plan, double *total_ms, int64_t *launches);
+
+/* Release a plan and everything it derived.  NULL is a no-op. */
+spk_status spk_free(spk_plan plan);
+
+/* Plain device-to-device copy of bytes (multiple of 16, 16-byte aligned
+ * pointers) with the library's streaming copy kernel; *ms receives its
+ * device time.  Used to measure the achievable HBM bandwidth. */
+spk_status spk_stream_copy(spk_ctx ctx, const void *src, void *dst, size_t bytes, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPK_H */

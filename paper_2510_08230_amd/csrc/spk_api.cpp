@@ -1,0 +1,741 @@
+// Host runtime behind the spk C ABI (include/spk.h): contexts, plans,
+// validation, the SpMV autotuner, and the CG driver (host-loop or
+// graph-replayed chunks of iterations with a convergence-rate-predicted
+// chunk size).  All GPU work goes through the launchers in spk_kernels.hip.
+#include "spk.h"
+#include "spk_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using spk::CsrDev;
+using spk::SolveState;
+using spk::SpmvTune;
+
+namespace {
+
+struct TuneKey {
+    int64_t n_rows, n_cols, nnz;
+    int pt, it, vt;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(n_rows, n_cols, nnz, pt, it, vt) < std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt);
+    }
+};
+
+struct TuneResult {
+    SpmvTune tune;
+    double ms;
+};
+
+}  // namespace
+
+struct spk_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+    int num_cu = 0;
+    std::string err;
+    unsigned *d_flags = nullptr;
+    unsigned *h_flags = nullptr;        // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::map<TuneKey, TuneResult> tune_cache;
+    int live_plans = 0;
+};
+
+struct spk_plan_s {
+    spk_ctx ctx = nullptr;
+    int kind = 0;                        // 0 = SpMV, 1 = solve
+    CsrDev A{};
+    spk_solver_cfg cfg{};
+    SpmvTune tune{};
+    int vec_grid = 1;
+    spk_plan_info info{};
+    double *r = nullptr, *p = nullptr, *q = nullptr, *partials = nullptr, *hist = nullptr;
+    int64_t hist_cap = 0;
+    SolveState *st = nullptr;
+    SolveState *h_st = nullptr;          // pinned mirror
+    std::map<int, hipGraphExec_t> graphs;
+    int profiling = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    int64_t prof_count = 0;
+};
+
+namespace {
+
+spk_status fail(spk_ctx ctx, spk_status code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+spk_status hip_fail(spk_ctx ctx, hipError_t e, const char *what) {
+    const spk_status code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SPK_ERR_OUT_OF_MEMORY
+                                                                                         : SPK_ERR_DEVICE;
+    return fail(ctx, code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SPK_HIP(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+bool valid_itype(int t) { return t == SPK_I32 || t == SPK_I64; }
+bool valid_dtype(int t) { return t >= SPK_F64 && t <= SPK_BF16; }
+
+// Host-side argument checks that need no device access.
+spk_status check_csr_args(spk_ctx ctx, const spk_csr *A) {
+    if (!A) return fail(ctx, SPK_ERR_INVALID_ARG, "null matrix descriptor");
+    if (!valid_itype(A->ptr_type) || !valid_itype(A->idx_type))
+        return fail(ctx, SPK_ERR_INVALID_ARG, "unknown index type");
+    if (!valid_dtype(A->val_type)) return fail(ctx, SPK_ERR_INVALID_ARG, "unknown value type");
+    if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return SPK_OK;   // reported as a verdict
+    if (!A->row_ptr) return fail(ctx, SPK_ERR_INVALID_ARG, "row_ptr is null");
+    if (A->nnz > 0 && (!A->col_idx || !A->values)) return fail(ctx, SPK_ERR_INVALID_ARG, "col_idx/values null");
+    return SPK_OK;
+}
+
+CsrDev to_dev(const spk_csr *A) {
+    CsrDev d;
+    d.n_rows = A->n_rows;
+    d.n_cols = A->n_cols;
+    d.nnz = A->nnz;
+    d.ptr_t = A->ptr_type;
+    d.idx_t = A->idx_type;
+    d.val_t = A->val_type;
+    d.rp = A->row_ptr;
+    d.ci = A->col_idx;
+    d.va = A->values;
+    return d;
+}
+
+size_t vec_bytes(int val_t) { return val_t == SPK_F64 ? 8 : 4; }
+
+spk_status gpu_verdict(spk_ctx ctx, const spk_csr *A, int32_t *verdict) {
+    if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) {
+        *verdict = SPK_CSR_BAD_SIZE;
+        return SPK_OK;
+    }
+    const CsrDev d = to_dev(A);
+    SPK_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(unsigned), ctx->stream));
+    SPK_HIP(ctx, spk::launch_validate(d, ctx->d_flags, ctx->stream));
+    SPK_HIP(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const unsigned f = *ctx->h_flags;
+    int32_t v = SPK_CSR_OK;
+    if (f & spk::VFLAG_BAD_FIRST) v = SPK_CSR_BAD_FIRST;
+    else if (f & spk::VFLAG_DECREASING) v = SPK_CSR_DECREASING;
+    else if (f & spk::VFLAG_BAD_LAST) v = SPK_CSR_BAD_LAST;
+    else if (f & spk::VFLAG_BAD_COLUMN) v = SPK_CSR_BAD_COLUMN;
+    if (v == SPK_CSR_OK && A->ptr_type == SPK_I32 && A->nnz > INT32_MAX) v = SPK_CSR_BAD_LAST;
+    *verdict = v;
+    return SPK_OK;
+}
+
+const char *verdict_name(int32_t v) {
+    switch (v) {
+        case SPK_CSR_BAD_SIZE: return "negative size";
+        case SPK_CSR_BAD_FIRST: return "row_ptr[0] != 0";
+        case SPK_CSR_DECREASING: return "row_ptr decreases";
+        case SPK_CSR_BAD_LAST: return "row_ptr[n_rows] != nnz";
+        case SPK_CSR_BAD_COLUMN: return "column index out of range";
+        default: return "ok";
+    }
+}
+
+// ------------------------------------------------------------------ tuning
+int64_t num_tiles(int64_t n) { return (n + spk::kTileRows - 1) / spk::kTileRows; }
+
+SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap) {
+    SpmvTune t{kind, lanes_log2, 1, remap};
+    const int bpc = spk::spmv_blocks_per_cu(A, t);
+    int64_t g = static_cast<int64_t>(ctx->num_cu) * bpc;
+    g = std::min<int64_t>(g, spk::kMaxGrid);
+    g = std::min<int64_t>(g, std::max<int64_t>(num_tiles(A.n_rows), 1));
+    t.grid = static_cast<int>(std::max<int64_t>(g, 1));
+    return t;
+}
+
+SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
+    const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
+    if (mean <= 16.0) return make_tune(ctx, A, 0, 0, 1);
+    int l2 = 0;
+    while ((1 << l2) < mean && l2 < 6) ++l2;
+    return make_tune(ctx, A, 1, l2, 1);
+}
+
+// Times each candidate on y = A x and keeps the fastest.  x, y: device
+// vectors of the plan's vector type (contents irrelevant for timing).
+spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneResult *out) {
+    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t};
+    auto hit = ctx->tune_cache.find(key);
+    if (hit != ctx->tune_cache.end()) {
+        *out = hit->second;
+        return SPK_OK;
+    }
+    std::vector<SpmvTune> cands;
+    cands.push_back(make_tune(ctx, A, 0, 0, 1));
+    cands.push_back(make_tune(ctx, A, 0, 0, 0));
+    const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
+    for (int l2 = 0; l2 <= 6; ++l2) {
+        const double L = static_cast<double>(1 << l2);
+        if (L > 4.0 * std::max(mean, 1.0) && l2 > 0) break;
+        cands.push_back(make_tune(ctx, A, 1, l2, 1));
+    }
+    TuneResult best{cands[0], 1e30};
+    for (const SpmvTune &t : cands) {
+        SPK_HIP(ctx, spk::launch_spmv(A, t, x, y, ctx->stream));   // warm-up
+        SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+        const int reps = 5;
+        for (int i = 0; i < reps; ++i) SPK_HIP(ctx, spk::launch_spmv(A, t, x, y, ctx->stream));
+        SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+        SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        SPK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        const double per = ms / reps;
+        if (per < best.ms) best = TuneResult{t, per};
+    }
+    ctx->tune_cache[key] = best;
+    *out = best;
+    return SPK_OK;
+}
+
+// SPK_SPMV_KERNEL forces a tiling (tests use it to cover each one):
+// "stream", "stream-noremap" or "vector:<lanes>" (lanes a power of two <= 64).
+bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
+    const char *env = std::getenv("SPK_SPMV_KERNEL");
+    if (!env || !*env) return false;
+    const std::string v(env);
+    if (v == "stream") {
+        *t = make_tune(ctx, A, 0, 0, 1);
+        return true;
+    }
+    if (v == "stream-noremap") {
+        *t = make_tune(ctx, A, 0, 0, 0);
+        return true;
+    }
+    if (v.rfind("vector:", 0) == 0) {
+        const int lanes = std::atoi(v.c_str() + 7);
+        int l2 = 0;
+        while ((1 << l2) < lanes && l2 < 6) ++l2;
+        *t = make_tune(ctx, A, 1, l2, 1);
+        return true;
+    }
+    return false;
+}
+
+spk_status choose_tune(spk_plan pl, const void *x, void *y) {
+    spk_ctx ctx = pl->ctx;
+    const CsrDev &A = pl->A;
+    if (A.n_rows == 0) {
+        pl->tune = SpmvTune{0, 0, 1, 0};
+        pl->info.tuned = 0;
+        return SPK_OK;
+    }
+    if (forced_tune(ctx, A, &pl->tune)) {
+        pl->info.tuned = 0;
+    } else if (A.nnz >= 100000) {
+        TuneResult tr;
+        spk_status s = autotune(ctx, A, x, y, &tr);
+        if (s != SPK_OK) return s;
+        pl->tune = tr.tune;
+        pl->info.tuned = 1;
+        pl->info.spmv_ms = tr.ms;
+    } else {
+        pl->tune = heuristic_tune(ctx, A);
+        pl->info.tuned = 0;
+    }
+    pl->info.spmv_kernel = pl->tune.kind;
+    pl->info.lanes = 1 << pl->tune.lanes_log2;
+    pl->info.grid = pl->tune.grid;
+    pl->info.xcd_remap = pl->tune.xcd_remap;
+    return SPK_OK;
+}
+
+// ------------------------------------------------------------------ profiling events
+spk_status prof_begin(spk_plan pl, hipEvent_t *end_ev) {
+    *end_ev = nullptr;
+    if (!pl->profiling) return SPK_OK;
+    if (pl->ev_used == pl->ev_pool.size()) {
+        hipEvent_t a, b;
+        SPK_HIP(pl->ctx, hipEventCreate(&a));
+        SPK_HIP(pl->ctx, hipEventCreate(&b));
+        pl->ev_pool.emplace_back(a, b);
+    }
+    auto &pr = pl->ev_pool[pl->ev_used++];
+    SPK_HIP(pl->ctx, hipEventRecord(pr.first, pl->ctx->stream));
+    *end_ev = pr.second;
+    return SPK_OK;
+}
+
+spk_status prof_end(spk_plan pl, hipEvent_t end_ev) {
+    if (end_ev) SPK_HIP(pl->ctx, hipEventRecord(end_ev, pl->ctx->stream));
+    return SPK_OK;
+}
+
+// Accumulate the first `useful` recorded launches (stream already synchronised).
+spk_status prof_collect(spk_plan pl, int64_t useful) {
+    const size_t n = std::min<size_t>(pl->ev_used, static_cast<size_t>(std::max<int64_t>(useful, 0)));
+    for (size_t i = 0; i < n; ++i) {
+        float ms = 0.f;
+        SPK_HIP(pl->ctx, hipEventElapsedTime(&ms, pl->ev_pool[i].first, pl->ev_pool[i].second));
+        pl->prof_ms += ms;
+        pl->prof_count += 1;
+    }
+    pl->ev_used = 0;
+    return SPK_OK;
+}
+
+// ------------------------------------------------------------------ CG driver
+spk_status launch_iterations(spk_plan pl, int count, hipStream_t s, bool with_prof) {
+    spk_ctx ctx = pl->ctx;
+    const int64_t n = pl->A.n_rows;
+    for (int i = 0; i < count; ++i) {
+        hipEvent_t e = nullptr;
+        if (with_prof) {
+            spk_status st = prof_begin(pl, &e);
+            if (st != SPK_OK) return st;
+        }
+        SPK_HIP(ctx, spk::launch_cg_spmv_pq(pl->A, pl->tune, pl->p, pl->q, pl->st, pl->partials, s));
+        if (with_prof) {
+            spk_status st = prof_end(pl, e);
+            if (st != SPK_OK) return st;
+        }
+        SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->p, pl->r, pl->q, pl->st, pl->partials, s));
+        SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, pl->r, pl->p, pl->st, s));
+    }
+    return SPK_OK;
+}
+
+spk_status graph_for(spk_plan pl, int count, hipGraphExec_t *out) {
+    auto it = pl->graphs.find(count);
+    if (it != pl->graphs.end()) {
+        *out = it->second;
+        return SPK_OK;
+    }
+    spk_ctx ctx = pl->ctx;
+    hipGraph_t g = nullptr;
+    SPK_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    spk_status s = launch_iterations(pl, count, ctx->cap_stream, false);
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (s != SPK_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
+    pl->graphs[count] = exec;
+    *out = exec;
+    return SPK_OK;
+}
+
+spk_status run_chunk(spk_plan pl, int count, bool graph) {
+    if (!graph) return launch_iterations(pl, count, pl->ctx->stream, pl->profiling != 0);
+    // binary decomposition into cached power-of-two graphs
+    for (int bit = 1 << 10; bit >= 1; bit >>= 1) {
+        while (count >= bit) {
+            hipGraphExec_t ex = nullptr;
+            spk_status s = graph_for(pl, bit, &ex);
+            if (s != SPK_OK) return s;
+            SPK_HIP(pl->ctx, hipGraphLaunch(ex, pl->ctx->stream));
+            count -= bit;
+        }
+    }
+    return SPK_OK;
+}
+
+spk_status pull_state(spk_plan pl) {
+    SPK_HIP(pl->ctx, hipMemcpyAsync(pl->h_st, pl->st, sizeof(SolveState), hipMemcpyDeviceToHost, pl->ctx->stream));
+    SPK_HIP(pl->ctx, hipStreamSynchronize(pl->ctx->stream));
+    return SPK_OK;
+}
+
+// Next chunk length from the observed residual decay (a scheduling guess only;
+// kernels become no-ops once the device-side stop flag is set).
+int next_chunk(int prev, int64_t k0, double r0, int64_t k1, double r1, double thresh, int64_t left) {
+    int next = std::min(2 * prev, 256);
+    if (k1 > k0 && r0 > 0.0 && r1 > 0.0 && thresh > 0.0 && r1 < r0) {
+        const double rate = std::pow(r1 / r0, 1.0 / static_cast<double>(k1 - k0));
+        if (rate < 1.0 && rate > 0.0) {
+            const double rem = std::log(thresh / r1) / std::log(rate);
+            if (std::isfinite(rem)) next = static_cast<int>(std::ceil(rem * 1.15)) + 2;
+        }
+    }
+    next = std::max(next, 1);
+    next = std::min<int64_t>(next, std::max<int64_t>(left, 1));
+    return std::min(next, 1024);
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+void spk_solver_cfg_default(spk_solver_cfg *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->solver = SPK_SOLVER_CG;
+    cfg->precision = SPK_PREC_FP64;
+    cfg->baseline = SPK_BASELINE_RHS_NORM;
+    cfg->precond = SPK_PRECOND_NONE;
+    cfg->max_iters = 1000;
+    cfg->reduction_factor = 1e-6;
+    cfg->exec_mode = SPK_EXEC_AUTO;
+    cfg->chunk_iters = 0;
+    cfg->record_history = 0;
+    cfg->true_residual = 1;
+    cfg->inner_reduction = 1e-4;
+    cfg->max_outer = 50;
+}
+
+const char *spk_status_string(spk_status s) {
+    switch (s) {
+        case SPK_OK: return "SPK_OK";
+        case SPK_ERR_INVALID_ARG: return "SPK_ERR_INVALID_ARG";
+        case SPK_ERR_UNSUPPORTED: return "SPK_ERR_UNSUPPORTED";
+        case SPK_ERR_OUT_OF_MEMORY: return "SPK_ERR_OUT_OF_MEMORY";
+        case SPK_ERR_BUDGET: return "SPK_ERR_BUDGET";
+        case SPK_ERR_DEVICE: return "SPK_ERR_DEVICE";
+        case SPK_ERR_INTERNAL: return "SPK_ERR_INTERNAL";
+        default: return "SPK_UNKNOWN_STATUS";
+    }
+}
+
+const char *spk_last_error(spk_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
+    if (!out) return SPK_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device_id < 0 || device_id >= count) return SPK_ERR_INVALID_ARG;
+    if (hipSetDevice(device_id) != hipSuccess) return SPK_ERR_DEVICE;
+    spk_ctx ctx = new spk_ctx_s();
+    ctx->device = device_id;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device_id) != hipSuccess) {
+        delete ctx;
+        return SPK_ERR_DEVICE;
+    }
+    ctx->num_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&ctx->d_flags, sizeof(unsigned)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        spk_finalize(ctx);
+        return SPK_ERR_DEVICE;
+    }
+    *out = ctx;
+    return SPK_OK;
+}
+
+spk_status spk_finalize(spk_ctx ctx) {
+    if (!ctx) return SPK_OK;
+    if (ctx->live_plans > 0) return fail(ctx, SPK_ERR_INVALID_ARG, "context still has live plans");
+    (void)hipSetDevice(ctx->device);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return SPK_OK;
+}
+
+spk_status spk_csr_check(spk_ctx ctx, const spk_csr *A, int32_t *verdict) {
+    if (!ctx || !verdict) return SPK_ERR_INVALID_ARG;
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    spk_status s = check_csr_args(ctx, A);
+    if (s != SPK_OK) return s;
+    return gpu_verdict(ctx, A, verdict);
+}
+
+spk_status spk_partition(spk_ctx ctx, const spk_csr *A, int64_t parts, int64_t *split_dev) {
+    if (!ctx || !split_dev) return SPK_ERR_INVALID_ARG;
+    if (parts < 1 || parts > (int64_t(1) << 31)) return fail(ctx, SPK_ERR_INVALID_ARG, "parts out of range");
+    spk_status s = check_csr_args(ctx, A);
+    if (s != SPK_OK) return s;
+    if (A->n_rows < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "negative size");
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    SPK_HIP(ctx, spk::launch_partition(to_dev(A), parts, split_dev, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return SPK_OK;
+}
+
+static spk_status plan_common(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
+    if (!ctx || !out) return SPK_ERR_INVALID_ARG;
+    *out = nullptr;
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    spk_status s = check_csr_args(ctx, A);
+    if (s != SPK_OK) return s;
+    int32_t verdict = 0;
+    s = gpu_verdict(ctx, A, &verdict);
+    if (s != SPK_OK) return s;
+    if (verdict != SPK_CSR_OK) return fail(ctx, SPK_ERR_INVALID_ARG, std::string("malformed CSR: ") + verdict_name(verdict));
+    return SPK_OK;
+}
+
+spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
+    spk_status s = plan_common(ctx, A, out);
+    if (s != SPK_OK) return s;
+    spk_plan pl = new spk_plan_s();
+    pl->ctx = ctx;
+    pl->kind = 0;
+    pl->A = to_dev(A);
+    spk_solver_cfg_default(&pl->cfg);
+    void *x = nullptr, *y = nullptr;
+    const size_t vb = vec_bytes(A->val_type);
+    if (A->nnz >= 100000) {
+        hipError_t e1 = hipMalloc(&x, std::max<size_t>(1, A->n_cols * vb));
+        hipError_t e2 = hipMalloc(&y, std::max<size_t>(1, A->n_rows * vb));
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (x) (void)hipFree(x);
+            if (y) (void)hipFree(y);
+            delete pl;
+            return fail(ctx, SPK_ERR_OUT_OF_MEMORY, "tuning buffers");
+        }
+        (void)hipMemsetAsync(x, 0, A->n_cols * vb, ctx->stream);
+    }
+    s = choose_tune(pl, x, y);
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (s != SPK_OK) {
+        delete pl;
+        return s;
+    }
+    pl->info.exec_mode = SPK_EXEC_HOST_LOOP;
+    ctx->live_plans++;
+    *out = pl;
+    return SPK_OK;
+}
+
+spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg_in, spk_plan *out) {
+    if (!ctx || !out) return SPK_ERR_INVALID_ARG;
+    spk_solver_cfg cfg;
+    if (cfg_in) cfg = *cfg_in;
+    else spk_solver_cfg_default(&cfg);
+    if (cfg.solver != SPK_SOLVER_CG) return fail(ctx, SPK_ERR_UNSUPPORTED, "only CG is built");
+    if (cfg.precond != SPK_PRECOND_NONE) return fail(ctx, SPK_ERR_UNSUPPORTED, "no preconditioner is built");
+    if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
+    if (cfg.precision != SPK_PREC_FP64) return fail(ctx, SPK_ERR_UNSUPPORTED, "mixed precision not built yet");
+    if (cfg.max_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_iters < 0");
+    if (!(cfg.reduction_factor >= 0.0)) return fail(ctx, SPK_ERR_INVALID_ARG, "reduction_factor must be >= 0");
+    if (cfg.exec_mode < SPK_EXEC_AUTO || cfg.exec_mode > SPK_EXEC_GRAPH)
+        return fail(ctx, SPK_ERR_INVALID_ARG, "unknown exec_mode");
+    if (cfg.chunk_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "chunk_iters < 0");
+    spk_status s = plan_common(ctx, A, out);
+    if (s != SPK_OK) return s;
+    if (A->n_rows != A->n_cols) return fail(ctx, SPK_ERR_INVALID_ARG, "solve needs a square matrix");
+    if (A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
+
+    spk_plan pl = new spk_plan_s();
+    pl->ctx = ctx;
+    pl->kind = 1;
+    pl->A = to_dev(A);
+    pl->cfg = cfg;
+    const int64_t n = A->n_rows;
+    const size_t nb = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(double);
+    auto cleanup = [&](spk_status code, const char *msg) {
+        if (pl->r) (void)hipFree(pl->r);
+        if (pl->p) (void)hipFree(pl->p);
+        if (pl->q) (void)hipFree(pl->q);
+        if (pl->partials) (void)hipFree(pl->partials);
+        if (pl->hist) (void)hipFree(pl->hist);
+        if (pl->st) (void)hipFree(pl->st);
+        if (pl->h_st) (void)hipHostFree(pl->h_st);
+        delete pl;
+        return fail(ctx, code, msg);
+    };
+    if (hipMalloc(&pl->r, nb) != hipSuccess || hipMalloc(&pl->p, nb) != hipSuccess ||
+        hipMalloc(&pl->q, nb) != hipSuccess ||
+        hipMalloc(&pl->partials, sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid) != hipSuccess ||
+        hipMalloc(&pl->st, sizeof(SolveState)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&pl->h_st), sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
+        return cleanup(SPK_ERR_OUT_OF_MEMORY, "solve workspace");
+    if (cfg.record_history) {
+        pl->hist_cap = cfg.max_iters + 1;
+        if (hipMalloc(&pl->hist, sizeof(double) * pl->hist_cap) != hipSuccess)
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "history buffer");
+    }
+    if (hipMemsetAsync(pl->st, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(pl->p, 0, nb, ctx->stream) != hipSuccess)
+        return cleanup(SPK_ERR_DEVICE, "workspace init");
+    std::memset(pl->h_st, 0, sizeof(SolveState));
+    s = choose_tune(pl, pl->p, pl->q);
+    if (s != SPK_OK) return cleanup(s, ctx->err.c_str());
+    {
+        const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
+        pl->vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 8));
+    }
+    int mode = cfg.exec_mode;
+    if (mode == SPK_EXEC_AUTO) mode = (A->nnz < 4000000) ? SPK_EXEC_GRAPH : SPK_EXEC_HOST_LOOP;
+    pl->info.exec_mode = mode;
+    pl->info.chunk_iters = cfg.chunk_iters;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(SPK_ERR_DEVICE, "plan sync");
+    ctx->live_plans++;
+    *out = pl;
+    return SPK_OK;
+}
+
+spk_status spk_execute_spmv(spk_plan pl, const void *x, void *y) {
+    if (!pl || pl->kind != 0) return SPK_ERR_INVALID_ARG;
+    spk_ctx ctx = pl->ctx;
+    if ((pl->A.n_cols > 0 && !x) || (pl->A.n_rows > 0 && !y)) return fail(ctx, SPK_ERR_INVALID_ARG, "null vector");
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    hipEvent_t e = nullptr;
+    spk_status s = prof_begin(pl, &e);
+    if (s != SPK_OK) return s;
+    SPK_HIP(ctx, spk::launch_spmv(pl->A, pl->tune, x, y, ctx->stream));
+    s = prof_end(pl, e);
+    if (s != SPK_OK) return s;
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return prof_collect(pl, pl->ev_used);
+}
+
+spk_status spk_execute_solve(spk_plan pl, const void *b_in, void *x_in, spk_log *log) {
+    if (!pl || pl->kind != 1) return SPK_ERR_INVALID_ARG;
+    spk_ctx ctx = pl->ctx;
+    const int64_t n = pl->A.n_rows;
+    if (n > 0 && (!b_in || !x_in)) return fail(ctx, SPK_ERR_INVALID_ARG, "null vector");
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    const double *b = static_cast<const double *>(b_in);
+    double *x = static_cast<double *>(x_in);
+    spk_log L;
+    std::memset(&L, 0, sizeof(L));
+    if (n == 0) {
+        L.converged = 1;
+        L.stop_reason = SPK_STOP_CONVERGED;
+        if (log) *log = L;
+        return SPK_OK;
+    }
+    const spk_solver_cfg &cfg = pl->cfg;
+    const bool graph = pl->info.exec_mode == SPK_EXEC_GRAPH && !pl->profiling;
+    SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->p, pl->st, pl->partials,
+                                     cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
+    int chunk = cfg.chunk_iters > 0 ? cfg.chunk_iters : 8;
+    int64_t launched = 0, k_prev = 0;
+    double r_prev = -1.0;
+    spk_status s = SPK_OK;
+    while (true) {
+        const int64_t left = cfg.max_iters - launched;
+        const int c = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(chunk, left)));
+        if ((s = run_chunk(pl, c, graph)) != SPK_OK) return s;
+        launched += c;
+        if ((s = pull_state(pl)) != SPK_OK) return s;
+        const SolveState &h = *pl->h_st;
+        if (r_prev < 0.0) r_prev = h.bnorm > 0.0 ? h.bnorm : 1.0;
+        if (h.stop != spk::STOP_RUNNING) break;
+        if (launched > cfg.max_iters + 1) return fail(ctx, SPK_ERR_INTERNAL, "iteration cap passed without stop");
+        if (cfg.chunk_iters <= 0)
+            chunk = next_chunk(chunk, k_prev, r_prev, h.iter, h.resnorm, h.thresh, cfg.max_iters - h.iter);
+        k_prev = h.iter;
+        r_prev = h.resnorm;
+    }
+    SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual, ctx->stream));
+    SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    if ((s = pull_state(pl)) != SPK_OK) return s;
+    float ms = 0.f;
+    SPK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (pl->profiling) {
+        const SolveState &h = *pl->h_st;
+        const int64_t useful = h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+        if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
+    }
+    const SolveState &h = *pl->h_st;
+    L.iterations = h.iter;
+    L.outer_iterations = 0;
+    L.implicit_resnorm = h.resnorm;
+    L.true_resnorm = cfg.true_residual ? h.true_resnorm : std::nan("");
+    L.rhs_norm = h.bnorm;
+    L.stop_reason = h.stop;
+    L.converged = h.stop == spk::STOP_CONVERGED;
+    L.elapsed_ms = ms;
+    if (log) *log = L;
+    return SPK_OK;
+}
+
+spk_status spk_plan_history(spk_plan pl, double *out, int64_t cap, int64_t *count) {
+    if (!pl || !count) return SPK_ERR_INVALID_ARG;
+    if (pl->kind != 1 || !pl->hist) return fail(pl->ctx, SPK_ERR_INVALID_ARG, "plan keeps no history");
+    const int64_t have = std::min<int64_t>(pl->h_st->iter + 1, pl->hist_cap);
+    *count = have;
+    const int64_t m = std::min<int64_t>(have, cap);
+    if (m > 0 && out) {
+        SPK_HIP(pl->ctx, hipSetDevice(pl->ctx->device));
+        SPK_HIP(pl->ctx, hipMemcpy(out, pl->hist, sizeof(double) * m, hipMemcpyDeviceToHost));
+    }
+    return SPK_OK;
+}
+
+spk_status spk_plan_get_info(spk_plan pl, spk_plan_info *info) {
+    if (!pl || !info) return SPK_ERR_INVALID_ARG;
+    *info = pl->info;
+    return SPK_OK;
+}
+
+spk_status spk_plan_set_profiling(spk_plan pl, int32_t on) {
+    if (!pl) return SPK_ERR_INVALID_ARG;
+    pl->profiling = on ? 1 : 0;
+    pl->prof_ms = 0.0;
+    pl->prof_count = 0;
+    pl->ev_used = 0;
+    return SPK_OK;
+}
+
+spk_status spk_plan_kernel_stats(spk_plan pl, double *total_ms, int64_t *launches) {
+    if (!pl || !total_ms || !launches) return SPK_ERR_INVALID_ARG;
+    *total_ms = pl->prof_ms;
+    *launches = pl->prof_count;
+    return SPK_OK;
+}
+
+spk_status spk_free(spk_plan pl) {
+    if (!pl) return SPK_OK;
+    spk_ctx ctx = pl->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &g : pl->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &e : pl->ev_pool) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (pl->r) (void)hipFree(pl->r);
+    if (pl->p) (void)hipFree(pl->p);
+    if (pl->q) (void)hipFree(pl->q);
+    if (pl->partials) (void)hipFree(pl->partials);
+    if (pl->hist) (void)hipFree(pl->hist);
+    if (pl->st) (void)hipFree(pl->st);
+    if (pl->h_st) (void)hipHostFree(pl->h_st);
+    ctx->live_plans--;
+    delete pl;
+    return SPK_OK;
+}
+
+spk_status spk_stream_copy(spk_ctx ctx, const void *src, void *dst, size_t bytes, double *ms) {
+    if (!ctx || !src || !dst || (bytes % 16) != 0 || (reinterpret_cast<uintptr_t>(src) & 15) ||
+        (reinterpret_cast<uintptr_t>(dst) & 15))
+        return fail(ctx, SPK_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and size");
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    const int grid = std::min(ctx->num_cu * 16, spk::kMaxGrid);
+    SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    SPK_HIP(ctx, spk::launch_copy(src, dst, bytes, grid, ctx->stream));
+    SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
+    float t = 0.f;
+    SPK_HIP(ctx, hipEventElapsedTime(&t, ctx->ev0, ctx->ev1));
+    if (ms) *ms = t;
+    return SPK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+"""The C-ABI library: it loads, exports every symbol include/spk.h declares,
+and the binding's struct layouts match the header (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spk.h")
+LIB = os.path.join(ROOT, "paper_2510_08230_amd", "libspk.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spk_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "libspk.so not built"
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), "libspk.so lacks %s" % name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (spk_[a-z_]+)\b", out))
+    assert set(names) <= exported
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2510_08230_amd import spk
+    assert set(declared_functions()) == set(spk.EXPORTED)
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "spk.h"
+#define P(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f));
+int main(void) {
+  printf("spk_csr %zu\nspk_solver_cfg %zu\nspk_log %zu\nspk_plan_info %zu\n",
+         sizeof(spk_csr), sizeof(spk_solver_cfg), sizeof(spk_log), sizeof(spk_plan_info));
+  P(spk_csr, values) P(spk_csr, ptr_type) P(spk_solver_cfg, max_iters) P(spk_solver_cfg, reduction_factor)
+  P(spk_solver_cfg, inner_reduction) P(spk_solver_cfg, max_outer) P(spk_log, elapsed_ms) P(spk_log, stop_reason)
+  P(spk_plan_info, spmv_ms)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2510_08230_amd import spk
+    src = tmp_path / "probe.c"
+    src.write_text(PROBE)
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    assert int(got["spk_csr"]) == ctypes.sizeof(spk.Csr)
+    assert int(got["spk_solver_cfg"]) == ctypes.sizeof(spk.SolverCfg)
+    assert int(got["spk_log"]) == ctypes.sizeof(spk.Log)
+    assert int(got["spk_plan_info"]) == ctypes.sizeof(spk.PlanInfo)
+    pairs = [("spk_csr.values", spk.Csr.values), ("spk_csr.ptr_type", spk.Csr.ptr_type),
+             ("spk_solver_cfg.max_iters", spk.SolverCfg.max_iters),
+             ("spk_solver_cfg.reduction_factor", spk.SolverCfg.reduction_factor),
+             ("spk_solver_cfg.inner_reduction", spk.SolverCfg.inner_reduction),
+             ("spk_solver_cfg.max_outer", spk.SolverCfg.max_outer),
+             ("spk_log.elapsed_ms", spk.Log.elapsed_ms), ("spk_log.stop_reason", spk.Log.stop_reason),
+             ("spk_plan_info.spmv_ms", spk.PlanInfo.spmv_ms)]
+    for key, field in pairs:
+        assert int(got[key]) == field.offset, key
+
+
+def test_defaults_and_status_strings():
+    from paper_2510_08230_amd import spk
+    cfg = spk.spk_solver_cfg_default()
+    assert cfg.max_iters == 1000 and cfg.reduction_factor == 1e-6    # Listings 1-2 defaults
+    assert cfg.solver == spk.SOLVER_CG and cfg.precision == spk.PREC_FP64 and cfg.true_residual == 1
+    assert spk.spk_status_string(spk.OK) == "SPK_OK"
+    assert spk.spk_status_string(spk.ERR_INVALID_ARG) == "SPK_ERR_INVALID_ARG"
+
+
+def test_enum_numbering_agrees_with_oracle():
+    """Stop reasons and CSR verdicts are numbered alike on both sides (defined independently)."""
+    import oracle
+    from paper_2510_08230_amd import spk
+    assert (spk.STOP_CONVERGED, spk.STOP_MAX_ITERS, spk.STOP_BREAKDOWN, spk.STOP_NON_FINITE) == \
+        (oracle.CONVERGED, oracle.MAX_ITERS, oracle.BREAKDOWN, oracle.NON_FINITE)
+    assert (spk.CSR_OK, spk.CSR_BAD_SIZE, spk.CSR_BAD_FIRST, spk.CSR_DECREASING, spk.CSR_BAD_LAST,
+            spk.CSR_BAD_COLUMN) == (oracle.CSR_OK, oracle.CSR_BAD_SIZE, oracle.CSR_BAD_FIRST,
+                                    oracle.CSR_DECREASING, oracle.CSR_BAD_LAST, oracle.CSR_BAD_COLUMN)
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    from paper_2510_08230_amd import spk
+    t = torch.zeros(4, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        spk.CsrMatrix(t, t, torch.zeros(4, dtype=torch.float64), 3, 3)

@@ -1,0 +1,159 @@
+"""CG on the GPU against the FP64 oracle.
+
+Stated tolerances (FP64, diagonal margin delta = 1, kappa_G <= 13):
+  * fixed-K iterates (stop test off, K <= 50): ||x_K - x_K^orc|| / ||x_K^orc|| <= 1e-12
+  * converged solve (tau = 1e-14): ||x - x^orc|| / ||x^orc|| <= 1e-12, iterations within +-1
+  * recurrence residual history within 1% per iteration
+  * closed forms (A = I, A = cI with dyadic b) exact.
+The GPU sums reductions in a different order than the oracle, so iterates
+agree to rounding, not bitwise; runs of the GPU path itself are bitwise
+reproducible."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+from tests.gpu_util import DEV, dev_csr, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spk():
+    from paper_2510_08230_amd import spk as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(spk):
+    c = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    yield c
+    spk.spk_finalize(c)
+
+
+def solve(spk, ctx, A, b, x0=None, tau=1e-14, max_iters=1000, mode=0, history=False, chunk=0, M=None):
+    cfg = spk.spk_solver_cfg_default()
+    cfg.reduction_factor = tau
+    cfg.max_iters = max_iters
+    cfg.exec_mode = mode
+    cfg.record_history = 1 if history else 0
+    cfg.chunk_iters = chunk
+    M = M if M is not None else dev_csr(spk, A)
+    pl = spk.spk_plan_solve(ctx, M, cfg)
+    x = to_dev(np.zeros(A.n_rows) if x0 is None else x0)
+    log = spk.spk_execute_solve(pl, to_dev(b), x)
+    hist = spk.spk_plan_history(pl) if history else None
+    spk.spk_free(pl)
+    return x.cpu().numpy(), log, hist
+
+
+MATS = {"stencil7_46": lambda: inputs.stencil7(46, 0), "randsym_1e5": lambda: inputs.randsym(100000, 0)}
+
+
+def test_identity_exact(spk, ctx):
+    b = np.array([1.0, -2.0, 0.5, 3.0, -0.25] * 100)
+    x, log, _ = solve(spk, ctx, inputs.diagonal(np.ones(b.size)), b)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 1 and np.array_equal(x, b)
+
+
+def test_scaled_identity_exact(spk, ctx):
+    b = np.array([inputs.unif(1, 15, i) for i in range(777)])
+    x, log, _ = solve(spk, ctx, inputs.diagonal(np.full(b.size, 4.0)), b)
+    assert log.iterations == 1 and np.array_equal(x, b / 4.0) and log.implicit_resnorm == 0.0
+
+
+def test_laplacian1d_closed_form(spk, ctx):
+    n = 31
+    i = np.arange(1, n + 1, dtype=np.float64)
+    x, log, _ = solve(spk, ctx, inputs.laplacian1d(n), np.ones(n), tau=1e-15, max_iters=n)
+    assert log.stop_reason == spk.STOP_CONVERGED and rel(x, i * (n + 1 - i) / 2) <= 1e-13
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("K", [1, 5, 50])
+def test_fixed_k_iterates(spk, ctx, name, K):
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 0)
+    x, log, _ = solve(spk, ctx, A, b, tau=0.0, max_iters=K)
+    xo, ro, _ = oracle.cg(A, b, tau=0.0, max_iters=K)
+    assert log.iterations == K and log.stop_reason == spk.STOP_MAX_ITERS
+    assert rel(x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("mode", [1, 2])
+def test_converged_parity(spk, ctx, name, mode):
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 0)
+    x, log, hist = solve(spk, ctx, A, b, mode=mode, history=True)
+    xo, ro, ho = oracle.cg(A, b, tau=1e-14, max_iters=1000, history=True)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert rel(x, xo) <= 1e-12
+    k = min(hist.size, ho.size)
+    assert np.all(np.abs(hist[:k] - ho[:k]) <= 0.01 * ho[:k])
+    assert abs(log.rhs_norm - ro.rhs_norm) <= 1e-14 * ro.rhs_norm
+    assert log.true_resnorm <= 1e-13 * log.rhs_norm
+    assert abs(log.true_resnorm - ro.true_resnorm) <= 1e-14 * ro.rhs_norm + 0.5 * ro.true_resnorm
+
+
+def test_modes_and_reruns_bitwise(spk, ctx):
+    A = inputs.stencil7(30, 2)
+    b = inputs.rhs(A.n_rows, 2)
+    runs = [solve(spk, ctx, A, b, mode=m, chunk=c)[0] for m, c in ((1, 0), (2, 0), (1, 3), (2, 5), (1, 0))]
+    for x in runs[1:]:
+        assert np.array_equal(x.view(np.uint64), runs[0].view(np.uint64))
+
+
+def test_stop_semantics(spk, ctx):
+    A = inputs.diagonal(np.array([2.0, 3.0, 5.0] * 50))
+    b = np.ones(150)
+    x0 = np.array([0.5, -1.0, 7.0] * 50)
+    x, log, h = solve(spk, ctx, A, b, x0=x0, tau=1e-12, max_iters=0, history=True)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 0 and np.array_equal(x, x0)
+    assert h.size == 1 and abs(h[0] - np.linalg.norm(b - A.to_dense() @ x0)) <= 1e-14 * h[0]
+    x, log, _ = solve(spk, ctx, A, np.zeros(150), x0=x0, tau=1e-12, max_iters=10)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 0 and not x.any()
+    assert log.true_resnorm == 0.0
+    xs = np.array([0.5, 1.0 / 3.0, 0.2] * 50)
+    x, log, _ = solve(spk, ctx, A, b, x0=xs, tau=1e-12, max_iters=10)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 0
+    x, log, _ = solve(spk, ctx, inputs.laplacian1d(200), np.ones(200), tau=1e-15, max_iters=3)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 3
+
+
+def test_breakdown_and_non_finite(spk, ctx):
+    _, log, _ = solve(spk, ctx, inputs.diagonal(np.array([1.0, -2.0])), np.ones(2), tau=1e-12)
+    assert log.stop_reason == spk.STOP_BREAKDOWN and log.iterations == 0
+    _, log, _ = solve(spk, ctx, inputs.diagonal(np.array([1.0, -1.0])), np.ones(2), tau=1e-12)
+    assert log.stop_reason == spk.STOP_BREAKDOWN
+    b = np.ones(4)
+    b[2] = np.nan
+    _, log, _ = solve(spk, ctx, inputs.diagonal(np.ones(4)), b, tau=1e-12)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+    _, log, _ = solve(spk, ctx, inputs.diagonal(np.array([1.0, np.inf, 1.0])), np.ones(3), tau=1e-12)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+
+
+def test_plan_errors(spk, ctx):
+    A = inputs.stencil7(4, 0)
+    with pytest.raises(spk.SpkError) as e:
+        spk.spk_plan_solve(ctx, dev_csr(spk, A, val=torch.float32))
+    assert e.value.status == spk.ERR_INVALID_ARG
+    R = inputs.CSR(2, 3, np.array([0, 1, 2]), np.array([0, 2], np.int32), np.ones(2))
+    with pytest.raises(spk.SpkError) as e:
+        spk.spk_plan_solve(ctx, dev_csr(spk, R))
+    assert e.value.status == spk.ERR_INVALID_ARG and "square" in str(e.value)
+
+
+def test_c2_full_size(spk, ctx):
+    """stencil7 N=215 (n = 9,938,375), seed 1, FP64, tau = 1e-14: the solve the benchmark times."""
+    A = inputs.stencil7(215, 1)
+    b = inputs.rhs(A.n_rows, 1)
+    x, log, _ = solve(spk, ctx, A, b)
+    xo, ro, _ = oracle.cg(A, b, tau=1e-14, max_iters=1000)
+    print("gpu its %d (%.1f ms), oracle its %d" % (log.iterations, log.elapsed_ms, ro.iterations))
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert rel(x, xo) <= 1e-12
