@@ -4,6 +4,7 @@
 // chunk size).  All GPU work goes through the launchers in spk_kernels.hip.
 #include "spk.h"
 #include "spk_internal.h"
+#include "spk_pool.h"
 
 #include <algorithm>
 #include <cmath>
@@ -45,6 +46,8 @@ struct spk_ctx_s {
     unsigned *h_flags = nullptr;        // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::map<TuneKey, TuneResult> tune_cache;
+    spk::DevicePool dpool;              // plan workspace cache
+    spk::PinnedPool hpool;              // pinned status mirrors
     int live_plans = 0;
 };
 
@@ -125,7 +128,7 @@ spk_status gpu_verdict(spk_ctx ctx, const spk_csr *A, int32_t *verdict) {
     }
     const CsrDev d = to_dev(A);
     SPK_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(unsigned), ctx->stream));
-    SPK_HIP(ctx, spk::launch_validate(d, ctx->d_flags, ctx->stream));
+    SPK_HIP(ctx, spk::launch_validate(d, ctx->d_flags, ctx->num_cu * 4, ctx->stream));
     SPK_HIP(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
     SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const unsigned f = *ctx->h_flags;
@@ -153,10 +156,18 @@ const char *verdict_name(int32_t v) {
 // ------------------------------------------------------------------ tuning
 int64_t num_tiles(int64_t n) { return (n + spk::kTileRows - 1) / spk::kTileRows; }
 
-SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap) {
-    SpmvTune t{kind, lanes_log2, 1, remap};
-    const int bpc = spk::spmv_blocks_per_cu(A, t);
-    int64_t g = static_cast<int64_t>(ctx->num_cu) * bpc;
+// The LDS tiling stages with 16-byte loads: values and col_idx must be 16-byte aligned.
+bool stream_ok(const CsrDev &A) {
+    return (reinterpret_cast<uintptr_t>(A.va) & 15) == 0 && (reinterpret_cast<uintptr_t>(A.ci) & 15) == 0;
+}
+
+// bpc <= 0: as many workgroups per CU as the occupancy calculator allows.
+SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap, int nt, int pf, int bpc) {
+    SpmvTune t{kind, lanes_log2, 1, remap, nt, pf, 0};
+    const int occ = spk::spmv_blocks_per_cu(A, t);
+    const int use = (bpc <= 0) ? occ : std::min(bpc, occ);
+    t.bpc = use;
+    int64_t g = static_cast<int64_t>(ctx->num_cu) * use;
     g = std::min<int64_t>(g, spk::kMaxGrid);
     g = std::min<int64_t>(g, std::max<int64_t>(num_tiles(A.n_rows), 1));
     t.grid = static_cast<int>(std::max<int64_t>(g, 1));
@@ -165,10 +176,10 @@ SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int r
 
 SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
-    if (mean <= 16.0) return make_tune(ctx, A, 0, 0, 1);
+    if (mean <= 16.0 && stream_ok(A)) return make_tune(ctx, A, 0, 0, 0, 0, 1, 0);
     int l2 = 0;
     while ((1 << l2) < mean && l2 < 6) ++l2;
-    return make_tune(ctx, A, 1, l2, 1);
+    return make_tune(ctx, A, 1, l2, 1, 0, 0, 0);
 }
 
 // Times each candidate on y = A x and keeps the fastest.  x, y: device
@@ -181,13 +192,16 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneRe
         return SPK_OK;
     }
     std::vector<SpmvTune> cands;
-    cands.push_back(make_tune(ctx, A, 0, 0, 1));
-    cands.push_back(make_tune(ctx, A, 0, 0, 0));
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
+    if (stream_ok(A) && mean <= 64.0) {
+        for (int pf = 1; pf >= 0; --pf)
+            for (int remap = 0; remap <= 1; ++remap)
+                for (int nt = 0; nt <= 1; ++nt) cands.push_back(make_tune(ctx, A, 0, 0, remap, nt, pf, 0));
+    }
     for (int l2 = 0; l2 <= 6; ++l2) {
         const double L = static_cast<double>(1 << l2);
         if (L > 4.0 * std::max(mean, 1.0) && l2 > 0) break;
-        cands.push_back(make_tune(ctx, A, 1, l2, 1));
+        cands.push_back(make_tune(ctx, A, 1, l2, 1, 0, 0, 0));
     }
     TuneResult best{cands[0], 1e30};
     for (const SpmvTune &t : cands) {
@@ -207,35 +221,54 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneRe
     return SPK_OK;
 }
 
-// SPK_SPMV_KERNEL forces a tiling (tests use it to cover each one):
-// "stream", "stream-noremap" or "vector:<lanes>" (lanes a power of two <= 64).
+// SPK_SPMV_KERNEL forces a tiling (tests and sweeps use it): "stream" or
+// "vector:<lanes>", optionally followed by ",key=value" with keys remap, nt,
+// pf, bpc (e.g. "stream,pf=1,nt=1,remap=0,bpc=4").
 bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     const char *env = std::getenv("SPK_SPMV_KERNEL");
     if (!env || !*env) return false;
-    const std::string v(env);
-    if (v == "stream") {
-        *t = make_tune(ctx, A, 0, 0, 1);
-        return true;
+    std::string v(env);
+    int kind = -1, l2 = 0, remap = -1, nt = 0, pf = 1, bpc = 0;
+    size_t pos = 0;
+    bool first = true;
+    while (pos <= v.size()) {
+        size_t comma = v.find(',', pos);
+        if (comma == std::string::npos) comma = v.size();
+        const std::string tok = v.substr(pos, comma - pos);
+        if (first) {
+            if (tok == "stream") kind = 0;
+            else if (tok == "stream-noremap") { kind = 0; remap = 0; }
+            else if (tok.rfind("vector:", 0) == 0) {
+                kind = 1;
+                const int lanes = std::atoi(tok.c_str() + 7);
+                while ((1 << l2) < lanes && l2 < 6) ++l2;
+            }
+            first = false;
+        } else {
+            const size_t eq = tok.find('=');
+            if (eq != std::string::npos) {
+                const std::string k = tok.substr(0, eq);
+                const int val = std::atoi(tok.c_str() + eq + 1);
+                if (k == "remap") remap = val;
+                else if (k == "nt") nt = val;
+                else if (k == "pf") pf = val;
+                else if (k == "bpc") bpc = val;
+            }
+        }
+        pos = comma + 1;
     }
-    if (v == "stream-noremap") {
-        *t = make_tune(ctx, A, 0, 0, 0);
-        return true;
-    }
-    if (v.rfind("vector:", 0) == 0) {
-        const int lanes = std::atoi(v.c_str() + 7);
-        int l2 = 0;
-        while ((1 << l2) < lanes && l2 < 6) ++l2;
-        *t = make_tune(ctx, A, 1, l2, 1);
-        return true;
-    }
-    return false;
+    if (kind < 0) return false;
+    if (kind == 0 && !stream_ok(A)) kind = 1;
+    if (remap < 0) remap = (kind == 0) ? 1 : 1;
+    *t = make_tune(ctx, A, kind, l2, remap, nt, pf, bpc);
+    return true;
 }
 
 spk_status choose_tune(spk_plan pl, const void *x, void *y) {
     spk_ctx ctx = pl->ctx;
     const CsrDev &A = pl->A;
     if (A.n_rows == 0) {
-        pl->tune = SpmvTune{0, 0, 1, 0};
+        pl->tune = SpmvTune{0, 0, 1, 0, 0, 0, 0};
         pl->info.tuned = 0;
         return SPK_OK;
     }
@@ -308,9 +341,11 @@ spk_status launch_iterations(spk_plan pl, int count, hipStream_t s, bool with_pr
             spk_status st = prof_end(pl, e);
             if (st != SPK_OK) return st;
         }
-        SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->p, pl->r, pl->q, pl->st, pl->partials, s));
-        SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, pl->r, pl->p, pl->st, s));
+        SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->tune.grid, i, pl->p, pl->r, pl->q, pl->st,
+                                           pl->partials, s));
+        SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, i, pl->r, pl->p, pl->st, pl->partials, s));
     }
+    SPK_HIP(ctx, spk::launch_cg_chunk_end(pl->st, count, s));
     return SPK_OK;
 }
 
@@ -376,6 +411,21 @@ int next_chunk(int prev, int64_t k0, double r0, int64_t k1, double r1, double th
     return std::min(next, 1024);
 }
 
+// Hand a plan's workspace back to the context pools (stream already idle).
+void release_workspace(spk_plan pl) {
+    spk_ctx ctx = pl->ctx;
+    ctx->dpool.put(pl->r);
+    ctx->dpool.put(pl->p);
+    ctx->dpool.put(pl->q);
+    ctx->dpool.put(pl->partials);
+    ctx->dpool.put(pl->hist);
+    ctx->dpool.put(pl->st);
+    ctx->hpool.put(pl->h_st);
+    pl->r = pl->p = pl->q = pl->partials = pl->hist = nullptr;
+    pl->st = nullptr;
+    pl->h_st = nullptr;
+}
+
 }  // namespace
 
 // ==================================================================== C ABI
@@ -428,6 +478,9 @@ spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
         return SPK_ERR_DEVICE;
     }
     ctx->num_cu = prop.multiProcessorCount;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) ctx->dpool.set_cap(total_b / 4);
+    ctx->hpool.set_cap(size_t(16) << 20);
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&ctx->d_flags, sizeof(unsigned)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
@@ -443,6 +496,9 @@ spk_status spk_finalize(spk_ctx ctx) {
     if (!ctx) return SPK_OK;
     if (ctx->live_plans > 0) return fail(ctx, SPK_ERR_INVALID_ARG, "context still has live plans");
     (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    ctx->dpool.trim();
+    ctx->hpool.trim();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
@@ -496,19 +552,20 @@ spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
     void *x = nullptr, *y = nullptr;
     const size_t vb = vec_bytes(A->val_type);
     if (A->nnz >= 100000) {
-        hipError_t e1 = hipMalloc(&x, std::max<size_t>(1, A->n_cols * vb));
-        hipError_t e2 = hipMalloc(&y, std::max<size_t>(1, A->n_rows * vb));
+        hipError_t e1 = ctx->dpool.get(std::max<size_t>(1, A->n_cols * vb), &x);
+        hipError_t e2 = ctx->dpool.get(std::max<size_t>(1, A->n_rows * vb), &y);
         if (e1 != hipSuccess || e2 != hipSuccess) {
-            if (x) (void)hipFree(x);
-            if (y) (void)hipFree(y);
+            ctx->dpool.put(x);
+            ctx->dpool.put(y);
             delete pl;
             return fail(ctx, SPK_ERR_OUT_OF_MEMORY, "tuning buffers");
         }
         (void)hipMemsetAsync(x, 0, A->n_cols * vb, ctx->stream);
     }
     s = choose_tune(pl, x, y);
-    if (x) (void)hipFree(x);
-    if (y) (void)hipFree(y);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dpool.put(x);
+    ctx->dpool.put(y);
     if (s != SPK_OK) {
         delete pl;
         return s;
@@ -546,26 +603,30 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     const int64_t n = A->n_rows;
     const size_t nb = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(double);
     auto cleanup = [&](spk_status code, const char *msg) {
-        if (pl->r) (void)hipFree(pl->r);
-        if (pl->p) (void)hipFree(pl->p);
-        if (pl->q) (void)hipFree(pl->q);
-        if (pl->partials) (void)hipFree(pl->partials);
-        if (pl->hist) (void)hipFree(pl->hist);
-        if (pl->st) (void)hipFree(pl->st);
-        if (pl->h_st) (void)hipHostFree(pl->h_st);
+        (void)hipStreamSynchronize(ctx->stream);
+        release_workspace(pl);
         delete pl;
         return fail(ctx, code, msg);
     };
-    if (hipMalloc(&pl->r, nb) != hipSuccess || hipMalloc(&pl->p, nb) != hipSuccess ||
-        hipMalloc(&pl->q, nb) != hipSuccess ||
-        hipMalloc(&pl->partials, sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid) != hipSuccess ||
-        hipMalloc(&pl->st, sizeof(SolveState)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&pl->h_st), sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
+    auto dget = [&](size_t bytes, double **out) {
+        void *v = nullptr;
+        const bool ok = ctx->dpool.get(bytes, &v) == hipSuccess;
+        *out = static_cast<double *>(v);
+        return ok;
+    };
+    void *stv = nullptr, *hstv = nullptr;
+    if (!dget(nb, &pl->r) || !dget(nb, &pl->p) || !dget(nb, &pl->q) ||
+        !dget(sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid, &pl->partials) ||
+        ctx->dpool.get(sizeof(SolveState), &stv) != hipSuccess || ctx->hpool.get(sizeof(SolveState), &hstv) != hipSuccess) {
+        pl->st = static_cast<SolveState *>(stv);
+        pl->h_st = static_cast<SolveState *>(hstv);
         return cleanup(SPK_ERR_OUT_OF_MEMORY, "solve workspace");
+    }
+    pl->st = static_cast<SolveState *>(stv);
+    pl->h_st = static_cast<SolveState *>(hstv);
     if (cfg.record_history) {
         pl->hist_cap = cfg.max_iters + 1;
-        if (hipMalloc(&pl->hist, sizeof(double) * pl->hist_cap) != hipSuccess)
-            return cleanup(SPK_ERR_OUT_OF_MEMORY, "history buffer");
+        if (!dget(sizeof(double) * pl->hist_cap, &pl->hist)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "history buffer");
     }
     if (hipMemsetAsync(pl->st, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
         hipMemsetAsync(pl->p, 0, nb, ctx->stream) != hipSuccess)
@@ -574,8 +635,9 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     s = choose_tune(pl, pl->p, pl->q);
     if (s != SPK_OK) return cleanup(s, ctx->err.c_str());
     {
+        // Streaming kernels: 4 workgroups per CU measured best for HBM copy rates.
         const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
-        pl->vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 8));
+        pl->vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 4));
     }
     int mode = cfg.exec_mode;
     if (mode == SPK_EXEC_AUTO) mode = (A->nnz < 4000000) ? SPK_EXEC_GRAPH : SPK_EXEC_HOST_LOOP;
@@ -710,13 +772,7 @@ spk_status spk_free(spk_plan pl) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    if (pl->r) (void)hipFree(pl->r);
-    if (pl->p) (void)hipFree(pl->p);
-    if (pl->q) (void)hipFree(pl->q);
-    if (pl->partials) (void)hipFree(pl->partials);
-    if (pl->hist) (void)hipFree(pl->hist);
-    if (pl->st) (void)hipFree(pl->st);
-    if (pl->h_st) (void)hipHostFree(pl->h_st);
+    release_workspace(pl);
     ctx->live_plans--;
     delete pl;
     return SPK_OK;
@@ -727,7 +783,7 @@ spk_status spk_stream_copy(spk_ctx ctx, const void *src, void *dst, size_t bytes
         (reinterpret_cast<uintptr_t>(dst) & 15))
         return fail(ctx, SPK_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and size");
     SPK_HIP(ctx, hipSetDevice(ctx->device));
-    const int grid = std::min(ctx->num_cu * 16, spk::kMaxGrid);
+    const int grid = std::min(ctx->num_cu * 4, spk::kMaxGrid);
     SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     SPK_HIP(ctx, spk::launch_copy(src, dst, bytes, grid, ctx->stream));
     SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));

@@ -26,16 +26,16 @@ enum Stop : int32_t {
 enum Site : int { SITE_INIT = 0, SITE_PQ = 1, SITE_RR = 2, SITE_TRUE = 3, SITE_COUNT = 4 };
 constexpr int kSiteWidth = 2;      // values reduced at once per site (max)
 
-// Device-resident scalars of one CG solve.  Written only by the last
-// workgroup of a reduction (or by the init kernel), read by later launches.
+// Device-resident scalars of one CG solve.  Loop kernels read only fields
+// written by earlier launches; workgroup 0 of a launch writes the results.
 struct SolveState {
-    double rho;           // r_k . r_k
-    double pq;            // p_k . A p_k
-    double alpha, beta;
+    double rho[4];        // ring: rho[k & 3] = r_k . r_k
+    double pq, alpha;     // last p.q and alpha (diagnostics)
     double bnorm;         // ||b||
     double thresh;        // reduction_factor * ||b||
     double resnorm;       // sqrt(rho) at the last check
     double true_resnorm;  // ||b - A x|| at exit (NaN if not computed)
+    int64_t base;         // absolute index of the current chunk's first iteration
     int64_t iter;         // completed updates
     int64_t max_iters;
     int32_t stop;         // Stop
@@ -43,7 +43,6 @@ struct SolveState {
     double *x;            // caller's solution vector for this execute
     double *hist;         // optional ||r_k|| history
     int64_t hist_cap;
-    unsigned counters[SITE_COUNT];   // arrival counters, reset to 0 by each last block
 };
 
 // Launch shape of the SpMV family (shared by every SpMV-based kernel).
@@ -52,6 +51,9 @@ struct SpmvTune {
     int lanes_log2;  // vector kernel: log2(lanes per row)
     int grid;        // workgroups
     int xcd_remap;   // 1 = contiguous tile ranges per XCD
+    int nt;          // 1 = non-temporal loads for the matrix value stream
+    int pf;          // LDS tiles: 1 = next tile's loads issued before the current tile is reduced
+    int bpc;         // workgroups per CU the grid was sized for
 };
 
 // Device CSR view with runtime-typed arrays.
@@ -65,22 +67,25 @@ struct CsrDev {
 enum : unsigned { VFLAG_BAD_FIRST = 1u, VFLAG_DECREASING = 2u, VFLAG_BAD_LAST = 4u, VFLAG_BAD_COLUMN = 8u };
 
 // ---- launchers (spk_kernels.hip) -------------------------------------------------
-hipError_t launch_validate(const CsrDev &A, unsigned *flags, hipStream_t s);
+hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
 
 // y = A x; x/y are double for F64 values, float otherwise.
 hipError_t launch_spmv(const CsrDev &A, const SpmvTune &t, const void *x, void *y, hipStream_t s);
 
 // CG (FP64).  partials: SITE_COUNT * kSiteWidth * kMaxGrid doubles.
+// Iteration j of a chunk = spmv_pq, update(j), pupdate(j); a chunk of c
+// iterations ends with chunk_end(c).
 hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, double *r,
                           double *p, SolveState *st, double *partials, double tau, int64_t max_iters,
                           double *hist, int64_t hist_cap, hipStream_t s);
 hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q,
                              SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cg_update(int64_t n, int grid, const double *p, double *r, const double *q,
-                            SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cg_pupdate(int64_t n, int grid, const double *r, double *p, SolveState *st,
-                             hipStream_t s);
+hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, const double *p, double *r,
+                            const double *q, SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st,
+                             double *partials, hipStream_t s);
+hipError_t launch_cg_chunk_end(SolveState *st, int count, hipStream_t s);
 // Sets x = 0 when b == 0, then (optionally) recomputes ||b - A x|| into the state.
 hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *b, double *x,
                               SolveState *st, double *partials, int true_residual, hipStream_t s);

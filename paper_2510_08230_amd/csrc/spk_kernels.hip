@@ -13,15 +13,18 @@
 // that XCD's L2.
 //
 // The CG solve (Section 6.2 benchmarks CG; the iteration is the textbook
-// Hestenes-Stiefel one) runs as three launches per iteration:
-//   spmv_pq : q = A p, p.q      -> alpha (or breakdown)
-//   update  : x += alpha p, r -= alpha q, r.r -> stop test, beta
-//   pupdate : p = r + beta p
-// Every reduction is deterministic: each workgroup writes its FP64 partial,
-// the last workgroup to arrive (agent-scope acq_rel counter) sums the
-// partials in a fixed order and updates the device-resident SolveState.
-// Kernels return at once when the state says the solve has stopped, so a
-// chunk of iterations enqueued past convergence costs only empty launches.
+// Hestenes-Stiefel one) runs as three launches per iteration k:
+//   spmv_pq : q = A p_k, partials of p.q
+//   update  : alpha = rho_k / p.q; x += alpha p, r -= alpha q; partials of r.r
+//   pupdate : rho_{k+1} = r.r, stop test, beta; p = r + beta p
+// Reductions need no atomics and no cache-flushing fences: each workgroup of
+// the producing launch stores one FP64 partial, and every workgroup of the
+// consuming launch re-sums all partials in the same fixed order, so all take
+// identical decisions (launch boundaries make the partials visible across
+// XCDs).  Per-iteration scalars live in a 4-slot ring indexed by the absolute
+// iteration (chunk base + index within the chunk), so no launch reads a
+// location that it writes.  Kernels return at once when the stop flag is
+// set, so iterations enqueued past convergence cost only empty launches.
 #include "spk_internal.h"
 
 #include <cmath>
@@ -36,6 +39,18 @@ __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ float widen(_Float16 v) { return static_cast<float>(v); }
 __device__ __forceinline__ float widen(bf16s v) { return __uint_as_float(static_cast<unsigned>(v.bits) << 16); }
+
+// Matrix-value load, optionally non-temporal (streamed data that should not
+// displace the gathered vector from the caches).
+template <typename T>
+__device__ __forceinline__ T ldv(const T *p, int nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+__device__ __forceinline__ bf16s ldv(const bf16s *p, int nt) {
+    bf16s r;
+    r.bits = nt ? __builtin_nontemporal_load(&p->bits) : p->bits;
+    return r;
+}
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -63,12 +78,11 @@ struct TileIter {
     }
 };
 
-// Deterministic grid reduction of NV doubles.  Every workgroup calls it once;
-// the last to arrive runs last(tot) on thread 0 with the fixed-order totals.
-template <int NV, class Last>
-__device__ __forceinline__ void reduce_finish(double (&v)[NV], double *partials, unsigned *counter, Last last) {
+// Block-level fixed-order reduction of NV doubles; thread 0 stores the
+// workgroup's partials at partials[j * kMaxGrid + blockIdx.x].
+template <int NV>
+__device__ __forceinline__ void block_partial(double (&v)[NV], double *partials) {
     __shared__ double sh[NV][kBlock / 64];
-    __shared__ int s_last;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
@@ -76,41 +90,39 @@ __device__ __forceinline__ void reduce_finish(double (&v)[NV], double *partials,
         if (lane == 0) sh[j][wid] = t;
     }
     __syncthreads();
-    const unsigned G = gridDim.x;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
             double t = sh[j][0];
 #pragma unroll
             for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
-            partials[j * kMaxGrid + blockIdx.x] = t;
+            partials[static_cast<size_t>(j) * kMaxGrid + blockIdx.x] = t;
         }
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == G - 1);
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
+
+// Every thread of the calling workgroup receives the fixed-order sums of the
+// G partials a previous launch stored (identical in every workgroup).
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *partials, int G, double (&tot)[NV]) {
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         double t = 0.0;
-        for (unsigned b = threadIdx.x; b < G; b += kBlock) t += partials[j * kMaxGrid + b];
+        for (int b = threadIdx.x; b < G; b += kBlock) t += partials[static_cast<size_t>(j) * kMaxGrid + b];
         t = wave_sum(t);
         if (lane == 0) sh[j][wid] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot[NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            double t = sh[j][0];
+    for (int j = 0; j < NV; ++j) {
+        double t = sh[j][0];
 #pragma unroll
-            for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
-            tot[j] = t;
-        }
-        *counter = 0u;
-        last(tot);
+        for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
+        tot[j] = t;
     }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ epilogues
@@ -123,16 +135,11 @@ struct EpiPlain {
     __device__ void finish() {}
 };
 
-// r = b - A x, p = r; reduces r.r and b.b, then sets up the solve state.
+// r = b - A x, p = r; partials of r.r and b.b.
 struct EpiInit {
     const double *b;
-    double *r, *p, *x;
-    SolveState *st;
+    double *r, *p;
     double *part;
-    double tau;
-    int64_t max_iters;
-    double *hist;
-    int64_t hist_cap;
     double rr, bb;
     __device__ bool skip() const { return false; }
     __device__ void row(int64_t i, double s) {
@@ -145,54 +152,15 @@ struct EpiInit {
     }
     __device__ void finish() {
         double v[2] = {rr, bb};
-        SolveState *S = st;
-        double *X = x, *H = hist;
-        const int64_t hc = hist_cap, mi = max_iters;
-        const double ta = tau;
-        reduce_finish<2>(v, part, &S->counters[SITE_INIT], [=](const double *tot) {
-            S->x = X;
-            S->hist = H;
-            S->hist_cap = hc;
-            S->max_iters = mi;
-            S->iter = 0;
-            S->zero_x = 0;
-            S->stop = STOP_RUNNING;
-            S->alpha = 0.0;
-            S->beta = 0.0;
-            S->pq = 0.0;
-            S->true_resnorm = __builtin_nan("");
-            const double bn = sqrt(tot[1]);
-            S->bnorm = bn;
-            S->thresh = ta * bn;
-            if (!isfinite(bn)) {
-                S->stop = STOP_NON_FINITE;
-                S->resnorm = bn;
-            } else if (bn == 0.0) {
-                S->zero_x = 1;
-                S->stop = STOP_CONVERGED;
-                S->resnorm = 0.0;
-                S->true_resnorm = 0.0;
-                S->rho = 0.0;
-                if (H && hc > 0) H[0] = 0.0;
-            } else {
-                const double rho = tot[0];
-                const double res = sqrt(rho);
-                S->rho = rho;
-                S->resnorm = res;
-                if (H && hc > 0) H[0] = res;
-                if (!isfinite(rho)) S->stop = STOP_NON_FINITE;
-                else if (res <= ta * bn) S->stop = STOP_CONVERGED;
-                else if (mi <= 0) S->stop = STOP_MAX_ITERS;
-            }
-        });
+        block_partial<2>(v, part);
     }
 };
 
-// q = A p; reduces p.q and forms alpha = rho / p.q.
+// q = A p; partials of p.q.
 struct EpiPq {
     double *q;
     const double *p;
-    SolveState *st;
+    const SolveState *st;
     double *part;
     double acc;
     __device__ bool skip() const { return st->stop != STOP_RUNNING; }
@@ -202,21 +170,14 @@ struct EpiPq {
     }
     __device__ void finish() {
         double v[1] = {acc};
-        SolveState *S = st;
-        reduce_finish<1>(v, part, &S->counters[SITE_PQ], [=](const double *tot) {
-            const double pq = tot[0];
-            S->pq = pq;
-            if (!isfinite(pq)) S->stop = STOP_NON_FINITE;
-            else if (pq <= 0.0) S->stop = STOP_BREAKDOWN;
-            else S->alpha = S->rho / pq;
-        });
+        block_partial<1>(v, part);
     }
 };
 
-// ||b - A x|| at exit.
+// Partials of ||b - A x||^2 at exit.
 struct EpiTrue {
     const double *b;
-    SolveState *st;
+    const SolveState *st;
     double *part;
     double acc;
     __device__ bool skip() const { return st->zero_x != 0 || st->stop == STOP_NON_FINITE; }
@@ -226,80 +187,130 @@ struct EpiTrue {
     }
     __device__ void finish() {
         double v[1] = {acc};
-        SolveState *S = st;
-        reduce_finish<1>(v, part, &S->counters[SITE_TRUE], [=](const double *tot) { S->true_resnorm = sqrt(tot[0]); });
+        block_partial<1>(v, part);
     }
 };
 
 // ------------------------------------------------------------------ SpMV tilings
 constexpr int kStreamCap = 2048;   // nnz staged in LDS per tile
+#ifndef SPK_ROW_UNROLL
+#define SPK_ROW_UNROLL 4
+#endif
+constexpr int kRowUnroll = SPK_ROW_UNROLL;   // gathers in flight per row step
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The contiguous nnz range [s, e) of one tile is copied into LDS in 16-byte
+// chunks by the gfx950 global-to-LDS DMA (global_load_lds_dwordx4): lane l of
+// a wave writes LDS bytes [16 l, 16 l + 16) past the wave's base, so no VGPR
+// holds staged data.  The range is widened down to a 16-byte boundary (s0);
+// chunk c covers elements [s0 + c*EPC, s0 + (c+1)*EPC).  Only a chunk running
+// past the end of the array (the matrix's last chunk) is copied element-wise.
+template <typename T>
+struct Chunks {
+    static constexpr int EPC = 16 / sizeof(T);
+    static constexpr int MAXC = (kStreamCap / EPC + 1 + kBlock - 1) / kBlock;   // chunk rounds per thread
+    static constexpr int LDS = kStreamCap / EPC + 1;                              // chunks per tile
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename T>
+__device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, int64_t e, int64_t total, u32x4 *lds) {
+    constexpr int EPC = Chunks<T>::EPC;
+    const int64_t s0 = s & ~static_cast<int64_t>(EPC - 1);
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+#pragma unroll
+    for (int u = 0; u < Chunks<T>::MAXC; ++u) {
+        const int cbase = u * kBlock + wbase;                  // this wave's first chunk this round
+        if (s0 + static_cast<int64_t>(cbase) * EPC >= e) break;   // wave-uniform
+        const int64_t k = s0 + static_cast<int64_t>(cbase + lane) * EPC;
+        if (k < e) {
+            if (k + EPC <= total) {
+                __builtin_amdgcn_global_load_lds(static_cast<const void *>(g + k),
+                                                 (lds_void *)(lds + cbase), 16, 0, 0);
+            } else {
+                T *dst = reinterpret_cast<T *>(lds + cbase + lane);
+                for (int j = 0; j < EPC; ++j)
+                    if (k + j < total) dst[j] = g[k + j];
+            }
+        }
+    }
+}
+
+// Sum of row [a, b) with values/columns read from LDS (offsets s0v / s0c).
+template <typename V, typename I, typename X, typename C>
+__device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, int64_t b, int64_t s0v, int64_t s0c,
+                                          const X *__restrict__ x) {
+    C sum = 0;
+    for (int64_t k0 = a; k0 < b; k0 += kRowUnroll) {
+        C av[kRowUnroll], xv[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t k = k0 + u;
+            if (k < b) {
+                av[u] = static_cast<C>(widen(sv[k - s0v]));
+                xv[u] = static_cast<C>(x[sc[k - s0c]]);
+            } else {
+                av[u] = 0;
+                xv[u] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) sum = fma(av[u], xv[u], sum);
+    }
+    return sum;
+}
+
+template <typename V, typename I, typename X, typename C>
+__device__ __forceinline__ C row_from_global(const V *__restrict__ va, const I *__restrict__ ci, int64_t a, int64_t b,
+                                             const X *__restrict__ x, int nt) {
+    C sum = 0;
+    for (int64_t k = a; k < b; ++k) {
+        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(x[ci[k]]), sum);
+    }
+    return sum;
+}
+
+// LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
+// thread per row reduces from LDS while gathering x.  Occupancy (several
+// workgroups per CU) overlaps one workgroup's DMA with another's gathers.
 template <typename V, typename P, typename I, typename X, typename C, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, const P *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const V *__restrict__ va,
-                                                        const X *__restrict__ x, int remap, Epi epi_in) {
+                                                        const X *__restrict__ x, int remap, int nt, Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
-    __shared__ V sv[kStreamCap];
-    __shared__ I sc[kStreamCap];
-    const int tid = threadIdx.x;
+    __shared__ u32x4 lv[Chunks<V>::LDS];
+    __shared__ u32x4 lc[Chunks<I>::LDS];
+    const V *sv = reinterpret_cast<const V *>(lv);
+    const I *sc = reinterpret_cast<const I *>(lc);
     const int64_t T = (n + kTileRows - 1) / kTileRows;
     for (TileIter it(T, remap); it.t < it.end; it.t += it.stride) {
         const int64_t r0 = it.t * kTileRows;
-        const int64_t r1 = min(r0 + (int64_t)kTileRows, n);
-        const int64_t row = r0 + tid;
+        const int64_t r1 = min(r0 + static_cast<int64_t>(kTileRows), n);
         const int64_t s = static_cast<int64_t>(rp[r0]);
-        const int64_t cnt = static_cast<int64_t>(rp[r1]) - s;
+        const int64_t e = static_cast<int64_t>(rp[r1]);
+        const int64_t row = r0 + threadIdx.x;
         int64_t a = 0, b = 0;
         if (row < r1) {
-            a = static_cast<int64_t>(rp[row]) - s;
-            b = static_cast<int64_t>(rp[row + 1]) - s;
+            a = static_cast<int64_t>(rp[row]);
+            b = static_cast<int64_t>(rp[row + 1]);
         }
-        if (cnt <= kStreamCap) {
-            V tv[kStreamCap / kBlock];
-            I tc[kStreamCap / kBlock];
-#pragma unroll
-            for (int u = 0; u < kStreamCap / kBlock; ++u) {
-                const int64_t k = tid + u * kBlock;
-                if (k < cnt) {
-                    tv[u] = va[s + k];
-                    tc[u] = ci[s + k];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kStreamCap / kBlock; ++u) {
-                const int64_t k = tid + u * kBlock;
-                if (k < cnt) {
-                    sv[k] = tv[u];
-                    sc[k] = tc[u];
-                }
-            }
-            __syncthreads();
+        if (e - s <= kStreamCap) {
+            dma_chunks<V>(va, s, e, nnz, lv);
+            dma_chunks<I>(ci, s, e, nnz, lc);
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA has landed
+            __syncthreads();                 // ... and every other wave's
             if (row < r1) {
-                C sum = 0;
-                for (int64_t k0 = a; k0 < b; k0 += 8) {
-                    C av[8], xv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int64_t k = k0 + u;
-                        if (k < b) {
-                            av[u] = static_cast<C>(widen(sv[k]));
-                            xv[u] = static_cast<C>(x[sc[k]]);
-                        } else {
-                            av[u] = 0;
-                            xv[u] = 0;
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) sum = fma(av[u], xv[u], sum);
-                }
-                epi.row(row, sum);
+                const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
+                const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
+                epi.row(row, row_from_lds<V, I, X, C>(sv, sc, a, b, s0v, s0c, x));
             }
-            __syncthreads();
+            __syncthreads();                 // LDS free for the next tile
         } else if (row < r1) {
-            C sum = 0;
-            for (int64_t k = s + a; k < s + b; ++k) sum = fma(static_cast<C>(widen(va[k])), static_cast<C>(x[ci[k]]), sum);
-            epi.row(row, sum);
+            epi.row(row, row_from_global<V, I, X, C>(va, ci, a, b, x, nt));
         }
     }
     epi.finish();
@@ -309,7 +320,7 @@ template <typename V, typename P, typename I, typename X, typename C, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv_vector(int64_t n, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const V *__restrict__ va,
                                                         const X *__restrict__ x, int lanes_log2, int remap,
-                                                        Epi epi_in) {
+                                                        int nt, Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
     const int L = 1 << lanes_log2;
@@ -325,8 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int64_t n, const P *__re
             C sum = 0;
             if (row < r1) {
                 const int64_t a = static_cast<int64_t>(rp[row]), b = static_cast<int64_t>(rp[row + 1]);
-                for (int64_t k = a + lane; k < b; k += L)
-                    sum = fma(static_cast<C>(widen(va[k])), static_cast<C>(x[ci[k]]), sum);
+                for (int64_t k = a + lane; k < b; k += L) {
+                    sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(x[ci[k]]), sum);
+                }
             }
             for (int off = L >> 1; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
             if (row < r1 && lane == 0) epi.row(row, sum);
@@ -356,22 +368,83 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
         using I = pointee_t<decltype(ci)>;
         const V *va = static_cast<const V *>(A.va);
         const dim3 grid(t.grid), block(kBlock);
-        if (t.kind == 0)
-            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
-                               t.xcd_remap, epi);
-        else
+        if (t.kind == 0) {
+            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
+                               t.xcd_remap, t.nt, epi);
+        } else {
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
-                               t.lanes_log2, t.xcd_remap, epi);
+                               t.lanes_log2, t.xcd_remap, t.nt, epi);
+        }
         return hipGetLastError();
     });
 }
 
-// ------------------------------------------------------------------ vector kernels
+// ------------------------------------------------------------------ CG scalar + vector kernels
+// One workgroup: finish the initial residual (||b||, rho_0, first stop test).
+__global__ __launch_bounds__(kBlock) void k_init_finish(SolveState *st, const double *part, int G, double tau,
+                                                        int64_t max_iters, double *x, double *hist, int64_t hist_cap) {
+    double tot[2];
+    sum_partials<2>(part, G, tot);
+    if (threadIdx.x != 0) return;
+    st->x = x;
+    st->hist = hist;
+    st->hist_cap = hist_cap;
+    st->max_iters = max_iters;
+    st->base = 0;
+    st->iter = 0;
+    st->zero_x = 0;
+    st->stop = STOP_RUNNING;
+    st->alpha = 0.0;
+    st->pq = 0.0;
+    st->true_resnorm = __builtin_nan("");
+    const double bn = sqrt(tot[1]);
+    st->bnorm = bn;
+    st->thresh = tau * bn;
+    if (!isfinite(bn)) {
+        st->stop = STOP_NON_FINITE;
+        st->resnorm = bn;
+    } else if (bn == 0.0) {
+        st->zero_x = 1;
+        st->stop = STOP_CONVERGED;
+        st->resnorm = 0.0;
+        st->true_resnorm = 0.0;
+        st->rho[0] = 0.0;
+        if (hist && hist_cap > 0) hist[0] = 0.0;
+    } else {
+        const double rho = tot[0];
+        const double res = sqrt(rho);
+        st->rho[0] = rho;
+        st->resnorm = res;
+        if (hist && hist_cap > 0) hist[0] = res;
+        if (!isfinite(rho)) st->stop = STOP_NON_FINITE;
+        else if (res <= tau * bn) st->stop = STOP_CONVERGED;
+        else if (max_iters <= 0) st->stop = STOP_MAX_ITERS;
+    }
+}
+
+// x += alpha p, r -= alpha q with alpha = rho_k / (p.q); partials of r.r.
+// j: index of this iteration within the launched chunk.
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double *__restrict__ p,
                                                       double *__restrict__ r, const double *__restrict__ q,
-                                                      SolveState *st, double *part) {
+                                                      SolveState *st, const double *part_pq, int G_pq,
+                                                      double *part_rr, int j) {
     if (st->stop != STOP_RUNNING) return;
-    const double alpha = st->alpha;
+    const int64_t k = st->base + j;
+    double tot[1];
+    sum_partials<1>(part_pq, G_pq, tot);
+    const double pq = tot[0];
+    if (!isfinite(pq) || pq <= 0.0) {   // every workgroup sees the same pq and stops alike
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->stop = isfinite(pq) ? STOP_BREAKDOWN : STOP_NON_FINITE;
+        }
+        return;
+    }
+    const double alpha = st->rho[k & 3] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = alpha;
+    }
     double *__restrict__ x = st->x;
     double acc = 0.0;
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -410,30 +483,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double *_
         }
     }
     double v[1] = {acc};
-    reduce_finish<1>(v, part, &st->counters[SITE_RR], [=](const double *tot) {
-        const double rho_new = tot[0];
-        const int64_t k = st->iter + 1;
-        st->iter = k;
-        const double res = sqrt(rho_new);
-        st->resnorm = res;
-        if (st->hist && k < st->hist_cap) st->hist[k] = res;
-        if (!isfinite(rho_new)) {
-            st->stop = STOP_NON_FINITE;
-        } else if (res <= st->thresh) {
-            st->stop = STOP_CONVERGED;
-        } else if (k >= st->max_iters) {
-            st->stop = STOP_MAX_ITERS;
-        } else {
-            st->beta = rho_new / st->rho;
-            st->rho = rho_new;
-        }
-    });
+    block_partial<1>(v, part_rr);
 }
 
+// rho_{k+1} = r.r; stop test; p = r + beta p with beta = rho_{k+1} / rho_k.
 __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double *__restrict__ r,
-                                                       double *__restrict__ p, SolveState *st) {
+                                                       double *__restrict__ p, SolveState *st, const double *part_rr,
+                                                       int G_rr, int j) {
     if (st->stop != STOP_RUNNING) return;
-    const double beta = st->beta;
+    const int64_t k = st->base + j;
+    double tot[1];
+    sum_partials<1>(part_rr, G_rr, tot);
+    const double rho_new = tot[0];
+    const int64_t k1 = k + 1;
+    const double res = sqrt(rho_new);
+    int stop = STOP_RUNNING;
+    if (!isfinite(rho_new)) stop = STOP_NON_FINITE;
+    else if (res <= st->thresh) stop = STOP_CONVERGED;
+    else if (k1 >= st->max_iters) stop = STOP_MAX_ITERS;
+    const double beta = rho_new / st->rho[k & 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter = k1;
+        st->resnorm = res;
+        st->rho[k1 & 3] = rho_new;
+        if (st->hist && k1 < st->hist_cap) st->hist[k1] = res;
+        if (stop != STOP_RUNNING) st->stop = stop;
+    }
+    if (stop != STOP_RUNNING) return;
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     const int64_t n2 = n >> 1;
@@ -449,7 +525,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double *
     if ((n & 1) && gid == 0) p[n - 1] = fma(beta, p[n - 1], r[n - 1]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, SolveState *st) {
+// Advance the chunk base after `count` iterations (one thread).
+__global__ void k_chunk_end(SolveState *st, int count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->base += count;
+}
+
+__global__ __launch_bounds__(kBlock) void k_true_finish(SolveState *st, const double *part, int G) {
+    if (st->zero_x != 0 || st->stop == STOP_NON_FINITE) return;
+    double tot[1];
+    sum_partials<1>(part, G, tot);
+    if (threadIdx.x == 0) st->true_resnorm = sqrt(tot[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, const SolveState *st) {
     if (!st->zero_x) return;
     double *x = st->x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
@@ -470,7 +558,25 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
     }
     for (int64_t i = gid; i < n_rows; i += stride)
         if (rp[i + 1] < rp[i]) f |= VFLAG_DECREASING;
-    for (int64_t k = gid; k < nnz; k += stride) {
+    // column indices: 16-byte loads when aligned, element loads for the tail
+    constexpr int EPC = 16 / sizeof(I);
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(ci) & 15) == 0) {
+        const int64_t nch = nnz / EPC;
+        const u32x4 *c16 = reinterpret_cast<const u32x4 *>(ci);
+        for (int64_t g = gid; g < nch; g += stride) {
+            const u32x4 v = c16[g];
+            I e[EPC];
+            __builtin_memcpy(e, &v, 16);
+#pragma unroll
+            for (int j = 0; j < EPC; ++j) {
+                const int64_t c = static_cast<int64_t>(e[j]);
+                if (c < 0 || c >= n_cols) f |= VFLAG_BAD_COLUMN;
+            }
+        }
+        done = nch * EPC;
+    }
+    for (int64_t k = done + gid; k < nnz; k += stride) {
         const int64_t c = static_cast<int64_t>(ci[k]);
         if (c < 0 || c >= n_cols) f |= VFLAG_BAD_COLUMN;
     }
@@ -511,9 +617,9 @@ int grid_for(int64_t n, int per_thread, int cap) {
 }  // namespace
 
 // ==================================================================== launchers
-hipError_t launch_validate(const CsrDev &A, unsigned *flags, hipStream_t s) {
+hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s) {
     const int64_t work = A.n_rows > A.nnz ? A.n_rows : A.nnz;
-    const int grid = grid_for(work, 8, kMaxGrid);
+    const int grid = grid_for(work, 8, max_grid);
     return dispatch_idx(A, [&](auto rp, auto ci) {
         using P = pointee_t<decltype(rp)>;
         using I = pointee_t<decltype(ci)>;
@@ -557,8 +663,12 @@ static double *site(double *partials, int k) { return partials + static_cast<siz
 hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, double *r, double *p,
                           SolveState *st, double *partials, double tau, int64_t max_iters, double *hist,
                           int64_t hist_cap, hipStream_t s) {
-    EpiInit e{b, r, p, x, st, site(partials, SITE_INIT), tau, max_iters, hist, hist_cap, 0.0, 0.0};
-    return launch_family<double, double, double>(A, t, x, e, s);
+    EpiInit e{b, r, p, site(partials, SITE_INIT), 0.0, 0.0};
+    hipError_t err = launch_family<double, double, double>(A, t, x, e, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kBlock), 0, s, st, site(partials, SITE_INIT), t.grid, tau,
+                       max_iters, x, hist, hist_cap);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q, SolveState *st,
@@ -567,25 +677,34 @@ hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p
     return launch_family<double, double, double>(A, t, p, e, s);
 }
 
-hipError_t launch_cg_update(int64_t n, int grid, const double *p, double *r, const double *q, SolveState *st,
-                            double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_RR));
+hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, const double *p, double *r, const double *q,
+                            SolveState *st, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_PQ),
+                       spmv_grid, site(partials, SITE_RR), j);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_pupdate(int64_t n, int grid, const double *r, double *p, SolveState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_pupdate, dim3(grid), dim3(kBlock), 0, s, n, r, p, st);
+hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st, double *partials,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_pupdate, dim3(grid), dim3(kBlock), 0, s, n, r, p, st, site(partials, SITE_RR), grid, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_chunk_end(SolveState *st, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, st, count);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *b, double *x_caller,
                               SolveState *st, double *partials, int true_residual, hipStream_t s) {
-    (void)x_caller;
     hipLaunchKernelGGL(k_zero_x, dim3(grid_for(A.n_rows, 8, kMaxGrid)), dim3(kBlock), 0, s, A.n_rows, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !true_residual) return e;
     EpiTrue et{b, st, site(partials, SITE_TRUE), 0.0};
-    return launch_family<double, double, double>(A, t, x_caller, et, s);
+    e = launch_family<double, double, double>(A, t, x_caller, et, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_true_finish, dim3(1), dim3(kBlock), 0, s, st, site(partials, SITE_TRUE), t.grid);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s) {
