@@ -36,10 +36,37 @@ def parse():
     ap.add_argument("--N", type=int, default=215, help="stencil7 grid edge (n = N^3)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tau", type=float, default=1e-14)
+    ap.add_argument("--precision", choices=["fp64", "mixed_fp32", "mixed_bf16"], default="fp64",
+                    help="fp64 CG, or FP32/BF16 inner CG with FP64 refinement")
+    ap.add_argument("--inner", type=float, default=1e-4, help="inner reduction factor (mixed)")
     ap.add_argument("--cpu-iters", type=int, default=25, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also time the plain copy kernel")
+    ap.add_argument("--serve", action="store_true",
+                    help="batched-serving run: randsym instances, Poisson arrivals, p50/p99 latency")
+    ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--load", type=float, default=0.7, help="offered load / saturated throughput")
+    ap.add_argument("--oracle-sample", type=int, default=16, help="instances checked against the oracle")
     return ap.parse_args()
+
+
+def measured_traffic(args, N):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-kernel scaled), or None when
+    that summary is for other kernel sources or another workload."""
+    if args.precision != "fp64" or N != 215 or args.seed != 1:
+        return None
+    path = os.path.join(ROOT, "profiles", "spmv_pq_cg_fp64_stencil7_N215_traffic.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2510_08230_amd import profsum
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_digest") != profsum.kernel_digest():
+        return None
+    return d["traffic_bytes"]
 
 
 def main():
@@ -48,6 +75,9 @@ def main():
         print("bench.py measures one GPU only: multi-GPU runs are not part of this build "
               "(the sharded design is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
 
     import numpy as np
     import torch
@@ -72,6 +102,11 @@ def main():
     cfg.reduction_factor = args.tau
     cfg.max_iters = 1000
     cfg.exec_mode = spk.EXEC_HOST_LOOP
+    cfg.precision = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32,
+                     "mixed_bf16": spk.PREC_MIXED_BF16}[args.precision]
+    cfg.inner_reduction = args.inner
+    if args.precision != "fp64":
+        cfg.max_iters = 10000
 
     def step(profile):
         pl = spk.spk_plan_solve(ctx, M, cfg)
@@ -102,10 +137,15 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     value = n * iters / wall
 
-    bytes_spmv = nnz * (8 + 4) + (n + 1) * 4 + 2 * n * 8
+    if args.precision == "fp64":
+        bytes_spmv = nnz * (8 + 4) + (n + 1) * 4 + 2 * n * 8
+    else:   # inner SpMV: FP32/BF16 values, int32 columns, FP32 vectors
+        vb = 4 if args.precision == "mixed_fp32" else 2
+        bytes_spmv = nnz * (vb + 4) + (n + 1) * 4 + 2 * n * 4
     avg_ms = kms / max(klaunch, 1)
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9
     last = logs[-1]
+    traffic = measured_traffic(args, N)
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
         "value": value,
@@ -117,15 +157,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "mixed_fp32" else "bf16+f32+f64"),
         "data": "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD)",
-        "config": {"workload": "cg_fp64_stencil7_N%d" % N, "n": n, "nnz": nnz, "seed": args.seed,
+        "config": {"workload": "cg_%s_stencil7_N%d" % (args.precision, N), "n": n, "nnz": nnz, "seed": args.seed,
                    "tau": args.tau, "index_types": "int32/int32", "iterations_per_solve": last.iterations,
+                   "outer_iterations": last.outer_iterations,
                    "stop_reason": last.stop_reason, "rel_true_residual": last.true_resnorm / last.rhs_norm,
                    "solve_device_ms": last.elapsed_ms, "spmv_tiling": info},
         "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq> (q = A p fused with p.q)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": klaunch},
     }
     if args.copy_calib:
@@ -145,6 +186,133 @@ def main():
                                "kind": "oracle",
                                "sample": "FP64 oracle CG, same system, %d iterations (plus initial and "
                                          "true residual), %.1f s" % (res.iterations, dt)}
+    print(json.dumps(out), flush=True)
+
+
+def serve(args):
+    """Batched serving of uneven solves: every instance is randsym(n_i) with
+    n_i log-uniform in [1e3, 1e6] (seeded), b uniform, x0 = 0, solved to
+    ||b - A x|| <= 1e-12 ||b|| by FP32 CG + FP64 refinement in the server.
+    A closed-loop pass (all submitted at once) measures the saturated rate;
+    the timed pass submits at Poisson arrival times with rate load * that
+    rate.  Baseline: plain FP64 GPU solves, one at a time, same tolerance."""
+    import math
+    import threading
+
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2510_08230_amd import spk
+
+    dev = torch.device("cuda:0")
+    tau = 1e-12
+    sizes, seeds = inputs.instances(args.instances, 4, 1e3, 1e6)
+    mats, rhs = [], []
+    for n, sd in zip(sizes, seeds):
+        A = inputs.randsym(int(n), int(sd) % (1 << 31))
+        b = inputs.rhs(int(n), int(sd) % (1 << 31))
+        M = spk.CsrMatrix(torch.from_numpy(A.row_ptr).to(torch.int32).to(dev), torch.from_numpy(A.col).to(dev),
+                          torch.from_numpy(A.val).to(dev), A.n_rows, A.n_cols)
+        mats.append((A, M))
+        rhs.append((b, torch.from_numpy(b).to(dev)))
+    xs = [torch.zeros(int(n), dtype=torch.float64, device=dev) for n in sizes]
+    ctx = spk.spk_init(0, torch.cuda.current_stream(dev).cuda_stream)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.precision = spk.PREC_MIXED_FP32
+    cfg.reduction_factor = tau
+    cfg.inner_reduction = args.inner
+    cfg.max_iters = 100000
+    budget = int(args.budget_gb * (1 << 30))
+
+    def run_pass(arrivals):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        srv = spk.spk_server_create(ctx, budget, args.slots, cfg)
+        t0 = time.perf_counter()
+        tickets = []
+        for i, (_, M) in enumerate(mats):
+            if arrivals is not None:
+                delay = t0 + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(spk.spk_server_submit(srv, M, rhs[i][1], xs[i]))
+        spk.spk_server_drain(srv)
+        makespan = time.perf_counter() - t0
+        lats, iters, stops = [], [], []
+        for t in tickets:
+            done, st, log, lat = spk.spk_server_poll(srv, t)
+            assert done and st == spk.OK
+            lats.append(lat * 1e-9)
+            iters.append(log.iterations)
+            stops.append(log.stop_reason)
+        stats = spk.spk_server_get_stats(srv)
+        spk.spk_server_destroy(srv)
+        return makespan, np.array(lats), np.array(iters), stops, stats
+
+    run_pass(None)                                   # warm-up (graph capture, pools)
+    sat_makespan, _, sat_iters, _, _ = run_pass(None)
+    sat_rate = len(mats) / sat_makespan              # solves/s, closed loop
+    lam = args.load * sat_rate
+    u = np.array([inputs.unif(4, 5, i) for i in range(len(mats))])
+    arrivals = np.cumsum(-np.log1p(-(u + 1.0) / 2.0) / lam)
+    arrivals -= arrivals[0]
+    makespan, lats, iters, stops, stats = run_pass(arrivals)
+    nvec = np.array([int(n) for n in sizes])
+    updates = float(np.sum(nvec * iters))
+
+    # accuracy: GPU residual for all, oracle solution for a sample
+    import oracle
+    worst_rel, worst_res = 0.0, 0.0
+    sample = list(range(0, len(mats), max(1, len(mats) // max(args.oracle_sample, 1))))[: args.oracle_sample]
+    for i in range(len(mats)):
+        A = mats[i][0]
+        x = xs[i].cpu().numpy()
+        worst_res = max(worst_res, float(np.linalg.norm(oracle.residual(A, rhs[i][0], x)) / np.linalg.norm(rhs[i][0])))
+        if i in sample:
+            xo, _, _ = oracle.cg(A, rhs[i][0], tau=1e-14, max_iters=5000)
+            worst_rel = max(worst_rel, float(np.linalg.norm(x - xo) / np.linalg.norm(xo)))
+
+    # baseline: plain FP64 GPU solves one at a time, same tolerance
+    bcfg = spk.spk_solver_cfg_default()
+    bcfg.reduction_factor = tau
+    bcfg.max_iters = 100000
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base_updates = 0.0
+    for i, (_, M) in enumerate(mats):
+        pl = spk.spk_plan_solve(ctx, M, bcfg)
+        log = spk.spk_execute_solve(pl, rhs[i][1], xs[i])
+        spk.spk_free(pl)
+        base_updates += float(nvec[i]) * log.iterations
+    torch.cuda.synchronize()
+    base_time = time.perf_counter() - t0
+    spk.spk_finalize(ctx)
+
+    out = {
+        "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
+        "value": updates / makespan,
+        "unit": "updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 2, "ms_per_step": makespan * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic (seeded randsym instances, log-uniform sizes)",
+        "config": {"workload": "serve_randsym_%d_loguniform_1e3_1e6" % len(mats), "instances": len(mats),
+                   "sum_n": int(nvec.sum()), "tau": tau, "inner_reduction": args.inner,
+                   "budget_bytes": budget, "max_slots": args.slots, "offered_load": args.load,
+                   "arrival_rate_per_s": lam, "saturated_solves_per_s": sat_rate},
+        "latency_s": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99)),
+                      "max": float(lats.max())},
+        "solves_per_s": len(mats) / makespan,
+        "server_stats": stats,
+        "accuracy": {"max_rel_residual": worst_res, "max_rel_err_vs_oracle_sample": worst_rel,
+                     "oracle_sample": len(sample), "all_converged": all(s == 1 for s in stops)},
+        "baseline_fp64_one_at_a_time": {"seconds": base_time, "updates_per_s": base_updates / base_time,
+                                        "solves_per_s": len(mats) / base_time},
+        "speedup_vs_fp64_one_at_a_time": base_time / makespan,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -205,6 +205,64 @@ spk_status spk_free(spk_plan plan);
  * device time.  Used to measure the achievable HBM bandwidth. */
 spk_status spk_stream_copy(spk_ctx ctx, const void *src, void *dst, size_t bytes, double *ms);
 
+/* ---------------------------------------------------------------- serving
+ * A continuous-batching solve server.  Requests of uneven sizes arrive from
+ * any host thread; a worker thread admits each into a free slot once its
+ * workspace fits the HBM budget, and every live request advances in the same
+ * batched launches (per-request FP32 CG with FP64 dot products and FP64
+ * iterative refinement: the mixed-precision solve above, on per-request
+ * 256-row tiles).  Requests that arrive while others run join between tick
+ * batches.  A request's result is bitwise independent of which other
+ * requests share the batch.  Small systems being overhead-bound is the
+ * paper's observation (Sections 6.1-6.2); batching many of them into one
+ * launch per step is how this build serves them. */
+typedef struct spk_server_s *spk_server;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed;
+    int64_t ticks;          /* batched steps run */
+    int64_t peak_slots;     /* most requests live at once */
+    int64_t peak_bytes;     /* most workspace bytes held at once */
+    int64_t budget_bytes;
+    int64_t max_slots;
+} spk_server_stats;
+
+/* Workspace bytes one request of n unknowns and nnz stored entries needs
+ * (counted against the budget).  Pure host computation. */
+size_t spk_server_request_bytes(int64_t n, int64_t nnz);
+
+/* Create a server on the context's device with an HBM budget for request
+ * workspace and at most max_slots live requests.  cfg: precision must be
+ * SPK_PREC_MIXED_FP32; reduction_factor is the FP64 stop test
+ * ||b - A x|| <= reduction_factor ||b||, inner_reduction the inner CG's,
+ * max_iters caps inner iterations per request, max_outer refinement steps.
+ * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY. */
+spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_slots, const spk_solver_cfg *cfg,
+                             spk_server *out);
+
+/* Queue a solve of A x = b (device pointers; A square with int32 row_ptr and
+ * col_idx and F64 values; x holds the initial guess and receives the
+ * solution).  The caller keeps A, b, x alive and untouched until the request
+ * is done.  *ticket identifies it.  Errors: INVALID_ARG, UNSUPPORTED (index or
+ * value types), BUDGET (the request alone exceeds the budget).  A malformed
+ * CSR is detected on the GPU before admission and reported by poll. */
+spk_status spk_server_submit(spk_server srv, const spk_csr *A, const void *b, void *x, uint64_t *ticket);
+
+/* Non-blocking: *done = 1 once the request finished; then log and
+ * *latency_ns (submission to completion, host steady clock) are filled and
+ * the return value is the request's status (OK, INVALID_ARG for a malformed
+ * matrix, BUDGET, DEVICE). */
+spk_status spk_server_poll(spk_server srv, uint64_t ticket, int32_t *done, spk_log *log, int64_t *latency_ns);
+
+/* Block until every submitted request is done. */
+spk_status spk_server_drain(spk_server srv);
+
+spk_status spk_server_get_stats(spk_server srv, spk_server_stats *stats);
+const char *spk_server_last_error(spk_server srv);
+
+/* Finish all queued and live requests, then release the server. */
+spk_status spk_server_destroy(spk_server srv);
+
 #ifdef __cplusplus
 }
 #endif

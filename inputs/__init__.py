@@ -23,6 +23,64 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
 _LIB = os.path.join(_HERE, "libspkgen.so")
 _lib = None
+_DEV_SRC = os.path.join(_HERE, "gen_device.hip")
+_DEV_LIB = os.path.join(_HERE, "libspkgen_dev.so")
+_dev_lib = None
+
+
+def build_device(force: bool = True) -> str:
+    """Compile gen_device.hip (hipcc, gfx950, no FP contraction) into libspkgen_dev.so."""
+    if force or not os.path.exists(_DEV_LIB):
+        tmp = _DEV_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               _DEV_SRC, "-o", tmp])
+        os.replace(tmp, _DEV_LIB)
+    return _DEV_LIB
+
+
+def _get_dev():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB):
+            build_device()
+        lib = ctypes.CDLL(_DEV_LIB)
+        vp = ctypes.c_void_p
+        lib.gen_dev_stencil7.restype = ctypes.c_int
+        lib.gen_dev_stencil7.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int, vp, vp, vp,
+                                         ctypes.c_int, vp]
+        lib.gen_dev_vec.restype = ctypes.c_int
+        lib.gen_dev_vec.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
+        _dev_lib = lib
+    return _dev_lib
+
+
+def dev_stencil7(N: int, seed: int, delta: float = 1.0, f32x: bool = False, val_f32: bool = False,
+                 device: str = "cuda:0"):
+    """stencil7(N) generated on the GPU: (row_ptr int64, col int32, val f64/f32) torch tensors,
+    bit-identical to stencil7(N, seed, delta, f32x) from the host generator."""
+    import torch
+    n = N ** 3
+    nnz = stencil7_nnz(N)
+    rp = torch.empty(n + 1, dtype=torch.int64, device=device)
+    col = torch.empty(nnz, dtype=torch.int32, device=device)
+    val = torch.empty(nnz, dtype=torch.float32 if val_f32 else torch.float64, device=device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    rc = _get_dev().gen_dev_stencil7(N, seed, float(delta), int(f32x), rp.data_ptr(), col.data_ptr(),
+                                     val.data_ptr(), int(val_f32), stream)
+    if rc != 0:
+        raise RuntimeError("gen_dev_stencil7 failed (hipError %d)" % rc)
+    return rp, col, val
+
+
+def dev_vec(n: int, seed: int, stream_id: int, device: str = "cuda:0"):
+    """Uniform[-1,1) vector on the GPU; dev_vec(n, seed, 2) equals rhs(n, seed)."""
+    import torch
+    b = torch.empty(n, dtype=torch.float64, device=device)
+    rc = _get_dev().gen_dev_vec(n, seed, stream_id, b.data_ptr(), torch.cuda.current_stream(device).cuda_stream)
+    if rc != 0:
+        raise RuntimeError("gen_dev_vec failed (hipError %d)" % rc)
+    return b
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +115,8 @@ def _get():
         lib.gen_randsym_max_nnz.argtypes = [i64, i32]
         lib.gen_randsym.restype = i64
         lib.gen_randsym.argtypes = [i64, u64, f64, i32, i32, vp, vp, vp]
+        lib.gen_stencil7_row.restype = i32
+        lib.gen_stencil7_row.argtypes = [i64, u64, f64, i32, i64, vp, vp]
         lib.gen_rhs.restype = None
         lib.gen_rhs.argtypes = [i64, u64, vp]
         lib.gen_vec.restype = None
@@ -131,6 +191,18 @@ def randsym(n: int, seed: int, delta: float = 1.0, deg: int = 3, f32x: bool = Fa
     if nnz < 0:
         raise ValueError("randsym: bad arguments or out of memory (%d)" % nnz)
     return CSR(n, n, rp, col[:nnz].copy(), val[:nnz].copy())
+
+
+def stencil7_rows(N: int, seed: int, rows, delta: float = 1.0, f32x: bool = False):
+    """Entries of selected rows of stencil7(N) without building the matrix:
+    list of (cols int64 array, vals float64 array), from the host generator."""
+    out = []
+    cols = np.empty(7, np.int64)
+    vals = np.empty(7, np.float64)
+    for i in rows:
+        m = int(_get().gen_stencil7_row(N, seed, float(delta), int(f32x), int(i), _p(cols), _p(vals)))
+        out.append((cols[:m].copy(), vals[:m].copy()))
+    return out
 
 
 def rhs(n: int, seed: int) -> np.ndarray:

@@ -111,6 +111,27 @@ int gen_stencil7(int64_t N, uint64_t seed, double delta, int f32x,
     return 0;
 }
 
+/* Entries of one row i of stencil7(N) (ascending columns) into cols/vals
+ * (7 slots each); returns the count.  Same arithmetic as gen_stencil7. */
+int gen_stencil7_row(int64_t N, uint64_t seed, double delta, int f32x, int64_t i, int64_t *cols, double *vals) {
+    const int64_t s1 = N, s2 = N * N;
+    const int64_t x = i % N, y = (i / N) % N, z = i / s2;
+    int m = 0, dpos;
+    if (z > 0)     { cols[m] = i - s2; vals[m] = offdiag(seed, 3 * (uint64_t)(i - s2) + 2, f32x); ++m; }
+    if (y > 0)     { cols[m] = i - s1; vals[m] = offdiag(seed, 3 * (uint64_t)(i - s1) + 1, f32x); ++m; }
+    if (x > 0)     { cols[m] = i - 1;  vals[m] = offdiag(seed, 3 * (uint64_t)(i - 1) + 0, f32x); ++m; }
+    dpos = m; cols[m] = i; vals[m] = 0.0; ++m;
+    if (x < N - 1) { cols[m] = i + 1;  vals[m] = offdiag(seed, 3 * (uint64_t)i + 0, f32x); ++m; }
+    if (y < N - 1) { cols[m] = i + s1; vals[m] = offdiag(seed, 3 * (uint64_t)i + 1, f32x); ++m; }
+    if (z < N - 1) { cols[m] = i + s2; vals[m] = offdiag(seed, 3 * (uint64_t)i + 2, f32x); ++m; }
+    double d = 0.0;
+    for (int t = 0; t < m; ++t)
+        if (t != dpos) d += fabs(vals[t]);
+    d += delta;
+    vals[dpos] = f32x ? round_up_f32(d) : d;
+    return m;
+}
+
 static int cmp_i64(const void *a, const void *b) {
     int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
     return (x > y) - (x < y);

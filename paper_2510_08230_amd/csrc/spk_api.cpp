@@ -13,6 +13,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 using spk::CsrDev;
@@ -63,7 +64,14 @@ struct spk_plan_s {
     int64_t hist_cap = 0;
     SolveState *st = nullptr;
     SolveState *h_st = nullptr;          // pinned mirror
-    std::map<int, hipGraphExec_t> graphs;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (loop kind, iterations) -> graph
+    // mixed precision: inner CG on A32 with FP32 vectors
+    CsrDev A32{};
+    SpmvTune tune32{};
+    void *a32_vals = nullptr;            // owned rounded copy (null when A32 aliases A)
+    float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    SolveState *st_in = nullptr, *h_st_in = nullptr;
+    double *out_dev = nullptr, *h_out = nullptr;   // refinement norms (device / pinned)
     int profiling = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     size_t ev_used = 0;
@@ -327,7 +335,10 @@ spk_status prof_collect(spk_plan pl, int64_t useful) {
 }
 
 // ------------------------------------------------------------------ CG driver
-spk_status launch_iterations(spk_plan pl, int count, hipStream_t s, bool with_prof) {
+// Loop kinds: 0 = FP64 CG on A, 1 = FP32 inner CG on A32 (mixed precision).
+enum { LOOP_FP64 = 0, LOOP_FP32 = 1 };
+
+spk_status launch_iterations(spk_plan pl, int kind, int count, hipStream_t s, bool with_prof) {
     spk_ctx ctx = pl->ctx;
     const int64_t n = pl->A.n_rows;
     for (int i = 0; i < count; ++i) {
@@ -336,21 +347,30 @@ spk_status launch_iterations(spk_plan pl, int count, hipStream_t s, bool with_pr
             spk_status st = prof_begin(pl, &e);
             if (st != SPK_OK) return st;
         }
-        SPK_HIP(ctx, spk::launch_cg_spmv_pq(pl->A, pl->tune, pl->p, pl->q, pl->st, pl->partials, s));
+        if (kind == LOOP_FP64)
+            SPK_HIP(ctx, spk::launch_cg_spmv_pq(pl->A, pl->tune, pl->p, pl->q, pl->st, pl->partials, s));
+        else
+            SPK_HIP(ctx, spk::launch_cg_spmv_pq32(pl->A32, pl->tune32, pl->p32, pl->q32, pl->st_in, pl->partials, s));
         if (with_prof) {
             spk_status st = prof_end(pl, e);
             if (st != SPK_OK) return st;
         }
-        SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->tune.grid, i, pl->p, pl->r, pl->q, pl->st,
-                                           pl->partials, s));
-        SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, i, pl->r, pl->p, pl->st, pl->partials, s));
+        if (kind == LOOP_FP64) {
+            SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->tune.grid, i, pl->p, pl->r, pl->q, pl->st,
+                                               pl->partials, s));
+            SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, i, pl->r, pl->p, pl->st, pl->partials, s));
+        } else {
+            SPK_HIP(ctx, spk::launch_cg_update32(n, pl->vec_grid, pl->tune32.grid, i, pl->p32, pl->r32, pl->q32,
+                                                 pl->st_in, pl->partials, s));
+            SPK_HIP(ctx, spk::launch_cg_pupdate32(n, pl->vec_grid, i, pl->r32, pl->p32, pl->st_in, pl->partials, s));
+        }
     }
-    SPK_HIP(ctx, spk::launch_cg_chunk_end(pl->st, count, s));
+    SPK_HIP(ctx, spk::launch_cg_chunk_end(kind == LOOP_FP64 ? pl->st : pl->st_in, count, s));
     return SPK_OK;
 }
 
-spk_status graph_for(spk_plan pl, int count, hipGraphExec_t *out) {
-    auto it = pl->graphs.find(count);
+spk_status graph_for(spk_plan pl, int kind, int count, hipGraphExec_t *out) {
+    auto it = pl->graphs.find({kind, count});
     if (it != pl->graphs.end()) {
         *out = it->second;
         return SPK_OK;
@@ -358,7 +378,7 @@ spk_status graph_for(spk_plan pl, int count, hipGraphExec_t *out) {
     spk_ctx ctx = pl->ctx;
     hipGraph_t g = nullptr;
     SPK_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    spk_status s = launch_iterations(pl, count, ctx->cap_stream, false);
+    spk_status s = launch_iterations(pl, kind, count, ctx->cap_stream, false);
     hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (s != SPK_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -369,18 +389,18 @@ spk_status graph_for(spk_plan pl, int count, hipGraphExec_t *out) {
     e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
-    pl->graphs[count] = exec;
+    pl->graphs[{kind, count}] = exec;
     *out = exec;
     return SPK_OK;
 }
 
-spk_status run_chunk(spk_plan pl, int count, bool graph) {
-    if (!graph) return launch_iterations(pl, count, pl->ctx->stream, pl->profiling != 0);
+spk_status run_chunk(spk_plan pl, int kind, int count, bool graph) {
+    if (!graph) return launch_iterations(pl, kind, count, pl->ctx->stream, pl->profiling != 0);
     // binary decomposition into cached power-of-two graphs
     for (int bit = 1 << 10; bit >= 1; bit >>= 1) {
         while (count >= bit) {
             hipGraphExec_t ex = nullptr;
-            spk_status s = graph_for(pl, bit, &ex);
+            spk_status s = graph_for(pl, kind, bit, &ex);
             if (s != SPK_OK) return s;
             SPK_HIP(pl->ctx, hipGraphLaunch(ex, pl->ctx->stream));
             count -= bit;
@@ -389,9 +409,9 @@ spk_status run_chunk(spk_plan pl, int count, bool graph) {
     return SPK_OK;
 }
 
-spk_status pull_state(spk_plan pl) {
-    SPK_HIP(pl->ctx, hipMemcpyAsync(pl->h_st, pl->st, sizeof(SolveState), hipMemcpyDeviceToHost, pl->ctx->stream));
-    SPK_HIP(pl->ctx, hipStreamSynchronize(pl->ctx->stream));
+spk_status pull(spk_ctx ctx, void *host, const void *dev, size_t bytes) {
+    SPK_HIP(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return SPK_OK;
 }
 
@@ -411,6 +431,33 @@ int next_chunk(int prev, int64_t k0, double r0, int64_t k1, double r1, double th
     return std::min(next, 1024);
 }
 
+// Run CG iterations of one loop kind until the device-side state stops.
+// The state must already be initialised (init / refinement kernels).
+spk_status run_loop(spk_plan pl, int kind, int64_t max_iters, bool graph) {
+    spk_ctx ctx = pl->ctx;
+    SolveState *st = kind == LOOP_FP64 ? pl->st : pl->st_in;
+    SolveState *h = kind == LOOP_FP64 ? pl->h_st : pl->h_st_in;
+    const int cfg_chunk = pl->cfg.chunk_iters;
+    spk_status s = pull(ctx, h, st, sizeof(SolveState));
+    if (s != SPK_OK) return s;
+    int chunk = cfg_chunk > 0 ? cfg_chunk : 8;
+    int64_t launched = 0, k_prev = 0;
+    double r_prev = h->resnorm > 0.0 ? h->resnorm : 1.0;
+    while (h->stop == spk::STOP_RUNNING) {
+        const int64_t left = max_iters - launched;
+        const int c = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(chunk, left)));
+        if ((s = run_chunk(pl, kind, c, graph)) != SPK_OK) return s;
+        launched += c;
+        if ((s = pull(ctx, h, st, sizeof(SolveState))) != SPK_OK) return s;
+        if (h->stop != spk::STOP_RUNNING) break;
+        if (launched > max_iters + 1) return fail(ctx, SPK_ERR_INTERNAL, "iteration cap passed without stop");
+        if (cfg_chunk <= 0) chunk = next_chunk(chunk, k_prev, r_prev, h->iter, h->resnorm, h->thresh, max_iters - h->iter);
+        k_prev = h->iter;
+        r_prev = h->resnorm;
+    }
+    return SPK_OK;
+}
+
 // Hand a plan's workspace back to the context pools (stream already idle).
 void release_workspace(spk_plan pl) {
     spk_ctx ctx = pl->ctx;
@@ -421,12 +468,27 @@ void release_workspace(spk_plan pl) {
     ctx->dpool.put(pl->hist);
     ctx->dpool.put(pl->st);
     ctx->hpool.put(pl->h_st);
+    ctx->dpool.put(pl->a32_vals);
+    ctx->dpool.put(pl->r32);
+    ctx->dpool.put(pl->p32);
+    ctx->dpool.put(pl->q32);
+    ctx->dpool.put(pl->d32);
+    ctx->dpool.put(pl->st_in);
+    ctx->hpool.put(pl->h_st_in);
+    ctx->dpool.put(pl->out_dev);
+    ctx->hpool.put(pl->h_out);
     pl->r = pl->p = pl->q = pl->partials = pl->hist = nullptr;
-    pl->st = nullptr;
-    pl->h_st = nullptr;
+    pl->st = pl->h_st = pl->st_in = pl->h_st_in = nullptr;
+    pl->a32_vals = nullptr;
+    pl->r32 = pl->p32 = pl->q32 = pl->d32 = nullptr;
+    pl->out_dev = pl->h_out = nullptr;
 }
 
 }  // namespace
+
+namespace spk {
+int ctx_device(const spk_ctx_s *ctx) { return ctx ? ctx->device : 0; }
+}  // namespace spk
 
 // ==================================================================== C ABI
 extern "C" {
@@ -584,16 +646,25 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     if (cfg.solver != SPK_SOLVER_CG) return fail(ctx, SPK_ERR_UNSUPPORTED, "only CG is built");
     if (cfg.precond != SPK_PRECOND_NONE) return fail(ctx, SPK_ERR_UNSUPPORTED, "no preconditioner is built");
     if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
-    if (cfg.precision != SPK_PREC_FP64) return fail(ctx, SPK_ERR_UNSUPPORTED, "mixed precision not built yet");
+    if (cfg.precision < SPK_PREC_FP64 || cfg.precision > SPK_PREC_MIXED_BF16)
+        return fail(ctx, SPK_ERR_INVALID_ARG, "unknown precision");
     if (cfg.max_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_iters < 0");
     if (!(cfg.reduction_factor >= 0.0)) return fail(ctx, SPK_ERR_INVALID_ARG, "reduction_factor must be >= 0");
     if (cfg.exec_mode < SPK_EXEC_AUTO || cfg.exec_mode > SPK_EXEC_GRAPH)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown exec_mode");
     if (cfg.chunk_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "chunk_iters < 0");
+    const bool mixed = cfg.precision != SPK_PREC_FP64;
+    if (mixed && (!(cfg.inner_reduction > 0.0) || cfg.inner_reduction >= 1.0))
+        return fail(ctx, SPK_ERR_INVALID_ARG, "inner_reduction must be in (0, 1)");
+    if (mixed && cfg.max_outer < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_outer < 0");
     spk_status s = plan_common(ctx, A, out);
     if (s != SPK_OK) return s;
     if (A->n_rows != A->n_cols) return fail(ctx, SPK_ERR_INVALID_ARG, "solve needs a square matrix");
-    if (A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
+    if (!mixed && A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
+    if (mixed && A->val_type != SPK_F64 && A->val_type != SPK_F32)
+        return fail(ctx, SPK_ERR_INVALID_ARG, "mixed precision needs F64 or F32 values");
+    if (cfg.precision == SPK_PREC_MIXED_BF16 && A->val_type != SPK_F64)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "BF16 inner values are rounded from F64 values only");
 
     spk_plan pl = new spk_plan_s();
     pl->ctx = ctx;
@@ -602,42 +673,78 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     pl->cfg = cfg;
     const int64_t n = A->n_rows;
     const size_t nb = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(double);
-    auto cleanup = [&](spk_status code, const char *msg) {
+    const size_t nf = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(float);
+    auto cleanup = [&](spk_status code, const std::string &msg) {
         (void)hipStreamSynchronize(ctx->stream);
         release_workspace(pl);
         delete pl;
         return fail(ctx, code, msg);
     };
-    auto dget = [&](size_t bytes, double **out) {
+    auto dget = [&](size_t bytes, auto **out) {
         void *v = nullptr;
         const bool ok = ctx->dpool.get(bytes, &v) == hipSuccess;
-        *out = static_cast<double *>(v);
+        *out = static_cast<std::remove_reference_t<decltype(**out)> *>(v);
         return ok;
     };
-    void *stv = nullptr, *hstv = nullptr;
-    if (!dget(nb, &pl->r) || !dget(nb, &pl->p) || !dget(nb, &pl->q) ||
-        !dget(sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid, &pl->partials) ||
-        ctx->dpool.get(sizeof(SolveState), &stv) != hipSuccess || ctx->hpool.get(sizeof(SolveState), &hstv) != hipSuccess) {
-        pl->st = static_cast<SolveState *>(stv);
-        pl->h_st = static_cast<SolveState *>(hstv);
-        return cleanup(SPK_ERR_OUT_OF_MEMORY, "solve workspace");
-    }
-    pl->st = static_cast<SolveState *>(stv);
-    pl->h_st = static_cast<SolveState *>(hstv);
-    if (cfg.record_history) {
-        pl->hist_cap = cfg.max_iters + 1;
-        if (!dget(sizeof(double) * pl->hist_cap, &pl->hist)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "history buffer");
-    }
-    if (hipMemsetAsync(pl->st, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
-        hipMemsetAsync(pl->p, 0, nb, ctx->stream) != hipSuccess)
-        return cleanup(SPK_ERR_DEVICE, "workspace init");
-    std::memset(pl->h_st, 0, sizeof(SolveState));
-    s = choose_tune(pl, pl->p, pl->q);
-    if (s != SPK_OK) return cleanup(s, ctx->err.c_str());
-    {
-        // Streaming kernels: 4 workgroups per CU measured best for HBM copy rates.
-        const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
-        pl->vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 4));
+    auto hget = [&](size_t bytes, auto **out) {
+        void *v = nullptr;
+        const bool ok = ctx->hpool.get(bytes, &v) == hipSuccess;
+        *out = static_cast<std::remove_reference_t<decltype(**out)> *>(v);
+        return ok;
+    };
+    const size_t partial_bytes = sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid;
+    if (!dget(partial_bytes, &pl->partials)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "partials");
+    const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
+    // Streaming kernels: 4 workgroups per CU measured best for HBM copy rates.
+    pl->vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 4));
+
+    if (!mixed) {
+        if (!dget(nb, &pl->r) || !dget(nb, &pl->p) || !dget(nb, &pl->q) || !dget(sizeof(SolveState), &pl->st) ||
+            !hget(sizeof(SolveState), &pl->h_st))
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "solve workspace");
+        if (cfg.record_history) {
+            pl->hist_cap = cfg.max_iters + 1;
+            if (!dget(sizeof(double) * pl->hist_cap, &pl->hist)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "history");
+        }
+        if (hipMemsetAsync(pl->st, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
+            hipMemsetAsync(pl->p, 0, nb, ctx->stream) != hipSuccess)
+            return cleanup(SPK_ERR_DEVICE, "workspace init");
+        std::memset(pl->h_st, 0, sizeof(SolveState));
+        s = choose_tune(pl, pl->p, pl->q);
+        if (s != SPK_OK) return cleanup(s, ctx->err);
+    } else {
+        if (!dget(nf, &pl->r32) || !dget(nf, &pl->p32) || !dget(nf, &pl->q32) || !dget(nf, &pl->d32) ||
+            !dget(sizeof(SolveState), &pl->st_in) || !hget(sizeof(SolveState), &pl->h_st_in) ||
+            !dget(4 * sizeof(double), &pl->out_dev) || !hget(4 * sizeof(double), &pl->h_out))
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "mixed workspace");
+        // inner matrix view: rounded copy of F64 values, or the F32 values themselves
+        pl->A32 = pl->A;
+        if (A->val_type == SPK_F64) {
+            const bool bf = cfg.precision == SPK_PREC_MIXED_BF16;
+            void *dst = nullptr;
+            if (ctx->dpool.get(std::max<size_t>(1, A->nnz * (bf ? 2 : 4)), &dst) != hipSuccess)
+                return cleanup(SPK_ERR_OUT_OF_MEMORY, "low-precision value copy");
+            pl->a32_vals = dst;
+            if (A->nnz > 0 &&
+                spk::launch_round_values(A->nnz, static_cast<const double *>(A->values), dst, bf ? 1 : 0,
+                                         ctx->num_cu * 4, ctx->stream) != hipSuccess)
+                return cleanup(SPK_ERR_DEVICE, "value rounding");
+            pl->A32.va = dst;
+            pl->A32.val_t = bf ? SPK_BF16 : SPK_F32;
+        }
+        if (hipMemsetAsync(pl->st_in, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
+            hipMemsetAsync(pl->p32, 0, nf, ctx->stream) != hipSuccess)
+            return cleanup(SPK_ERR_DEVICE, "workspace init");
+        std::memset(pl->h_st_in, 0, sizeof(SolveState));
+        // Inner SpMV (many launches): timed candidates on A32.  Refinement SpMV
+        // (a few launches): launch-shape heuristic on A.
+        const CsrDev outer = pl->A;
+        pl->A = pl->A32;
+        s = choose_tune(pl, pl->p32, pl->q32);
+        pl->A = outer;
+        if (s != SPK_OK) return cleanup(s, ctx->err);
+        pl->tune32 = pl->tune;
+        pl->tune = heuristic_tune(ctx, pl->A);
     }
     int mode = cfg.exec_mode;
     if (mode == SPK_EXEC_AUTO) mode = (A->nnz < 4000000) ? SPK_EXEC_GRAPH : SPK_EXEC_HOST_LOOP;
@@ -664,14 +771,95 @@ spk_status spk_execute_spmv(spk_plan pl, const void *x, void *y) {
     return prof_collect(pl, pl->ev_used);
 }
 
+static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log *L, bool graph) {
+    spk_ctx ctx = pl->ctx;
+    const spk_solver_cfg &cfg = pl->cfg;
+    SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->p, pl->st, pl->partials,
+                                     cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
+    spk_status s = run_loop(pl, LOOP_FP64, cfg.max_iters, graph);
+    if (s != SPK_OK) return s;
+    SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual, ctx->stream));
+    if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
+    const SolveState &h = *pl->h_st;
+    if (pl->profiling) {
+        const int64_t useful = h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+        if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
+    }
+    L->iterations = h.iter;
+    L->outer_iterations = 0;
+    L->implicit_resnorm = h.resnorm;
+    L->true_resnorm = cfg.true_residual ? h.true_resnorm : std::nan("");
+    L->rhs_norm = h.bnorm;
+    L->stop_reason = h.stop;
+    return SPK_OK;
+}
+
+// Mixed precision with FP64 iterative refinement (Wilkinson/Moler; the
+// three-precision form of Carson & Higham 2018 with FP32/BF16 factors):
+//   repeat: r = b - A x (FP64); stop if ||r|| <= tau ||b||;
+//           solve A32 d = fl32(r) by FP32 CG (FP64 dots) to inner_reduction;
+//           x += d.
+static spk_status execute_mixed(spk_plan pl, const double *b, double *x, spk_log *L, bool graph) {
+    spk_ctx ctx = pl->ctx;
+    const spk_solver_cfg &cfg = pl->cfg;
+    const int64_t n = pl->A.n_rows;
+    int64_t inner_total = 0, outer = 0;
+    double bnorm = 0.0, rnorm = 0.0;
+    int stop = spk::STOP_RUNNING;
+    spk_status s = SPK_OK;
+    while (true) {
+        SPK_HIP(ctx, spk::launch_ir_residual(pl->A, pl->tune, b, x, pl->r32, pl->p32, pl->d32, pl->st_in,
+                                             pl->partials, cfg.inner_reduction, cfg.max_iters - inner_total,
+                                             pl->out_dev, ctx->stream));
+        if ((s = pull(ctx, pl->h_out, pl->out_dev, 3 * sizeof(double))) != SPK_OK) return s;
+        rnorm = pl->h_out[0];
+        bnorm = pl->h_out[2];
+        if (!std::isfinite(bnorm) || !std::isfinite(rnorm)) {
+            stop = spk::STOP_NON_FINITE;
+            break;
+        }
+        if (bnorm == 0.0) {
+            SPK_HIP(ctx, hipMemsetAsync(x, 0, sizeof(double) * n, ctx->stream));
+            rnorm = 0.0;
+            stop = spk::STOP_CONVERGED;
+            break;
+        }
+        if (rnorm <= cfg.reduction_factor * bnorm) {
+            stop = spk::STOP_CONVERGED;
+            break;
+        }
+        if (outer >= cfg.max_outer || inner_total >= cfg.max_iters) {
+            stop = spk::STOP_MAX_ITERS;
+            break;
+        }
+        if ((s = run_loop(pl, LOOP_FP32, cfg.max_iters - inner_total, graph)) != SPK_OK) return s;
+        const SolveState &h = *pl->h_st_in;
+        inner_total += h.iter;
+        if ((h.stop == spk::STOP_BREAKDOWN || h.stop == spk::STOP_NON_FINITE) && h.iter == 0) {
+            stop = h.stop;
+            break;
+        }
+        SPK_HIP(ctx, spk::launch_ir_correct(n, pl->vec_grid, x, pl->d32, ctx->stream));
+        ++outer;
+    }
+    if (pl->profiling) {
+        if ((s = prof_collect(pl, inner_total)) != SPK_OK) return s;
+    }
+    L->iterations = inner_total;
+    L->outer_iterations = outer;
+    L->implicit_resnorm = rnorm;
+    L->true_resnorm = rnorm;   // the last refinement residual is b - A x in FP64
+    L->rhs_norm = bnorm;
+    L->stop_reason = stop;
+    return SPK_OK;
+}
+
 spk_status spk_execute_solve(spk_plan pl, const void *b_in, void *x_in, spk_log *log) {
     if (!pl || pl->kind != 1) return SPK_ERR_INVALID_ARG;
     spk_ctx ctx = pl->ctx;
     const int64_t n = pl->A.n_rows;
     if (n > 0 && (!b_in || !x_in)) return fail(ctx, SPK_ERR_INVALID_ARG, "null vector");
     SPK_HIP(ctx, hipSetDevice(ctx->device));
-    const double *b = static_cast<const double *>(b_in);
-    double *x = static_cast<double *>(x_in);
     spk_log L;
     std::memset(&L, 0, sizeof(L));
     if (n == 0) {
@@ -680,48 +868,17 @@ spk_status spk_execute_solve(spk_plan pl, const void *b_in, void *x_in, spk_log 
         if (log) *log = L;
         return SPK_OK;
     }
-    const spk_solver_cfg &cfg = pl->cfg;
     const bool graph = pl->info.exec_mode == SPK_EXEC_GRAPH && !pl->profiling;
     SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->p, pl->st, pl->partials,
-                                     cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
-    int chunk = cfg.chunk_iters > 0 ? cfg.chunk_iters : 8;
-    int64_t launched = 0, k_prev = 0;
-    double r_prev = -1.0;
-    spk_status s = SPK_OK;
-    while (true) {
-        const int64_t left = cfg.max_iters - launched;
-        const int c = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(chunk, left)));
-        if ((s = run_chunk(pl, c, graph)) != SPK_OK) return s;
-        launched += c;
-        if ((s = pull_state(pl)) != SPK_OK) return s;
-        const SolveState &h = *pl->h_st;
-        if (r_prev < 0.0) r_prev = h.bnorm > 0.0 ? h.bnorm : 1.0;
-        if (h.stop != spk::STOP_RUNNING) break;
-        if (launched > cfg.max_iters + 1) return fail(ctx, SPK_ERR_INTERNAL, "iteration cap passed without stop");
-        if (cfg.chunk_iters <= 0)
-            chunk = next_chunk(chunk, k_prev, r_prev, h.iter, h.resnorm, h.thresh, cfg.max_iters - h.iter);
-        k_prev = h.iter;
-        r_prev = h.resnorm;
-    }
-    SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual, ctx->stream));
+    spk_status s = pl->cfg.precision == SPK_PREC_FP64
+                       ? execute_fp64(pl, static_cast<const double *>(b_in), static_cast<double *>(x_in), &L, graph)
+                       : execute_mixed(pl, static_cast<const double *>(b_in), static_cast<double *>(x_in), &L, graph);
+    if (s != SPK_OK) return s;
     SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-    if ((s = pull_state(pl)) != SPK_OK) return s;
+    SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
     float ms = 0.f;
     SPK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    if (pl->profiling) {
-        const SolveState &h = *pl->h_st;
-        const int64_t useful = h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
-        if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
-    }
-    const SolveState &h = *pl->h_st;
-    L.iterations = h.iter;
-    L.outer_iterations = 0;
-    L.implicit_resnorm = h.resnorm;
-    L.true_resnorm = cfg.true_residual ? h.true_resnorm : std::nan("");
-    L.rhs_norm = h.bnorm;
-    L.stop_reason = h.stop;
-    L.converged = h.stop == spk::STOP_CONVERGED;
+    L.converged = L.stop_reason == SPK_STOP_CONVERGED;
     L.elapsed_ms = ms;
     if (log) *log = L;
     return SPK_OK;

@@ -1,0 +1,220 @@
+// Device helpers shared by the gfx950 kernel translation units: value
+// widening, fixed-order reductions, the LDS-DMA tile staging of CSR values and
+// column indices, and the per-row reducers.  Everything here is internal
+// linkage (header-only, inline/static).
+#pragma once
+
+#include "spk_internal.h"
+
+#include <cmath>
+#include <type_traits>
+
+namespace spk {
+namespace dev {
+
+struct bf16s { uint16_t bits; };
+
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(_Float16 v) { return static_cast<float>(v); }
+__device__ __forceinline__ float widen(bf16s v) { return __uint_as_float(static_cast<unsigned>(v.bits) << 16); }
+
+// Matrix-value load, optionally non-temporal (streamed data that should not
+// displace the gathered vector from the caches).
+template <typename T>
+__device__ __forceinline__ T ldv(const T *p, int nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+__device__ __forceinline__ bf16s ldv(const bf16s *p, int nt) {
+    bf16s r;
+    r.bits = nt ? __builtin_nontemporal_load(&p->bits) : p->bits;
+    return r;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Tiles visited by this workgroup.
+struct TileIter {
+    int64_t t, end, stride;
+    __device__ TileIter(int64_t T, int remap) {
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        if (remap && G >= kNumXcd) {
+            const int64_t xcd = b % kNumXcd, m = b / kNumXcd;
+            const int64_t M = (G - xcd + kNumXcd - 1) / kNumXcd;   // workgroups on this XCD
+            t = xcd * T / kNumXcd + m;
+            end = (xcd + 1) * T / kNumXcd;
+            stride = M;
+        } else {
+            t = b;
+            end = T;
+            stride = G;
+        }
+    }
+};
+
+// Block-level fixed-order reduction of NV doubles; thread 0 stores the
+// workgroup's partials at partials[j * kMaxGrid + blockIdx.x].
+template <int NV>
+__device__ __forceinline__ void block_partial(double (&v)[NV], double *partials) {
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const double t = wave_sum(v[j]);
+        if (lane == 0) sh[j][wid] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double t = sh[j][0];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
+            partials[static_cast<size_t>(j) * kMaxGrid + blockIdx.x] = t;
+        }
+    }
+}
+
+// Every thread of the calling workgroup receives the fixed-order sums of the
+// G partials partials[j * stride + b] (b < G) a previous launch stored
+// (identical in every workgroup that calls it).
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *partials, int64_t G, int64_t stride, double (&tot)[NV]) {
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double t = 0.0;
+        for (int64_t b = threadIdx.x; b < G; b += kBlock) t += partials[static_cast<size_t>(j) * stride + b];
+        t = wave_sum(t);
+        if (lane == 0) sh[j][wid] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double t = sh[j][0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
+        tot[j] = t;
+    }
+    __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *partials, int G, double (&tot)[NV]) {
+    sum_partials<NV>(partials, static_cast<int64_t>(G), static_cast<int64_t>(kMaxGrid), tot);
+}
+
+// Fixed-order workgroup reduction of NV doubles; thread 0 stores total j at
+// out[j * stride].  Safe to call repeatedly (trailing barrier).
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double *out, int64_t stride) {
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const double t = wave_sum(v[j]);
+        if (lane == 0) sh[j][wid] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double t = sh[j][0];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
+            out[static_cast<size_t>(j) * stride] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ SpMV tilings
+constexpr int kStreamCap = 2048;   // nnz staged in LDS per tile
+#ifndef SPK_ROW_UNROLL
+#define SPK_ROW_UNROLL 4
+#endif
+constexpr int kRowUnroll = SPK_ROW_UNROLL;   // gathers in flight per row step
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The contiguous nnz range [s, e) of one tile is copied into LDS in 16-byte
+// chunks by the gfx950 global-to-LDS DMA (global_load_lds_dwordx4): lane l of
+// a wave writes LDS bytes [16 l, 16 l + 16) past the wave's base, so no VGPR
+// holds staged data.  The range is widened down to a 16-byte boundary (s0);
+// chunk c covers elements [s0 + c*EPC, s0 + (c+1)*EPC).  Only a chunk running
+// past the end of the array (the matrix's last chunk) is copied element-wise.
+template <typename T>
+struct Chunks {
+    static constexpr int EPC = 16 / sizeof(T);
+    static constexpr int MAXC = (kStreamCap / EPC + 1 + kBlock - 1) / kBlock;   // chunk rounds per thread
+    static constexpr int LDS = kStreamCap / EPC + 1;                              // chunks per tile
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename T>
+__device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, int64_t e, int64_t total, u32x4 *lds) {
+    constexpr int EPC = Chunks<T>::EPC;
+    const int64_t s0 = s & ~static_cast<int64_t>(EPC - 1);
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+#pragma unroll
+    for (int u = 0; u < Chunks<T>::MAXC; ++u) {
+        const int cbase = u * kBlock + wbase;                  // this wave's first chunk this round
+        if (s0 + static_cast<int64_t>(cbase) * EPC >= e) break;   // wave-uniform
+        const int64_t k = s0 + static_cast<int64_t>(cbase + lane) * EPC;
+        if (k < e) {
+            if (k + EPC <= total) {
+                __builtin_amdgcn_global_load_lds(static_cast<const void *>(g + k),
+                                                 (lds_void *)(lds + cbase), 16, 0, 0);
+            } else {
+                T *dst = reinterpret_cast<T *>(lds + cbase + lane);
+                for (int j = 0; j < EPC; ++j)
+                    if (k + j < total) dst[j] = g[k + j];
+            }
+        }
+    }
+}
+
+// Sum of row [a, b) with values/columns read from LDS (offsets s0v / s0c).
+template <typename V, typename I, typename X, typename C>
+__device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, int64_t b, int64_t s0v, int64_t s0c,
+                                          const X *__restrict__ x) {
+    C sum = 0;
+    for (int64_t k0 = a; k0 < b; k0 += kRowUnroll) {
+        C av[kRowUnroll], xv[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t k = k0 + u;
+            if (k < b) {
+                av[u] = static_cast<C>(widen(sv[k - s0v]));
+                xv[u] = static_cast<C>(x[sc[k - s0c]]);
+            } else {
+                av[u] = 0;
+                xv[u] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) sum = fma(av[u], xv[u], sum);
+    }
+    return sum;
+}
+
+template <typename V, typename I, typename X, typename C>
+__device__ __forceinline__ C row_from_global(const V *__restrict__ va, const I *__restrict__ ci, int64_t a, int64_t b,
+                                             const X *__restrict__ x, int nt) {
+    C sum = 0;
+    for (int64_t k = a; k < b; ++k) {
+        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(x[ci[k]]), sum);
+    }
+    return sum;
+}
+
+}  // namespace dev
+}  // namespace spk

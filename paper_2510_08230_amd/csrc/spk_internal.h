@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct spk_ctx_s;
+
 namespace spk {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
@@ -24,7 +26,7 @@ enum Stop : int32_t {
 
 // Reduction sites: each owns an arrival counter and a partials slab.
 enum Site : int { SITE_INIT = 0, SITE_PQ = 1, SITE_RR = 2, SITE_TRUE = 3, SITE_COUNT = 4 };
-constexpr int kSiteWidth = 2;      // values reduced at once per site (max)
+constexpr int kSiteWidth = 3;      // values reduced at once per site (max)
 
 // Device-resident scalars of one CG solve.  Loop kernels read only fields
 // written by earlier launches; workgroup 0 of a launch writes the results.
@@ -40,7 +42,7 @@ struct SolveState {
     int64_t max_iters;
     int32_t stop;         // Stop
     int32_t zero_x;       // b == 0: the finaliser sets x = 0
-    double *x;            // caller's solution vector for this execute
+    void *x;              // solution vector of this solve (FP64 x, or FP32 d of an inner solve)
     double *hist;         // optional ||r_k|| history
     int64_t hist_cap;
 };
@@ -86,6 +88,23 @@ hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, const dou
 hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st,
                              double *partials, hipStream_t s);
 hipError_t launch_cg_chunk_end(SolveState *st, int count, hipStream_t s);
+
+// Mixed precision: inner CG on FP32 vectors (A32 values F32, F16 or BF16),
+// refinement steps in FP64 (A values F64, or F32 taken as exact).
+hipError_t launch_cg_spmv_pq32(const CsrDev &A32, const SpmvTune &t, const float *p, float *q, SolveState *st,
+                               double *partials, hipStream_t s);
+hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, const float *p, float *r, const float *q,
+                              SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cg_pupdate32(int64_t n, int grid, int j, const float *r, float *p, SolveState *st,
+                               double *partials, hipStream_t s);
+// r = b - A x (FP64); r32 = p32 = fl32(r), d32 = 0; inner state set up;
+// out[0] = ||r||, out[1] = ||r32|| (device doubles).
+hipError_t launch_ir_residual(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, float *r32,
+                              float *p32, float *d32, SolveState *in, double *partials, double tau_in,
+                              int64_t max_inner, double *out, hipStream_t s);
+hipError_t launch_ir_correct(int64_t n, int grid, double *x, const float *d, hipStream_t s);
+// Round FP64 values to FP32 (bf16 = 0) or BF16 (bf16 = 1, round to nearest even).
+hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int bf16, int grid, hipStream_t s);
 // Sets x = 0 when b == 0, then (optionally) recomputes ||b - A x|| into the state.
 hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *b, double *x,
                               SolveState *st, double *partials, int true_residual, hipStream_t s);
@@ -94,5 +113,72 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipSt
 
 // Workgroups of the SpMV kernel resident per CU for this tune/type (occupancy API).
 int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t);
+
+// HIP device of a context (spk_api.cpp).
+int ctx_device(const struct ::spk_ctx_s *ctx);
+
+}  // namespace spk
+
+// ==== batched serving ==========================================================
+namespace spk {
+
+// Per-slot life cycle, advanced on the device once per tick.
+enum Phase : int32_t {
+    PH_FREE = 0,     // slot unused
+    PH_OUTER = 1,    // refinement residual r = b - A x (FP64) this tick
+    PH_INNER = 2,    // FP32 CG iterations on A32 d = r32
+    PH_CORRECT = 3,  // x += d this tick
+    PH_ZEROX = 4,    // b == 0: x = 0 this tick
+    PH_DONE = 5      // finished; waiting for the host to retire it
+};
+
+// Per-slot partial-sum sites (kPartSites doubles per tile).
+enum : int { PART_PQ = 0, PART_RR = 1, PART_OUT = 2 /* 3 sites: r.r, r32.r32, b.b */, kPartSites = 5 };
+
+// Written by the host at admission; read-only on the device.
+struct SlotDesc {
+    int64_t n, nnz, tiles;
+    const int32_t *rp, *ci;
+    const double *va64;     // the request's FP64 values
+    const float *va32;      // rounded copy (slot workspace)
+    const double *b;
+    double *x;
+    float *r, *p, *q, *d;   // slot workspace
+    double *part;           // slot workspace: kPartSites * tiles
+    double tau, tau_in;
+    int64_t max_iters, max_outer;
+};
+
+// Device-resident per-slot scalars.
+struct SlotState {
+    double rho[4];
+    double thresh_in, bnorm, rnorm, alpha, beta;
+    int64_t iter_in, iters, outer;
+    int32_t phase, next_phase, stop_in, stop;
+};
+
+// Compact per-slot record the host polls after each batch of ticks.
+struct SlotStatus {
+    int32_t phase, stop;
+    int64_t iters, outer;
+    double rnorm, bnorm;
+};
+
+// Device tables of one server: counts plus tile and slot lists.
+struct BatchDev {
+    const int32_t *counts;   // [0] live tiles, [1] live slots
+    const int2 *tiles;       // (slot, local tile)
+    const int32_t *slots;    // live slot ids
+    const SlotDesc *desc;
+    SlotState *state;
+    SlotStatus *status;
+    int tile_grid, slot_grid;
+};
+
+// One tick: six launches advancing every live slot by one step of its phase.
+hipError_t launch_batch_tick(const BatchDev &B, hipStream_t s);
+// FP64 -> FP32 values of a newly admitted request.
+hipError_t launch_round_f32(int64_t nnz, const double *src, float *dst, int grid, hipStream_t s);
+int batch_tile_blocks_per_cu();
 
 }  // namespace spk

@@ -25,7 +25,7 @@
 // iteration (chunk base + index within the chunk), so no launch reads a
 // location that it writes.  Kernels return at once when the stop flag is
 // set, so iterations enqueued past convergence cost only empty launches.
-#include "spk_internal.h"
+#include "spk_device.h"
 
 #include <cmath>
 #include <type_traits>
@@ -33,97 +33,7 @@
 namespace spk {
 namespace {
 
-struct bf16s { uint16_t bits; };
-
-__device__ __forceinline__ double widen(double v) { return v; }
-__device__ __forceinline__ float widen(float v) { return v; }
-__device__ __forceinline__ float widen(_Float16 v) { return static_cast<float>(v); }
-__device__ __forceinline__ float widen(bf16s v) { return __uint_as_float(static_cast<unsigned>(v.bits) << 16); }
-
-// Matrix-value load, optionally non-temporal (streamed data that should not
-// displace the gathered vector from the caches).
-template <typename T>
-__device__ __forceinline__ T ldv(const T *p, int nt) {
-    return nt ? __builtin_nontemporal_load(p) : *p;
-}
-__device__ __forceinline__ bf16s ldv(const bf16s *p, int nt) {
-    bf16s r;
-    r.bits = nt ? __builtin_nontemporal_load(&p->bits) : p->bits;
-    return r;
-}
-
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Tiles visited by this workgroup.
-struct TileIter {
-    int64_t t, end, stride;
-    __device__ TileIter(int64_t T, int remap) {
-        const int64_t G = gridDim.x, b = blockIdx.x;
-        if (remap && G >= kNumXcd) {
-            const int64_t xcd = b % kNumXcd, m = b / kNumXcd;
-            const int64_t M = (G - xcd + kNumXcd - 1) / kNumXcd;   // workgroups on this XCD
-            t = xcd * T / kNumXcd + m;
-            end = (xcd + 1) * T / kNumXcd;
-            stride = M;
-        } else {
-            t = b;
-            end = T;
-            stride = G;
-        }
-    }
-};
-
-// Block-level fixed-order reduction of NV doubles; thread 0 stores the
-// workgroup's partials at partials[j * kMaxGrid + blockIdx.x].
-template <int NV>
-__device__ __forceinline__ void block_partial(double (&v)[NV], double *partials) {
-    __shared__ double sh[NV][kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const double t = wave_sum(v[j]);
-        if (lane == 0) sh[j][wid] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            double t = sh[j][0];
-#pragma unroll
-            for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
-            partials[static_cast<size_t>(j) * kMaxGrid + blockIdx.x] = t;
-        }
-    }
-}
-
-// Every thread of the calling workgroup receives the fixed-order sums of the
-// G partials a previous launch stored (identical in every workgroup).
-template <int NV>
-__device__ __forceinline__ void sum_partials(const double *partials, int G, double (&tot)[NV]) {
-    __shared__ double sh[NV][kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        double t = 0.0;
-        for (int b = threadIdx.x; b < G; b += kBlock) t += partials[static_cast<size_t>(j) * kMaxGrid + b];
-        t = wave_sum(t);
-        if (lane == 0) sh[j][wid] = t;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        double t = sh[j][0];
-#pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) t += sh[j][w];
-        tot[j] = t;
-    }
-    __syncthreads();
-}
+using namespace dev;
 
 // ------------------------------------------------------------------ epilogues
 template <class X>
@@ -156,21 +66,50 @@ struct EpiInit {
     }
 };
 
-// q = A p; partials of p.q.
+// q = A p (stored in T); partials of p.q accumulated in FP64 from the stored values.
+template <typename T>
 struct EpiPq {
-    double *q;
-    const double *p;
+    T *q;
+    const T *p;
     const SolveState *st;
     double *part;
     double acc;
     __device__ bool skip() const { return st->stop != STOP_RUNNING; }
-    __device__ void row(int64_t i, double s) {
-        q[i] = s;
-        acc = fma(p[i], s, acc);
+    template <class C>
+    __device__ void row(int64_t i, C s) {
+        const T qi = static_cast<T>(s);
+        q[i] = qi;
+        acc = fma(static_cast<double>(p[i]), static_cast<double>(qi), acc);
     }
     __device__ void finish() {
         double v[1] = {acc};
         block_partial<1>(v, part);
+    }
+};
+
+// Refinement step of the mixed-precision solve: r = b - A x in FP64, then the
+// inner right-hand side r32 = p32 = fl32(r) and d32 = 0; partials of ||r||^2
+// (FP64), ||r32||^2 (FP64 sums of the rounded values) and ||b||^2.
+struct EpiIrResidual {
+    const double *b;
+    float *r32, *p32, *d32;
+    double *part;
+    double rr, rr32, bb;
+    __device__ bool skip() const { return false; }
+    __device__ void row(int64_t i, double s) {
+        const double bi = b[i];
+        const double ri = bi - s;
+        const float ri32 = static_cast<float>(ri);
+        r32[i] = ri32;
+        p32[i] = ri32;
+        d32[i] = 0.0f;
+        rr = fma(ri, ri, rr);
+        rr32 = fma(static_cast<double>(ri32), static_cast<double>(ri32), rr32);
+        bb = fma(bi, bi, bb);
+    }
+    __device__ void finish() {
+        double v[3] = {rr, rr32, bb};
+        block_partial<3>(v, part);
     }
 };
 
@@ -190,88 +129,6 @@ struct EpiTrue {
         block_partial<1>(v, part);
     }
 };
-
-// ------------------------------------------------------------------ SpMV tilings
-constexpr int kStreamCap = 2048;   // nnz staged in LDS per tile
-#ifndef SPK_ROW_UNROLL
-#define SPK_ROW_UNROLL 4
-#endif
-constexpr int kRowUnroll = SPK_ROW_UNROLL;   // gathers in flight per row step
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// The contiguous nnz range [s, e) of one tile is copied into LDS in 16-byte
-// chunks by the gfx950 global-to-LDS DMA (global_load_lds_dwordx4): lane l of
-// a wave writes LDS bytes [16 l, 16 l + 16) past the wave's base, so no VGPR
-// holds staged data.  The range is widened down to a 16-byte boundary (s0);
-// chunk c covers elements [s0 + c*EPC, s0 + (c+1)*EPC).  Only a chunk running
-// past the end of the array (the matrix's last chunk) is copied element-wise.
-template <typename T>
-struct Chunks {
-    static constexpr int EPC = 16 / sizeof(T);
-    static constexpr int MAXC = (kStreamCap / EPC + 1 + kBlock - 1) / kBlock;   // chunk rounds per thread
-    static constexpr int LDS = kStreamCap / EPC + 1;                              // chunks per tile
-};
-
-typedef __attribute__((address_space(3))) void lds_void;
-
-template <typename T>
-__device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, int64_t e, int64_t total, u32x4 *lds) {
-    constexpr int EPC = Chunks<T>::EPC;
-    const int64_t s0 = s & ~static_cast<int64_t>(EPC - 1);
-    const int lane = threadIdx.x & 63;
-    const int wbase = threadIdx.x & ~63;
-#pragma unroll
-    for (int u = 0; u < Chunks<T>::MAXC; ++u) {
-        const int cbase = u * kBlock + wbase;                  // this wave's first chunk this round
-        if (s0 + static_cast<int64_t>(cbase) * EPC >= e) break;   // wave-uniform
-        const int64_t k = s0 + static_cast<int64_t>(cbase + lane) * EPC;
-        if (k < e) {
-            if (k + EPC <= total) {
-                __builtin_amdgcn_global_load_lds(static_cast<const void *>(g + k),
-                                                 (lds_void *)(lds + cbase), 16, 0, 0);
-            } else {
-                T *dst = reinterpret_cast<T *>(lds + cbase + lane);
-                for (int j = 0; j < EPC; ++j)
-                    if (k + j < total) dst[j] = g[k + j];
-            }
-        }
-    }
-}
-
-// Sum of row [a, b) with values/columns read from LDS (offsets s0v / s0c).
-template <typename V, typename I, typename X, typename C>
-__device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, int64_t b, int64_t s0v, int64_t s0c,
-                                          const X *__restrict__ x) {
-    C sum = 0;
-    for (int64_t k0 = a; k0 < b; k0 += kRowUnroll) {
-        C av[kRowUnroll], xv[kRowUnroll];
-#pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
-            const int64_t k = k0 + u;
-            if (k < b) {
-                av[u] = static_cast<C>(widen(sv[k - s0v]));
-                xv[u] = static_cast<C>(x[sc[k - s0c]]);
-            } else {
-                av[u] = 0;
-                xv[u] = 0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) sum = fma(av[u], xv[u], sum);
-    }
-    return sum;
-}
-
-template <typename V, typename I, typename X, typename C>
-__device__ __forceinline__ C row_from_global(const V *__restrict__ va, const I *__restrict__ ci, int64_t a, int64_t b,
-                                             const X *__restrict__ x, int nt) {
-    C sum = 0;
-    for (int64_t k = a; k < b; ++k) {
-        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(x[ci[k]]), sum);
-    }
-    return sum;
-}
 
 // LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
 // thread per row reduces from LDS while gathering x.  Occupancy (several
@@ -422,12 +279,19 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(SolveState *st, const do
     }
 }
 
-// x += alpha p, r -= alpha q with alpha = rho_k / (p.q); partials of r.r.
-// j: index of this iteration within the launched chunk.
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double *__restrict__ p,
-                                                      double *__restrict__ r, const double *__restrict__ q,
-                                                      SolveState *st, const double *part_pq, int G_pq,
-                                                      double *part_rr, int j) {
+template <typename T>
+struct Vec16 {
+    static constexpr int W = 16 / sizeof(T);
+    typedef T type __attribute__((ext_vector_type(W)));
+};
+
+// x += alpha p, r -= alpha q with alpha = rho_k / (p.q) (FP64 scalar, applied
+// in T); partials of r.r accumulated in FP64.  j: index of this iteration
+// within the launched chunk.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const T *__restrict__ p, T *__restrict__ r,
+                                                      const T *__restrict__ q, SolveState *st, const double *part_pq,
+                                                      int G_pq, double *part_rr, int j) {
     if (st->stop != STOP_RUNNING) return;
     const int64_t k = st->base + j;
     double tot[1];
@@ -440,56 +304,53 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double *_
         }
         return;
     }
-    const double alpha = st->rho[k & 3] / pq;
+    const double alpha_d = st->rho[k & 3] / pq;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pq = pq;
-        st->alpha = alpha;
+        st->alpha = alpha_d;
     }
-    double *__restrict__ x = st->x;
+    const T alpha = static_cast<T>(alpha_d);
+    T *__restrict__ x = static_cast<T *>(st->x);
     double acc = 0.0;
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    constexpr int W = Vec16<T>::W;
+    using VT = typename Vec16<T>::type;
+    int64_t done = 0;
     if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
-        const int64_t n2 = n >> 1;
-        double2 *x2 = reinterpret_cast<double2 *>(x);
-        double2 *r2 = reinterpret_cast<double2 *>(r);
-        const double2 *p2 = reinterpret_cast<const double2 *>(p);
-        const double2 *q2 = reinterpret_cast<const double2 *>(q);
-        for (int64_t i = gid; i < n2; i += stride) {
-            double2 xv = x2[i], rv = r2[i];
-            const double2 pv = p2[i], qv = q2[i];
-            xv.x = fma(alpha, pv.x, xv.x);
-            xv.y = fma(alpha, pv.y, xv.y);
-            rv.x = fma(-alpha, qv.x, rv.x);
-            rv.y = fma(-alpha, qv.y, rv.y);
-            x2[i] = xv;
-            r2[i] = rv;
-            acc = fma(rv.x, rv.x, acc);
-            acc = fma(rv.y, rv.y, acc);
+        const int64_t nv = n / W;
+        VT *xv_ = reinterpret_cast<VT *>(x);
+        VT *rv_ = reinterpret_cast<VT *>(r);
+        const VT *pv_ = reinterpret_cast<const VT *>(p);
+        const VT *qv_ = reinterpret_cast<const VT *>(q);
+        for (int64_t i = gid; i < nv; i += stride) {
+            VT xv = xv_[i], rv = rv_[i];
+            const VT pv = pv_[i], qv = qv_[i];
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                xv[c] = fma(alpha, pv[c], xv[c]);
+                rv[c] = fma(-alpha, qv[c], rv[c]);
+                acc = fma(static_cast<double>(rv[c]), static_cast<double>(rv[c]), acc);
+            }
+            xv_[i] = xv;
+            rv_[i] = rv;
         }
-        if ((n & 1) && gid == 0) {
-            const int64_t i = n - 1;
-            x[i] = fma(alpha, p[i], x[i]);
-            const double ri = fma(-alpha, q[i], r[i]);
-            r[i] = ri;
-            acc = fma(ri, ri, acc);
-        }
-    } else {
-        for (int64_t i = gid; i < n; i += stride) {
-            x[i] = fma(alpha, p[i], x[i]);
-            const double ri = fma(-alpha, q[i], r[i]);
-            r[i] = ri;
-            acc = fma(ri, ri, acc);
-        }
+        done = nv * W;
+    }
+    for (int64_t i = done + gid; i < n; i += stride) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const T ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        acc = fma(static_cast<double>(ri), static_cast<double>(ri), acc);
     }
     double v[1] = {acc};
     block_partial<1>(v, part_rr);
 }
 
 // rho_{k+1} = r.r; stop test; p = r + beta p with beta = rho_{k+1} / rho_k.
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double *__restrict__ r,
-                                                       double *__restrict__ p, SolveState *st, const double *part_rr,
-                                                       int G_rr, int j) {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const T *__restrict__ r, T *__restrict__ p,
+                                                       SolveState *st, const double *part_rr, int G_rr, int j) {
     if (st->stop != STOP_RUNNING) return;
     const int64_t k = st->base + j;
     double tot[1];
@@ -501,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double *
     if (!isfinite(rho_new)) stop = STOP_NON_FINITE;
     else if (res <= st->thresh) stop = STOP_CONVERGED;
     else if (k1 >= st->max_iters) stop = STOP_MAX_ITERS;
-    const double beta = rho_new / st->rho[k & 3];
+    const double beta_d = rho_new / st->rho[k & 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iter = k1;
         st->resnorm = res;
@@ -510,19 +371,89 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double *
         if (stop != STOP_RUNNING) st->stop = stop;
     }
     if (stop != STOP_RUNNING) return;
+    const T beta = static_cast<T>(beta_d);
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    const int64_t n2 = n >> 1;
-    const double2 *r2 = reinterpret_cast<const double2 *>(r);
-    double2 *p2 = reinterpret_cast<double2 *>(p);
-    for (int64_t i = gid; i < n2; i += stride) {
-        const double2 rv = r2[i];
-        double2 pv = p2[i];
-        pv.x = fma(beta, pv.x, rv.x);
-        pv.y = fma(beta, pv.y, rv.y);
-        p2[i] = pv;
+    constexpr int W = Vec16<T>::W;
+    using VT = typename Vec16<T>::type;
+    const int64_t nv = n / W;
+    const VT *rv_ = reinterpret_cast<const VT *>(r);
+    VT *pv_ = reinterpret_cast<VT *>(p);
+    for (int64_t i = gid; i < nv; i += stride) {
+        const VT rv = rv_[i];
+        VT pv = pv_[i];
+#pragma unroll
+        for (int c = 0; c < W; ++c) pv[c] = fma(beta, pv[c], rv[c]);
+        pv_[i] = pv;
     }
-    if ((n & 1) && gid == 0) p[n - 1] = fma(beta, p[n - 1], r[n - 1]);
+    for (int64_t i = nv * W + gid; i < n; i += stride) p[i] = fma(beta, p[i], r[i]);
+}
+
+// Refinement: finish the outer residual (||r64||, the outer stop test) and
+// set up the inner CG on A32 d = r32 from d = 0 (rho_0 = ||r32||^2).
+// out[0] = ||r64||, out[1] = ||r32|| (read by the host after the launch).
+__global__ __launch_bounds__(kBlock) void k_ir_finish(SolveState *in, const double *part, int G, double tau_in,
+                                                      int64_t max_inner, float *d32, double *out) {
+    double tot[3];
+    sum_partials<3>(part, G, tot);
+    if (threadIdx.x != 0) return;
+    out[0] = sqrt(tot[0]);
+    out[2] = sqrt(tot[2]);
+    const double r32 = sqrt(tot[1]);
+    out[1] = r32;
+    in->x = d32;
+    in->hist = nullptr;
+    in->hist_cap = 0;
+    in->max_iters = max_inner;
+    in->base = 0;
+    in->iter = 0;
+    in->zero_x = 0;
+    in->alpha = 0.0;
+    in->pq = 0.0;
+    in->bnorm = r32;
+    in->thresh = tau_in * r32;
+    in->rho[0] = tot[1];
+    in->resnorm = r32;
+    in->stop = STOP_RUNNING;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) in->stop = STOP_NON_FINITE;
+    else if (r32 == 0.0) in->stop = STOP_CONVERGED;
+    else if (max_inner <= 0) in->stop = STOP_MAX_ITERS;
+}
+
+// x64 += d32 after an inner solve.
+__global__ __launch_bounds__(kBlock) void k_ir_correct(int64_t n, double *__restrict__ x, const float *__restrict__ d) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride)
+        x[i] += static_cast<double>(d[i]);
+}
+
+// Round FP64 matrix values to the inner-solve storage type.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_round_values(int64_t nnz, const double *__restrict__ src, V *__restrict__ dst);
+
+template <>
+__global__ __launch_bounds__(kBlock) void k_round_values<float>(int64_t nnz, const double *__restrict__ src,
+                                                               float *__restrict__ dst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nnz; i += stride)
+        dst[i] = static_cast<float>(src[i]);
+}
+
+// FP64 -> bfloat16 with round-to-nearest-even (NaN kept quiet).
+__device__ __forceinline__ uint16_t to_bf16_rne(double v) {
+    const float f = static_cast<float>(v);
+    const unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    const unsigned rounding = 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>((u + rounding) >> 16);
+}
+
+template <>
+__global__ __launch_bounds__(kBlock) void k_round_values<bf16s>(int64_t nnz, const double *__restrict__ src,
+                                                               bf16s *__restrict__ dst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nnz; i += stride)
+        dst[i].bits = to_bf16_rne(src[i]);
 }
 
 // Advance the chunk base after `count` iterations (one thread).
@@ -539,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_true_finish(SolveState *st, const do
 
 __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, const SolveState *st) {
     if (!st->zero_x) return;
-    double *x = st->x;
+    double *x = static_cast<double *>(st->x);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0;
 }
@@ -673,20 +604,71 @@ hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, d
 
 hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q, SolveState *st,
                              double *partials, hipStream_t s) {
-    EpiPq e{q, p, st, site(partials, SITE_PQ), 0.0};
+    EpiPq<double> e{q, p, st, site(partials, SITE_PQ), 0.0};
     return launch_family<double, double, double>(A, t, p, e, s);
+}
+
+hipError_t launch_cg_spmv_pq32(const CsrDev &A32, const SpmvTune &t, const float *p, float *q, SolveState *st,
+                               double *partials, hipStream_t s) {
+    EpiPq<float> e{q, p, st, site(partials, SITE_PQ), 0.0};
+    if (A32.val_t == 1) return launch_family<float, float, float>(A32, t, p, e, s);
+    if (A32.val_t == 3) return launch_family<bf16s, float, float>(A32, t, p, e, s);
+    if (A32.val_t == 2) return launch_family<_Float16, float, float>(A32, t, p, e, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, const double *p, double *r, const double *q,
                             SolveState *st, double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_PQ),
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_PQ),
+                       spmv_grid, site(partials, SITE_RR), j);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, const float *p, float *r, const float *q,
+                              SolveState *st, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_PQ),
                        spmv_grid, site(partials, SITE_RR), j);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st, double *partials,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_pupdate, dim3(grid), dim3(kBlock), 0, s, n, r, p, st, site(partials, SITE_RR), grid, j);
+    hipLaunchKernelGGL(k_cg_pupdate<double>, dim3(grid), dim3(kBlock), 0, s, n, r, p, st, site(partials, SITE_RR),
+                       grid, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_pupdate32(int64_t n, int grid, int j, const float *r, float *p, SolveState *st,
+                               double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_pupdate<float>, dim3(grid), dim3(kBlock), 0, s, n, r, p, st, site(partials, SITE_RR),
+                       grid, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_residual(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, float *r32,
+                              float *p32, float *d32, SolveState *in, double *partials, double tau_in,
+                              int64_t max_inner, double *out, hipStream_t s) {
+    EpiIrResidual e{b, r32, p32, d32, site(partials, SITE_INIT), 0.0, 0.0, 0.0};
+    hipError_t err = hipSuccess;
+    if (A.val_t == 0) err = launch_family<double, double, double>(A, t, x, e, s);
+    else if (A.val_t == 1) err = launch_family<float, double, double>(A, t, x, e, s);
+    else return hipErrorInvalidValue;
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, in, site(partials, SITE_INIT), t.grid, tau_in,
+                       max_inner, d32, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_correct(int64_t n, int grid, double *x, const float *d, hipStream_t s) {
+    hipLaunchKernelGGL(k_ir_correct, dim3(grid), dim3(kBlock), 0, s, n, x, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int bf16, int grid, hipStream_t s) {
+    if (bf16)
+        hipLaunchKernelGGL(k_round_values<bf16s>, dim3(grid), dim3(kBlock), 0, s, nnz, src, static_cast<bf16s *>(dst));
+    else
+        hipLaunchKernelGGL(k_round_values<float>, dim3(grid), dim3(kBlock), 0, s, nnz, src, static_cast<float *>(dst));
     return hipGetLastError();
 }
 
@@ -720,11 +702,11 @@ int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t) {
     const bool i64 = A.idx_t != 0;
     if (A.val_t == 0) {
         if (t.kind == 0) {
-            if (i64) q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq>);
-            else q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq>);
+            if (i64) q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>>);
+            else q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq<double>>);
         } else {
-            if (i64) q(k_spmv_vector<double, int64_t, int64_t, double, double, EpiPq>);
-            else q(k_spmv_vector<double, int64_t, int32_t, double, double, EpiPq>);
+            if (i64) q(k_spmv_vector<double, int64_t, int64_t, double, double, EpiPq<double>>);
+            else q(k_spmv_vector<double, int64_t, int32_t, double, double, EpiPq<double>>);
         }
     } else {
         if (t.kind == 0) q(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPlain<float>>);

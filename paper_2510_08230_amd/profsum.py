@@ -1,0 +1,103 @@
+"""Summaries of rocprofv3 CSV output for the profiles/ directory.
+
+  python -m paper_2510_08230_amd.profsum stats  KERNEL_STATS_CSV --cmd "..."
+  python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B --cmd "..."
+
+``stats`` renders the per-kernel duration table.  ``traffic`` reports the
+median FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dispatches of one
+kernel, scaled by what the same counters read for the library's plain copy
+kernel (k_copy16) of known size, plus the kernel-source digest the numbers
+belong to (the benchmark drops them once the sources change).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_device.h", "csrc/spk_internal.h"]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats_md(path: str, cmd: str, top: int = 15) -> str:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["# rocprofv3 kernel statistics", "", "Command (repository root):", "", "    " + cmd, "",
+           "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("|", "/")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        out.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path: str, counter: str):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
+    f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    w = _per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(d, sub):
+        got = [v for k, v in d.items() if sub in k]
+        if not got:
+            raise SystemExit("no dispatch of %r in the counter CSV" % sub)
+        vals = [x for lst in got for x in lst]
+        top = max(vals)
+        return statistics.median([x for x in vals if x > 0.5 * top])   # drop launches that returned at once
+
+    copy_f = pick(f, "k_copy16")
+    copy_w = pick(w, "k_copy16")
+    scale_f = copy_bytes / (copy_f * 1024.0)
+    scale_w = copy_bytes / (copy_w * 1024.0)
+    kf = pick(f, kernel)
+    kw = pick(w, kernel)
+    return {"kernel": kernel, "fetch_kib": kf, "write_kib": kw, "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+            "copy_bytes_each_way": copy_bytes, "fetch_scale": scale_f, "write_scale": scale_w,
+            "read_bytes": kf * 1024.0 * scale_f, "write_bytes": kw * 1024.0 * scale_w,
+            "traffic_bytes": kf * 1024.0 * scale_f + kw * 1024.0 * scale_w, "kernel_digest": kernel_digest()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--cmd", required=True)
+    a = ap.parse_args()
+    if a.what == "stats":
+        print(stats_md(a.csv, a.cmd), end="")
+    else:
+        d = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
+        d["command"] = a.cmd
+        print(json.dumps(d, indent=1))
+
+
+if __name__ == "__main__":
+    main()

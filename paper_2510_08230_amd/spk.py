@@ -72,6 +72,15 @@ class PlanInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("ticks", ctypes.c_int64), ("peak_slots", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp, _i32, _i64, _f64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _P = ctypes.POINTER
 _SIGS = {
@@ -92,6 +101,14 @@ _SIGS = {
     "spk_plan_kernel_stats": (ctypes.c_int, [_vp, _P(_f64), _P(_i64)]),
     "spk_free": (ctypes.c_int, [_vp]),
     "spk_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, _sz, _P(_f64)]),
+    "spk_server_request_bytes": (_sz, [_i64, _i64]),
+    "spk_server_create": (ctypes.c_int, [_vp, _sz, _i32, _P(SolverCfg), _P(_vp)]),
+    "spk_server_submit": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(ctypes.c_uint64)]),
+    "spk_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(_i32), _P(Log), _P(_i64)]),
+    "spk_server_drain": (ctypes.c_int, [_vp]),
+    "spk_server_get_stats": (ctypes.c_int, [_vp, _P(ServerStats)]),
+    "spk_server_last_error": (ctypes.c_char_p, [_vp]),
+    "spk_server_destroy": (ctypes.c_int, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -260,3 +277,70 @@ def spk_stream_copy(ctx: Context, src, dst, nbytes: int) -> float:
     _check(_lib.spk_stream_copy(ctx.handle, _dev_ptr(src, "src"), _dev_ptr(dst, "dst"), int(nbytes),
                                 ctypes.byref(ms)), ctx)
     return ms.value
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    def __init__(self, handle):
+        self.handle = handle
+        self.keep = {}   # ticket -> (matrix, b, x): kept alive until the request is done
+
+
+def spk_server_request_bytes(n: int, nnz: int) -> int:
+    return int(_lib.spk_server_request_bytes(int(n), int(nnz)))
+
+
+def _server_check(status, srv):
+    if status != OK:
+        msg = _lib.spk_server_last_error(srv.handle).decode() if srv is not None and srv.handle else ""
+        raise SpkError(status, msg)
+
+
+def spk_server_create(ctx: Context, hbm_budget_bytes: int, max_slots: int, cfg: SolverCfg | None = None) -> Server:
+    h = ctypes.c_void_p()
+    c = ctypes.byref(cfg) if cfg is not None else None
+    _check(_lib.spk_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), c, ctypes.byref(h)), ctx)
+    return Server(h)
+
+
+def spk_server_submit(srv: Server, A: CsrMatrix, b, x) -> int:
+    if b.numel() != A.desc.n_rows or x.numel() != A.desc.n_rows:
+        raise ValueError("b and x must have n entries")
+    if str(b.dtype) != "torch.float64" or str(x.dtype) != "torch.float64":
+        raise ValueError("b and x must be float64")
+    t = ctypes.c_uint64()
+    _server_check(_lib.spk_server_submit(srv.handle, ctypes.byref(A.desc), _dev_ptr(b, "b"), _dev_ptr(x, "x"),
+                                         ctypes.byref(t)), srv)
+    srv.keep[t.value] = (A, b, x)
+    return t.value
+
+
+def spk_server_poll(srv: Server, ticket: int):
+    """Returns (done, status, Log or None, latency_ns or None) without raising on a failed request."""
+    done = ctypes.c_int32()
+    log = Log()
+    lat = ctypes.c_int64()
+    st = _lib.spk_server_poll(srv.handle, int(ticket), ctypes.byref(done), ctypes.byref(log), ctypes.byref(lat))
+    if not done.value:
+        if st != OK:
+            _server_check(st, srv)
+        return False, OK, None, None
+    srv.keep.pop(int(ticket), None)
+    return True, st, log, lat.value
+
+
+def spk_server_drain(srv: Server):
+    _server_check(_lib.spk_server_drain(srv.handle), srv)
+
+
+def spk_server_get_stats(srv: Server) -> dict:
+    st = ServerStats()
+    _server_check(_lib.spk_server_get_stats(srv.handle, ctypes.byref(st)), srv)
+    return st.as_dict()
+
+
+def spk_server_destroy(srv: Server):
+    if srv.handle:
+        _lib.spk_server_destroy(srv.handle)
+        srv.handle = None
+        srv.keep.clear()

@@ -99,3 +99,16 @@ def test_binding_rejects_host_tensors():
     t = torch.zeros(4, dtype=torch.int64)
     with pytest.raises(ValueError):
         spk.CsrMatrix(t, t, torch.zeros(4, dtype=torch.float64), 3, 3)
+
+
+def test_server_request_bytes_formula():
+    """Workspace per request: 4 FP32 vectors, the FP32 value copy and 5 FP64 partials per 256-row tile,
+    each piece rounded up to 256 bytes."""
+    from paper_2510_08230_amd import spk
+
+    def al(b):
+        return (b + 255) // 256 * 256
+    for n, nnz in [(1, 1), (1000, 7000), (256, 1792), (257, 0), (1_000_000, 7_000_000)]:
+        tiles = (n + 255) // 256
+        want = 4 * al(4 * n) + al(4 * max(nnz, 1)) + al(8 * 5 * max(tiles, 1))
+        assert spk.spk_server_request_bytes(n, nnz) == want

@@ -1,0 +1,125 @@
+"""Mixed precision (FP32 or BF16 inner CG with FP64 dot products, FP64
+iterative refinement) on the GPU against the FP64 oracle.
+
+Stated tolerance (the mixed-precision configuration asks for it): the
+refined solution is within 1e-10 (relative 2-norm) of the oracle's FP64 CG
+solution solved to 1e-14.  Derivation: the refinement stops at
+||b - A x|| <= tau ||b|| with tau = 1e-12 computed in FP64, so
+||x - x*|| / ||x*|| <= kappa * tau <= 13 * 1e-12 for these matrices
+(kappa_G <= 13), and the oracle's own error is ~1e-14."""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+from tests.gpu_util import dev_csr, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spk():
+    from paper_2510_08230_amd import spk as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(spk):
+    c = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    yield c
+    spk.spk_finalize(c)
+
+
+def solve_mixed(spk, ctx, A, b, prec, tau=1e-12, x0=None, val=torch.float64, max_outer=50, inner=1e-4,
+                mode=0, max_iters=10000):
+    cfg = spk.spk_solver_cfg_default()
+    cfg.precision = prec
+    cfg.reduction_factor = tau
+    cfg.inner_reduction = inner
+    cfg.max_outer = max_outer
+    cfg.max_iters = max_iters
+    cfg.exec_mode = mode
+    pl = spk.spk_plan_solve(ctx, dev_csr(spk, A, val=val), cfg)
+    x = to_dev(np.zeros(A.n_rows) if x0 is None else x0)
+    log = spk.spk_execute_solve(pl, to_dev(b), x)
+    spk.spk_free(pl)
+    return x.cpu().numpy(), log
+
+
+MATS = {"stencil7_46": lambda: inputs.stencil7(46, 0), "randsym_1e5": lambda: inputs.randsym(100000, 0)}
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_refined_solution_matches_fp64_oracle(spk, ctx, name, prec, mode):
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 0)
+    p = spk.PREC_MIXED_FP32 if prec == "fp32" else spk.PREC_MIXED_BF16
+    x, log = solve_mixed(spk, ctx, A, b, p, mode=mode)
+    xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=2000)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.outer_iterations >= 1
+    assert rel(x, xo) <= 1e-10
+    # the oracle recomputes the residual of the GPU's x: the FP64 stop test held
+    r = oracle.residual(A, b, x)
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b) * 1.01
+    assert abs(log.true_resnorm - np.linalg.norm(r)) <= 1e-3 * np.linalg.norm(r) + 1e-16 * np.linalg.norm(b)
+
+
+def test_fp32_values_taken_as_exact(spk, ctx):
+    """FP32-exact matrix passed with F32 values: refinement reads the same FP32 values."""
+    A = inputs.stencil7(30, 5, f32x=True)
+    b = inputs.rhs(A.n_rows, 5)
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, val=torch.float32)
+    xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=2000)
+    assert log.stop_reason == spk.STOP_CONVERGED and rel(x, xo) <= 1e-10
+
+
+def test_mixed_stop_semantics(spk, ctx):
+    A = inputs.stencil7(10, 1)
+    b = inputs.rhs(A.n_rows, 1)
+    x0 = inputs.vec(A.n_rows, 1, 6)
+    x, log = solve_mixed(spk, ctx, A, np.zeros(A.n_rows), spk.PREC_MIXED_FP32, x0=x0)
+    assert log.stop_reason == spk.STOP_CONVERGED and not x.any() and log.iterations == 0
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, x0=x0, max_outer=0)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and np.array_equal(x, x0) and log.outer_iterations == 0
+    bn = b.copy()
+    bn[7] = np.nan
+    _, log = solve_mixed(spk, ctx, A, bn, spk.PREC_MIXED_FP32)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+    # one refinement step with a loose inner tolerance does not reach 1e-12
+    _, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, max_outer=1, inner=1e-2)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.outer_iterations == 1
+
+
+def test_mixed_reruns_bitwise(spk, ctx):
+    A = inputs.randsym(30000, 3)
+    b = inputs.rhs(A.n_rows, 3)
+    x1, _ = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, mode=1)
+    x2, _ = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, mode=2)
+    assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+
+
+def test_mixed_plan_errors(spk, ctx):
+    A = inputs.stencil7(4, 0)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.precision = spk.PREC_MIXED_BF16
+    with pytest.raises(spk.SpkError) as e:
+        spk.spk_plan_solve(ctx, dev_csr(spk, A, val=torch.float32), cfg)
+    assert e.value.status == spk.ERR_UNSUPPORTED
+    cfg.precision = spk.PREC_MIXED_FP32
+    cfg.inner_reduction = 1.5
+    with pytest.raises(spk.SpkError) as e:
+        spk.spk_plan_solve(ctx, dev_csr(spk, A), cfg)
+    assert e.value.status == spk.ERR_INVALID_ARG
+
+
+def test_c3_full_size(spk, ctx):
+    """stencil7 N=215 (n = 9,938,375), seed 1: FP32 inner + FP64 refinement within 1e-10 of the oracle."""
+    A = inputs.stencil7(215, 1)
+    b = inputs.rhs(A.n_rows, 1)
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32)
+    xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=1000)
+    print("mixed: %d inner its, %d outer, %.1f ms" % (log.iterations, log.outer_iterations, log.elapsed_ms))
+    assert log.stop_reason == spk.STOP_CONVERGED and rel(x, xo) <= 1e-10
