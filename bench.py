@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=25, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also time the plain copy kernel")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time the steps without per-launch HIP events (no roofline; needed for graph/persistent)")
     ap.add_argument("--serve", action="store_true",
                     help="batched-serving run: randsym instances, Poisson arrivals, p50/p99 latency")
     ap.add_argument("--instances", type=int, default=256)
@@ -49,6 +51,11 @@ def parse():
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--load", type=float, default=0.7, help="offered load / saturated throughput")
     ap.add_argument("--oracle-sample", type=int, default=16, help="instances checked against the oracle")
+    ap.add_argument("--large", action="store_true",
+                    help="large instance: stencil7 N=1048 generated on the device, FP32-exact values, "
+                         "int64 row_ptr, FP32 CG + FP64 refinement")
+    ap.add_argument("--exec", choices=["auto", "host", "graph"], default="host",
+                    help="iteration driver: host loop, captured graphs, or the plan's choice")
     return ap.parse_args()
 
 
@@ -78,6 +85,9 @@ def main():
     if args.serve:
         serve(args)
         return
+    if args.large:
+        large(args)
+        return
 
     import numpy as np
     import torch
@@ -101,7 +111,7 @@ def main():
     cfg = spk.spk_solver_cfg_default()
     cfg.reduction_factor = args.tau
     cfg.max_iters = 1000
-    cfg.exec_mode = spk.EXEC_HOST_LOOP
+    cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
     cfg.precision = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32,
                      "mixed_bf16": spk.PREC_MIXED_BF16}[args.precision]
     cfg.inner_reduction = args.inner
@@ -126,7 +136,7 @@ def main():
     iters, kms, klaunch = 0, 0.0, 0
     logs = []
     for _ in range(args.steps):
-        log, (ms, cnt), info = step(True)
+        log, (ms, cnt), info = step(not args.no_profile)
         iters += log.iterations
         kms += ms
         klaunch += cnt
@@ -142,8 +152,8 @@ def main():
     else:   # inner SpMV: FP32/BF16 values, int32 columns, FP32 vectors
         vb = 4 if args.precision == "mixed_fp32" else 2
         bytes_spmv = nnz * (vb + 4) + (n + 1) * 4 + 2 * n * 4
-    avg_ms = kms / max(klaunch, 1)
-    achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9
+    avg_ms = kms / klaunch if klaunch else None
+    achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     last = logs[-1]
     traffic = measured_traffic(args, N)
     out = {
@@ -166,7 +176,7 @@ def main():
                    "solve_device_ms": last.elapsed_ms, "spmv_tiling": info},
         "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq> (q = A p fused with p.q)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": klaunch},
     }
     if args.copy_calib:
@@ -186,6 +196,79 @@ def main():
                                "kind": "oracle",
                                "sample": "FP64 oracle CG, same system, %d iterations (plus initial and "
                                          "true residual), %.1f s" % (res.iterations, dt)}
+    print(json.dumps(out), flush=True)
+
+
+def large(args):
+    """stencil7 N (default 1048: n = 1,151,022,592, nnz = 8,050,568,320) with
+    FP32-exact values generated on the device (int64 row_ptr, int32 col_idx,
+    FP32 values, ~110 GB with the vectors); FP32 inner CG with FP64 dot
+    products and FP64 refinement reading the same FP32 values, to
+    ||b - A x|| <= 1e-12 ||b||.  Roofline: the inner SpMV+p.q kernel,
+    algorithmic bytes nnz*(4+4) + (n+1)*8 + 2n*4 per launch."""
+    import torch
+
+    import inputs
+    from paper_2510_08230_amd import spk
+
+    N = 1048 if args.N == 215 else args.N
+    seed = 5
+    dev = torch.device("cuda:0")
+    n = N ** 3
+    rp, col, val = inputs.dev_stencil7(N, seed, f32x=True, val_f32=True)
+    nnz = int(col.numel())
+    b = inputs.dev_vec(n, seed, 2)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    M = spk.CsrMatrix(rp, col, val, n, n)
+    ctx = spk.spk_init(0, torch.cuda.current_stream(dev).cuda_stream)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.precision = spk.PREC_MIXED_FP32
+    cfg.reduction_factor = 1e-12
+    cfg.inner_reduction = args.inner
+    cfg.max_iters = 10000
+    cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
+
+    def step(profile):
+        pl = spk.spk_plan_solve(ctx, M, cfg)
+        if profile:
+            spk.spk_plan_set_profiling(pl, True)
+        x.zero_()
+        log = spk.spk_execute_solve(pl, b, x)
+        st = spk.spk_plan_kernel_stats(pl)
+        info = spk.spk_plan_get_info(pl)
+        spk.spk_free(pl)
+        return log, st, info
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, kms, kl = 0, 0.0, 0
+    for _ in range(args.steps):
+        log, (ms, cnt), info = step(not args.no_profile)
+        iters += log.iterations
+        kms += ms
+        kl += cnt
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    spk.spk_finalize(ctx)
+    bytes_spmv = nnz * 8 + (n + 1) * 8 + 2 * n * 4
+    avg = kms / max(kl, 1)
+    achieved = bytes_spmv / (avg * 1e-3) / 1e9
+    out = {
+        "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
+        "value": n * iters / wall, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic (seeded stencil7 generated on the device, FP32-exact values)",
+        "config": {"workload": "cg_mixed_fp32_stencil7_N%d_device" % N, "n": n, "nnz": nnz, "seed": seed,
+                   "tau": 1e-12, "index_types": "int64/int32", "iterations_per_solve": log.iterations,
+                   "outer_iterations": log.outer_iterations, "stop_reason": log.stop_reason,
+                   "rel_true_residual": log.true_resnorm / log.rhs_norm, "solve_device_ms": log.elapsed_ms,
+                   "spmv_tiling": info, "hbm_bytes_resident_est": (n + 1) * 8 + nnz * 8 + 2 * n * 8 + 4 * n * 4},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq<float>> (inner q = A32 p fused with p.q)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg, "launches": kl},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -77,9 +77,11 @@ typedef enum {
 typedef enum { SPK_BASELINE_RHS_NORM = 0 } spk_baseline;
 typedef enum { SPK_PRECOND_NONE = 0 } spk_precond;
 typedef enum {
-    SPK_EXEC_AUTO = 0,        /* the plan's autotuner picks */
+    SPK_EXEC_AUTO = 0,        /* the library's choice: the host loop, which measured fastest */
     SPK_EXEC_HOST_LOOP = 1,   /* kernels launched from a host loop, status polled per chunk */
-    SPK_EXEC_GRAPH = 2        /* chunks of iterations replayed from a captured HIP graph */
+    SPK_EXEC_GRAPH = 2,       /* chunks of iterations replayed from a captured HIP graph */
+    SPK_EXEC_PERSISTENT = 3   /* FP64: the whole solve in one cooperative launch with grid
+                                 barriers (mixed precision falls back to SPK_EXEC_GRAPH) */
 } spk_exec_mode;
 
 typedef struct spk_ctx_s *spk_ctx;

@@ -42,6 +42,7 @@ struct spk_ctx_s {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
     int num_cu = 0;
+    int wall_khz = 0;                   // wall_clock64() rate
     std::string err;
     unsigned *d_flags = nullptr;
     unsigned *h_flags = nullptr;        // pinned
@@ -59,6 +60,8 @@ struct spk_plan_s {
     spk_solver_cfg cfg{};
     SpmvTune tune{};
     int vec_grid = 1;
+    int persist_grid = 0;                // cooperative grid of the persistent solve (0 = not used)
+    unsigned *bar = nullptr;             // persistent grid-barrier words
     spk_plan_info info{};
     double *r = nullptr, *p = nullptr, *q = nullptr, *partials = nullptr, *hist = nullptr;
     int64_t hist_cap = 0;
@@ -202,9 +205,8 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneRe
     std::vector<SpmvTune> cands;
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
     if (stream_ok(A) && mean <= 64.0) {
-        for (int pf = 1; pf >= 0; --pf)
-            for (int remap = 0; remap <= 1; ++remap)
-                for (int nt = 0; nt <= 1; ++nt) cands.push_back(make_tune(ctx, A, 0, 0, remap, nt, pf, 0));
+        // tile-to-XCD maps: round-robin, contiguous eighths, XCD-blocked runs of k tiles
+        for (int remap : {0, 1, 16, 64, 256}) cands.push_back(make_tune(ctx, A, 0, 0, remap, 0, 0, 0));
     }
     for (int l2 = 0; l2 <= 6; ++l2) {
         const double L = static_cast<double>(1 << l2);
@@ -338,6 +340,9 @@ spk_status prof_collect(spk_plan pl, int64_t useful) {
 // Loop kinds: 0 = FP64 CG on A, 1 = FP32 inner CG on A32 (mixed precision).
 enum { LOOP_FP64 = 0, LOOP_FP32 = 1 };
 
+// Iteration j of a chunk: q = A p with p.q partials; alpha and r -= alpha q
+// with r.r partials; x += alpha p, the stop test and p = r + beta p.  A chunk
+// of `count` iterations ends by advancing the base.
 spk_status launch_iterations(spk_plan pl, int kind, int count, hipStream_t s, bool with_prof) {
     spk_ctx ctx = pl->ctx;
     const int64_t n = pl->A.n_rows;
@@ -356,12 +361,11 @@ spk_status launch_iterations(spk_plan pl, int kind, int count, hipStream_t s, bo
             if (st != SPK_OK) return st;
         }
         if (kind == LOOP_FP64) {
-            SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->tune.grid, i, pl->p, pl->r, pl->q, pl->st,
-                                               pl->partials, s));
+            SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->tune.grid, i, pl->r, pl->q, pl->st, pl->partials, s));
             SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, i, pl->r, pl->p, pl->st, pl->partials, s));
         } else {
-            SPK_HIP(ctx, spk::launch_cg_update32(n, pl->vec_grid, pl->tune32.grid, i, pl->p32, pl->r32, pl->q32,
-                                                 pl->st_in, pl->partials, s));
+            SPK_HIP(ctx, spk::launch_cg_update32(n, pl->vec_grid, pl->tune32.grid, i, pl->r32, pl->q32, pl->st_in,
+                                                 pl->partials, s));
             SPK_HIP(ctx, spk::launch_cg_pupdate32(n, pl->vec_grid, i, pl->r32, pl->p32, pl->st_in, pl->partials, s));
         }
     }
@@ -477,6 +481,8 @@ void release_workspace(spk_plan pl) {
     ctx->hpool.put(pl->h_st_in);
     ctx->dpool.put(pl->out_dev);
     ctx->hpool.put(pl->h_out);
+    ctx->dpool.put(pl->bar);
+    pl->bar = nullptr;
     pl->r = pl->p = pl->q = pl->partials = pl->hist = nullptr;
     pl->st = pl->h_st = pl->st_in = pl->h_st_in = nullptr;
     pl->a32_vals = nullptr;
@@ -540,6 +546,9 @@ spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
         return SPK_ERR_DEVICE;
     }
     ctx->num_cu = prop.multiProcessorCount;
+    if (hipDeviceGetAttribute(&ctx->wall_khz, hipDeviceAttributeWallClockRate, device_id) != hipSuccess ||
+        ctx->wall_khz <= 0)
+        ctx->wall_khz = 100000;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) ctx->dpool.set_cap(total_b / 4);
     ctx->hpool.set_cap(size_t(16) << 20);
@@ -650,7 +659,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown precision");
     if (cfg.max_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_iters < 0");
     if (!(cfg.reduction_factor >= 0.0)) return fail(ctx, SPK_ERR_INVALID_ARG, "reduction_factor must be >= 0");
-    if (cfg.exec_mode < SPK_EXEC_AUTO || cfg.exec_mode > SPK_EXEC_GRAPH)
+    if (cfg.exec_mode < SPK_EXEC_AUTO || cfg.exec_mode > SPK_EXEC_PERSISTENT)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown exec_mode");
     if (cfg.chunk_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "chunk_iters < 0");
     const bool mixed = cfg.precision != SPK_PREC_FP64;
@@ -747,7 +756,28 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         pl->tune = heuristic_tune(ctx, pl->A);
     }
     int mode = cfg.exec_mode;
-    if (mode == SPK_EXEC_AUTO) mode = (A->nnz < 4000000) ? SPK_EXEC_GRAPH : SPK_EXEC_HOST_LOOP;
+    // Automatic choice: the host-issued loop.  On MI355X its launches queue
+    // back to back (about 8 us per iteration at the smallest sizes), which
+    // measured faster than replaying captured chunks or one cooperative
+    // launch with grid barriers.
+    if (mode == SPK_EXEC_AUTO) mode = SPK_EXEC_HOST_LOOP;
+    if (mode == SPK_EXEC_PERSISTENT && mixed) mode = SPK_EXEC_GRAPH;
+    if (mode == SPK_EXEC_PERSISTENT) {
+        const int occ = spk::persistent_blocks_per_cu(pl->A);
+        const int64_t tiles = std::max<int64_t>((n + spk::kTileRows - 1) / spk::kTileRows, 1);
+        const int64_t g = std::min<int64_t>({tiles, int64_t(occ) * ctx->num_cu, int64_t(spk::kMaxGrid)});
+        void *bv = nullptr;
+        if (occ <= 0 || g < 1) {
+            mode = SPK_EXEC_GRAPH;
+        } else if (ctx->dpool.get(4 * sizeof(unsigned), &bv) != hipSuccess) {
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "barrier words");
+        } else {
+            pl->bar = static_cast<unsigned *>(bv);
+            pl->persist_grid = static_cast<int>(g);
+            if (hipMemsetAsync(pl->bar, 0, 4 * sizeof(unsigned), ctx->stream) != hipSuccess)
+                return cleanup(SPK_ERR_DEVICE, "barrier init");
+        }
+    }
     pl->info.exec_mode = mode;
     pl->info.chunk_iters = cfg.chunk_iters;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(SPK_ERR_DEVICE, "plan sync");
@@ -774,12 +804,27 @@ spk_status spk_execute_spmv(spk_plan pl, const void *x, void *y) {
 static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log *L, bool graph) {
     spk_ctx ctx = pl->ctx;
     const spk_solver_cfg &cfg = pl->cfg;
-    SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->p, pl->st, pl->partials,
-                                     cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
-    spk_status s = run_loop(pl, LOOP_FP64, cfg.max_iters, graph);
-    if (s != SPK_OK) return s;
-    SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual, ctx->stream));
-    if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
+    spk_status s = SPK_OK;
+    if (pl->persist_grid > 0) {
+        // one cooperative launch; the barrier gives up after 2 s of waiting
+        const uint64_t spin = static_cast<uint64_t>(ctx->wall_khz) * 2000ull;
+        SPK_HIP(ctx, hipMemsetAsync(pl->bar, 0, 4 * sizeof(unsigned), ctx->stream));
+        SPK_HIP(ctx, spk::launch_cg_persistent(pl->A, pl->persist_grid, pl->tune.xcd_remap, b, x, pl->r, pl->p, pl->q,
+                                               pl->st, pl->partials, pl->bar, spin, cfg.reduction_factor,
+                                               cfg.max_iters, pl->hist, pl->hist_cap, cfg.true_residual, ctx->stream));
+        unsigned flags[4] = {0, 0, 0, 0};
+        SPK_HIP(ctx, hipMemcpyAsync(flags, pl->bar, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream));
+        if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
+        if (flags[2] != 0) return fail(ctx, SPK_ERR_DEVICE, "persistent solve: a grid barrier timed out");
+    } else {
+        SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->p, pl->st, pl->partials,
+                                         cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
+        s = run_loop(pl, LOOP_FP64, cfg.max_iters, graph);
+        if (s != SPK_OK) return s;
+        SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
+                                             ctx->stream));
+        if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
+    }
     const SolveState &h = *pl->h_st;
     if (pl->profiling) {
         const int64_t useful = h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
@@ -835,15 +880,15 @@ static spk_status execute_mixed(spk_plan pl, const double *b, double *x, spk_log
         if ((s = run_loop(pl, LOOP_FP32, cfg.max_iters - inner_total, graph)) != SPK_OK) return s;
         const SolveState &h = *pl->h_st_in;
         inner_total += h.iter;
+        if (pl->profiling) {   // this inner solve's SpMV launches that did work
+            if ((s = prof_collect(pl, h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0))) != SPK_OK) return s;
+        }
         if ((h.stop == spk::STOP_BREAKDOWN || h.stop == spk::STOP_NON_FINITE) && h.iter == 0) {
             stop = h.stop;
             break;
         }
         SPK_HIP(ctx, spk::launch_ir_correct(n, pl->vec_grid, x, pl->d32, ctx->stream));
         ++outer;
-    }
-    if (pl->profiling) {
-        if ((s = prof_collect(pl, inner_total)) != SPK_OK) return s;
     }
     L->iterations = inner_total;
     L->outer_iterations = outer;

@@ -38,22 +38,49 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Tiles visited by this workgroup.
+// Tiles visited by this workgroup (workgroups are dispatched round-robin over
+// the 8 XCDs, workgroup b on XCD b % 8).
+//   remap = 0: tile t -> workgroup t mod G (consecutive tiles on different XCDs)
+//   remap = 1: XCD x walks the contiguous eighth [x T/8, (x+1) T/8)
+//   remap = k >= 2: tiles grouped in blocks of k; block B belongs to XCD B % 8,
+//     and each XCD walks its blocks in order, so all XCDs sweep one front
+//     while each block's neighbouring rows share one L2.
 struct TileIter {
-    int64_t t, end, stride;
+    int64_t j, end, stride;   // position in this XCD's (or the global) tile sequence
+    int64_t k, xcd;           // block size and XCD for remap >= 2
+    int mode;
     __device__ TileIter(int64_t T, int remap) {
         const int64_t G = gridDim.x, b = blockIdx.x;
-        if (remap && G >= kNumXcd) {
-            const int64_t xcd = b % kNumXcd, m = b / kNumXcd;
-            const int64_t M = (G - xcd + kNumXcd - 1) / kNumXcd;   // workgroups on this XCD
-            t = xcd * T / kNumXcd + m;
+        mode = (G >= kNumXcd && remap >= 1) ? (remap == 1 ? 1 : 2) : 0;
+        k = remap;
+        xcd = b % kNumXcd;
+        const int64_t m = b / kNumXcd;
+        const int64_t M = (G - xcd + kNumXcd - 1) / kNumXcd;   // workgroups on this XCD
+        if (mode == 0) {
+            j = b;
+            end = T;
+            stride = G;
+        } else if (mode == 1) {
+            j = xcd * T / kNumXcd + m;
             end = (xcd + 1) * T / kNumXcd;
             stride = M;
         } else {
-            t = b;
-            end = T;
-            stride = G;
+            // tiles of this XCD: blocks xcd, xcd + 8, ...; the last block may be short
+            const int64_t nb = (T + k - 1) / k;                    // blocks
+            const int64_t my_blocks = nb > xcd ? (nb - xcd + kNumXcd - 1) / kNumXcd : 0;
+            int64_t count = my_blocks * k;
+            if (my_blocks > 0 && (xcd + (my_blocks - 1) * kNumXcd) == nb - 1) count -= nb * k - T;
+            j = m;
+            end = count;
+            stride = M;
         }
+    }
+    __device__ bool valid() const { return j < end; }
+    __device__ void next() { j += stride; }
+    __device__ int64_t tile() const {
+        if (mode != 2) return j;
+        const int64_t blk = (j / k) * kNumXcd + xcd;
+        return blk * k + j % k;
     }
 };
 
@@ -182,10 +209,25 @@ __device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, i
     }
 }
 
+// Gathers of the SpMV's input vector at column c.
+template <typename X, typename C>
+struct PlainGather {   // x[c]
+    const X *__restrict__ x;
+    __device__ __forceinline__ C operator()(int64_t c) const { return static_cast<C>(x[c]); }
+};
+
+template <typename T>
+struct PUpdateGather {   // p_k[c] = fma(beta, p_{k-1}[c], r_k[c]): the CG direction formed on the fly
+    T beta;
+    const T *__restrict__ p_old;
+    const T *__restrict__ r;
+    __device__ __forceinline__ T operator()(int64_t c) const { return fma(beta, p_old[c], r[c]); }
+};
+
 // Sum of row [a, b) with values/columns read from LDS (offsets s0v / s0c).
-template <typename V, typename I, typename X, typename C>
+template <typename V, typename I, typename C, class Gx>
 __device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, int64_t b, int64_t s0v, int64_t s0c,
-                                          const X *__restrict__ x) {
+                                          const Gx &gx) {
     C sum = 0;
     for (int64_t k0 = a; k0 < b; k0 += kRowUnroll) {
         C av[kRowUnroll], xv[kRowUnroll];
@@ -194,7 +236,7 @@ __device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, i
             const int64_t k = k0 + u;
             if (k < b) {
                 av[u] = static_cast<C>(widen(sv[k - s0v]));
-                xv[u] = static_cast<C>(x[sc[k - s0c]]);
+                xv[u] = static_cast<C>(gx(static_cast<int64_t>(sc[k - s0c])));
             } else {
                 av[u] = 0;
                 xv[u] = 0;
@@ -206,13 +248,12 @@ __device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, i
     return sum;
 }
 
-template <typename V, typename I, typename X, typename C>
+template <typename V, typename I, typename C, class Gx>
 __device__ __forceinline__ C row_from_global(const V *__restrict__ va, const I *__restrict__ ci, int64_t a, int64_t b,
-                                             const X *__restrict__ x, int nt) {
+                                             const Gx &gx, int nt) {
     C sum = 0;
-    for (int64_t k = a; k < b; ++k) {
-        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(x[ci[k]]), sum);
-    }
+    for (int64_t k = a; k < b; ++k)
+        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(gx(static_cast<int64_t>(ci[k]))), sum);
     return sum;
 }
 

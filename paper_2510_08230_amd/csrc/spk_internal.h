@@ -76,15 +76,16 @@ hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipS
 hipError_t launch_spmv(const CsrDev &A, const SpmvTune &t, const void *x, void *y, hipStream_t s);
 
 // CG (FP64).  partials: SITE_COUNT * kSiteWidth * kMaxGrid doubles.
-// Iteration j of a chunk = spmv_pq, update(j), pupdate(j); a chunk of c
-// iterations ends with chunk_end(c).
+// Iteration j of a chunk = spmv_pq (q = A p, p.q partials), update(j)
+// (alpha, r -= alpha q, r.r partials), pupdate(j) (x += alpha p, stop test,
+// beta, p = r + beta p); a chunk of c iterations ends with chunk_end(c).
 hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, double *r,
                           double *p, SolveState *st, double *partials, double tau, int64_t max_iters,
                           double *hist, int64_t hist_cap, hipStream_t s);
 hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q,
                              SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, const double *p, double *r,
-                            const double *q, SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, double *r, const double *q, SolveState *st,
+                            double *partials, hipStream_t s);
 hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st,
                              double *partials, hipStream_t s);
 hipError_t launch_cg_chunk_end(SolveState *st, int count, hipStream_t s);
@@ -93,8 +94,8 @@ hipError_t launch_cg_chunk_end(SolveState *st, int count, hipStream_t s);
 // refinement steps in FP64 (A values F64, or F32 taken as exact).
 hipError_t launch_cg_spmv_pq32(const CsrDev &A32, const SpmvTune &t, const float *p, float *q, SolveState *st,
                                double *partials, hipStream_t s);
-hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, const float *p, float *r, const float *q,
-                              SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, float *r, const float *q, SolveState *st,
+                              double *partials, hipStream_t s);
 hipError_t launch_cg_pupdate32(int64_t n, int grid, int j, const float *r, float *p, SolveState *st,
                                double *partials, hipStream_t s);
 // r = b - A x (FP64); r32 = p32 = fl32(r), d32 = 0; inner state set up;
@@ -110,6 +111,16 @@ hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *
                               SolveState *st, double *partials, int true_residual, hipStream_t s);
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s);
+
+// Whole FP64 CG solve in one cooperative launch (grid must be co-resident:
+// grid <= persistent_blocks_per_cu * CUs).  partials: at least 5 * kMaxGrid
+// doubles.  bar: 3 unsigned, [0] and [2] zero at launch.  Afterwards
+// bar[2] != 0 means a barrier waited longer than spin_ticks (wall clock).
+hipError_t launch_cg_persistent(const CsrDev &A, int grid, int remap, const double *b, double *x, double *r, double *p,
+                                double *q, SolveState *st, double *partials, unsigned *bar, uint64_t spin_ticks,
+                                double tau, int64_t max_iters, double *hist, int64_t hist_cap, int true_residual,
+                                hipStream_t s);
+int persistent_blocks_per_cu(const CsrDev &A);
 
 // Workgroups of the SpMV kernel resident per CU for this tune/type (occupancy API).
 int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t);

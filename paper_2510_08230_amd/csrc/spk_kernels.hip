@@ -133,19 +133,18 @@ struct EpiTrue {
 // LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
 // thread per row reduces from LDS while gathering x.  Occupancy (several
 // workgroups per CU) overlaps one workgroup's DMA with another's gathers.
-template <typename V, typename P, typename I, typename X, typename C, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
-                                                        const I *__restrict__ ci, const V *__restrict__ va,
-                                                        const X *__restrict__ x, int remap, int nt, Epi epi_in) {
-    Epi epi = epi_in;
-    if (epi.skip()) return;
-    __shared__ u32x4 lv[Chunks<V>::LDS];
-    __shared__ u32x4 lc[Chunks<I>::LDS];
+// The tile loop of the LDS-staged SpMV, shared by the per-launch kernel and the
+// persistent CG kernel: calls epi.row(row, sum) for every row of the tiles
+// this workgroup visits.  lv / lc: the workgroup's LDS staging buffers.
+template <typename V, typename P, typename I, typename C, class Gx, class Epi>
+__device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
+                                               const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
+                                               int remap, int nt, Epi &epi, u32x4 *lv, u32x4 *lc) {
     const V *sv = reinterpret_cast<const V *>(lv);
     const I *sc = reinterpret_cast<const I *>(lc);
     const int64_t T = (n + kTileRows - 1) / kTileRows;
-    for (TileIter it(T, remap); it.t < it.end; it.t += it.stride) {
-        const int64_t r0 = it.t * kTileRows;
+    for (TileIter it(T, remap); it.valid(); it.next()) {
+        const int64_t r0 = it.tile() * kTileRows;
         const int64_t r1 = min(r0 + static_cast<int64_t>(kTileRows), n);
         const int64_t s = static_cast<int64_t>(rp[r0]);
         const int64_t e = static_cast<int64_t>(rp[r1]);
@@ -163,14 +162,52 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, 
             if (row < r1) {
                 const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
                 const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
-                epi.row(row, row_from_lds<V, I, X, C>(sv, sc, a, b, s0v, s0c, x));
+                epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx));
             }
             __syncthreads();                 // LDS free for the next tile
         } else if (row < r1) {
-            epi.row(row, row_from_global<V, I, X, C>(va, ci, a, b, x, nt));
+            epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt));
         }
     }
+}
+
+template <typename V, typename P, typename I, typename X, typename C, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
+                                                        const I *__restrict__ ci, const V *__restrict__ va,
+                                                        const X *__restrict__ x, int remap, int nt, Epi epi_in) {
+    Epi epi = epi_in;
+    if (epi.skip()) return;
+    __shared__ u32x4 lv[Chunks<V>::LDS];
+    __shared__ u32x4 lc[Chunks<I>::LDS];
+    spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, epi, lv, lc);
     epi.finish();
+}
+
+template <typename V, typename P, typename I, typename C, class Gx, class Epi>
+__device__ __forceinline__ void spmv_tiles_vector(int64_t n, const P *__restrict__ rp, const I *__restrict__ ci,
+                                                  const V *__restrict__ va, const Gx &gx, int lanes_log2, int remap,
+                                                  int nt, Epi &epi) {
+    const int L = 1 << lanes_log2;
+    const int lane = threadIdx.x & (L - 1);
+    const int group = threadIdx.x >> lanes_log2;
+    const int groups = kBlock >> lanes_log2;
+    const int64_t T = (n + kTileRows - 1) / kTileRows;
+    for (TileIter it(T, remap); it.valid(); it.next()) {
+        const int64_t r0 = it.tile() * kTileRows;
+        const int64_t r1 = min(r0 + (int64_t)kTileRows, n);
+        for (int pass = 0; pass < L; ++pass) {
+            const int64_t row = r0 + static_cast<int64_t>(pass) * groups + group;
+            C sum = 0;
+            if (row < r1) {
+                const int64_t a = static_cast<int64_t>(rp[row]), b = static_cast<int64_t>(rp[row + 1]);
+                for (int64_t k = a + lane; k < b; k += L)
+                    sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(gx(static_cast<int64_t>(ci[k]))),
+                              sum);
+            }
+            for (int off = L >> 1; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+            if (row < r1 && lane == 0) epi.row(row, sum);
+        }
+    }
 }
 
 template <typename V, typename P, typename I, typename X, typename C, class Epi>
@@ -180,27 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int64_t n, const P *__re
                                                         int nt, Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
-    const int L = 1 << lanes_log2;
-    const int lane = threadIdx.x & (L - 1);
-    const int group = threadIdx.x >> lanes_log2;
-    const int groups = kBlock >> lanes_log2;
-    const int64_t T = (n + kTileRows - 1) / kTileRows;
-    for (TileIter it(T, remap); it.t < it.end; it.t += it.stride) {
-        const int64_t r0 = it.t * kTileRows;
-        const int64_t r1 = min(r0 + (int64_t)kTileRows, n);
-        for (int pass = 0; pass < L; ++pass) {
-            const int64_t row = r0 + static_cast<int64_t>(pass) * groups + group;
-            C sum = 0;
-            if (row < r1) {
-                const int64_t a = static_cast<int64_t>(rp[row]), b = static_cast<int64_t>(rp[row + 1]);
-                for (int64_t k = a + lane; k < b; k += L) {
-                    sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(x[ci[k]]), sum);
-                }
-            }
-            for (int off = L >> 1; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
-            if (row < r1 && lane == 0) epi.row(row, sum);
-        }
-    }
+    spmv_tiles_vector<V, P, I, C>(n, rp, ci, va, PlainGather<X, C>{x}, lanes_log2, remap, nt, epi);
     epi.finish();
 }
 
@@ -285,13 +302,13 @@ struct Vec16 {
     typedef T type __attribute__((ext_vector_type(W)));
 };
 
-// x += alpha p, r -= alpha q with alpha = rho_k / (p.q) (FP64 scalar, applied
-// in T); partials of r.r accumulated in FP64.  j: index of this iteration
-// within the launched chunk.
+// r -= alpha q with alpha = rho_k / (p . q) (FP64 scalar, applied in T);
+// partials of r.r accumulated in FP64.  x += alpha p is left to the p-update
+// kernel, which reads p anyway.  j: index of this iteration within the chunk.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const T *__restrict__ p, T *__restrict__ r,
-                                                      const T *__restrict__ q, SolveState *st, const double *part_pq,
-                                                      int G_pq, double *part_rr, int j) {
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, T *__restrict__ r, const T *__restrict__ q,
+                                                      SolveState *st, const double *part_pq, int G_pq,
+                                                      double *part_rr, int j) {
     if (st->stop != STOP_RUNNING) return;
     const int64_t k = st->base + j;
     double tot[1];
@@ -310,35 +327,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const T *__rest
         st->alpha = alpha_d;
     }
     const T alpha = static_cast<T>(alpha_d);
-    T *__restrict__ x = static_cast<T *>(st->x);
     double acc = 0.0;
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     constexpr int W = Vec16<T>::W;
     using VT = typename Vec16<T>::type;
-    int64_t done = 0;
-    if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
-        const int64_t nv = n / W;
-        VT *xv_ = reinterpret_cast<VT *>(x);
-        VT *rv_ = reinterpret_cast<VT *>(r);
-        const VT *pv_ = reinterpret_cast<const VT *>(p);
-        const VT *qv_ = reinterpret_cast<const VT *>(q);
-        for (int64_t i = gid; i < nv; i += stride) {
-            VT xv = xv_[i], rv = rv_[i];
-            const VT pv = pv_[i], qv = qv_[i];
+    const int64_t nv = n / W;
+    VT *rv_ = reinterpret_cast<VT *>(r);
+    const VT *qv_ = reinterpret_cast<const VT *>(q);
+    for (int64_t i = gid; i < nv; i += stride) {
+        VT rv = rv_[i];
+        const VT qv = qv_[i];
 #pragma unroll
-            for (int c = 0; c < W; ++c) {
-                xv[c] = fma(alpha, pv[c], xv[c]);
-                rv[c] = fma(-alpha, qv[c], rv[c]);
-                acc = fma(static_cast<double>(rv[c]), static_cast<double>(rv[c]), acc);
-            }
-            xv_[i] = xv;
-            rv_[i] = rv;
+        for (int c = 0; c < W; ++c) {
+            rv[c] = fma(-alpha, qv[c], rv[c]);
+            acc = fma(static_cast<double>(rv[c]), static_cast<double>(rv[c]), acc);
         }
-        done = nv * W;
+        rv_[i] = rv;
     }
-    for (int64_t i = done + gid; i < n; i += stride) {
-        x[i] = fma(alpha, p[i], x[i]);
+    for (int64_t i = nv * W + gid; i < n; i += stride) {
         const T ri = fma(-alpha, q[i], r[i]);
         r[i] = ri;
         acc = fma(static_cast<double>(ri), static_cast<double>(ri), acc);
@@ -347,11 +354,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const T *__rest
     block_partial<1>(v, part_rr);
 }
 
-// rho_{k+1} = r.r; stop test; p = r + beta p with beta = rho_{k+1} / rho_k.
+// End of iteration k: x += alpha_k p_k (deferred from the update), then the
+// stop test on rho_{k+1} = r.r (partials of the update kernel), beta =
+// rho_{k+1} / rho_k and, unless stopping, p = r + beta p.  One pass over
+// x, p and r.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const T *__restrict__ r, T *__restrict__ p,
                                                        SolveState *st, const double *part_rr, int G_rr, int j) {
-    if (st->stop != STOP_RUNNING) return;
+    if (st->stop != STOP_RUNNING) return;   // breakdown in the update: x keeps x_k
     const int64_t k = st->base + j;
     double tot[1];
     sum_partials<1>(part_rr, G_rr, tot);
@@ -363,6 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const T *__res
     else if (res <= st->thresh) stop = STOP_CONVERGED;
     else if (k1 >= st->max_iters) stop = STOP_MAX_ITERS;
     const double beta_d = rho_new / st->rho[k & 3];
+    const T alpha = static_cast<T>(st->alpha);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iter = k1;
         st->resnorm = res;
@@ -370,23 +381,47 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const T *__res
         if (st->hist && k1 < st->hist_cap) st->hist[k1] = res;
         if (stop != STOP_RUNNING) st->stop = stop;
     }
-    if (stop != STOP_RUNNING) return;
     const T beta = static_cast<T>(beta_d);
+    T *__restrict__ x = static_cast<T *>(st->x);
+    const bool more = stop == STOP_RUNNING;
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     constexpr int W = Vec16<T>::W;
     using VT = typename Vec16<T>::type;
-    const int64_t nv = n / W;
-    const VT *rv_ = reinterpret_cast<const VT *>(r);
-    VT *pv_ = reinterpret_cast<VT *>(p);
-    for (int64_t i = gid; i < nv; i += stride) {
-        const VT rv = rv_[i];
-        VT pv = pv_[i];
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        const int64_t nv = n / W;
+        VT *xv_ = reinterpret_cast<VT *>(x);
+        VT *pv_ = reinterpret_cast<VT *>(p);
+        const VT *rv_ = reinterpret_cast<const VT *>(r);
+        if (more) {
+            for (int64_t i = gid; i < nv; i += stride) {
+                VT xv = xv_[i], pv = pv_[i];
+                const VT rv = rv_[i];
 #pragma unroll
-        for (int c = 0; c < W; ++c) pv[c] = fma(beta, pv[c], rv[c]);
-        pv_[i] = pv;
+                for (int c = 0; c < W; ++c) {
+                    xv[c] = fma(alpha, pv[c], xv[c]);
+                    pv[c] = fma(beta, pv[c], rv[c]);
+                }
+                xv_[i] = xv;
+                pv_[i] = pv;
+            }
+        } else {
+            for (int64_t i = gid; i < nv; i += stride) {
+                VT xv = xv_[i];
+                const VT pv = pv_[i];
+#pragma unroll
+                for (int c = 0; c < W; ++c) xv[c] = fma(alpha, pv[c], xv[c]);
+                xv_[i] = xv;
+            }
+        }
+        done = nv * W;
     }
-    for (int64_t i = nv * W + gid; i < n; i += stride) p[i] = fma(beta, p[i], r[i]);
+    for (int64_t i = done + gid; i < n; i += stride) {
+        const T pi = p[i];
+        x[i] = fma(alpha, pi, x[i]);
+        if (more) p[i] = fma(beta, pi, r[i]);
+    }
 }
 
 // Refinement: finish the outer residual (||r64||, the outer stop test) and
@@ -473,6 +508,202 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, const SolveState *
     double *x = static_cast<double *>(st->x);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ persistent CG
+// The whole FP64 CG solve in one cooperative launch (all workgroups resident):
+// init, then per iteration SpMV+p.q | update+r.r | p-update, each phase
+// followed by a grid barrier.  After a barrier every workgroup sums the same
+// partials in the same order, so all take identical decisions (alpha, beta,
+// stop) and leave the loop together.  Workgroup 0 mirrors the results into
+// the SolveState for the host.  The barrier's release/acquire at agent scope
+// makes each phase's vector writes visible to every XCD before the next phase.
+// A barrier that waits longer than a wall-clock limit sets the error flag;
+// every workgroup then leaves, so the launch always ends.
+
+struct PersistArgs {
+    int64_t n, nnz;
+    const void *rp, *ci;
+    const double *va, *b;
+    double *x, *r, *p, *q;
+    SolveState *st;
+    double *part;          // 5 disjoint slabs of kMaxGrid doubles
+    unsigned *bar;         // [0] arrivals, [1] generation, [2] error flag
+    uint64_t spin_ticks;   // barrier wait limit in wall_clock64() ticks
+    double tau;
+    int64_t max_iters;
+    double *hist;
+    int64_t hist_cap;
+    int remap, true_residual;
+};
+
+// Grid-wide barrier; returns false once any workgroup has timed out.
+__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned &gen, uint64_t spin_ticks) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        if (ok) {
+            const unsigned g0 = gen;
+            const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == gridDim.x - 1) {
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar[1], g0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                    if (wall_clock64() - t0 > spin_ticks) {
+                        __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+            gen = g0 + 1;
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <typename P, typename I>
+__global__ __launch_bounds__(kBlock) void k_cg_persistent(PersistArgs a) {
+    __shared__ u32x4 lv[Chunks<double>::LDS];
+    __shared__ u32x4 lc[Chunks<I>::LDS];
+    __shared__ unsigned s_gen0;
+    const P *rp = static_cast<const P *>(a.rp);
+    const I *ci = static_cast<const I *>(a.ci);
+    const int64_t n = a.n;
+    const int G = gridDim.x;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (threadIdx.x == 0) s_gen0 = __hip_atomic_load(&a.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    unsigned gen = s_gen0;
+    // disjoint slabs: init (2), p.q, r.r; the init slabs are reused by the true residual
+    double *part_a = a.part, *part_b = a.part + 2 * kMaxGrid, *part_c = a.part + 3 * kMaxGrid;
+    // this workgroup's contiguous, even-aligned row chunk for the vector phases
+    int64_t chunk = (n + G - 1) / G;
+    chunk += chunk & 1;
+    const int64_t v0 = min(static_cast<int64_t>(blockIdx.x) * chunk, n);
+    const int64_t v1 = min(v0 + chunk, n);
+
+    // ---- init: r = b - A x, p = r; ||b||, rho_0
+    {
+        EpiInit e{a.b, a.r, a.p, part_a, 0.0, 0.0};
+        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, e, lv, lc);
+        e.finish();   // partials of r.r, b.b into part_a[0..G), part_a[kMaxGrid..)
+    }
+    if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
+    double tot2[2];
+    sum_partials<2>(part_a, G, tot2);
+    const double bn = sqrt(tot2[1]);
+    double rho = tot2[0];
+    int stop = STOP_RUNNING, zero_x = 0;
+    double res = sqrt(rho);
+    if (!isfinite(bn)) {
+        stop = STOP_NON_FINITE;
+        res = bn;
+    } else if (bn == 0.0) {
+        stop = STOP_CONVERGED;
+        zero_x = 1;
+        res = 0.0;
+    } else if (!isfinite(rho)) stop = STOP_NON_FINITE;
+    else if (res <= a.tau * bn) stop = STOP_CONVERGED;
+    else if (a.max_iters <= 0) stop = STOP_MAX_ITERS;
+    if (lead) {
+        SolveState *S = a.st;
+        S->x = a.x;
+        S->hist = a.hist;
+        S->hist_cap = a.hist_cap;
+        S->max_iters = a.max_iters;
+        S->base = 0;
+        S->iter = 0;
+        S->zero_x = zero_x;
+        S->bnorm = bn;
+        S->thresh = a.tau * bn;
+        S->rho[0] = zero_x ? 0.0 : rho;
+        S->resnorm = res;
+        S->true_resnorm = zero_x ? 0.0 : __builtin_nan("");
+        S->stop = stop;
+        if (a.hist && a.hist_cap > 0) a.hist[0] = res;
+    }
+    int64_t k = 0;
+    while (stop == STOP_RUNNING) {
+        // q = A p, partials of p.q
+        {
+            EpiPq<double> e{a.q, a.p, a.st, part_b, 0.0};
+            spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.p}, a.remap, 0,
+                                                 e, lv, lc);
+            e.finish();
+        }
+        if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
+        double t1[1];
+        sum_partials<1>(part_b, G, t1);
+        const double pq = t1[0];
+        if (!isfinite(pq) || pq <= 0.0) {
+            stop = isfinite(pq) ? STOP_BREAKDOWN : STOP_NON_FINITE;
+            if (lead) {
+                a.st->pq = pq;
+                a.st->stop = stop;
+            }
+            break;
+        }
+        const double alpha = rho / pq;
+        double acc = 0.0;
+        for (int64_t i = v0 + threadIdx.x; i < v1; i += kBlock) {
+            a.x[i] = fma(alpha, a.p[i], a.x[i]);
+            const double ri = fma(-alpha, a.q[i], a.r[i]);
+            a.r[i] = ri;
+            acc = fma(ri, ri, acc);
+        }
+        {
+            double v[1] = {acc};
+            block_partial<1>(v, part_c);
+        }
+        if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
+        sum_partials<1>(part_c, G, t1);
+        const double rho_new = t1[0];
+        k += 1;
+        res = sqrt(rho_new);
+        if (!isfinite(rho_new)) stop = STOP_NON_FINITE;
+        else if (res <= a.tau * bn) stop = STOP_CONVERGED;
+        else if (k >= a.max_iters) stop = STOP_MAX_ITERS;
+        if (lead) {
+            a.st->iter = k;
+            a.st->resnorm = res;
+            a.st->pq = pq;
+            a.st->alpha = alpha;
+            a.st->rho[k & 3] = rho_new;
+            if (a.hist && k < a.hist_cap) a.hist[k] = res;
+            if (stop != STOP_RUNNING) a.st->stop = stop;
+        }
+        if (stop != STOP_RUNNING) break;
+        const double beta = rho_new / rho;
+        rho = rho_new;
+        for (int64_t i = v0 + threadIdx.x; i < v1; i += kBlock) a.p[i] = fma(beta, a.p[i], a.r[i]);
+        if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
+    }
+    if (zero_x) {
+        for (int64_t i = v0 + threadIdx.x; i < v1; i += kBlock) a.x[i] = 0.0;
+        return;
+    }
+    if (!a.true_residual || stop == STOP_NON_FINITE) return;
+    if (!grid_sync(a.bar, gen, a.spin_ticks)) return;   // x complete everywhere
+    {
+        EpiTrue e{a.b, a.st, part_a, 0.0};
+        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, e, lv, lc);
+        e.finish();
+    }
+    if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
+    double t1[1];
+    sum_partials<1>(part_a, G, t1);
+    if (lead) a.st->true_resnorm = sqrt(t1[0]);
 }
 
 // ------------------------------------------------------------------ structure kernels
@@ -617,16 +848,16 @@ hipError_t launch_cg_spmv_pq32(const CsrDev &A32, const SpmvTune &t, const float
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, const double *p, double *r, const double *q,
-                            SolveState *st, double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<double>, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_PQ),
+hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, double *r, const double *q, SolveState *st,
+                            double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(grid), dim3(kBlock), 0, s, n, r, q, st, site(partials, SITE_PQ),
                        spmv_grid, site(partials, SITE_RR), j);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, const float *p, float *r, const float *q,
-                              SolveState *st, double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(grid), dim3(kBlock), 0, s, n, p, r, q, st, site(partials, SITE_PQ),
+hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, float *r, const float *q, SolveState *st,
+                              double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(grid), dim3(kBlock), 0, s, n, r, q, st, site(partials, SITE_PQ),
                        spmv_grid, site(partials, SITE_RR), j);
     return hipGetLastError();
 }
@@ -687,6 +918,35 @@ hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_true_finish, dim3(1), dim3(kBlock), 0, s, st, site(partials, SITE_TRUE), t.grid);
     return hipGetLastError();
+}
+
+template <typename P, typename I>
+static hipError_t launch_persist_t(const PersistArgs &a, int grid, hipStream_t s) {
+    void *args[] = {const_cast<PersistArgs *>(&a)};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_persistent<P, I>), dim3(grid), dim3(kBlock),
+                                      args, 0, s);
+}
+
+hipError_t launch_cg_persistent(const CsrDev &A, int grid, int remap, const double *b, double *x, double *r, double *p,
+                                double *q, SolveState *st, double *partials, unsigned *bar, uint64_t spin_ticks,
+                                double tau, int64_t max_iters, double *hist, int64_t hist_cap, int true_residual,
+                                hipStream_t s) {
+    PersistArgs a{A.n_rows, A.nnz, A.rp, A.ci, static_cast<const double *>(A.va), b, x, r, p, q, st, partials, bar,
+                  spin_ticks, tau, max_iters, hist, hist_cap, remap, true_residual};
+    if (A.ptr_t == 0 && A.idx_t == 0) return launch_persist_t<int32_t, int32_t>(a, grid, s);
+    if (A.ptr_t == 0) return launch_persist_t<int32_t, int64_t>(a, grid, s);
+    if (A.idx_t == 0) return launch_persist_t<int64_t, int32_t>(a, grid, s);
+    return launch_persist_t<int64_t, int64_t>(a, grid, s);
+}
+
+int persistent_blocks_per_cu(const CsrDev &A) {
+    int blocks = 0;
+    hipError_t e;
+    if (A.ptr_t == 0 && A.idx_t == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int32_t, int32_t>, kBlock, 0);
+    else if (A.ptr_t == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int32_t, int64_t>, kBlock, 0);
+    else if (A.idx_t == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int64_t, int32_t>, kBlock, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int64_t, int64_t>, kBlock, 0);
+    return (e == hipSuccess && blocks > 0) ? blocks : 0;
 }
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s) {

@@ -29,7 +29,7 @@ CSR_OK, CSR_BAD_SIZE, CSR_BAD_FIRST, CSR_DECREASING, CSR_BAD_LAST, CSR_BAD_COLUM
 STOP_RUNNING, STOP_CONVERGED, STOP_MAX_ITERS, STOP_BREAKDOWN, STOP_NON_FINITE = range(5)
 SOLVER_CG = 0
 PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = range(3)
-EXEC_AUTO, EXEC_HOST_LOOP, EXEC_GRAPH = range(3)
+EXEC_AUTO, EXEC_HOST_LOOP, EXEC_GRAPH, EXEC_PERSISTENT = range(4)
 
 
 class SpkError(RuntimeError):

@@ -84,7 +84,7 @@ def test_fixed_k_iterates(spk, ctx, name, K):
 
 
 @pytest.mark.parametrize("name", sorted(MATS))
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_converged_parity(spk, ctx, name, mode):
     A = MATS[name]()
     b = inputs.rhs(A.n_rows, 0)
@@ -105,6 +105,47 @@ def test_modes_and_reruns_bitwise(spk, ctx):
     runs = [solve(spk, ctx, A, b, mode=m, chunk=c)[0] for m, c in ((1, 0), (2, 0), (1, 3), (2, 5), (1, 0))]
     for x in runs[1:]:
         assert np.array_equal(x.view(np.uint64), runs[0].view(np.uint64))
+
+
+def test_persistent_reruns_bitwise_and_parity(spk, ctx):
+    """One cooperative launch per solve: reproducible bit for bit, and within tolerance of the oracle."""
+    A = inputs.stencil7(30, 2)
+    b = inputs.rhs(A.n_rows, 2)
+    x1, l1, h1 = solve(spk, ctx, A, b, mode=3, history=True)
+    x2, l2, _ = solve(spk, ctx, A, b, mode=3)
+    assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64)) and l1.iterations == l2.iterations
+    xo, ro, ho = oracle.cg(A, b, tau=1e-14, max_iters=1000, history=True)
+    assert l1.stop_reason == spk.STOP_CONVERGED and abs(l1.iterations - ro.iterations) <= 1
+    assert rel(x1, xo) <= 1e-12
+    k = min(h1.size, ho.size)
+    assert np.all(np.abs(h1[:k] - ho[:k]) <= 0.01 * ho[:k])
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_stop_semantics_modes(spk, ctx, mode):
+    A = inputs.diagonal(np.array([2.0, 3.0, 5.0] * 50))
+    b = np.ones(150)
+    x0 = np.array([0.5, -1.0, 7.0] * 50)
+    x, log, _ = solve(spk, ctx, A, b, x0=x0, tau=1e-12, max_iters=0, mode=mode)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 0 and np.array_equal(x, x0)
+    x, log, _ = solve(spk, ctx, A, np.zeros(150), x0=x0, tau=1e-12, max_iters=10, mode=mode)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 0 and not x.any()
+    _, log, _ = solve(spk, ctx, inputs.diagonal(np.array([1.0, -2.0])), np.ones(2), tau=1e-12, mode=mode)
+    assert log.stop_reason == spk.STOP_BREAKDOWN and log.iterations == 0
+    bn = np.ones(4)
+    bn[1] = np.inf
+    _, log, _ = solve(spk, ctx, inputs.diagonal(np.ones(4)), bn, tau=1e-12, mode=mode)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+
+
+def test_persistent_full_size(spk, ctx):
+    """The persistent launch at stencil7 N=215 (all workgroups of the device, 3 barriers per iteration)."""
+    A = inputs.stencil7(215, 1)
+    b = inputs.rhs(A.n_rows, 1)
+    x, log, _ = solve(spk, ctx, A, b, mode=3)
+    xo, ro, _ = oracle.cg(A, b, tau=1e-14, max_iters=1000)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert rel(x, xo) <= 1e-12
 
 
 def test_stop_semantics(spk, ctx):
