@@ -112,6 +112,8 @@ def _get():
         lib.gen_stencil7.restype = i32
         lib.gen_stencil7.argtypes = [i64, u64, f64, i32, vp, vp, vp]
         lib.gen_randsym_max_nnz.restype = i64
+        lib.gen_stencil7_ns.restype = i32
+        lib.gen_stencil7_ns.argtypes = [i64, u64, f64, vp, vp, vp]
         lib.gen_randsym_max_nnz.argtypes = [i64, i32]
         lib.gen_randsym.restype = i64
         lib.gen_randsym.argtypes = [i64, u64, f64, i32, i32, vp, vp, vp]
@@ -179,6 +181,19 @@ def stencil7(N: int, seed: int, delta: float = 1.0, f32x: bool = False) -> CSR:
     rc = _get().gen_stencil7(N, seed, float(delta), int(f32x), _p(rp), _p(col), _p(val))
     if rc != 0:
         raise ValueError("stencil7: N must be >= 1")
+    return CSR(n, n, rp, col, val)
+
+
+def stencil7_ns(N: int, seed: int, delta: float = 1.0) -> CSR:
+    """Nonsymmetric stencil7: independent draws for a_ij and a_ji (stream 16),
+    strictly row diagonally dominant."""
+    n = N * N * N
+    nnz = stencil7_nnz(N)
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz, np.float64)
+    if _get().gen_stencil7_ns(N, seed, float(delta), _p(rp), _p(col), _p(val)) != 0:
+        raise ValueError("stencil7_ns: N must be >= 1")
     return CSR(n, n, rp, col, val)
 
 

@@ -132,6 +132,42 @@ int gen_stencil7_row(int64_t N, uint64_t seed, double delta, int f32x, int64_t i
     return m;
 }
 
+/*
+ * stencil7_ns(N): the stencil7 pattern with every off-diagonal entry drawn on
+ * its own (a_ij and a_ji independent, so A is nonsymmetric): entry (i, dir)
+ * is uniform[-1,1) draw (seed, stream 16, 6 i + dir), dir = 0..5 for the
+ * neighbours -N^2, -N, -1, +1, +N, +N^2.  Diagonal = sum of |off-diagonals|
+ * of the row (ascending column order) + delta: strictly row diagonally
+ * dominant.  Same sizes as stencil7.
+ */
+int gen_stencil7_ns(int64_t N, uint64_t seed, double delta, int64_t *row_ptr, int32_t *col, double *val) {
+    if (N < 1) return -1;
+    const int64_t n = N * N * N, s1 = N, s2 = N * N;
+    int64_t k = 0;
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t x = i % N, y = (i / N) % N, z = i / s2;
+        const uint64_t e0 = 6 * (uint64_t)i;
+        int64_t cj[7];
+        double cv[7];
+        int m = 0, dpos = -1;
+        if (z > 0)     { cj[m] = i - s2; cv[m] = gen_unif_f64(seed, 16, e0 + 0); ++m; }
+        if (y > 0)     { cj[m] = i - s1; cv[m] = gen_unif_f64(seed, 16, e0 + 1); ++m; }
+        if (x > 0)     { cj[m] = i - 1;  cv[m] = gen_unif_f64(seed, 16, e0 + 2); ++m; }
+        dpos = m; cj[m] = i; cv[m] = 0.0; ++m;
+        if (x < N - 1) { cj[m] = i + 1;  cv[m] = gen_unif_f64(seed, 16, e0 + 3); ++m; }
+        if (y < N - 1) { cj[m] = i + s1; cv[m] = gen_unif_f64(seed, 16, e0 + 4); ++m; }
+        if (z < N - 1) { cj[m] = i + s2; cv[m] = gen_unif_f64(seed, 16, e0 + 5); ++m; }
+        double d = 0.0;
+        for (int t = 0; t < m; ++t)
+            if (t != dpos) d += fabs(cv[t]);
+        cv[dpos] = d + delta;
+        for (int t = 0; t < m; ++t) { col[k] = (int32_t)cj[t]; val[k] = cv[t]; ++k; }
+        row_ptr[i + 1] = k;
+    }
+    return 0;
+}
+
 static int cmp_i64(const void *a, const void *b) {
     int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
     return (x > y) - (x < y);

@@ -10,7 +10,10 @@ the definition it follows in ``oracle.c``: the CSR SpMV definition (the
 operator apply of Section 4.2 / the SpMV benchmark of Section 6.1), textbook
 Hestenes-Stiefel CG (the CG solver benchmarked in Section 6.2) with the
 Iteration / ResidualNorm(rhs_norm) criteria of the Section 3.5 configuration
-example, the nnz-balanced row partition and the Gershgorin condition bound.
+example, CGS (the other Krylov solver of Section 6.2, Barrett et al.
+template), CG with the scalar Jacobi preconditioner of the Section 3.5
+example (Saad Alg. 9.1), the nnz-balanced row partition and the Gershgorin
+condition bound.
 """
 from __future__ import annotations
 
@@ -60,6 +63,12 @@ def load(path: str = _LIB):
     lib.orc_residual.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     lib.orc_cg.restype = ctypes.c_int
     lib.orc_cg.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_cgs.restype = ctypes.c_int
+    lib.orc_cgs.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_pcg_jacobi.restype = ctypes.c_int
+    lib.orc_pcg_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_diagonal.restype = None
+    lib.orc_diagonal.argtypes = [i64, vp, vp, vp, vp]
     lib.orc_partition.restype = None
     lib.orc_partition.argtypes = [i64, vp, i64, vp]
     lib.orc_gershgorin_kappa.restype = f64
@@ -120,19 +129,35 @@ class Oracle:
         self.lib.orc_residual(A.n_rows, _p(rp), _p(ci), _p(va), _p(b), _p(x), _p(r))
         return r
 
-    def cg(self, A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
-        """Returns (x, CGResult, hist or None)."""
+    def _krylov(self, fn, A, b, x0, tau, max_iters, history):
         rp, ci, va = _csr64(A)
         n = A.n_rows
         b = np.ascontiguousarray(b, np.float64)
         x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
         res = CGResult()
         hist = np.full(max_iters + 1, np.nan) if history else None
-        self.lib.orc_cg(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tau), int(max_iters),
-                        ctypes.byref(res), _p(hist))
+        fn(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tau), int(max_iters), ctypes.byref(res), _p(hist))
         if hist is not None:
             hist = hist[: res.iterations + 1]
         return x, res, hist
+
+    def cg(self, A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+        """Textbook CG.  Returns (x, CGResult, hist or None)."""
+        return self._krylov(self.lib.orc_cg, A, b, x0, tau, max_iters, history)
+
+    def cgs(self, A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+        """CGS (Barrett et al. template, shadow residual r0).  Returns (x, CGResult, hist or None)."""
+        return self._krylov(self.lib.orc_cgs, A, b, x0, tau, max_iters, history)
+
+    def pcg_jacobi(self, A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+        """CG preconditioned by diag(A).  Returns (x, CGResult, hist or None)."""
+        return self._krylov(self.lib.orc_pcg_jacobi, A, b, x0, tau, max_iters, history)
+
+    def diagonal(self, A) -> np.ndarray:
+        rp, ci, va = _csr64(A)
+        d = np.empty(A.n_rows, np.float64)
+        self.lib.orc_diagonal(A.n_rows, _p(rp), _p(ci), _p(va), _p(d))
+        return d
 
     def partition(self, row_ptr, parts: int) -> np.ndarray:
         rp = np.ascontiguousarray(row_ptr, np.int64)
@@ -169,6 +194,18 @@ def residual(A, b, x):
 
 def cg(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
     return default().cg(A, b, x0, tau, max_iters, history)
+
+
+def cgs(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+    return default().cgs(A, b, x0, tau, max_iters, history)
+
+
+def pcg_jacobi(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+    return default().pcg_jacobi(A, b, x0, tau, max_iters, history)
+
+
+def diagonal(A):
+    return default().diagonal(A)
 
 
 def csr_validate(n_rows, n_cols, nnz, row_ptr, col):

@@ -24,6 +24,14 @@
  *    an inclusive comparison; the test runs once before the first iteration
  *    and after every update; ||b|| = 0 returns x = 0 as converged; p.q <= 0 is
  *    a breakdown; a non-finite scalar stops with a non-finite verdict.
+ *  - CGS is among the solvers the paper benchmarks against its baselines
+ *    (Section 6.2) without printing the iteration; the oracle takes the
+ *    unpreconditioned template of Barrett et al. (1994) with shadow residual
+ *    r0 and the same stop tests; an exact zero rho or sigma is a breakdown.
+ *  - The scalar Jacobi preconditioner appears in the configuration example
+ *    (Section 3.5, Listing 2, block size 1); the oracle applies it as
+ *    z = r / diag(A) inside textbook PCG (Saad, Alg. 9.1) and keeps the stop
+ *    test on the unpreconditioned residual norm.
  */
 #include <math.h>
 #include <stdint.h>
@@ -170,6 +178,206 @@ done:
         res->true_resnorm = (n > 0) ? NAN : 0.0;
     }
     free(r); free(p); free(q);
+    return reason;
+}
+
+/*
+ * Conjugate gradient squared (Sonneveld 1989), unpreconditioned, in the form
+ * of Barrett et al., "Templates for the Solution of Linear Systems" (1994),
+ * with the shadow residual rt = r0.  Same argument conventions, stop tests
+ * and stop reasons as orc_cg; one iteration = two products with A.
+ *
+ *   r0 = b - A x0, rt = r0
+ *   for i = 1, 2, ...:
+ *     rho_{i-1} = rt.r_{i-1}                 (zero: breakdown)
+ *     i = 1: u = r_0, p = u
+ *     else:  beta = rho_{i-1} / rho_{i-2}
+ *            u = r_{i-1} + beta q,  p = u + beta (q + beta p)
+ *     v = A p;  sigma = rt.v                  (zero: breakdown)
+ *     alpha = rho_{i-1} / sigma
+ *     q = u - alpha v;  uh = u + q
+ *     x_i = x_{i-1} + alpha uh;  r_i = r_{i-1} - alpha A uh
+ * with the stop test on ||r_i|| <= tau ||b|| or i == max_iters.
+ */
+int orc_cgs(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+            const double *b, double *x, double tau, int64_t max_iters,
+            orc_cg_result *res, double *hist) {
+    const size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(bytes), *rt = (double *)malloc(bytes), *p = (double *)malloc(bytes);
+    double *u = (double *)malloc(bytes), *q = (double *)malloc(bytes), *v = (double *)malloc(bytes);
+    double *uh = (double *)malloc(bytes), *qh = (double *)malloc(bytes);
+    int64_t k = 0;
+    int reason = ORC_RUNNING;
+    double rho_prev = 0.0, resnorm = 0.0;
+    const double bnorm = sqrt(dot(n, b, b));
+    res->rhs_norm = bnorm;
+
+    if (!isfinite(bnorm)) {
+        reason = ORC_NON_FINITE;
+        resnorm = bnorm;
+        goto done;
+    }
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        reason = ORC_CONVERGED;
+        resnorm = 0.0;
+        if (hist) hist[0] = 0.0;
+        goto done;
+    }
+    orc_residual(n, row_ptr, col, val, b, x, r);
+    for (int64_t i = 0; i < n; ++i) rt[i] = r[i];
+    resnorm = sqrt(dot(n, r, r));
+    if (hist) hist[0] = resnorm;
+    if (!isfinite(resnorm)) reason = ORC_NON_FINITE;
+    else if (resnorm <= tau * bnorm) reason = ORC_CONVERGED;
+    else if (k >= max_iters) reason = ORC_MAX_ITERS;
+
+    while (reason == ORC_RUNNING) {
+        const double rho = dot(n, rt, r);
+        if (!isfinite(rho)) { reason = ORC_NON_FINITE; break; }
+        if (rho == 0.0) { reason = ORC_BREAKDOWN; break; }
+        if (k == 0) {
+            for (int64_t i = 0; i < n; ++i) u[i] = r[i];
+            for (int64_t i = 0; i < n; ++i) p[i] = u[i];
+        } else {
+            const double beta = rho / rho_prev;
+            for (int64_t i = 0; i < n; ++i) u[i] = r[i] + beta * q[i];
+            for (int64_t i = 0; i < n; ++i) p[i] = u[i] + beta * (q[i] + beta * p[i]);
+        }
+        orc_spmv(n, row_ptr, col, val, p, v);
+        const double sigma = dot(n, rt, v);
+        if (!isfinite(sigma)) { reason = ORC_NON_FINITE; break; }
+        if (sigma == 0.0) { reason = ORC_BREAKDOWN; break; }
+        const double alpha = rho / sigma;
+        for (int64_t i = 0; i < n; ++i) q[i] = u[i] - alpha * v[i];
+        for (int64_t i = 0; i < n; ++i) uh[i] = u[i] + q[i];
+        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * uh[i];
+        orc_spmv(n, row_ptr, col, val, uh, qh);
+        for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * qh[i];
+        k += 1;
+        resnorm = sqrt(dot(n, r, r));
+        if (hist) hist[k] = resnorm;
+        if (!isfinite(resnorm)) { reason = ORC_NON_FINITE; break; }
+        if (resnorm <= tau * bnorm) { reason = ORC_CONVERGED; break; }
+        if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }
+        rho_prev = rho;
+    }
+
+done:
+    res->iterations = k;
+    res->stop_reason = reason;
+    res->implicit_resnorm = resnorm;
+    if (reason != ORC_NON_FINITE && n > 0) {
+        orc_residual(n, row_ptr, col, val, b, x, r);
+        res->true_resnorm = sqrt(dot(n, r, r));
+    } else {
+        res->true_resnorm = (n > 0) ? NAN : 0.0;
+    }
+    free(r); free(rt); free(p); free(u); free(q); free(v); free(uh); free(qh);
+    return reason;
+}
+
+/*
+ * Diagonal of A: d_i = sum of the stored entries of row i in column i (0 when
+ * there is none).
+ */
+void orc_diagonal(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val, double *d) {
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) s += val[k];
+        d[i] = s;
+    }
+}
+
+/*
+ * Conjugate gradient with the scalar Jacobi preconditioner M = diag(A)
+ * (Saad, Alg. 9.1, with z = M^{-1} r computed as r_i / d_i).  Same
+ * conventions as orc_cg; the stop test uses the unpreconditioned recurrence
+ * residual ||r_k||.  A zero or non-finite diagonal entry returns
+ * ORC_BREAKDOWN before the first iteration with x unchanged.
+ *
+ *   r0 = b - A x0, z0 = M^{-1} r0, p0 = z0, rho0 = r0.z0
+ *   for k = 0, 1, ...:
+ *     q = A p_k;  alpha = rho_k / (p_k.q)             (p.q <= 0: breakdown)
+ *     x_{k+1} = x_k + alpha p_k;  r_{k+1} = r_k - alpha q
+ *     z_{k+1} = M^{-1} r_{k+1};  rho_{k+1} = r_{k+1}.z_{k+1}
+ *     beta = rho_{k+1} / rho_k;  p_{k+1} = z_{k+1} + beta p_k
+ */
+int orc_pcg_jacobi(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+                   const double *b, double *x, double tau, int64_t max_iters,
+                   orc_cg_result *res, double *hist) {
+    const size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(bytes), *z = (double *)malloc(bytes), *p = (double *)malloc(bytes);
+    double *q = (double *)malloc(bytes), *d = (double *)malloc(bytes);
+    int64_t k = 0;
+    int reason = ORC_RUNNING;
+    double rho = 0.0, resnorm = 0.0;
+    const double bnorm = sqrt(dot(n, b, b));
+    res->rhs_norm = bnorm;
+
+    if (!isfinite(bnorm)) {
+        reason = ORC_NON_FINITE;
+        resnorm = bnorm;
+        goto done;
+    }
+    orc_diagonal(n, row_ptr, col, val, d);
+    for (int64_t i = 0; i < n; ++i) {
+        if (d[i] == 0.0 || !isfinite(d[i])) {
+            reason = ORC_BREAKDOWN;
+            resnorm = NAN;
+            goto done;
+        }
+    }
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        reason = ORC_CONVERGED;
+        resnorm = 0.0;
+        if (hist) hist[0] = 0.0;
+        goto done;
+    }
+    orc_residual(n, row_ptr, col, val, b, x, r);
+    for (int64_t i = 0; i < n; ++i) z[i] = r[i] / d[i];
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+    rho = dot(n, r, z);
+    resnorm = sqrt(dot(n, r, r));
+    if (hist) hist[0] = resnorm;
+    if (!isfinite(rho) || !isfinite(resnorm)) reason = ORC_NON_FINITE;
+    else if (resnorm <= tau * bnorm) reason = ORC_CONVERGED;
+    else if (k >= max_iters) reason = ORC_MAX_ITERS;
+
+    while (reason == ORC_RUNNING) {
+        orc_spmv(n, row_ptr, col, val, p, q);
+        const double pq = dot(n, p, q);
+        if (!isfinite(pq)) { reason = ORC_NON_FINITE; break; }
+        if (pq <= 0.0) { reason = ORC_BREAKDOWN; break; }
+        const double alpha = rho / pq;
+        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+        for (int64_t i = 0; i < n; ++i) z[i] = r[i] / d[i];
+        const double rho_new = dot(n, r, z);
+        k += 1;
+        resnorm = sqrt(dot(n, r, r));
+        if (hist) hist[k] = resnorm;
+        if (!isfinite(rho_new) || !isfinite(resnorm)) { reason = ORC_NON_FINITE; break; }
+        if (resnorm <= tau * bnorm) { reason = ORC_CONVERGED; break; }
+        if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }
+        const double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+
+done:
+    res->iterations = k;
+    res->stop_reason = reason;
+    res->implicit_resnorm = resnorm;
+    if (reason != ORC_NON_FINITE && n > 0) {
+        orc_residual(n, row_ptr, col, val, b, x, r);
+        res->true_resnorm = sqrt(dot(n, r, r));
+    } else {
+        res->true_resnorm = (n > 0) ? NAN : 0.0;
+    }
+    free(r); free(z); free(p); free(q); free(d);
     return reason;
 }
 

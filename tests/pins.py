@@ -269,6 +269,198 @@ def pin_cg_breakdown_nonfinite(orc):
     assert r.stop_reason == 4
 
 
+# ----------------------------------------------------------------- CGS
+def _ns_dense(N, seed, delta=1.0):
+    A = inputs.stencil7_ns(N, seed, delta)
+    return A, A.to_dense()
+
+
+def _bicg_poly_residual(D, r0, rt, k):
+    """phi_k(A) r0 of BiCG from its Petrov-Galerkin definition: r0 - A K c with
+    K = [r0, A r0, ..]_k and (L^T A K) c = L^T r0, L = [rt, A^T rt, ..]_k.
+    Returns (c, apply) where apply(v) = phi_k(A) v for the same polynomial."""
+    K = np.column_stack([np.linalg.matrix_power(D, j) @ r0 for j in range(k)])
+    L = np.column_stack([np.linalg.matrix_power(D.T, j) @ rt for j in range(k)])
+    c = np.linalg.solve(L.T @ D @ K, L.T @ r0)
+
+    def apply(v):
+        out = v.copy()
+        Av = D @ v
+        for j in range(k):
+            out -= c[j] * Av
+            Av = D @ Av
+        return out
+    return c, apply
+
+
+def pin_cgs_first_step_closed_form(orc):
+    """One CGS step from x0 (rt = r0): alpha = r0.r0 / r0.A r0, x1 = x0 + alpha (2 r0 - alpha A r0),
+    r1 = (I - alpha A)^2 r0; nonsymmetric A and a nonzero guess."""
+    A, D = _ns_dense(3, 2)
+    n = A.n_rows
+    b = inputs.rhs(n, 2)
+    x0 = inputs.vec(n, 3, 20)
+    r0 = b - D @ x0
+    Ar = D @ r0
+    alpha = (r0 @ r0) / (r0 @ Ar)
+    x1 = x0 + alpha * (2 * r0 - alpha * Ar)
+    r1 = r0 - 2 * alpha * Ar + alpha * alpha * (D @ Ar)
+    x, r, h = orc.cgs(A, b, x0=x0, tau=0.0, max_iters=1, history=True)
+    assert r.iterations == 1 and r.stop_reason == 2
+    assert _rel(x, x1) <= 1e-13
+    assert abs(h[1] - np.linalg.norm(r1)) <= 1e-12 * np.linalg.norm(r1)
+
+
+def pin_cgs_squared_bicg_polynomial(orc):
+    """The CGS residual after k steps is phi_k(A)^2 r0 with phi_k the BiCG residual
+    polynomial (Sonneveld): checked for k = 2, 3 on a nonsymmetric and a symmetric A."""
+    for A, D in (_ns_dense(3, 4), (inputs.randsym(20, 4, delta=0.5), None)):
+        if D is None:
+            D = A.to_dense()
+        n = A.n_rows
+        b = inputs.rhs(n, 5)
+        xs = np.linalg.solve(D, b)
+        for k in (2, 3):
+            _, apply = _bicg_poly_residual(D, b, b, k)
+            rk = apply(apply(b))
+            xk_ref = xs - np.linalg.solve(D, rk)
+            x, r, h = orc.cgs(A, b, tau=0.0, max_iters=k, history=True)
+            assert r.iterations == k
+            assert _rel(x, xk_ref) <= 1e-9, (k, _rel(x, xk_ref))
+            assert abs(h[k] - np.linalg.norm(rk)) <= 1e-8 * np.linalg.norm(b)
+
+
+def pin_cgs_diag_distinct(orc):
+    """Diagonal A with m distinct eigenvalues: phi_m vanishes on the spectrum, so CGS
+    converges at iteration m and not before."""
+    d = np.repeat(np.array([1.0, 2.5, 4.0, 7.0]), 3)
+    b = np.array([inputs.unif(6, 17, i) for i in range(d.size)])
+    x, r, h = orc.cgs(inputs.diagonal(d), b, tau=1e-12, max_iters=50, history=True)
+    assert r.stop_reason == 1 and r.iterations == 4
+    assert np.all(h[:4] > 1e-12 * np.linalg.norm(b))
+    assert _rel(x, b / d) <= 1e-12
+
+
+def pin_cgs_dense_solve_and_scipy(orc):
+    """Nonsymmetric diagonally dominant systems: converged x vs numpy.linalg.solve,
+    iteration count vs scipy.sparse.linalg.cgs (independent code, same criterion)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    for seed in range(3):
+        A, D = _ns_dense(4, seed, delta=0.5)
+        b = inputs.rhs(A.n_rows, seed)
+        tau = 1e-10
+        x, r, _ = orc.cgs(A, b, tau=tau, max_iters=500)
+        assert r.stop_reason == 1
+        cond = np.linalg.cond(D)
+        assert _rel(x, np.linalg.solve(D, b)) <= 10 * cond * tau
+        assert r.true_resnorm <= 10 * tau * r.rhs_norm
+        count = [0]
+
+        def cb(_xk):
+            count[0] += 1
+        S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n_rows, A.n_cols))
+        _, info = spla.cgs(S, b, rtol=tau, atol=0.0, maxiter=500, callback=cb)
+        assert info == 0 and abs(r.iterations - count[0]) <= 2
+
+
+def pin_cgs_stop_semantics(orc):
+    A = inputs.diagonal(np.array([2.0, 3.0, 5.0]))
+    b = np.array([1.0, 1.0, 1.0])
+    x0 = np.array([0.5, -1.0, 7.0])
+    x, r, h = orc.cgs(A, b, x0=x0, tau=1e-12, max_iters=0, history=True)
+    assert r.stop_reason == 2 and r.iterations == 0 and np.array_equal(x, x0)
+    assert h[0] == np.linalg.norm(b - A.to_dense() @ x0)
+    x, r, _ = orc.cgs(A, np.zeros(3), x0=x0, tau=1e-12, max_iters=10)
+    assert r.stop_reason == 1 and r.iterations == 0 and np.array_equal(x, np.zeros(3))
+    x, r, _ = orc.cgs(A, b, x0=np.array([0.5, 1.0 / 3.0, 0.2]), tau=1e-12, max_iters=10)
+    assert r.stop_reason == 1 and r.iterations == 0
+    x, r, _ = orc.cgs(inputs.laplacian1d(20), np.ones(20), tau=1e-15, max_iters=3)
+    assert r.stop_reason == 2 and r.iterations == 3
+    # skew-symmetric: rt . A r0 = 0 on the first step -> breakdown, x untouched
+    S = inputs.from_dense(np.array([[0.0, 1.0], [-1.0, 0.0]]))
+    x, r, _ = orc.cgs(S, np.array([1.0, 1.0]), tau=1e-12, max_iters=10)
+    assert r.stop_reason == 3 and r.iterations == 0 and np.array_equal(x, np.zeros(2))
+    bb = np.ones(4)
+    bb[1] = np.inf
+    _, r, _ = orc.cgs(inputs.diagonal(np.ones(4)), bb, tau=1e-12)
+    assert r.stop_reason == 4
+
+
+# ----------------------------------------------------------------- Jacobi PCG
+def _scaled_spd(n, seed):
+    """S A S with S a positive diagonal: SPD with a strongly varying diagonal."""
+    A = inputs.randsym(n, seed, delta=0.5)
+    s = np.array([2.0 ** (inputs.unif(seed, 18, i) * 3) for i in range(n)])
+    D = A.to_dense() * s[:, None] * s[None, :]
+    return inputs.from_dense(D), D
+
+
+def pin_diagonal_sums_duplicates(orc):
+    A = inputs.CSR(3, 3, np.array([0, 3, 4, 6], np.int64), np.array([2, 0, 0, 1, 2, 2], np.int32),
+                   np.array([5.0, 1.5, 2.25, -4.0, 0.5, 0.25]))
+    assert np.array_equal(orc.diagonal(A), np.diag(A.to_dense()))
+    assert np.array_equal(orc.diagonal(inputs.CSR(2, 2, np.array([0, 1, 1], np.int64),
+                                                  np.array([1], np.int32), np.array([3.0]))), [0.0, 0.0])
+
+
+def pin_pcg_diagonal_one_step(orc):
+    """M = A for diagonal A: converged after exactly one iteration with x = b / d."""
+    d = np.array([1.0, 3.0, 0.25, 8.0, 2.0, 5.5])
+    b = np.array([inputs.unif(7, 19, i) for i in range(d.size)])
+    x, r, _ = orc.pcg_jacobi(inputs.diagonal(d), b, tau=1e-14, max_iters=10)
+    assert r.stop_reason == 1 and r.iterations == 1
+    assert _rel(x, b / d) <= 1e-15
+
+
+def pin_pcg_is_cg_on_scaled_system(orc):
+    """x_k of Jacobi PCG = D^{-1/2} y_k, y_k the CG iterate of D^{-1/2} A D^{-1/2} y = D^{-1/2} b,
+    taken from its Krylov-minimiser definition (dense), for k = 1..5."""
+    A, D = _scaled_spd(24, 3)
+    b = inputs.rhs(24, 3)
+    dh = 1.0 / np.sqrt(np.diag(D))
+    Ah = D * dh[:, None] * dh[None, :]
+    bh = b * dh
+    for k in range(1, 6):
+        K = np.column_stack([np.linalg.matrix_power(Ah, j) @ bh for j in range(k)])
+        y = K @ np.linalg.solve(K.T @ Ah @ K, K.T @ bh)
+        x, r, h = orc.pcg_jacobi(A, b, tau=0.0, max_iters=k, history=True)
+        assert r.iterations == k
+        assert _rel(x, dh * y) <= 1e-10, (k, _rel(x, dh * y))
+        assert abs(h[k] - np.linalg.norm(b - D @ x)) <= 1e-10 * np.linalg.norm(b)
+
+
+def pin_pcg_dense_solve(orc):
+    for seed in range(2):
+        A, D = _scaled_spd(30, seed)
+        b = inputs.rhs(30, seed)
+        x, r, _ = orc.pcg_jacobi(A, b, tau=1e-12, max_iters=500)
+        assert r.stop_reason == 1
+        assert _rel(x, np.linalg.solve(D, b)) <= np.linalg.cond(D) * 1e-12 * 10
+        _, rc, _ = orc.cg(A, b, tau=1e-12, max_iters=500)
+        assert r.iterations < rc.iterations   # the scaling is what Jacobi undoes
+
+
+def pin_pcg_stop_semantics(orc):
+    A = inputs.laplacian1d(6)
+    x0 = np.arange(6.0)
+    # zero diagonal entry: no preconditioner, breakdown before the first iteration
+    Z = inputs.diagonal(np.array([1.0, 0.0, 2.0]))
+    x, r, _ = orc.pcg_jacobi(Z, np.ones(3), x0=np.array([1.0, 2.0, 3.0]), tau=1e-12)
+    assert r.stop_reason == 3 and r.iterations == 0 and np.array_equal(x, [1.0, 2.0, 3.0])
+    x, r, h = orc.pcg_jacobi(A, np.ones(6), x0=x0, tau=1e-12, max_iters=0, history=True)
+    assert r.stop_reason == 2 and r.iterations == 0 and np.array_equal(x, x0)
+    assert h[0] == np.linalg.norm(np.ones(6) - A.to_dense() @ x0)
+    x, r, _ = orc.pcg_jacobi(A, np.zeros(6), x0=x0, tau=1e-12)
+    assert r.stop_reason == 1 and r.iterations == 0 and np.array_equal(x, np.zeros(6))
+    x, r, _ = orc.pcg_jacobi(inputs.laplacian1d(20), np.ones(20), tau=1e-15, max_iters=3)
+    assert r.stop_reason == 2 and r.iterations == 3
+    # indefinite with a positive diagonal: p.q < 0 on the first step
+    _, r, _ = orc.pcg_jacobi(inputs.from_dense(np.array([[1.0, 2.0], [2.0, 1.0]])), np.array([1.0, -1.0]),
+                             tau=1e-12)
+    assert r.stop_reason == 3 and r.iterations == 0
+
+
 # ----------------------------------------------------------------- partition, kappa
 def pin_partition(orc):
     for rp in (inputs.stencil7(5, 0).row_ptr, inputs.randsym(300, 2).row_ptr,

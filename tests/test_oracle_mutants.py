@@ -16,35 +16,73 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
+# (name, text, replacement, scope): the mutation replaces every occurrence of
+# the text inside the function whose definition starts with `scope` (the
+# whole file when scope is None); the text must occur there.
 MUTANTS = [
-    ("spmv wrong gather index", "s += val[k] * x[col[k]];", "s += val[k] * x[i];"),
+    ("spmv wrong gather index", "s += val[k] * x[col[k]];", "s += val[k] * x[i];", None),
     ("spmv dropped last term", "for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += val[k] * x[col[k]];",
-     "for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] - 1; ++k) s += val[k] * x[col[k]];"),
-    ("spmv_abs dropped abs", "s += fabs(val[k]) * fabs(x[col[k]]);", "s += fabs(val[k]) * x[col[k]];"),
-    ("residual sign", "r[i] = b[i] - r[i];", "r[i] = r[i] - b[i];"),
-    ("alpha transposed", "const double alpha = rho / pq;", "const double alpha = pq / rho;"),
-    ("x update uses r", "x[i] = x[i] + alpha * p[i];", "x[i] = x[i] + alpha * r[i];"),
-    ("r update sign", "r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];"),
-    ("beta transposed", "const double beta = rho_new / rho;", "const double beta = rho / rho_new;"),
-    ("p update sign", "p[i] = r[i] + beta * p[i];", "p[i] = r[i] - beta * p[i];"),
-    ("rho not carried", "rho = rho_new;\n", "\n"),
+     "for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] - 1; ++k) s += val[k] * x[col[k]];", None),
+    ("spmv_abs dropped abs", "s += fabs(val[k]) * fabs(x[col[k]]);", "s += fabs(val[k]) * x[col[k]];", None),
+    ("residual sign", "r[i] = b[i] - r[i];", "r[i] = r[i] - b[i];", None),
+    ("alpha transposed", "const double alpha = rho / pq;", "const double alpha = pq / rho;", "int orc_cg("),
+    ("x update uses r", "x[i] = x[i] + alpha * p[i];", "x[i] = x[i] + alpha * r[i];", "int orc_cg("),
+    ("r update sign", "r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];", "int orc_cg("),
+    ("beta transposed", "const double beta = rho_new / rho;", "const double beta = rho / rho_new;", "int orc_cg("),
+    ("p update sign", "p[i] = r[i] + beta * p[i];", "p[i] = r[i] - beta * p[i];", "int orc_cg("),
+    ("rho not carried", "rho = rho_new;\n", "\n", "int orc_cg("),
     ("criterion drops rhs norm", "if (resnorm <= tau * bnorm) { reason = ORC_CONVERGED; break; }",
-     "if (resnorm <= tau) { reason = ORC_CONVERGED; break; }"),
+     "if (resnorm <= tau) { reason = ORC_CONVERGED; break; }", "int orc_cg("),
     ("iteration cap off by one", "if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }",
-     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }"),
-    ("no initial check", "else if (resnorm <= tau * bnorm) reason = ORC_CONVERGED;", ""),
+     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }", "int orc_cg("),
+    ("no initial check", "else if (resnorm <= tau * bnorm) reason = ORC_CONVERGED;", "", "int orc_cg("),
     ("breakdown test inclusive dropped", "if (pq <= 0.0) { reason = ORC_BREAKDOWN; break; }",
-     "if (pq < 0.0) { reason = ORC_BREAKDOWN; break; }"),
-    ("zero rhs keeps guess", "for (int64_t i = 0; i < n; ++i) x[i] = 0.0;", ";"),
+     "if (pq < 0.0) { reason = ORC_BREAKDOWN; break; }", "int orc_cg("),
+    ("zero rhs keeps guess", "for (int64_t i = 0; i < n; ++i) x[i] = 0.0;", ";", "int orc_cg("),
     ("validate strict monotone", "if (row_ptr[i + 1] < row_ptr[i]) return ORC_CSR_DECREASING;",
-     "if (row_ptr[i + 1] <= row_ptr[i]) return ORC_CSR_DECREASING;"),
+     "if (row_ptr[i + 1] <= row_ptr[i]) return ORC_CSR_DECREASING;", None),
     ("validate column bound", "if (col[k] < 0 || col[k] >= n_cols) return ORC_CSR_BAD_COLUMN;",
-     "if (col[k] < 0 || col[k] > n_cols) return ORC_CSR_BAD_COLUMN;"),
-    ("validate check order", "if (row_ptr[0] != 0) return ORC_CSR_BAD_FIRST;\n", "\n"),
+     "if (col[k] < 0 || col[k] > n_cols) return ORC_CSR_BAD_COLUMN;", None),
+    ("validate check order", "if (row_ptr[0] != 0) return ORC_CSR_BAD_FIRST;\n", "\n", None),
     ("partition strict target", "while (i < n && row_ptr[i] < target) ++i;",
-     "while (i < n && row_ptr[i] <= target) ++i;"),
-    ("gershgorin sign", "if (d - R < lo) lo = d - R;", "if (d + R < lo) lo = d + R;"),
-    ("history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;"),
+     "while (i < n && row_ptr[i] <= target) ++i;", None),
+    ("gershgorin sign", "if (d - R < lo) lo = d - R;", "if (d + R < lo) lo = d + R;", None),
+    ("history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "int orc_cg("),
+    # CGS
+    ("cgs beta transposed", "const double beta = rho / rho_prev;", "const double beta = rho_prev / rho;",
+     "int orc_cgs("),
+    ("cgs u uses p", "u[i] = r[i] + beta * q[i];", "u[i] = r[i] + beta * p[i];", "int orc_cgs("),
+    ("cgs p drops beta squared", "p[i] = u[i] + beta * (q[i] + beta * p[i]);", "p[i] = u[i] + beta * (q[i] + p[i]);",
+     "int orc_cgs("),
+    ("cgs q sign", "q[i] = u[i] - alpha * v[i];", "q[i] = u[i] + alpha * v[i];", "int orc_cgs("),
+    ("cgs uh drops q", "uh[i] = u[i] + q[i];", "uh[i] = u[i];", "int orc_cgs("),
+    ("cgs x update uses u", "x[i] = x[i] + alpha * uh[i];", "x[i] = x[i] + alpha * u[i];", "int orc_cgs("),
+    ("cgs r update sign", "r[i] = r[i] - alpha * qh[i];", "r[i] = r[i] + alpha * qh[i];", "int orc_cgs("),
+    ("cgs sigma uses r", "const double sigma = dot(n, rt, v);", "const double sigma = dot(n, r, v);",
+     "int orc_cgs("),
+    ("cgs rho uses r.r", "const double rho = dot(n, rt, r);", "const double rho = dot(n, r, r);", "int orc_cgs("),
+    ("cgs rho_prev not carried", "rho_prev = rho;\n", "\n", "int orc_cgs("),
+    ("cgs shadow is b", "rt[i] = r[i];", "rt[i] = b[i];", "int orc_cgs("),
+    ("cgs sigma breakdown dropped", "if (sigma == 0.0) { reason = ORC_BREAKDOWN; break; }", "", "int orc_cgs("),
+    ("cgs cap off by one", "if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }",
+     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }", "int orc_cgs("),
+    ("cgs history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "int orc_cgs("),
+    # Jacobi PCG
+    ("diagonal keeps last duplicate", "if (col[k] == i) s += val[k];", "if (col[k] == i) s = val[k];",
+     "void orc_diagonal("),
+    ("pcg z multiplies", "z[i] = r[i] / d[i];", "z[i] = r[i] * d[i];", "int orc_pcg_jacobi("),
+    ("pcg rho uses r.r", "const double rho_new = dot(n, r, z);", "const double rho_new = dot(n, r, r);",
+     "int orc_pcg_jacobi("),
+    ("pcg p update uses r", "p[i] = z[i] + beta * p[i];", "p[i] = r[i] + beta * p[i];", "int orc_pcg_jacobi("),
+    ("pcg initial direction r", "for (int64_t i = 0; i < n; ++i) p[i] = z[i];",
+     "for (int64_t i = 0; i < n; ++i) p[i] = r[i];", "int orc_pcg_jacobi("),
+    ("pcg stop on preconditioned norm", "resnorm = sqrt(dot(n, r, r));\n        if (hist) hist[k] = resnorm;",
+     "resnorm = sqrt(rho_new);\n        if (hist) hist[k] = resnorm;", "int orc_pcg_jacobi("),
+    ("pcg zero diagonal accepted", "if (d[i] == 0.0 || !isfinite(d[i])) {", "if (!isfinite(d[i])) {",
+     "int orc_pcg_jacobi("),
+    ("pcg alpha transposed", "const double alpha = rho / pq;", "const double alpha = pq / rho;",
+     "int orc_pcg_jacobi("),
+    ("pcg rho not carried", "rho = rho_new;\n", "\n", "int orc_pcg_jacobi("),
 ]
 
 RUNNER = r"""
@@ -64,12 +102,23 @@ sys.exit(1 if failed else 0)
 """
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_is_caught(tmp_path, name, old, new):
+def mutate(src, old, new, scope):
+    """src with `old` replaced by `new` inside the function starting at `scope`."""
+    if scope is None:
+        assert src.count(old) == 1, "mutation site %r not unique/present" % old
+        return src.replace(old, new)
+    a = src.index(scope)
+    b = src.index("\n}\n", a)
+    body = src[a:b]
+    assert old in body, "mutation site %r not in %s" % (old, scope)
+    return src[:a] + body.replace(old, new) + src[b:]
+
+
+@pytest.mark.parametrize("name,old,new,scope", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new, scope):
     src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
-    assert src.count(old) == 1, "mutation site for %r not unique/present" % name
     mpath = tmp_path / "mutant.c"
-    mpath.write_text(src.replace(old, new))
+    mpath.write_text(mutate(src, old, new, scope))
     lib = oracle.build(force=True, src=str(mpath), out=str(tmp_path / "libmutant.so"))
     try:
         proc = subprocess.run([sys.executable, "-c", RUNNER.format(root=ROOT, lib=lib)],
