@@ -69,6 +69,10 @@ def load(path: str = _LIB):
     lib.orc_pcg_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
     lib.orc_diagonal.restype = None
     lib.orc_diagonal.argtypes = [i64, vp, vp, vp, vp]
+    lib.orc_coo_spmv.restype = None
+    lib.orc_coo_spmv.argtypes = [i64, i64, vp, vp, vp, vp, vp]
+    lib.orc_coo_validate.restype = ctypes.c_int
+    lib.orc_coo_validate.argtypes = [i64, i64, i64, vp, vp, ctypes.POINTER(ctypes.c_int)]
     lib.orc_partition.restype = None
     lib.orc_partition.argtypes = [i64, vp, i64, vp]
     lib.orc_gershgorin_kappa.restype = f64
@@ -113,6 +117,24 @@ class Oracle:
         y = np.empty(A.n_rows, np.float64)
         self.lib.orc_spmv(A.n_rows, _p(rp), _p(ci), _p(va), _p(x), _p(y))
         return y
+
+    def coo_spmv(self, n_rows, row, col, val, x) -> np.ndarray:
+        """COO product from its definition (entries in any order, duplicates summed)."""
+        row = np.ascontiguousarray(row, np.int64)
+        col = np.ascontiguousarray(col, np.int64)
+        val = np.ascontiguousarray(val, np.float64)
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.empty(n_rows, np.float64)
+        self.lib.orc_coo_spmv(n_rows, row.size, _p(row), _p(col), _p(val), _p(x), _p(y))
+        return y
+
+    def coo_validate(self, n_rows, n_cols, row, col):
+        """(verdict, row_sorted) of a COO matrix."""
+        row = np.ascontiguousarray(row, np.int64)
+        col = np.ascontiguousarray(col, np.int64)
+        srt = ctypes.c_int(0)
+        v = self.lib.orc_coo_validate(n_rows, n_cols, row.size, _p(row), _p(col), ctypes.byref(srt))
+        return int(v), bool(srt.value)
 
     def spmv_abs(self, A, x) -> np.ndarray:
         rp, ci, va = _csr64(A)
@@ -186,6 +208,14 @@ def spmv(A, x):
 
 def spmv_abs(A, x):
     return default().spmv_abs(A, x)
+
+
+def coo_spmv(n_rows, row, col, val, x):
+    return default().coo_spmv(n_rows, row, col, val, x)
+
+
+def coo_validate(n_rows, n_cols, row, col):
+    return default().coo_validate(n_rows, n_cols, row, col)
 
 
 def residual(A, b, x):

@@ -87,6 +87,57 @@ def pin_spmv_scipy_stencil(orc):
 
 
 # ----------------------------------------------------------------- validation
+def _coo_of(A):
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+    return rows, A.col.astype(np.int64), A.val.copy()
+
+
+def pin_coo_spmv_scipy_and_dense(orc):
+    """COO product vs scipy.sparse.coo_matrix (independent code) and dense numpy, entries
+    shuffled and duplicated, within the gamma bound of the longest row."""
+    import scipy.sparse as sp
+    A = inputs.dyadic_random(60, 45, 6, 11)
+    rows, cols, vals = _coo_of(A)
+    vals = vals * np.array([inputs.unif(12, 23, k) for k in range(vals.size)])   # generic values
+    perm = np.argsort(np.array([inputs.hash64(12, 24, k) for k in range(vals.size)], np.uint64), kind="stable")
+    rows, cols, vals = (np.concatenate([rows[perm], rows[:7]]), np.concatenate([cols[perm], cols[:7]]),
+                        np.concatenate([vals[perm], vals[:7]]))
+    x = np.array([inputs.unif(12, 25, j) for j in range(45)])
+    y = orc.coo_spmv(60, rows, cols, vals, x)
+    ys = sp.coo_matrix((vals, (rows, cols)), shape=(60, 45)).tocsr() @ x
+    D = np.zeros((60, 45))
+    np.add.at(D, (rows, cols), vals)
+    m = np.bincount(rows, minlength=60)
+    absb = np.zeros(60)
+    np.add.at(absb, rows, np.abs(vals) * np.abs(x[cols]))
+    assert np.all(np.abs(y - ys) <= 2 * gamma(m) * absb)
+    assert np.all(np.abs(y - D @ x) <= 2 * gamma(m) * absb)
+
+
+def pin_coo_spmv_dyadic_exact_and_empty_rows(orc):
+    A = inputs.dyadic_random(40, 30, 5, 13)
+    rows, cols, vals = _coo_of(A)
+    keep = rows % 3 != 1                      # every third row left empty
+    rows, cols, vals = rows[keep], cols[keep], vals[keep]
+    x = np.array([float((j * 7) % 11 - 5) for j in range(30)])
+    y = orc.coo_spmv(40, rows, cols, vals, x)
+    D = np.zeros((40, 30))
+    np.add.at(D, (rows, cols), vals)
+    assert np.array_equal(y, D @ x) and not y[1::3].any()
+
+
+def pin_coo_validate(orc):
+    r = np.array([0, 0, 2, 2, 3], np.int64)
+    c = np.array([1, 0, 2, 3, 0], np.int64)
+    assert orc.coo_validate(4, 4, r, c) == (0, True)
+    assert orc.coo_validate(4, 4, r[::-1], c) == (0, False)
+    assert orc.coo_validate(3, 4, r, c)[0] == 2          # row 3 out of range
+    assert orc.coo_validate(4, 3, r, c)[0] == 5          # column 3 out of range
+    assert orc.coo_validate(4, 4, np.array([0, -1], np.int64), np.array([0, 0], np.int64))[0] == 2
+    assert orc.coo_validate(-1, 4, r, c)[0] == 1
+    assert orc.coo_validate(4, 4, r[:0], c[:0]) == (0, True)
+
+
 def pin_csr_validate(orc):
     rp = np.array([0, 2, 3, 5], np.int64)
     ci = np.array([0, 2, 1, 0, 2], np.int64)

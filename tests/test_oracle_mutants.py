@@ -42,12 +42,24 @@ MUTANTS = [
     ("validate strict monotone", "if (row_ptr[i + 1] < row_ptr[i]) return ORC_CSR_DECREASING;",
      "if (row_ptr[i + 1] <= row_ptr[i]) return ORC_CSR_DECREASING;", None),
     ("validate column bound", "if (col[k] < 0 || col[k] >= n_cols) return ORC_CSR_BAD_COLUMN;",
-     "if (col[k] < 0 || col[k] > n_cols) return ORC_CSR_BAD_COLUMN;", None),
+     "if (col[k] < 0 || col[k] > n_cols) return ORC_CSR_BAD_COLUMN;", "int orc_csr_validate("),
     ("validate check order", "if (row_ptr[0] != 0) return ORC_CSR_BAD_FIRST;\n", "\n", None),
     ("partition strict target", "while (i < n && row_ptr[i] < target) ++i;",
      "while (i < n && row_ptr[i] <= target) ++i;", None),
     ("gershgorin sign", "if (d - R < lo) lo = d - R;", "if (d + R < lo) lo = d + R;", None),
     ("history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "int orc_cg("),
+    # COO
+    ("coo no zero fill", "for (int64_t i = 0; i < n_rows; ++i) y[i] = 0.0;", ";", "void orc_coo_spmv("),
+    ("coo gather by row", "y[row[k]] += val[k] * x[col[k]];", "y[row[k]] += val[k] * x[row[k]];",
+     "void orc_coo_spmv("),
+    ("coo last entry dropped", "for (int64_t k = 0; k < nnz; ++k) y[row[k]]", "for (int64_t k = 1; k < nnz; ++k) y[row[k]]",
+     "void orc_coo_spmv("),
+    ("coo row bound", "if (row[k] < 0 || row[k] >= n_rows) return ORC_CSR_BAD_FIRST;",
+     "if (row[k] < 0 || row[k] > n_rows) return ORC_CSR_BAD_FIRST;", "int orc_coo_validate("),
+    ("coo column bound", "if (col[k] < 0 || col[k] >= n_cols) return ORC_CSR_BAD_COLUMN;",
+     "if (col[k] < 0 || col[k] > n_cols) return ORC_CSR_BAD_COLUMN;", "int orc_coo_validate("),
+    ("coo sortedness strict", "if (k > 0 && row[k] < row[k - 1]) *row_sorted = 0;",
+     "if (k > 0 && row[k] <= row[k - 1]) *row_sorted = 0;", "int orc_coo_validate("),
     # CGS
     ("cgs beta transposed", "const double beta = rho / rho_prev;", "const double beta = rho_prev / rho;",
      "int orc_cgs("),
