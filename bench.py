@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--N", type=int, default=215, help="stencil7 grid edge (n = N^3)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tau", type=float, default=1e-14)
+    ap.add_argument("--solver", choices=["cg", "cgs"], default="cg",
+                    help="cgs runs on the nonsymmetric stencil7 variant of the same size")
+    ap.add_argument("--precond", choices=["none", "jacobi"], default="none")
     ap.add_argument("--precision", choices=["fp64", "mixed_fp32", "mixed_bf16"], default="fp64",
                     help="fp64 CG, or FP32/BF16 inner CG with FP64 refinement")
     ap.add_argument("--inner", type=float, default=1e-4, help="inner reduction factor (mixed)")
@@ -63,7 +66,7 @@ def measured_traffic(args, N):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-kernel scaled), or None when
     that summary is for other kernel sources or another workload."""
-    if args.precision != "fp64" or N != 215 or args.seed != 1:
+    if args.precision != "fp64" or N != 215 or args.seed != 1 or args.solver != "cg" or args.precond != "none":
         return None
     path = os.path.join(ROOT, "profiles", "spmv_pq_cg_fp64_stencil7_N215_traffic.json")
     if not os.path.exists(path):
@@ -97,7 +100,11 @@ def main():
 
     dev = torch.device("cuda:0")
     N = args.N
-    A = inputs.stencil7(N, args.seed)
+    cgs = args.solver == "cgs"
+    if (cgs or args.precond != "none") and args.precision != "fp64":
+        print("CGS and the Jacobi preconditioner run in FP64 only", file=sys.stderr)
+        sys.exit(2)
+    A = inputs.stencil7_ns(N, args.seed) if cgs else inputs.stencil7(N, args.seed)
     b_h = inputs.rhs(A.n_rows, args.seed)
     n, nnz = A.n_rows, A.nnz
     rp = torch.from_numpy(A.row_ptr).to(torch.int32).to(dev)
@@ -115,6 +122,8 @@ def main():
     cfg.precision = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32,
                      "mixed_bf16": spk.PREC_MIXED_BF16}[args.precision]
     cfg.inner_reduction = args.inner
+    cfg.solver = spk.SOLVER_CGS if cgs else spk.SOLVER_CG
+    cfg.precond = spk.PRECOND_JACOBI if args.precond == "jacobi" else spk.PRECOND_NONE
     if args.precision != "fp64":
         cfg.max_iters = 10000
 
@@ -156,6 +165,12 @@ def main():
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     last = logs[-1]
     traffic = measured_traffic(args, N)
+    if cgs:
+        workload = "cgs_fp64_stencil7ns_N%d" % N
+        spmv_kernel = "k_spmv_*<EpiCgsV>, k_spmv_*<EpiCgsR> (two SpMVs per CGS iteration)"
+    else:
+        workload = "%s_%s_stencil7_N%d" % ("pcg_jacobi" if args.precond == "jacobi" else "cg", args.precision, N)
+        spmv_kernel = "k_spmv_*<EpiPq> (q = A p fused with p.q)"
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
         "value": value,
@@ -168,13 +183,15 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "mixed_fp32" else "bf16+f32+f64"),
-        "data": "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD)",
-        "config": {"workload": "cg_%s_stencil7_N%d" % (args.precision, N), "n": n, "nnz": nnz, "seed": args.seed,
+        "data": ("synthetic (seeded nonsymmetric stencil7, independent uniform[-1,1) off-diagonals, "
+                 "row diagonally dominant)" if cgs else
+                 "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD)"),
+        "config": {"workload": workload, "n": n, "nnz": nnz, "seed": args.seed,
                    "tau": args.tau, "index_types": "int32/int32", "iterations_per_solve": last.iterations,
                    "outer_iterations": last.outer_iterations,
                    "stop_reason": last.stop_reason, "rel_true_residual": last.true_resnorm / last.rhs_norm,
                    "solve_device_ms": last.elapsed_ms, "spmv_tiling": info},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq> (q = A p fused with p.q)",
+        "roofline": {"bound": "hbm", "kernel": spmv_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": klaunch},
@@ -190,12 +207,18 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
-        _, res, _ = oracle.cg(A, b_h, tau=0.0, max_iters=args.cpu_iters)
+        fn, label = oracle.cg, "CG"
+        if cgs:
+            fn, label = oracle.cgs, "CGS"
+        elif args.precond == "jacobi":
+            fn, label = oracle.pcg_jacobi, "Jacobi PCG"
+        iters = args.cpu_iters if not cgs else max(args.cpu_iters // 2, 1)
+        _, res, _ = fn(A, b_h, tau=0.0, max_iters=iters)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": n * res.iterations / dt, "unit": "updates/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": "FP64 oracle CG, same system, %d iterations (plus initial and "
-                                         "true residual), %.1f s" % (res.iterations, dt)}
+                               "sample": "FP64 oracle %s, same system, %d iterations (plus initial and "
+                                         "true residual), %.1f s" % (label, res.iterations, dt)}
     print(json.dumps(out), flush=True)
 
 
@@ -225,6 +248,8 @@ def large(args):
     cfg.precision = spk.PREC_MIXED_FP32
     cfg.reduction_factor = 1e-12
     cfg.inner_reduction = args.inner
+    cfg.solver = spk.SOLVER_CGS if cgs else spk.SOLVER_CG
+    cfg.precond = spk.PRECOND_JACOBI if args.precond == "jacobi" else spk.PRECOND_NONE
     cfg.max_iters = 10000
     cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
 
@@ -305,6 +330,8 @@ def serve(args):
     cfg.precision = spk.PREC_MIXED_FP32
     cfg.reduction_factor = tau
     cfg.inner_reduction = args.inner
+    cfg.solver = spk.SOLVER_CGS if cgs else spk.SOLVER_CG
+    cfg.precond = spk.PRECOND_JACOBI if args.precond == "jacobi" else spk.PRECOND_NONE
     cfg.max_iters = 100000
     budget = int(args.budget_gb * (1 << 30))
 

@@ -3,11 +3,13 @@
  *
  * The operation: a CSR sparse matrix A applied to a vector (SpMV, y = A x;
  * the operator apply of the paper's Section 4.2, benchmarked as a matrix
- * times a random vector in Section 6.1), and an unpreconditioned conjugate
- * gradient solve of A x = b (the CG solver of Section 6.2), stopped by an
- * iteration cap or by ||r|| <= reduction_factor * ||b|| (the "Iteration" and
- * "ResidualNorm" criteria with baseline rhs_norm of the configuration example
- * in Section 3.5, Listing 2).  The solution overwrites the initial guess and
+ * times a random vector in Section 6.1), and Krylov solves of A x = b: the
+ * conjugate gradient solve of Section 6.2 (unpreconditioned, or with the
+ * scalar Jacobi preconditioner of the Section 3.5 configuration example) and
+ * CGS, the other solver benchmarked in Section 6.2, for nonsymmetric A.
+ * Solves stop on an iteration cap or on ||r|| <= reduction_factor * ||b||
+ * (the "Iteration" and "ResidualNorm" criteria with baseline rhs_norm of the
+ * configuration example in Section 3.5, Listing 2).  The solution overwrites the initial guess and
  * a log reports convergence (Section 3.5, around Listing 1).  Value types
  * half/float/double and index types int32/int64 follow Table 1.
  *
@@ -64,24 +66,34 @@ typedef enum {
     SPK_STOP_RUNNING = 0,
     SPK_STOP_CONVERGED = 1,   /* ||r_k|| <= reduction_factor * ||b||, or b = 0 (then x = 0) */
     SPK_STOP_MAX_ITERS = 2,   /* k == max_iters */
-    SPK_STOP_BREAKDOWN = 3,   /* p.Ap <= 0: A is not positive definite along p */
+    SPK_STOP_BREAKDOWN = 3,   /* CG: p.Ap <= 0 (A not positive definite along p), or a zero
+                                 or non-finite diagonal with the Jacobi preconditioner;
+                                 CGS: rt.r == 0 or rt.Ap == 0 */
     SPK_STOP_NON_FINITE = 4   /* a NaN or Inf appeared in a norm or inner product */
 } spk_stop_reason;
 
-typedef enum { SPK_SOLVER_CG = 0 } spk_solver;
+typedef enum {
+    SPK_SOLVER_CG = 0,        /* conjugate gradient: A symmetric positive definite */
+    SPK_SOLVER_CGS = 1        /* conjugate gradient squared: general nonsingular A; FP64,
+                                 no preconditioner; two SpMVs per iteration */
+} spk_solver;
 typedef enum {
     SPK_PREC_FP64 = 0,        /* FP64 values, vectors and reductions */
     SPK_PREC_MIXED_FP32 = 1,  /* FP32 inner CG (FP64 reductions) + FP64 iterative refinement */
     SPK_PREC_MIXED_BF16 = 2   /* BF16 matrix values in the inner CG, otherwise as MIXED_FP32 */
 } spk_precision;
 typedef enum { SPK_BASELINE_RHS_NORM = 0 } spk_baseline;
-typedef enum { SPK_PRECOND_NONE = 0 } spk_precond;
+typedef enum {
+    SPK_PRECOND_NONE = 0,
+    SPK_PRECOND_JACOBI = 1    /* scalar Jacobi, M = diag(A) (CG, FP64); the stop test stays
+                                 on the unpreconditioned residual ||r|| */
+} spk_precond;
 typedef enum {
     SPK_EXEC_AUTO = 0,        /* the library's choice: the host loop, which measured fastest */
     SPK_EXEC_HOST_LOOP = 1,   /* kernels launched from a host loop, status polled per chunk */
     SPK_EXEC_GRAPH = 2,       /* chunks of iterations replayed from a captured HIP graph */
-    SPK_EXEC_PERSISTENT = 3   /* FP64: the whole solve in one cooperative launch with grid
-                                 barriers (mixed precision falls back to SPK_EXEC_GRAPH) */
+    SPK_EXEC_PERSISTENT = 3   /* FP64 CG: the whole solve in one cooperative launch with grid
+                                 barriers (other solves fall back to SPK_EXEC_GRAPH) */
 } spk_exec_mode;
 
 typedef struct spk_ctx_s *spk_ctx;
@@ -98,12 +110,24 @@ typedef struct {
     const void *values;
 } spk_csr;
 
+/* A COO (coordinate) matrix in device memory, the SpMV benchmark's second
+ * format (Section 6.1): nnz (row, column, value) triplets in three arrays.
+ * Row indices must be non-decreasing (entries sorted by row; any column order
+ * within a row; duplicates summed).  row_idx and col_idx share idx_type. */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    int32_t idx_type, val_type;
+    const void *row_idx;
+    const void *col_idx;
+    const void *values;
+} spk_coo;
+
 /* Solver configuration; spk_solver_cfg_default fills the defaults noted. */
 typedef struct {
-    int32_t solver;            /* SPK_SOLVER_CG */
+    int32_t solver;            /* SPK_SOLVER_CG (or SPK_SOLVER_CGS) */
     int32_t precision;         /* SPK_PREC_FP64 */
     int32_t baseline;          /* SPK_BASELINE_RHS_NORM */
-    int32_t precond;           /* SPK_PRECOND_NONE */
+    int32_t precond;           /* SPK_PRECOND_NONE (or SPK_PRECOND_JACOBI) */
     int64_t max_iters;         /* "Iteration" criterion; 1000 (Listings 1-2) */
     double reduction_factor;   /* "ResidualNorm" criterion; 1e-6 (Listings 1-2) */
     int32_t exec_mode;         /* SPK_EXEC_AUTO */
@@ -173,10 +197,29 @@ spk_status spk_partition(spk_ctx ctx, const spk_csr *A, int64_t parts, int64_t *
  * widened to FP32; accumulation is in the vector type). */
 spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out);
 
+/* Validate a device COO matrix on the GPU.  *verdict receives an
+ * spk_csr_verdict: BAD_SIZE for a negative size, BAD_FIRST for a row index
+ * out of range, BAD_COLUMN for a column index out of range (checked in that
+ * order); *row_sorted = 1 when the row indices are non-decreasing.  Returns
+ * OK whatever the verdict; INVALID_ARG for null pointers or unknown types. */
+spk_status spk_coo_check(spk_ctx ctx, const spk_coo *A, int32_t *verdict, int32_t *row_sorted);
+
+/* Plan y = A x for a COO matrix (executed with spk_execute_spmv).  Validates
+ * A (INVALID_ARG if malformed or not sorted by row), then derives on the GPU
+ * the row pointer of the same matrix (n_rows + 1 entries, int32 when
+ * nnz < 2^31, else int64; owned by the plan) so that each product runs the
+ * CSR kernels over the caller's col_idx and values, which the plan borrows.
+ * Results equal those of spk_plan_spmv on the corresponding CSR matrix. */
+spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
+
 /* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
  * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
  * an FP32/BF16 copy for the inner solve) or F32 values (taken as exact).
- * Errors: INVALID_ARG, UNSUPPORTED (options this build lacks), OUT_OF_MEMORY. */
+ * CGS and the Jacobi preconditioner are FP64 only; the Jacobi plan computes
+ * 1 / diag(A) (a zero or non-finite diagonal entry makes every solve of the
+ * plan stop with SPK_STOP_BREAKDOWN, x unchanged).
+ * Errors: INVALID_ARG, UNSUPPORTED (other solver / precision /
+ * preconditioner combinations), OUT_OF_MEMORY. */
 spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg, spk_plan *out);
 
 /* y = A x with the plan's matrix; x has n_cols entries, y has n_rows. */

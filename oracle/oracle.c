@@ -90,18 +90,19 @@ void orc_coo_spmv(int64_t n_rows, int64_t nnz, const int64_t *row, const int64_t
 }
 
 /* A COO matrix is well formed when sizes are non-negative and every row and
- * column index is in range (verdicts as for CSR: BAD_SIZE, BAD_COLUMN for an
- * out-of-range column, BAD_FIRST for an out-of-range row); row_sorted
- * reports whether the row indices are non-decreasing. */
+ * column index is in range.  Checks in this order, each over all entries:
+ * sizes (BAD_SIZE), row indices (BAD_FIRST), column indices (BAD_COLUMN).
+ * row_sorted reports whether the row indices are non-decreasing. */
 int orc_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row, const int64_t *col,
                      int *row_sorted) {
     *row_sorted = 1;
     if (n_rows < 0 || n_cols < 0 || nnz < 0) return ORC_CSR_BAD_SIZE;
-    for (int64_t k = 0; k < nnz; ++k) {
+    for (int64_t k = 1; k < nnz; ++k)
+        if (row[k] < row[k - 1]) *row_sorted = 0;
+    for (int64_t k = 0; k < nnz; ++k)
         if (row[k] < 0 || row[k] >= n_rows) return ORC_CSR_BAD_FIRST;
+    for (int64_t k = 0; k < nnz; ++k)
         if (col[k] < 0 || col[k] >= n_cols) return ORC_CSR_BAD_COLUMN;
-        if (k > 0 && row[k] < row[k - 1]) *row_sorted = 0;
-    }
     return ORC_CSR_OK;
 }
 

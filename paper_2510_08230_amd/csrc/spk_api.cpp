@@ -64,6 +64,11 @@ struct spk_plan_s {
     unsigned *bar = nullptr;             // persistent grid-barrier words
     spk_plan_info info{};
     double *r = nullptr, *p = nullptr, *q = nullptr, *partials = nullptr, *hist = nullptr;
+    int algo = 0;                        // ALGO_CG / ALGO_CGS / ALGO_PCG
+    double *rt = nullptr, *u = nullptr, *v = nullptr, *uh = nullptr;   // CGS
+    double *dinv = nullptr;              // Jacobi: 1 / diag(A)
+    void *coo_rp = nullptr;              // COO SpMV: derived row pointer (owned)
+    unsigned *diag_flag = nullptr;       // Jacobi: nonzero = unusable diagonal
     int64_t hist_cap = 0;
     SolveState *st = nullptr;
     SolveState *h_st = nullptr;          // pinned mirror
@@ -172,11 +177,12 @@ bool stream_ok(const CsrDev &A) {
     return (reinterpret_cast<uintptr_t>(A.va) & 15) == 0 && (reinterpret_cast<uintptr_t>(A.ci) & 15) == 0;
 }
 
-// bpc <= 0: as many workgroups per CU as the occupancy calculator allows.
+// bpc <= 0: as many workgroups per CU as the occupancy calculator allows;
+// otherwise bpc per CU (extra workgroups queue until a slot frees).
 SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap, int nt, int pf, int bpc) {
     SpmvTune t{kind, lanes_log2, 1, remap, nt, pf, 0};
     const int occ = spk::spmv_blocks_per_cu(A, t);
-    const int use = (bpc <= 0) ? occ : std::min(bpc, occ);
+    const int use = (bpc <= 0) ? occ : std::min(bpc, 32);   // a forced count may oversubscribe
     t.bpc = use;
     int64_t g = static_cast<int64_t>(ctx->num_cu) * use;
     g = std::min<int64_t>(g, spk::kMaxGrid);
@@ -205,8 +211,16 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneRe
     std::vector<SpmvTune> cands;
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
     if (stream_ok(A) && mean <= 64.0) {
-        // tile-to-XCD maps: round-robin, contiguous eighths, XCD-blocked runs of k tiles
-        for (int remap : {0, 1, 16, 64, 256}) cands.push_back(make_tune(ctx, A, 0, 0, remap, 0, 0, 0));
+        // tile-to-XCD maps (round-robin, contiguous eighths, XCD-blocked runs of
+        // k tiles) x matrix loads cached or non-temporal x the occupancy
+        // calculator's workgroups per CU or one more (its figure can be low)
+        for (int remap : {0, 1, 64, 256})
+            for (int nt : {0, 1}) {
+                const SpmvTune t = make_tune(ctx, A, 0, 0, remap, nt, 1, 0);
+                cands.push_back(t);
+                const SpmvTune t1 = make_tune(ctx, A, 0, 0, remap, nt, 1, t.bpc + 1);
+                if (t1.grid != t.grid) cands.push_back(t1);
+            }
     }
     for (int l2 = 0; l2 <= 6; ++l2) {
         const double L = static_cast<double>(1 << l2);
@@ -337,8 +351,10 @@ spk_status prof_collect(spk_plan pl, int64_t useful) {
 }
 
 // ------------------------------------------------------------------ CG driver
-// Loop kinds: 0 = FP64 CG on A, 1 = FP32 inner CG on A32 (mixed precision).
-enum { LOOP_FP64 = 0, LOOP_FP32 = 1 };
+// Loop kinds: FP64 CG on A, FP32 inner CG on A32 (mixed precision), FP64
+// CGS, FP64 Jacobi-preconditioned CG.
+enum { LOOP_FP64 = 0, LOOP_FP32 = 1, LOOP_CGS = 2, LOOP_PCG = 3 };
+enum { ALGO_CG = 0, ALGO_CGS = 1, ALGO_PCG = 2 };
 
 // Iteration j of a chunk: q = A p with p.q partials; alpha and r -= alpha q
 // with r.r partials; x += alpha p, the stop test and p = r + beta p.  A chunk
@@ -346,30 +362,47 @@ enum { LOOP_FP64 = 0, LOOP_FP32 = 1 };
 spk_status launch_iterations(spk_plan pl, int kind, int count, hipStream_t s, bool with_prof) {
     spk_ctx ctx = pl->ctx;
     const int64_t n = pl->A.n_rows;
+    hipEvent_t e = nullptr;
+    auto pb = [&]() { return with_prof ? prof_begin(pl, &e) : SPK_OK; };
+    auto pe = [&]() { return with_prof ? prof_end(pl, e) : SPK_OK; };
+    spk_status st = SPK_OK;
     for (int i = 0; i < count; ++i) {
-        hipEvent_t e = nullptr;
-        if (with_prof) {
-            spk_status st = prof_begin(pl, &e);
-            if (st != SPK_OK) return st;
+        if (kind == LOOP_CGS) {
+            SPK_HIP(ctx, spk::launch_cgs_dir(n, pl->vec_grid, pl->tune.grid, i, pl->r, pl->u, pl->p, pl->q, pl->st,
+                                             pl->partials, s));
+            if ((st = pb()) != SPK_OK) return st;
+            SPK_HIP(ctx, spk::launch_cgs_spmv_v(pl->A, pl->tune, pl->p, pl->v, pl->rt, pl->st, pl->partials, s));
+            if ((st = pe()) != SPK_OK) return st;
+            SPK_HIP(ctx, spk::launch_cgs_update(n, pl->vec_grid, pl->tune.grid, i, pl->u, pl->v, pl->q, pl->uh,
+                                                pl->st, pl->partials, s));
+            if ((st = pb()) != SPK_OK) return st;
+            SPK_HIP(ctx, spk::launch_cgs_spmv_r(pl->A, pl->tune, pl->uh, pl->r, pl->rt, pl->st, pl->partials, s));
+            if ((st = pe()) != SPK_OK) return st;
+            continue;
         }
-        if (kind == LOOP_FP64)
-            SPK_HIP(ctx, spk::launch_cg_spmv_pq(pl->A, pl->tune, pl->p, pl->q, pl->st, pl->partials, s));
-        else
+        if ((st = pb()) != SPK_OK) return st;
+        if (kind == LOOP_FP32)
             SPK_HIP(ctx, spk::launch_cg_spmv_pq32(pl->A32, pl->tune32, pl->p32, pl->q32, pl->st_in, pl->partials, s));
-        if (with_prof) {
-            spk_status st = prof_end(pl, e);
-            if (st != SPK_OK) return st;
-        }
+        else
+            SPK_HIP(ctx, spk::launch_cg_spmv_pq(pl->A, pl->tune, pl->p, pl->q, pl->st, pl->partials, s));
+        if ((st = pe()) != SPK_OK) return st;
         if (kind == LOOP_FP64) {
             SPK_HIP(ctx, spk::launch_cg_update(n, pl->vec_grid, pl->tune.grid, i, pl->r, pl->q, pl->st, pl->partials, s));
             SPK_HIP(ctx, spk::launch_cg_pupdate(n, pl->vec_grid, i, pl->r, pl->p, pl->st, pl->partials, s));
+        } else if (kind == LOOP_PCG) {
+            SPK_HIP(ctx, spk::launch_pcg_update(n, pl->vec_grid, pl->tune.grid, i, pl->r, pl->q, pl->dinv, pl->st,
+                                                pl->partials, s));
+            SPK_HIP(ctx, spk::launch_pcg_pupdate(n, pl->vec_grid, i, pl->r, pl->dinv, pl->p, pl->st, pl->partials, s));
         } else {
             SPK_HIP(ctx, spk::launch_cg_update32(n, pl->vec_grid, pl->tune32.grid, i, pl->r32, pl->q32, pl->st_in,
                                                  pl->partials, s));
             SPK_HIP(ctx, spk::launch_cg_pupdate32(n, pl->vec_grid, i, pl->r32, pl->p32, pl->st_in, pl->partials, s));
         }
     }
-    SPK_HIP(ctx, spk::launch_cg_chunk_end(kind == LOOP_FP64 ? pl->st : pl->st_in, count, s));
+    if (kind == LOOP_CGS)
+        SPK_HIP(ctx, spk::launch_cgs_check(pl->st, pl->partials, pl->tune.grid, count, s));
+    else
+        SPK_HIP(ctx, spk::launch_cg_chunk_end(kind == LOOP_FP32 ? pl->st_in : pl->st, count, s));
     return SPK_OK;
 }
 
@@ -439,8 +472,8 @@ int next_chunk(int prev, int64_t k0, double r0, int64_t k1, double r1, double th
 // The state must already be initialised (init / refinement kernels).
 spk_status run_loop(spk_plan pl, int kind, int64_t max_iters, bool graph) {
     spk_ctx ctx = pl->ctx;
-    SolveState *st = kind == LOOP_FP64 ? pl->st : pl->st_in;
-    SolveState *h = kind == LOOP_FP64 ? pl->h_st : pl->h_st_in;
+    SolveState *st = kind == LOOP_FP32 ? pl->st_in : pl->st;
+    SolveState *h = kind == LOOP_FP32 ? pl->h_st_in : pl->h_st;
     const int cfg_chunk = pl->cfg.chunk_iters;
     spk_status s = pull(ctx, h, st, sizeof(SolveState));
     if (s != SPK_OK) return s;
@@ -482,6 +515,16 @@ void release_workspace(spk_plan pl) {
     ctx->dpool.put(pl->out_dev);
     ctx->hpool.put(pl->h_out);
     ctx->dpool.put(pl->bar);
+    ctx->dpool.put(pl->rt);
+    ctx->dpool.put(pl->u);
+    ctx->dpool.put(pl->v);
+    ctx->dpool.put(pl->uh);
+    ctx->dpool.put(pl->dinv);
+    ctx->dpool.put(pl->diag_flag);
+    ctx->dpool.put(pl->coo_rp);
+    pl->coo_rp = nullptr;
+    pl->rt = pl->u = pl->v = pl->uh = pl->dinv = nullptr;
+    pl->diag_flag = nullptr;
     pl->bar = nullptr;
     pl->r = pl->p = pl->q = pl->partials = pl->hist = nullptr;
     pl->st = pl->h_st = pl->st_in = pl->h_st_in = nullptr;
@@ -612,6 +655,9 @@ static spk_status plan_common(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
     return SPK_OK;
 }
 
+// Tune and finish an SpMV plan whose matrix view is already set.
+static spk_status finish_spmv_plan(spk_ctx ctx, spk_plan pl, const spk_csr *A, spk_plan *out);
+
 spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
     spk_status s = plan_common(ctx, A, out);
     if (s != SPK_OK) return s;
@@ -619,6 +665,88 @@ spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
     pl->ctx = ctx;
     pl->kind = 0;
     pl->A = to_dev(A);
+    return finish_spmv_plan(ctx, pl, A, out);
+}
+
+static spk_status coo_args(spk_ctx ctx, const spk_coo *A) {
+    if (!A) return fail(ctx, SPK_ERR_INVALID_ARG, "null matrix descriptor");
+    if (!valid_itype(A->idx_type)) return fail(ctx, SPK_ERR_INVALID_ARG, "unknown index type");
+    if (!valid_dtype(A->val_type)) return fail(ctx, SPK_ERR_INVALID_ARG, "unknown value type");
+    if (A->nnz > 0 && (!A->row_idx || !A->col_idx || !A->values))
+        return fail(ctx, SPK_ERR_INVALID_ARG, "row_idx/col_idx/values null");
+    return SPK_OK;
+}
+
+static spk_status coo_verdict(spk_ctx ctx, const spk_coo *A, int32_t *verdict, int32_t *sorted) {
+    *sorted = 1;
+    if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) {
+        *verdict = SPK_CSR_BAD_SIZE;
+        return SPK_OK;
+    }
+    SPK_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(unsigned), ctx->stream));
+    SPK_HIP(ctx, spk::launch_coo_validate(A->n_rows, A->n_cols, A->nnz, A->row_idx, A->col_idx, A->idx_type,
+                                          ctx->d_flags, ctx->num_cu * 4, ctx->stream));
+    SPK_HIP(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const unsigned f = *ctx->h_flags;
+    *verdict = (f & spk::VFLAG_BAD_FIRST) ? SPK_CSR_BAD_FIRST
+                                          : ((f & spk::VFLAG_BAD_COLUMN) ? SPK_CSR_BAD_COLUMN : SPK_CSR_OK);
+    *sorted = (f & spk::VFLAG_UNSORTED) ? 0 : 1;
+    return SPK_OK;
+}
+
+spk_status spk_coo_check(spk_ctx ctx, const spk_coo *A, int32_t *verdict, int32_t *row_sorted) {
+    if (!ctx || !verdict || !row_sorted) return SPK_ERR_INVALID_ARG;
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    spk_status s = coo_args(ctx, A);
+    if (s != SPK_OK) return s;
+    return coo_verdict(ctx, A, verdict, row_sorted);
+}
+
+spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out) {
+    if (!ctx || !out) return SPK_ERR_INVALID_ARG;
+    *out = nullptr;
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    spk_status s = coo_args(ctx, A);
+    if (s != SPK_OK) return s;
+    int32_t verdict = 0, sorted = 1;
+    if ((s = coo_verdict(ctx, A, &verdict, &sorted)) != SPK_OK) return s;
+    if (verdict != SPK_CSR_OK)
+        return fail(ctx, SPK_ERR_INVALID_ARG, std::string("malformed COO: ") +
+                                                  (verdict == SPK_CSR_BAD_FIRST ? "row index out of range"
+                                                                                : verdict_name(verdict)));
+    if (!sorted) return fail(ctx, SPK_ERR_INVALID_ARG, "COO entries must be sorted by row");
+    spk_csr csr{};
+    csr.n_rows = A->n_rows;
+    csr.n_cols = A->n_cols;
+    csr.nnz = A->nnz;
+    csr.ptr_type = A->nnz > INT32_MAX ? SPK_I64 : SPK_I32;
+    csr.idx_type = A->idx_type;
+    csr.val_type = A->val_type;
+    csr.col_idx = A->col_idx;
+    csr.values = A->values;
+    spk_plan pl = new spk_plan_s();
+    pl->ctx = ctx;
+    pl->kind = 0;
+    const size_t pb = (csr.ptr_type == SPK_I64 ? 8 : 4) * static_cast<size_t>(A->n_rows + 1);
+    if (ctx->dpool.get(pb, &pl->coo_rp) != hipSuccess) {
+        delete pl;
+        return fail(ctx, SPK_ERR_OUT_OF_MEMORY, "COO row pointer");
+    }
+    csr.row_ptr = pl->coo_rp;
+    if (spk::launch_coo_rowptr(A->n_rows, A->nnz, A->row_idx, A->idx_type, pl->coo_rp, csr.ptr_type,
+                               ctx->stream) != hipSuccess) {
+        (void)hipStreamSynchronize(ctx->stream);
+        release_workspace(pl);
+        delete pl;
+        return fail(ctx, SPK_ERR_DEVICE, "COO row pointer");
+    }
+    pl->A = to_dev(&csr);
+    return finish_spmv_plan(ctx, pl, &csr, out);
+}
+
+static spk_status finish_spmv_plan(spk_ctx ctx, spk_plan pl, const spk_csr *A, spk_plan *out) {
+    spk_status s = SPK_OK;
     spk_solver_cfg_default(&pl->cfg);
     void *x = nullptr, *y = nullptr;
     const size_t vb = vec_bytes(A->val_type);
@@ -628,6 +756,7 @@ spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
         if (e1 != hipSuccess || e2 != hipSuccess) {
             ctx->dpool.put(x);
             ctx->dpool.put(y);
+            release_workspace(pl);
             delete pl;
             return fail(ctx, SPK_ERR_OUT_OF_MEMORY, "tuning buffers");
         }
@@ -638,6 +767,7 @@ spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
     ctx->dpool.put(x);
     ctx->dpool.put(y);
     if (s != SPK_OK) {
+        release_workspace(pl);
         delete pl;
         return s;
     }
@@ -652,8 +782,14 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     spk_solver_cfg cfg;
     if (cfg_in) cfg = *cfg_in;
     else spk_solver_cfg_default(&cfg);
-    if (cfg.solver != SPK_SOLVER_CG) return fail(ctx, SPK_ERR_UNSUPPORTED, "only CG is built");
-    if (cfg.precond != SPK_PRECOND_NONE) return fail(ctx, SPK_ERR_UNSUPPORTED, "no preconditioner is built");
+    if (cfg.solver != SPK_SOLVER_CG && cfg.solver != SPK_SOLVER_CGS)
+        return fail(ctx, SPK_ERR_INVALID_ARG, "unknown solver");
+    if (cfg.precond != SPK_PRECOND_NONE && cfg.precond != SPK_PRECOND_JACOBI)
+        return fail(ctx, SPK_ERR_INVALID_ARG, "unknown preconditioner");
+    if (cfg.solver == SPK_SOLVER_CGS && cfg.precond != SPK_PRECOND_NONE)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS runs unpreconditioned");
+    if ((cfg.solver == SPK_SOLVER_CGS || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS and Jacobi CG run in FP64 precision");
     if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
     if (cfg.precision < SPK_PREC_FP64 || cfg.precision > SPK_PREC_MIXED_BF16)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown precision");
@@ -680,6 +816,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     pl->kind = 1;
     pl->A = to_dev(A);
     pl->cfg = cfg;
+    pl->algo = cfg.solver == SPK_SOLVER_CGS ? ALGO_CGS : (cfg.precond == SPK_PRECOND_JACOBI ? ALGO_PCG : ALGO_CG);
     const int64_t n = A->n_rows;
     const size_t nb = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(double);
     const size_t nf = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(float);
@@ -719,6 +856,16 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             hipMemsetAsync(pl->p, 0, nb, ctx->stream) != hipSuccess)
             return cleanup(SPK_ERR_DEVICE, "workspace init");
         std::memset(pl->h_st, 0, sizeof(SolveState));
+        if (pl->algo == ALGO_CGS &&
+            (!dget(nb, &pl->rt) || !dget(nb, &pl->u) || !dget(nb, &pl->v) || !dget(nb, &pl->uh)))
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "CGS workspace");
+        if (pl->algo == ALGO_PCG) {
+            if (!dget(nb, &pl->dinv) || !dget(sizeof(unsigned), &pl->diag_flag))
+                return cleanup(SPK_ERR_OUT_OF_MEMORY, "Jacobi workspace");
+            if (hipMemsetAsync(pl->diag_flag, 0, sizeof(unsigned), ctx->stream) != hipSuccess ||
+                spk::launch_diag_inv(pl->A, pl->dinv, pl->diag_flag, ctx->stream) != hipSuccess)
+                return cleanup(SPK_ERR_DEVICE, "Jacobi diagonal");
+        }
         s = choose_tune(pl, pl->p, pl->q);
         if (s != SPK_OK) return cleanup(s, ctx->err);
     } else {
@@ -761,7 +908,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     // measured faster than replaying captured chunks or one cooperative
     // launch with grid barriers.
     if (mode == SPK_EXEC_AUTO) mode = SPK_EXEC_HOST_LOOP;
-    if (mode == SPK_EXEC_PERSISTENT && mixed) mode = SPK_EXEC_GRAPH;
+    if (mode == SPK_EXEC_PERSISTENT && (mixed || pl->algo != ALGO_CG)) mode = SPK_EXEC_GRAPH;
     if (mode == SPK_EXEC_PERSISTENT) {
         const int occ = spk::persistent_blocks_per_cu(pl->A);
         const int64_t tiles = std::max<int64_t>((n + spk::kTileRows - 1) / spk::kTileRows, 1);
@@ -817,17 +964,29 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
         if (flags[2] != 0) return fail(ctx, SPK_ERR_DEVICE, "persistent solve: a grid barrier timed out");
     } else {
-        SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->p, pl->st, pl->partials,
-                                         cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
-        s = run_loop(pl, LOOP_FP64, cfg.max_iters, graph);
+        int kind = LOOP_FP64;
+        if (pl->algo == ALGO_PCG) {
+            SPK_HIP(ctx, spk::launch_pcg_init(pl->A, pl->tune, b, x, pl->dinv, pl->diag_flag, pl->r, pl->p, pl->st,
+                                              pl->partials, cfg.reduction_factor, cfg.max_iters, pl->hist,
+                                              pl->hist_cap, ctx->stream));
+            kind = LOOP_PCG;
+        } else {
+            // CGS: the same initial residual, with the shadow residual rt = r_0 in place of p
+            SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->algo == ALGO_CGS ? pl->rt : pl->p,
+                                             pl->st, pl->partials, cfg.reduction_factor, cfg.max_iters, pl->hist,
+                                             pl->hist_cap, ctx->stream));
+            if (pl->algo == ALGO_CGS) kind = LOOP_CGS;
+        }
+        s = run_loop(pl, kind, cfg.max_iters, graph);
         if (s != SPK_OK) return s;
         SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
                                              ctx->stream));
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
     }
     const SolveState &h = *pl->h_st;
-    if (pl->profiling) {
-        const int64_t useful = h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+    if (pl->profiling) {   // SpMV launches that did work (two per CGS iteration)
+        const int64_t per = pl->algo == ALGO_CGS ? 2 : 1;
+        const int64_t useful = per * h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
         if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
     }
     L->iterations = h.iter;

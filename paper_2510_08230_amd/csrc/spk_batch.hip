@@ -37,8 +37,8 @@ __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const 
     }
     C sum = 0;
     if (e - s <= kStreamCap) {
-        dma_chunks<V>(va, s, e, nnz, lv);
-        dma_chunks<int32_t>(ci, s, e, nnz, lc);
+        dma_chunks<V>(va, s, e, nnz, lv, 0);
+        dma_chunks<int32_t>(ci, s, e, nnz, lc, 0);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (has_row)

@@ -84,6 +84,26 @@ struct TileIter {
     }
 };
 
+// Bounds of one row tile: its first row, its entry range [s, e) and this
+// thread's row range [a, b) (empty past the last row).
+template <typename P>
+struct TileMeta {
+    int64_t r0;
+    P s, e, a, b;
+    __device__ __forceinline__ void load(const P *__restrict__ rp, int64_t n, int64_t tile) {
+        r0 = tile * kTileRows;
+        const int64_t r1 = r0 + kTileRows < n ? r0 + kTileRows : n;
+        s = rp[r0];
+        e = rp[r1];
+        const int64_t row = r0 + threadIdx.x;
+        a = b = 0;
+        if (row < r1) {
+            a = rp[row];
+            b = rp[row + 1];
+        }
+    }
+};
+
 // Block-level fixed-order reduction of NV doubles; thread 0 stores the
 // workgroup's partials at partials[j * kMaxGrid + blockIdx.x].
 template <int NV>
@@ -185,8 +205,11 @@ struct Chunks {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// nt = 1: the loads carry the non-temporal policy (the matrix streams through
+// once; the gathered vector should keep its place in L2).
 template <typename T>
-__device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, int64_t e, int64_t total, u32x4 *lds) {
+__device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, int64_t e, int64_t total, u32x4 *lds,
+                                           int nt) {
     constexpr int EPC = Chunks<T>::EPC;
     const int64_t s0 = s & ~static_cast<int64_t>(EPC - 1);
     const int lane = threadIdx.x & 63;
@@ -198,8 +221,12 @@ __device__ __forceinline__ void dma_chunks(const T *__restrict__ g, int64_t s, i
         const int64_t k = s0 + static_cast<int64_t>(cbase + lane) * EPC;
         if (k < e) {
             if (k + EPC <= total) {
-                __builtin_amdgcn_global_load_lds(static_cast<const void *>(g + k),
-                                                 (lds_void *)(lds + cbase), 16, 0, 0);
+                if (nt)
+                    __builtin_amdgcn_global_load_lds(static_cast<const void *>(g + k),
+                                                     (lds_void *)(lds + cbase), 16, 0, 2);
+                else
+                    __builtin_amdgcn_global_load_lds(static_cast<const void *>(g + k),
+                                                     (lds_void *)(lds + cbase), 16, 0, 0);
             } else {
                 T *dst = reinterpret_cast<T *>(lds + cbase + lane);
                 for (int j = 0; j < EPC; ++j)

@@ -54,7 +54,7 @@ struct SpmvTune {
     int grid;        // workgroups
     int xcd_remap;   // 1 = contiguous tile ranges per XCD
     int nt;          // 1 = non-temporal loads for the matrix value stream
-    int pf;          // LDS tiles: 1 = next tile's loads issued before the current tile is reduced
+    int pf;          // LDS tiles: 1 = the next tile's row pointers load while this tile's entries stream in
     int bpc;         // workgroups per CU the grid was sized for
 };
 
@@ -66,11 +66,19 @@ struct CsrDev {
 };
 
 // Validation flag bits (set by the GPU check, order resolved on the host).
-enum : unsigned { VFLAG_BAD_FIRST = 1u, VFLAG_DECREASING = 2u, VFLAG_BAD_LAST = 4u, VFLAG_BAD_COLUMN = 8u };
+enum : unsigned { VFLAG_BAD_FIRST = 1u, VFLAG_DECREASING = 2u, VFLAG_BAD_LAST = 4u, VFLAG_BAD_COLUMN = 8u,
+                  VFLAG_UNSORTED = 16u };
 
 // ---- launchers (spk_kernels.hip) -------------------------------------------------
 hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
+// COO (idx_t 0 = int32, 1 = int64): flags gets VFLAG_BAD_FIRST for a row
+// index out of range, VFLAG_BAD_COLUMN, VFLAG_UNSORTED for a decreasing row.
+hipError_t launch_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const void *row, const void *col,
+                               int idx_t, unsigned *flags, int max_grid, hipStream_t s);
+// Row pointer (n_rows + 1 entries of ptr_t) of a valid row-sorted COO matrix.
+hipError_t launch_coo_rowptr(int64_t n_rows, int64_t nnz, const void *row, int idx_t, void *rp, int ptr_t,
+                             hipStream_t s);
 
 // y = A x; x/y are double for F64 values, float otherwise.
 hipError_t launch_spmv(const CsrDev &A, const SpmvTune &t, const void *x, void *y, hipStream_t s);
@@ -111,6 +119,32 @@ hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *
                               SolveState *st, double *partials, int true_residual, hipStream_t s);
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s);
+
+// CGS (FP64; spk_krylov.hip).  Iteration j of a chunk = dir(j), spmv_v,
+// update(j), spmv_r; a chunk of c iterations ends with check(c).  The initial
+// residual is launch_cg_init with the shadow residual rt in place of p.
+hipError_t launch_cgs_dir(int64_t n, int grid, int spmv_grid, int j, const double *r, double *u, double *p,
+                          const double *q, SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cgs_spmv_v(const CsrDev &A, const SpmvTune &t, const double *p, double *v, const double *rt,
+                             SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cgs_update(int64_t n, int grid, int spmv_grid, int j, const double *u, const double *v, double *q,
+                             double *uh, SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cgs_spmv_r(const CsrDev &A, const SpmvTune &t, const double *uh, double *r, const double *rt,
+                             SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_cgs_check(SolveState *st, double *partials, int spmv_grid, int count, hipStream_t s);
+
+// Jacobi-preconditioned CG (FP64; spk_krylov.hip).  diag_inv runs once per
+// plan (flag: one zeroed unsigned, set when a diagonal entry is zero or not
+// finite).  Iteration j = launch_cg_spmv_pq, pcg_update(j), pcg_pupdate(j);
+// chunks end with launch_cg_chunk_end.
+hipError_t launch_diag_inv(const CsrDev &A, double *dinv, unsigned *flag, hipStream_t s);
+hipError_t launch_pcg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, const double *dinv,
+                           const unsigned *bad_diag, double *r, double *p, SolveState *st, double *partials,
+                           double tau, int64_t max_iters, double *hist, int64_t hist_cap, hipStream_t s);
+hipError_t launch_pcg_update(int64_t n, int grid, int spmv_grid, int j, double *r, const double *q,
+                             const double *dinv, SolveState *st, double *partials, hipStream_t s);
+hipError_t launch_pcg_pupdate(int64_t n, int grid, int j, const double *r, const double *dinv, double *p,
+                              SolveState *st, double *partials, hipStream_t s);
 
 // Whole FP64 CG solve in one cooperative launch (grid must be co-resident:
 // grid <= persistent_blocks_per_cu * CUs).  partials: at least 5 * kMaxGrid

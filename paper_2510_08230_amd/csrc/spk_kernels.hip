@@ -25,7 +25,7 @@
 // iteration (chunk base + index within the chunk), so no launch reads a
 // location that it writes.  Kernels return at once when the stop flag is
 // set, so iterations enqueued past convergence cost only empty launches.
-#include "spk_device.h"
+#include "spk_spmv.h"
 
 #include <cmath>
 #include <type_traits>
@@ -34,6 +34,7 @@ namespace spk {
 namespace {
 
 using namespace dev;
+using namespace tile;
 
 // ------------------------------------------------------------------ epilogues
 template <class X>
@@ -130,129 +131,6 @@ struct EpiTrue {
     }
 };
 
-// LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
-// thread per row reduces from LDS while gathering x.  Occupancy (several
-// workgroups per CU) overlaps one workgroup's DMA with another's gathers.
-// The tile loop of the LDS-staged SpMV, shared by the per-launch kernel and the
-// persistent CG kernel: calls epi.row(row, sum) for every row of the tiles
-// this workgroup visits.  lv / lc: the workgroup's LDS staging buffers.
-template <typename V, typename P, typename I, typename C, class Gx, class Epi>
-__device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
-                                               const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
-                                               int remap, int nt, Epi &epi, u32x4 *lv, u32x4 *lc) {
-    const V *sv = reinterpret_cast<const V *>(lv);
-    const I *sc = reinterpret_cast<const I *>(lc);
-    const int64_t T = (n + kTileRows - 1) / kTileRows;
-    for (TileIter it(T, remap); it.valid(); it.next()) {
-        const int64_t r0 = it.tile() * kTileRows;
-        const int64_t r1 = min(r0 + static_cast<int64_t>(kTileRows), n);
-        const int64_t s = static_cast<int64_t>(rp[r0]);
-        const int64_t e = static_cast<int64_t>(rp[r1]);
-        const int64_t row = r0 + threadIdx.x;
-        int64_t a = 0, b = 0;
-        if (row < r1) {
-            a = static_cast<int64_t>(rp[row]);
-            b = static_cast<int64_t>(rp[row + 1]);
-        }
-        if (e - s <= kStreamCap) {
-            dma_chunks<V>(va, s, e, nnz, lv);
-            dma_chunks<I>(ci, s, e, nnz, lc);
-            __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA has landed
-            __syncthreads();                 // ... and every other wave's
-            if (row < r1) {
-                const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
-                const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
-                epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx));
-            }
-            __syncthreads();                 // LDS free for the next tile
-        } else if (row < r1) {
-            epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt));
-        }
-    }
-}
-
-template <typename V, typename P, typename I, typename X, typename C, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
-                                                        const I *__restrict__ ci, const V *__restrict__ va,
-                                                        const X *__restrict__ x, int remap, int nt, Epi epi_in) {
-    Epi epi = epi_in;
-    if (epi.skip()) return;
-    __shared__ u32x4 lv[Chunks<V>::LDS];
-    __shared__ u32x4 lc[Chunks<I>::LDS];
-    spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, epi, lv, lc);
-    epi.finish();
-}
-
-template <typename V, typename P, typename I, typename C, class Gx, class Epi>
-__device__ __forceinline__ void spmv_tiles_vector(int64_t n, const P *__restrict__ rp, const I *__restrict__ ci,
-                                                  const V *__restrict__ va, const Gx &gx, int lanes_log2, int remap,
-                                                  int nt, Epi &epi) {
-    const int L = 1 << lanes_log2;
-    const int lane = threadIdx.x & (L - 1);
-    const int group = threadIdx.x >> lanes_log2;
-    const int groups = kBlock >> lanes_log2;
-    const int64_t T = (n + kTileRows - 1) / kTileRows;
-    for (TileIter it(T, remap); it.valid(); it.next()) {
-        const int64_t r0 = it.tile() * kTileRows;
-        const int64_t r1 = min(r0 + (int64_t)kTileRows, n);
-        for (int pass = 0; pass < L; ++pass) {
-            const int64_t row = r0 + static_cast<int64_t>(pass) * groups + group;
-            C sum = 0;
-            if (row < r1) {
-                const int64_t a = static_cast<int64_t>(rp[row]), b = static_cast<int64_t>(rp[row + 1]);
-                for (int64_t k = a + lane; k < b; k += L)
-                    sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(gx(static_cast<int64_t>(ci[k]))),
-                              sum);
-            }
-            for (int off = L >> 1; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
-            if (row < r1 && lane == 0) epi.row(row, sum);
-        }
-    }
-}
-
-template <typename V, typename P, typename I, typename X, typename C, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv_vector(int64_t n, const P *__restrict__ rp,
-                                                        const I *__restrict__ ci, const V *__restrict__ va,
-                                                        const X *__restrict__ x, int lanes_log2, int remap,
-                                                        int nt, Epi epi_in) {
-    Epi epi = epi_in;
-    if (epi.skip()) return;
-    spmv_tiles_vector<V, P, I, C>(n, rp, ci, va, PlainGather<X, C>{x}, lanes_log2, remap, nt, epi);
-    epi.finish();
-}
-
-template <class F>
-hipError_t dispatch_idx(const CsrDev &A, F &&f) {
-    if (A.ptr_t == 0) {
-        if (A.idx_t == 0) return f(static_cast<const int32_t *>(A.rp), static_cast<const int32_t *>(A.ci));
-        return f(static_cast<const int32_t *>(A.rp), static_cast<const int64_t *>(A.ci));
-    }
-    if (A.idx_t == 0) return f(static_cast<const int64_t *>(A.rp), static_cast<const int32_t *>(A.ci));
-    return f(static_cast<const int64_t *>(A.rp), static_cast<const int64_t *>(A.ci));
-}
-
-template <class Ptr>
-using pointee_t = std::remove_const_t<std::remove_pointer_t<Ptr>>;
-
-template <typename V, typename X, typename C, class Epi>
-hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const Epi &epi, hipStream_t s) {
-    if (A.n_rows == 0) return hipSuccess;
-    return dispatch_idx(A, [&](auto rp, auto ci) {
-        using P = pointee_t<decltype(rp)>;
-        using I = pointee_t<decltype(ci)>;
-        const V *va = static_cast<const V *>(A.va);
-        const dim3 grid(t.grid), block(kBlock);
-        if (t.kind == 0) {
-            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
-                               t.xcd_remap, t.nt, epi);
-        } else {
-            hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
-                               t.lanes_log2, t.xcd_remap, t.nt, epi);
-        }
-        return hipGetLastError();
-    });
-}
-
 // ------------------------------------------------------------------ CG scalar + vector kernels
 // One workgroup: finish the initial residual (||b||, rho_0, first stop test).
 __global__ __launch_bounds__(kBlock) void k_init_finish(SolveState *st, const double *part, int G, double tau,
@@ -296,11 +174,6 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(SolveState *st, const do
     }
 }
 
-template <typename T>
-struct Vec16 {
-    static constexpr int W = 16 / sizeof(T);
-    typedef T type __attribute__((ext_vector_type(W)));
-};
 
 // r -= alpha q with alpha = rho_k / (p . q) (FP64 scalar, applied in T);
 // partials of r.r accumulated in FP64.  x += alpha p is left to the p-update
@@ -596,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(PersistArgs a) {
     // ---- init: r = b - A x, p = r; ||b||, rho_0
     {
         EpiInit e{a.b, a.r, a.p, part_a, 0.0, 0.0};
-        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, e, lv, lc);
+        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, 1, e, lv, lc);
         e.finish();   // partials of r.r, b.b into part_a[0..G), part_a[kMaxGrid..)
     }
     if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
@@ -638,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(PersistArgs a) {
         // q = A p, partials of p.q
         {
             EpiPq<double> e{a.q, a.p, a.st, part_b, 0.0};
-            spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.p}, a.remap, 0,
+            spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.p}, a.remap, 0, 1,
                                                  e, lv, lc);
             e.finish();
         }
@@ -697,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_persistent(PersistArgs a) {
     if (!grid_sync(a.bar, gen, a.spin_ticks)) return;   // x complete everywhere
     {
         EpiTrue e{a.b, a.st, part_a, 0.0};
-        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, e, lv, lc);
+        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, 1, e, lv, lc);
         e.finish();
     }
     if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
@@ -745,6 +618,44 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
     if (f) atomicOr(flags, f);
 }
 
+// COO structure: row and column indices in range, rows non-decreasing.
+template <typename I>
+__global__ __launch_bounds__(kBlock) void k_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                                         const I *__restrict__ row, const I *__restrict__ col,
+                                                         unsigned *flags) {
+    unsigned f = 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; k < nnz; k += stride) {
+        const int64_t r = static_cast<int64_t>(row[k]);
+        const int64_t c = static_cast<int64_t>(col[k]);
+        if (r < 0 || r >= n_rows) f |= VFLAG_BAD_FIRST;
+        if (c < 0 || c >= n_cols) f |= VFLAG_BAD_COLUMN;
+        if (k > 0 && r < static_cast<int64_t>(row[k - 1])) f |= VFLAG_UNSORTED;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// Row pointer of a row-sorted COO matrix: rp[i] = first entry whose row is
+// >= i.  Entry k writes the pointers of the rows in (row[k-1], row[k]]; the
+// first entry also those up to row[0], the last those after it.
+template <typename I, typename P>
+__global__ __launch_bounds__(kBlock) void k_coo_rowptr(int64_t n_rows, int64_t nnz, const I *__restrict__ row,
+                                                       P *__restrict__ rp) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (nnz == 0) {
+        for (int64_t i = gid; i <= n_rows; i += stride) rp[i] = 0;
+        return;
+    }
+    for (int64_t k = gid; k < nnz; k += stride) {
+        const int64_t r = static_cast<int64_t>(row[k]);
+        const int64_t lo = k == 0 ? 0 : static_cast<int64_t>(row[k - 1]) + 1;
+        for (int64_t i = lo; i <= r; ++i) rp[i] = static_cast<P>(k);
+        if (k == nnz - 1)
+            for (int64_t i = r + 1; i <= n_rows; ++i) rp[i] = static_cast<P>(nnz);
+    }
+}
+
 template <typename P>
 __global__ __launch_bounds__(kBlock) void k_partition(int64_t n, const P *__restrict__ rp, int64_t parts,
                                                       int64_t *split) {
@@ -790,6 +701,37 @@ hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipSt
     });
 }
 
+hipError_t launch_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const void *row, const void *col,
+                               int idx_t, unsigned *flags, int max_grid, hipStream_t s) {
+    if (nnz == 0) return hipSuccess;
+    const int grid = grid_for(nnz, 8, max_grid);
+    if (idx_t == 0)
+        hipLaunchKernelGGL(k_coo_validate<int32_t>, dim3(grid), dim3(kBlock), 0, s, n_rows, n_cols, nnz,
+                           static_cast<const int32_t *>(row), static_cast<const int32_t *>(col), flags);
+    else
+        hipLaunchKernelGGL(k_coo_validate<int64_t>, dim3(grid), dim3(kBlock), 0, s, n_rows, n_cols, nnz,
+                           static_cast<const int64_t *>(row), static_cast<const int64_t *>(col), flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_coo_rowptr(int64_t n_rows, int64_t nnz, const void *row, int idx_t, void *rp, int ptr_t,
+                             hipStream_t s) {
+    const int grid = grid_for(nnz > n_rows ? nnz : n_rows + 1, 8, kMaxGrid);
+    if (idx_t == 0 && ptr_t == 0)
+        hipLaunchKernelGGL((k_coo_rowptr<int32_t, int32_t>), dim3(grid), dim3(kBlock), 0, s, n_rows, nnz,
+                           static_cast<const int32_t *>(row), static_cast<int32_t *>(rp));
+    else if (idx_t == 0)
+        hipLaunchKernelGGL((k_coo_rowptr<int32_t, int64_t>), dim3(grid), dim3(kBlock), 0, s, n_rows, nnz,
+                           static_cast<const int32_t *>(row), static_cast<int64_t *>(rp));
+    else if (ptr_t == 0)
+        hipLaunchKernelGGL((k_coo_rowptr<int64_t, int32_t>), dim3(grid), dim3(kBlock), 0, s, n_rows, nnz,
+                           static_cast<const int64_t *>(row), static_cast<int32_t *>(rp));
+    else
+        hipLaunchKernelGGL((k_coo_rowptr<int64_t, int64_t>), dim3(grid), dim3(kBlock), 0, s, n_rows, nnz,
+                           static_cast<const int64_t *>(row), static_cast<int64_t *>(rp));
+    return hipGetLastError();
+}
+
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s) {
     const int64_t blocks = (parts + 1 + kBlock - 1) / kBlock;
     if (A.ptr_t == 0)
@@ -820,7 +762,6 @@ hipError_t launch_spmv(const CsrDev &A, const SpmvTune &t, const void *x, void *
     }
 }
 
-static double *site(double *partials, int k) { return partials + static_cast<size_t>(k) * kSiteWidth * kMaxGrid; }
 
 hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, double *r, double *p,
                           SolveState *st, double *partials, double tau, int64_t max_iters, double *hist,

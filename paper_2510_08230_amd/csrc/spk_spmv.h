@@ -1,0 +1,165 @@
+// The SpMV tilings and their launch helper, shared by the kernel sources.
+//
+//   * LDS-staged row tiles: a workgroup owns 256 consecutive rows; it streams
+//     the tile's values and column indices from HBM into LDS with fully
+//     coalesced loads (one contiguous nnz range per tile), then each thread
+//     reduces one row from LDS while gathering x.  Tiles whose nnz exceed the
+//     LDS capacity fall back to direct loads.
+//   * lanes-per-row vector kernel: 2^k lanes of a wave64 share a row.
+// Both hand each row sum to an epilogue object (row(i, s), finish()), which is
+// where the solvers fuse their elementwise work and dot-product partials.
+#pragma once
+
+#include "spk_device.h"
+
+#include <type_traits>
+
+namespace spk {
+namespace tile {
+
+using namespace dev;
+
+// Partial-sum slab k of the workspace.
+inline double *site(double *partials, int k) { return partials + static_cast<size_t>(k) * kSiteWidth * kMaxGrid; }
+
+template <typename T>
+struct Vec16 {
+    static constexpr int W = 16 / sizeof(T);
+    typedef T type __attribute__((ext_vector_type(W)));
+};
+
+// LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
+// thread per row reduces from LDS while gathering x.  Occupancy (several
+// workgroups per CU) overlaps one workgroup's DMA with another's gathers.
+// The tile loop of the LDS-staged SpMV, shared by the per-launch kernel and the
+// persistent CG kernel: calls epi.row(row, sum) for every row of the tiles
+// this workgroup visits.  lv / lc: the workgroup's LDS staging buffers.
+template <typename V, typename P, typename I, typename C, class Gx, class Epi>
+__device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
+                                               const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
+                                               int remap, int nt, int pf, Epi &epi, u32x4 *lv, u32x4 *lc) {
+    const V *sv = reinterpret_cast<const V *>(lv);
+    const I *sc = reinterpret_cast<const I *>(lc);
+    const int64_t T = (n + kTileRows - 1) / kTileRows;
+    TileIter it(T, remap);
+    if (!it.valid()) return;
+    // pf = 1: the row pointers of the next tile are loaded while the current
+    // tile's entries stream in, so each tile starts with its bounds at hand.
+    TileMeta<P> cur, nxt;
+    cur.load(rp, n, it.tile());
+    while (true) {
+        TileIter after = it;
+        after.next();
+        const bool more = after.valid();
+        const int64_t r1 = min(cur.r0 + static_cast<int64_t>(kTileRows), n);
+        const int64_t row = cur.r0 + threadIdx.x;
+        const int64_t s = static_cast<int64_t>(cur.s), e = static_cast<int64_t>(cur.e);
+        const int64_t a = static_cast<int64_t>(cur.a), b = static_cast<int64_t>(cur.b);
+        if (e - s <= kStreamCap) {
+            dma_chunks<V>(va, s, e, nnz, lv, nt);
+            dma_chunks<I>(ci, s, e, nnz, lc, nt);
+            if (more && pf) nxt.load(rp, n, after.tile());
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA (and the prefetch) has landed
+            __syncthreads();                 // ... and every other wave's
+            if (row < r1) {
+                const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
+                const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
+                epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx));
+            }
+            __syncthreads();                 // LDS free for the next tile
+        } else {
+            if (more && pf) nxt.load(rp, n, after.tile());
+            if (row < r1) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt));
+        }
+        if (!more) break;
+        if (!pf) nxt.load(rp, n, after.tile());
+        it = after;
+        cur = nxt;
+    }
+}
+
+template <typename V, typename P, typename I, typename X, typename C, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
+                                                        const I *__restrict__ ci, const V *__restrict__ va,
+                                                        const X *__restrict__ x, int remap, int nt, int pf,
+                                                        Epi epi_in) {
+    Epi epi = epi_in;
+    if (epi.skip()) return;
+    __shared__ u32x4 lv[Chunks<V>::LDS];
+    __shared__ u32x4 lc[Chunks<I>::LDS];
+    spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, pf, epi, lv, lc);
+    epi.finish();
+}
+
+template <typename V, typename P, typename I, typename C, class Gx, class Epi>
+__device__ __forceinline__ void spmv_tiles_vector(int64_t n, const P *__restrict__ rp, const I *__restrict__ ci,
+                                                  const V *__restrict__ va, const Gx &gx, int lanes_log2, int remap,
+                                                  int nt, Epi &epi) {
+    const int L = 1 << lanes_log2;
+    const int lane = threadIdx.x & (L - 1);
+    const int group = threadIdx.x >> lanes_log2;
+    const int groups = kBlock >> lanes_log2;
+    const int64_t T = (n + kTileRows - 1) / kTileRows;
+    for (TileIter it(T, remap); it.valid(); it.next()) {
+        const int64_t r0 = it.tile() * kTileRows;
+        const int64_t r1 = min(r0 + (int64_t)kTileRows, n);
+        for (int pass = 0; pass < L; ++pass) {
+            const int64_t row = r0 + static_cast<int64_t>(pass) * groups + group;
+            C sum = 0;
+            if (row < r1) {
+                const int64_t a = static_cast<int64_t>(rp[row]), b = static_cast<int64_t>(rp[row + 1]);
+                for (int64_t k = a + lane; k < b; k += L)
+                    sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(gx(static_cast<int64_t>(ci[k]))),
+                              sum);
+            }
+            for (int off = L >> 1; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+            if (row < r1 && lane == 0) epi.row(row, sum);
+        }
+    }
+}
+
+template <typename V, typename P, typename I, typename X, typename C, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmv_vector(int64_t n, const P *__restrict__ rp,
+                                                        const I *__restrict__ ci, const V *__restrict__ va,
+                                                        const X *__restrict__ x, int lanes_log2, int remap,
+                                                        int nt, Epi epi_in) {
+    Epi epi = epi_in;
+    if (epi.skip()) return;
+    spmv_tiles_vector<V, P, I, C>(n, rp, ci, va, PlainGather<X, C>{x}, lanes_log2, remap, nt, epi);
+    epi.finish();
+}
+
+template <class F>
+hipError_t dispatch_idx(const CsrDev &A, F &&f) {
+    if (A.ptr_t == 0) {
+        if (A.idx_t == 0) return f(static_cast<const int32_t *>(A.rp), static_cast<const int32_t *>(A.ci));
+        return f(static_cast<const int32_t *>(A.rp), static_cast<const int64_t *>(A.ci));
+    }
+    if (A.idx_t == 0) return f(static_cast<const int64_t *>(A.rp), static_cast<const int32_t *>(A.ci));
+    return f(static_cast<const int64_t *>(A.rp), static_cast<const int64_t *>(A.ci));
+}
+
+template <class Ptr>
+using pointee_t = std::remove_const_t<std::remove_pointer_t<Ptr>>;
+
+template <typename V, typename X, typename C, class Epi>
+hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const Epi &epi, hipStream_t s) {
+    if (A.n_rows == 0) return hipSuccess;
+    return dispatch_idx(A, [&](auto rp, auto ci) {
+        using P = pointee_t<decltype(rp)>;
+        using I = pointee_t<decltype(ci)>;
+        const V *va = static_cast<const V *>(A.va);
+        const dim3 grid(t.grid), block(kBlock);
+        if (t.kind == 0) {
+            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
+                               t.xcd_remap, t.nt, t.pf, epi);
+        } else {
+            hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
+                               t.lanes_log2, t.xcd_remap, t.nt, epi);
+        }
+        return hipGetLastError();
+    });
+}
+
+}  // namespace tile
+}  // namespace spk

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
-  python -m paper_2510_08230_amd.profsum stats  KERNEL_STATS_CSV --cmd "..."
+  python -m paper_2510_08230_amd.profsum stats  KERNEL_STATS_CSV [--trace KERNEL_TRACE_CSV] --cmd "..."
   python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B --cmd "..."
 
 ``stats`` renders the per-kernel duration table.  ``traffic`` reports the
@@ -19,7 +19,8 @@ import os
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_device.h", "csrc/spk_internal.h"]
+KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_krylov.hip", "csrc/spk_spmv.h", "csrc/spk_device.h",
+                  "csrc/spk_internal.h"]
 
 
 def kernel_digest() -> str:
@@ -42,6 +43,31 @@ def stats_md(path: str, cmd: str, top: int = 15) -> str:
         out.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (
             name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
             float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def working_launches_md(trace_csv: str, top: int = 8) -> str:
+    """Per kernel: launches that did work (duration >= 20% of the kernel's
+    longest; launches enqueued past convergence return at once), with their
+    mean and median duration, from a --kernel-trace CSV."""
+    durs = {}
+    for r in csv.DictReader(open(trace_csv)):
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        durs.setdefault(r["Kernel_Name"], []).append(d)
+    rows = []
+    for name, v in durs.items():
+        top_d = max(v)
+        w = [x for x in v if x >= 0.2 * top_d]
+        rows.append((sum(w), name, len(w), len(v), statistics.mean(w), statistics.median(w)))
+    rows.sort(reverse=True)
+    out = ["", "Launches that did work (duration >= 20% of the kernel's longest launch; launches enqueued",
+           "after convergence return at once and are left out):", "",
+           "| kernel | working / all launches | mean us | median us |", "|---|---|---|---|"]
+    for _, name, nw, na, mean, med in rows[:top]:
+        name = name.replace("(anonymous namespace)::", "").replace("|", "/")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        out.append("| %s | %d / %d | %.1f | %.1f |" % (name, nw, na, mean, med))
     return "\n".join(out) + "\n"
 
 
@@ -83,6 +109,7 @@ def main():
     sub = ap.add_subparsers(dest="what", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
+    s.add_argument("--trace", help="kernel-trace CSV of the same run: adds the working-launch table")
     s.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
@@ -93,6 +120,8 @@ def main():
     a = ap.parse_args()
     if a.what == "stats":
         print(stats_md(a.csv, a.cmd), end="")
+        if a.trace:
+            print(working_launches_md(a.trace), end="")
     else:
         d = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
         d["command"] = a.cmd

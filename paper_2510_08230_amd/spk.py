@@ -27,7 +27,8 @@ F64, F32, F16, BF16 = range(4)
 I32, I64 = range(2)
 CSR_OK, CSR_BAD_SIZE, CSR_BAD_FIRST, CSR_DECREASING, CSR_BAD_LAST, CSR_BAD_COLUMN = range(6)
 STOP_RUNNING, STOP_CONVERGED, STOP_MAX_ITERS, STOP_BREAKDOWN, STOP_NON_FINITE = range(5)
-SOLVER_CG = 0
+SOLVER_CG, SOLVER_CGS = 0, 1
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
 PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = range(3)
 EXEC_AUTO, EXEC_HOST_LOOP, EXEC_GRAPH, EXEC_PERSISTENT = range(4)
 
@@ -43,6 +44,12 @@ class Csr(ctypes.Structure):
                 ("ptr_type", ctypes.c_int32), ("idx_type", ctypes.c_int32), ("val_type", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
                 ("values", ctypes.c_void_p)]
+
+
+class Coo(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("idx_type", ctypes.c_int32), ("val_type", ctypes.c_int32), ("row_idx", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
 
 
 class SolverCfg(ctypes.Structure):
@@ -92,6 +99,8 @@ _SIGS = {
     "spk_csr_check": (ctypes.c_int, [_vp, _P(Csr), _P(_i32)]),
     "spk_partition": (ctypes.c_int, [_vp, _P(Csr), _i64, _vp]),
     "spk_plan_spmv": (ctypes.c_int, [_vp, _P(Csr), _P(_vp)]),
+    "spk_coo_check": (ctypes.c_int, [_vp, _P(Coo), _P(_i32), _P(_i32)]),
+    "spk_plan_spmv_coo": (ctypes.c_int, [_vp, _P(Coo), _P(_vp)]),
     "spk_plan_solve": (ctypes.c_int, [_vp, _P(Csr), _P(SolverCfg), _P(_vp)]),
     "spk_execute_spmv": (ctypes.c_int, [_vp, _vp, _vp]),
     "spk_execute_solve": (ctypes.c_int, [_vp, _vp, _vp, _P(Log)]),
@@ -171,6 +180,28 @@ class CsrMatrix:
         self.desc.values = _dev_ptr(values, "values") if values.numel() else None
 
 
+class CooMatrix:
+    """Device COO descriptor (entries sorted by row); keeps the borrowed tensors alive."""
+
+    def __init__(self, row_idx, col_idx, values, n_rows, n_cols):
+        self.tensors = (row_idx, col_idx, values)
+        if row_idx.dim() != 1 or col_idx.dim() != 1 or values.dim() != 1:
+            raise ValueError("COO arrays must be 1-D")
+        if not (row_idx.numel() == col_idx.numel() == values.numel()):
+            raise ValueError("row_idx, col_idx and values must have nnz entries each")
+        if row_idx.dtype != col_idx.dtype:
+            raise ValueError("row_idx and col_idx must share one index type")
+        self.desc = Coo()
+        self.desc.n_rows = int(n_rows)
+        self.desc.n_cols = int(n_cols)
+        self.desc.nnz = int(values.numel())
+        self.desc.idx_type = _TORCH_IDX[str(col_idx.dtype)]
+        self.desc.val_type = _TORCH_VAL[str(values.dtype)]
+        self.desc.row_idx = _dev_ptr(row_idx, "row_idx") if row_idx.numel() else None
+        self.desc.col_idx = _dev_ptr(col_idx, "col_idx") if col_idx.numel() else None
+        self.desc.values = _dev_ptr(values, "values") if values.numel() else None
+
+
 class Plan:
     def __init__(self, handle, ctx, matrix):
         self.handle = handle
@@ -210,6 +241,19 @@ def spk_partition(ctx: Context, A: CsrMatrix, parts: int, split):
 def spk_plan_spmv(ctx: Context, A: CsrMatrix) -> Plan:
     h = ctypes.c_void_p()
     _check(_lib.spk_plan_spmv(ctx.handle, ctypes.byref(A.desc), ctypes.byref(h)), ctx)
+    return Plan(h, ctx, A)
+
+
+def spk_coo_check(ctx: Context, A: CooMatrix):
+    """(verdict, row_sorted)."""
+    v, srt = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.spk_coo_check(ctx.handle, ctypes.byref(A.desc), ctypes.byref(v), ctypes.byref(srt)), ctx)
+    return v.value, bool(srt.value)
+
+
+def spk_plan_spmv_coo(ctx: Context, A: CooMatrix) -> Plan:
+    h = ctypes.c_void_p()
+    _check(_lib.spk_plan_spmv_coo(ctx.handle, ctypes.byref(A.desc), ctypes.byref(h)), ctx)
     return Plan(h, ctx, A)
 
 

@@ -136,6 +136,9 @@ def pin_coo_validate(orc):
     assert orc.coo_validate(4, 4, np.array([0, -1], np.int64), np.array([0, 0], np.int64))[0] == 2
     assert orc.coo_validate(-1, 4, r, c)[0] == 1
     assert orc.coo_validate(4, 4, r[:0], c[:0]) == (0, True)
+    # a bad column before a bad row: rows are checked first over all entries
+    assert orc.coo_validate(3, 3, np.array([0, 1, 3], np.int64), np.array([5, 0, 0], np.int64))[0] == 2
+    assert orc.coo_validate(4, 4, np.array([1, 1, 0, 2], np.int64), np.array([0, 1, 2, 3], np.int64)) == (0, False)
 
 
 def pin_csr_validate(orc):

@@ -41,11 +41,14 @@ PROBE = r"""
 #include "spk.h"
 #define P(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f));
 int main(void) {
-  printf("spk_csr %zu\nspk_solver_cfg %zu\nspk_log %zu\nspk_plan_info %zu\n",
-         sizeof(spk_csr), sizeof(spk_solver_cfg), sizeof(spk_log), sizeof(spk_plan_info));
+  printf("spk_csr %zu\nspk_solver_cfg %zu\nspk_log %zu\nspk_plan_info %zu\nspk_coo %zu\n",
+         sizeof(spk_csr), sizeof(spk_solver_cfg), sizeof(spk_log), sizeof(spk_plan_info), sizeof(spk_coo));
+  P(spk_coo, idx_type) P(spk_coo, row_idx) P(spk_coo, values)
   P(spk_csr, values) P(spk_csr, ptr_type) P(spk_solver_cfg, max_iters) P(spk_solver_cfg, reduction_factor)
   P(spk_solver_cfg, inner_reduction) P(spk_solver_cfg, max_outer) P(spk_log, elapsed_ms) P(spk_log, stop_reason)
   P(spk_plan_info, spmv_ms)
+  printf("SPK_SOLVER_CGS %d\nSPK_PRECOND_JACOBI %d\nSPK_EXEC_PERSISTENT %d\nSPK_PREC_MIXED_BF16 %d\n",
+         (int)SPK_SOLVER_CGS, (int)SPK_PRECOND_JACOBI, (int)SPK_EXEC_PERSISTENT, (int)SPK_PREC_MIXED_BF16);
   return 0;
 }
 """
@@ -62,15 +65,20 @@ def test_struct_layouts_match_header(tmp_path):
     assert int(got["spk_solver_cfg"]) == ctypes.sizeof(spk.SolverCfg)
     assert int(got["spk_log"]) == ctypes.sizeof(spk.Log)
     assert int(got["spk_plan_info"]) == ctypes.sizeof(spk.PlanInfo)
+    assert int(got["spk_coo"]) == ctypes.sizeof(spk.Coo)
     pairs = [("spk_csr.values", spk.Csr.values), ("spk_csr.ptr_type", spk.Csr.ptr_type),
              ("spk_solver_cfg.max_iters", spk.SolverCfg.max_iters),
              ("spk_solver_cfg.reduction_factor", spk.SolverCfg.reduction_factor),
              ("spk_solver_cfg.inner_reduction", spk.SolverCfg.inner_reduction),
              ("spk_solver_cfg.max_outer", spk.SolverCfg.max_outer),
              ("spk_log.elapsed_ms", spk.Log.elapsed_ms), ("spk_log.stop_reason", spk.Log.stop_reason),
-             ("spk_plan_info.spmv_ms", spk.PlanInfo.spmv_ms)]
+             ("spk_plan_info.spmv_ms", spk.PlanInfo.spmv_ms), ("spk_coo.idx_type", spk.Coo.idx_type),
+             ("spk_coo.row_idx", spk.Coo.row_idx), ("spk_coo.values", spk.Coo.values)]
     for key, field in pairs:
         assert int(got[key]) == field.offset, key
+    assert int(got["SPK_SOLVER_CGS"]) == spk.SOLVER_CGS and int(got["SPK_PRECOND_JACOBI"]) == spk.PRECOND_JACOBI
+    assert int(got["SPK_EXEC_PERSISTENT"]) == spk.EXEC_PERSISTENT
+    assert int(got["SPK_PREC_MIXED_BF16"]) == spk.PREC_MIXED_BF16
 
 
 def test_defaults_and_status_strings():

@@ -1,0 +1,270 @@
+"""CGS and Jacobi-preconditioned CG on the GPU against the FP64 oracle.
+
+Stated tolerances (FP64; diagonally dominant inputs, delta = 1 unless noted):
+  * fixed-K iterates (stop test off): ||x_K - x_K^orc|| / ||x_K^orc|| <= 1e-12
+  * converged solves: ||x - x^orc|| / ||x^orc|| <= 1e-12, iterations within +-1,
+    recurrence residual history within 1% per iteration
+  * closed forms (diagonal A) to rounding.
+Derivation: a 1-ulp relative perturbation of b moves the oracle's own CGS
+iterates by at most 4e-15 (relative) over 20 iterations of stencil7_ns N=46
+and its residual history by at most 4e-9, so a reordering of the sums and
+fused multiply-adds on the GPU, which perturb each step at the ulp level,
+stay far inside these bounds; PCG inherits CG's bounds.
+The two paths sum in different orders, so they agree to rounding, not
+bitwise; runs of the GPU path are bitwise reproducible."""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+from tests.gpu_util import dev_csr, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spk():
+    from paper_2510_08230_amd import spk as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(spk):
+    c = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    yield c
+    spk.spk_finalize(c)
+
+
+def solve(spk, ctx, A, b, solver, precond=0, x0=None, tau=1e-14, max_iters=1000, mode=0, history=False,
+          chunk=0, M=None):
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = solver
+    cfg.precond = precond
+    cfg.reduction_factor = tau
+    cfg.max_iters = max_iters
+    cfg.exec_mode = mode
+    cfg.record_history = 1 if history else 0
+    cfg.chunk_iters = chunk
+    M = M if M is not None else dev_csr(spk, A)
+    pl = spk.spk_plan_solve(ctx, M, cfg)
+    x = to_dev(np.zeros(A.n_rows) if x0 is None else x0)
+    log = spk.spk_execute_solve(pl, to_dev(b), x)
+    hist = spk.spk_plan_history(pl) if history else None
+    spk.spk_free(pl)
+    return x.cpu().numpy(), log, hist
+
+
+def cgs(spk, ctx, A, b, **kw):
+    return solve(spk, ctx, A, b, spk.SOLVER_CGS, **kw)
+
+
+def pcg(spk, ctx, A, b, **kw):
+    return solve(spk, ctx, A, b, spk.SOLVER_CG, spk.PRECOND_JACOBI, **kw)
+
+
+def scaled_spd(n, seed):
+    """S A S (S positive diagonal, entries 1..8): SPD with a strongly varying diagonal."""
+    A = inputs.randsym(n, seed, delta=0.5)
+    s = np.array([2.0 ** (inputs.unif(seed, 18, i) * 3) for i in range(n)])
+    rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+    return inputs.CSR(n, n, A.row_ptr.copy(), A.col.copy(), A.val * s[rows] * s[A.col.astype(np.int64)])
+
+
+NS = {"stencil7ns_46": lambda: inputs.stencil7_ns(46, 0),
+      "stencil7ns_20_d0.2": lambda: inputs.stencil7_ns(20, 1, delta=0.2),
+      "randsym_3e4": lambda: inputs.randsym(30000, 2)}
+SPD = {"stencil7_46": lambda: inputs.stencil7(46, 0), "scaled_randsym_5e4": lambda: scaled_spd(50000, 3)}
+
+
+# ----------------------------------------------------------------- CGS
+@pytest.mark.parametrize("name", sorted(NS))
+@pytest.mark.parametrize("K", [1, 3, 10])
+def test_cgs_fixed_k_iterates(spk, ctx, name, K):
+    A = NS[name]()
+    b = inputs.rhs(A.n_rows, 1)
+    x, log, _ = cgs(spk, ctx, A, b, tau=0.0, max_iters=K)
+    xo, ro, _ = oracle.cgs(A, b, tau=0.0, max_iters=K)
+    assert log.iterations == K and log.stop_reason == spk.STOP_MAX_ITERS
+    assert rel(x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(NS))
+@pytest.mark.parametrize("mode,chunk", [(1, 0), (2, 0), (1, 3)])
+def test_cgs_converged_parity(spk, ctx, name, mode, chunk):
+    A = NS[name]()
+    b = inputs.rhs(A.n_rows, 2)
+    x, log, hist = cgs(spk, ctx, A, b, tau=1e-12, mode=mode, chunk=chunk, history=True)
+    xo, ro, ho = oracle.cgs(A, b, tau=1e-12, history=True)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert rel(x, xo) <= 1e-12
+    k = min(hist.size, ho.size)
+    assert np.all(np.abs(hist[:k] - ho[:k]) <= 0.01 * ho[:k])
+    assert abs(log.rhs_norm - ro.rhs_norm) <= 1e-14 * ro.rhs_norm
+    assert log.true_resnorm <= 10 * 1e-12 * log.rhs_norm
+    # the true residual recomputed by the oracle's SpMV from the GPU's x
+    assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-12 * log.rhs_norm
+
+
+def test_cgs_nonzero_guess_and_reruns_bitwise(spk, ctx):
+    A = inputs.stencil7_ns(30, 4)
+    b = inputs.rhs(A.n_rows, 4)
+    x0 = inputs.vec(A.n_rows, 4, 20)
+    runs = [cgs(spk, ctx, A, b, x0=x0, tau=1e-12, mode=m, chunk=c) for m, c in ((1, 0), (2, 0), (1, 5), (2, 3))]
+    for x, log, _ in runs[1:]:
+        assert np.array_equal(x.view(np.uint64), runs[0][0].view(np.uint64))
+        assert log.iterations == runs[0][1].iterations
+    xo, ro, _ = oracle.cgs(A, b, x0=x0, tau=1e-12)
+    assert abs(runs[0][1].iterations - ro.iterations) <= 1 and rel(runs[0][0], xo) <= 1e-12
+
+
+def test_cgs_diag_distinct_terminates(spk, ctx):
+    d = np.repeat(np.array([1.0, 2.5, 4.0, 7.0]), 300)
+    b = np.array([inputs.unif(6, 17, i) for i in range(d.size)])
+    x, log, _ = cgs(spk, ctx, inputs.diagonal(d), b, tau=1e-12, max_iters=50)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 4
+    assert rel(x, b / d) <= 1e-12
+
+
+def test_cgs_stop_semantics(spk, ctx):
+    A = inputs.stencil7_ns(8, 3)
+    b = inputs.rhs(A.n_rows, 3)
+    x0 = inputs.vec(A.n_rows, 3, 21)
+    x, log, h = cgs(spk, ctx, A, b, x0=x0, max_iters=0, history=True)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 0 and np.array_equal(x, x0)
+    x, log, _ = cgs(spk, ctx, A, np.zeros(A.n_rows), x0=x0, max_iters=10)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 0 and not x.any()
+    x, log, _ = cgs(spk, ctx, A, b, tau=1e-15, max_iters=3)
+    xo, ro, _ = oracle.cgs(A, b, tau=1e-15, max_iters=3)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 3 and rel(x, xo) <= 1e-12
+    # rt . A r0 = 0 on the first step (skew-symmetric blocks): breakdown, x untouched
+    S = inputs.from_dense(np.kron(np.eye(64), np.array([[0.0, 1.0], [-1.0, 0.0]])))
+    x, log, _ = cgs(spk, ctx, S, np.ones(128), max_iters=10)
+    _, ro, _ = oracle.cgs(S, np.ones(128), max_iters=10)
+    assert log.stop_reason == ro.stop_reason == spk.STOP_BREAKDOWN and log.iterations == 0 and not x.any()
+    bb = b.copy()
+    bb[5] = np.inf
+    _, log, _ = cgs(spk, ctx, A, bb, max_iters=10)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+
+
+def test_cgs_plan_errors(spk, ctx):
+    A = inputs.stencil7_ns(6, 0)
+    M = dev_csr(spk, A)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = spk.SOLVER_CGS
+    cfg.precond = spk.PRECOND_JACOBI
+    with pytest.raises(spk.SpkError):
+        spk.spk_plan_solve(ctx, M, cfg)
+    cfg.precond = spk.PRECOND_NONE
+    cfg.precision = spk.PREC_MIXED_FP32
+    with pytest.raises(spk.SpkError):
+        spk.spk_plan_solve(ctx, M, cfg)
+    cfg.precision = spk.PREC_FP64
+    cfg.solver = 7
+    with pytest.raises(spk.SpkError):
+        spk.spk_plan_solve(ctx, M, cfg)
+
+
+# ----------------------------------------------------------------- Jacobi PCG
+@pytest.mark.parametrize("name", sorted(SPD))
+@pytest.mark.parametrize("K", [1, 5, 30])
+def test_pcg_fixed_k_iterates(spk, ctx, name, K):
+    A = SPD[name]()
+    b = inputs.rhs(A.n_rows, 5)
+    x, log, _ = pcg(spk, ctx, A, b, tau=0.0, max_iters=K)
+    xo, ro, _ = oracle.pcg_jacobi(A, b, tau=0.0, max_iters=K)
+    assert log.iterations == K and log.stop_reason == spk.STOP_MAX_ITERS
+    assert rel(x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(SPD))
+@pytest.mark.parametrize("mode", [1, 2])
+def test_pcg_converged_parity(spk, ctx, name, mode):
+    A = SPD[name]()
+    b = inputs.rhs(A.n_rows, 6)
+    x, log, hist = pcg(spk, ctx, A, b, mode=mode, history=True)
+    xo, ro, ho = oracle.pcg_jacobi(A, b, tau=1e-14, history=True)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert rel(x, xo) <= 1e-12
+    k = min(hist.size, ho.size)
+    assert np.all(np.abs(hist[:k] - ho[:k]) <= 0.01 * ho[:k])
+    assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-14 * log.rhs_norm
+
+
+def test_pcg_fewer_iterations_than_cg_on_scaled_matrix(spk, ctx):
+    A = scaled_spd(50000, 3)
+    b = inputs.rhs(A.n_rows, 7)
+    _, lp, _ = pcg(spk, ctx, A, b, tau=1e-10)
+    _, lc, _ = solve(spk, ctx, A, b, spk.SOLVER_CG, tau=1e-10, max_iters=5000)   # ~1.8e3 needed
+    _, ro, _ = oracle.pcg_jacobi(A, b, tau=1e-10)
+    assert lp.stop_reason == lc.stop_reason == spk.STOP_CONVERGED
+    assert abs(lp.iterations - ro.iterations) <= 1 and lp.iterations < lc.iterations
+
+
+def test_pcg_diagonal_one_step(spk, ctx):
+    d = np.array([1.0, 3.0, 0.25, 8.0, 2.0, 5.5] * 200)
+    b = np.array([inputs.unif(7, 19, i) for i in range(d.size)])
+    x, log, _ = pcg(spk, ctx, inputs.diagonal(d), b, max_iters=10)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 1
+    assert rel(x, b / d) <= 1e-15
+
+
+def test_pcg_unusable_diagonal_and_stop_semantics(spk, ctx):
+    d = np.ones(700)
+    d[333] = 0.0
+    x0 = inputs.vec(700, 8, 22)
+    x, log, _ = pcg(spk, ctx, inputs.diagonal(d), np.ones(700), x0=x0, max_iters=10)
+    _, ro, _ = oracle.pcg_jacobi(inputs.diagonal(d), np.ones(700), x0=x0, max_iters=10)
+    assert log.stop_reason == ro.stop_reason == spk.STOP_BREAKDOWN and log.iterations == 0
+    assert np.array_equal(x, x0)
+    A = inputs.stencil7(9, 1)
+    b = inputs.rhs(A.n_rows, 1)
+    x1 = inputs.vec(A.n_rows, 9, 22)
+    x, log, _ = pcg(spk, ctx, A, b, x0=x1, max_iters=0)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 0 and np.array_equal(x, x1)
+    x, log, _ = pcg(spk, ctx, A, np.zeros(A.n_rows), x0=x1)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 0 and not x.any()
+    # indefinite with a positive diagonal: p.q < 0 on the first step
+    I2 = inputs.from_dense(np.kron(np.eye(50), np.array([[1.0, 2.0], [2.0, 1.0]])))
+    bb = np.tile([1.0, -1.0], 50)
+    _, log, _ = pcg(spk, ctx, I2, bb)
+    assert log.stop_reason == spk.STOP_BREAKDOWN and log.iterations == 0
+
+
+# ----------------------------------------------------------------- full size
+def test_cgs_full_size_residual():
+    """Nonsymmetric stencil7 N=215 (the FP64 CG workload's pattern and size): the converged
+    GPU solution's true residual, recomputed by the oracle's SpMV, meets the criterion, and the
+    first two iterates match the oracle's."""
+    from paper_2510_08230_amd import spk
+    ctx = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        A = inputs.stencil7_ns(215, 1)
+        b = inputs.rhs(A.n_rows, 1)
+        M = dev_csr(spk, A, ptr="i32")
+        x, log, _ = cgs(spk, ctx, A, b, tau=1e-12, M=M)
+        assert log.stop_reason == spk.STOP_CONVERGED
+        assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-12 * log.rhs_norm
+        x2, _, _ = cgs(spk, ctx, A, b, tau=0.0, max_iters=2, M=M)
+        xo, _, _ = oracle.cgs(A, b, tau=0.0, max_iters=2)
+        assert rel(x2, xo) <= 1e-12
+    finally:
+        spk.spk_finalize(ctx)
+
+
+def test_pcg_full_size_residual():
+    from paper_2510_08230_amd import spk
+    ctx = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        A = inputs.stencil7(215, 1)
+        b = inputs.rhs(A.n_rows, 1)
+        M = dev_csr(spk, A, ptr="i32")
+        x, log, _ = pcg(spk, ctx, A, b, tau=1e-14, M=M)
+        assert log.stop_reason == spk.STOP_CONVERGED
+        assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-14 * log.rhs_norm
+        x2, _, _ = pcg(spk, ctx, A, b, tau=0.0, max_iters=2, M=M)
+        xo, _, _ = oracle.pcg_jacobi(A, b, tau=0.0, max_iters=2)
+        assert rel(x2, xo) <= 1e-12
+    finally:
+        spk.spk_finalize(ctx)

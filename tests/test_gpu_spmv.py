@@ -14,8 +14,8 @@ from tests.gpu_util import DEV, U32, U64, dev_csr, gamma, to_dev
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["stream", "stream-noremap", "stream,remap=3", "stream,remap=64", "vector:1", "vector:4", "vector:8",
-           "vector:64", "vector:8,remap=16", ""]
+KERNELS = ["stream", "stream-noremap", "stream,remap=3", "stream,remap=64", "stream,nt=1,remap=64,bpc=5",
+           "stream,pf=0,nt=1", "vector:1", "vector:4", "vector:8", "vector:64", "vector:8,remap=16", ""]
 
 
 @pytest.fixture(scope="module")

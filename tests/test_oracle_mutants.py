@@ -58,8 +58,11 @@ MUTANTS = [
      "if (row[k] < 0 || row[k] > n_rows) return ORC_CSR_BAD_FIRST;", "int orc_coo_validate("),
     ("coo column bound", "if (col[k] < 0 || col[k] >= n_cols) return ORC_CSR_BAD_COLUMN;",
      "if (col[k] < 0 || col[k] > n_cols) return ORC_CSR_BAD_COLUMN;", "int orc_coo_validate("),
-    ("coo sortedness strict", "if (k > 0 && row[k] < row[k - 1]) *row_sorted = 0;",
-     "if (k > 0 && row[k] <= row[k - 1]) *row_sorted = 0;", "int orc_coo_validate("),
+    ("coo sortedness strict", "if (row[k] < row[k - 1]) *row_sorted = 0;",
+     "if (row[k] <= row[k - 1]) *row_sorted = 0;", "int orc_coo_validate("),
+    ("coo check order", "if (row[k] < 0 || row[k] >= n_rows) return ORC_CSR_BAD_FIRST;\n    for",
+     "if (row[k] < 0 || row[k] >= n_rows) return ORC_CSR_BAD_FIRST;\n    for (int64_t k = 0; k < 0; ++k)\n    for",
+     "int orc_coo_validate("),
     # CGS
     ("cgs beta transposed", "const double beta = rho / rho_prev;", "const double beta = rho_prev / rho;",
      "int orc_cgs("),
