@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="large instance: stencil7 N=1048 generated on the device, FP32-exact values, "
                          "int64 row_ptr, FP32 CG + FP64 refinement")
+    ap.add_argument("--spmv", choices=["csr", "coo"], default=None,
+                    help="standalone SpMV mode y = A x (stencil7 N, seed): GFLOP/s at 2 nnz per product")
+    ap.add_argument("--values", choices=["fp32", "fp64"], default="fp32", help="SpMV mode value/vector type")
     ap.add_argument("--exec", choices=["auto", "host", "graph"], default="host",
                     help="iteration driver: host loop, captured graphs, or the plan's choice")
     return ap.parse_args()
@@ -90,6 +93,9 @@ def main():
         return
     if args.large:
         large(args)
+        return
+    if args.spmv:
+        spmv_mode(args)
         return
 
     import numpy as np
@@ -219,6 +225,88 @@ def main():
                                "kind": "oracle",
                                "sample": "FP64 oracle %s, same system, %d iterations (plus initial and "
                                          "true residual), %.1f s" % (label, res.iterations, dt)}
+    print(json.dumps(out), flush=True)
+
+
+def spmv_mode(args):
+    """y = A x on stencil7 N (default 215), FP32 (the paper's SpMV benchmark type) or FP64
+    values and vectors, CSR or row-sorted COO input.  A step is one product; the plan
+    (validation, COO row pointer, tuning) is made once, outside the timed region."""
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2510_08230_amd import spk
+
+    dev = torch.device("cuda:0")
+    N = args.N
+    A = inputs.stencil7(N, args.seed)
+    n, nnz = A.n_rows, A.nnz
+    vt = torch.float32 if args.values == "fp32" else torch.float64
+    vb = 4 if args.values == "fp32" else 8
+    x_h = inputs.vec(n, args.seed, 5)
+    if args.values == "fp32":
+        x_h = x_h.astype(np.float32).astype(np.float64)
+    va = torch.from_numpy(A.val).to(vt).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    if args.spmv == "csr":
+        M = spk.CsrMatrix(torch.from_numpy(A.row_ptr).to(torch.int32).to(dev), ci, va, n, n)
+    else:
+        rows = torch.from_numpy(np.repeat(np.arange(n, dtype=np.int32), np.diff(A.row_ptr))).to(dev)
+        M = spk.CooMatrix(rows, ci, va, n, n)
+    x = torch.from_numpy(x_h).to(vt).to(dev)
+    y = torch.empty(n, dtype=vt, device=dev)
+    ctx = spk.spk_init(0, torch.cuda.current_stream(dev).cuda_stream)
+    pl = spk.spk_plan_spmv(ctx, M) if args.spmv == "csr" else spk.spk_plan_spmv_coo(ctx, M)
+    info = spk.spk_plan_get_info(pl)
+    for _ in range(max(args.warmup, 1)):
+        spk.spk_execute_spmv(pl, x, y)
+    spk.spk_plan_set_profiling(pl, not args.no_profile)
+    steps = max(args.steps, 1) * 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        spk.spk_execute_spmv(pl, x, y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, cnt = spk.spk_plan_kernel_stats(pl)
+    spk.spk_free(pl)
+    spk.spk_finalize(ctx)
+    # CSR tiles read the derived row pointer for COO too: (n+1) int32
+    bytes_spmv = nnz * (vb + 4) + (n + 1) * 4 + 2 * n * vb
+    avg_ms = kms / cnt if cnt else None
+    achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
+    out = {
+        "metric": "SpMV GFLOP/s (2 nnz per product), 1 MI355X",
+        "value": 2.0 * nnz * steps / wall / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": steps, "warmup": max(args.warmup, 1),
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.values == "fp32" else "f64",
+        "data": "synthetic (seeded stencil7, uniform[-1,1) values; x uniform[-1,1))",
+        "config": {"workload": "spmv_%s_%s_stencil7_N%d" % (args.spmv, args.values, N), "n": n, "nnz": nnz,
+                   "format": args.spmv, "index_types": "int32", "spmv_tiling": info,
+                   "kernel_gflops": 2.0 * nnz / (avg_ms * 1e-3) / 1e9 if avg_ms else None},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPlain>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": cnt},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        reps = 3
+        t0 = time.perf_counter()
+        if args.spmv == "csr":
+            for _ in range(reps):
+                oracle.spmv(A, x_h)
+        else:
+            rows_h = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+            for _ in range(reps):
+                oracle.coo_spmv(n, rows_h, A.col, A.val, x_h)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 2.0 * nnz * reps / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle %s product, same matrix, %d products, %.1f s"
+                                         % (args.spmv.upper(), reps, dt)}
     print(json.dumps(out), flush=True)
 
 
