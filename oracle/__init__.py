@@ -12,8 +12,9 @@ Hestenes-Stiefel CG (the CG solver benchmarked in Section 6.2) with the
 Iteration / ResidualNorm(rhs_norm) criteria of the Section 3.5 configuration
 example, CGS (the other Krylov solver of Section 6.2, Barrett et al.
 template), CG with the scalar Jacobi preconditioner of the Section 3.5
-example (Saad Alg. 9.1), the nnz-balanced row partition and the Gershgorin
-condition bound.
+example (Saad Alg. 9.1), restarted GMRES(m) with modified Gram-Schmidt and
+Givens rotations (the solver of the Section 3.5 listings; Saad Alg. 6.9),
+the nnz-balanced row partition and the Gershgorin condition bound.
 """
 from __future__ import annotations
 
@@ -67,6 +68,8 @@ def load(path: str = _LIB):
     lib.orc_cgs.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
     lib.orc_pcg_jacobi.restype = ctypes.c_int
     lib.orc_pcg_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_gmres.restype = ctypes.c_int
+    lib.orc_gmres.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, i64, ctypes.POINTER(CGResult), vp]
     lib.orc_diagonal.restype = None
     lib.orc_diagonal.argtypes = [i64, vp, vp, vp, vp]
     lib.orc_coo_spmv.restype = None
@@ -175,6 +178,20 @@ class Oracle:
         """CG preconditioned by diag(A).  Returns (x, CGResult, hist or None)."""
         return self._krylov(self.lib.orc_pcg_jacobi, A, b, x0, tau, max_iters, history)
 
+    def gmres(self, A, b, x0=None, tau=1e-14, max_iters=10000, m=30, history=False):
+        """Restarted GMRES(m), MGS Arnoldi, Givens rotations.  Returns (x, CGResult, hist or None)."""
+        rp, ci, va = _csr64(A)
+        n = A.n_rows
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
+        res = CGResult()
+        hist = np.full(max_iters + 1, np.nan) if history else None
+        self.lib.orc_gmres(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tau), int(max_iters), int(m),
+                           ctypes.byref(res), _p(hist))
+        if hist is not None:
+            hist = hist[: res.iterations + 1]
+        return x, res, hist
+
     def diagonal(self, A) -> np.ndarray:
         rp, ci, va = _csr64(A)
         d = np.empty(A.n_rows, np.float64)
@@ -236,6 +253,10 @@ def pcg_jacobi(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
 
 def diagonal(A):
     return default().diagonal(A)
+
+
+def gmres(A, b, x0=None, tau=1e-14, max_iters=10000, m=30, history=False):
+    return default().gmres(A, b, x0, tau, max_iters, m, history)
 
 
 def csr_validate(n_rows, n_cols, nnz, row_ptr, col):

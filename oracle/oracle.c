@@ -31,6 +31,11 @@
  *  - The SpMV benchmark also runs on the coordinate (COO) format (Section
  *    6.1); the oracle's COO product is its definition, accumulated in
  *    storage order.
+ *  - GMRES is the solver of the paper's usage examples (Listings 1-2, with a
+ *    Krylov dimension) and of its solver benchmarks (Section 6.2); the
+ *    oracle takes textbook restarted GMRES(m) with modified Gram-Schmidt and
+ *    Givens rotations, tests the rotation residual estimate after every
+ *    Arnoldi step and the true residual at each restart.
  *  - The scalar Jacobi preconditioner appears in the configuration example
  *    (Section 3.5, Listing 2, block size 1); the oracle applies it as
  *    z = r / diag(A) inside textbook PCG (Saad, Alg. 9.1) and keeps the stop
@@ -406,6 +411,128 @@ done:
         res->true_resnorm = (n > 0) ? NAN : 0.0;
     }
     free(r); free(z); free(p); free(q); free(d);
+    return reason;
+}
+
+/*
+ * Restarted GMRES(m), unpreconditioned (Saad, Alg. 6.9 with the Givens
+ * rotations of Sec. 6.5.3; Arnoldi by modified Gram-Schmidt).  Same argument
+ * conventions and stop reasons as orc_cg; `iterations` counts Arnoldi steps
+ * over all cycles and hist[k] holds the residual-norm estimate |g_{k}|
+ * after step k (hist[0] = ||r_0||).  Each cycle:
+ *
+ *   r = b - A x, beta = ||r||  (stop here if beta <= tau ||b||)
+ *   v_0 = r / beta, g = beta e_0
+ *   for j = 0 .. m-1:
+ *     w = A v_j;  for i = 0..j: h_ij = w.v_i, w -= h_ij v_i;  h_{j+1,j} = ||w||
+ *     rotate column j by the earlier rotations, then zero h_{j+1,j} with a new
+ *     one (c, s) = (h_jj, h_{j+1,j}) / hypot(h_jj, h_{j+1,j}); g_{j+1} = -s g_j,
+ *     g_j = c g_j;  stop the cycle if |g_{j+1}| <= tau ||b||, the cap is
+ *     reached or h_{j+1,j} = 0;  v_{j+1} = w / h_{j+1,j}
+ *   solve the triangular R y = g over the columns used;  x += V y
+ *
+ * The triangular solve uses the columns built in the cycle (a cap in the
+ * middle of a cycle still updates x).
+ */
+int orc_gmres(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+              const double *b, double *x, double tau, int64_t max_iters, int64_t m,
+              orc_cg_result *res, double *hist) {
+    if (m < 1) m = 1;
+    const size_t vb = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *V = (double *)malloc(vb * (size_t)(m + 1));
+    double *w = (double *)malloc(vb);
+    double *H = (double *)calloc((size_t)((m + 1) * m), sizeof(double));   /* H[i * m + j] */
+    double *cs = (double *)malloc(sizeof(double) * (size_t)m);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)m);
+    double *g = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+    double *y = (double *)malloc(sizeof(double) * (size_t)m);
+    int64_t k = 0;
+    int reason = ORC_RUNNING;
+    double resnorm = 0.0;
+    const double bnorm = sqrt(dot(n, b, b));
+    res->rhs_norm = bnorm;
+
+    if (!isfinite(bnorm)) {
+        reason = ORC_NON_FINITE;
+        resnorm = bnorm;
+        goto done;
+    }
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        reason = ORC_CONVERGED;
+        resnorm = 0.0;
+        if (hist) hist[0] = 0.0;
+        goto done;
+    }
+    while (reason == ORC_RUNNING) {
+        orc_residual(n, row_ptr, col, val, b, x, V);
+        const double beta = sqrt(dot(n, V, V));
+        resnorm = beta;
+        if (k == 0 && hist) hist[0] = beta;
+        if (!isfinite(beta)) { reason = ORC_NON_FINITE; break; }
+        if (beta <= tau * bnorm) { reason = ORC_CONVERGED; break; }
+        if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }
+        for (int64_t i = 0; i < n; ++i) V[i] = V[i] / beta;
+        for (int64_t i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int64_t used = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            const double *vj = V + (size_t)j * (size_t)n;
+            orc_spmv(n, row_ptr, col, val, vj, w);
+            for (int64_t i = 0; i <= j; ++i) {
+                const double *vi = V + (size_t)i * (size_t)n;
+                const double h = dot(n, w, vi);
+                H[i * m + j] = h;
+                for (int64_t t = 0; t < n; ++t) w[t] = w[t] - h * vi[t];
+            }
+            const double hnext = sqrt(dot(n, w, w));
+            for (int64_t i = 0; i < j; ++i) {
+                const double a = H[i * m + j], c = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            const double a = H[j * m + j];
+            const double d = hypot(a, hnext);
+            if (d == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+            else { cs[j] = a / d; sn[j] = hnext / d; }
+            H[j * m + j] = cs[j] * a + sn[j] * hnext;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k += 1;
+            used = j + 1;
+            resnorm = fabs(g[j + 1]);
+            if (hist) hist[k] = resnorm;
+            if (!isfinite(resnorm)) { reason = ORC_NON_FINITE; break; }
+            if (resnorm <= tau * bnorm) { reason = ORC_CONVERGED; break; }
+            if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }
+            if (hnext == 0.0) break;
+            double *vn = V + (size_t)(j + 1) * (size_t)n;
+            for (int64_t t = 0; t < n; ++t) vn[t] = w[t] / hnext;
+        }
+        if (reason == ORC_NON_FINITE) break;
+        for (int64_t i = used - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int64_t t = i + 1; t < used; ++t) s -= H[i * m + t] * y[t];
+            y[i] = s / H[i * m + i];
+        }
+        for (int64_t i = 0; i < used; ++i) {
+            const double *vi = V + (size_t)i * (size_t)n;
+            for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y[i] * vi[t];
+        }
+    }
+
+done:
+    res->iterations = k;
+    res->stop_reason = reason;
+    res->implicit_resnorm = resnorm;
+    if (reason != ORC_NON_FINITE && n > 0) {
+        orc_residual(n, row_ptr, col, val, b, x, w);
+        res->true_resnorm = sqrt(dot(n, w, w));
+    } else {
+        res->true_resnorm = (n > 0) ? NAN : 0.0;
+    }
+    free(V); free(w); free(H); free(cs); free(sn); free(g); free(y);
     return reason;
 }
 

@@ -441,6 +441,95 @@ def pin_cgs_stop_semantics(orc):
     assert r.stop_reason == 4
 
 
+# ----------------------------------------------------------------- GMRES
+def _lsq_step(D, x0, b, k):
+    """x0 + argmin over K_k(A, r0) of ||b - A x||, from an orthonormal Krylov basis (dense QR)."""
+    r0 = b - D @ x0
+    K = np.column_stack([np.linalg.matrix_power(D, j) @ r0 for j in range(k)])
+    Q, _ = np.linalg.qr(K)
+    y, *_ = np.linalg.lstsq(D @ Q, r0, rcond=None)
+    return x0 + Q @ y
+
+
+def pin_gmres_krylov_least_squares(orc):
+    """Every iterate of the first cycle minimises ||b - A x|| over x0 + K_k(A, r0)
+    (dense least squares), and the recorded estimate equals that minimum."""
+    A, D = _ns_dense(3, 5)
+    b = inputs.rhs(A.n_rows, 5)
+    x0 = inputs.vec(A.n_rows, 5, 20)
+    for k in range(1, 7):
+        xr = _lsq_step(D, x0, b, k)
+        x, r, h = orc.gmres(A, b, x0=x0, tau=0.0, max_iters=k, m=30, history=True)
+        assert r.iterations == k and r.stop_reason == 2
+        assert _rel(x, xr) <= 1e-9, (k, _rel(x, xr))
+        assert abs(h[k] - np.linalg.norm(b - D @ xr)) <= 1e-9 * np.linalg.norm(b)
+
+
+def pin_gmres_restart(orc):
+    """GMRES(2): the third step restarts from x_2 and minimises over x_2 + K_1(A, r_2);
+    a cap in the middle of a cycle still applies the columns built so far."""
+    A, D = _ns_dense(3, 6)
+    b = inputs.rhs(A.n_rows, 6)
+    x0 = np.zeros(A.n_rows)
+    x2 = _lsq_step(D, x0, b, 2)
+    x3 = _lsq_step(D, x2, b, 1)
+    x5 = _lsq_step(D, _lsq_step(D, x2, b, 2), b, 1)
+    x, r, _ = orc.gmres(A, b, tau=0.0, max_iters=3, m=2)
+    assert r.iterations == 3 and _rel(x, x3) <= 1e-9
+    x, r, _ = orc.gmres(A, b, tau=0.0, max_iters=5, m=2)
+    assert r.iterations == 5 and _rel(x, x5) <= 1e-9
+
+
+def pin_gmres_diag_distinct_and_dense(orc):
+    """Diagonal A with 5 distinct eigenvalues: converged at step 5, not before; nonsymmetric
+    systems converge to numpy.linalg.solve within cond * tau."""
+    d = np.repeat(np.array([1.0, 2.0, 3.5, 6.0, 9.0]), 3)
+    b = np.array([inputs.unif(8, 28, i) for i in range(d.size)])
+    x, r, h = orc.gmres(inputs.diagonal(d), b, tau=1e-12, max_iters=50, m=30, history=True)
+    assert r.stop_reason == 1 and r.iterations == 5 and np.all(h[:5] > 1e-12 * np.linalg.norm(b))
+    assert _rel(x, b / d) <= 1e-12
+    for seed in range(2):
+        A, D = _ns_dense(4, seed, delta=0.5)
+        bb = inputs.rhs(A.n_rows, seed)
+        for m in (30, 4):
+            x, r, _ = orc.gmres(A, bb, tau=1e-10, max_iters=2000, m=m)
+            assert r.stop_reason == 1 and r.true_resnorm <= 2e-10 * r.rhs_norm
+            assert _rel(x, np.linalg.solve(D, bb)) <= 10 * np.linalg.cond(D) * 1e-10
+
+
+def pin_gmres_scipy(orc):
+    """scipy.sparse.linalg.gmres (independent code, restart m) reaches the same solution."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    A, D = _ns_dense(5, 3, delta=0.3)
+    b = inputs.rhs(A.n_rows, 3)
+    S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n_rows, A.n_cols))
+    xs, info = spla.gmres(S, b, rtol=1e-11, atol=0.0, restart=10, maxiter=500)
+    x, r, _ = orc.gmres(A, b, tau=1e-11, max_iters=5000, m=10)
+    assert info == 0 and r.stop_reason == 1
+    assert _rel(x, xs) <= 10 * np.linalg.cond(D) * 1e-11
+
+
+def pin_gmres_stop_semantics(orc):
+    A, D = _ns_dense(2, 7)
+    n = A.n_rows
+    b = inputs.rhs(n, 7)
+    x0 = inputs.vec(n, 7, 21)
+    x, r, h = orc.gmres(A, b, x0=x0, tau=1e-12, max_iters=0, history=True)
+    assert r.stop_reason == 2 and r.iterations == 0 and np.array_equal(x, x0)
+    r0 = np.linalg.norm(b - D @ x0)
+    assert abs(h[0] - r0) <= 1e-14 * r0
+    x, r, _ = orc.gmres(A, np.zeros(n), x0=x0, tau=1e-12)
+    assert r.stop_reason == 1 and r.iterations == 0 and not x.any()
+    xs = np.linalg.solve(D, b)
+    _, r, _ = orc.gmres(A, D @ xs, x0=xs, tau=1e-12)
+    assert r.stop_reason == 1 and r.iterations == 0
+    bb = b.copy()
+    bb[0] = np.nan
+    _, r, _ = orc.gmres(A, bb, tau=1e-12)
+    assert r.stop_reason == 4
+
+
 # ----------------------------------------------------------------- Jacobi PCG
 def _scaled_spd(n, seed):
     """S A S with S a positive diagonal: SPD with a strongly varying diagonal."""

@@ -82,6 +82,27 @@ MUTANTS = [
     ("cgs cap off by one", "if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }",
      "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }", "int orc_cgs("),
     ("cgs history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "int orc_cgs("),
+    # GMRES
+    ("gmres projection sign", "for (int64_t t = 0; t < n; ++t) w[t] = w[t] - h * vi[t];",
+     "for (int64_t t = 0; t < n; ++t) w[t] = w[t] + h * vi[t];", "int orc_gmres("),
+    ("gmres projection uses v_j", "const double h = dot(n, w, vi);", "const double h = dot(n, w, vj);",
+     "int orc_gmres("),
+    ("gmres old rotations skipped", "for (int64_t i = 0; i < j; ++i) {\n                const double a",
+     "for (int64_t i = 0; i < 0; ++i) {\n                const double a", "int orc_gmres("),
+    ("gmres rotation sign", "H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;", "H[(i + 1) * m + j] = sn[i] * a + cs[i] * c;",
+     "int orc_gmres("),
+    ("gmres g update sign", "g[j + 1] = -sn[j] * g[j];", "g[j + 1] = sn[j] * g[j];", "int orc_gmres("),
+    ("gmres g not rotated", "g[j] = cs[j] * g[j];", ";", "int orc_gmres("),
+    ("gmres back substitution index", "for (int64_t t = i + 1; t < used; ++t) s -= H[i * m + t] * y[t];",
+     "for (int64_t t = i + 1; t < used; ++t) s -= H[t * m + i] * y[t];", "int orc_gmres("),
+    ("gmres basis not normalised", "for (int64_t t = 0; t < n; ++t) vn[t] = w[t] / hnext;",
+     "for (int64_t t = 0; t < n; ++t) vn[t] = w[t];", "int orc_gmres("),
+    ("gmres x update drops last column", "for (int64_t i = 0; i < used; ++i) {\n            const double *vi",
+     "for (int64_t i = 0; i + 1 < used; ++i) {\n            const double *vi", "int orc_gmres("),
+    ("gmres restart keeps old residual", "orc_residual(n, row_ptr, col, val, b, x, V);\n        const double beta",
+     "if (k == 0) orc_residual(n, row_ptr, col, val, b, x, V);\n        const double beta", "int orc_gmres("),
+    ("gmres cap off by one", "if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }\n            if (hnext",
+     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }\n            if (hnext", "int orc_gmres("),
     # Jacobi PCG
     ("diagonal keeps last duplicate", "if (col[k] == i) s += val[k];", "if (col[k] == i) s = val[k];",
      "void orc_diagonal("),
