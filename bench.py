@@ -36,8 +36,9 @@ def parse():
     ap.add_argument("--N", type=int, default=215, help="stencil7 grid edge (n = N^3)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tau", type=float, default=1e-14)
-    ap.add_argument("--solver", choices=["cg", "cgs"], default="cg",
-                    help="cgs runs on the nonsymmetric stencil7 variant of the same size")
+    ap.add_argument("--solver", choices=["cg", "cgs", "gmres"], default="cg",
+                    help="cgs and gmres run on the nonsymmetric stencil7 variant of the same size")
+    ap.add_argument("--krylov-dim", type=int, default=30, help="GMRES restart length")
     ap.add_argument("--precond", choices=["none", "jacobi"], default="none")
     ap.add_argument("--precision", choices=["fp64", "mixed_fp32", "mixed_bf16"], default="fp64",
                     help="fp64 CG, or FP32/BF16 inner CG with FP64 refinement")
@@ -107,10 +108,11 @@ def main():
     dev = torch.device("cuda:0")
     N = args.N
     cgs = args.solver == "cgs"
-    if (cgs or args.precond != "none") and args.precision != "fp64":
-        print("CGS and the Jacobi preconditioner run in FP64 only", file=sys.stderr)
+    gm = args.solver == "gmres"
+    if (cgs or gm or args.precond != "none") and args.precision != "fp64":
+        print("CGS, GMRES and the Jacobi preconditioner run in FP64 only", file=sys.stderr)
         sys.exit(2)
-    A = inputs.stencil7_ns(N, args.seed) if cgs else inputs.stencil7(N, args.seed)
+    A = inputs.stencil7_ns(N, args.seed) if (cgs or gm) else inputs.stencil7(N, args.seed)
     b_h = inputs.rhs(A.n_rows, args.seed)
     n, nnz = A.n_rows, A.nnz
     rp = torch.from_numpy(A.row_ptr).to(torch.int32).to(dev)
@@ -128,7 +130,8 @@ def main():
     cfg.precision = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32,
                      "mixed_bf16": spk.PREC_MIXED_BF16}[args.precision]
     cfg.inner_reduction = args.inner
-    cfg.solver = spk.SOLVER_CGS if cgs else spk.SOLVER_CG
+    cfg.solver = spk.SOLVER_CGS if cgs else (spk.SOLVER_GMRES if gm else spk.SOLVER_CG)
+    cfg.krylov_dim = args.krylov_dim
     cfg.precond = spk.PRECOND_JACOBI if args.precond == "jacobi" else spk.PRECOND_NONE
     if args.precision != "fp64":
         cfg.max_iters = 10000
@@ -174,6 +177,9 @@ def main():
     if cgs:
         workload = "cgs_fp64_stencil7ns_N%d" % N
         spmv_kernel = "k_spmv_*<EpiCgsV>, k_spmv_*<EpiCgsR> (two SpMVs per CGS iteration)"
+    elif gm:
+        workload = "gmres%d_fp64_stencil7ns_N%d" % (args.krylov_dim, N)
+        spmv_kernel = "k_spmv_*<EpiGmW> (w = A v_j / ||v_j||, one per Arnoldi step)"
     else:
         workload = "%s_%s_stencil7_N%d" % ("pcg_jacobi" if args.precond == "jacobi" else "cg", args.precision, N)
         spmv_kernel = "k_spmv_*<EpiPq> (q = A p fused with p.q)"
@@ -190,7 +196,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "mixed_fp32" else "bf16+f32+f64"),
         "data": ("synthetic (seeded nonsymmetric stencil7, independent uniform[-1,1) off-diagonals, "
-                 "row diagonally dominant)" if cgs else
+                 "row diagonally dominant)" if (cgs or gm) else
                  "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD)"),
         "config": {"workload": workload, "n": n, "nnz": nnz, "seed": args.seed,
                    "tau": args.tau, "index_types": "int32/int32", "iterations_per_solve": last.iterations,
@@ -216,9 +222,12 @@ def main():
         fn, label = oracle.cg, "CG"
         if cgs:
             fn, label = oracle.cgs, "CGS"
+        elif gm:
+            fn, label = (lambda A_, b_, tau, max_iters: oracle.gmres(A_, b_, tau=tau, max_iters=max_iters,
+                                                                   m=args.krylov_dim)), "GMRES"
         elif args.precond == "jacobi":
             fn, label = oracle.pcg_jacobi, "Jacobi PCG"
-        iters = args.cpu_iters if not cgs else max(args.cpu_iters // 2, 1)
+        iters = args.cpu_iters if not (cgs or gm) else max(args.cpu_iters // 2, 1)
         _, res, _ = fn(A, b_h, tau=0.0, max_iters=iters)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": n * res.iterations / dt, "unit": "updates/s", "cores": 1,
@@ -336,8 +345,6 @@ def large(args):
     cfg.precision = spk.PREC_MIXED_FP32
     cfg.reduction_factor = 1e-12
     cfg.inner_reduction = args.inner
-    cfg.solver = spk.SOLVER_CGS if cgs else spk.SOLVER_CG
-    cfg.precond = spk.PRECOND_JACOBI if args.precond == "jacobi" else spk.PRECOND_NONE
     cfg.max_iters = 10000
     cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
 
@@ -418,8 +425,6 @@ def serve(args):
     cfg.precision = spk.PREC_MIXED_FP32
     cfg.reduction_factor = tau
     cfg.inner_reduction = args.inner
-    cfg.solver = spk.SOLVER_CGS if cgs else spk.SOLVER_CG
-    cfg.precond = spk.PRECOND_JACOBI if args.precond == "jacobi" else spk.PRECOND_NONE
     cfg.max_iters = 100000
     budget = int(args.budget_gb * (1 << 30))
 

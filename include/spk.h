@@ -74,8 +74,12 @@ typedef enum {
 
 typedef enum {
     SPK_SOLVER_CG = 0,        /* conjugate gradient: A symmetric positive definite */
-    SPK_SOLVER_CGS = 1        /* conjugate gradient squared: general nonsingular A; FP64,
+    SPK_SOLVER_CGS = 1,       /* conjugate gradient squared: general nonsingular A; FP64,
                                  no preconditioner; two SpMVs per iteration */
+    SPK_SOLVER_GMRES = 2      /* restarted GMRES(krylov_dim): general nonsingular A; FP64, no
+                                 preconditioner; iterations count Arnoldi steps and the stop test
+                                 uses the Givens residual estimate (the true residual at each
+                                 restart) */
 } spk_solver;
 typedef enum {
     SPK_PREC_FP64 = 0,        /* FP64 values, vectors and reductions */
@@ -124,7 +128,7 @@ typedef struct {
 
 /* Solver configuration; spk_solver_cfg_default fills the defaults noted. */
 typedef struct {
-    int32_t solver;            /* SPK_SOLVER_CG (or SPK_SOLVER_CGS) */
+    int32_t solver;            /* SPK_SOLVER_CG (or SPK_SOLVER_CGS, SPK_SOLVER_GMRES) */
     int32_t precision;         /* SPK_PREC_FP64 */
     int32_t baseline;          /* SPK_BASELINE_RHS_NORM */
     int32_t precond;           /* SPK_PRECOND_NONE (or SPK_PRECOND_JACOBI) */
@@ -136,7 +140,8 @@ typedef struct {
     int32_t true_residual;     /* 1: recompute ||b - A x|| at exit (default 1) */
     double inner_reduction;    /* mixed: inner CG reduction factor (default 1e-4) */
     int64_t max_outer;         /* mixed: refinement step cap (default 50) */
-    int64_t reserved[4];
+    int64_t krylov_dim;        /* GMRES restart length, 1..32 (default 30, Listings 1-2) */
+    int64_t reserved[3];
 } spk_solver_cfg;
 
 /* What a solve did (the paper's logger). */
@@ -215,7 +220,8 @@ spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
 /* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
  * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
  * an FP32/BF16 copy for the inner solve) or F32 values (taken as exact).
- * CGS and the Jacobi preconditioner are FP64 only; the Jacobi plan computes
+ * CGS, GMRES and the Jacobi preconditioner are FP64 only (GMRES and CGS
+ * unpreconditioned, GMRES runs in the host loop); the Jacobi plan computes
  * 1 / diag(A) (a zero or non-finite diagonal entry makes every solve of the
  * plan stop with SPK_STOP_BREAKDOWN, x unchanged).
  * Errors: INVALID_ARG, UNSUPPORTED (other solver / precision /

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libspk.so")
-SOURCES = ["spk_kernels.hip", "spk_krylov.hip", "spk_batch.hip", "spk_api.cpp", "spk_server.cpp"]
+SOURCES = ["spk_kernels.hip", "spk_krylov.hip", "spk_gmres.hip", "spk_batch.hip", "spk_api.cpp", "spk_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

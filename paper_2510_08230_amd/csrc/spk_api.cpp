@@ -25,10 +25,17 @@ namespace {
 struct TuneKey {
     int64_t n_rows, n_cols, nnz;
     int pt, it, vt;
+    int use;   // TUNE_PLAIN or TUNE_CG
     bool operator<(const TuneKey &o) const {
-        return std::tie(n_rows, n_cols, nnz, pt, it, vt) < std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt);
+        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use) <
+               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use);
     }
 };
+
+// What a tuning run times: the plain product y = A x, or the solvers' SpMV
+// fused with the p.q partials (its register count, and so its residency,
+// differs).
+enum { TUNE_PLAIN = 0, TUNE_CG = 1 };
 
 struct TuneResult {
     SpmvTune tune;
@@ -68,6 +75,8 @@ struct spk_plan_s {
     double *rt = nullptr, *u = nullptr, *v = nullptr, *uh = nullptr;   // CGS
     double *dinv = nullptr;              // Jacobi: 1 / diag(A)
     void *coo_rp = nullptr;              // COO SpMV: derived row pointer (owned)
+    double *gm_V = nullptr, *gm_w = nullptr, *gm_part = nullptr;   // GMRES basis, work vector, partials
+    spk::GmresState *gm_st = nullptr;    // GMRES small arrays
     unsigned *diag_flag = nullptr;       // Jacobi: nonzero = unusable diagonal
     int64_t hist_cap = 0;
     SolveState *st = nullptr;
@@ -199,10 +208,12 @@ SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
     return make_tune(ctx, A, 1, l2, 1, 0, 0, 0);
 }
 
-// Times each candidate on y = A x and keeps the fastest.  x, y: device
-// vectors of the plan's vector type (contents irrelevant for timing).
-spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneResult *out) {
-    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t};
+// Times each candidate and keeps the fastest.  x, y: device vectors of the
+// plan's vector type (contents irrelevant for timing).  use = TUNE_CG times
+// the solvers' fused SpMV with st (stop flag clear) and partials.
+spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int use, SolveState *st,
+                    double *partials, TuneResult *out) {
+    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use};
     auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
         *out = hit->second;
@@ -227,12 +238,20 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, TuneRe
         if (L > 4.0 * std::max(mean, 1.0) && l2 > 0) break;
         cands.push_back(make_tune(ctx, A, 1, l2, 1, 0, 0, 0));
     }
+    auto launch = [&](const SpmvTune &t) -> hipError_t {
+        if (use == TUNE_PLAIN) return spk::launch_spmv(A, t, x, y, ctx->stream);
+        if (A.val_t == SPK_F64)
+            return spk::launch_cg_spmv_pq(A, t, static_cast<const double *>(x), static_cast<double *>(y), st,
+                                          partials, ctx->stream);
+        return spk::launch_cg_spmv_pq32(A, t, static_cast<const float *>(x), static_cast<float *>(y), st, partials,
+                                        ctx->stream);
+    };
     TuneResult best{cands[0], 1e30};
     for (const SpmvTune &t : cands) {
-        SPK_HIP(ctx, spk::launch_spmv(A, t, x, y, ctx->stream));   // warm-up
+        SPK_HIP(ctx, launch(t));   // warm-up
         SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
         const int reps = 5;
-        for (int i = 0; i < reps; ++i) SPK_HIP(ctx, spk::launch_spmv(A, t, x, y, ctx->stream));
+        for (int i = 0; i < reps; ++i) SPK_HIP(ctx, launch(t));
         SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
         SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
         float ms = 0.f;
@@ -288,7 +307,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     return true;
 }
 
-spk_status choose_tune(spk_plan pl, const void *x, void *y) {
+spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN, SolveState *st = nullptr) {
     spk_ctx ctx = pl->ctx;
     const CsrDev &A = pl->A;
     if (A.n_rows == 0) {
@@ -300,7 +319,7 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y) {
         pl->info.tuned = 0;
     } else if (A.nnz >= 100000) {
         TuneResult tr;
-        spk_status s = autotune(ctx, A, x, y, &tr);
+        spk_status s = autotune(ctx, A, x, y, use, st, pl->partials, &tr);
         if (s != SPK_OK) return s;
         pl->tune = tr.tune;
         pl->info.tuned = 1;
@@ -354,7 +373,7 @@ spk_status prof_collect(spk_plan pl, int64_t useful) {
 // Loop kinds: FP64 CG on A, FP32 inner CG on A32 (mixed precision), FP64
 // CGS, FP64 Jacobi-preconditioned CG.
 enum { LOOP_FP64 = 0, LOOP_FP32 = 1, LOOP_CGS = 2, LOOP_PCG = 3 };
-enum { ALGO_CG = 0, ALGO_CGS = 1, ALGO_PCG = 2 };
+enum { ALGO_CG = 0, ALGO_CGS = 1, ALGO_PCG = 2, ALGO_GMRES = 3 };
 
 // Iteration j of a chunk: q = A p with p.q partials; alpha and r -= alpha q
 // with r.r partials; x += alpha p, the stop test and p = r + beta p.  A chunk
@@ -522,7 +541,13 @@ void release_workspace(spk_plan pl) {
     ctx->dpool.put(pl->dinv);
     ctx->dpool.put(pl->diag_flag);
     ctx->dpool.put(pl->coo_rp);
+    ctx->dpool.put(pl->gm_V);
+    ctx->dpool.put(pl->gm_w);
+    ctx->dpool.put(pl->gm_part);
+    ctx->dpool.put(pl->gm_st);
     pl->coo_rp = nullptr;
+    pl->gm_V = pl->gm_w = pl->gm_part = nullptr;
+    pl->gm_st = nullptr;
     pl->rt = pl->u = pl->v = pl->uh = pl->dinv = nullptr;
     pl->diag_flag = nullptr;
     pl->bar = nullptr;
@@ -557,6 +582,7 @@ void spk_solver_cfg_default(spk_solver_cfg *cfg) {
     cfg->true_residual = 1;
     cfg->inner_reduction = 1e-4;
     cfg->max_outer = 50;
+    cfg->krylov_dim = 30;
 }
 
 const char *spk_status_string(spk_status s) {
@@ -782,14 +808,16 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     spk_solver_cfg cfg;
     if (cfg_in) cfg = *cfg_in;
     else spk_solver_cfg_default(&cfg);
-    if (cfg.solver != SPK_SOLVER_CG && cfg.solver != SPK_SOLVER_CGS)
+    if (cfg.solver != SPK_SOLVER_CG && cfg.solver != SPK_SOLVER_CGS && cfg.solver != SPK_SOLVER_GMRES)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown solver");
+    if (cfg.solver == SPK_SOLVER_GMRES && (cfg.krylov_dim < 1 || cfg.krylov_dim > spk::kMaxKrylov))
+        return fail(ctx, SPK_ERR_INVALID_ARG, "krylov_dim must be in 1..32");
     if (cfg.precond != SPK_PRECOND_NONE && cfg.precond != SPK_PRECOND_JACOBI)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown preconditioner");
-    if (cfg.solver == SPK_SOLVER_CGS && cfg.precond != SPK_PRECOND_NONE)
-        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS runs unpreconditioned");
-    if ((cfg.solver == SPK_SOLVER_CGS || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
-        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS and Jacobi CG run in FP64 precision");
+    if (cfg.solver != SPK_SOLVER_CG && cfg.precond != SPK_PRECOND_NONE)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS and GMRES run unpreconditioned");
+    if ((cfg.solver != SPK_SOLVER_CG || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS, GMRES and Jacobi CG run in FP64 precision");
     if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
     if (cfg.precision < SPK_PREC_FP64 || cfg.precision > SPK_PREC_MIXED_BF16)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown precision");
@@ -816,7 +844,10 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     pl->kind = 1;
     pl->A = to_dev(A);
     pl->cfg = cfg;
-    pl->algo = cfg.solver == SPK_SOLVER_CGS ? ALGO_CGS : (cfg.precond == SPK_PRECOND_JACOBI ? ALGO_PCG : ALGO_CG);
+    pl->algo = cfg.solver == SPK_SOLVER_CGS     ? ALGO_CGS
+               : cfg.solver == SPK_SOLVER_GMRES ? ALGO_GMRES
+               : cfg.precond == SPK_PRECOND_JACOBI ? ALGO_PCG
+                                                   : ALGO_CG;
     const int64_t n = A->n_rows;
     const size_t nb = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(double);
     const size_t nf = static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(float);
@@ -859,6 +890,12 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         if (pl->algo == ALGO_CGS &&
             (!dget(nb, &pl->rt) || !dget(nb, &pl->u) || !dget(nb, &pl->v) || !dget(nb, &pl->uh)))
             return cleanup(SPK_ERR_OUT_OF_MEMORY, "CGS workspace");
+        if (pl->algo == ALGO_GMRES) {
+            const size_t vbytes = nb * static_cast<size_t>(cfg.krylov_dim + 1);
+            if (!dget(vbytes, &pl->gm_V) || !dget(nb, &pl->gm_w) || !dget(sizeof(spk::GmresState), &pl->gm_st) ||
+                !dget(sizeof(double) * (spk::kMaxKrylov + 1) * spk::kMaxGrid, &pl->gm_part))
+                return cleanup(SPK_ERR_OUT_OF_MEMORY, "GMRES workspace");
+        }
         if (pl->algo == ALGO_PCG) {
             if (!dget(nb, &pl->dinv) || !dget(sizeof(unsigned), &pl->diag_flag))
                 return cleanup(SPK_ERR_OUT_OF_MEMORY, "Jacobi workspace");
@@ -866,7 +903,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
                 spk::launch_diag_inv(pl->A, pl->dinv, pl->diag_flag, ctx->stream) != hipSuccess)
                 return cleanup(SPK_ERR_DEVICE, "Jacobi diagonal");
         }
-        s = choose_tune(pl, pl->p, pl->q);
+        s = choose_tune(pl, pl->p, pl->q, TUNE_CG, pl->st);
         if (s != SPK_OK) return cleanup(s, ctx->err);
     } else {
         if (!dget(nf, &pl->r32) || !dget(nf, &pl->p32) || !dget(nf, &pl->q32) || !dget(nf, &pl->d32) ||
@@ -896,7 +933,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         // (a few launches): launch-shape heuristic on A.
         const CsrDev outer = pl->A;
         pl->A = pl->A32;
-        s = choose_tune(pl, pl->p32, pl->q32);
+        s = choose_tune(pl, pl->p32, pl->q32, TUNE_CG, pl->st_in);
         pl->A = outer;
         if (s != SPK_OK) return cleanup(s, ctx->err);
         pl->tune32 = pl->tune;
@@ -909,6 +946,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     // launch with grid barriers.
     if (mode == SPK_EXEC_AUTO) mode = SPK_EXEC_HOST_LOOP;
     if (mode == SPK_EXEC_PERSISTENT && (mixed || pl->algo != ALGO_CG)) mode = SPK_EXEC_GRAPH;
+    if (pl->algo == ALGO_GMRES) mode = SPK_EXEC_HOST_LOOP;   // cycles read b and x directly
     if (mode == SPK_EXEC_PERSISTENT) {
         const int occ = spk::persistent_blocks_per_cu(pl->A);
         const int64_t tiles = std::max<int64_t>((n + spk::kTileRows - 1) / spk::kTileRows, 1);
@@ -948,6 +986,38 @@ spk_status spk_execute_spmv(spk_plan pl, const void *x, void *y) {
     return prof_collect(pl, pl->ev_used);
 }
 
+// Restarted GMRES: each cycle (restart residual, krylov_dim Arnoldi steps,
+// triangular solve, x update) is enqueued whole; the state is read once per
+// cycle.  Steps after the device ends a cycle return at once.
+static spk_status run_gmres(spk_plan pl, const double *b, double *x) {
+    spk_ctx ctx = pl->ctx;
+    const spk_solver_cfg &cfg = pl->cfg;
+    const int m = static_cast<int>(cfg.krylov_dim);
+    const int64_t n = pl->A.n_rows;
+    hipStream_t s = ctx->stream;
+    SPK_HIP(ctx, spk::launch_gm_begin(pl->st, pl->gm_st, x, pl->hist, pl->hist_cap, cfg.max_iters, s));
+    // every cycle but the last completes at least one step
+    const int64_t max_cycles = cfg.max_iters + 2;
+    for (int64_t c = 0; c < max_cycles; ++c) {
+        SPK_HIP(ctx, spk::launch_gm_cycle_start(pl->A, pl->tune, b, x, pl->gm_V, pl->st, pl->gm_st, pl->partials,
+                                                cfg.reduction_factor, m, s));
+        for (int j = 0; j < m; ++j) {
+            hipEvent_t e = nullptr;
+            spk_status ps = prof_begin(pl, &e);
+            if (ps != SPK_OK) return ps;
+            SPK_HIP(ctx, spk::launch_gm_step_spmv(pl->A, pl->tune, pl->gm_V, pl->gm_w, j, pl->st, pl->gm_st, s));
+            if ((ps = prof_end(pl, e)) != SPK_OK) return ps;
+            SPK_HIP(ctx, spk::launch_gm_step_rest(n, pl->vec_grid, pl->gm_V, pl->gm_w, j, m, pl->st, pl->gm_st,
+                                                  pl->gm_part, s));
+        }
+        SPK_HIP(ctx, spk::launch_gm_cycle_end(n, pl->vec_grid, m, pl->gm_V, pl->st, pl->gm_st, s));
+        spk_status ps = pull(ctx, pl->h_st, pl->st, sizeof(SolveState));
+        if (ps != SPK_OK) return ps;
+        if (pl->h_st->stop != spk::STOP_RUNNING) return SPK_OK;
+    }
+    return fail(ctx, SPK_ERR_INTERNAL, "GMRES cycle cap passed without stop");
+}
+
 static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log *L, bool graph) {
     spk_ctx ctx = pl->ctx;
     const spk_solver_cfg &cfg = pl->cfg;
@@ -963,6 +1033,11 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
         SPK_HIP(ctx, hipMemcpyAsync(flags, pl->bar, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream));
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
         if (flags[2] != 0) return fail(ctx, SPK_ERR_DEVICE, "persistent solve: a grid barrier timed out");
+    } else if (pl->algo == ALGO_GMRES) {
+        if ((s = run_gmres(pl, b, x)) != SPK_OK) return s;
+        SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
+                                             ctx->stream));
+        if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
     } else {
         int kind = LOOP_FP64;
         if (pl->algo == ALGO_PCG) {

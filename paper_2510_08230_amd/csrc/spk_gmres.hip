@@ -1,0 +1,356 @@
+// gfx950 kernels of restarted GMRES(m), the solver of the paper's usage
+// examples (Listings 1-2, Krylov dimension 30) and of its solver benchmarks
+// (Section 6.2).
+//
+// Arnoldi orthogonalisation is classical Gram-Schmidt applied twice (CGS2):
+// on a GPU each pass is one streaming kernel over the basis (a multi-dot
+// and/or a multi-axpy, all HBM-bound), where modified Gram-Schmidt would
+// need one dependent pass and one reduction per basis vector.  A step j
+// (J = j + 1 basis vectors) is:
+//   SpMV      : w = A v_j          (v_j stored unnormalised; the row sums are
+//                                    scaled by 1 / ||v_j|| in the epilogue)
+//   dots      : v_j *= 1 / ||v_j|| (written back), partials of h1 = V^T w
+//   reduce    : h1
+//   pass2     : w -= V h1, partials of h2 = V^T w
+//   reduce    : h2
+//   pass3     : v_{j+1} = w - V h2 (unnormalised), partial of ||v_{j+1}||^2
+//   givens    : column j of H = h1 + h2 and ||v_{j+1}||, earlier rotations,
+//               a new rotation, g, the residual estimate |g_{j+1}|, stop test
+// A cycle starts with the residual r = b - A x written into v_0 and ends
+// with the triangular solve R y = g and x += V y over the columns built.
+// Kernels return at once when the solve has stopped or the cycle is done,
+// so the host can enqueue a whole cycle and poll once.
+#include "spk_spmv.h"
+
+#include <cmath>
+
+namespace spk {
+namespace {
+
+using namespace dev;
+using namespace tile;
+
+__device__ __forceinline__ bool gm_idle(const SolveState *st, const GmresState *gs) {
+    return st->stop != STOP_RUNNING || gs->cycle_done != 0;
+}
+
+// r = b - A x into v_0; partials of r.r and b.b.
+struct EpiGmRes {
+    const double *b;
+    double *v0;
+    const SolveState *st;
+    double *part;
+    double rr, bb;
+    __device__ bool skip() const { return st->stop != STOP_RUNNING; }
+    __device__ void row(int64_t i, double s) {
+        const double bi = b[i];
+        const double ri = bi - s;
+        v0[i] = ri;
+        rr = fma(ri, ri, rr);
+        bb = fma(bi, bi, bb);
+    }
+    __device__ void finish() {
+        double w[2] = {rr, bb};
+        block_partial<2>(w, part);
+    }
+};
+
+// w = (A v_j) / ||v_j||.
+struct EpiGmW {
+    double *w;
+    const SolveState *st;
+    const GmresState *gs;
+    __device__ bool skip() const { return gm_idle(st, gs); }
+    __device__ void row(int64_t i, double s) { w[i] = s * gs->inv_scale; }
+    __device__ void finish() {}
+};
+
+// Solve set-up (one thread): the state fields every later kernel reads.
+__global__ void k_gm_begin(SolveState *st, GmresState *gs, double *x, double *hist, int64_t hist_cap,
+                           int64_t max_iters) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->x = x;
+    st->hist = hist;
+    st->hist_cap = hist_cap;
+    st->max_iters = max_iters;
+    st->base = 0;
+    st->iter = 0;
+    st->zero_x = 0;
+    st->stop = STOP_RUNNING;
+    st->alpha = 0.0;
+    st->pq = 0.0;
+    st->true_resnorm = __builtin_nan("");
+    gs->cycle_done = 0;
+    gs->used = 0;
+}
+
+// Cycle start: ||b||, beta = ||r||, the stop tests on r, g = beta e_0.
+__global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, GmresState *gs, const double *part, int G,
+                                                           double tau, int m) {
+    if (st->stop != STOP_RUNNING) {
+        if (threadIdx.x == 0) gs->cycle_done = 1;
+        return;
+    }
+    double tot[2];
+    sum_partials<2>(part, G, tot);
+    if (threadIdx.x != 0) return;
+    const double bn = sqrt(tot[1]);
+    const double beta = sqrt(tot[0]);
+    st->bnorm = bn;
+    st->thresh = tau * bn;
+    int stop = STOP_RUNNING;
+    if (!isfinite(bn)) {
+        stop = STOP_NON_FINITE;
+        st->resnorm = bn;
+    } else if (bn == 0.0) {
+        st->zero_x = 1;
+        stop = STOP_CONVERGED;
+        st->resnorm = 0.0;
+        st->true_resnorm = 0.0;
+        if (st->iter == 0 && st->hist && st->hist_cap > 0) st->hist[0] = 0.0;
+    } else {
+        st->resnorm = beta;
+        if (st->iter == 0 && st->hist && st->hist_cap > 0) st->hist[0] = beta;
+        if (!isfinite(beta)) stop = STOP_NON_FINITE;
+        else if (beta <= tau * bn) stop = STOP_CONVERGED;
+        else if (st->iter >= st->max_iters) stop = STOP_MAX_ITERS;
+    }
+    gs->used = 0;
+    gs->cycle_done = stop != STOP_RUNNING;
+    gs->inv_scale = 1.0 / beta;
+    gs->g[0] = beta;
+    for (int i = 1; i <= m; ++i) gs->g[i] = 0.0;
+    if (stop != STOP_RUNNING) st->stop = stop;
+}
+
+// Basis vector t of the Krylov block (contiguous, n apart).
+__device__ __forceinline__ const double *vec(const double *V, int64_t n, int t) { return V + static_cast<int64_t>(t) * n; }
+
+// v_j *= 1/||v_j|| (written back); partials of h1_t = w . v_t, t <= j.  The
+// written vector comes in as its own pointer so that the loads of the other
+// basis vectors can be issued ahead of the store.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, const double *__restrict__ V, double *__restrict__ vj,
+                                                    const double *__restrict__ w, int j, const SolveState *st,
+                                                    const GmresState *gs, double *part) {
+    if (gm_idle(st, gs)) return;
+    const double inv = gs->inv_scale;
+    double acc[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+        const double v = vj[i] * inv;
+        double vt[NV];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) vt[t] = t < j ? vec(V, n, t)[i] : 0.0;
+        vj[i] = v;
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+            if (t < j) acc[t] = fma(wi, vt[t], acc[t]);
+            else if (t == j) acc[t] = fma(wi, v, acc[t]);
+        }
+    }
+    block_partial<NV>(acc, part);
+}
+
+// Partial sums of one coefficient per workgroup: out[t] = sum of part row t.
+__global__ __launch_bounds__(kBlock) void k_gm_reduce(const double *part, int G, double *out, const SolveState *st,
+                                                      const GmresState *gs) {
+    if (gm_idle(st, gs)) return;
+    const int t = blockIdx.x;
+    double tot[1];
+    sum_partials<1>(part + static_cast<int64_t>(t) * kMaxGrid, G, tot);
+    if (threadIdx.x == 0) out[t] = tot[0];
+}
+
+// w -= V h1 over t <= j; partials of h2_t = w . v_t.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, const double *V, double *__restrict__ w, int j,
+                                                     const SolveState *st, const GmresState *gs, double *part) {
+    if (gm_idle(st, gs)) return;
+    __shared__ double h[NV];
+    if (threadIdx.x < NV) h[threadIdx.x] = threadIdx.x <= j ? gs->h1[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        double v[NV];
+        double wi = w[i];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+            v[t] = t <= j ? vec(V, n, t)[i] : 0.0;
+            wi = fma(-h[t], v[t], wi);
+        }
+        w[i] = wi;
+#pragma unroll
+        for (int t = 0; t < NV; ++t) acc[t] = fma(wi, v[t], acc[t]);
+    }
+    block_partial<NV>(acc, part);
+}
+
+// v_{j+1} = w - V h2 over t <= j (unnormalised); partial of ||v_{j+1}||^2.
+// vn (= v_{j+1}) does not overlap the basis vectors read.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, const double *__restrict__ V, double *__restrict__ vn,
+                                                     const double *__restrict__ w, int j, const SolveState *st,
+                                                     const GmresState *gs, double *part) {
+    if (gm_idle(st, gs)) return;
+    __shared__ double h[NV];
+    if (threadIdx.x < NV) h[threadIdx.x] = threadIdx.x <= j ? gs->h2[threadIdx.x] : 0.0;
+    __syncthreads();
+    double nrm = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        double vt[NV];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) vt[t] = t <= j ? vec(V, n, t)[i] : 0.0;
+        double wi = w[i];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) wi = fma(-h[t], vt[t], wi);
+        vn[i] = wi;
+        nrm = fma(wi, wi, nrm);
+    }
+    double a[1] = {nrm};
+    block_partial<1>(a, part);
+}
+
+// Column j of the Hessenberg matrix, its rotations, the residual estimate
+// and the stop test (one workgroup; thread 0 does the scalar work).
+__global__ __launch_bounds__(kBlock) void k_gm_givens(SolveState *st, GmresState *gs, const double *part_n, int G,
+                                                      int j, int m) {
+    if (gm_idle(st, gs)) return;
+    double tot[1];
+    sum_partials<1>(part_n, G, tot);
+    if (threadIdx.x != 0) return;
+    const double hn = sqrt(tot[0]);
+    double *H = gs->H;
+    for (int t = 0; t <= j; ++t) H[t * kMaxKrylov + j] = gs->h1[t] + gs->h2[t];
+    for (int t = 0; t < j; ++t) {
+        const double a = H[t * kMaxKrylov + j], c = H[(t + 1) * kMaxKrylov + j];
+        H[t * kMaxKrylov + j] = gs->cs[t] * a + gs->sn[t] * c;
+        H[(t + 1) * kMaxKrylov + j] = -gs->sn[t] * a + gs->cs[t] * c;
+    }
+    const double a = H[j * kMaxKrylov + j];
+    const double d = hypot(a, hn);
+    double c = 1.0, s = 0.0;
+    if (d != 0.0) {
+        c = a / d;
+        s = hn / d;
+    }
+    gs->cs[j] = c;
+    gs->sn[j] = s;
+    H[j * kMaxKrylov + j] = c * a + s * hn;
+    H[(j + 1) * kMaxKrylov + j] = 0.0;
+    gs->g[j + 1] = -s * gs->g[j];
+    gs->g[j] = c * gs->g[j];
+    const int64_t k = st->iter + 1;
+    const double res = fabs(gs->g[j + 1]);
+    st->iter = k;
+    st->resnorm = res;
+    if (st->hist && k < st->hist_cap) st->hist[k] = res;
+    int stop = STOP_RUNNING;
+    if (!isfinite(res)) stop = STOP_NON_FINITE;
+    else if (res <= st->thresh) stop = STOP_CONVERGED;
+    else if (k >= st->max_iters) stop = STOP_MAX_ITERS;
+    gs->used = j + 1;
+    if (stop != STOP_RUNNING || hn == 0.0 || j + 1 == m) gs->cycle_done = 1;
+    else gs->inv_scale = 1.0 / hn;
+    if (stop != STOP_RUNNING) st->stop = stop;
+}
+
+// R y = g by back substitution over the columns built (one thread).
+__global__ void k_gm_solve(const SolveState *st, GmresState *gs) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int used = gs->used;
+    if (st->stop == STOP_NON_FINITE || used == 0) return;
+    for (int i = used - 1; i >= 0; --i) {
+        double s = gs->g[i];
+        for (int t = i + 1; t < used; ++t) s -= gs->H[i * kMaxKrylov + t] * gs->y[t];
+        gs->y[i] = s / gs->H[i * kMaxKrylov + i];
+    }
+}
+
+// x += V y over the columns built, added column by column.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, const double *V, const SolveState *st,
+                                                        const GmresState *gs) {
+    const int used = gs->used;
+    if (st->stop == STOP_NON_FINITE || used == 0) return;
+    __shared__ double y[NV];
+    if (threadIdx.x < NV) y[threadIdx.x] = threadIdx.x < used ? gs->y[threadIdx.x] : 0.0;
+    __syncthreads();
+    double *x = static_cast<double *>(st->x);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        double xi = x[i];
+#pragma unroll
+        for (int t = 0; t < NV; ++t)
+            if (t < used) xi = fma(y[t], vec(V, n, t)[i], xi);
+        x[i] = xi;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+static int nv_bucket(int J) { return J <= 8 ? 8 : (J <= 16 ? 16 : 32); }
+
+hipError_t launch_gm_begin(SolveState *st, GmresState *gs, double *x, double *hist, int64_t hist_cap,
+                           int64_t max_iters, hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_begin, dim3(1), dim3(64), 0, s, st, gs, x, hist, hist_cap, max_iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, double *V,
+                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, hipStream_t s) {
+    EpiGmRes e{b, V, st, site(partials, SITE_INIT), 0.0, 0.0};
+    hipError_t err = launch_family<double, double, double>(A, t, x, e, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_gm_cycle_start, dim3(1), dim3(kBlock), 0, s, st, gs, site(partials, SITE_INIT), t.grid, tau,
+                       m);
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const double *V, double *w, int j,
+                               const SolveState *st, const GmresState *gs, hipStream_t s) {
+    EpiGmW e{w, st, gs};
+    return launch_family<double, double, double>(A, t, V + static_cast<int64_t>(j) * A.n_rows, e, s);
+}
+
+hipError_t launch_gm_step_rest(int64_t n, int grid, double *V, double *w, int j, int m, SolveState *st,
+                               GmresState *gs, double *gpart, hipStream_t s) {
+    const int J = j + 1;
+    const int nv = nv_bucket(J);
+#define SPK_GM_NV(K, ...)                                                                                   \
+    do {                                                                                                    \
+        if (nv == 8) hipLaunchKernelGGL(K<8>, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                 \
+        else if (nv == 16) hipLaunchKernelGGL(K<16>, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);          \
+        else hipLaunchKernelGGL(K<32>, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                        \
+    } while (0)
+    double *vj = V + static_cast<int64_t>(j) * n;
+    double *vn = V + static_cast<int64_t>(j + 1) * n;
+    SPK_GM_NV(k_gm_dots, n, V, vj, w, j, st, gs, gpart);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h1[0], st, gs);
+    SPK_GM_NV(k_gm_pass2, n, V, w, j, st, gs, gpart);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h2[0], st, gs);
+    SPK_GM_NV(k_gm_pass3, n, V, vn, w, j, st, gs, gpart);
+    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kBlock), 0, s, st, gs, gpart, grid, j, m);
+#undef SPK_GM_NV
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const double *V, SolveState *st, GmresState *gs,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, st, gs);
+    const int nv = nv_bucket(m);
+    if (nv == 8) hipLaunchKernelGGL(k_gm_update_x<8>, dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    else if (nv == 16) hipLaunchKernelGGL(k_gm_update_x<16>, dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    else hipLaunchKernelGGL(k_gm_update_x<32>, dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    return hipGetLastError();
+}
+
+}  // namespace spk

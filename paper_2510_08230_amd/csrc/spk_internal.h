@@ -47,6 +47,19 @@ struct SolveState {
     int64_t hist_cap;
 };
 
+// Restarted GMRES: the small per-solve arrays (device memory, one per plan).
+constexpr int kMaxKrylov = 32;   // largest restart length m
+struct GmresState {
+    double H[(kMaxKrylov + 1) * kMaxKrylov];   // rotated Hessenberg, H[i * kMaxKrylov + j]
+    double cs[kMaxKrylov], sn[kMaxKrylov];     // Givens rotations
+    double g[kMaxKrylov + 1];                  // rotated right-hand side beta e_0
+    double y[kMaxKrylov];                      // solution of R y = g
+    double h1[kMaxKrylov + 1], h2[kMaxKrylov + 1];   // the two Gram-Schmidt passes' coefficients
+    double inv_scale;                          // 1 / norm of the unnormalised basis vector v_j
+    int32_t used;                              // columns built in this cycle
+    int32_t cycle_done;                        // nonzero: later kernels of the cycle return at once
+};
+
 // Launch shape of the SpMV family (shared by every SpMV-based kernel).
 struct SpmvTune {
     int kind;        // 0 = LDS-staged row tiles, 1 = lanes-per-row vector kernel
@@ -132,6 +145,22 @@ hipError_t launch_cgs_update(int64_t n, int grid, int spmv_grid, int j, const do
 hipError_t launch_cgs_spmv_r(const CsrDev &A, const SpmvTune &t, const double *uh, double *r, const double *rt,
                              SolveState *st, double *partials, hipStream_t s);
 hipError_t launch_cgs_check(SolveState *st, double *partials, int spmv_grid, int count, hipStream_t s);
+
+// Restarted GMRES(m) (FP64; spk_gmres.hip).  V holds m + 1 basis vectors of
+// n doubles back to back, w one more vector, gpart (kMaxKrylov + 1) *
+// kMaxGrid doubles.  A solve is begin, then per cycle: cycle_start (r = b - A x
+// into v_0, beta, stop test), for j = 0..m-1 step_spmv(j) and step_rest(j),
+// then cycle_end (R y = g, x += V y); the host polls after each cycle.
+hipError_t launch_gm_begin(SolveState *st, GmresState *gs, double *x, double *hist, int64_t hist_cap,
+                           int64_t max_iters, hipStream_t s);
+hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, double *V,
+                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, hipStream_t s);
+hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const double *V, double *w, int j,
+                               const SolveState *st, const GmresState *gs, hipStream_t s);
+hipError_t launch_gm_step_rest(int64_t n, int grid, double *V, double *w, int j, int m, SolveState *st,
+                               GmresState *gs, double *gpart, hipStream_t s);
+hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const double *V, SolveState *st, GmresState *gs,
+                               hipStream_t s);
 
 // Jacobi-preconditioned CG (FP64; spk_krylov.hip).  diag_inv runs once per
 // plan (flag: one zeroed unsigned, set when a diagonal entry is zero or not

@@ -896,25 +896,44 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipSt
     return hipGetLastError();
 }
 
+// The smaller residency of the plain and the p.q-fused SpMV of this type and
+// tiling (plans time one of them; the other may run on the same launch shape).
 int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t) {
-    int blocks = 0;
-    hipError_t e = hipSuccess;
-    auto q = [&](auto kern) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, kBlock, 0); };
+    int lo = 1 << 30;
+    auto q = [&](auto kern) {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, kBlock, 0) != hipSuccess) blocks = 1;
+        lo = blocks < lo ? blocks : lo;
+    };
     const bool i64 = A.idx_t != 0;
     if (A.val_t == 0) {
         if (t.kind == 0) {
-            if (i64) q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>>);
-            else q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq<double>>);
+            if (i64) {
+                q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>>);
+                q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPlain<double>>);
+            } else {
+                q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq<double>>);
+                q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPlain<double>>);
+            }
         } else {
-            if (i64) q(k_spmv_vector<double, int64_t, int64_t, double, double, EpiPq<double>>);
-            else q(k_spmv_vector<double, int64_t, int32_t, double, double, EpiPq<double>>);
+            if (i64) {
+                q(k_spmv_vector<double, int64_t, int64_t, double, double, EpiPq<double>>);
+                q(k_spmv_vector<double, int64_t, int64_t, double, double, EpiPlain<double>>);
+            } else {
+                q(k_spmv_vector<double, int64_t, int32_t, double, double, EpiPq<double>>);
+                q(k_spmv_vector<double, int64_t, int32_t, double, double, EpiPlain<double>>);
+            }
         }
     } else {
-        if (t.kind == 0) q(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPlain<float>>);
-        else q(k_spmv_vector<float, int64_t, int32_t, float, float, EpiPlain<float>>);
+        if (t.kind == 0) {
+            q(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPlain<float>>);
+            q(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPq<float>>);
+        } else {
+            q(k_spmv_vector<float, int64_t, int32_t, float, float, EpiPlain<float>>);
+            q(k_spmv_vector<float, int64_t, int32_t, float, float, EpiPq<float>>);
+        }
     }
-    if (e != hipSuccess || blocks < 1) blocks = 1;
-    return blocks;
+    return lo < 1 ? 1 : lo;
 }
 
 }  // namespace spk

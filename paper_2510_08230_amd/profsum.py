@@ -19,7 +19,8 @@ import os
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_krylov.hip", "csrc/spk_spmv.h", "csrc/spk_device.h",
+KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_krylov.hip", "csrc/spk_gmres.hip", "csrc/spk_spmv.h",
+                  "csrc/spk_device.h",
                   "csrc/spk_internal.h"]
 
 

@@ -27,7 +27,7 @@ F64, F32, F16, BF16 = range(4)
 I32, I64 = range(2)
 CSR_OK, CSR_BAD_SIZE, CSR_BAD_FIRST, CSR_DECREASING, CSR_BAD_LAST, CSR_BAD_COLUMN = range(6)
 STOP_RUNNING, STOP_CONVERGED, STOP_MAX_ITERS, STOP_BREAKDOWN, STOP_NON_FINITE = range(5)
-SOLVER_CG, SOLVER_CGS = 0, 1
+SOLVER_CG, SOLVER_CGS, SOLVER_GMRES = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = range(3)
 EXEC_AUTO, EXEC_HOST_LOOP, EXEC_GRAPH, EXEC_PERSISTENT = range(4)
@@ -57,7 +57,7 @@ class SolverCfg(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("max_iters", ctypes.c_int64), ("reduction_factor", ctypes.c_double),
                 ("exec_mode", ctypes.c_int32), ("chunk_iters", ctypes.c_int32), ("record_history", ctypes.c_int32),
                 ("true_residual", ctypes.c_int32), ("inner_reduction", ctypes.c_double),
-                ("max_outer", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+                ("max_outer", ctypes.c_int64), ("krylov_dim", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
 
 class Log(ctypes.Structure):

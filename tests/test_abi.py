@@ -47,6 +47,8 @@ int main(void) {
   P(spk_csr, values) P(spk_csr, ptr_type) P(spk_solver_cfg, max_iters) P(spk_solver_cfg, reduction_factor)
   P(spk_solver_cfg, inner_reduction) P(spk_solver_cfg, max_outer) P(spk_log, elapsed_ms) P(spk_log, stop_reason)
   P(spk_plan_info, spmv_ms)
+  printf("SPK_SOLVER_GMRES %d\n", (int)SPK_SOLVER_GMRES);
+  P(spk_solver_cfg, krylov_dim)
   printf("SPK_SOLVER_CGS %d\nSPK_PRECOND_JACOBI %d\nSPK_EXEC_PERSISTENT %d\nSPK_PREC_MIXED_BF16 %d\n",
          (int)SPK_SOLVER_CGS, (int)SPK_PRECOND_JACOBI, (int)SPK_EXEC_PERSISTENT, (int)SPK_PREC_MIXED_BF16);
   return 0;
@@ -78,6 +80,8 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[key]) == field.offset, key
     assert int(got["SPK_SOLVER_CGS"]) == spk.SOLVER_CGS and int(got["SPK_PRECOND_JACOBI"]) == spk.PRECOND_JACOBI
     assert int(got["SPK_EXEC_PERSISTENT"]) == spk.EXEC_PERSISTENT
+    assert int(got["SPK_SOLVER_GMRES"]) == spk.SOLVER_GMRES
+    assert int(got["spk_solver_cfg.krylov_dim"]) == spk.SolverCfg.krylov_dim.offset
     assert int(got["SPK_PREC_MIXED_BF16"]) == spk.PREC_MIXED_BF16
 
 
@@ -85,6 +89,7 @@ def test_defaults_and_status_strings():
     from paper_2510_08230_amd import spk
     cfg = spk.spk_solver_cfg_default()
     assert cfg.max_iters == 1000 and cfg.reduction_factor == 1e-6    # Listings 1-2 defaults
+    assert cfg.krylov_dim == 30                                         # Listings 1-2
     assert cfg.solver == spk.SOLVER_CG and cfg.precision == spk.PREC_FP64 and cfg.true_residual == 1
     assert spk.spk_status_string(spk.OK) == "SPK_OK"
     assert spk.spk_status_string(spk.ERR_INVALID_ARG) == "SPK_ERR_INVALID_ARG"

@@ -1,0 +1,163 @@
+"""Restarted GMRES(m) on the GPU against the FP64 oracle.
+
+The GPU orthogonalises by classical Gram-Schmidt applied twice (one
+streaming pass per sweep over the basis), the oracle by modified
+Gram-Schmidt; in exact arithmetic both give the same Arnoldi basis, so the
+iterates agree to rounding.
+
+Stated tolerances (FP64, diagonally dominant inputs):
+  * fixed-K iterates (stop test off, K within and across restarts):
+    ||x_K - x_K^orc|| / ||x_K^orc|| <= 1e-12
+  * converged solves: the same bound on x, iterations within +-1, residual
+    estimates within 1% per step, true residual <= 10 tau ||b||.
+Derivation: a 1-ulp relative perturbation of b moves the oracle's own
+GMRES(30) and GMRES(5) iterates by at most 8e-16 (relative) over 45 steps
+of stencil7_ns N=46 and N=20 (delta 0.2), and its residual estimates by at
+most 5e-7; the GPU's different summation order and Gram-Schmidt form
+perturb each step at that level."""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+from tests.gpu_util import dev_csr, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spk():
+    from paper_2510_08230_amd import spk as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(spk):
+    c = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    yield c
+    spk.spk_finalize(c)
+
+
+def gmres(spk, ctx, A, b, m=30, x0=None, tau=1e-14, max_iters=1000, history=False, M=None):
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = spk.SOLVER_GMRES
+    cfg.krylov_dim = m
+    cfg.reduction_factor = tau
+    cfg.max_iters = max_iters
+    cfg.record_history = 1 if history else 0
+    M = M if M is not None else dev_csr(spk, A)
+    pl = spk.spk_plan_solve(ctx, M, cfg)
+    x = to_dev(np.zeros(A.n_rows) if x0 is None else x0)
+    log = spk.spk_execute_solve(pl, to_dev(b), x)
+    hist = spk.spk_plan_history(pl) if history else None
+    spk.spk_free(pl)
+    return x.cpu().numpy(), log, hist
+
+
+MATS = {"stencil7ns_46": lambda: inputs.stencil7_ns(46, 0),
+        "stencil7ns_20_d0.2": lambda: inputs.stencil7_ns(20, 1, delta=0.2),
+        "randsym_3e4": lambda: inputs.randsym(30000, 2)}
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("m,K", [(30, 1), (30, 7), (30, 30), (30, 45), (5, 12), (1, 4), (17, 20)])
+def test_gmres_fixed_k_iterates(spk, ctx, name, m, K):
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 1)
+    x, log, _ = gmres(spk, ctx, A, b, m=m, tau=0.0, max_iters=K)
+    xo, ro, _ = oracle.gmres(A, b, tau=0.0, max_iters=K, m=m)
+    assert log.iterations == K and log.stop_reason == spk.STOP_MAX_ITERS
+    assert rel(x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("m", [30, 5])
+def test_gmres_converged_parity(spk, ctx, name, m):
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 2)
+    x, log, hist = gmres(spk, ctx, A, b, m=m, tau=1e-12, history=True)
+    xo, ro, ho = oracle.gmres(A, b, tau=1e-12, m=m, history=True)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert rel(x, xo) <= 1e-12
+    k = min(hist.size, ho.size)
+    assert np.all(np.abs(hist[:k] - ho[:k]) <= 0.01 * ho[:k])
+    assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-12 * log.rhs_norm
+    assert log.true_resnorm <= 10 * 1e-12 * log.rhs_norm
+
+
+def test_gmres_nonzero_guess_and_reruns_bitwise(spk, ctx):
+    A = inputs.stencil7_ns(30, 4)
+    b = inputs.rhs(A.n_rows, 4)
+    x0 = inputs.vec(A.n_rows, 4, 20)
+    runs = [gmres(spk, ctx, A, b, m=8, x0=x0, tau=1e-12) for _ in range(3)]
+    for x, log, _ in runs[1:]:
+        assert np.array_equal(x.view(np.uint64), runs[0][0].view(np.uint64))
+        assert log.iterations == runs[0][1].iterations
+    xo, ro, _ = oracle.gmres(A, b, x0=x0, tau=1e-12, m=8)
+    assert abs(runs[0][1].iterations - ro.iterations) <= 1 and rel(runs[0][0], xo) <= 1e-12
+
+
+def test_gmres_diag_distinct_terminates(spk, ctx):
+    d = np.repeat(np.array([1.0, 2.0, 3.5, 6.0, 9.0]), 300)
+    b = np.array([inputs.unif(8, 28, i) for i in range(d.size)])
+    x, log, _ = gmres(spk, ctx, inputs.diagonal(d), b, tau=1e-12, max_iters=50)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 5
+    assert rel(x, b / d) <= 1e-12
+
+
+def test_gmres_stop_semantics(spk, ctx):
+    A = inputs.stencil7_ns(9, 7)
+    n = A.n_rows
+    b = inputs.rhs(n, 7)
+    x0 = inputs.vec(n, 7, 21)
+    x, log, h = gmres(spk, ctx, A, b, x0=x0, max_iters=0, history=True)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 0 and np.array_equal(x, x0)
+    x, log, _ = gmres(spk, ctx, A, np.zeros(n), x0=x0)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations == 0 and not x.any()
+    bb = b.copy()
+    bb[3] = np.nan
+    _, log, _ = gmres(spk, ctx, A, bb)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+    # the cap inside a cycle still applies the columns built
+    x, log, _ = gmres(spk, ctx, A, b, m=5, tau=1e-15, max_iters=7)
+    xo, _, _ = oracle.gmres(A, b, tau=1e-15, max_iters=7, m=5)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 7 and rel(x, xo) <= 1e-12
+
+
+def test_gmres_plan_errors(spk, ctx):
+    M = dev_csr(spk, inputs.stencil7_ns(6, 0))
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = spk.SOLVER_GMRES
+    for bad in (0, 33, -1):
+        cfg.krylov_dim = bad
+        with pytest.raises(spk.SpkError):
+            spk.spk_plan_solve(ctx, M, cfg)
+    cfg.krylov_dim = 30
+    cfg.precond = spk.PRECOND_JACOBI
+    with pytest.raises(spk.SpkError):
+        spk.spk_plan_solve(ctx, M, cfg)
+    cfg.precond = spk.PRECOND_NONE
+    cfg.precision = spk.PREC_MIXED_FP32
+    with pytest.raises(spk.SpkError):
+        spk.spk_plan_solve(ctx, M, cfg)
+
+
+def test_gmres_full_size_residual():
+    """Nonsymmetric stencil7 N=215: the converged GMRES(30) solution's true residual,
+    recomputed by the oracle's SpMV, meets the criterion; the first two iterates match
+    the oracle's."""
+    from paper_2510_08230_amd import spk
+    ctx = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        A = inputs.stencil7_ns(215, 1)
+        b = inputs.rhs(A.n_rows, 1)
+        M = dev_csr(spk, A, ptr="i32")
+        x, log, _ = gmres(spk, ctx, A, b, tau=1e-12, M=M)
+        assert log.stop_reason == spk.STOP_CONVERGED
+        assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-12 * log.rhs_norm
+        x2, _, _ = gmres(spk, ctx, A, b, tau=0.0, max_iters=2, M=M)
+        xo, _, _ = oracle.gmres(A, b, tau=0.0, max_iters=2, m=30)
+        assert rel(x2, xo) <= 1e-12
+    finally:
+        spk.spk_finalize(ctx)
