@@ -1,13 +1,14 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
   python -m paper_2510_08230_amd.profsum stats  KERNEL_STATS_CSV [--trace KERNEL_TRACE_CSV] --cmd "..."
-  python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B --cmd "..."
+  python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B [--last N] --cmd "..."
 
 ``stats`` renders the per-kernel duration table.  ``traffic`` reports the
 median FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dispatches of one
 kernel, scaled by what the same counters read for the library's plain copy
-kernel (k_copy16) of known size, plus the kernel-source digest the numbers
-belong to (the benchmark drops them once the sources change).
+kernel (k_copy16) of known size, plus the digest of the sources the CG
+SpMV kernel is built from (the benchmark drops the figures once those
+sources change).
 """
 from __future__ import annotations
 
@@ -19,9 +20,7 @@ import os
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_krylov.hip", "csrc/spk_gmres.hip", "csrc/spk_spmv.h",
-                  "csrc/spk_device.h",
-                  "csrc/spk_internal.h"]
+KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_spmv.h", "csrc/spk_device.h", "csrc/spk_internal.h"]
 
 
 def kernel_digest() -> str:
@@ -73,28 +72,38 @@ def working_launches_md(trace_csv: str, top: int = 8) -> str:
 
 
 def _per_kernel(path: str, counter: str):
-    vals = {}
+    """Kernel name -> counter values in dispatch order."""
+    rows = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    vals = {}
+    for _, name, v in rows:
+        vals.setdefault(name, []).append(v)
     return vals
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, last: int = 20) -> dict:
+    """Median counter value of the last `last` working dispatches of the kernel
+    whose name contains `kernel` (the timed loop's, after any tuning runs),
+    scaled by the copy kernel's reading of a known size."""
     f = _per_kernel(fetch_csv, "FETCH_SIZE")
     w = _per_kernel(write_csv, "WRITE_SIZE")
 
-    def pick(d, sub):
+    def pick(d, sub, tail=last):
         got = [v for k, v in d.items() if sub in k]
         if not got:
             raise SystemExit("no dispatch of %r in the counter CSV" % sub)
-        vals = [x for lst in got for x in lst]
-        top = max(vals)
-        return statistics.median([x for x in vals if x > 0.5 * top])   # drop launches that returned at once
+        if len(got) > 1:
+            raise SystemExit("%r matches %d kernels; name one" % (sub, len(got)))
+        vals = got[0]
+        work = [x for x in vals if x > 0.01 * max(vals)]   # drop launches that returned at once
+        return statistics.median(work[-tail:] if tail else work)
 
-    copy_f = pick(f, "k_copy16")
-    copy_w = pick(w, "k_copy16")
+    copy_f = pick(f, "k_copy16", 0)
+    copy_w = pick(w, "k_copy16", 0)
     scale_f = copy_bytes / (copy_f * 1024.0)
     scale_w = copy_bytes / (copy_w * 1024.0)
     kf = pick(f, kernel)
@@ -117,6 +126,7 @@ def main():
     t.add_argument("write_csv")
     t.add_argument("--kernel", required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--last", type=int, default=20, help="use the kernel's last N working dispatches")
     t.add_argument("--cmd", required=True)
     a = ap.parse_args()
     if a.what == "stats":
@@ -124,7 +134,7 @@ def main():
         if a.trace:
             print(working_launches_md(a.trace), end="")
     else:
-        d = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
+        d = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.last)
         d["command"] = a.cmd
         print(json.dumps(d, indent=1))
 
