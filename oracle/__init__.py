@@ -70,6 +70,10 @@ def load(path: str = _LIB):
     lib.orc_pcg_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
     lib.orc_gmres.restype = ctypes.c_int
     lib.orc_gmres.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_cgs_jacobi.restype = ctypes.c_int
+    lib.orc_cgs_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
+    lib.orc_gmres_jacobi.restype = ctypes.c_int
+    lib.orc_gmres_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, i64, ctypes.POINTER(CGResult), vp]
     lib.orc_diagonal.restype = None
     lib.orc_diagonal.argtypes = [i64, vp, vp, vp, vp]
     lib.orc_coo_spmv.restype = None
@@ -178,19 +182,24 @@ class Oracle:
         """CG preconditioned by diag(A).  Returns (x, CGResult, hist or None)."""
         return self._krylov(self.lib.orc_pcg_jacobi, A, b, x0, tau, max_iters, history)
 
-    def gmres(self, A, b, x0=None, tau=1e-14, max_iters=10000, m=30, history=False):
-        """Restarted GMRES(m), MGS Arnoldi, Givens rotations.  Returns (x, CGResult, hist or None)."""
+    def gmres(self, A, b, x0=None, tau=1e-14, max_iters=10000, m=30, history=False, jacobi=False):
+        """Restarted GMRES(m), MGS Arnoldi, Givens rotations; jacobi: M = diag(A) on the right.
+        Returns (x, CGResult, hist or None)."""
         rp, ci, va = _csr64(A)
         n = A.n_rows
         b = np.ascontiguousarray(b, np.float64)
         x = np.zeros(n) if x0 is None else np.array(x0, np.float64, copy=True)
         res = CGResult()
         hist = np.full(max_iters + 1, np.nan) if history else None
-        self.lib.orc_gmres(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tau), int(max_iters), int(m),
-                           ctypes.byref(res), _p(hist))
+        fn = self.lib.orc_gmres_jacobi if jacobi else self.lib.orc_gmres
+        fn(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tau), int(max_iters), int(m), ctypes.byref(res), _p(hist))
         if hist is not None:
             hist = hist[: res.iterations + 1]
         return x, res, hist
+
+    def cgs_jacobi(self, A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+        """CGS with M = diag(A) on the right.  Returns (x, CGResult, hist or None)."""
+        return self._krylov(self.lib.orc_cgs_jacobi, A, b, x0, tau, max_iters, history)
 
     def diagonal(self, A) -> np.ndarray:
         rp, ci, va = _csr64(A)
@@ -255,8 +264,12 @@ def diagonal(A):
     return default().diagonal(A)
 
 
-def gmres(A, b, x0=None, tau=1e-14, max_iters=10000, m=30, history=False):
-    return default().gmres(A, b, x0, tau, max_iters, m, history)
+def gmres(A, b, x0=None, tau=1e-14, max_iters=10000, m=30, history=False, jacobi=False):
+    return default().gmres(A, b, x0, tau, max_iters, m, history, jacobi)
+
+
+def cgs_jacobi(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):
+    return default().cgs_jacobi(A, b, x0, tau, max_iters, history)
 
 
 def csr_validate(n_rows, n_cols, nnz, row_ptr, col):

@@ -232,9 +232,9 @@ done:
  *     x_i = x_{i-1} + alpha uh;  r_i = r_{i-1} - alpha A uh
  * with the stop test on ||r_i|| <= tau ||b|| or i == max_iters.
  */
-int orc_cgs(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
-            const double *b, double *x, double tau, int64_t max_iters,
-            orc_cg_result *res, double *hist) {
+static int cgs_core(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+                    const double *b, double *x, double tau, int64_t max_iters,
+                    orc_cg_result *res, double *hist, const double *d) {
     const size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *r = (double *)malloc(bytes), *rt = (double *)malloc(bytes), *p = (double *)malloc(bytes);
     double *u = (double *)malloc(bytes), *q = (double *)malloc(bytes), *v = (double *)malloc(bytes);
@@ -277,13 +277,20 @@ int orc_cgs(int64_t n, const int64_t *row_ptr, const int64_t *col, const double 
             for (int64_t i = 0; i < n; ++i) u[i] = r[i] + beta * q[i];
             for (int64_t i = 0; i < n; ++i) p[i] = u[i] + beta * (q[i] + beta * p[i]);
         }
-        orc_spmv(n, row_ptr, col, val, p, v);
+        if (d) {   /* v = A M^{-1} p */
+            for (int64_t i = 0; i < n; ++i) qh[i] = p[i] / d[i];
+            orc_spmv(n, row_ptr, col, val, qh, v);
+        } else {
+            orc_spmv(n, row_ptr, col, val, p, v);
+        }
         const double sigma = dot(n, rt, v);
         if (!isfinite(sigma)) { reason = ORC_NON_FINITE; break; }
         if (sigma == 0.0) { reason = ORC_BREAKDOWN; break; }
         const double alpha = rho / sigma;
         for (int64_t i = 0; i < n; ++i) q[i] = u[i] - alpha * v[i];
         for (int64_t i = 0; i < n; ++i) uh[i] = u[i] + q[i];
+        if (d)     /* uh = M^{-1} (u + q) */
+            for (int64_t i = 0; i < n; ++i) uh[i] = uh[i] / d[i];
         for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * uh[i];
         orc_spmv(n, row_ptr, col, val, uh, qh);
         for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * qh[i];
@@ -310,6 +317,13 @@ done:
     return reason;
 }
 
+int orc_cgs(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+            const double *b, double *x, double tau, int64_t max_iters,
+            orc_cg_result *res, double *hist) {
+    return cgs_core(n, row_ptr, col, val, b, x, tau, max_iters, res, hist, NULL);
+}
+
+
 /*
  * Diagonal of A: d_i = sum of the stored entries of row i in column i (0 when
  * there is none).
@@ -321,6 +335,49 @@ void orc_diagonal(int64_t n, const int64_t *row_ptr, const int64_t *col, const d
             if (col[k] == i) s += val[k];
         d[i] = s;
     }
+}
+
+/*
+ * CGS (here) and GMRES(m) (after gmres_core) with the scalar Jacobi
+ * preconditioner M = diag(A) applied on the right (Barrett et al.'s preconditioned CGS template; Saad, Alg. 9.5
+ * for GMRES): the iteration runs on A M^{-1} and the residual it tests is
+ * the unpreconditioned b - A x.  A zero or non-finite diagonal entry stops
+ * with ORC_BREAKDOWN before the first iteration, x unchanged (after the
+ * non-finite-||b|| check, as in orc_pcg_jacobi).
+ */
+static int jacobi_diag_ok(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+                          const double *b, double *x, orc_cg_result *res, double **d_out) {
+    const double bnorm = sqrt(dot(n, b, b));
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    orc_diagonal(n, row_ptr, col, val, d);
+    int ok = isfinite(bnorm) ? 1 : 0;   /* a non-finite ||b|| is left to the solver's own check */
+    for (int64_t i = 0; ok && i < n; ++i)
+        if (d[i] == 0.0 || !isfinite(d[i])) ok = -1;
+    if (ok == -1) {
+        res->iterations = 0;
+        res->stop_reason = ORC_BREAKDOWN;
+        res->rhs_norm = bnorm;
+        res->implicit_resnorm = NAN;
+        double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        orc_residual(n, row_ptr, col, val, b, x, r);
+        res->true_resnorm = sqrt(dot(n, r, r));
+        free(r);
+        free(d);
+        *d_out = NULL;
+        return 0;
+    }
+    *d_out = d;
+    return 1;
+}
+
+int orc_cgs_jacobi(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+                   const double *b, double *x, double tau, int64_t max_iters,
+                   orc_cg_result *res, double *hist) {
+    double *d = NULL;
+    if (!jacobi_diag_ok(n, row_ptr, col, val, b, x, res, &d)) return res->stop_reason;
+    const int reason = cgs_core(n, row_ptr, col, val, b, x, tau, max_iters, res, hist, d);
+    free(d);
+    return reason;
 }
 
 /*
@@ -434,9 +491,9 @@ done:
  * The triangular solve uses the columns built in the cycle (a cap in the
  * middle of a cycle still updates x).
  */
-int orc_gmres(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
-              const double *b, double *x, double tau, int64_t max_iters, int64_t m,
-              orc_cg_result *res, double *hist) {
+static int gmres_core(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+                      const double *b, double *x, double tau, int64_t max_iters, int64_t m,
+                      orc_cg_result *res, double *hist, const double *d) {
     if (m < 1) m = 1;
     const size_t vb = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *V = (double *)malloc(vb * (size_t)(m + 1));
@@ -446,6 +503,7 @@ int orc_gmres(int64_t n, const int64_t *row_ptr, const int64_t *col, const doubl
     double *sn = (double *)malloc(sizeof(double) * (size_t)m);
     double *g = (double *)malloc(sizeof(double) * (size_t)(m + 1));
     double *y = (double *)malloc(sizeof(double) * (size_t)m);
+    double *y_n = (double *)malloc(vb);   /* M^{-1}-scaled work vector */
     int64_t k = 0;
     int reason = ORC_RUNNING;
     double resnorm = 0.0;
@@ -478,7 +536,12 @@ int orc_gmres(int64_t n, const int64_t *row_ptr, const int64_t *col, const doubl
         int64_t used = 0;
         for (int64_t j = 0; j < m; ++j) {
             const double *vj = V + (size_t)j * (size_t)n;
-            orc_spmv(n, row_ptr, col, val, vj, w);
+            if (d) {   /* w = A M^{-1} v_j */
+                for (int64_t t = 0; t < n; ++t) y_n[t] = vj[t] / d[t];
+                orc_spmv(n, row_ptr, col, val, y_n, w);
+            } else {
+                orc_spmv(n, row_ptr, col, val, vj, w);
+            }
             for (int64_t i = 0; i <= j; ++i) {
                 const double *vi = V + (size_t)i * (size_t)n;
                 const double h = dot(n, w, vi);
@@ -516,9 +579,18 @@ int orc_gmres(int64_t n, const int64_t *row_ptr, const int64_t *col, const doubl
             for (int64_t t = i + 1; t < used; ++t) s -= H[i * m + t] * y[t];
             y[i] = s / H[i * m + i];
         }
-        for (int64_t i = 0; i < used; ++i) {
-            const double *vi = V + (size_t)i * (size_t)n;
-            for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y[i] * vi[t];
+        if (d) {   /* x += M^{-1} (V y) */
+            for (int64_t t = 0; t < n; ++t) y_n[t] = 0.0;
+            for (int64_t i = 0; i < used; ++i) {
+                const double *vi = V + (size_t)i * (size_t)n;
+                for (int64_t t = 0; t < n; ++t) y_n[t] = y_n[t] + y[i] * vi[t];
+            }
+            for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y_n[t] / d[t];
+        } else {
+            for (int64_t i = 0; i < used; ++i) {
+                const double *vi = V + (size_t)i * (size_t)n;
+                for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y[i] * vi[t];
+            }
         }
     }
 
@@ -532,9 +604,26 @@ done:
     } else {
         res->true_resnorm = (n > 0) ? NAN : 0.0;
     }
-    free(V); free(w); free(H); free(cs); free(sn); free(g); free(y);
+    free(V); free(w); free(H); free(cs); free(sn); free(g); free(y); free(y_n);
     return reason;
 }
+
+int orc_gmres(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+              const double *b, double *x, double tau, int64_t max_iters, int64_t m,
+              orc_cg_result *res, double *hist) {
+    return gmres_core(n, row_ptr, col, val, b, x, tau, max_iters, m, res, hist, NULL);
+}
+
+int orc_gmres_jacobi(int64_t n, const int64_t *row_ptr, const int64_t *col, const double *val,
+                     const double *b, double *x, double tau, int64_t max_iters, int64_t m,
+                     orc_cg_result *res, double *hist) {
+    double *d = NULL;
+    if (!jacobi_diag_ok(n, row_ptr, col, val, b, x, res, &d)) return res->stop_reason;
+    const int reason = gmres_core(n, row_ptr, col, val, b, x, tau, max_iters, m, res, hist, d);
+    free(d);
+    return reason;
+}
+
 
 /*
  * nnz-balanced row partition into P parts:

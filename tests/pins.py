@@ -530,6 +530,71 @@ def pin_gmres_stop_semantics(orc):
     assert r.stop_reason == 4
 
 
+# ----------------------------------------------------------------- right-preconditioned CGS / GMRES
+def _ns_scaled(N, seed):
+    """Nonsymmetric stencil with rows scaled by positive factors 1..8: a varying diagonal."""
+    A = inputs.stencil7_ns(N, seed)
+    s = np.array([2.0 ** (inputs.unif(seed, 29, i) * 3) for i in range(A.n_rows)])
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    B = inputs.CSR(A.n_rows, A.n_cols, A.row_ptr.copy(), A.col.copy(), A.val * s[rows])
+    return B, B.to_dense()
+
+
+def pin_gmres_jacobi_least_squares(orc):
+    """Right-preconditioned GMRES: x_k = x0 + D^{-1} z with z minimising ||r0 - A D^{-1} z|| over
+    K_k(A D^{-1}, r0) (dense least squares); the estimate equals the true residual."""
+    A, D = _ns_scaled(3, 8)
+    b = inputs.rhs(A.n_rows, 8)
+    x0 = inputs.vec(A.n_rows, 8, 20)
+    dinv = 1.0 / np.diag(D)
+    Ah = D * dinv[None, :]
+    r0 = b - D @ x0
+    for k in (1, 3, 6):
+        K = np.column_stack([np.linalg.matrix_power(Ah, j) @ r0 for j in range(k)])
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(Ah @ Q, r0, rcond=None)
+        xr = x0 + dinv * (Q @ y)
+        x, r, h = orc.gmres(A, b, x0=x0, tau=0.0, max_iters=k, m=30, history=True, jacobi=True)
+        assert r.iterations == k and _rel(x, xr) <= 1e-9, (k, _rel(x, xr))
+        assert abs(h[k] - np.linalg.norm(b - D @ xr)) <= 1e-9 * np.linalg.norm(b)
+
+
+def pin_cgs_jacobi_first_step(orc):
+    """Right-preconditioned CGS, one step: with Ah = A D^{-1}, alpha = r0.r0 / r0.Ah r0,
+    x1 = x0 + alpha D^{-1} (2 r0 - alpha Ah r0), r1 = (I - alpha Ah)^2 r0."""
+    A, D = _ns_scaled(3, 9)
+    b = inputs.rhs(A.n_rows, 9)
+    x0 = inputs.vec(A.n_rows, 9, 20)
+    dinv = 1.0 / np.diag(D)
+    Ah = D * dinv[None, :]
+    r0 = b - D @ x0
+    Ar = Ah @ r0
+    alpha = (r0 @ r0) / (r0 @ Ar)
+    x1 = x0 + alpha * dinv * (2 * r0 - alpha * Ar)
+    r1 = r0 - 2 * alpha * Ar + alpha * alpha * (Ah @ Ar)
+    x, r, h = orc.cgs_jacobi(A, b, x0=x0, tau=0.0, max_iters=1, history=True)
+    assert r.iterations == 1 and _rel(x, x1) <= 1e-13
+    assert abs(h[1] - np.linalg.norm(r1)) <= 1e-12 * np.linalg.norm(r1)
+
+
+def pin_right_jacobi_solves_and_breakdown(orc):
+    A, D = _ns_scaled(4, 10)
+    b = inputs.rhs(A.n_rows, 10)
+    xs = np.linalg.solve(D, b)
+    cond = np.linalg.cond(D)
+    x, r, _ = orc.cgs_jacobi(A, b, tau=1e-11, max_iters=500)
+    assert r.stop_reason == 1 and _rel(x, xs) <= 10 * cond * 1e-11 and r.true_resnorm <= 2e-11 * r.rhs_norm
+    x, r, _ = orc.gmres(A, b, tau=1e-11, max_iters=500, m=10, jacobi=True)
+    assert r.stop_reason == 1 and _rel(x, xs) <= 10 * cond * 1e-11 and r.true_resnorm <= 2e-11 * r.rhs_norm
+    _, rc, _ = orc.gmres(A, b, tau=1e-11, max_iters=500, m=10)
+    assert r.iterations < rc.iterations   # the row scaling is what Jacobi undoes
+    Z = inputs.diagonal(np.array([1.0, 0.0, 2.0]))
+    x0 = np.array([1.0, 2.0, 3.0])
+    for f in (lambda **k: orc.cgs_jacobi(Z, np.ones(3), **k), lambda **k: orc.gmres(Z, np.ones(3), jacobi=True, **k)):
+        x, r, _ = f(x0=x0, tau=1e-12)
+        assert r.stop_reason == 3 and r.iterations == 0 and np.array_equal(x, x0)
+
+
 # ----------------------------------------------------------------- Jacobi PCG
 def _scaled_spd(n, seed):
     """S A S with S a positive diagonal: SPD with a strongly varying diagonal."""

@@ -65,44 +65,55 @@ MUTANTS = [
      "int orc_coo_validate("),
     # CGS
     ("cgs beta transposed", "const double beta = rho / rho_prev;", "const double beta = rho_prev / rho;",
-     "int orc_cgs("),
-    ("cgs u uses p", "u[i] = r[i] + beta * q[i];", "u[i] = r[i] + beta * p[i];", "int orc_cgs("),
+     "static int cgs_core("),
+    ("cgs u uses p", "u[i] = r[i] + beta * q[i];", "u[i] = r[i] + beta * p[i];", "static int cgs_core("),
     ("cgs p drops beta squared", "p[i] = u[i] + beta * (q[i] + beta * p[i]);", "p[i] = u[i] + beta * (q[i] + p[i]);",
-     "int orc_cgs("),
-    ("cgs q sign", "q[i] = u[i] - alpha * v[i];", "q[i] = u[i] + alpha * v[i];", "int orc_cgs("),
-    ("cgs uh drops q", "uh[i] = u[i] + q[i];", "uh[i] = u[i];", "int orc_cgs("),
-    ("cgs x update uses u", "x[i] = x[i] + alpha * uh[i];", "x[i] = x[i] + alpha * u[i];", "int orc_cgs("),
-    ("cgs r update sign", "r[i] = r[i] - alpha * qh[i];", "r[i] = r[i] + alpha * qh[i];", "int orc_cgs("),
+     "static int cgs_core("),
+    ("cgs q sign", "q[i] = u[i] - alpha * v[i];", "q[i] = u[i] + alpha * v[i];", "static int cgs_core("),
+    ("cgs uh drops q", "uh[i] = u[i] + q[i];", "uh[i] = u[i];", "static int cgs_core("),
+    ("cgs x update uses u", "x[i] = x[i] + alpha * uh[i];", "x[i] = x[i] + alpha * u[i];", "static int cgs_core("),
+    ("cgs r update sign", "r[i] = r[i] - alpha * qh[i];", "r[i] = r[i] + alpha * qh[i];", "static int cgs_core("),
     ("cgs sigma uses r", "const double sigma = dot(n, rt, v);", "const double sigma = dot(n, r, v);",
-     "int orc_cgs("),
-    ("cgs rho uses r.r", "const double rho = dot(n, rt, r);", "const double rho = dot(n, r, r);", "int orc_cgs("),
-    ("cgs rho_prev not carried", "rho_prev = rho;\n", "\n", "int orc_cgs("),
-    ("cgs shadow is b", "rt[i] = r[i];", "rt[i] = b[i];", "int orc_cgs("),
-    ("cgs sigma breakdown dropped", "if (sigma == 0.0) { reason = ORC_BREAKDOWN; break; }", "", "int orc_cgs("),
+     "static int cgs_core("),
+    ("cgs rho uses r.r", "const double rho = dot(n, rt, r);", "const double rho = dot(n, r, r);", "static int cgs_core("),
+    ("cgs rho_prev not carried", "rho_prev = rho;\n", "\n", "static int cgs_core("),
+    ("cgs shadow is b", "rt[i] = r[i];", "rt[i] = b[i];", "static int cgs_core("),
+    ("cgs sigma breakdown dropped", "if (sigma == 0.0) { reason = ORC_BREAKDOWN; break; }", "", "static int cgs_core("),
     ("cgs cap off by one", "if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }",
-     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }", "int orc_cgs("),
-    ("cgs history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "int orc_cgs("),
+     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }", "static int cgs_core("),
+    ("cgs history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "static int cgs_core("),
     # GMRES
     ("gmres projection sign", "for (int64_t t = 0; t < n; ++t) w[t] = w[t] - h * vi[t];",
-     "for (int64_t t = 0; t < n; ++t) w[t] = w[t] + h * vi[t];", "int orc_gmres("),
+     "for (int64_t t = 0; t < n; ++t) w[t] = w[t] + h * vi[t];", "static int gmres_core("),
     ("gmres projection uses v_j", "const double h = dot(n, w, vi);", "const double h = dot(n, w, vj);",
-     "int orc_gmres("),
+     "static int gmres_core("),
     ("gmres old rotations skipped", "for (int64_t i = 0; i < j; ++i) {\n                const double a",
-     "for (int64_t i = 0; i < 0; ++i) {\n                const double a", "int orc_gmres("),
+     "for (int64_t i = 0; i < 0; ++i) {\n                const double a", "static int gmres_core("),
     ("gmres rotation sign", "H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;", "H[(i + 1) * m + j] = sn[i] * a + cs[i] * c;",
-     "int orc_gmres("),
-    ("gmres g update sign", "g[j + 1] = -sn[j] * g[j];", "g[j + 1] = sn[j] * g[j];", "int orc_gmres("),
-    ("gmres g not rotated", "g[j] = cs[j] * g[j];", ";", "int orc_gmres("),
+     "static int gmres_core("),
+    ("gmres g update sign", "g[j + 1] = -sn[j] * g[j];", "g[j + 1] = sn[j] * g[j];", "static int gmres_core("),
+    ("gmres g not rotated", "g[j] = cs[j] * g[j];", ";", "static int gmres_core("),
     ("gmres back substitution index", "for (int64_t t = i + 1; t < used; ++t) s -= H[i * m + t] * y[t];",
-     "for (int64_t t = i + 1; t < used; ++t) s -= H[t * m + i] * y[t];", "int orc_gmres("),
+     "for (int64_t t = i + 1; t < used; ++t) s -= H[t * m + i] * y[t];", "static int gmres_core("),
     ("gmres basis not normalised", "for (int64_t t = 0; t < n; ++t) vn[t] = w[t] / hnext;",
-     "for (int64_t t = 0; t < n; ++t) vn[t] = w[t];", "int orc_gmres("),
-    ("gmres x update drops last column", "for (int64_t i = 0; i < used; ++i) {\n            const double *vi",
-     "for (int64_t i = 0; i + 1 < used; ++i) {\n            const double *vi", "int orc_gmres("),
+     "for (int64_t t = 0; t < n; ++t) vn[t] = w[t];", "static int gmres_core("),
+    ("gmres x update drops last column", "for (int64_t i = 0; i < used; ++i) {\n                const double *vi",
+     "for (int64_t i = 0; i + 1 < used; ++i) {\n                const double *vi", "static int gmres_core("),
     ("gmres restart keeps old residual", "orc_residual(n, row_ptr, col, val, b, x, V);\n        const double beta",
-     "if (k == 0) orc_residual(n, row_ptr, col, val, b, x, V);\n        const double beta", "int orc_gmres("),
+     "if (k == 0) orc_residual(n, row_ptr, col, val, b, x, V);\n        const double beta", "static int gmres_core("),
     ("gmres cap off by one", "if (k >= max_iters) { reason = ORC_MAX_ITERS; break; }\n            if (hnext",
-     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }\n            if (hnext", "int orc_gmres("),
+     "if (k > max_iters) { reason = ORC_MAX_ITERS; break; }\n            if (hnext", "static int gmres_core("),
+    # right-preconditioned (Jacobi) CGS and GMRES
+    ("cgs jacobi p not scaled", "for (int64_t i = 0; i < n; ++i) qh[i] = p[i] / d[i];",
+     "for (int64_t i = 0; i < n; ++i) qh[i] = p[i];", "static int cgs_core("),
+    ("cgs jacobi uh scaled twice", "for (int64_t i = 0; i < n; ++i) uh[i] = uh[i] / d[i];",
+     "for (int64_t i = 0; i < n; ++i) uh[i] = uh[i] / (d[i] * d[i]);", "static int cgs_core("),
+    ("gmres jacobi v not scaled", "for (int64_t t = 0; t < n; ++t) y_n[t] = vj[t] / d[t];",
+     "for (int64_t t = 0; t < n; ++t) y_n[t] = vj[t];", "static int gmres_core("),
+    ("gmres jacobi x update unscaled", "for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y_n[t] / d[t];",
+     "for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y_n[t];", "static int gmres_core("),
+    ("jacobi zero diagonal accepted", "if (d[i] == 0.0 || !isfinite(d[i])) ok = -1;",
+     "if (!isfinite(d[i])) ok = -1;", "static int jacobi_diag_ok("),
     # Jacobi PCG
     ("diagonal keeps last duplicate", "if (col[k] == i) s += val[k];", "if (col[k] == i) s = val[k];",
      "void orc_diagonal("),
