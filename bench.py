@@ -178,11 +178,12 @@ def main():
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     last = logs[-1]
     traffic = measured_traffic(args, N)
+    jname = "_jacobi" if args.precond == "jacobi" else ""
     if cgs:
-        workload = "cgs_fp64_stencil7ns_N%d" % N
+        workload = "cgs%s_fp64_stencil7ns_N%d" % (jname, N)
         spmv_kernel = "k_spmv_*<EpiCgsV>, k_spmv_*<EpiCgsR> (two SpMVs per CGS iteration)"
     elif gm:
-        workload = "gmres%d_fp64_stencil7ns_N%d" % (args.krylov_dim, N)
+        workload = "gmres%d%s_fp64_stencil7ns_N%d" % (args.krylov_dim, jname, N)
         spmv_kernel = "k_spmv_*<EpiGmW> (w = A v_j / ||v_j||, one per Arnoldi step)"
     else:
         workload = "%s_%s_stencil7_N%d" % ("pcg_jacobi" if args.precond == "jacobi" else "cg", args.precision, N)
@@ -226,13 +227,15 @@ def main():
         # the oracle converged, else against a GPU run of the same fixed
         # number of iterations (untimed).
         import oracle
+        jac = args.precond == "jacobi"
         fn, label = oracle.cg, "CG"
         if cgs:
-            fn, label = oracle.cgs, "CGS"
+            fn, label = (oracle.cgs_jacobi, "CGS with Jacobi on the right") if jac else (oracle.cgs, "CGS")
         elif gm:
-            fn, label = (lambda A_, b_, tau, max_iters: oracle.gmres(A_, b_, tau=tau, max_iters=max_iters,
-                                                                   m=args.krylov_dim)), "GMRES(%d)" % args.krylov_dim
-        elif args.precond == "jacobi":
+            fn = (lambda A_, b_, tau, max_iters: oracle.gmres(A_, b_, tau=tau, max_iters=max_iters,
+                                                             m=args.krylov_dim, jacobi=jac))
+            label = "GMRES(%d)%s" % (args.krylov_dim, " with Jacobi on the right" if jac else "")
+        elif jac:
             fn, label = oracle.pcg_jacobi, "Jacobi PCG"
         cap = args.cpu_iters if args.cpu_iters > 0 else (12 if gm else 60)
         t0 = time.perf_counter()
@@ -407,8 +410,8 @@ def large(args):
     wall = time.perf_counter() - t0
     spk.spk_finalize(ctx)
     bytes_spmv = nnz * 8 + (n + 1) * 8 + 2 * n * 4
-    avg = kms / max(kl, 1)
-    achieved = bytes_spmv / (avg * 1e-3) / 1e9
+    avg = kms / kl if kl else None
+    achieved = bytes_spmv / (avg * 1e-3) / 1e9 if avg else None
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
         "value": n * iters / wall, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -420,7 +423,8 @@ def large(args):
                    "rel_true_residual": log.true_resnorm / log.rhs_norm, "solve_device_ms": log.elapsed_ms,
                    "spmv_tiling": info, "hbm_bytes_resident_est": (n + 1) * 8 + nnz * 8 + 2 * n * 8 + 4 * n * 4},
         "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq<float>> (inner q = A32 p fused with p.q)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": None, "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg, "launches": kl},
     }
     print(json.dumps(out), flush=True)

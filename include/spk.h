@@ -74,10 +74,10 @@ typedef enum {
 
 typedef enum {
     SPK_SOLVER_CG = 0,        /* conjugate gradient: A symmetric positive definite */
-    SPK_SOLVER_CGS = 1,       /* conjugate gradient squared: general nonsingular A; FP64,
-                                 no preconditioner; two SpMVs per iteration */
-    SPK_SOLVER_GMRES = 2      /* restarted GMRES(krylov_dim): general nonsingular A; FP64, no
-                                 preconditioner; iterations count Arnoldi steps and the stop test
+    SPK_SOLVER_CGS = 1,       /* conjugate gradient squared: general nonsingular A; FP64;
+                                 two SpMVs per iteration */
+    SPK_SOLVER_GMRES = 2      /* restarted GMRES(krylov_dim): general nonsingular A; FP64;
+                                 iterations count Arnoldi steps and the stop test
                                  uses the Givens residual estimate (the true residual at each
                                  restart) */
 } spk_solver;
@@ -89,8 +89,9 @@ typedef enum {
 typedef enum { SPK_BASELINE_RHS_NORM = 0 } spk_baseline;
 typedef enum {
     SPK_PRECOND_NONE = 0,
-    SPK_PRECOND_JACOBI = 1    /* scalar Jacobi, M = diag(A) (CG, FP64); the stop test stays
-                                 on the unpreconditioned residual ||r|| */
+    SPK_PRECOND_JACOBI = 1    /* scalar Jacobi, M = diag(A), FP64: CG applies it as PCG; CGS and
+                                 GMRES on the right (the plan keeps the values of A M^{-1}).
+                                 The stop test stays on the unpreconditioned residual ||r|| */
 } spk_precond;
 typedef enum {
     SPK_EXEC_AUTO = 0,        /* the library's choice: the host loop, which measured fastest */
@@ -220,10 +221,11 @@ spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
 /* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
  * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
  * an FP32/BF16 copy for the inner solve) or F32 values (taken as exact).
- * CGS, GMRES and the Jacobi preconditioner are FP64 only (GMRES and CGS
- * unpreconditioned, GMRES runs in the host loop); the Jacobi plan computes
- * 1 / diag(A) (a zero or non-finite diagonal entry makes every solve of the
- * plan stop with SPK_STOP_BREAKDOWN, x unchanged).
+ * CGS, GMRES and the Jacobi preconditioner are FP64 only (GMRES runs in the
+ * host loop); a Jacobi plan computes 1 / diag(A) (and for CGS and GMRES a
+ * scaled copy of the values, nnz doubles); a zero or non-finite diagonal
+ * entry makes every solve of the plan stop with SPK_STOP_BREAKDOWN, x
+ * unchanged.
  * Errors: INVALID_ARG, UNSUPPORTED (other solver / precision /
  * preconditioner combinations), OUT_OF_MEMORY. */
 spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg, spk_plan *out);

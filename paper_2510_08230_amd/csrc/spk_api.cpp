@@ -78,6 +78,10 @@ struct spk_plan_s {
     double *gm_V = nullptr, *gm_w = nullptr, *gm_part = nullptr;   // GMRES basis, work vector, partials
     spk::GmresState *gm_st = nullptr;    // GMRES small arrays
     unsigned *diag_flag = nullptr;       // Jacobi: nonzero = unusable diagonal
+    bool right_jacobi = false;           // CGS / GMRES on A M^{-1}, M = diag(A)
+    bool bad_diag = false;               // right Jacobi: unusable diagonal (every solve breaks down)
+    CsrDev A_orig{};                     // right Jacobi: the caller's matrix (A holds A M^{-1})
+    double *scaled_vals = nullptr;       // right Jacobi: values of A M^{-1}
     int64_t hist_cap = 0;
     SolveState *st = nullptr;
     SolveState *h_st = nullptr;          // pinned mirror
@@ -541,6 +545,8 @@ void release_workspace(spk_plan pl) {
     ctx->dpool.put(pl->dinv);
     ctx->dpool.put(pl->diag_flag);
     ctx->dpool.put(pl->coo_rp);
+    ctx->dpool.put(pl->scaled_vals);
+    pl->scaled_vals = nullptr;
     ctx->dpool.put(pl->gm_V);
     ctx->dpool.put(pl->gm_w);
     ctx->dpool.put(pl->gm_part);
@@ -814,8 +820,6 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         return fail(ctx, SPK_ERR_INVALID_ARG, "krylov_dim must be in 1..32");
     if (cfg.precond != SPK_PRECOND_NONE && cfg.precond != SPK_PRECOND_JACOBI)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown preconditioner");
-    if (cfg.solver != SPK_SOLVER_CG && cfg.precond != SPK_PRECOND_NONE)
-        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS and GMRES run unpreconditioned");
     if ((cfg.solver != SPK_SOLVER_CG || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
         return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS, GMRES and Jacobi CG run in FP64 precision");
     if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
@@ -895,6 +899,25 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             if (!dget(vbytes, &pl->gm_V) || !dget(nb, &pl->gm_w) || !dget(sizeof(spk::GmresState), &pl->gm_st) ||
                 !dget(sizeof(double) * (spk::kMaxKrylov + 1) * spk::kMaxGrid, &pl->gm_part))
                 return cleanup(SPK_ERR_OUT_OF_MEMORY, "GMRES workspace");
+        }
+        pl->right_jacobi = (pl->algo == ALGO_CGS || pl->algo == ALGO_GMRES) && cfg.precond == SPK_PRECOND_JACOBI;
+        if (pl->right_jacobi) {
+            // iterate on A M^{-1}: a scaled copy of the values, once per plan
+            pl->A_orig = pl->A;
+            if (!dget(nb, &pl->dinv) || !dget(sizeof(unsigned), &pl->diag_flag) ||
+                !dget(std::max<size_t>(1, sizeof(double) * A->nnz), &pl->scaled_vals))
+                return cleanup(SPK_ERR_OUT_OF_MEMORY, "Jacobi workspace");
+            if (hipMemsetAsync(pl->diag_flag, 0, sizeof(unsigned), ctx->stream) != hipSuccess ||
+                spk::launch_diag_inv(pl->A, pl->dinv, pl->diag_flag, ctx->stream) != hipSuccess ||
+                spk::launch_scale_cols(pl->A, pl->dinv, pl->scaled_vals, ctx->stream) != hipSuccess)
+                return cleanup(SPK_ERR_DEVICE, "Jacobi scaling");
+            unsigned flag = 0;
+            if (hipMemcpyAsync(&flag, pl->diag_flag, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess)
+                return cleanup(SPK_ERR_DEVICE, "Jacobi scaling");
+            pl->bad_diag = flag != 0;
+            pl->A.va = pl->scaled_vals;
         }
         if (pl->algo == ALGO_PCG) {
             if (!dget(nb, &pl->dinv) || !dget(sizeof(unsigned), &pl->diag_flag))
@@ -1021,8 +1044,32 @@ static spk_status run_gmres(spk_plan pl, const double *b, double *x) {
 static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log *L, bool graph) {
     spk_ctx ctx = pl->ctx;
     const spk_solver_cfg &cfg = pl->cfg;
+    const int64_t n = pl->A.n_rows;
     spk_status s = SPK_OK;
-    if (pl->persist_grid > 0) {
+    if (pl->right_jacobi && pl->bad_diag) {
+        // no preconditioner: the initial check reports the breakdown, x unchanged
+        SPK_HIP(ctx, spk::launch_pcg_init(pl->A_orig, pl->tune, b, x, pl->dinv, pl->diag_flag, pl->r, pl->p, pl->st,
+                                          pl->partials, cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap,
+                                          ctx->stream));
+        SPK_HIP(ctx, spk::launch_cg_finalize(pl->A_orig, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
+                                             ctx->stream));
+        if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
+    } else if (pl->right_jacobi) {
+        // solve A M^{-1} u = b for u = M x, then x = M^{-1} u; the residual of
+        // the scaled system is the caller's b - A x
+        SPK_HIP(ctx, spk::launch_jacobi_vec(n, x, pl->dinv, 1, ctx->stream));
+        if (pl->algo == ALGO_GMRES) {
+            if ((s = run_gmres(pl, b, x)) != SPK_OK) return s;
+        } else {
+            SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->rt, pl->st, pl->partials,
+                                             cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
+            if ((s = run_loop(pl, LOOP_CGS, cfg.max_iters, graph)) != SPK_OK) return s;
+        }
+        SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
+                                             ctx->stream));
+        SPK_HIP(ctx, spk::launch_jacobi_vec(n, x, pl->dinv, 0, ctx->stream));
+        if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
+    } else if (pl->persist_grid > 0) {
         // one cooperative launch; the barrier gives up after 2 s of waiting
         const uint64_t spin = static_cast<uint64_t>(ctx->wall_khz) * 2000ull;
         SPK_HIP(ctx, hipMemsetAsync(pl->bar, 0, 4 * sizeof(unsigned), ctx->stream));

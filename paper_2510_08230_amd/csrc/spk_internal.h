@@ -167,6 +167,10 @@ hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const double *V, Solv
 // finite).  Iteration j = launch_cg_spmv_pq, pcg_update(j), pcg_pupdate(j);
 // chunks end with launch_cg_chunk_end.
 hipError_t launch_diag_inv(const CsrDev &A, double *dinv, unsigned *flag, hipStream_t s);
+// Right preconditioning of CGS / GMRES by M = diag(A): out = A M^{-1}
+// values (F64, nnz), and x <- M x (to_u = 1) or x <- M^{-1} x (to_u = 0).
+hipError_t launch_scale_cols(const CsrDev &A, const double *dinv, double *out, hipStream_t s);
+hipError_t launch_jacobi_vec(int64_t n, double *x, const double *dinv, int to_u, hipStream_t s);
 hipError_t launch_pcg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, const double *dinv,
                            const unsigned *bad_diag, double *r, double *p, SolveState *st, double *partials,
                            double tau, int64_t max_iters, double *hist, int64_t hist_cap, hipStream_t s);

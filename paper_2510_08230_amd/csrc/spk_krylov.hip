@@ -238,6 +238,26 @@ __global__ __launch_bounds__(kBlock) void k_diag_inv(int64_t n, const P *__restr
     if (bad) flag[0] = 1u;   // plain store: every writer stores the same value
 }
 
+// Right preconditioning by M = diag(A): the scaled copy of the values,
+// out_k = val_k / d_{col_k} (as val_k * dinv_{col_k}).
+template <typename I>
+__global__ __launch_bounds__(kBlock) void k_scale_cols(int64_t nnz, const I *__restrict__ ci,
+                                                       const double *__restrict__ va, const double *__restrict__ dinv,
+                                                       double *__restrict__ out) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; k < nnz; k += stride)
+        out[k] = va[k] * dinv[static_cast<int64_t>(ci[k])];
+}
+
+// to_u = 1: x <- D x (= x / dinv), the unknown of the right-preconditioned
+// system; to_u = 0: x <- D^{-1} u (= u * dinv).
+__global__ __launch_bounds__(kBlock) void k_jacobi_vec(int64_t n, double *__restrict__ x,
+                                                       const double *__restrict__ dinv, int to_u) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride)
+        x[i] = to_u ? x[i] / dinv[i] : x[i] * dinv[i];
+}
+
 // r = b - A x, p = z = dinv r; partials of r.r, r.z and b.b.
 struct EpiPcgInit {
     const double *b, *dinv;
@@ -460,6 +480,24 @@ hipError_t launch_diag_inv(const CsrDev &A, double *dinv, unsigned *flag, hipStr
                            static_cast<const double *>(A.va), dinv, flag);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_scale_cols(const CsrDev &A, const double *dinv, double *out, hipStream_t s) {
+    if (A.nnz == 0) return hipSuccess;
+    const int grid = grid_for(A.nnz, 8, kMaxGrid);
+    if (A.idx_t == 0)
+        hipLaunchKernelGGL(k_scale_cols<int32_t>, dim3(grid), dim3(kBlock), 0, s, A.nnz,
+                           static_cast<const int32_t *>(A.ci), static_cast<const double *>(A.va), dinv, out);
+    else
+        hipLaunchKernelGGL(k_scale_cols<int64_t>, dim3(grid), dim3(kBlock), 0, s, A.nnz,
+                           static_cast<const int64_t *>(A.ci), static_cast<const double *>(A.va), dinv, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_vec(int64_t n, double *x, const double *dinv, int to_u, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jacobi_vec, dim3(grid_for(n, 8, kMaxGrid)), dim3(kBlock), 0, s, n, x, dinv, to_u);
+    return hipGetLastError();
 }
 
 hipError_t launch_pcg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, const double *dinv,

@@ -39,9 +39,10 @@ def ctx(spk):
     spk.spk_finalize(c)
 
 
-def gmres(spk, ctx, A, b, m=30, x0=None, tau=1e-14, max_iters=1000, history=False, M=None):
+def gmres(spk, ctx, A, b, m=30, x0=None, tau=1e-14, max_iters=1000, history=False, M=None, jacobi=False):
     cfg = spk.spk_solver_cfg_default()
     cfg.solver = spk.SOLVER_GMRES
+    cfg.precond = spk.PRECOND_JACOBI if jacobi else spk.PRECOND_NONE
     cfg.krylov_dim = m
     cfg.reduction_factor = tau
     cfg.max_iters = max_iters
@@ -134,13 +135,45 @@ def test_gmres_plan_errors(spk, ctx):
         with pytest.raises(spk.SpkError):
             spk.spk_plan_solve(ctx, M, cfg)
     cfg.krylov_dim = 30
-    cfg.precond = spk.PRECOND_JACOBI
-    with pytest.raises(spk.SpkError):
-        spk.spk_plan_solve(ctx, M, cfg)
-    cfg.precond = spk.PRECOND_NONE
     cfg.precision = spk.PREC_MIXED_FP32
     with pytest.raises(spk.SpkError):
         spk.spk_plan_solve(ctx, M, cfg)
+
+
+def row_scaled_ns(N, seed):
+    A = inputs.stencil7_ns(N, seed)
+    s = np.array([2.0 ** (inputs.unif(seed, 29, i) * 3) for i in range(A.n_rows)])
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    return inputs.CSR(A.n_rows, A.n_cols, A.row_ptr.copy(), A.col.copy(), A.val * s[rows])
+
+
+@pytest.mark.parametrize("m,K", [(30, 5), (30, 30), (30, 40), (6, 15)])
+def test_gmres_jacobi_fixed_k_iterates(spk, ctx, m, K):
+    A = row_scaled_ns(46, 5)
+    b = inputs.rhs(A.n_rows, 3)
+    x0 = inputs.vec(A.n_rows, 3, 20)
+    x, log, _ = gmres(spk, ctx, A, b, m=m, x0=x0, tau=0.0, max_iters=K, jacobi=True)
+    xo, ro, _ = oracle.gmres(A, b, x0=x0, tau=0.0, max_iters=K, m=m, jacobi=True)
+    assert log.iterations == K and log.stop_reason == spk.STOP_MAX_ITERS
+    assert rel(x, xo) <= 1e-12
+
+
+def test_gmres_jacobi_listing_configuration(spk, ctx):
+    """The configuration example of the paper (GMRES, Krylov dimension 30, Jacobi with block
+    size 1, at most 1000 iterations, residual reduction 1e-6 relative to ||b||)."""
+    A = row_scaled_ns(46, 7)
+    b = inputs.rhs(A.n_rows, 7)
+    x, log, hist = gmres(spk, ctx, A, b, m=30, tau=1e-6, max_iters=1000, history=True, jacobi=True)
+    xo, ro, ho = oracle.gmres(A, b, tau=1e-6, max_iters=1000, m=30, history=True, jacobi=True)
+    _, lu, _ = gmres(spk, ctx, A, b, m=30, tau=1e-6, max_iters=1000)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert log.iterations < lu.iterations
+    # at tau = 1e-6 one step more or less moves x by ~1e-6: compare at the GPU's step count
+    xk, _, _ = oracle.gmres(A, b, tau=0.0, max_iters=log.iterations, m=30, jacobi=True)
+    assert rel(x, xk) <= 1e-12
+    k = min(hist.size, ho.size)
+    assert np.all(np.abs(hist[:k] - ho[:k]) <= 0.01 * ho[:k])
+    assert log.true_resnorm <= 1e-6 * log.rhs_norm
 
 
 def test_gmres_full_size_residual():

@@ -153,10 +153,6 @@ def test_cgs_plan_errors(spk, ctx):
     M = dev_csr(spk, A)
     cfg = spk.spk_solver_cfg_default()
     cfg.solver = spk.SOLVER_CGS
-    cfg.precond = spk.PRECOND_JACOBI
-    with pytest.raises(spk.SpkError):
-        spk.spk_plan_solve(ctx, M, cfg)
-    cfg.precond = spk.PRECOND_NONE
     cfg.precision = spk.PREC_MIXED_FP32
     with pytest.raises(spk.SpkError):
         spk.spk_plan_solve(ctx, M, cfg)
@@ -164,6 +160,55 @@ def test_cgs_plan_errors(spk, ctx):
     cfg.solver = 7
     with pytest.raises(spk.SpkError):
         spk.spk_plan_solve(ctx, M, cfg)
+
+
+# ----------------------------------------------------------------- CGS with Jacobi on the right
+def row_scaled_ns(N, seed):
+    """Nonsymmetric stencil with rows scaled by 1..8 (a strongly varying diagonal)."""
+    A = inputs.stencil7_ns(N, seed)
+    s = np.array([2.0 ** (inputs.unif(seed, 29, i) * 3) for i in range(A.n_rows)])
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    return inputs.CSR(A.n_rows, A.n_cols, A.row_ptr.copy(), A.col.copy(), A.val * s[rows])
+
+
+RJ = {"scaled_ns_46": lambda: row_scaled_ns(46, 5), "scaled_ns_20": lambda: row_scaled_ns(20, 6)}
+
+
+@pytest.mark.parametrize("name", sorted(RJ))
+@pytest.mark.parametrize("K", [1, 4, 12])
+def test_cgs_jacobi_fixed_k_iterates(spk, ctx, name, K):
+    A = RJ[name]()
+    b = inputs.rhs(A.n_rows, 3)
+    x0 = inputs.vec(A.n_rows, 3, 20)
+    x, log, _ = cgs(spk, ctx, A, b, precond=spk.PRECOND_JACOBI, x0=x0, tau=0.0, max_iters=K)
+    xo, ro, _ = oracle.cgs_jacobi(A, b, x0=x0, tau=0.0, max_iters=K)
+    assert log.iterations == K and log.stop_reason == spk.STOP_MAX_ITERS
+    assert rel(x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cgs_jacobi_converged_parity(spk, ctx, mode):
+    A = row_scaled_ns(46, 5)
+    b = inputs.rhs(A.n_rows, 4)
+    x, log, hist = cgs(spk, ctx, A, b, precond=spk.PRECOND_JACOBI, tau=1e-12, mode=mode, history=True)
+    xo, ro, ho = oracle.cgs_jacobi(A, b, tau=1e-12, history=True)
+    _, lu, _ = cgs(spk, ctx, A, b, tau=1e-12)
+    assert log.stop_reason == spk.STOP_CONVERGED and abs(log.iterations - ro.iterations) <= 1
+    assert log.iterations < lu.iterations
+    assert rel(x, xo) <= 1e-12
+    k = min(hist.size, ho.size)
+    assert np.all(np.abs(hist[:k] - ho[:k]) <= 0.01 * ho[:k])
+    assert np.linalg.norm(oracle.residual(A, b, x)) <= 10 * 1e-12 * log.rhs_norm
+
+
+def test_cgs_jacobi_unusable_diagonal(spk, ctx):
+    d = np.ones(900)
+    d[450] = 0.0
+    x0 = inputs.vec(900, 9, 22)
+    for solver in (spk.SOLVER_CGS, spk.SOLVER_GMRES):
+        x, log, _ = solve(spk, ctx, inputs.diagonal(d), np.ones(900), solver, spk.PRECOND_JACOBI, x0=x0)
+        assert log.stop_reason == spk.STOP_BREAKDOWN and log.iterations == 0 and np.array_equal(x, x0)
+        assert abs(log.true_resnorm - np.linalg.norm(np.ones(900) - d * x0)) <= 1e-12 * log.true_resnorm
 
 
 # ----------------------------------------------------------------- Jacobi PCG
