@@ -76,15 +76,17 @@ typedef enum {
     SPK_SOLVER_CG = 0,        /* conjugate gradient: A symmetric positive definite */
     SPK_SOLVER_CGS = 1,       /* conjugate gradient squared: general nonsingular A; FP64;
                                  two SpMVs per iteration */
-    SPK_SOLVER_GMRES = 2      /* restarted GMRES(krylov_dim): general nonsingular A; FP64;
+    SPK_SOLVER_GMRES = 2      /* restarted GMRES(krylov_dim): general nonsingular A;
                                  iterations count Arnoldi steps and the stop test
                                  uses the Givens residual estimate (the true residual at each
-                                 restart) */
+                                 restart).  With a mixed precision it is the inner solver
+                                 of the refinement (GMRES-IR) */
 } spk_solver;
 typedef enum {
     SPK_PREC_FP64 = 0,        /* FP64 values, vectors and reductions */
-    SPK_PREC_MIXED_FP32 = 1,  /* FP32 inner CG (FP64 reductions) + FP64 iterative refinement */
-    SPK_PREC_MIXED_BF16 = 2   /* BF16 matrix values in the inner CG, otherwise as MIXED_FP32 */
+    SPK_PREC_MIXED_FP32 = 1,  /* FP32 inner solve (CG or GMRES: FP32 vectors, FP64 reductions)
+                                 + FP64 iterative refinement */
+    SPK_PREC_MIXED_BF16 = 2   /* BF16 matrix values in the inner solve, otherwise as MIXED_FP32 */
 } spk_precision;
 typedef enum { SPK_BASELINE_RHS_NORM = 0 } spk_baseline;
 typedef enum {
@@ -139,7 +141,7 @@ typedef struct {
     int32_t chunk_iters;       /* iterations per status poll / graph replay; 0 = auto */
     int32_t record_history;    /* 1: keep ||r_k|| for k = 0..iterations */
     int32_t true_residual;     /* 1: recompute ||b - A x|| at exit (default 1) */
-    double inner_reduction;    /* mixed: inner CG reduction factor (default 1e-4) */
+    double inner_reduction;    /* mixed: inner solve reduction factor (default 1e-4) */
     int64_t max_outer;         /* mixed: refinement step cap (default 50) */
     int64_t krylov_dim;        /* GMRES restart length, 1..32 (default 30, Listings 1-2) */
     int64_t reserved[3];
@@ -147,7 +149,7 @@ typedef struct {
 
 /* What a solve did (the paper's logger). */
 typedef struct {
-    int64_t iterations;        /* CG updates performed (inner updates summed for mixed) */
+    int64_t iterations;        /* solver iterations (inner iterations summed for mixed) */
     int64_t outer_iterations;  /* refinement steps (mixed), else 0 */
     double implicit_resnorm;   /* ||r_k|| of the recurrence residual at exit */
     double true_resnorm;       /* ||b - A x|| recomputed in FP64 at exit (NaN if not computed) */
@@ -221,8 +223,9 @@ spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
 /* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
  * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
  * an FP32/BF16 copy for the inner solve) or F32 values (taken as exact).
- * CGS, GMRES and the Jacobi preconditioner are FP64 only (GMRES runs in the
- * host loop); a Jacobi plan computes 1 / diag(A) (and for CGS and GMRES a
+ * CGS and the Jacobi preconditioner are FP64 only; GMRES runs in the host
+ * loop, in FP64 or as the inner solver of a mixed precision (its basis then
+ * holds (krylov_dim + 1) n floats); a Jacobi plan computes 1 / diag(A) (and for CGS and GMRES a
  * scaled copy of the values, nnz doubles); a zero or non-finite diagonal
  * entry makes every solve of the plan stop with SPK_STOP_BREAKDOWN, x
  * unchanged.

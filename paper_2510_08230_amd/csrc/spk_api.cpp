@@ -75,7 +75,8 @@ struct spk_plan_s {
     double *rt = nullptr, *u = nullptr, *v = nullptr, *uh = nullptr;   // CGS
     double *dinv = nullptr;              // Jacobi: 1 / diag(A)
     void *coo_rp = nullptr;              // COO SpMV: derived row pointer (owned)
-    double *gm_V = nullptr, *gm_w = nullptr, *gm_part = nullptr;   // GMRES basis, work vector, partials
+    void *gm_V = nullptr, *gm_w = nullptr;   // GMRES basis and work vector (FP64, or FP32 in GMRES-IR)
+    double *gm_part = nullptr;               // GMRES per-workgroup partials
     spk::GmresState *gm_st = nullptr;    // GMRES small arrays
     unsigned *diag_flag = nullptr;       // Jacobi: nonzero = unusable diagonal
     bool right_jacobi = false;           // CGS / GMRES on A M^{-1}, M = diag(A)
@@ -820,8 +821,8 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         return fail(ctx, SPK_ERR_INVALID_ARG, "krylov_dim must be in 1..32");
     if (cfg.precond != SPK_PRECOND_NONE && cfg.precond != SPK_PRECOND_JACOBI)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown preconditioner");
-    if ((cfg.solver != SPK_SOLVER_CG || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
-        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS, GMRES and Jacobi CG run in FP64 precision");
+    if ((cfg.solver == SPK_SOLVER_CGS || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS and the Jacobi preconditioner run in FP64 precision");
     if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
     if (cfg.precision < SPK_PREC_FP64 || cfg.precision > SPK_PREC_MIXED_BF16)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown precision");
@@ -864,13 +865,13 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     auto dget = [&](size_t bytes, auto **out) {
         void *v = nullptr;
         const bool ok = ctx->dpool.get(bytes, &v) == hipSuccess;
-        *out = static_cast<std::remove_reference_t<decltype(**out)> *>(v);
+        *out = static_cast<std::remove_reference_t<decltype(*out)>>(v);
         return ok;
     };
     auto hget = [&](size_t bytes, auto **out) {
         void *v = nullptr;
         const bool ok = ctx->hpool.get(bytes, &v) == hipSuccess;
-        *out = static_cast<std::remove_reference_t<decltype(**out)> *>(v);
+        *out = static_cast<std::remove_reference_t<decltype(*out)>>(v);
         return ok;
     };
     const size_t partial_bytes = sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid;
@@ -948,6 +949,12 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             pl->A32.va = dst;
             pl->A32.val_t = bf ? SPK_BF16 : SPK_F32;
         }
+        if (pl->algo == ALGO_GMRES) {   // GMRES-IR: FP32 basis
+            const size_t vbytes = nf * static_cast<size_t>(cfg.krylov_dim + 1);
+            if (!dget(vbytes, &pl->gm_V) || !dget(nf, &pl->gm_w) || !dget(sizeof(spk::GmresState), &pl->gm_st) ||
+                !dget(sizeof(double) * (spk::kMaxKrylov + 1) * spk::kMaxGrid, &pl->gm_part))
+                return cleanup(SPK_ERR_OUT_OF_MEMORY, "GMRES workspace");
+        }
         if (hipMemsetAsync(pl->st_in, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
             hipMemsetAsync(pl->p32, 0, nf, ctx->stream) != hipSuccess)
             return cleanup(SPK_ERR_DEVICE, "workspace init");
@@ -1011,32 +1018,40 @@ spk_status spk_execute_spmv(spk_plan pl, const void *x, void *y) {
 
 // Restarted GMRES: each cycle (restart residual, krylov_dim Arnoldi steps,
 // triangular solve, x update) is enqueued whole; the state is read once per
-// cycle.  Steps after the device ends a cycle return at once.
-static spk_status run_gmres(spk_plan pl, const double *b, double *x) {
+// cycle.  Steps after the device ends a cycle return at once.  inner: the
+// FP32 solve of a refinement step (A32 d = r32 from d = 0, state st_in, to
+// inner_reduction, at most max_iters steps), else the FP64 solve of A x = b.
+static spk_status run_gmres(spk_plan pl, const void *b, void *x, bool inner, int64_t max_iters) {
     spk_ctx ctx = pl->ctx;
     const spk_solver_cfg &cfg = pl->cfg;
     const int m = static_cast<int>(cfg.krylov_dim);
     const int64_t n = pl->A.n_rows;
     hipStream_t s = ctx->stream;
-    SPK_HIP(ctx, spk::launch_gm_begin(pl->st, pl->gm_st, x, pl->hist, pl->hist_cap, cfg.max_iters, s));
+    const CsrDev &A = inner ? pl->A32 : pl->A;
+    const SpmvTune &tune = inner ? pl->tune32 : pl->tune;
+    SolveState *st = inner ? pl->st_in : pl->st;
+    SolveState *h_st = inner ? pl->h_st_in : pl->h_st;
+    const double tau = inner ? cfg.inner_reduction : cfg.reduction_factor;
+    SPK_HIP(ctx, spk::launch_gm_begin(st, pl->gm_st, x, inner ? nullptr : pl->hist, inner ? 0 : pl->hist_cap,
+                                      max_iters, s));
     // every cycle but the last completes at least one step
-    const int64_t max_cycles = cfg.max_iters + 2;
+    const int64_t max_cycles = max_iters + 2;
     for (int64_t c = 0; c < max_cycles; ++c) {
-        SPK_HIP(ctx, spk::launch_gm_cycle_start(pl->A, pl->tune, b, x, pl->gm_V, pl->st, pl->gm_st, pl->partials,
-                                                cfg.reduction_factor, m, s));
+        SPK_HIP(ctx, spk::launch_gm_cycle_start(A, tune, b, x, pl->gm_V, st, pl->gm_st, pl->partials, tau, m, inner,
+                                                s));
         for (int j = 0; j < m; ++j) {
             hipEvent_t e = nullptr;
             spk_status ps = prof_begin(pl, &e);
             if (ps != SPK_OK) return ps;
-            SPK_HIP(ctx, spk::launch_gm_step_spmv(pl->A, pl->tune, pl->gm_V, pl->gm_w, j, pl->st, pl->gm_st, s));
+            SPK_HIP(ctx, spk::launch_gm_step_spmv(A, tune, pl->gm_V, pl->gm_w, j, st, pl->gm_st, inner, s));
             if ((ps = prof_end(pl, e)) != SPK_OK) return ps;
-            SPK_HIP(ctx, spk::launch_gm_step_rest(n, pl->vec_grid, pl->gm_V, pl->gm_w, j, m, pl->st, pl->gm_st,
-                                                  pl->gm_part, s));
+            SPK_HIP(ctx, spk::launch_gm_step_rest(n, pl->vec_grid, pl->gm_V, pl->gm_w, j, m, st, pl->gm_st,
+                                                  pl->gm_part, inner, s));
         }
-        SPK_HIP(ctx, spk::launch_gm_cycle_end(n, pl->vec_grid, m, pl->gm_V, pl->st, pl->gm_st, s));
-        spk_status ps = pull(ctx, pl->h_st, pl->st, sizeof(SolveState));
+        SPK_HIP(ctx, spk::launch_gm_cycle_end(n, pl->vec_grid, m, pl->gm_V, st, pl->gm_st, inner, s));
+        spk_status ps = pull(ctx, h_st, st, sizeof(SolveState));
         if (ps != SPK_OK) return ps;
-        if (pl->h_st->stop != spk::STOP_RUNNING) return SPK_OK;
+        if (h_st->stop != spk::STOP_RUNNING) return SPK_OK;
     }
     return fail(ctx, SPK_ERR_INTERNAL, "GMRES cycle cap passed without stop");
 }
@@ -1059,7 +1074,7 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
         // the scaled system is the caller's b - A x
         SPK_HIP(ctx, spk::launch_jacobi_vec(n, x, pl->dinv, 1, ctx->stream));
         if (pl->algo == ALGO_GMRES) {
-            if ((s = run_gmres(pl, b, x)) != SPK_OK) return s;
+            if ((s = run_gmres(pl, b, x, false, cfg.max_iters)) != SPK_OK) return s;
         } else {
             SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->rt, pl->st, pl->partials,
                                              cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap, ctx->stream));
@@ -1081,7 +1096,7 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
         if (flags[2] != 0) return fail(ctx, SPK_ERR_DEVICE, "persistent solve: a grid barrier timed out");
     } else if (pl->algo == ALGO_GMRES) {
-        if ((s = run_gmres(pl, b, x)) != SPK_OK) return s;
+        if ((s = run_gmres(pl, b, x, false, cfg.max_iters)) != SPK_OK) return s;
         SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
                                              ctx->stream));
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
@@ -1158,7 +1173,11 @@ static spk_status execute_mixed(spk_plan pl, const double *b, double *x, spk_log
             stop = spk::STOP_MAX_ITERS;
             break;
         }
-        if ((s = run_loop(pl, LOOP_FP32, cfg.max_iters - inner_total, graph)) != SPK_OK) return s;
+        if (pl->algo == ALGO_GMRES) {
+            if ((s = run_gmres(pl, pl->r32, pl->d32, true, cfg.max_iters - inner_total)) != SPK_OK) return s;
+        } else if ((s = run_loop(pl, LOOP_FP32, cfg.max_iters - inner_total, graph)) != SPK_OK) {
+            return s;
+        }
         const SolveState &h = *pl->h_st_in;
         inner_total += h.iter;
         if (pl->profiling) {   // this inner solve's SpMV launches that did work

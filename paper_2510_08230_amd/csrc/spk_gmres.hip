@@ -20,6 +20,11 @@
 // with the triangular solve R y = g and x += V y over the columns built.
 // Kernels return at once when the solve has stopped or the cycle is done,
 // so the host can enqueue a whole cycle and poll once.
+//
+// The basis, w and x are of type T: double for the FP64 solve, float for the
+// inner solve of mixed-precision refinement (FP32/BF16 matrix values).  Every
+// dot product, norm and Gram-Schmidt combination is formed in FP64 from the
+// stored values and rounded once to T; H, g and the rotations are FP64.
 #include "spk_spmv.h"
 
 #include <cmath>
@@ -35,18 +40,20 @@ __device__ __forceinline__ bool gm_idle(const SolveState *st, const GmresState *
 }
 
 // r = b - A x into v_0; partials of r.r and b.b.
+template <typename T>
 struct EpiGmRes {
-    const double *b;
-    double *v0;
+    const T *b;
+    T *v0;
     const SolveState *st;
     double *part;
     double rr, bb;
     __device__ bool skip() const { return st->stop != STOP_RUNNING; }
-    __device__ void row(int64_t i, double s) {
-        const double bi = b[i];
-        const double ri = bi - s;
+    template <class C>
+    __device__ void row(int64_t i, C s) {
+        const double bi = static_cast<double>(b[i]);
+        const T ri = static_cast<T>(bi - static_cast<double>(s));
         v0[i] = ri;
-        rr = fma(ri, ri, rr);
+        rr = fma(static_cast<double>(ri), static_cast<double>(ri), rr);
         bb = fma(bi, bi, bb);
     }
     __device__ void finish() {
@@ -56,17 +63,19 @@ struct EpiGmRes {
 };
 
 // w = (A v_j) / ||v_j||.
+template <typename T>
 struct EpiGmW {
-    double *w;
+    T *w;
     const SolveState *st;
     const GmresState *gs;
     __device__ bool skip() const { return gm_idle(st, gs); }
-    __device__ void row(int64_t i, double s) { w[i] = s * gs->inv_scale; }
+    template <class C>
+    __device__ void row(int64_t i, C s) { w[i] = static_cast<T>(static_cast<double>(s) * gs->inv_scale); }
     __device__ void finish() {}
 };
 
 // Solve set-up (one thread): the state fields every later kernel reads.
-__global__ void k_gm_begin(SolveState *st, GmresState *gs, double *x, double *hist, int64_t hist_cap,
+__global__ void k_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist, int64_t hist_cap,
                            int64_t max_iters) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->x = x;
@@ -124,14 +133,15 @@ __global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, Gmres
 }
 
 // Basis vector t of the Krylov block (contiguous, n apart).
-__device__ __forceinline__ const double *vec(const double *V, int64_t n, int t) { return V + static_cast<int64_t>(t) * n; }
+template <typename T>
+__device__ __forceinline__ const T *vec(const T *V, int64_t n, int t) { return V + static_cast<int64_t>(t) * n; }
 
 // v_j *= 1/||v_j|| (written back); partials of h1_t = w . v_t, t <= j.  The
 // written vector comes in as its own pointer so that the loads of the other
 // basis vectors can be issued ahead of the store.
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, const double *__restrict__ V, double *__restrict__ vj,
-                                                    const double *__restrict__ w, int j, const SolveState *st,
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, const T *__restrict__ V, T *__restrict__ vj,
+                                                    const T *__restrict__ w, int j, const SolveState *st,
                                                     const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
     const double inv = gs->inv_scale;
@@ -140,16 +150,16 @@ __global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, const double *__r
     for (int t = 0; t < NV; ++t) acc[t] = 0.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        const double wi = w[i];
-        const double v = vj[i] * inv;
-        double vt[NV];
+        const double wi = static_cast<double>(w[i]);
+        const T v = static_cast<T>(static_cast<double>(vj[i]) * inv);
+        T vt[NV];
 #pragma unroll
-        for (int t = 0; t < NV; ++t) vt[t] = t < j ? vec(V, n, t)[i] : 0.0;
+        for (int t = 0; t < NV; ++t) vt[t] = t < j ? vec(V, n, t)[i] : T(0);
         vj[i] = v;
 #pragma unroll
         for (int t = 0; t < NV; ++t) {
-            if (t < j) acc[t] = fma(wi, vt[t], acc[t]);
-            else if (t == j) acc[t] = fma(wi, v, acc[t]);
+            if (t < j) acc[t] = fma(wi, static_cast<double>(vt[t]), acc[t]);
+            else if (t == j) acc[t] = fma(wi, static_cast<double>(v), acc[t]);
         }
     }
     block_partial<NV>(acc, part);
@@ -166,8 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_gm_reduce(const double *part, int G,
 }
 
 // w -= V h1 over t <= j; partials of h2_t = w . v_t.
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, const double *V, double *__restrict__ w, int j,
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, const T *__restrict__ V, T *__restrict__ w, int j,
                                                      const SolveState *st, const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
     __shared__ double h[NV];
@@ -179,24 +189,26 @@ __global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, const double *V,
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
         double v[NV];
-        double wi = w[i];
+        double wi = static_cast<double>(w[i]);
 #pragma unroll
         for (int t = 0; t < NV; ++t) {
-            v[t] = t <= j ? vec(V, n, t)[i] : 0.0;
+            v[t] = t <= j ? static_cast<double>(vec(V, n, t)[i]) : 0.0;
             wi = fma(-h[t], v[t], wi);
         }
-        w[i] = wi;
+        const T ws = static_cast<T>(wi);
+        w[i] = ws;
+        const double wd = static_cast<double>(ws);
 #pragma unroll
-        for (int t = 0; t < NV; ++t) acc[t] = fma(wi, v[t], acc[t]);
+        for (int t = 0; t < NV; ++t) acc[t] = fma(wd, v[t], acc[t]);
     }
     block_partial<NV>(acc, part);
 }
 
 // v_{j+1} = w - V h2 over t <= j (unnormalised); partial of ||v_{j+1}||^2.
 // vn (= v_{j+1}) does not overlap the basis vectors read.
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, const double *__restrict__ V, double *__restrict__ vn,
-                                                     const double *__restrict__ w, int j, const SolveState *st,
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, const T *__restrict__ V, T *__restrict__ vn,
+                                                     const T *__restrict__ w, int j, const SolveState *st,
                                                      const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
     __shared__ double h[NV];
@@ -205,14 +217,15 @@ __global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, const double *__
     double nrm = 0.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        double vt[NV];
+        T vt[NV];
 #pragma unroll
-        for (int t = 0; t < NV; ++t) vt[t] = t <= j ? vec(V, n, t)[i] : 0.0;
-        double wi = w[i];
+        for (int t = 0; t < NV; ++t) vt[t] = t <= j ? vec(V, n, t)[i] : T(0);
+        double wi = static_cast<double>(w[i]);
 #pragma unroll
-        for (int t = 0; t < NV; ++t) wi = fma(-h[t], vt[t], wi);
-        vn[i] = wi;
-        nrm = fma(wi, wi, nrm);
+        for (int t = 0; t < NV; ++t) wi = fma(-h[t], static_cast<double>(vt[t]), wi);
+        const T ws = static_cast<T>(wi);
+        vn[i] = ws;
+        nrm = fma(static_cast<double>(ws), static_cast<double>(ws), nrm);
     }
     double a[1] = {nrm};
     block_partial<1>(a, part);
@@ -274,23 +287,24 @@ __global__ void k_gm_solve(const SolveState *st, GmresState *gs) {
     }
 }
 
-// x += V y over the columns built, added column by column.
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, const double *V, const SolveState *st,
+// x += V y over the columns built, added column by column (in FP64, then
+// rounded once to T).
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, const T *V, const SolveState *st,
                                                         const GmresState *gs) {
     const int used = gs->used;
     if (st->stop == STOP_NON_FINITE || used == 0) return;
     __shared__ double y[NV];
     if (threadIdx.x < NV) y[threadIdx.x] = threadIdx.x < used ? gs->y[threadIdx.x] : 0.0;
     __syncthreads();
-    double *x = static_cast<double *>(st->x);
+    T *x = static_cast<T *>(st->x);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        double xi = x[i];
+        double xi = static_cast<double>(x[i]);
 #pragma unroll
         for (int t = 0; t < NV; ++t)
-            if (t < used) xi = fma(y[t], vec(V, n, t)[i], xi);
-        x[i] = xi;
+            if (t < used) xi = fma(y[t], static_cast<double>(vec(V, n, t)[i]), xi);
+        x[i] = static_cast<T>(xi);
     }
 }
 
@@ -299,40 +313,70 @@ __global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, const double 
 // ------------------------------------------------------------------ launchers
 static int nv_bucket(int J) { return J <= 8 ? 8 : (J <= 16 ? 16 : 32); }
 
-hipError_t launch_gm_begin(SolveState *st, GmresState *gs, double *x, double *hist, int64_t hist_cap,
+// SpMV with a GMRES epilogue: FP64 vectors need F64 values; FP32 vectors
+// take F32, BF16 or F16 values.
+template <typename T, class Epi>
+static hipError_t gm_spmv(const CsrDev &A, const SpmvTune &t, const T *x, const Epi &e, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (A.val_t != 0) return hipErrorInvalidValue;
+        return launch_family<double, double, double>(A, t, x, e, s);
+    } else {
+        if (A.val_t == 1) return launch_family<float, float, float>(A, t, x, e, s);
+        if (A.val_t == 3) return launch_family<bf16s, float, float>(A, t, x, e, s);
+        if (A.val_t == 2) return launch_family<_Float16, float, float>(A, t, x, e, s);
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist, int64_t hist_cap,
                            int64_t max_iters, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_begin, dim3(1), dim3(64), 0, s, st, gs, x, hist, hist_cap, max_iters);
     return hipGetLastError();
 }
 
-hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, double *V,
-                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, hipStream_t s) {
-    EpiGmRes e{b, V, st, site(partials, SITE_INIT), 0.0, 0.0};
-    hipError_t err = launch_family<double, double, double>(A, t, x, e, s);
+template <typename T>
+static hipError_t cycle_start_t(const CsrDev &A, const SpmvTune &t, const void *b, const void *x, void *V,
+                                SolveState *st, GmresState *gs, double *partials, double tau, int m, hipStream_t s) {
+    EpiGmRes<T> e{static_cast<const T *>(b), static_cast<T *>(V), st, site(partials, SITE_INIT), 0.0, 0.0};
+    hipError_t err = gm_spmv<T>(A, t, static_cast<const T *>(x), e, s);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_gm_cycle_start, dim3(1), dim3(kBlock), 0, s, st, gs, site(partials, SITE_INIT), t.grid, tau,
                        m);
     return hipGetLastError();
 }
 
-hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const double *V, double *w, int j,
-                               const SolveState *st, const GmresState *gs, hipStream_t s) {
-    EpiGmW e{w, st, gs};
-    return launch_family<double, double, double>(A, t, V + static_cast<int64_t>(j) * A.n_rows, e, s);
+hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const void *b, const void *x, void *V,
+                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, bool fp32,
+                                 hipStream_t s) {
+    return fp32 ? cycle_start_t<float>(A, t, b, x, V, st, gs, partials, tau, m, s)
+                : cycle_start_t<double>(A, t, b, x, V, st, gs, partials, tau, m, s);
 }
 
-hipError_t launch_gm_step_rest(int64_t n, int grid, double *V, double *w, int j, int m, SolveState *st,
-                               GmresState *gs, double *gpart, hipStream_t s) {
+template <typename T>
+static hipError_t step_spmv_t(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
+                              const SolveState *st, const GmresState *gs, hipStream_t s) {
+    EpiGmW<T> e{static_cast<T *>(w), st, gs};
+    return gm_spmv<T>(A, t, static_cast<const T *>(V) + static_cast<int64_t>(j) * A.n_rows, e, s);
+}
+
+hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
+                               const SolveState *st, const GmresState *gs, bool fp32, hipStream_t s) {
+    return fp32 ? step_spmv_t<float>(A, t, V, w, j, st, gs, s) : step_spmv_t<double>(A, t, V, w, j, st, gs, s);
+}
+
+template <typename T>
+static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, SolveState *st, GmresState *gs,
+                              double *gpart, hipStream_t s) {
     const int J = j + 1;
     const int nv = nv_bucket(J);
+    T *vj = V + static_cast<int64_t>(j) * n;
+    T *vn = V + static_cast<int64_t>(j + 1) * n;
 #define SPK_GM_NV(K, ...)                                                                                   \
     do {                                                                                                    \
-        if (nv == 8) hipLaunchKernelGGL(K<8>, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                 \
-        else if (nv == 16) hipLaunchKernelGGL(K<16>, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);          \
-        else hipLaunchKernelGGL(K<32>, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                        \
+        if (nv == 8) hipLaunchKernelGGL((K<T, 8>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);            \
+        else if (nv == 16) hipLaunchKernelGGL((K<T, 16>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);     \
+        else hipLaunchKernelGGL((K<T, 32>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
     } while (0)
-    double *vj = V + static_cast<int64_t>(j) * n;
-    double *vn = V + static_cast<int64_t>(j + 1) * n;
     SPK_GM_NV(k_gm_dots, n, V, vj, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h1[0], st, gs);
     SPK_GM_NV(k_gm_pass2, n, V, w, j, st, gs, gpart);
@@ -343,14 +387,27 @@ hipError_t launch_gm_step_rest(int64_t n, int grid, double *V, double *w, int j,
     return hipGetLastError();
 }
 
-hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const double *V, SolveState *st, GmresState *gs,
-                               hipStream_t s) {
+hipError_t launch_gm_step_rest(int64_t n, int grid, void *V, void *w, int j, int m, SolveState *st, GmresState *gs,
+                               double *gpart, bool fp32, hipStream_t s) {
+    return fp32 ? step_rest_t<float>(n, grid, static_cast<float *>(V), static_cast<float *>(w), j, m, st, gs, gpart, s)
+                : step_rest_t<double>(n, grid, static_cast<double *>(V), static_cast<double *>(w), j, m, st, gs,
+                                      gpart, s);
+}
+
+template <typename T>
+static hipError_t cycle_end_t(int64_t n, int grid, int m, const T *V, SolveState *st, GmresState *gs, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, st, gs);
     const int nv = nv_bucket(m);
-    if (nv == 8) hipLaunchKernelGGL(k_gm_update_x<8>, dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
-    else if (nv == 16) hipLaunchKernelGGL(k_gm_update_x<16>, dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
-    else hipLaunchKernelGGL(k_gm_update_x<32>, dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    if (nv == 8) hipLaunchKernelGGL((k_gm_update_x<T, 8>), dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    else if (nv == 16) hipLaunchKernelGGL((k_gm_update_x<T, 16>), dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    else hipLaunchKernelGGL((k_gm_update_x<T, 32>), dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
     return hipGetLastError();
+}
+
+hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const void *V, SolveState *st, GmresState *gs, bool fp32,
+                               hipStream_t s) {
+    return fp32 ? cycle_end_t<float>(n, grid, m, static_cast<const float *>(V), st, gs, s)
+                : cycle_end_t<double>(n, grid, m, static_cast<const double *>(V), st, gs, s);
 }
 
 }  // namespace spk

@@ -151,15 +151,17 @@ hipError_t launch_cgs_check(SolveState *st, double *partials, int spmv_grid, int
 // kMaxGrid doubles.  A solve is begin, then per cycle: cycle_start (r = b - A x
 // into v_0, beta, stop test), for j = 0..m-1 step_spmv(j) and step_rest(j),
 // then cycle_end (R y = g, x += V y); the host polls after each cycle.
-hipError_t launch_gm_begin(SolveState *st, GmresState *gs, double *x, double *hist, int64_t hist_cap,
+hipError_t launch_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist, int64_t hist_cap,
                            int64_t max_iters, hipStream_t s);
-hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, double *V,
-                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, hipStream_t s);
-hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const double *V, double *w, int j,
-                               const SolveState *st, const GmresState *gs, hipStream_t s);
-hipError_t launch_gm_step_rest(int64_t n, int grid, double *V, double *w, int j, int m, SolveState *st,
-                               GmresState *gs, double *gpart, hipStream_t s);
-hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const double *V, SolveState *st, GmresState *gs,
+// fp32: FP32 basis, w and x (A's values F32, BF16 or F16), else FP64 (F64 values).
+hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const void *b, const void *x, void *V,
+                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, bool fp32,
+                                 hipStream_t s);
+hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
+                               const SolveState *st, const GmresState *gs, bool fp32, hipStream_t s);
+hipError_t launch_gm_step_rest(int64_t n, int grid, void *V, void *w, int j, int m, SolveState *st, GmresState *gs,
+                               double *gpart, bool fp32, hipStream_t s);
+hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const void *V, SolveState *st, GmresState *gs, bool fp32,
                                hipStream_t s);
 
 // Jacobi-preconditioned CG (FP64; spk_krylov.hip).  diag_inv runs once per

@@ -136,8 +136,12 @@ def test_gmres_plan_errors(spk, ctx):
             spk.spk_plan_solve(ctx, M, cfg)
     cfg.krylov_dim = 30
     cfg.precision = spk.PREC_MIXED_FP32
-    with pytest.raises(spk.SpkError):
+    cfg.precond = spk.PRECOND_JACOBI
+    with pytest.raises(spk.SpkError) as e:
         spk.spk_plan_solve(ctx, M, cfg)
+    assert e.value.status == spk.ERR_UNSUPPORTED
+    cfg.precond = spk.PRECOND_NONE
+    spk.spk_free(spk.spk_plan_solve(ctx, M, cfg))   # GMRES-IR
 
 
 def row_scaled_ns(N, seed):
@@ -192,5 +196,123 @@ def test_gmres_full_size_residual():
         x2, _, _ = gmres(spk, ctx, A, b, tau=0.0, max_iters=2, M=M)
         xo, _, _ = oracle.gmres(A, b, tau=0.0, max_iters=2, m=30)
         assert rel(x2, xo) <= 1e-12
+    finally:
+        spk.spk_finalize(ctx)
+
+
+# --------------------------------------------------------------------- GMRES-IR
+# GMRES(m) as the inner solver of FP64 iterative refinement: FP32 basis and
+# work vector (matrix values FP32 or BF16), FP64 dot products, norms,
+# Gram-Schmidt combinations and Hessenberg arithmetic.
+#
+# Stated tolerances:
+#  * refined solution vs the oracle's FP64 GMRES solved to 1e-14: 1e-10
+#    relative.  The refinement stops at ||b - A x|| <= 1e-12 ||b|| in FP64, so
+#    the error is at most kappa_2(A) * 1e-12; kappa_2 is 5.5-6.1 for
+#    stencil7_ns (delta 1, N = 20-36), 10.9 for stencil7_ns(20, delta 0.2)
+#    (Lanczos on A^T A and its inverse) and at most 18.3 for randsym (symmetric,
+#    Gershgorin) -> below 2e-11.
+#  * one inner solve of K <= 20 steps vs the oracle's FP64 GMRES on the same
+#    FP32-rounded matrix and right-hand side: 2e-5 relative.  Each FP32 store
+#    perturbs a step by u32 = 6e-8 relative (a u32 perturbation of the data
+#    moves the oracle's iterate by 5.7e-8), compounded over K steps and
+#    amplified by kappa: K * kappa * u32 <= 20 * 18.3 * 6e-8 = 2.2e-5.
+
+def gmres_ir(spk, ctx, A, b, prec="fp32", m=30, tau=1e-12, inner=1e-4, max_outer=50, max_iters=10000,
+             x0=None, val=torch.float64):
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = spk.SOLVER_GMRES
+    cfg.krylov_dim = m
+    cfg.precision = spk.PREC_MIXED_FP32 if prec == "fp32" else spk.PREC_MIXED_BF16
+    cfg.reduction_factor = tau
+    cfg.inner_reduction = inner
+    cfg.max_outer = max_outer
+    cfg.max_iters = max_iters
+    pl = spk.spk_plan_solve(ctx, dev_csr(spk, A, val=val), cfg)
+    x = to_dev(np.zeros(A.n_rows) if x0 is None else x0)
+    log = spk.spk_execute_solve(pl, to_dev(b), x)
+    spk.spk_free(pl)
+    return x.cpu().numpy(), log
+
+
+def rounded32(A):
+    return inputs.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("m", [30, 8])
+def test_gmres_ir_matches_fp64_oracle(spk, ctx, name, prec, m):
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 2)
+    x, log = gmres_ir(spk, ctx, A, b, prec=prec, m=m)
+    xo, ro, _ = oracle.gmres(A, b, tau=1e-14, m=30, max_iters=3000)
+    assert ro.stop_reason == 1
+    assert log.stop_reason == spk.STOP_CONVERGED and log.outer_iterations >= 1
+    assert rel(x, xo) <= 1e-10
+    r = oracle.residual(A, b, x)
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b) * 1.01
+    assert abs(log.true_resnorm - np.linalg.norm(r)) <= 1e-3 * np.linalg.norm(r) + 1e-16 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("m,K", [(30, 20), (5, 12), (8, 17)])
+def test_gmres_ir_inner_solve_iterates(spk, ctx, name, m, K):
+    """One refinement step from x = 0 whose inner solve runs exactly K steps:
+    x = d, the FP32 GMRES(m) iterate for A32 d = fl32(b)."""
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 3)
+    x, log = gmres_ir(spk, ctx, A, b, m=m, inner=1e-30, max_outer=1, max_iters=K)
+    assert log.iterations == K and log.outer_iterations == 1 and log.stop_reason == spk.STOP_MAX_ITERS
+    b32 = b.astype(np.float32).astype(np.float64)
+    xo, _, _ = oracle.gmres(rounded32(A), b32, tau=0.0, max_iters=K, m=m)
+    assert rel(x, xo) <= 2e-5
+    assert np.array_equal(x, x.astype(np.float32).astype(np.float64))   # x0 = 0: x holds FP32 values
+
+
+def test_gmres_ir_stop_semantics_and_reruns(spk, ctx):
+    A = inputs.stencil7_ns(10, 1)
+    n = A.n_rows
+    b = inputs.rhs(n, 1)
+    x0 = inputs.vec(n, 1, 6)
+    x, log = gmres_ir(spk, ctx, A, np.zeros(n), x0=x0)
+    assert log.stop_reason == spk.STOP_CONVERGED and not x.any() and log.iterations == 0
+    x, log = gmres_ir(spk, ctx, A, b, x0=x0, max_outer=0)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and np.array_equal(x, x0) and log.outer_iterations == 0
+    bn = b.copy()
+    bn[7] = np.nan
+    _, log = gmres_ir(spk, ctx, A, bn)
+    assert log.stop_reason == spk.STOP_NON_FINITE
+    _, log = gmres_ir(spk, ctx, A, b, max_outer=1, inner=1e-2)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.outer_iterations == 1
+    # total inner steps capped by max_iters
+    _, log = gmres_ir(spk, ctx, A, b, max_iters=7, inner=1e-8)
+    assert log.stop_reason == spk.STOP_MAX_ITERS and log.iterations == 7
+    r1 = gmres_ir(spk, ctx, A, b, x0=x0, m=6)
+    r2 = gmres_ir(spk, ctx, A, b, x0=x0, m=6)
+    assert np.array_equal(r1[0].view(np.uint64), r2[0].view(np.uint64))
+    assert r1[1].iterations == r2[1].iterations and r1[1].stop_reason == spk.STOP_CONVERGED
+
+
+def test_gmres_ir_fp32_values_taken_as_exact(spk, ctx):
+    A = rounded32(inputs.stencil7_ns(30, 5))
+    b = inputs.rhs(A.n_rows, 5)
+    x, log = gmres_ir(spk, ctx, A, b, val=torch.float32)
+    xo, _, _ = oracle.gmres(A, b, tau=1e-14, m=30, max_iters=3000)
+    assert log.stop_reason == spk.STOP_CONVERGED and rel(x, xo) <= 1e-10
+
+
+def test_gmres_ir_full_size_residual():
+    """Nonsymmetric stencil7 N=215: GMRES-IR (FP32 inner GMRES(30)) meets the FP64
+    criterion, checked by the oracle's SpMV of the GPU's x."""
+    from paper_2510_08230_amd import spk
+    ctx = spk.spk_init(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        A = inputs.stencil7_ns(215, 1)
+        b = inputs.rhs(A.n_rows, 1)
+        x, log = gmres_ir(spk, ctx, A, b)
+        print("gmres-ir: %d inner steps, %d outer, %.1f ms" % (log.iterations, log.outer_iterations, log.elapsed_ms))
+        assert log.stop_reason == spk.STOP_CONVERGED
+        assert np.linalg.norm(oracle.residual(A, b, x)) <= 1e-12 * np.linalg.norm(b) * 1.01
     finally:
         spk.spk_finalize(ctx)
