@@ -896,7 +896,8 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             (!dget(nb, &pl->rt) || !dget(nb, &pl->u) || !dget(nb, &pl->v) || !dget(nb, &pl->uh)))
             return cleanup(SPK_ERR_OUT_OF_MEMORY, "CGS workspace");
         if (pl->algo == ALGO_GMRES) {
-            const size_t vbytes = nb * static_cast<size_t>(cfg.krylov_dim + 1);
+            const size_t vbytes =
+                sizeof(double) * static_cast<size_t>(spk::gm_ld(std::max<int64_t>(n, 1))) * (cfg.krylov_dim + 1);
             if (!dget(vbytes, &pl->gm_V) || !dget(nb, &pl->gm_w) || !dget(sizeof(spk::GmresState), &pl->gm_st) ||
                 !dget(sizeof(double) * (spk::kMaxKrylov + 1) * spk::kMaxGrid, &pl->gm_part))
                 return cleanup(SPK_ERR_OUT_OF_MEMORY, "GMRES workspace");
@@ -950,7 +951,8 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             pl->A32.val_t = bf ? SPK_BF16 : SPK_F32;
         }
         if (pl->algo == ALGO_GMRES) {   // GMRES-IR: FP32 basis
-            const size_t vbytes = nf * static_cast<size_t>(cfg.krylov_dim + 1);
+            const size_t vbytes =
+                sizeof(float) * static_cast<size_t>(spk::gm_ld(std::max<int64_t>(n, 1))) * (cfg.krylov_dim + 1);
             if (!dget(vbytes, &pl->gm_V) || !dget(nf, &pl->gm_w) || !dget(sizeof(spk::GmresState), &pl->gm_st) ||
                 !dget(sizeof(double) * (spk::kMaxKrylov + 1) * spk::kMaxGrid, &pl->gm_part))
                 return cleanup(SPK_ERR_OUT_OF_MEMORY, "GMRES workspace");

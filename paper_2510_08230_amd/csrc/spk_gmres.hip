@@ -132,34 +132,133 @@ __global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, Gmres
     if (stop != STOP_RUNNING) st->stop = stop;
 }
 
-// Basis vector t of the Krylov block (contiguous, n apart).
+// The vector passes move packs of K consecutive elements per lane and load
+// (per-element 4-byte loads left the FP32 passes bound by load issue at
+// about 2.2 TB/s).  Two shapes, chosen by the basis bucket NV:
+//  * streaming (dots and pass2 up to NV = 8, pass3 up to 16): 16-byte packs,
+//    each vector's pack combined as it arrives; low register use, high
+//    occupancy.
+//  * load-all-first (larger NV, and update_x): a thread issues the loads of
+//    every basis vector it needs before combining them, so one pack of all J
+//    vectors is in flight at once.  K trades that register footprint against
+//    occupancy: pack_len<T, NV, B>() is the widest pack (16 bytes at most)
+//    with NV * K * B <= 256, B = sizeof(T) up to NV = 16, else 8 (the
+//    compiler holds FP32 values converted to FP64).
+// Measured on stencil7_ns N=215: FP32 pass3 at J = 9..16 104 us streaming,
+// 147 us loading all first; FP32 dots at J <= 8 43 us against 58 us; FP64
+// dots at J = 17..32 400 us loading all first, 580 us streaming.
+// Basis columns sit ld = gm_ld(n) elements apart (16-byte aligned); the last
+// pack of a vector is loaded element by element when n is not a multiple
+// of K.
+template <typename T, int NV, int B>
+constexpr int pack_len() {
+    int k = 16 / static_cast<int>(sizeof(T));
+    while (k > 1 && NV * k * B > 256) k /= 2;
+    return k;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void ld_pack(const T *__restrict__ p, int64_t i0, int64_t n, T (&o)[K]) {
+    if constexpr (K == 1) {
+        o[0] = p[i0];
+    } else {
+        typedef T vk __attribute__((ext_vector_type(K)));
+        if (i0 + K <= n) {
+            const vk v = *reinterpret_cast<const vk *>(p + i0);
+#pragma unroll
+            for (int e = 0; e < K; ++e) o[e] = v[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < K; ++e) o[e] = i0 + e < n ? p[i0 + e] : T(0);
+        }
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void st_pack(T *__restrict__ p, int64_t i0, int64_t n, const T (&o)[K]) {
+    if constexpr (K == 1) {
+        p[i0] = o[0];
+    } else {
+        typedef T vk __attribute__((ext_vector_type(K)));
+        if (i0 + K <= n) {
+            vk v;
+#pragma unroll
+            for (int e = 0; e < K; ++e) v[e] = o[e];
+            *reinterpret_cast<vk *>(p + i0) = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < K; ++e)
+                if (i0 + e < n) p[i0 + e] = o[e];
+        }
+    }
+}
+
+// Basis vector t of the Krylov block.
 template <typename T>
-__device__ __forceinline__ const T *vec(const T *V, int64_t n, int t) { return V + static_cast<int64_t>(t) * n; }
+__device__ __forceinline__ const T *vec(const T *V, int64_t ld, int t) { return V + static_cast<int64_t>(t) * ld; }
 
 // v_j *= 1/||v_j|| (written back); partials of h1_t = w . v_t, t <= j.  The
 // written vector comes in as its own pointer so that the loads of the other
-// basis vectors can be issued ahead of the store.
+// basis vectors can be issued ahead of its store.
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, const T *__restrict__ V, T *__restrict__ vj,
-                                                    const T *__restrict__ w, int j, const SolveState *st,
-                                                    const GmresState *gs, double *part) {
+__global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                    T *__restrict__ vj, const T *__restrict__ w, int j,
+                                                    const SolveState *st, const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
+    constexpr bool stream = NV <= 8;
+    constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
     const double inv = gs->inv_scale;
     double acc[NV];
 #pragma unroll
     for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+    const int64_t np = (n + K - 1) / K;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        const double wi = static_cast<double>(w[i]);
-        const T v = static_cast<T>(static_cast<double>(vj[i]) * inv);
-        T vt[NV];
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
+        const int64_t i0 = q * K;
+        T wv[K], vv[K];
+        ld_pack<T, K>(w, i0, n, wv);
+        ld_pack<T, K>(vj, i0, n, vv);
 #pragma unroll
-        for (int t = 0; t < NV; ++t) vt[t] = t < j ? vec(V, n, t)[i] : T(0);
-        vj[i] = v;
+        for (int e = 0; e < K; ++e) vv[e] = static_cast<T>(static_cast<double>(vv[e]) * inv);
+        if constexpr (stream) {
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t < j) {
+                    T vt[K];
+                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt);
+#pragma unroll
+                    for (int e = 0; e < K; ++e)
+                        acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vt[e]), acc[t]);
+                }
+            }
+        } else {
+            T vt[NV][K];
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t < j) {
+                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < K; ++e) vt[t][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t < j) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e)
+                        acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vt[t][e]), acc[t]);
+                }
+            }
+        }
+        st_pack<T, K>(vj, i0, n, vv);
 #pragma unroll
         for (int t = 0; t < NV; ++t) {
-            if (t < j) acc[t] = fma(wi, static_cast<double>(vt[t]), acc[t]);
-            else if (t == j) acc[t] = fma(wi, static_cast<double>(v), acc[t]);
+            if (t == j) {
+#pragma unroll
+                for (int e = 0; e < K; ++e)
+                    acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vv[e]), acc[t]);
+            }
         }
     }
     block_partial<NV>(acc, part);
@@ -177,29 +276,62 @@ __global__ __launch_bounds__(kBlock) void k_gm_reduce(const double *part, int G,
 
 // w -= V h1 over t <= j; partials of h2_t = w . v_t.
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, const T *__restrict__ V, T *__restrict__ w, int j,
-                                                     const SolveState *st, const GmresState *gs, double *part) {
+__global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                     T *__restrict__ w, int j, const SolveState *st,
+                                                     const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
+    constexpr bool stream = NV <= 8;
+    constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
     __shared__ double h[NV];
     if (threadIdx.x < NV) h[threadIdx.x] = threadIdx.x <= j ? gs->h1[threadIdx.x] : 0.0;
     __syncthreads();
     double acc[NV];
 #pragma unroll
     for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+    const int64_t np = (n + K - 1) / K;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        double v[NV];
-        double wi = static_cast<double>(w[i]);
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
+        const int64_t i0 = q * K;
+        T wv[K], vt[NV][K];
+        ld_pack<T, K>(w, i0, n, wv);
+        double wd[K];
+#pragma unroll
+        for (int e = 0; e < K; ++e) wd[e] = static_cast<double>(wv[e]);
+        if constexpr (stream) {   // combine each vector as it arrives
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t <= j) {
+                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
+#pragma unroll
+                    for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[t][e]), wd[e]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t <= j) {
+                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < K; ++e) vt[t][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NV; ++t)
+#pragma unroll
+                for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[t][e]), wd[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < K; ++e) wv[e] = static_cast<T>(wd[e]);
+        st_pack<T, K>(w, i0, n, wv);
 #pragma unroll
         for (int t = 0; t < NV; ++t) {
-            v[t] = t <= j ? static_cast<double>(vec(V, n, t)[i]) : 0.0;
-            wi = fma(-h[t], v[t], wi);
-        }
-        const T ws = static_cast<T>(wi);
-        w[i] = ws;
-        const double wd = static_cast<double>(ws);
+            if (t <= j) {
 #pragma unroll
-        for (int t = 0; t < NV; ++t) acc[t] = fma(wd, v[t], acc[t]);
+                for (int e = 0; e < K; ++e)
+                    acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vt[t][e]), acc[t]);
+            }
+        }
     }
     block_partial<NV>(acc, part);
 }
@@ -207,25 +339,57 @@ __global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, const T *__restr
 // v_{j+1} = w - V h2 over t <= j (unnormalised); partial of ||v_{j+1}||^2.
 // vn (= v_{j+1}) does not overlap the basis vectors read.
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, const T *__restrict__ V, T *__restrict__ vn,
-                                                     const T *__restrict__ w, int j, const SolveState *st,
-                                                     const GmresState *gs, double *part) {
+__global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                     T *__restrict__ vn, const T *__restrict__ w, int j,
+                                                     const SolveState *st, const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
+    constexpr bool stream = NV <= 16;
+    constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
     __shared__ double h[NV];
     if (threadIdx.x < NV) h[threadIdx.x] = threadIdx.x <= j ? gs->h2[threadIdx.x] : 0.0;
     __syncthreads();
     double nrm = 0.0;
+    const int64_t np = (n + K - 1) / K;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        T vt[NV];
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
+        const int64_t i0 = q * K;
+        T wv[K];
+        ld_pack<T, K>(w, i0, n, wv);
+        double wd[K];
 #pragma unroll
-        for (int t = 0; t < NV; ++t) vt[t] = t <= j ? vec(V, n, t)[i] : T(0);
-        double wi = static_cast<double>(w[i]);
+        for (int e = 0; e < K; ++e) wd[e] = static_cast<double>(wv[e]);
+        if constexpr (stream) {
 #pragma unroll
-        for (int t = 0; t < NV; ++t) wi = fma(-h[t], static_cast<double>(vt[t]), wi);
-        const T ws = static_cast<T>(wi);
-        vn[i] = ws;
-        nrm = fma(static_cast<double>(ws), static_cast<double>(ws), nrm);
+            for (int t = 0; t < NV; ++t) {
+                if (t <= j) {
+                    T vt[K];
+                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt);
+#pragma unroll
+                    for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[e]), wd[e]);
+                }
+            }
+        } else {
+            T vt[NV][K];
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t <= j) {
+                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < K; ++e) vt[t][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NV; ++t)
+#pragma unroll
+                for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[t][e]), wd[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            wv[e] = static_cast<T>(wd[e]);
+            nrm = fma(static_cast<double>(wv[e]), static_cast<double>(wv[e]), nrm);
+        }
+        st_pack<T, K>(vn, i0, n, wv);
     }
     double a[1] = {nrm};
     block_partial<1>(a, part);
@@ -288,23 +452,55 @@ __global__ void k_gm_solve(const SolveState *st, GmresState *gs) {
 }
 
 // x += V y over the columns built, added column by column (in FP64, then
-// rounded once to T).
+// rounded once to T).  x is the caller's vector: packed only when aligned
+// to the pack.
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, const T *V, const SolveState *st,
-                                                        const GmresState *gs) {
+__global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                        const SolveState *st, const GmresState *gs) {
     const int used = gs->used;
     if (st->stop == STOP_NON_FINITE || used == 0) return;
+    constexpr int K = pack_len<T, NV, 8>();
     __shared__ double y[NV];
     if (threadIdx.x < NV) y[threadIdx.x] = threadIdx.x < used ? gs->y[threadIdx.x] : 0.0;
     __syncthreads();
-    T *x = static_cast<T *>(st->x);
+    T *__restrict__ x = static_cast<T *>(st->x);
+    const bool aligned = (reinterpret_cast<uintptr_t>(x) % (K * sizeof(T))) == 0;
+    const int64_t np = (n + K - 1) / K;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        double xi = static_cast<double>(x[i]);
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
+        const int64_t i0 = q * K;
+        T xv[K], vt[NV][K];
+        if (aligned) {
+            ld_pack<T, K>(x, i0, n, xv);
+        } else {
+#pragma unroll
+            for (int e = 0; e < K; ++e) xv[e] = i0 + e < n ? x[i0 + e] : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+            if (t < used) {
+                ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < K; ++e) vt[t][e] = T(0);
+            }
+        }
+        double xd[K];
+#pragma unroll
+        for (int e = 0; e < K; ++e) xd[e] = static_cast<double>(xv[e]);
 #pragma unroll
         for (int t = 0; t < NV; ++t)
-            if (t < used) xi = fma(y[t], static_cast<double>(vec(V, n, t)[i]), xi);
-        x[i] = static_cast<T>(xi);
+#pragma unroll
+            for (int e = 0; e < K; ++e) xd[e] = fma(y[t], static_cast<double>(vt[t][e]), xd[e]);
+#pragma unroll
+        for (int e = 0; e < K; ++e) xv[e] = static_cast<T>(xd[e]);
+        if (aligned) {
+            st_pack<T, K>(x, i0, n, xv);
+        } else {
+#pragma unroll
+            for (int e = 0; e < K; ++e)
+                if (i0 + e < n) x[i0 + e] = xv[e];
+        }
     }
 }
 
@@ -356,7 +552,7 @@ template <typename T>
 static hipError_t step_spmv_t(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
                               const SolveState *st, const GmresState *gs, hipStream_t s) {
     EpiGmW<T> e{static_cast<T *>(w), st, gs};
-    return gm_spmv<T>(A, t, static_cast<const T *>(V) + static_cast<int64_t>(j) * A.n_rows, e, s);
+    return gm_spmv<T>(A, t, static_cast<const T *>(V) + static_cast<int64_t>(j) * gm_ld(A.n_rows), e, s);
 }
 
 hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
@@ -369,19 +565,20 @@ static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, Sol
                               double *gpart, hipStream_t s) {
     const int J = j + 1;
     const int nv = nv_bucket(J);
-    T *vj = V + static_cast<int64_t>(j) * n;
-    T *vn = V + static_cast<int64_t>(j + 1) * n;
+    const int64_t ld = gm_ld(n);
+    T *vj = V + static_cast<int64_t>(j) * ld;
+    T *vn = V + static_cast<int64_t>(j + 1) * ld;
 #define SPK_GM_NV(K, ...)                                                                                   \
     do {                                                                                                    \
         if (nv == 8) hipLaunchKernelGGL((K<T, 8>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);            \
         else if (nv == 16) hipLaunchKernelGGL((K<T, 16>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);     \
         else hipLaunchKernelGGL((K<T, 32>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
     } while (0)
-    SPK_GM_NV(k_gm_dots, n, V, vj, w, j, st, gs, gpart);
+    SPK_GM_NV(k_gm_dots, n, ld, V, vj, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h1[0], st, gs);
-    SPK_GM_NV(k_gm_pass2, n, V, w, j, st, gs, gpart);
+    SPK_GM_NV(k_gm_pass2, n, ld, V, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h2[0], st, gs);
-    SPK_GM_NV(k_gm_pass3, n, V, vn, w, j, st, gs, gpart);
+    SPK_GM_NV(k_gm_pass3, n, ld, V, vn, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kBlock), 0, s, st, gs, gpart, grid, j, m);
 #undef SPK_GM_NV
     return hipGetLastError();
@@ -398,9 +595,10 @@ template <typename T>
 static hipError_t cycle_end_t(int64_t n, int grid, int m, const T *V, SolveState *st, GmresState *gs, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, st, gs);
     const int nv = nv_bucket(m);
-    if (nv == 8) hipLaunchKernelGGL((k_gm_update_x<T, 8>), dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
-    else if (nv == 16) hipLaunchKernelGGL((k_gm_update_x<T, 16>), dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
-    else hipLaunchKernelGGL((k_gm_update_x<T, 32>), dim3(grid), dim3(kBlock), 0, s, n, V, st, gs);
+    const int64_t ld = gm_ld(n);
+    if (nv == 8) hipLaunchKernelGGL((k_gm_update_x<T, 8>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, st, gs);
+    else if (nv == 16) hipLaunchKernelGGL((k_gm_update_x<T, 16>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, st, gs);
+    else hipLaunchKernelGGL((k_gm_update_x<T, 32>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, st, gs);
     return hipGetLastError();
 }
 

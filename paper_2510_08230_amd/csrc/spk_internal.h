@@ -146,11 +146,13 @@ hipError_t launch_cgs_spmv_r(const CsrDev &A, const SpmvTune &t, const double *u
                              SolveState *st, double *partials, hipStream_t s);
 hipError_t launch_cgs_check(SolveState *st, double *partials, int spmv_grid, int count, hipStream_t s);
 
-// Restarted GMRES(m) (FP64; spk_gmres.hip).  V holds m + 1 basis vectors of
-// n doubles back to back, w one more vector, gpart (kMaxKrylov + 1) *
-// kMaxGrid doubles.  A solve is begin, then per cycle: cycle_start (r = b - A x
+// Restarted GMRES(m) (spk_gmres.hip).  V holds m + 1 basis vectors, column t
+// at V + t * gm_ld(n) elements (16-byte aligned for the packed passes); w is
+// one more vector (16-byte aligned), gpart (kMaxKrylov + 1) * kMaxGrid
+// doubles.  A solve is begin, then per cycle: cycle_start (r = b - A x
 // into v_0, beta, stop test), for j = 0..m-1 step_spmv(j) and step_rest(j),
 // then cycle_end (R y = g, x += V y); the host polls after each cycle.
+constexpr int64_t gm_ld(int64_t n) { return (n + 63) / 64 * 64; }
 hipError_t launch_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist, int64_t hist_cap,
                            int64_t max_iters, hipStream_t s);
 // fp32: FP32 basis, w and x (A's values F32, BF16 or F16), else FP64 (F64 values).
