@@ -37,6 +37,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=215, help="stencil7 grid edge (n = N^3)")
+    ap.add_argument("--pattern", choices=["stencil7", "randsym"], default="stencil7",
+                    help="solve-mode matrix: stencil7 N (default) or randsym n (CG only)")
+    ap.add_argument("--n", type=int, default=10_000_000, help="randsym dimension")
+    ap.add_argument("--delta", type=float, default=1.0,
+                    help="diagonal margin: a_ii = sum |a_ij| + delta (1e-2 gives the harder system)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tau", type=float, default=1e-14)
     ap.add_argument("--solver", choices=["cg", "cgs", "gmres"], default="cg",
@@ -49,7 +54,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="cap on the oracle iterations of cpu_baseline (0: 60, or 12 for GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calib", action="store_true", help="also time the plain copy kernel")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="time the plain copy kernel (the default; kept for older command lines)")
+    ap.add_argument("--no-copy-calib", action="store_true", help="skip the copy-kernel calibration")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-launch HIP events (no roofline; needed for graph/persistent)")
     ap.add_argument("--serve", action="store_true",
@@ -70,11 +77,31 @@ def parse():
     return ap.parse_args()
 
 
+def host_info():
+    """CPU model, logical CPU count and memory of the host the oracle ran on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["mem_gb"] = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
 def measured_traffic(args, N):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-kernel scaled), or None when
     that summary is for other kernel sources or another workload."""
-    if args.precision != "fp64" or N != 215 or args.seed != 1 or args.solver != "cg" or args.precond != "none":
+    if (args.precision != "fp64" or N != 215 or args.seed != 1 or args.solver != "cg" or args.precond != "none"
+            or args.pattern != "stencil7" or args.delta != 1.0):
         return None
     path = os.path.join(ROOT, "profiles", "spmv_pq_cg_fp64_stencil7_N215_traffic.json")
     if not os.path.exists(path):
@@ -91,7 +118,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: multi-GPU runs are not part of this build "
-              "(the sharded design is described in DESIGN.md).", file=sys.stderr)
+              "(a run on several GPUs is not supported).", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve(args)
@@ -116,7 +143,15 @@ def main():
     if (cgs or args.precond != "none") and args.precision != "fp64":
         print("CGS and the Jacobi preconditioner run in FP64 only", file=sys.stderr)
         sys.exit(2)
-    A = inputs.stencil7_ns(N, args.seed) if (cgs or gm) else inputs.stencil7(N, args.seed)
+    if args.pattern == "randsym":
+        if cgs or gm:
+            print("the randsym pattern is symmetric: use it with CG", file=sys.stderr)
+            sys.exit(2)
+        A = inputs.randsym(args.n, args.seed, delta=args.delta)
+    elif cgs or gm:
+        A = inputs.stencil7_ns(N, args.seed, delta=args.delta)
+    else:
+        A = inputs.stencil7(N, args.seed, delta=args.delta)
     b_h = inputs.rhs(A.n_rows, args.seed)
     n, nnz = A.n_rows, A.nnz
     rp = torch.from_numpy(A.row_ptr).to(torch.int32).to(dev)
@@ -179,16 +214,20 @@ def main():
     last = logs[-1]
     traffic = measured_traffic(args, N)
     jname = "_jacobi" if args.precond == "jacobi" else ""
+    dname = "" if args.delta == 1.0 else "_delta%g" % args.delta
+    mname = ("randsym_n%d" % n) if args.pattern == "randsym" else ("stencil7ns_N%d" if (cgs or gm) else
+                                                                 "stencil7_N%d") % N
     if cgs:
-        workload = "cgs%s_fp64_stencil7ns_N%d" % (jname, N)
+        workload = "cgs%s_fp64_%s" % (jname, mname)
         spmv_kernel = "k_spmv_*<EpiCgsV>, k_spmv_*<EpiCgsR> (two SpMVs per CGS iteration)"
     elif gm:
-        workload = "gmres%d%s_%s_stencil7ns_N%d" % (args.krylov_dim, jname, args.precision, N)
+        workload = "gmres%d%s_%s_%s" % (args.krylov_dim, jname, args.precision, mname)
         spmv_kernel = "k_spmv_*<EpiGmW> (w = A v_j / ||v_j||, one per Arnoldi step%s)" % (
             "" if args.precision == "fp64" else "; inner GMRES of the refinement")
     else:
-        workload = "%s_%s_stencil7_N%d" % ("pcg_jacobi" if args.precond == "jacobi" else "cg", args.precision, N)
+        workload = "%s_%s_%s" % ("pcg_jacobi" if args.precond == "jacobi" else "cg", args.precision, mname)
         spmv_kernel = "k_spmv_*<EpiPq> (q = A p fused with p.q)"
+    workload += dname
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
         "value": value,
@@ -201,9 +240,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "mixed_fp32" else "bf16+f32+f64"),
-        "data": ("synthetic (seeded nonsymmetric stencil7, independent uniform[-1,1) off-diagonals, "
-                 "row diagonally dominant)" if (cgs or gm) else
-                 "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD)"),
+        "data": ("synthetic (seeded randsym: 3 uniform partners per row, symmetrised, uniform[-1,1) values, "
+                 "diagonally dominant SPD, delta %g)" % args.delta if args.pattern == "randsym" else
+                 "synthetic (seeded nonsymmetric stencil7, independent uniform[-1,1) off-diagonals, "
+                 "row diagonally dominant, delta %g)" % args.delta if (cgs or gm) else
+                 "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD, "
+                 "delta %g)" % args.delta),
         "config": {"workload": workload, "n": n, "nnz": nnz, "seed": args.seed,
                    "tau": args.tau, "index_types": "int32/int32", "iterations_per_solve": last.iterations,
                    "outer_iterations": last.outer_iterations,
@@ -214,12 +256,34 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": klaunch},
     }
-    if args.copy_calib:
+    # Rates the paper and the roofline discussion also use: nonzeros and GFLOP/s
+    # (2 nnz flops per SpMV) over the timed steps, and for CG the whole
+    # iteration's bytes against the floor nnz (S_v + S_i) + (n+1) S_p + 7 n S_x
+    # (A once; p gathered once; x, r, p read and written once) and against the
+    # 10 n S_x of vectors the three launches move, over the last solve's device time.
+    spmv_per_iter = 2 if cgs else 1
+    spmvs = iters * spmv_per_iter
+    derived = {"nnz_per_s": nnz * spmvs / wall, "gflop_per_s": 2.0 * nnz * spmvs / wall / 1e9}
+    if not (cgs or gm) and last.iterations > 0:
+        sv, sx = (8, 8) if args.precision == "fp64" else ((4 if args.precision == "mixed_fp32" else 2), 4)
+        mat = nnz * (sv + 4) + (n + 1) * 4
+        floor_b, moved_b = mat + 7 * n * sx, mat + 10 * n * sx
+        t_it = last.elapsed_ms * 1e-3 / last.iterations
+        derived["iteration"] = {
+            "floor_bytes": floor_b, "moved_bytes": moved_b, "ms": t_it * 1e3,
+            "GBs_vs_floor": floor_b / t_it / 1e9, "frac_floor": floor_b / t_it / 1e9 / HBM_PEAK_GBS,
+            "GBs_moved": moved_b / t_it / 1e9,
+            "note": "solve device time / iterations (includes the initial and true-residual products)"}
+    out["derived"] = derived
+    if not args.no_copy_calib:
         nbytes = 1 << 30
         src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         best = min(spk.spk_stream_copy(ctx, src, dst, nbytes) for _ in range(5))
-        out["copy_calib"] = {"bytes": 2 * nbytes, "ms": best, "GBs": 2 * nbytes / (best * 1e-3) / 1e9}
+        cgbs = 2 * nbytes / (best * 1e-3) / 1e9
+        out["copy_calib"] = {"bytes": 2 * nbytes, "ms": best, "GBs": cgbs}
+        if achieved:
+            out["roofline"]["frac_vs_copy"] = achieved / cgbs
 
     if not args.no_cpu_baseline:
         # The FP64 oracle on the same system with the same tolerance, capped at
@@ -262,7 +326,7 @@ def main():
                              "solve meets the FP64 criterion: rel_true_residual)")
         err = float(np.linalg.norm(x_gpu - xo) / np.linalg.norm(xo))
         out["cpu_baseline"] = {"value": n * res.iterations / dt, "unit": "updates/s", "cores": 1,
-                               "kind": "oracle",
+                               "kind": "oracle", "host": host_info(),
                                "sample": "FP64 oracle %s, same system and tolerance, %d iterations (plus initial "
                                          "and true residual), %.1f s" % (label, res.iterations, dt)}
         out["error_vs_oracle"] = {"rel_2norm": err, "compared": compared,
@@ -355,6 +419,7 @@ def spmv_mode(args):
                                   "compared": "last timed product vs the oracle's product of the same "
                                               "(identically rounded) inputs"}
         out["cpu_baseline"] = {"value": 2.0 * nnz * reps / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+                               "host": host_info(),
                                "sample": "FP64 oracle %s product, same matrix, %d products, %.1f s"
                                          % (args.spmv.upper(), reps, dt)}
     print(json.dumps(out), flush=True)
@@ -567,6 +632,7 @@ def serve(args):
         for i in sample:
             worst_rel = max(worst_rel, float(np.linalg.norm(served[i] - sols[i]) / np.linalg.norm(sols[i])))
         out["cpu_baseline"] = {"value": o_updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                               "host": host_info(),
                                "sample": "FP64 oracle CG to the same tolerance on %d of the %d instances "
                                          "(every %d-th), %.1f s" % (len(sample), len(mats),
                                                                    max(1, len(mats) // max(args.oracle_sample, 1)), dt)}
