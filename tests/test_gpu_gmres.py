@@ -316,3 +316,49 @@ def test_gmres_ir_full_size_residual():
         assert np.linalg.norm(oracle.residual(A, b, x)) <= 1e-12 * np.linalg.norm(b) * 1.01
     finally:
         spk.spk_finalize(ctx)
+
+
+# The packed passes load the last pack of a vector element by element when n
+# is not a multiple of the pack (2 doubles, up to 4 floats), and update x
+# element by element when the caller's x is not aligned to the pack.
+RAGGED = {"n729": lambda: inputs.stencil7_ns(9, 3), "n1331": lambda: inputs.stencil7_ns(11, 4),
+          "n30002": lambda: inputs.randsym(30002, 5)}
+
+
+@pytest.mark.parametrize("name", sorted(RAGGED))
+@pytest.mark.parametrize("m,K", [(5, 12), (30, 20)])
+def test_ragged_tails(spk, ctx, name, m, K):
+    A = RAGGED[name]()
+    b = inputs.rhs(A.n_rows, 6)
+    x, log, _ = gmres(spk, ctx, A, b, m=m, tau=0.0, max_iters=K)
+    xo, _, _ = oracle.gmres(A, b, tau=0.0, max_iters=K, m=m)
+    assert log.iterations == K and rel(x, xo) <= 1e-12
+    xi, logi = gmres_ir(spk, ctx, A, b, m=m, inner=1e-30, max_outer=1, max_iters=K)
+    xoi, _, _ = oracle.gmres(rounded32(A), b.astype(np.float32).astype(np.float64), tau=0.0, max_iters=K, m=m)
+    assert logi.iterations == K and rel(xi, xoi) <= 2e-5
+
+
+def test_unaligned_solution_vector(spk, ctx):
+    """x an 8-byte-offset view (not 16-byte aligned): same iterates as an aligned x."""
+    A = inputs.stencil7_ns(12, 2)
+    n = A.n_rows
+    b = inputs.rhs(n, 2)
+    x0 = inputs.vec(n, 2, 20)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = spk.SOLVER_GMRES
+    cfg.krylov_dim = 7
+    cfg.reduction_factor = 0.0
+    cfg.max_iters = 17
+    pl = spk.spk_plan_solve(ctx, dev_csr(spk, A), cfg)
+    big = torch.zeros(n + 1, dtype=torch.float64, device="cuda:0")
+    xu = big[1:]
+    assert xu.data_ptr() % 16 == 8
+    xu.copy_(to_dev(x0))
+    xa = to_dev(x0)
+    bd = to_dev(b)
+    spk.spk_execute_solve(pl, bd, xu)
+    spk.spk_execute_solve(pl, bd, xa)
+    spk.spk_free(pl)
+    assert np.array_equal(xu.cpu().numpy().view(np.uint64), xa.cpu().numpy().view(np.uint64))
+    xo, _, _ = oracle.gmres(A, b, x0=x0, tau=0.0, max_iters=17, m=7)
+    assert rel(xa.cpu().numpy(), xo) <= 1e-12
