@@ -307,7 +307,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     }
     if (kind < 0) return false;
     if (kind == 0 && !stream_ok(A)) kind = 1;
-    if (remap < 0) remap = (kind == 0) ? 1 : 1;
+    if (remap < 0) remap = 1;
     *t = make_tune(ctx, A, kind, l2, remap, nt, pf, bpc);
     return true;
 }
