@@ -48,8 +48,8 @@ def parse():
                     help="cgs and gmres run on the nonsymmetric stencil7 variant of the same size")
     ap.add_argument("--krylov-dim", type=int, default=30, help="GMRES restart length")
     ap.add_argument("--precond", choices=["none", "jacobi"], default="none")
-    ap.add_argument("--precision", choices=["fp64", "mixed_fp32", "mixed_bf16"], default="fp64",
-                    help="fp64 CG, or FP32/BF16 inner CG with FP64 refinement")
+    ap.add_argument("--precision", choices=["fp64", "mixed_fp32", "mixed_bf16", "mixed_fp16"], default="fp64",
+                    help="fp64 solve, or an inner solve on FP32/BF16/FP16 matrix values with FP64 refinement")
     ap.add_argument("--inner", type=float, default=1e-4, help="inner reduction factor (mixed)")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="cap on the oracle iterations of cpu_baseline (0: 60, or 12 for GMRES)")
@@ -167,7 +167,7 @@ def main():
     cfg.max_iters = 1000
     cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
     cfg.precision = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32,
-                     "mixed_bf16": spk.PREC_MIXED_BF16}[args.precision]
+                     "mixed_bf16": spk.PREC_MIXED_BF16, "mixed_fp16": spk.PREC_MIXED_FP16}[args.precision]
     cfg.inner_reduction = args.inner
     cfg.solver = spk.SOLVER_CGS if cgs else (spk.SOLVER_GMRES if gm else spk.SOLVER_CG)
     cfg.krylov_dim = args.krylov_dim
@@ -239,7 +239,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else ("f32+f64" if args.precision == "mixed_fp32" else "bf16+f32+f64"),
+        "dtype": {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64",
+                  "mixed_fp16": "f16+f32+f64"}[args.precision],
         "data": ("synthetic (seeded randsym: 3 uniform partners per row, symmetrised, uniform[-1,1) values, "
                  "diagonally dominant SPD, delta %g)" % args.delta if args.pattern == "randsym" else
                  "synthetic (seeded nonsymmetric stencil7, independent uniform[-1,1) off-diagonals, "

@@ -86,7 +86,9 @@ typedef enum {
     SPK_PREC_FP64 = 0,        /* FP64 values, vectors and reductions */
     SPK_PREC_MIXED_FP32 = 1,  /* FP32 inner solve (CG or GMRES: FP32 vectors, FP64 reductions)
                                  + FP64 iterative refinement */
-    SPK_PREC_MIXED_BF16 = 2   /* BF16 matrix values in the inner solve, otherwise as MIXED_FP32 */
+    SPK_PREC_MIXED_BF16 = 2,  /* BF16 matrix values in the inner solve, otherwise as MIXED_FP32 */
+    SPK_PREC_MIXED_FP16 = 3   /* IEEE binary16 ("half", Table 1) matrix values in the inner solve,
+                                 otherwise as MIXED_FP32 */
 } spk_precision;
 typedef enum { SPK_BASELINE_RHS_NORM = 0 } spk_baseline;
 typedef enum {
@@ -222,7 +224,8 @@ spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
 
 /* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
  * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
- * an FP32/BF16 copy for the inner solve) or F32 values (taken as exact).
+ * an FP32, BF16 or FP16 copy for the inner solve, each value rounded once to
+ * nearest even) or, for MIXED_FP32, F32 values (taken as exact).
  * CGS and the Jacobi preconditioner are FP64 only; GMRES runs in the host
  * loop, in FP64 or as the inner solver of a mixed precision (its basis then
  * holds (krylov_dim + 1) n floats); a Jacobi plan computes 1 / diag(A) (and for CGS and GMRES a

@@ -824,7 +824,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     if ((cfg.solver == SPK_SOLVER_CGS || cfg.precond == SPK_PRECOND_JACOBI) && cfg.precision != SPK_PREC_FP64)
         return fail(ctx, SPK_ERR_UNSUPPORTED, "CGS and the Jacobi preconditioner run in FP64 precision");
     if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
-    if (cfg.precision < SPK_PREC_FP64 || cfg.precision > SPK_PREC_MIXED_BF16)
+    if (cfg.precision < SPK_PREC_FP64 || cfg.precision > SPK_PREC_MIXED_FP16)
         return fail(ctx, SPK_ERR_INVALID_ARG, "unknown precision");
     if (cfg.max_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_iters < 0");
     if (!(cfg.reduction_factor >= 0.0)) return fail(ctx, SPK_ERR_INVALID_ARG, "reduction_factor must be >= 0");
@@ -841,8 +841,8 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     if (!mixed && A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
     if (mixed && A->val_type != SPK_F64 && A->val_type != SPK_F32)
         return fail(ctx, SPK_ERR_INVALID_ARG, "mixed precision needs F64 or F32 values");
-    if (cfg.precision == SPK_PREC_MIXED_BF16 && A->val_type != SPK_F64)
-        return fail(ctx, SPK_ERR_UNSUPPORTED, "BF16 inner values are rounded from F64 values only");
+    if ((cfg.precision == SPK_PREC_MIXED_BF16 || cfg.precision == SPK_PREC_MIXED_FP16) && A->val_type != SPK_F64)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "BF16 and FP16 inner values are rounded from F64 values only");
 
     spk_plan pl = new spk_plan_s();
     pl->ctx = ctx;
@@ -938,17 +938,19 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         // inner matrix view: rounded copy of F64 values, or the F32 values themselves
         pl->A32 = pl->A;
         if (A->val_type == SPK_F64) {
-            const bool bf = cfg.precision == SPK_PREC_MIXED_BF16;
+            const int to = cfg.precision == SPK_PREC_MIXED_BF16   ? SPK_BF16
+                           : cfg.precision == SPK_PREC_MIXED_FP16 ? SPK_F16
+                                                                  : SPK_F32;
+            const size_t width = to == SPK_F32 ? 4 : 2;
             void *dst = nullptr;
-            if (ctx->dpool.get(std::max<size_t>(1, A->nnz * (bf ? 2 : 4)), &dst) != hipSuccess)
+            if (ctx->dpool.get(std::max<size_t>(1, A->nnz * width), &dst) != hipSuccess)
                 return cleanup(SPK_ERR_OUT_OF_MEMORY, "low-precision value copy");
             pl->a32_vals = dst;
-            if (A->nnz > 0 &&
-                spk::launch_round_values(A->nnz, static_cast<const double *>(A->values), dst, bf ? 1 : 0,
-                                         ctx->num_cu * 4, ctx->stream) != hipSuccess)
+            if (A->nnz > 0 && spk::launch_round_values(A->nnz, static_cast<const double *>(A->values), dst, to,
+                                                       ctx->num_cu * 4, ctx->stream) != hipSuccess)
                 return cleanup(SPK_ERR_DEVICE, "value rounding");
             pl->A32.va = dst;
-            pl->A32.val_t = bf ? SPK_BF16 : SPK_F32;
+            pl->A32.val_t = to;
         }
         if (pl->algo == ALGO_GMRES) {   // GMRES-IR: FP32 basis
             const size_t vbytes =

@@ -126,7 +126,8 @@ hipError_t launch_ir_residual(const CsrDev &A, const SpmvTune &t, const double *
                               int64_t max_inner, double *out, hipStream_t s);
 hipError_t launch_ir_correct(int64_t n, int grid, double *x, const float *d, hipStream_t s);
 // Round FP64 values to FP32 (bf16 = 0) or BF16 (bf16 = 1, round to nearest even).
-hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int bf16, int grid, hipStream_t s);
+// to: spk_dtype code 1 (F32), 2 (F16) or 3 (BF16); each value rounded once, to nearest even.
+hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int to, int grid, hipStream_t s);
 // Sets x = 0 when b == 0, then (optionally) recomputes ||b - A x|| into the state.
 hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *b, double *x,
                               SolveState *st, double *partials, int true_residual, hipStream_t s);

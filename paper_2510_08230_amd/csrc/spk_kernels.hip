@@ -347,11 +347,20 @@ __global__ __launch_bounds__(kBlock) void k_round_values<float>(int64_t nnz, con
         dst[i] = static_cast<float>(src[i]);
 }
 
-// FP64 -> bfloat16 with round-to-nearest-even (NaN kept quiet).
+// FP64 -> bfloat16, rounded once to nearest even (NaN kept quiet).  The
+// FP64 value is first narrowed to FP32 rounding to odd (truncate, then set
+// the last bit if anything was dropped), which keeps the information the
+// second rounding needs: FP32 carries 24 bits, more than bfloat16's 8 + 2,
+// so nearest-even from the odd-rounded FP32 equals nearest-even from FP64
+// (Boldo & Melquiond, round-to-odd).
 __device__ __forceinline__ uint16_t to_bf16_rne(double v) {
-    const float f = static_cast<float>(v);
-    const unsigned u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    const float t = __double2float_rz(v);
+    unsigned u = __float_as_uint(t);
+    if ((u & 0x7f800000u) == 0x7f800000u) {   // Inf or NaN (truncation cannot overflow to Inf)
+        if (u & 0x7fffffu) return static_cast<uint16_t>((u >> 16) | 0x40u);
+        return static_cast<uint16_t>(u >> 16);
+    }
+    if (static_cast<double>(t) != v) u |= 1u;   // sticky: round to odd
     const unsigned rounding = 0x7fffu + ((u >> 16) & 1u);
     return static_cast<uint16_t>((u + rounding) >> 16);
 }
@@ -362,6 +371,16 @@ __global__ __launch_bounds__(kBlock) void k_round_values<bf16s>(int64_t nnz, con
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nnz; i += stride)
         dst[i].bits = to_bf16_rne(src[i]);
+}
+
+// FP64 -> binary16: the compiler's conversion rounds once to nearest even
+// (subnormal halves and overflow to Inf included).
+template <>
+__global__ __launch_bounds__(kBlock) void k_round_values<_Float16>(int64_t nnz, const double *__restrict__ src,
+                                                                  _Float16 *__restrict__ dst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nnz; i += stride)
+        dst[i] = static_cast<_Float16>(src[i]);
 }
 
 // Advance the chunk base after `count` iterations (one thread).
@@ -836,11 +855,16 @@ hipError_t launch_ir_correct(int64_t n, int grid, double *x, const float *d, hip
     return hipGetLastError();
 }
 
-hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int bf16, int grid, hipStream_t s) {
-    if (bf16)
+hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int to, int grid, hipStream_t s) {
+    if (to == 3)   // BF16
         hipLaunchKernelGGL(k_round_values<bf16s>, dim3(grid), dim3(kBlock), 0, s, nnz, src, static_cast<bf16s *>(dst));
-    else
+    else if (to == 2)   // F16
+        hipLaunchKernelGGL(k_round_values<_Float16>, dim3(grid), dim3(kBlock), 0, s, nnz, src,
+                           static_cast<_Float16 *>(dst));
+    else if (to == 1)   // F32
         hipLaunchKernelGGL(k_round_values<float>, dim3(grid), dim3(kBlock), 0, s, nnz, src, static_cast<float *>(dst));
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ CSR_OK, CSR_BAD_SIZE, CSR_BAD_FIRST, CSR_DECREASING, CSR_BAD_LAST, CSR_BAD_COLUM
 STOP_RUNNING, STOP_CONVERGED, STOP_MAX_ITERS, STOP_BREAKDOWN, STOP_NON_FINITE = range(5)
 SOLVER_CG, SOLVER_CGS, SOLVER_GMRES = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
-PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = range(3)
+PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16, PREC_MIXED_FP16 = range(4)
 EXEC_AUTO, EXEC_HOST_LOOP, EXEC_GRAPH, EXEC_PERSISTENT = range(4)
 
 

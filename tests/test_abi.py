@@ -51,6 +51,7 @@ int main(void) {
   P(spk_solver_cfg, krylov_dim)
   printf("SPK_SOLVER_CGS %d\nSPK_PRECOND_JACOBI %d\nSPK_EXEC_PERSISTENT %d\nSPK_PREC_MIXED_BF16 %d\n",
          (int)SPK_SOLVER_CGS, (int)SPK_PRECOND_JACOBI, (int)SPK_EXEC_PERSISTENT, (int)SPK_PREC_MIXED_BF16);
+  printf("SPK_PREC_MIXED_FP16 %d\n", (int)SPK_PREC_MIXED_FP16);
   return 0;
 }
 """
@@ -83,6 +84,7 @@ def test_struct_layouts_match_header(tmp_path):
     assert int(got["SPK_SOLVER_GMRES"]) == spk.SOLVER_GMRES
     assert int(got["spk_solver_cfg.krylov_dim"]) == spk.SolverCfg.krylov_dim.offset
     assert int(got["SPK_PREC_MIXED_BF16"]) == spk.PREC_MIXED_BF16
+    assert int(got["SPK_PREC_MIXED_FP16"]) == spk.PREC_MIXED_FP16
 
 
 def test_defaults_and_status_strings():

@@ -223,7 +223,7 @@ def gmres_ir(spk, ctx, A, b, prec="fp32", m=30, tau=1e-12, inner=1e-4, max_outer
     cfg = spk.spk_solver_cfg_default()
     cfg.solver = spk.SOLVER_GMRES
     cfg.krylov_dim = m
-    cfg.precision = spk.PREC_MIXED_FP32 if prec == "fp32" else spk.PREC_MIXED_BF16
+    cfg.precision = {"fp32": spk.PREC_MIXED_FP32, "bf16": spk.PREC_MIXED_BF16, "fp16": spk.PREC_MIXED_FP16}[prec]
     cfg.reduction_factor = tau
     cfg.inner_reduction = inner
     cfg.max_outer = max_outer
@@ -240,7 +240,7 @@ def rounded32(A):
 
 
 @pytest.mark.parametrize("name", sorted(MATS))
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("m", [30, 8])
 def test_gmres_ir_matches_fp64_oracle(spk, ctx, name, prec, m):
     A = MATS[name]()

@@ -1,5 +1,6 @@
-"""Mixed precision (FP32 or BF16 inner CG with FP64 dot products, FP64
-iterative refinement) on the GPU against the FP64 oracle.
+"""Mixed precision (FP32, BF16 or FP16 matrix values in an inner CG with
+FP32 vectors and FP64 dot products, FP64 iterative refinement) on the GPU
+against the FP64 oracle.
 
 Stated tolerance (the mixed-precision configuration asks for it): the
 refined solution is within 1e-10 (relative 2-norm) of the oracle's FP64 CG
@@ -50,13 +51,16 @@ def solve_mixed(spk, ctx, A, b, prec, tau=1e-12, x0=None, val=torch.float64, max
 MATS = {"stencil7_46": lambda: inputs.stencil7(46, 0), "randsym_1e5": lambda: inputs.randsym(100000, 0)}
 
 
+PRECS = {"fp32": "PREC_MIXED_FP32", "bf16": "PREC_MIXED_BF16", "fp16": "PREC_MIXED_FP16"}
+
+
 @pytest.mark.parametrize("name", sorted(MATS))
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", sorted(PRECS))
 @pytest.mark.parametrize("mode", [1, 2])
 def test_refined_solution_matches_fp64_oracle(spk, ctx, name, prec, mode):
     A = MATS[name]()
     b = inputs.rhs(A.n_rows, 0)
-    p = spk.PREC_MIXED_FP32 if prec == "fp32" else spk.PREC_MIXED_BF16
+    p = getattr(spk, PRECS[prec])
     x, log = solve_mixed(spk, ctx, A, b, p, mode=mode)
     xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=2000)
     assert log.stop_reason == spk.STOP_CONVERGED and log.outer_iterations >= 1
@@ -104,10 +108,15 @@ def test_mixed_reruns_bitwise(spk, ctx):
 def test_mixed_plan_errors(spk, ctx):
     A = inputs.stencil7(4, 0)
     cfg = spk.spk_solver_cfg_default()
-    cfg.precision = spk.PREC_MIXED_BF16
+    for prec in (spk.PREC_MIXED_BF16, spk.PREC_MIXED_FP16):   # rounded from F64 values only
+        cfg.precision = prec
+        with pytest.raises(spk.SpkError) as e:
+            spk.spk_plan_solve(ctx, dev_csr(spk, A, val=torch.float32), cfg)
+        assert e.value.status == spk.ERR_UNSUPPORTED
+    cfg.precision = 4
     with pytest.raises(spk.SpkError) as e:
-        spk.spk_plan_solve(ctx, dev_csr(spk, A, val=torch.float32), cfg)
-    assert e.value.status == spk.ERR_UNSUPPORTED
+        spk.spk_plan_solve(ctx, dev_csr(spk, A), cfg)
+    assert e.value.status == spk.ERR_INVALID_ARG
     cfg.precision = spk.PREC_MIXED_FP32
     cfg.inner_reduction = 1.5
     with pytest.raises(spk.SpkError) as e:
