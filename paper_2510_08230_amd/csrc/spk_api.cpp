@@ -1041,8 +1041,12 @@ static spk_status run_gmres(spk_plan pl, const void *b, void *x, bool inner, int
     // every cycle but the last completes at least one step
     const int64_t max_cycles = max_iters + 2;
     for (int64_t c = 0; c < max_cycles; ++c) {
-        SPK_HIP(ctx, spk::launch_gm_cycle_start(A, tune, b, x, pl->gm_V, st, pl->gm_st, pl->partials, tau, m, inner,
-                                                s));
+        if (inner && c == 0)   // the inner solve starts from d = 0: r = b needs no product
+            SPK_HIP(ctx, spk::launch_gm_cycle_start_zero(n, pl->vec_grid, b, pl->gm_V, st, pl->gm_st, pl->partials,
+                                                         tau, m, inner, s));
+        else
+            SPK_HIP(ctx, spk::launch_gm_cycle_start(A, tune, b, x, pl->gm_V, st, pl->gm_st, pl->partials, tau, m,
+                                                    inner, s));
         for (int j = 0; j < m; ++j) {
             hipEvent_t e = nullptr;
             spk_status ps = prof_begin(pl, &e);

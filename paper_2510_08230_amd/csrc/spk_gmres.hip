@@ -74,6 +74,23 @@ struct EpiGmW {
     __device__ void finish() {}
 };
 
+// r = b into v_0 when x = 0 (the first cycle of a refinement's inner solve,
+// which starts from d = 0): the partials EpiGmRes would give, without the SpMV.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gm_residual_zero(int64_t n, const T *__restrict__ b, T *__restrict__ v0,
+                                                             const SolveState *st, double *part) {
+    if (st->stop != STOP_RUNNING) return;
+    double rr = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const T bi = b[i];
+        v0[i] = bi;
+        rr = fma(static_cast<double>(bi), static_cast<double>(bi), rr);
+    }
+    double w[2] = {rr, rr};
+    block_partial<2>(w, part);
+}
+
 // Solve set-up (one thread): the state fields every later kernel reads.
 __global__ void k_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist, int64_t hist_cap,
                            int64_t max_iters) {
@@ -546,6 +563,18 @@ hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const void 
                                  hipStream_t s) {
     return fp32 ? cycle_start_t<float>(A, t, b, x, V, st, gs, partials, tau, m, s)
                 : cycle_start_t<double>(A, t, b, x, V, st, gs, partials, tau, m, s);
+}
+
+hipError_t launch_gm_cycle_start_zero(int64_t n, int grid, const void *b, void *V, SolveState *st, GmresState *gs,
+                                      double *partials, double tau, int m, bool fp32, hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(k_gm_residual_zero<float>, dim3(grid), dim3(kBlock), 0, s, n, static_cast<const float *>(b),
+                           static_cast<float *>(V), st, site(partials, SITE_INIT));
+    else
+        hipLaunchKernelGGL(k_gm_residual_zero<double>, dim3(grid), dim3(kBlock), 0, s, n,
+                           static_cast<const double *>(b), static_cast<double *>(V), st, site(partials, SITE_INIT));
+    hipLaunchKernelGGL(k_gm_cycle_start, dim3(1), dim3(kBlock), 0, s, st, gs, site(partials, SITE_INIT), grid, tau, m);
+    return hipGetLastError();
 }
 
 template <typename T>

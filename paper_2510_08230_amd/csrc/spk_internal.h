@@ -160,6 +160,9 @@ hipError_t launch_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist
 hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const void *b, const void *x, void *V,
                                  SolveState *st, GmresState *gs, double *partials, double tau, int m, bool fp32,
                                  hipStream_t s);
+// The same when x = 0 (no product: r = b); grid workgroups of kBlock.
+hipError_t launch_gm_cycle_start_zero(int64_t n, int grid, const void *b, void *V, SolveState *st, GmresState *gs,
+                                      double *partials, double tau, int m, bool fp32, hipStream_t s);
 hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
                                const SolveState *st, const GmresState *gs, bool fp32, hipStream_t s);
 hipError_t launch_gm_step_rest(int64_t n, int grid, void *V, void *w, int j, int m, SolveState *st, GmresState *gs,
