@@ -4,6 +4,7 @@
 // chunk size).  All GPU work goes through the launchers in spk_kernels.hip.
 #include "spk.h"
 #include "spk_internal.h"
+#include "spk_launch.h"
 #include "spk_pool.h"
 
 #include <algorithm>

@@ -15,6 +15,7 @@
 // Scalars a launch writes are read only by later launches; the phase a tick
 // acts on is committed by the last launch of the tick.
 #include "spk_device.h"
+#include "spk_launch.h"
 
 namespace spk {
 namespace {

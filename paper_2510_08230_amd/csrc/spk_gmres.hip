@@ -25,6 +25,7 @@
 // inner solve of mixed-precision refinement (FP32/BF16 matrix values).  Every
 // dot product, norm and Gram-Schmidt combination is formed in FP64 from the
 // stored values and rounded once to T; H, g and the rotations are FP64.
+#include "spk_launch.h"
 #include "spk_spmv.h"
 
 #include <cmath>

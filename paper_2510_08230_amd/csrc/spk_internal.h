@@ -1,5 +1,6 @@
-// Internal declarations shared by the host runtime (spk_api.cpp) and the
-// gfx950 kernels (spk_kernels.hip).  Not part of the public ABI.
+// Internal types and constants shared by the host runtime (spk_api.cpp,
+// spk_server.cpp) and the gfx950 kernels.  The launchers that start the
+// kernels are declared in spk_launch.h.  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -82,127 +83,6 @@ struct CsrDev {
 enum : unsigned { VFLAG_BAD_FIRST = 1u, VFLAG_DECREASING = 2u, VFLAG_BAD_LAST = 4u, VFLAG_BAD_COLUMN = 8u,
                   VFLAG_UNSORTED = 16u };
 
-// ---- launchers (spk_kernels.hip) -------------------------------------------------
-hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
-hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
-// COO (idx_t 0 = int32, 1 = int64): flags gets VFLAG_BAD_FIRST for a row
-// index out of range, VFLAG_BAD_COLUMN, VFLAG_UNSORTED for a decreasing row.
-hipError_t launch_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const void *row, const void *col,
-                               int idx_t, unsigned *flags, int max_grid, hipStream_t s);
-// Row pointer (n_rows + 1 entries of ptr_t) of a valid row-sorted COO matrix.
-hipError_t launch_coo_rowptr(int64_t n_rows, int64_t nnz, const void *row, int idx_t, void *rp, int ptr_t,
-                             hipStream_t s);
-
-// y = A x; x/y are double for F64 values, float otherwise.
-hipError_t launch_spmv(const CsrDev &A, const SpmvTune &t, const void *x, void *y, hipStream_t s);
-
-// CG (FP64).  partials: SITE_COUNT * kSiteWidth * kMaxGrid doubles.
-// Iteration j of a chunk = spmv_pq (q = A p, p.q partials), update(j)
-// (alpha, r -= alpha q, r.r partials), pupdate(j) (x += alpha p, stop test,
-// beta, p = r + beta p); a chunk of c iterations ends with chunk_end(c).
-hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, double *r,
-                          double *p, SolveState *st, double *partials, double tau, int64_t max_iters,
-                          double *hist, int64_t hist_cap, hipStream_t s);
-hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q,
-                             SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, double *r, const double *q, SolveState *st,
-                            double *partials, hipStream_t s);
-hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st,
-                             double *partials, hipStream_t s);
-hipError_t launch_cg_chunk_end(SolveState *st, int count, hipStream_t s);
-
-// Mixed precision: inner CG on FP32 vectors (A32 values F32, F16 or BF16),
-// refinement steps in FP64 (A values F64, or F32 taken as exact).
-hipError_t launch_cg_spmv_pq32(const CsrDev &A32, const SpmvTune &t, const float *p, float *q, SolveState *st,
-                               double *partials, hipStream_t s);
-hipError_t launch_cg_update32(int64_t n, int grid, int spmv_grid, int j, float *r, const float *q, SolveState *st,
-                              double *partials, hipStream_t s);
-hipError_t launch_cg_pupdate32(int64_t n, int grid, int j, const float *r, float *p, SolveState *st,
-                               double *partials, hipStream_t s);
-// r = b - A x (FP64); r32 = p32 = fl32(r), d32 = 0; inner state set up;
-// out[0] = ||r||, out[1] = ||r32|| (device doubles).
-hipError_t launch_ir_residual(const CsrDev &A, const SpmvTune &t, const double *b, const double *x, float *r32,
-                              float *p32, float *d32, SolveState *in, double *partials, double tau_in,
-                              int64_t max_inner, double *out, hipStream_t s);
-hipError_t launch_ir_correct(int64_t n, int grid, double *x, const float *d, hipStream_t s);
-// Round FP64 values to FP32 (bf16 = 0) or BF16 (bf16 = 1, round to nearest even).
-// to: spk_dtype code 1 (F32), 2 (F16) or 3 (BF16); each value rounded once, to nearest even.
-hipError_t launch_round_values(int64_t nnz, const double *src, void *dst, int to, int grid, hipStream_t s);
-// Sets x = 0 when b == 0, then (optionally) recomputes ||b - A x|| into the state.
-hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *b, double *x,
-                              SolveState *st, double *partials, int true_residual, hipStream_t s);
-
-hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s);
-
-// CGS (FP64; spk_krylov.hip).  Iteration j of a chunk = dir(j), spmv_v,
-// update(j), spmv_r; a chunk of c iterations ends with check(c).  The initial
-// residual is launch_cg_init with the shadow residual rt in place of p.
-hipError_t launch_cgs_dir(int64_t n, int grid, int spmv_grid, int j, const double *r, double *u, double *p,
-                          const double *q, SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cgs_spmv_v(const CsrDev &A, const SpmvTune &t, const double *p, double *v, const double *rt,
-                             SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cgs_update(int64_t n, int grid, int spmv_grid, int j, const double *u, const double *v, double *q,
-                             double *uh, SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cgs_spmv_r(const CsrDev &A, const SpmvTune &t, const double *uh, double *r, const double *rt,
-                             SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_cgs_check(SolveState *st, double *partials, int spmv_grid, int count, hipStream_t s);
-
-// Restarted GMRES(m) (spk_gmres.hip).  V holds m + 1 basis vectors, column t
-// at V + t * gm_ld(n) elements (16-byte aligned for the packed passes); w is
-// one more vector (16-byte aligned), gpart (kMaxKrylov + 1) * kMaxGrid
-// doubles.  A solve is begin, then per cycle: cycle_start (r = b - A x
-// into v_0, beta, stop test), for j = 0..m-1 step_spmv(j) and step_rest(j),
-// then cycle_end (R y = g, x += V y); the host polls after each cycle.
-constexpr int64_t gm_ld(int64_t n) { return (n + 63) / 64 * 64; }
-hipError_t launch_gm_begin(SolveState *st, GmresState *gs, void *x, double *hist, int64_t hist_cap,
-                           int64_t max_iters, hipStream_t s);
-// fp32: FP32 basis, w and x (A's values F32, BF16 or F16), else FP64 (F64 values).
-hipError_t launch_gm_cycle_start(const CsrDev &A, const SpmvTune &t, const void *b, const void *x, void *V,
-                                 SolveState *st, GmresState *gs, double *partials, double tau, int m, bool fp32,
-                                 hipStream_t s);
-// The same when x = 0 (no product: r = b); grid workgroups of kBlock.
-hipError_t launch_gm_cycle_start_zero(int64_t n, int grid, const void *b, void *V, SolveState *st, GmresState *gs,
-                                      double *partials, double tau, int m, bool fp32, hipStream_t s);
-hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const void *V, void *w, int j,
-                               const SolveState *st, const GmresState *gs, bool fp32, hipStream_t s);
-hipError_t launch_gm_step_rest(int64_t n, int grid, void *V, void *w, int j, int m, SolveState *st, GmresState *gs,
-                               double *gpart, bool fp32, hipStream_t s);
-hipError_t launch_gm_cycle_end(int64_t n, int grid, int m, const void *V, SolveState *st, GmresState *gs, bool fp32,
-                               hipStream_t s);
-
-// Jacobi-preconditioned CG (FP64; spk_krylov.hip).  diag_inv runs once per
-// plan (flag: one zeroed unsigned, set when a diagonal entry is zero or not
-// finite).  Iteration j = launch_cg_spmv_pq, pcg_update(j), pcg_pupdate(j);
-// chunks end with launch_cg_chunk_end.
-hipError_t launch_diag_inv(const CsrDev &A, double *dinv, unsigned *flag, hipStream_t s);
-// Right preconditioning of CGS / GMRES by M = diag(A): out = A M^{-1}
-// values (F64, nnz), and x <- M x (to_u = 1) or x <- M^{-1} x (to_u = 0).
-hipError_t launch_scale_cols(const CsrDev &A, const double *dinv, double *out, hipStream_t s);
-hipError_t launch_jacobi_vec(int64_t n, double *x, const double *dinv, int to_u, hipStream_t s);
-hipError_t launch_pcg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, const double *dinv,
-                           const unsigned *bad_diag, double *r, double *p, SolveState *st, double *partials,
-                           double tau, int64_t max_iters, double *hist, int64_t hist_cap, hipStream_t s);
-hipError_t launch_pcg_update(int64_t n, int grid, int spmv_grid, int j, double *r, const double *q,
-                             const double *dinv, SolveState *st, double *partials, hipStream_t s);
-hipError_t launch_pcg_pupdate(int64_t n, int grid, int j, const double *r, const double *dinv, double *p,
-                              SolveState *st, double *partials, hipStream_t s);
-
-// Whole FP64 CG solve in one cooperative launch (grid must be co-resident:
-// grid <= persistent_blocks_per_cu * CUs).  partials: at least 5 * kMaxGrid
-// doubles.  bar: 3 unsigned, [0] and [2] zero at launch.  Afterwards
-// bar[2] != 0 means a barrier waited longer than spin_ticks (wall clock).
-hipError_t launch_cg_persistent(const CsrDev &A, int grid, int remap, const double *b, double *x, double *r, double *p,
-                                double *q, SolveState *st, double *partials, unsigned *bar, uint64_t spin_ticks,
-                                double tau, int64_t max_iters, double *hist, int64_t hist_cap, int true_residual,
-                                hipStream_t s);
-int persistent_blocks_per_cu(const CsrDev &A);
-
-// Workgroups of the SpMV kernel resident per CU for this tune/type (occupancy API).
-int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t);
-
-// HIP device of a context (spk_api.cpp).
-int ctx_device(const struct ::spk_ctx_s *ctx);
-
 }  // namespace spk
 
 // ==== batched serving ==========================================================
@@ -260,11 +140,5 @@ struct BatchDev {
     SlotStatus *status;
     int tile_grid, slot_grid;
 };
-
-// One tick: six launches advancing every live slot by one step of its phase.
-hipError_t launch_batch_tick(const BatchDev &B, hipStream_t s);
-// FP64 -> FP32 values of a newly admitted request.
-hipError_t launch_round_f32(int64_t nnz, const double *src, float *dst, int grid, hipStream_t s);
-int batch_tile_blocks_per_cu();
 
 }  // namespace spk

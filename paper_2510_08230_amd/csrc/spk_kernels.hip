@@ -25,6 +25,7 @@
 // iteration (chunk base + index within the chunk), so no launch reads a
 // location that it writes.  Kernels return at once when the stop flag is
 // set, so iterations enqueued past convergence cost only empty launches.
+#include "spk_launch.h"
 #include "spk_spmv.h"
 
 #include <cmath>

@@ -23,6 +23,7 @@
 //   update(k) : alpha = rho_k / p.q; r -= alpha q; partials of r.r and r.z
 //   pupdate(k): x += alpha p; stop test on ||r||; rho_{k+1} = r.z;
 //               p = z + beta p
+#include "spk_launch.h"
 #include "spk_spmv.h"
 
 #include <cmath>

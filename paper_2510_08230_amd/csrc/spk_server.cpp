@@ -10,6 +10,7 @@
 // on the device with the requests already in flight.
 #include "spk.h"
 #include "spk_internal.h"
+#include "spk_launch.h"
 #include "spk_pool.h"
 
 #include <algorithm>
