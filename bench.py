@@ -96,10 +96,11 @@ def host_info():
     return info
 
 
-def measured_traffic(args, N):
+def measured_traffic(args, N, tiling=None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-kernel scaled), or None when
-    that summary is for other kernel sources or another workload."""
+    that summary is for other kernel sources, another workload or another
+    launch shape (tiling: this run's spk_plan_info)."""
     if (args.precision != "fp64" or N != 215 or args.seed != 1 or args.solver != "cg" or args.precond != "none"
             or args.pattern != "stencil7" or args.delta != 1.0):
         return None
@@ -111,6 +112,9 @@ def measured_traffic(args, N):
         d = json.load(f)
     if d.get("kernel_digest") != profsum.kernel_digest():
         return None
+    if tiling is not None and d.get("tiling") is not None:
+        if any(d["tiling"][k] != tiling.get(k) for k in profsum.TILING_KEYS):
+            return None
     return d["traffic_bytes"]
 
 
@@ -212,7 +216,7 @@ def main():
     avg_ms = kms / klaunch if klaunch else None
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     last = logs[-1]
-    traffic = measured_traffic(args, N)
+    traffic = measured_traffic(args, N, info)
     jname = "_jacobi" if args.precond == "jacobi" else ""
     dname = "" if args.delta == 1.0 else "_delta%g" % args.delta
     mname = ("randsym_n%d" % n) if args.pattern == "randsym" else ("stencil7ns_N%d" if (cgs or gm) else

@@ -228,15 +228,19 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
     std::vector<SpmvTune> cands;
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
     if (stream_ok(A) && mean <= 64.0) {
-        // tile-to-XCD maps (round-robin, contiguous eighths, XCD-blocked runs of
-        // k tiles) x matrix loads cached or non-temporal x the occupancy
-        // calculator's workgroups per CU or one more (its figure can be low)
-        for (int remap : {0, 1, 64, 256})
-            for (int nt : {0, 1}) {
+        // tile-to-XCD maps (XCD-blocked runs of k tiles, contiguous eighths,
+        // round-robin) x matrix loads cached or non-temporal x the occupancy
+        // calculator's workgroups per CU or one more (its figure can be low).
+        // Ordered by prior preference: XCD-blocked tile orders (at equal time
+        // they move fewer bytes: stencil7 N=215, 1.20 GB per product against
+        // 1.36 GB round-robin), non-temporal matrix loads, one workgroup per
+        // CU above the calculator's figure (all measured best in the CG loop).
+        for (int remap : {64, 256, 1, 0})
+            for (int nt : {1, 0}) {
                 const SpmvTune t = make_tune(ctx, A, 0, 0, remap, nt, 1, 0);
-                cands.push_back(t);
                 const SpmvTune t1 = make_tune(ctx, A, 0, 0, remap, nt, 1, t.bpc + 1);
                 if (t1.grid != t.grid) cands.push_back(t1);
+                cands.push_back(t);
             }
     }
     for (int l2 = 0; l2 <= 6; ++l2) {
@@ -263,7 +267,10 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
         float ms = 0.f;
         SPK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         const double per = ms / reps;
-        if (per < best.ms) best = TuneResult{t, per};
+        // a later candidate must be 3% faster to replace the best: near-ties
+        // (within timing noise, which a profiler attached to the process
+        // widens) resolve to the earlier candidate, so runs choose alike
+        if (per < 0.97 * best.ms) best = TuneResult{t, per};
     }
     ctx->tune_cache[key] = best;
     *out = best;

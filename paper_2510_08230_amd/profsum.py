@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
   python -m paper_2510_08230_amd.profsum stats  KERNEL_STATS_CSV [--trace KERNEL_TRACE_CSV] --cmd "..."
-  python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B [--last N] --cmd "..."
+  python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B [--last N]
+      [--logs FETCH_LOG WRITE_LOG] --cmd "..."
 
 ``stats`` renders the per-kernel duration table.  ``traffic`` reports the
 median FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dispatches of one
@@ -114,6 +115,18 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, last: 
             "traffic_bytes": kf * 1024.0 * scale_f + kw * 1024.0 * scale_w, "kernel_digest": kernel_digest()}
 
 
+TILING_KEYS = ("spmv_kernel", "lanes", "grid", "xcd_remap")
+
+
+def bench_tiling(log_path: str) -> dict:
+    """The SpMV launch shape a benchmark run reported (its JSON line)."""
+    for line in reversed(open(log_path).read().splitlines()):
+        if line.startswith("{"):
+            t = json.loads(line)["config"]["spmv_tiling"]
+            return {k: t[k] for k in TILING_KEYS}
+    raise SystemExit("no benchmark JSON line in %s" % log_path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -128,6 +141,8 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--last", type=int, default=20, help="use the kernel's last N working dispatches")
     t.add_argument("--cmd", required=True)
+    t.add_argument("--logs", nargs=2, metavar=("FETCH_LOG", "WRITE_LOG"),
+                   help="the two runs' benchmark output: their SpMV tiling (which must agree) is recorded")
     a = ap.parse_args()
     if a.what == "stats":
         print(stats_md(a.csv, a.cmd), end="")
@@ -135,6 +150,11 @@ def main():
             print(working_launches_md(a.trace), end="")
     else:
         d = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.last)
+        if a.logs:
+            tilings = [bench_tiling(p) for p in a.logs]
+            if tilings[0] != tilings[1]:
+                raise SystemExit("the two runs chose different SpMV tilings: %s vs %s" % tuple(tilings))
+            d["tiling"] = tilings[0]
         d["command"] = a.cmd
         print(json.dumps(d, indent=1))
 
