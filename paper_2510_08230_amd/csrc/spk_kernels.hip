@@ -444,7 +444,9 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned &gen, uint64_t
                 __hip_atomic_store(&bar[1], g0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                // relaxed polling (an acquiring load would invalidate the caches on every
+                // poll); one acquire fence once the generation has moved
+                while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
                     if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                         ok = 0;
                         break;
@@ -458,6 +460,7 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned &gen, uint64_t
                 }
             }
             gen = g0 + 1;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         s_ok = ok;
     }
