@@ -132,3 +132,36 @@ def test_c3_full_size(spk, ctx):
     xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=1000)
     print("mixed: %d inner its, %d outer, %.1f ms" % (log.iterations, log.outer_iterations, log.elapsed_ms))
     assert log.stop_reason == spk.STOP_CONVERGED and rel(x, xo) <= 1e-10
+
+
+def rne_bf16(v):
+    """FP64 -> nearest bfloat16 (ties to even), as FP64 (normal range only)."""
+    m, e = np.frexp(v)
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)
+
+
+LOW = {"fp32": lambda v: v.astype(np.float32).astype(np.float64),
+       "bf16": rne_bf16,
+       "fp16": lambda v: v.astype(np.float16).astype(np.float64)}
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("prec", sorted(PRECS))
+@pytest.mark.parametrize("K", [5, 20])
+def test_inner_solve_iterates(spk, ctx, name, prec, K):
+    """One refinement step from x = 0 whose inner CG runs exactly K iterations:
+    x = d, the FP32 CG iterate for A_low d = fl32(b), where A_low holds the
+    values rounded once to nearest even (FP32, BF16 or FP16).  Compared with
+    the oracle's FP64 CG on the same rounded matrix and right-hand side.
+    Tolerance 2e-5: FP32 vector storage perturbs each step by u32 = 6e-8,
+    compounded over K <= 20 steps and amplified by kappa_G <= 13 (about
+    1.6e-5).  A wrong rounding of the values (truncation instead of nearest)
+    moves the iterate by ~6e-4 for FP16 (stencil7 N=46, K = 20)."""
+    A = MATS[name]()
+    b = inputs.rhs(A.n_rows, 4)
+    x, log = solve_mixed(spk, ctx, A, b, getattr(spk, PRECS[prec]), inner=1e-30, max_outer=1, max_iters=K)
+    assert log.iterations == K and log.outer_iterations == 1 and log.stop_reason == spk.STOP_MAX_ITERS
+    A_low = inputs.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, LOW[prec](A.val))
+    b32 = b.astype(np.float32).astype(np.float64)
+    xo, _, _ = oracle.cg(A_low, b32, tau=0.0, max_iters=K)
+    assert rel(x, xo) <= 2e-5
