@@ -72,8 +72,9 @@ def parse():
     ap.add_argument("--spmv", choices=["csr", "coo"], default=None,
                     help="standalone SpMV mode y = A x (stencil7 N, seed): GFLOP/s at 2 nnz per product")
     ap.add_argument("--values", choices=["fp32", "fp64"], default="fp32", help="SpMV mode value/vector type")
-    ap.add_argument("--exec", choices=["auto", "host", "graph"], default="host",
-                    help="iteration driver: host loop, captured graphs, or the plan's choice")
+    ap.add_argument("--exec", choices=["auto", "host", "graph", "persistent"], default="host",
+                    help="iteration driver: host loop, captured graphs, one cooperative launch (FP64 CG; "
+                         "other solves fall back to graphs), or the plan's choice")
     return ap.parse_args()
 
 
@@ -169,7 +170,8 @@ def main():
     cfg = spk.spk_solver_cfg_default()
     cfg.reduction_factor = args.tau
     cfg.max_iters = 1000
-    cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
+    cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH,
+                     "persistent": spk.EXEC_PERSISTENT}[args.exec]
     cfg.precision = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32,
                      "mixed_bf16": spk.PREC_MIXED_BF16, "mixed_fp16": spk.PREC_MIXED_FP16}[args.precision]
     cfg.inner_reduction = args.inner
@@ -457,7 +459,8 @@ def large(args):
     cfg.reduction_factor = 1e-12
     cfg.inner_reduction = args.inner
     cfg.max_iters = 10000
-    cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH}[args.exec]
+    cfg.exec_mode = {"auto": spk.EXEC_AUTO, "host": spk.EXEC_HOST_LOOP, "graph": spk.EXEC_GRAPH,
+                     "persistent": spk.EXEC_PERSISTENT}[args.exec]
 
     def step(profile):
         pl = spk.spk_plan_solve(ctx, M, cfg)
