@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, int64_t ld, cons
     constexpr bool stream = NV <= 8;
     constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
     __shared__ double h[NV];
-    if (threadIdx.x < NV) h[threadIdx.x] = threadIdx.x <= j ? gs->h1[threadIdx.x] : 0.0;
+    if (threadIdx.x < NV) h[threadIdx.x] = static_cast<int>(threadIdx.x) <= j ? gs->h1[threadIdx.x] : 0.0;
     __syncthreads();
     double acc[NV];
 #pragma unroll
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, int64_t ld, cons
     constexpr bool stream = NV <= 16;
     constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
     __shared__ double h[NV];
-    if (threadIdx.x < NV) h[threadIdx.x] = threadIdx.x <= j ? gs->h2[threadIdx.x] : 0.0;
+    if (threadIdx.x < NV) h[threadIdx.x] = static_cast<int>(threadIdx.x) <= j ? gs->h2[threadIdx.x] : 0.0;
     __syncthreads();
     double nrm = 0.0;
     const int64_t np = (n + K - 1) / K;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_update_x(int64_t n, int64_t ld, c
     if (st->stop == STOP_NON_FINITE || used == 0) return;
     constexpr int K = pack_len<T, NV, 8>();
     __shared__ double y[NV];
-    if (threadIdx.x < NV) y[threadIdx.x] = threadIdx.x < used ? gs->y[threadIdx.x] : 0.0;
+    if (threadIdx.x < NV) y[threadIdx.x] = static_cast<int>(threadIdx.x) < used ? gs->y[threadIdx.x] : 0.0;
     __syncthreads();
     T *__restrict__ x = static_cast<T *>(st->x);
     const bool aligned = (reinterpret_cast<uintptr_t>(x) % (K * sizeof(T))) == 0;
