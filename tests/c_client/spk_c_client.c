@@ -10,6 +10,10 @@
  * (the vector of the product); the client writes y.f64, sol.f64 and prints
  * one line "verdict iterations stop_reason rhs_norm true_resnorm".
  * SOLVER: 0 CG, 1 CGS, 2 GMRES; PRECOND: 0 none, 1 Jacobi.
+ * SOLVER 9: the serving API instead of a plan: three requests on the same
+ * matrix with right-hand sides b, b/2 and -b (mixed FP32 with FP64
+ * refinement) submitted together, drained, and their solutions written to
+ * sol.f64, sol_half.f64 and sol_neg.f64; the line printed is request 0's.
  */
 #include <hip/hip_runtime_api.h>
 #include <stdio.h>
@@ -100,15 +104,59 @@ int main(int argc, char **argv) {
 
     spk_solver_cfg cfg;
     spk_solver_cfg_default(&cfg);
-    cfg.solver = atoi(argv[2]);
+    const int solver = atoi(argv[2]);
     cfg.precond = atoi(argv[3]);
     cfg.reduction_factor = atof(argv[4]);
     cfg.max_iters = atoll(argv[5]);
-    spk_plan pl = NULL;
-    CHECK(spk_plan_solve(ctx, &A, &cfg, &pl));
     spk_log log;
-    CHECK(spk_execute_solve(pl, d_b, d_x, &log));
-    CHECK(spk_free(pl));
+    if (solver == 9) {
+        /* serving: b, b/2 and -b (exact scalings) in one batch */
+        double *bh = malloc(sizeof(double) * (size_t)n), *bn = malloc(sizeof(double) * (size_t)n);
+        for (long long i = 0; i < n; ++i) {
+            bh[i] = 0.5 * b[i];
+            bn[i] = -b[i];
+        }
+        double *d_bh = to_device(bh, sizeof(double) * (size_t)n), *d_bn = to_device(bn, sizeof(double) * (size_t)n);
+        double *d_xh = NULL, *d_xn = NULL;
+        if (hipMalloc((void **)&d_xh, sizeof(double) * (size_t)n) != hipSuccess ||
+            hipMalloc((void **)&d_xn, sizeof(double) * (size_t)n) != hipSuccess ||
+            hipMemset(d_xh, 0, sizeof(double) * (size_t)n) != hipSuccess ||
+            hipMemset(d_xn, 0, sizeof(double) * (size_t)n) != hipSuccess)
+            return 3;
+        cfg.precision = SPK_PREC_MIXED_FP32;
+        spk_server srv = NULL;
+        CHECK(spk_server_create(ctx, (size_t)1 << 30, 4, &cfg, &srv));
+        uint64_t t[3];
+        CHECK(spk_server_submit(srv, &A, d_b, d_x, &t[0]));
+        CHECK(spk_server_submit(srv, &A, d_bh, d_xh, &t[1]));
+        CHECK(spk_server_submit(srv, &A, d_bn, d_xn, &t[2]));
+        CHECK(spk_server_drain(srv));
+        for (int k = 2; k >= 0; --k) {   /* request 0 last, so log ends as its log */
+            int32_t done = 0;
+            int64_t lat = 0;
+            CHECK(spk_server_poll(srv, t[k], &done, &log, &lat));
+            if (!done) { fprintf(stderr, "request %d not done after drain\n", k); return 5; }
+        }
+        CHECK(spk_server_destroy(srv));
+        double *h = malloc(sizeof(double) * (size_t)n);
+        if (hipMemcpy(h, d_xh, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return 3;
+        write_file(dir, "sol_half.f64", h, sizeof(double) * (size_t)n);
+        if (hipMemcpy(h, d_xn, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return 3;
+        write_file(dir, "sol_neg.f64", h, sizeof(double) * (size_t)n);
+        hipFree(d_bh);
+        hipFree(d_bn);
+        hipFree(d_xh);
+        hipFree(d_xn);
+        free(h);
+        free(bh);
+        free(bn);
+    } else {
+        cfg.solver = solver;
+        spk_plan pl = NULL;
+        CHECK(spk_plan_solve(ctx, &A, &cfg, &pl));
+        CHECK(spk_execute_solve(pl, d_b, d_x, &log));
+        CHECK(spk_free(pl));
+    }
     CHECK(spk_finalize(ctx));
 
     double *y = malloc(sizeof(double) * (size_t)n), *sol = malloc(sizeof(double) * (size_t)n);

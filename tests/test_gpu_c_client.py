@@ -63,3 +63,33 @@ def test_c_client_matches_oracle(tmp_path, name):
     assert np.linalg.norm(x - xo) <= 1e-12 * np.linalg.norm(xo)
     assert abs(float(bnorm) - ro.rhs_norm) <= 1e-14 * ro.rhs_norm
     assert float(true_res) <= 10 * 1e-13 * float(bnorm)
+
+
+def test_c_client_serving(tmp_path):
+    """Three requests through the serving API from plain C: b, b/2 and -b on one
+    matrix.  Scaling by a power of two and negation are exact in every operation,
+    so the three solutions are exact scalings of one another (bitwise); request 0
+    meets the FP64 criterion and is within 1e-10 of the oracle's FP64 CG solution
+    (the mixed-precision tolerance)."""
+    assert os.path.exists(EXE), "the C client is not built (run __graft_entry__.build())"
+    A = inputs.stencil7(24, 3)
+    n = A.n_rows
+    b = inputs.rhs(n, 7)
+    (tmp_path / "meta.txt").write_text("%d %d\n" % (n, A.nnz))
+    A.row_ptr.astype(np.int32).tofile(tmp_path / "row_ptr.i32")
+    A.col.astype(np.int32).tofile(tmp_path / "col.i32")
+    A.val.astype(np.float64).tofile(tmp_path / "val.f64")
+    b.tofile(tmp_path / "b.f64")
+    inputs.vec(n, 7, 5).tofile(tmp_path / "x.f64")
+    out = subprocess.run([EXE, str(tmp_path), "9", "0", "1e-12", "10000"], capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    verdict, iters, stop, bnorm, true_res = out.stdout.split()
+    assert int(verdict) == 0 and int(stop) == 1 and int(iters) > 0
+    x = np.fromfile(tmp_path / "sol.f64", np.float64)
+    xh = np.fromfile(tmp_path / "sol_half.f64", np.float64)
+    xn = np.fromfile(tmp_path / "sol_neg.f64", np.float64)
+    assert np.array_equal(xh, 0.5 * x) and np.array_equal(xn, -x)
+    assert np.linalg.norm(oracle.residual(A, b, x)) <= 1e-12 * np.linalg.norm(b) * 1.01
+    xo, _, _ = oracle.cg(A, b, tau=1e-14)
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
