@@ -313,3 +313,40 @@ def test_pcg_full_size_residual():
         assert rel(x2, xo) <= 1e-12
     finally:
         spk.spk_finalize(ctx)
+
+
+# Scaling b by a power of two or negating it is exact in every operation of
+# every solver (products, sums, square roots of the scaled squares, the
+# relative stop test), so the solutions scale exactly, bit for bit.
+SCALE_CASES = {"cg": (lambda: inputs.stencil7(20, 2), "SOLVER_CG", "PRECOND_NONE", "PREC_FP64"),
+               "pcg": (lambda: inputs.stencil7(20, 2), "SOLVER_CG", "PRECOND_JACOBI", "PREC_FP64"),
+               "cgs": (lambda: inputs.stencil7_ns(20, 3), "SOLVER_CGS", "PRECOND_NONE", "PREC_FP64"),
+               "cgs_jacobi": (lambda: inputs.stencil7_ns(20, 3), "SOLVER_CGS", "PRECOND_JACOBI", "PREC_FP64"),
+               "gmres": (lambda: inputs.stencil7_ns(20, 3), "SOLVER_GMRES", "PRECOND_NONE", "PREC_FP64"),
+               "gmres_jacobi": (lambda: inputs.stencil7_ns(20, 3), "SOLVER_GMRES", "PRECOND_JACOBI", "PREC_FP64"),
+               "mixed_cg": (lambda: inputs.stencil7(20, 2), "SOLVER_CG", "PRECOND_NONE", "PREC_MIXED_FP32"),
+               "gmres_ir_fp16": (lambda: inputs.stencil7_ns(20, 3), "SOLVER_GMRES", "PRECOND_NONE",
+                                 "PREC_MIXED_FP16")}
+
+
+@pytest.mark.parametrize("name", sorted(SCALE_CASES))
+def test_solutions_scale_exactly(spk, ctx, name):
+    make, solver, precond, prec = SCALE_CASES[name]
+    A = make()
+    b = inputs.rhs(A.n_rows, 9)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = getattr(spk, solver)
+    cfg.precond = getattr(spk, precond)
+    cfg.precision = getattr(spk, prec)
+    cfg.reduction_factor = 1e-12
+    cfg.max_iters = 5000
+    pl = spk.spk_plan_solve(ctx, dev_csr(spk, A), cfg)
+    sols, logs = [], []
+    for s in (1.0, 0.5, -4.0):
+        x = to_dev(np.zeros(A.n_rows))
+        logs.append(spk.spk_execute_solve(pl, to_dev(s * b), x))
+        sols.append(x.cpu().numpy())
+    spk.spk_free(pl)
+    assert logs[0].stop_reason == spk.STOP_CONVERGED
+    assert all(lg.iterations == logs[0].iterations for lg in logs)
+    assert np.array_equal(sols[1], 0.5 * sols[0]) and np.array_equal(sols[2], -4.0 * sols[0])
