@@ -122,8 +122,7 @@ def measured_traffic(args, N, tiling=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: multi-GPU runs are not part of this build "
-              "(a run on several GPUs is not supported).", file=sys.stderr)
+        print("bench.py measures one GPU only: a run on several GPUs is not supported.", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve(args)

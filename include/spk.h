@@ -38,7 +38,7 @@ extern "C" {
 typedef enum {
     SPK_OK = 0,
     SPK_ERR_INVALID_ARG = 1,   /* null pointer, bad size, malformed CSR, dtype mismatch */
-    SPK_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+    SPK_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
     SPK_ERR_OUT_OF_MEMORY = 3, /* device or pinned-host allocation failed */
     SPK_ERR_BUDGET = 4,        /* request exceeds a configured memory budget */
     SPK_ERR_DEVICE = 5,        /* a HIP runtime call failed */
@@ -274,7 +274,7 @@ spk_status spk_stream_copy(spk_ctx ctx, const void *src, void *dst, size_t bytes
  * batches.  A request's result is bitwise independent of which other
  * requests share the batch.  Small systems being overhead-bound is the
  * paper's observation (Sections 6.1-6.2); batching many of them into one
- * launch per step is how this build serves them. */
+ * launch per step is how the library serves them. */
 typedef struct spk_server_s *spk_server;
 
 typedef struct {
