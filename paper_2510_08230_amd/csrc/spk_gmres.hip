@@ -2,29 +2,37 @@
 // examples (Listings 1-2, Krylov dimension 30) and of its solver benchmarks
 // (Section 6.2).
 //
-// Arnoldi orthogonalisation is classical Gram-Schmidt applied twice (CGS2):
-// on a GPU each pass is one streaming kernel over the basis (a multi-dot
-// and/or a multi-axpy, all HBM-bound), where modified Gram-Schmidt would
-// need one dependent pass and one reduction per basis vector.  A step j
-// (J = j + 1 basis vectors) is:
-//   SpMV      : w = A v_j          (v_j stored unnormalised; the row sums are
-//                                    scaled by 1 / ||v_j|| in the epilogue)
-//   dots      : v_j *= 1 / ||v_j|| (written back), partials of h1 = V^T w
-//   reduce    : h1
-//   pass2     : w -= V h1, partials of h2 = V^T w
-//   reduce    : h2
-//   pass3     : v_{j+1} = w - V h2 (unnormalised), partial of ||v_{j+1}||^2
-//   givens    : column j of H = h1 + h2 and ||v_{j+1}||, earlier rotations,
-//               a new rotation, g, the residual estimate |g_{j+1}|, stop test
-// A cycle starts with the residual r = b - A x written into v_0 and ends
-// with the triangular solve R y = g and x += V y over the columns built.
-// Kernels return at once when the solve has stopped or the cycle is done,
-// so the host can enqueue a whole cycle and poll once.
+// Arnoldi orthogonalisation is classical Gram-Schmidt applied twice, with
+// the second projection delayed by one pass: each pass is one streaming
+// kernel over the basis (multi-dot and multi-axpy, HBM-bound), and a step
+// reads the basis twice instead of three times.  At step j the basis holds
+// the finished vectors q_0..q_{j-1} (Q_j) and, in slot j, the candidate
+// u_j = Q_j a + nu q_j: once orthogonalised, with a (its components along
+// Q_j) and nu known but the second projection not yet subtracted.
+//   SpMV   : w = A u_j
+//   passA  : partials of b_t = q_t . w (t < j) and of u_j . w
+//   reduce : b
+//   coef   : with Qb = [Q_j, q_j] and A Q_j = Qb Hu (earlier columns),
+//            A q_j = (w - Qb e) / nu, e = Hu a; its projections
+//            h = Qb^T A q_j = (Qb^T w - e) / nu, where q_j . w =
+//            (u_j . w - a . b) / nu; u_{j+1} = w / nu - Qb d, d = e / nu + h
+//   passB  : q_j = (u_j - Q_j a) / nu written over u_j; u_{j+1} into slot
+//            j+1; partials of a' = Qb^T u_{j+1} and of ||u_{j+1}||^2
+//   reduce : a'
+//   final  : nu' = sqrt(||u_{j+1}||^2 - ||a'||^2); column j of Hu is h + a'
+//            with nu' below it (A q_j = Qb (h + a') + nu' q_{j+1}); earlier
+//            rotations, a new rotation, g, the residual estimate |g_{j+1}|,
+//            the stop test
+// A cycle starts with the residual r = b - A x written into slot 0 as the
+// candidate u_0 (a empty, nu = ||r||) and ends with the triangular solve
+// R y = g and x += Q y over the columns built.  Kernels return at once when
+// the solve has stopped or the cycle is done, so the host can enqueue a
+// whole cycle and poll once.
 //
 // The basis, w and x are of type T: double for the FP64 solve, float for the
-// inner solve of mixed-precision refinement (FP32/BF16 matrix values).  Every
-// dot product, norm and Gram-Schmidt combination is formed in FP64 from the
-// stored values and rounded once to T; H, g and the rotations are FP64.
+// inner solve of mixed-precision refinement (FP32/BF16/FP16 matrix values).
+// Every dot product, norm and Gram-Schmidt combination is formed in FP64 from
+// the stored values and rounded once to T; Hu, H, g and the rotations are FP64.
 #include "spk_launch.h"
 #include "spk_spmv.h"
 
@@ -63,7 +71,7 @@ struct EpiGmRes {
     }
 };
 
-// w = (A v_j) / ||v_j||.
+// w = A u_j.
 template <typename T>
 struct EpiGmW {
     T *w;
@@ -71,7 +79,7 @@ struct EpiGmW {
     const GmresState *gs;
     __device__ bool skip() const { return gm_idle(st, gs); }
     template <class C>
-    __device__ void row(int64_t i, C s) { w[i] = static_cast<T>(static_cast<double>(s) * gs->inv_scale); }
+    __device__ void row(int64_t i, C s) { w[i] = static_cast<T>(s); }
     __device__ void finish() {}
 };
 
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, Gmres
     }
     gs->used = 0;
     gs->cycle_done = stop != STOP_RUNNING;
-    gs->inv_scale = 1.0 / beta;
+    gs->nu = beta;   // candidate u_0 = r = beta q_0
     gs->g[0] = beta;
     for (int i = 1; i <= m; ++i) gs->g[i] = 0.0;
     if (stop != STOP_RUNNING) st->stop = stop;
@@ -153,18 +161,18 @@ __global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, Gmres
 // The vector passes move packs of K consecutive elements per lane and load
 // (per-element 4-byte loads left the FP32 passes bound by load issue at
 // about 2.2 TB/s).  Two shapes, chosen by the basis bucket NV:
-//  * streaming (dots and pass2 up to NV = 8, pass3 up to 16): 16-byte packs,
-//    each vector's pack combined as it arrives; low register use, high
-//    occupancy.
+//  * streaming (passA and passB up to NV = 8): 16-byte packs, each vector's
+//    pack combined as it arrives; low register use, high occupancy.
 //  * load-all-first (larger NV, and update_x): a thread issues the loads of
 //    every basis vector it needs before combining them, so one pack of all J
 //    vectors is in flight at once.  K trades that register footprint against
 //    occupancy: pack_len<T, NV, B>() is the widest pack (16 bytes at most)
 //    with NV * K * B <= 256, B = sizeof(T) up to NV = 16, else 8 (the
 //    compiler holds FP32 values converted to FP64).
-// Measured on stencil7_ns N=215: FP32 pass3 at J = 9..16 104 us streaming,
-// 147 us loading all first; FP32 dots at J <= 8 43 us against 58 us; FP64
-// dots at J = 17..32 400 us loading all first, 580 us streaming.
+// passB keeps every finished vector's pack until u_{j+1} is formed (its dot
+// products need it), so it runs at lower occupancy than passA.  Measured on
+// stencil7_ns N=215 (FP64, J = 17..32): passA 343 us, passB 515 us, where
+// the three passes of the undelayed scheme took 400 + 381 + 383 us.
 // Basis columns sit ld = gm_ld(n) elements apart (16-byte aligned); the last
 // pack of a vector is loaded element by element when n is not a multiple
 // of K.
@@ -215,17 +223,15 @@ __device__ __forceinline__ void st_pack(T *__restrict__ p, int64_t i0, int64_t n
 template <typename T>
 __device__ __forceinline__ const T *vec(const T *V, int64_t ld, int t) { return V + static_cast<int64_t>(t) * ld; }
 
-// v_j *= 1/||v_j|| (written back); partials of h1_t = w . v_t, t <= j.  The
-// written vector comes in as its own pointer so that the loads of the other
-// basis vectors can be issued ahead of its store.
+// First pass of step j: partials of b_t = q_t . w (t < j) and of u_j . w
+// (t = j; the candidate sits in slot j).
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, int64_t ld, const T *__restrict__ V,
-                                                    T *__restrict__ vj, const T *__restrict__ w, int j,
-                                                    const SolveState *st, const GmresState *gs, double *part) {
+__global__ __launch_bounds__(kBlock) void k_gm_passA(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                     const T *__restrict__ w, int j, const SolveState *st,
+                                                     const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
     constexpr bool stream = NV <= 8;
     constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
-    const double inv = gs->inv_scale;
     double acc[NV];
 #pragma unroll
     for (int t = 0; t < NV; ++t) acc[t] = 0.0;
@@ -233,15 +239,12 @@ __global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, int64_t ld, const
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
         const int64_t i0 = q * K;
-        T wv[K], vv[K];
+        T wv[K];
         ld_pack<T, K>(w, i0, n, wv);
-        ld_pack<T, K>(vj, i0, n, vv);
-#pragma unroll
-        for (int e = 0; e < K; ++e) vv[e] = static_cast<T>(static_cast<double>(vv[e]) * inv);
         if constexpr (stream) {
 #pragma unroll
             for (int t = 0; t < NV; ++t) {
-                if (t < j) {
+                if (t <= j) {
                     T vt[K];
                     ld_pack<T, K>(vec(V, ld, t), i0, n, vt);
 #pragma unroll
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, int64_t ld, const
             T vt[NV][K];
 #pragma unroll
             for (int t = 0; t < NV; ++t) {
-                if (t < j) {
+                if (t <= j) {
                     ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
                 } else {
 #pragma unroll
@@ -262,20 +265,11 @@ __global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t n, int64_t ld, const
             }
 #pragma unroll
             for (int t = 0; t < NV; ++t) {
-                if (t < j) {
+                if (t <= j) {
 #pragma unroll
                     for (int e = 0; e < K; ++e)
                         acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vt[t][e]), acc[t]);
                 }
-            }
-        }
-        st_pack<T, K>(vj, i0, n, vv);
-#pragma unroll
-        for (int t = 0; t < NV; ++t) {
-            if (t == j) {
-#pragma unroll
-                for (int e = 0; e < K; ++e)
-                    acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vv[e]), acc[t]);
             }
         }
     }
@@ -292,138 +286,129 @@ __global__ __launch_bounds__(kBlock) void k_gm_reduce(const double *part, int G,
     if (threadIdx.x == 0) out[t] = tot[0];
 }
 
-// w -= V h1 over t <= j; partials of h2_t = w . v_t.
+// Step coefficients (one thread; J <= 33 terms): h (column j before the
+// delayed correction) and d (u_{j+1} = w / nu - sum d_t q_t, t <= j).
+__global__ void k_gm_coef(const SolveState *st, GmresState *gs, int j) {
+    if (gm_idle(st, gs) || threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double inv = 1.0 / gs->nu;
+    double qwj = gs->b[j];   // u_j . w  ->  q_j . w
+    for (int t = 0; t < j; ++t) qwj = fma(-gs->a[t], gs->b[t], qwj);
+    qwj *= inv;
+    for (int s = 0; s <= j; ++s) {
+        // e_s = sum_{t < j} Hu[s][t] a_t (Hu[s][t] = 0 for s > t + 1)
+        double e = 0.0;
+        for (int t = s > 0 ? s - 1 : 0; t < j; ++t) e = fma(gs->Hu[s * kMaxKrylov + t], gs->a[t], e);
+        const double qw = s < j ? gs->b[s] : qwj;
+        const double h = (qw - e) * inv;
+        gs->h[s] = h;
+        gs->d[s] = fma(e, inv, h);
+    }
+}
+
+// Second pass of step j: q_j = (u_j - Q_j a) / nu over the candidate,
+// u_{j+1} = w / nu - Q_j d - d_j q_j into slot j + 1, partials of
+// a'_t = q_t . u_{j+1} (t <= j, rows 0..NV-1) and of ||u_{j+1}||^2 (row NV).
+// uj (slot j, read and written) and un (slot j + 1) do not overlap the
+// finished vectors read through V.
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_pass2(int64_t n, int64_t ld, const T *__restrict__ V,
-                                                     T *__restrict__ w, int j, const SolveState *st,
+__global__ __launch_bounds__(kBlock) void k_gm_passB(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                     T *__restrict__ uj, T *__restrict__ un,
+                                                     const T *__restrict__ w, int j, const SolveState *st,
                                                      const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
     constexpr bool stream = NV <= 8;
     constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
-    __shared__ double h[NV];
-    if (threadIdx.x < NV) h[threadIdx.x] = static_cast<int>(threadIdx.x) <= j ? gs->h1[threadIdx.x] : 0.0;
+    __shared__ double ca[NV], cd[NV + 1];
+    if (threadIdx.x < NV) ca[threadIdx.x] = static_cast<int>(threadIdx.x) < j ? gs->a[threadIdx.x] : 0.0;
+    if (threadIdx.x <= NV) cd[threadIdx.x] = static_cast<int>(threadIdx.x) <= j ? gs->d[threadIdx.x] : 0.0;
     __syncthreads();
-    double acc[NV];
+    const double inv = 1.0 / gs->nu;
+    const double dj = cd[j];
+    double acc[NV + 1];
 #pragma unroll
-    for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+    for (int t = 0; t <= NV; ++t) acc[t] = 0.0;
     const int64_t np = (n + K - 1) / K;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
         const int64_t i0 = q * K;
-        T wv[K], vt[NV][K];
+        T wv[K], uv[K], vt[NV][K];
         ld_pack<T, K>(w, i0, n, wv);
-        double wd[K];
-#pragma unroll
-        for (int e = 0; e < K; ++e) wd[e] = static_cast<double>(wv[e]);
-        if constexpr (stream) {   // combine each vector as it arrives
-#pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                if (t <= j) {
-                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
-#pragma unroll
-                    for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[t][e]), wd[e]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                if (t <= j) {
-                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < K; ++e) vt[t][e] = T(0);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < NV; ++t)
-#pragma unroll
-                for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[t][e]), wd[e]);
-        }
-#pragma unroll
-        for (int e = 0; e < K; ++e) wv[e] = static_cast<T>(wd[e]);
-        st_pack<T, K>(w, i0, n, wv);
-#pragma unroll
-        for (int t = 0; t < NV; ++t) {
-            if (t <= j) {
-#pragma unroll
-                for (int e = 0; e < K; ++e)
-                    acc[t] = fma(static_cast<double>(wv[e]), static_cast<double>(vt[t][e]), acc[t]);
-            }
-        }
-    }
-    block_partial<NV>(acc, part);
-}
-
-// v_{j+1} = w - V h2 over t <= j (unnormalised); partial of ||v_{j+1}||^2.
-// vn (= v_{j+1}) does not overlap the basis vectors read.
-template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_gm_pass3(int64_t n, int64_t ld, const T *__restrict__ V,
-                                                     T *__restrict__ vn, const T *__restrict__ w, int j,
-                                                     const SolveState *st, const GmresState *gs, double *part) {
-    if (gm_idle(st, gs)) return;
-    constexpr bool stream = NV <= 16;
-    constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
-    __shared__ double h[NV];
-    if (threadIdx.x < NV) h[threadIdx.x] = static_cast<int>(threadIdx.x) <= j ? gs->h2[threadIdx.x] : 0.0;
-    __syncthreads();
-    double nrm = 0.0;
-    const int64_t np = (n + K - 1) / K;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
-        const int64_t i0 = q * K;
-        T wv[K];
-        ld_pack<T, K>(w, i0, n, wv);
-        double wd[K];
-#pragma unroll
-        for (int e = 0; e < K; ++e) wd[e] = static_cast<double>(wv[e]);
-        if constexpr (stream) {
-#pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                if (t <= j) {
-                    T vt[K];
-                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt);
-#pragma unroll
-                    for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[e]), wd[e]);
-                }
-            }
-        } else {
-            T vt[NV][K];
-#pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                if (t <= j) {
-                    ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < K; ++e) vt[t][e] = T(0);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < NV; ++t)
-#pragma unroll
-                for (int e = 0; e < K; ++e) wd[e] = fma(-h[t], static_cast<double>(vt[t][e]), wd[e]);
-        }
+        ld_pack<T, K>(uj, i0, n, uv);
+        double qd[K], nd[K];
 #pragma unroll
         for (int e = 0; e < K; ++e) {
-            wv[e] = static_cast<T>(wd[e]);
-            nrm = fma(static_cast<double>(wv[e]), static_cast<double>(wv[e]), nrm);
+            qd[e] = static_cast<double>(uv[e]);
+            nd[e] = static_cast<double>(wv[e]) * inv;
         }
-        st_pack<T, K>(vn, i0, n, wv);
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+            if (t < j) {
+                ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
+                if constexpr (stream) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e) {
+                        const double v = static_cast<double>(vt[t][e]);
+                        qd[e] = fma(-ca[t], v, qd[e]);
+                        nd[e] = fma(-cd[t], v, nd[e]);
+                    }
+                }
+            }
+        }
+        if constexpr (!stream) {
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t < j) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e) {
+                        const double v = static_cast<double>(vt[t][e]);
+                        qd[e] = fma(-ca[t], v, qd[e]);
+                        nd[e] = fma(-cd[t], v, nd[e]);
+                    }
+                }
+            }
+        }
+        T qv[K], nv[K];
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            qv[e] = static_cast<T>(qd[e] * inv);
+            nv[e] = static_cast<T>(fma(-dj, static_cast<double>(qv[e]), nd[e]));
+        }
+        st_pack<T, K>(uj, i0, n, qv);
+        st_pack<T, K>(un, i0, n, nv);
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            const double u1 = static_cast<double>(nv[e]);
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                if (t < j) acc[t] = fma(static_cast<double>(vt[t][e]), u1, acc[t]);
+                else if (t == j) acc[t] = fma(static_cast<double>(qv[e]), u1, acc[t]);
+            }
+            acc[NV] = fma(u1, u1, acc[NV]);
+        }
     }
-    double a[1] = {nrm};
-    block_partial<1>(a, part);
+    block_partial<NV + 1>(acc, part);
 }
 
-// Column j of the Hessenberg matrix, its rotations, the residual estimate
-// and the stop test (one workgroup; thread 0 does the scalar work).
-__global__ __launch_bounds__(kBlock) void k_gm_givens(SolveState *st, GmresState *gs, const double *part_n, int G,
-                                                      int j, int m) {
+// End of step j (one workgroup; thread 0 does the scalar work): nu' from
+// ||u_{j+1}||^2 (partials row nvrow) and a'; column j of Hu and of the
+// rotated H; earlier rotations, a new rotation, g, the residual estimate and
+// the stop test.
+__global__ __launch_bounds__(kBlock) void k_gm_final(SolveState *st, GmresState *gs, const double *part, int G,
+                                                     int nvrow, int j, int m) {
     if (gm_idle(st, gs)) return;
     double tot[1];
-    sum_partials<1>(part_n, G, tot);
+    sum_partials<1>(part + static_cast<int64_t>(nvrow) * kMaxGrid, G, tot);
     if (threadIdx.x != 0) return;
-    const double hn = sqrt(tot[0]);
+    double s2 = 0.0;
+    for (int t = 0; t <= j; ++t) s2 = fma(gs->a[t], gs->a[t], s2);
+    const double hn = sqrt(fmax(tot[0] - s2, 0.0));
     double *H = gs->H;
-    for (int t = 0; t <= j; ++t) H[t * kMaxKrylov + j] = gs->h1[t] + gs->h2[t];
+    for (int t = 0; t <= j; ++t) {
+        const double c = gs->h[t] + gs->a[t];
+        gs->Hu[t * kMaxKrylov + j] = c;
+        H[t * kMaxKrylov + j] = c;
+    }
+    gs->Hu[(j + 1) * kMaxKrylov + j] = hn;
     for (int t = 0; t < j; ++t) {
         const double a = H[t * kMaxKrylov + j], c = H[(t + 1) * kMaxKrylov + j];
         H[t * kMaxKrylov + j] = gs->cs[t] * a + gs->sn[t] * c;
@@ -452,8 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_gm_givens(SolveState *st, GmresState
     else if (res <= st->thresh) stop = STOP_CONVERGED;
     else if (k >= st->max_iters) stop = STOP_MAX_ITERS;
     gs->used = j + 1;
+    gs->nu = hn;   // the candidate u_{j+1} = Qb a' + nu' q_{j+1}
     if (stop != STOP_RUNNING || hn == 0.0 || j + 1 == m) gs->cycle_done = 1;
-    else gs->inv_scale = 1.0 / hn;
     if (stop != STOP_RUNNING) st->stop = stop;
 }
 
@@ -596,20 +581,20 @@ static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, Sol
     const int J = j + 1;
     const int nv = nv_bucket(J);
     const int64_t ld = gm_ld(n);
-    T *vj = V + static_cast<int64_t>(j) * ld;
-    T *vn = V + static_cast<int64_t>(j + 1) * ld;
+    T *uj = V + static_cast<int64_t>(j) * ld;
+    T *un = V + static_cast<int64_t>(j + 1) * ld;
 #define SPK_GM_NV(K, ...)                                                                                   \
     do {                                                                                                    \
         if (nv == 8) hipLaunchKernelGGL((K<T, 8>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);            \
         else if (nv == 16) hipLaunchKernelGGL((K<T, 16>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);     \
         else hipLaunchKernelGGL((K<T, 32>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
     } while (0)
-    SPK_GM_NV(k_gm_dots, n, ld, V, vj, w, j, st, gs, gpart);
-    hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h1[0], st, gs);
-    SPK_GM_NV(k_gm_pass2, n, ld, V, w, j, st, gs, gpart);
-    hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->h2[0], st, gs);
-    SPK_GM_NV(k_gm_pass3, n, ld, V, vn, w, j, st, gs, gpart);
-    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kBlock), 0, s, st, gs, gpart, grid, j, m);
+    SPK_GM_NV(k_gm_passA, n, ld, V, w, j, st, gs, gpart);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->b[0], st, gs);
+    hipLaunchKernelGGL(k_gm_coef, dim3(1), dim3(64), 0, s, st, gs, j);
+    SPK_GM_NV(k_gm_passB, n, ld, V, uj, un, w, j, st, gs, gpart);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->a[0], st, gs);
+    hipLaunchKernelGGL(k_gm_final, dim3(1), dim3(kBlock), 0, s, st, gs, gpart, grid, nv, j, m);
 #undef SPK_GM_NV
     return hipGetLastError();
 }

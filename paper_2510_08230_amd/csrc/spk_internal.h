@@ -52,11 +52,15 @@ struct SolveState {
 constexpr int kMaxKrylov = 32;   // largest restart length m
 struct GmresState {
     double H[(kMaxKrylov + 1) * kMaxKrylov];   // rotated Hessenberg, H[i * kMaxKrylov + j]
+    double Hu[(kMaxKrylov + 1) * kMaxKrylov];  // the same columns unrotated (A Q = Q Hu)
     double cs[kMaxKrylov], sn[kMaxKrylov];     // Givens rotations
     double g[kMaxKrylov + 1];                  // rotated right-hand side beta e_0
     double y[kMaxKrylov];                      // solution of R y = g
-    double h1[kMaxKrylov + 1], h2[kMaxKrylov + 1];   // the two Gram-Schmidt passes' coefficients
-    double inv_scale;                          // 1 / norm of the unnormalised basis vector v_j
+    double b[kMaxKrylov + 1];                  // first pass: q_t . w (t < j), u_j . w
+    double a[kMaxKrylov + 1];                  // candidate u_j = Q_j a + nu q_j: its components along Q_j
+    double h[kMaxKrylov + 1];                  // column j before the delayed correction
+    double d[kMaxKrylov + 1];                  // u_{j+1} = w / nu - sum d_t q_t
+    double nu;                                 // norm of the candidate's part orthogonal to Q_j
     int32_t used;                              // columns built in this cycle
     int32_t cycle_done;                        // nonzero: later kernels of the cycle return at once
 };

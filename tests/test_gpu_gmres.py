@@ -1,9 +1,9 @@
 """Restarted GMRES(m) on the GPU against the FP64 oracle.
 
-The GPU orthogonalises by classical Gram-Schmidt applied twice (one
-streaming pass per sweep over the basis), the oracle by modified
-Gram-Schmidt; in exact arithmetic both give the same Arnoldi basis, so the
-iterates agree to rounding.
+The GPU orthogonalises by classical Gram-Schmidt applied twice, the second
+projection delayed by one pass (two streaming passes over the basis per
+step), the oracle by modified Gram-Schmidt; in exact arithmetic both give
+the same Arnoldi basis, so the iterates agree to rounding.
 
 Stated tolerances (FP64, diagonally dominant inputs):
   * fixed-K iterates (stop test off, K within and across restarts):
