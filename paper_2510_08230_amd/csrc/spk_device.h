@@ -251,10 +251,30 @@ struct PUpdateGather {   // p_k[c] = fma(beta, p_{k-1}[c], r_k[c]): the CG direc
     __device__ __forceinline__ T operator()(int64_t c) const { return fma(beta, p_old[c], r[c]); }
 };
 
+// Column of an entry from its stored index.  ColPlain: the column index
+// itself.  ColCoded: the entry holds a one-byte code, and the column is its
+// row plus the code's offset in the matrix's table (held in LDS).
+enum class Code8 : uint8_t {};
+
+struct ColPlain {
+    template <typename I>
+    __device__ __forceinline__ int64_t operator()(I v, int64_t) const {
+        static_assert(std::is_integral_v<I>, "coded columns need ColCoded");
+        return static_cast<int64_t>(v);
+    }
+};
+
+struct ColCoded {
+    const int64_t *dict;   // LDS copy of the offset table
+    __device__ __forceinline__ int64_t operator()(Code8 v, int64_t row) const {
+        return row + dict[static_cast<uint8_t>(v)];
+    }
+};
+
 // Sum of row [a, b) with values/columns read from LDS (offsets s0v / s0c).
-template <typename V, typename I, typename C, class Gx>
+template <typename V, typename I, typename C, class Gx, class D = ColPlain>
 __device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, int64_t b, int64_t s0v, int64_t s0c,
-                                          const Gx &gx) {
+                                          const Gx &gx, const D &col = D{}, int64_t row = 0) {
     C sum = 0;
     for (int64_t k0 = a; k0 < b; k0 += kRowUnroll) {
         C av[kRowUnroll], xv[kRowUnroll];
@@ -263,7 +283,7 @@ __device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, i
             const int64_t k = k0 + u;
             if (k < b) {
                 av[u] = static_cast<C>(widen(sv[k - s0v]));
-                xv[u] = static_cast<C>(gx(static_cast<int64_t>(sc[k - s0c])));
+                xv[u] = static_cast<C>(gx(col(sc[k - s0c], row)));
             } else {
                 av[u] = 0;
                 xv[u] = 0;
@@ -275,12 +295,12 @@ __device__ __forceinline__ C row_from_lds(const V *sv, const I *sc, int64_t a, i
     return sum;
 }
 
-template <typename V, typename I, typename C, class Gx>
+template <typename V, typename I, typename C, class Gx, class D = ColPlain>
 __device__ __forceinline__ C row_from_global(const V *__restrict__ va, const I *__restrict__ ci, int64_t a, int64_t b,
-                                             const Gx &gx, int nt) {
+                                             const Gx &gx, int nt, const D &col = D{}, int64_t row = 0) {
     C sum = 0;
     for (int64_t k = a; k < b; ++k)
-        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(gx(static_cast<int64_t>(ci[k]))), sum);
+        sum = fma(static_cast<C>(widen(ldv(va + k, nt))), static_cast<C>(gx(col(ci[k], row))), sum);
     return sum;
 }
 

@@ -74,6 +74,7 @@ struct SpmvTune {
     int nt;          // 1 = non-temporal loads for the matrix value stream
     int pf;          // LDS tiles: 1 = the next tile's row pointers load while this tile's entries stream in
     int bpc;         // workgroups per CU the grid was sized for
+    int codes = 0;   // LDS tiles: 1 = read the matrix's one-byte column codes (CsrDev::codes)
 };
 
 // Device CSR view with runtime-typed arrays.
@@ -81,7 +82,14 @@ struct CsrDev {
     int64_t n_rows, n_cols, nnz;
     int ptr_t, idx_t, val_t;   // spk_itype / spk_dtype codes
     const void *rp, *ci, *va;
+    // Optional one-byte column codes (null when absent): byte k names entry k's
+    // column offset from its row, c - i, in a table of kCodeDict int64 offsets
+    // stored in the kCodeDict * 8 bytes just before the codes.
+    const void *codes = nullptr;
 };
+
+constexpr int kCodeDict = 256;    // distinct column offsets a code table holds
+constexpr int kCodeSlots = 1024;  // plan-time hash table of distinct offsets (power of two)
 
 // Validation flag bits (set by the GPU check, order resolved on the host).
 enum : unsigned { VFLAG_BAD_FIRST = 1u, VFLAG_DECREASING = 2u, VFLAG_BAD_LAST = 4u, VFLAG_BAD_COLUMN = 8u,

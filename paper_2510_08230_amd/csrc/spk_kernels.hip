@@ -28,6 +28,7 @@
 #include "spk_launch.h"
 #include "spk_spmv.h"
 
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -641,6 +642,129 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
     if (f) atomicOr(flags, f);
 }
 
+// ------------------------------------------------------------------ column codes
+// Plan-time derivation of the one-byte column codes that the LDS-tile SpMV can
+// stream in place of column indices: index compression by offset from the
+// row, for patterns with few distinct offsets c - i (stencils, banded
+// matrices).  Random patterns overflow the table and keep their indices.
+//   k_code_collect: each workgroup gathers the distinct offsets of its rows in
+//     an LDS hash set, then merges them into the global open-addressing
+//     table; more than kCodeDict distinct offsets sets the overflow word.
+//   k_code_table: one workgroup ranks the table's offsets into an ascending
+//     kCodeDict-entry table (unused entries 0).
+//   k_code_encode: every entry's offset is found by binary search in that
+//     table and its position stored as one byte; an offset missing from the
+//     table sets the error word and the plan keeps the plain indices.
+constexpr int kCodeLdsSlots = 512;
+constexpr long long kCodeEmpty = LLONG_MIN;   // below every offset -(n - 1) .. n - 1
+
+__device__ __forceinline__ unsigned code_hash(long long d, int bits) {
+    return static_cast<unsigned>((static_cast<unsigned long long>(d) * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+}
+
+__global__ __launch_bounds__(kBlock) void k_code_clear(long long *table, unsigned *words) {
+    for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) table[i] = kCodeEmpty;
+    if (threadIdx.x < 2) words[threadIdx.x] = 0;
+}
+
+// Inserts d into an open-addressing set of 2^bits slots; returns 1 if this
+// call placed it, 0 if it was present, -1 if every slot holds another value.
+__device__ __forceinline__ int code_insert(long long *set, int bits, long long d) {
+    const unsigned mask = (1u << bits) - 1u;
+    unsigned h = code_hash(d, bits);
+    for (unsigned probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
+        long long v = set[h];
+        if (v == d) return 0;
+        if (v == kCodeEmpty) {
+            v = static_cast<long long>(atomicCAS(reinterpret_cast<unsigned long long *>(set + h),
+                                                 static_cast<unsigned long long>(kCodeEmpty),
+                                                 static_cast<unsigned long long>(d)));
+            if (v == kCodeEmpty) return 1;
+            if (v == d) return 0;
+        }
+    }
+    return -1;
+}
+
+template <typename P, typename I>
+__global__ __launch_bounds__(kBlock) void k_code_collect(int64_t n_rows, const P *__restrict__ rp,
+                                                         const I *__restrict__ ci, long long *table,
+                                                         unsigned *words) {
+    __shared__ long long set[kCodeLdsSlots];
+    __shared__ unsigned used, over;
+    for (int i = threadIdx.x; i < kCodeLdsSlots; i += kBlock) set[i] = kCodeEmpty;
+    if (threadIdx.x == 0) used = over = 0;
+    __syncthreads();
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < n_rows; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        if (i < n_rows) {
+            const int64_t a = static_cast<int64_t>(rp[i]), b = static_cast<int64_t>(rp[i + 1]);
+            for (int64_t k = a; k < b && !over; ++k) {
+                const int r = code_insert(set, 9, static_cast<long long>(ci[k]) - i);
+                if (r < 0 || (r > 0 && atomicAdd(&used, 1u) >= static_cast<unsigned>(kCodeDict))) over = 1;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && words[1]) over = 1;   // another workgroup already overflowed
+        __syncthreads();
+        if (over) break;                               // uniform: read after the barrier
+    }
+    if (over) {
+        if (threadIdx.x == 0) atomicOr(&words[1], 1u);
+        return;
+    }
+    for (int i = threadIdx.x; i < kCodeLdsSlots; i += kBlock) {
+        const long long d = set[i];
+        if (d == kCodeEmpty) continue;
+        const int r = code_insert(table, 10, d);
+        if (r < 0 || (r > 0 && atomicAdd(&words[0], 1u) >= static_cast<unsigned>(kCodeDict))) atomicOr(&words[1], 1u);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_code_table(const long long *__restrict__ table, int64_t *dict) {
+    __shared__ long long t[kCodeSlots];
+    __shared__ long long out[kCodeDict];
+    for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) t[i] = table[i];
+    for (int i = threadIdx.x; i < kCodeDict; i += kBlock) out[i] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) {
+        const long long d = t[i];
+        if (d == kCodeEmpty) continue;
+        int rank = 0;
+        for (int j = 0; j < kCodeSlots; ++j) rank += (t[j] != kCodeEmpty && t[j] < d) ? 1 : 0;
+        if (rank < kCodeDict) out[rank] = d;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = out[i];
+}
+
+template <typename P, typename I>
+__global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, int ndict, const P *__restrict__ rp,
+                                                        const I *__restrict__ ci, const int64_t *__restrict__ dict,
+                                                        uint8_t *__restrict__ codes, unsigned *words) {
+    __shared__ int64_t t[kCodeDict];
+    for (int i = threadIdx.x; i < kCodeDict; i += kBlock) t[i] = dict[i];
+    __syncthreads();
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    unsigned bad = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n_rows; i += stride) {
+        const int64_t a = static_cast<int64_t>(rp[i]), b = static_cast<int64_t>(rp[i + 1]);
+        for (int64_t k = a; k < b; ++k) {
+            const int64_t d = static_cast<int64_t>(ci[k]) - i;
+            int lo = 0, hi = ndict;   // t[lo] <= d < t[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (t[mid] <= d) lo = mid;
+                else hi = mid;
+            }
+            if (t[lo] == d) codes[k] = static_cast<uint8_t>(lo);
+            else bad = 1;
+        }
+    }
+    if (bad) atomicOr(&words[1], 2u);
+}
+
 // COO structure: row and column indices in range, rows non-decreasing.
 template <typename I>
 __global__ __launch_bounds__(kBlock) void k_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz,
@@ -720,6 +844,33 @@ hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipSt
         using P = pointee_t<decltype(rp)>;
         using I = pointee_t<decltype(ci)>;
         hipLaunchKernelGGL((k_validate<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, A.n_cols, A.nnz, rp, ci, flags);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_code_collect(const CsrDev &A, long long *table, unsigned *words, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_code_clear, dim3(1), dim3(kBlock), 0, s, table, words);
+    if (A.n_rows == 0) return hipGetLastError();
+    return dispatch_idx(A, [&](auto rp, auto ci) {
+        using P = pointee_t<decltype(rp)>;
+        using I = pointee_t<decltype(ci)>;
+        hipLaunchKernelGGL((k_code_collect<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, ci, table, words);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_code_encode(const CsrDev &A, const long long *table, unsigned ndict, void *codes_base,
+                              unsigned *words, int grid, hipStream_t s) {
+    if (ndict < 1 || ndict > static_cast<unsigned>(kCodeDict)) return hipErrorInvalidValue;
+    int64_t *dict = static_cast<int64_t *>(codes_base);
+    uint8_t *codes = static_cast<uint8_t *>(codes_base) + kCodeDict * sizeof(int64_t);
+    hipLaunchKernelGGL(k_code_table, dim3(1), dim3(kBlock), 0, s, table, dict);
+    if (A.n_rows == 0) return hipGetLastError();
+    return dispatch_idx(A, [&](auto rp, auto ci) {
+        using P = pointee_t<decltype(rp)>;
+        using I = pointee_t<decltype(ci)>;
+        hipLaunchKernelGGL((k_code_encode<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, static_cast<int>(ndict),
+                           rp, ci, dict, codes, words);
         return hipGetLastError();
     });
 }

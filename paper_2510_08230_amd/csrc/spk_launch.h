@@ -10,6 +10,14 @@ namespace spk {
 // ---- launchers (spk_kernels.hip) -------------------------------------------------
 hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
+// Column codes (plan time).  collect: the distinct column offsets c - i into
+// table (kCodeSlots int64 words; words[0] = distinct offsets, words[1] != 0 =
+// more than kCodeDict of them).  encode: the sorted offset table into the
+// first kCodeDict * 8 bytes of codes_base and one code byte per entry after
+// it; words[1] != 0 afterwards = an entry without a code (codes unusable).
+hipError_t launch_code_collect(const CsrDev &A, long long *table, unsigned *words, int grid, hipStream_t s);
+hipError_t launch_code_encode(const CsrDev &A, const long long *table, unsigned ndict, void *codes_base,
+                              unsigned *words, int grid, hipStream_t s);
 // COO (idx_t 0 = int32, 1 = int64): flags gets VFLAG_BAD_FIRST for a row
 // index out of range, VFLAG_BAD_COLUMN, VFLAG_UNSORTED for a decreasing row.
 hipError_t launch_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const void *row, const void *col,

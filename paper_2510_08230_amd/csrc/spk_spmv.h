@@ -34,10 +34,11 @@ struct Vec16 {
 // The tile loop of the LDS-staged SpMV, shared by the per-launch kernel and the
 // persistent CG kernel: calls epi.row(row, sum) for every row of the tiles
 // this workgroup visits.  lv / lc: the workgroup's LDS staging buffers.
-template <typename V, typename P, typename I, typename C, class Gx, class Epi>
+template <typename V, typename P, typename I, typename C, class Gx, class Epi, class D = ColPlain>
 __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
-                                               int remap, int nt, int pf, Epi &epi, u32x4 *lv, u32x4 *lc) {
+                                               int remap, int nt, int pf, Epi &epi, u32x4 *lv, u32x4 *lc,
+                                               const D &col = D{}) {
     const V *sv = reinterpret_cast<const V *>(lv);
     const I *sc = reinterpret_cast<const I *>(lc);
     const int64_t T = (n + kTileRows - 1) / kTileRows;
@@ -64,12 +65,12 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
             if (row < r1) {
                 const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
                 const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
-                epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx));
+                epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row));
             }
             __syncthreads();                 // LDS free for the next tile
         } else {
             if (more && pf) nxt.load(rp, n, after.tile());
-            if (row < r1) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt));
+            if (row < r1) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt, col, row));
         }
         if (!more) break;
         if (!pf) nxt.load(rp, n, after.tile());
@@ -87,7 +88,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, 
     if (epi.skip()) return;
     __shared__ u32x4 lv[Chunks<V>::LDS];
     __shared__ u32x4 lc[Chunks<I>::LDS];
-    spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, pf, epi, lv, lc);
+    if constexpr (std::is_same_v<I, Code8>) {
+        // the offset table sits in the kCodeDict * 8 bytes before the codes
+        __shared__ int64_t dict[kCodeDict];
+        const int64_t *g = reinterpret_cast<const int64_t *>(ci) - kCodeDict;
+        for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = g[i];
+        __syncthreads();
+        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, pf, epi, lv, lc,
+                                   ColCoded{dict});
+    } else {
+        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, pf, epi, lv, lc);
+    }
     epi.finish();
 }
 
@@ -150,7 +161,10 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
         using I = pointee_t<decltype(ci)>;
         const V *va = static_cast<const V *>(A.va);
         const dim3 grid(t.grid), block(kBlock);
-        if (t.kind == 0) {
+        if (t.kind == 0 && t.codes && A.codes) {
+            hipLaunchKernelGGL((k_spmv_stream<V, P, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp,
+                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, epi);
+        } else if (t.kind == 0) {
             hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
                                t.xcd_remap, t.nt, t.pf, epi);
         } else {

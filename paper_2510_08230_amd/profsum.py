@@ -115,7 +115,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, last: 
             "traffic_bytes": kf * 1024.0 * scale_f + kw * 1024.0 * scale_w, "kernel_digest": kernel_digest()}
 
 
-TILING_KEYS = ("spmv_kernel", "lanes", "grid", "xcd_remap")
+TILING_KEYS = ("spmv_kernel", "lanes", "grid", "xcd_remap", "col_codes")
 
 
 def bench_tiling(log_path: str) -> dict:

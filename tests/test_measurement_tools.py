@@ -50,13 +50,14 @@ def test_traffic_scales_by_the_copy_kernel(tmp_path):
 
 def tiling(remap=64, grid=1280):
     return {"spmv_kernel": 0, "lanes": 1, "grid": grid, "xcd_remap": remap, "exec_mode": 1, "chunk_iters": 0,
-            "tuned": 1, "reserved": 0, "spmv_ms": 0.18}
+            "tuned": 1, "col_codes": 1, "spmv_ms": 0.18}
 
 
 def test_bench_tiling_reads_the_json_line(tmp_path):
     log = tmp_path / "run.log"
     log.write_text("profiler noise\n" + json.dumps({"config": {"spmv_tiling": tiling(0, 1024)}}) + "\nmore noise\n")
-    assert profsum.bench_tiling(str(log)) == {"spmv_kernel": 0, "lanes": 1, "grid": 1024, "xcd_remap": 0}
+    assert profsum.bench_tiling(str(log)) == {"spmv_kernel": 0, "lanes": 1, "grid": 1024, "xcd_remap": 0,
+                                              "col_codes": 1}
     (tmp_path / "empty.log").write_text("no json here\n")
     with pytest.raises(SystemExit):
         profsum.bench_tiling(str(tmp_path / "empty.log"))
