@@ -391,39 +391,40 @@ spk_status build_codes(spk_plan pl) {
     CsrDev &A = pl->A;
     const char *env = std::getenv("SPK_COL_CODES");
     if ((env && std::strcmp(env, "0") == 0) || A.nnz == 0 || A.n_rows == 0 || !stream_ok(A)) return SPK_OK;
-    void *tab = nullptr;
+    void *tab = nullptr, *buf = nullptr;
+    const size_t bytes = sizeof(int64_t) * spk::kCodeDict + ((static_cast<size_t>(A.nnz) + 15) & ~size_t(15));
     if (ctx->dpool.get(sizeof(long long) * spk::kCodeSlots + 2 * sizeof(unsigned), &tab) != hipSuccess)
         return SPK_OK;
+    if (ctx->dpool.get(bytes, &buf) != hipSuccess) {   // no room for codes: plain indices
+        ctx->dpool.put(tab);
+        return SPK_OK;
+    }
     long long *table = static_cast<long long *>(tab);
     unsigned *words = reinterpret_cast<unsigned *>(table + spk::kCodeSlots);
     unsigned h[2] = {0, 0};
-    const int grid = ctx->num_cu * 4;
-    auto done = [&](spk_status st) {
-        (void)hipStreamSynchronize(ctx->stream);
-        ctx->dpool.put(tab);
-        return st;
-    };
-    if (spk::launch_code_collect(A, table, words, grid, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(h, words, sizeof(h), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-        return done(fail(ctx, SPK_ERR_DEVICE, "column code collection"));
-    if (h[1] != 0 || h[0] < 1 || h[0] > static_cast<unsigned>(spk::kCodeDict)) return done(SPK_OK);
-    const size_t bytes = sizeof(int64_t) * spk::kCodeDict + ((static_cast<size_t>(A.nnz) + 15) & ~size_t(15));
-    void *buf = nullptr;
-    if (ctx->dpool.get(bytes, &buf) != hipSuccess) return done(SPK_OK);
-    if (spk::launch_code_encode(A, table, h[0], buf, words, grid, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(h, words, sizeof(h), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-        ctx->dpool.put(buf);
-        return done(fail(ctx, SPK_ERR_DEVICE, "column code encoding"));
+    // a sample of the tiles first (every 8th and the last: structured
+    // patterns repeat their offsets); if an entry's offset was missed, all
+    // tiles.  Two waves of workgroups per CU for the latency-bound walks.
+    const int grid = ctx->num_cu * 8;
+    bool ok = true;
+    for (int step : {8, 1}) {
+        ok = spk::launch_code_build(A, step, table, words, buf, grid, ctx->stream) == hipSuccess &&
+             hipMemcpyAsync(h, words, sizeof(h), hipMemcpyDeviceToHost, ctx->stream) == hipSuccess &&
+             hipStreamSynchronize(ctx->stream) == hipSuccess;
+        if (!ok || !(h[1] & 2u)) break;
     }
-    if (h[1] != 0) {
+    ctx->dpool.put(tab);
+    if (!ok) {
         ctx->dpool.put(buf);
-        return done(SPK_OK);
+        return fail(ctx, SPK_ERR_DEVICE, "column codes");
+    }
+    if (h[1] != 0 || h[0] < 1 || h[0] > static_cast<unsigned>(spk::kCodeDict)) {
+        ctx->dpool.put(buf);
+        return SPK_OK;
     }
     pl->codes_buf = buf;
     A.codes = static_cast<const char *>(buf) + sizeof(int64_t) * spk::kCodeDict;
-    return done(SPK_OK);
+    return SPK_OK;
 }
 
 // ------------------------------------------------------------------ profiling events

@@ -647,14 +647,19 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
 // stream in place of column indices: index compression by offset from the
 // row, for patterns with few distinct offsets c - i (stencils, banded
 // matrices).  Random patterns overflow the table and keep their indices.
-//   k_code_collect: each workgroup gathers the distinct offsets of its rows in
-//     an LDS hash set, then merges them into the global open-addressing
-//     table; more than kCodeDict distinct offsets sets the overflow word.
+//   k_code_collect: each workgroup gathers the distinct offsets of its tiles
+//     (all tiles, or every step-th tile and the last one) in an LDS hash
+//     set, then merges them into the global open-addressing table; more than
+//     kCodeDict distinct offsets sets the overflow word.
 //   k_code_table: one workgroup ranks the table's offsets into an ascending
-//     kCodeDict-entry table (unused entries 0).
+//     kCodeDict-entry table (unused entries 0), unless the collection
+//     overflowed.
 //   k_code_encode: every entry's offset is found by binary search in that
 //     table and its position stored as one byte; an offset missing from the
-//     table sets the error word and the plan keeps the plain indices.
+//     table (possible after a sampled collection) sets the error word, and
+//     the plan collects again over every tile, or keeps the plain indices.
+// The three launch back to back; the host reads the words once at the end.
+// words[0] = distinct offsets, words[1] = overflow (1) / missing code (2).
 constexpr int kCodeLdsSlots = 512;
 constexpr long long kCodeEmpty = LLONG_MIN;   // below every offset -(n - 1) .. n - 1
 
@@ -686,25 +691,88 @@ __device__ __forceinline__ int code_insert(long long *set, int bits, long long d
     return -1;
 }
 
+// The entries of the 256-row tile at row r0, for the code kernels.  When the
+// tile's entries fit the LDS row map (the usual case), load() maps each entry
+// to its row and gives this thread the offsets of entries s + threadIdx.x +
+// j * kBlock (j < kCodeBatch; invalid past e), all loads issued before any
+// is used; otherwise mapped is false and each thread walks its own row
+// [a, b).  Every thread of the workgroup must call load() and done().
+constexpr int kCodeBatch = kStreamCap / kBlock;
+
+template <typename P, typename I>
+struct CodeTile {
+    int64_t s, e, a, b, row;
+    bool mapped;
+    int64_t d[kCodeBatch];
+    __device__ __forceinline__ void load(int64_t n_rows, const P *__restrict__ rp, const I *__restrict__ ci,
+                                         int64_t r0, unsigned short *row_of) {
+        const int64_t r1 = r0 + kTileRows < n_rows ? r0 + kTileRows : n_rows;
+        s = static_cast<int64_t>(rp[r0]);
+        e = static_cast<int64_t>(rp[r1]);
+        row = r0 + threadIdx.x;
+        a = b = 0;
+        if (row < r1) {
+            a = static_cast<int64_t>(rp[row]);
+            b = static_cast<int64_t>(rp[row + 1]);
+        }
+        mapped = e - s <= kStreamCap;   // uniform
+        if (!mapped) return;
+        for (int64_t k = a; k < b; ++k) row_of[k - s] = static_cast<unsigned short>(threadIdx.x);
+        __syncthreads();
+        int64_t c[kCodeBatch];
+#pragma unroll
+        for (int j = 0; j < kCodeBatch; ++j) {
+            const int64_t k = s + threadIdx.x + j * kBlock;
+            c[j] = k < e ? static_cast<int64_t>(ci[k]) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kCodeBatch; ++j) {
+            const int64_t k = s + threadIdx.x + j * kBlock;
+            d[j] = k < e ? c[j] - (r0 + row_of[k - s]) : 0;
+        }
+    }
+    __device__ __forceinline__ bool valid(int j) const { return s + threadIdx.x + j * kBlock < e; }
+    __device__ __forceinline__ int64_t entry(int j) const { return s + threadIdx.x + j * kBlock; }
+    __device__ __forceinline__ void done() const {
+        if (mapped) __syncthreads();   // row map free for the next tile
+    }
+};
+
+// Tiles of the collection: every tile (step 1), or every step-th tile and the
+// last one (a sample; the encode pass then proves the table complete).
+__device__ __forceinline__ int64_t code_tiles(int64_t T, int step) { return (T + step - 1) / step + (step > 1); }
+__device__ __forceinline__ int64_t code_tile(int64_t u, int64_t T, int step) {
+    const int64_t t = u * step;
+    return t < T ? t : T - 1;
+}
+
 template <typename P, typename I>
 __global__ __launch_bounds__(kBlock) void k_code_collect(int64_t n_rows, const P *__restrict__ rp,
-                                                         const I *__restrict__ ci, long long *table,
+                                                         const I *__restrict__ ci, int step, long long *table,
                                                          unsigned *words) {
     __shared__ long long set[kCodeLdsSlots];
+    __shared__ unsigned short row_of[kStreamCap];
     __shared__ unsigned used, over;
     for (int i = threadIdx.x; i < kCodeLdsSlots; i += kBlock) set[i] = kCodeEmpty;
     if (threadIdx.x == 0) used = over = 0;
     __syncthreads();
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < n_rows; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        if (i < n_rows) {
-            const int64_t a = static_cast<int64_t>(rp[i]), b = static_cast<int64_t>(rp[i + 1]);
-            for (int64_t k = a; k < b && !over; ++k) {
-                const int r = code_insert(set, 9, static_cast<long long>(ci[k]) - i);
-                if (r < 0 || (r > 0 && atomicAdd(&used, 1u) >= static_cast<unsigned>(kCodeDict))) over = 1;
-            }
+    const int64_t T = (n_rows + kTileRows - 1) / kTileRows;
+    const int64_t U = code_tiles(T, step);
+    auto add = [&](long long d) {
+        const int r = code_insert(set, 9, d);
+        if (r < 0 || (r > 0 && atomicAdd(&used, 1u) >= static_cast<unsigned>(kCodeDict))) over = 1;
+    };
+    for (int64_t u = blockIdx.x; u < U; u += gridDim.x) {
+        CodeTile<P, I> t;
+        t.load(n_rows, rp, ci, code_tile(u, T, step) * kTileRows, row_of);
+        if (t.mapped) {
+#pragma unroll
+            for (int j = 0; j < kCodeBatch; ++j)
+                if (t.valid(j) && !over) add(t.d[j]);
+        } else {
+            for (int64_t k = t.a; k < t.b && !over; ++k) add(static_cast<long long>(ci[k]) - t.row);
         }
+        t.done();
         __syncthreads();
         if (threadIdx.x == 0 && words[1]) over = 1;   // another workgroup already overflowed
         __syncthreads();
@@ -722,45 +790,75 @@ __global__ __launch_bounds__(kBlock) void k_code_collect(int64_t n_rows, const P
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_code_table(const long long *__restrict__ table, int64_t *dict) {
-    __shared__ long long t[kCodeSlots];
+__global__ __launch_bounds__(kBlock) void k_code_table(const long long *__restrict__ table,
+                                                       const unsigned *__restrict__ words, int64_t *dict) {
+    __shared__ long long t[kCodeDict];
     __shared__ long long out[kCodeDict];
-    for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) t[i] = table[i];
+    __shared__ unsigned cnt;
+    if (words[1] != 0 || words[0] > static_cast<unsigned>(kCodeDict)) return;   // no codes: uniform
+    if (threadIdx.x == 0) cnt = 0;
     for (int i = threadIdx.x; i < kCodeDict; i += kBlock) out[i] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) {
-        const long long d = t[i];
+    for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) {   // compact (at most kCodeDict entries)
+        const long long d = table[i];
         if (d == kCodeEmpty) continue;
+        const unsigned at = atomicAdd(&cnt, 1u);
+        if (at < static_cast<unsigned>(kCodeDict)) t[at] = d;
+    }
+    __syncthreads();
+    const int m = cnt < static_cast<unsigned>(kCodeDict) ? static_cast<int>(cnt) : kCodeDict;
+    for (int i = threadIdx.x; i < m; i += kBlock) {
         int rank = 0;
-        for (int j = 0; j < kCodeSlots; ++j) rank += (t[j] != kCodeEmpty && t[j] < d) ? 1 : 0;
-        if (rank < kCodeDict) out[rank] = d;
+        for (int j = 0; j < m; ++j) rank += t[j] < t[i] ? 1 : 0;
+        out[rank] = t[i];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = out[i];
 }
 
+// Position of d in the ascending table t[0, n), or -1.
+__device__ __forceinline__ int code_find(const int64_t *t, int n, int64_t d) {
+    int lo = 0, hi = n;   // t[lo] <= d < t[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t[mid] <= d) lo = mid;
+        else hi = mid;
+    }
+    return t[lo] == d ? lo : -1;
+}
+
 template <typename P, typename I>
-__global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, int ndict, const P *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const int64_t *__restrict__ dict,
                                                         uint8_t *__restrict__ codes, unsigned *words) {
-    __shared__ int64_t t[kCodeDict];
-    for (int i = threadIdx.x; i < kCodeDict; i += kBlock) t[i] = dict[i];
+    __shared__ int64_t tab[kCodeDict];
+    __shared__ unsigned short row_of[kStreamCap];
+    const unsigned nd = words[0];
+    if (words[1] != 0 || nd < 1 || nd > static_cast<unsigned>(kCodeDict)) return;   // no codes: uniform
+    const int ndict = static_cast<int>(nd);
+    for (int i = threadIdx.x; i < kCodeDict; i += kBlock) tab[i] = dict[i];
     __syncthreads();
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     unsigned bad = 0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n_rows; i += stride) {
-        const int64_t a = static_cast<int64_t>(rp[i]), b = static_cast<int64_t>(rp[i + 1]);
-        for (int64_t k = a; k < b; ++k) {
-            const int64_t d = static_cast<int64_t>(ci[k]) - i;
-            int lo = 0, hi = ndict;   // t[lo] <= d < t[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (t[mid] <= d) lo = mid;
-                else hi = mid;
+    const int64_t T = (n_rows + kTileRows - 1) / kTileRows;
+    for (int64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+        CodeTile<P, I> t;
+        t.load(n_rows, rp, ci, tile * kTileRows, row_of);
+        if (t.mapped) {
+#pragma unroll
+            for (int j = 0; j < kCodeBatch; ++j) {
+                if (!t.valid(j)) continue;
+                const int c = code_find(tab, ndict, t.d[j]);
+                if (c >= 0) codes[t.entry(j)] = static_cast<uint8_t>(c);
+                else bad = 1;
             }
-            if (t[lo] == d) codes[k] = static_cast<uint8_t>(lo);
-            else bad = 1;
+        } else {
+            for (int64_t k = t.a; k < t.b; ++k) {
+                const int c = code_find(tab, ndict, static_cast<int64_t>(ci[k]) - t.row);
+                if (c >= 0) codes[k] = static_cast<uint8_t>(c);
+                else bad = 1;
+            }
         }
+        t.done();
     }
     if (bad) atomicOr(&words[1], 2u);
 }
@@ -848,29 +946,21 @@ hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipSt
     });
 }
 
-hipError_t launch_code_collect(const CsrDev &A, long long *table, unsigned *words, int grid, hipStream_t s) {
+hipError_t launch_code_build(const CsrDev &A, int step, long long *table, unsigned *words, void *codes_base,
+                             int grid, hipStream_t s) {
+    int64_t *dict = static_cast<int64_t *>(codes_base);
+    uint8_t *codes = static_cast<uint8_t *>(codes_base) + kCodeDict * sizeof(int64_t);
+    if (step < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_code_clear, dim3(1), dim3(kBlock), 0, s, table, words);
     if (A.n_rows == 0) return hipGetLastError();
     return dispatch_idx(A, [&](auto rp, auto ci) {
         using P = pointee_t<decltype(rp)>;
         using I = pointee_t<decltype(ci)>;
-        hipLaunchKernelGGL((k_code_collect<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, ci, table, words);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_code_encode(const CsrDev &A, const long long *table, unsigned ndict, void *codes_base,
-                              unsigned *words, int grid, hipStream_t s) {
-    if (ndict < 1 || ndict > static_cast<unsigned>(kCodeDict)) return hipErrorInvalidValue;
-    int64_t *dict = static_cast<int64_t *>(codes_base);
-    uint8_t *codes = static_cast<uint8_t *>(codes_base) + kCodeDict * sizeof(int64_t);
-    hipLaunchKernelGGL(k_code_table, dim3(1), dim3(kBlock), 0, s, table, dict);
-    if (A.n_rows == 0) return hipGetLastError();
-    return dispatch_idx(A, [&](auto rp, auto ci) {
-        using P = pointee_t<decltype(rp)>;
-        using I = pointee_t<decltype(ci)>;
-        hipLaunchKernelGGL((k_code_encode<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, static_cast<int>(ndict),
-                           rp, ci, dict, codes, words);
+        hipLaunchKernelGGL((k_code_collect<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, ci, step, table,
+                           words);
+        hipLaunchKernelGGL(k_code_table, dim3(1), dim3(kBlock), 0, s, table, words, dict);
+        hipLaunchKernelGGL((k_code_encode<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, ci, dict, codes,
+                           words);
         return hipGetLastError();
     });
 }

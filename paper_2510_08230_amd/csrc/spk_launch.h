@@ -10,14 +10,15 @@ namespace spk {
 // ---- launchers (spk_kernels.hip) -------------------------------------------------
 hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
-// Column codes (plan time).  collect: the distinct column offsets c - i into
-// table (kCodeSlots int64 words; words[0] = distinct offsets, words[1] != 0 =
-// more than kCodeDict of them).  encode: the sorted offset table into the
-// first kCodeDict * 8 bytes of codes_base and one code byte per entry after
-// it; words[1] != 0 afterwards = an entry without a code (codes unusable).
-hipError_t launch_code_collect(const CsrDev &A, long long *table, unsigned *words, int grid, hipStream_t s);
-hipError_t launch_code_encode(const CsrDev &A, const long long *table, unsigned ndict, void *codes_base,
-                              unsigned *words, int grid, hipStream_t s);
+// Column codes (plan time): collects the distinct column offsets c - i of
+// every step-th row tile (and the last) into table (kCodeSlots int64 words),
+// then, when there are at most kCodeDict of them, writes the ascending offset
+// table into the first kCodeDict * 8 bytes of codes_base and one code byte
+// per entry after it.  Afterwards words[0] = distinct offsets collected;
+// words[1] = 0: codes usable, bit 0: more than kCodeDict offsets, bit 1: an
+// entry's offset was not collected (sampled collection incomplete).
+hipError_t launch_code_build(const CsrDev &A, int step, long long *table, unsigned *words, void *codes_base,
+                             int grid, hipStream_t s);
 // COO (idx_t 0 = int32, 1 = int64): flags gets VFLAG_BAD_FIRST for a row
 // index out of range, VFLAG_BAD_COLUMN, VFLAG_UNSORTED for a decreasing row.
 hipError_t launch_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz, const void *row, const void *col,

@@ -5,7 +5,8 @@ A coded product sums every row in the same order as the plain-index kernel,
 so its result must equal that kernel's bit for bit, on every value type,
 index type, ragged tail and tile size; solves with and without codes must
 give identical iterates.  The plan takes codes exactly when the pattern has
-at most 256 distinct offsets c - i (checked at 256 and 257), and the FP64
+at most 256 distinct offsets c - i (checked at 256 and 257, and with an
+offset that occurs in one row only, which a sampled collection misses), and the FP64
 products stay within the summation bound 2 gamma_m(u) (|A||x|)_i of the
 oracle's."""
 import numpy as np
@@ -32,10 +33,10 @@ def ctx(spk):
     spk.spk_finalize(c)
 
 
-def banded(n, offsets, seed, empty_every=0):
+def banded(n, offsets, seed, empty_every=0, extra=None):
     """n x n matrix with entries at columns i + d for every d in offsets that
-    stays in range (rows i with i % empty_every == 1 left empty), values
-    uniform[-1, 1)."""
+    stays in range (rows i with i % empty_every == 1 left empty; row i of
+    extra also holds the offsets extra[i]), values uniform[-1, 1)."""
     rng = np.random.default_rng(seed)
     rp, cols = [0], []
     offs = np.asarray(sorted(offsets), np.int64)
@@ -43,7 +44,7 @@ def banded(n, offsets, seed, empty_every=0):
         if empty_every and i % empty_every == 1:
             rp.append(len(cols))
             continue
-        c = i + offs
+        c = i + (np.asarray(sorted(set(offsets) | set(extra[i])), np.int64) if extra and i in extra else offs)
         cols.extend(c[(c >= 0) & (c < n)].tolist())
         rp.append(len(cols))
     col = np.asarray(cols, np.int32)
@@ -65,8 +66,12 @@ MATS = {
     "stencil7_23": lambda: inputs.stencil7(23, 0),              # 12167 rows: ragged last tile
     "stencil7_46": lambda: inputs.stencil7(46, 1),
     "stencil7ns_17": lambda: inputs.stencil7_ns(17, 2),
+    # 9 entries per row: 2304 per tile, past the plan's LDS row map (rows walked per thread)
+    "band9": lambda: banded(3001, [-700, -64, -3, -1, 0, 1, 2, 64, 700], 3),
     "band9_empty_rows": lambda: banded(5003, [-700, -64, -3, -1, 0, 1, 2, 64, 700], 3, empty_every=7),
     "randsym_100": lambda: inputs.randsym(100, 4),              # offsets within +-99
+    # offset 37 only in row 300 (second tile): a sampled collection misses it
+    "band3_rare_offset": lambda: banded(5000, [-1, 0, 1], 5, extra={300: [37]}),
 }
 
 
