@@ -384,13 +384,19 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN
 
 // One-byte column codes for the LDS-tile SpMV (kernels k_code_*): built when
 // the pattern has at most kCodeDict distinct column offsets c - i and the
-// LDS tiling can stage them; SPK_COL_CODES=0 turns them off.  A pattern
-// without codes, or a failed allocation, leaves the plain indices in use.
+// LDS tiling can stage them, for matrices of at least kCodeMinNnz entries
+// (below that the plan-time build and its read-back cost more than a solve
+// saves: 3 bytes per entry per product).  SPK_COL_CODES=0 turns them off,
+// SPK_COL_CODES=1 builds them at any size.  A pattern without codes, or a
+// failed allocation, leaves the plain indices in use.
+constexpr int64_t kCodeMinNnz = int64_t(1) << 22;
+
 spk_status build_codes(spk_plan pl) {
     spk_ctx ctx = pl->ctx;
     CsrDev &A = pl->A;
     const char *env = std::getenv("SPK_COL_CODES");
     if ((env && std::strcmp(env, "0") == 0) || A.nnz == 0 || A.n_rows == 0 || !stream_ok(A)) return SPK_OK;
+    if (!(env && std::strcmp(env, "1") == 0) && A.nnz < kCodeMinNnz) return SPK_OK;
     void *tab = nullptr, *buf = nullptr;
     const size_t bytes = sizeof(int64_t) * spk::kCodeDict + ((static_cast<size_t>(A.nnz) + 15) & ~size_t(15));
     if (ctx->dpool.get(sizeof(long long) * spk::kCodeSlots + 2 * sizeof(unsigned), &tab) != hipSuccess)

@@ -6,7 +6,9 @@ so its result must equal that kernel's bit for bit, on every value type,
 index type, ragged tail and tile size; solves with and without codes must
 give identical iterates.  The plan takes codes exactly when the pattern has
 at most 256 distinct offsets c - i (checked at 256 and 257, and with an
-offset that occurs in one row only, which a sampled collection misses), and the FP64
+offset that occurs in one row only, which a sampled collection misses) and
+the matrix has 2^22 entries or more (SPK_COL_CODES=1, set here, builds them
+at any size), and the FP64
 products stay within the summation bound 2 gamma_m(u) (|A||x|)_i of the
 oracle's."""
 import numpy as np
@@ -24,6 +26,12 @@ pytestmark = pytest.mark.gpu
 def spk():
     from paper_2510_08230_amd import spk as m
     return m
+
+
+@pytest.fixture(autouse=True)
+def codes_at_any_size(monkeypatch):
+    # plans build codes for matrices of 2^22 entries and more unless asked
+    monkeypatch.setenv("SPK_COL_CODES", "1")
 
 
 @pytest.fixture(scope="module")
@@ -119,16 +127,21 @@ def test_random_pattern_keeps_indices(spk, ctx):
     assert np.all(np.abs(y - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
 
 
-def test_codes_off_by_environment(spk, ctx, monkeypatch):
-    A = inputs.stencil7(20, 0)
-    monkeypatch.setenv("SPK_COL_CODES", "0")
+@pytest.mark.parametrize("env,coded", [("0", 0), (None, 0), ("1", 1)])
+def test_codes_by_environment_and_size(spk, ctx, monkeypatch, env, coded):
+    A = inputs.stencil7(20, 0)   # 54,400 entries: below the default size for codes
+    if env is None:
+        monkeypatch.delenv("SPK_COL_CODES")
+    else:
+        monkeypatch.setenv("SPK_COL_CODES", env)
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
     _, info = spmv(spk, ctx, dev_csr(spk, A), to_dev(inputs.vec(A.n_cols, 1, 5)), A.n_rows)
-    assert info["col_codes"] == 0
+    assert info["col_codes"] == coded
 
 
-def solve(spk, ctx, A, b, precision, solver):
+def solve(spk, ctx, A, b, precision, solver, precond=0):
     cfg = spk.spk_solver_cfg_default()
+    cfg.precond = precond
     cfg.reduction_factor = 1e-12
     cfg.max_iters = 2000
     cfg.precision = precision
@@ -143,17 +156,20 @@ def solve(spk, ctx, A, b, precision, solver):
     return x.cpu().numpy(), log, info
 
 
-@pytest.mark.parametrize("case", ["cg_fp64", "cg_mixed_fp32", "cg_mixed_bf16", "gmres_fp64", "cgs_fp64"])
+@pytest.mark.parametrize("case", ["cg_fp64", "cg_mixed_fp32", "cg_mixed_bf16", "gmres_fp64", "gmres_mixed_fp32",
+                                  "cgs_fp64", "pcg_fp64", "gmresjac_fp64"])
 def test_solves_identical_with_and_without_codes(spk, ctx, monkeypatch, case):
     solver_name, prec_name = case.split("_", 1)
-    solver = {"cg": spk.SOLVER_CG, "gmres": spk.SOLVER_GMRES, "cgs": spk.SOLVER_CGS}[solver_name]
+    solver = {"cg": spk.SOLVER_CG, "pcg": spk.SOLVER_CG, "gmres": spk.SOLVER_GMRES, "gmresjac": spk.SOLVER_GMRES,
+              "cgs": spk.SOLVER_CGS}[solver_name]
+    precond = spk.PRECOND_JACOBI if solver_name in ("pcg", "gmresjac") else spk.PRECOND_NONE
     prec = {"fp64": spk.PREC_FP64, "mixed_fp32": spk.PREC_MIXED_FP32, "mixed_bf16": spk.PREC_MIXED_BF16}[prec_name]
-    A = inputs.stencil7(30, 3) if solver_name == "cg" else inputs.stencil7_ns(30, 3)
+    A = inputs.stencil7(30, 3) if solver_name in ("cg", "pcg") else inputs.stencil7_ns(30, 3)
     b = inputs.vec(A.n_rows, 3, 2)
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,codes=0")
-    x0, l0, _ = solve(spk, ctx, A, b, prec, solver)
+    x0, l0, _ = solve(spk, ctx, A, b, prec, solver, precond)
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
-    x1, l1, i1 = solve(spk, ctx, A, b, prec, solver)
+    x1, l1, i1 = solve(spk, ctx, A, b, prec, solver, precond)
     assert i1["col_codes"] == 1
     assert l0.iterations == l1.iterations and l0.outer_iterations == l1.outer_iterations
     assert np.array_equal(x0, x1)
