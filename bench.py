@@ -97,6 +97,17 @@ def host_info():
     return info
 
 
+def index_bytes(info, n, nnz, sp):
+    """Index bytes one row-tile product reads: the column index (or, with
+    column codes, one byte per entry plus the 2 KiB offset table) and the row
+    pointers (or, when packed, an int64 per 256-row tile and a uint16 per
+    row).  sp: row-pointer width of the caller's CSR."""
+    cc = int(info.get("col_codes") or 0)
+    cols = nnz * 1 + 2048 if cc & 1 else nnz * 4
+    rows = ((n + 255) // 256 + 1) * 8 + 2 * n if cc & 2 else (n + 1) * sp
+    return cols + rows
+
+
 def measured_traffic(args, N, tiling=None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-kernel scaled), or None when
@@ -209,14 +220,14 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     value = n * iters / wall
 
-    # index bytes per entry: the int32 column, or the one-byte column code
-    # (plus its 2 KiB offset table) when the plan derived codes
-    si, table = (1, 2048) if info.get("col_codes") else (4, 0)
+    # index bytes: int32 columns and row pointers, or the plan's column codes
+    # and packed row pointers
+    idx = index_bytes(info, n, nnz, 4)
     if args.precision == "fp64":
-        bytes_spmv = nnz * (8 + si) + table + (n + 1) * 4 + 2 * n * 8
+        bytes_spmv = nnz * 8 + idx + 2 * n * 8
     else:   # inner SpMV: FP32/BF16 values, int32 columns, FP32 vectors
         vb = 4 if args.precision == "mixed_fp32" else 2
-        bytes_spmv = nnz * (vb + si) + table + (n + 1) * 4 + 2 * n * 4
+        bytes_spmv = nnz * vb + idx + 2 * n * 4
     avg_ms = kms / klaunch if klaunch else None
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     last = logs[-1]
@@ -275,7 +286,7 @@ def main():
     derived = {"nnz_per_s": nnz * spmvs / wall, "gflop_per_s": 2.0 * nnz * spmvs / wall / 1e9}
     if not (cgs or gm) and last.iterations > 0:
         sv, sx = (8, 8) if args.precision == "fp64" else ((4 if args.precision == "mixed_fp32" else 2), 4)
-        mat = nnz * (sv + si) + table + (n + 1) * 4
+        mat = nnz * sv + idx
         floor_b, moved_b = mat + 7 * n * sx, mat + 10 * n * sx
         t_it = last.elapsed_ms * 1e-3 / last.iterations
         derived["iteration"] = {
@@ -388,10 +399,9 @@ def spmv_mode(args):
     kms, cnt = spk.spk_plan_kernel_stats(pl)
     spk.spk_free(pl)
     spk.spk_finalize(ctx)
-    # CSR tiles read the derived row pointer for COO too: (n+1) int32; one
-    # byte per entry (and a 2 KiB table) in place of the column with codes
-    si, table = (1, 2048) if info.get("col_codes") else (4, 0)
-    bytes_spmv = nnz * (vb + si) + table + (n + 1) * 4 + 2 * n * vb
+    # CSR tiles read the derived row pointer for COO too: (n+1) int32 (or the
+    # packed form); column codes in place of the columns when derived
+    bytes_spmv = nnz * vb + index_bytes(info, n, nnz, 4) + 2 * n * vb
     avg_ms = kms / cnt if cnt else None
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     out = {
@@ -490,8 +500,7 @@ def large(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     spk.spk_finalize(ctx)
-    si, table = (1, 2048) if info.get("col_codes") else (4, 0)
-    bytes_spmv = nnz * (4 + si) + table + (n + 1) * 8 + 2 * n * 4
+    bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 8) + 2 * n * 4
     avg = kms / kl if kl else None
     achieved = bytes_spmv / (avg * 1e-3) / 1e9 if avg else None
     out = {

@@ -170,9 +170,11 @@ typedef struct {
     int32_t exec_mode;         /* resolved spk_exec_mode */
     int32_t chunk_iters;       /* resolved chunk size */
     int32_t tuned;             /* 1 = chosen by timing candidates, 0 = heuristic/cached */
-    int32_t col_codes;         /* 1 = the row-tile SpMV reads one byte per entry naming its
-                                  column offset from the row in a table of at most 256
-                                  offsets derived at plan time, in place of col_idx */
+    int32_t col_codes;         /* bit 0: the row-tile SpMV reads one byte per entry naming
+                                  its column offset from the row in a table of at most 256
+                                  offsets derived at plan time, in place of col_idx;
+                                  bit 1: it also reads packed row pointers (an int64 per
+                                  256-row tile, a uint16 offset per row) in place of row_ptr */
     double spmv_ms;            /* measured time of the chosen SpMV (0 if not tuned) */
 } spk_plan_info;
 

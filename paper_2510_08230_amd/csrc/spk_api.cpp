@@ -378,7 +378,7 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN
     pl->info.lanes = 1 << pl->tune.lanes_log2;
     pl->info.grid = pl->tune.grid;
     pl->info.xcd_remap = pl->tune.xcd_remap;
-    pl->info.col_codes = pl->tune.kind == 0 && pl->tune.codes && A.codes;
+    pl->info.col_codes = (pl->tune.kind == 0 && pl->tune.codes && A.codes) ? (A.rowpack ? 3 : 1) : 0;
     return SPK_OK;
 }
 
@@ -388,7 +388,10 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN
 // (below that the plan-time build and its read-back cost more than a solve
 // saves: 3 bytes per entry per product).  SPK_COL_CODES=0 turns them off,
 // SPK_COL_CODES=1 builds them at any size.  A pattern without codes, or a
-// failed allocation, leaves the plain indices in use.
+// failed allocation, leaves the plain indices in use.  With the codes come
+// packed row pointers (per tile an int64 base, per row a uint16 offset:
+// 2 bytes per row instead of 4 or 8) unless a row starts 65536 or more
+// entries into its tile; SPK_ROW_PACK=0 keeps the plain row pointers.
 constexpr int64_t kCodeMinNnz = int64_t(1) << 22;
 
 spk_status build_codes(spk_plan pl) {
@@ -398,8 +401,8 @@ spk_status build_codes(spk_plan pl) {
     if ((env && std::strcmp(env, "0") == 0) || A.nnz == 0 || A.n_rows == 0 || !stream_ok(A)) return SPK_OK;
     if (!(env && std::strcmp(env, "1") == 0) && A.nnz < kCodeMinNnz) return SPK_OK;
     void *tab = nullptr, *buf = nullptr;
-    const size_t bytes = sizeof(int64_t) * spk::kCodeDict + ((static_cast<size_t>(A.nnz) + 15) & ~size_t(15));
-    if (ctx->dpool.get(sizeof(long long) * spk::kCodeSlots + 2 * sizeof(unsigned), &tab) != hipSuccess)
+    const size_t bytes = spk::code_buffer_bytes(A.n_rows, A.nnz);
+    if (ctx->dpool.get(sizeof(long long) * spk::kCodeSlots + 4 * sizeof(unsigned), &tab) != hipSuccess)
         return SPK_OK;
     if (ctx->dpool.get(bytes, &buf) != hipSuccess) {   // no room for codes: plain indices
         ctx->dpool.put(tab);
@@ -407,7 +410,7 @@ spk_status build_codes(spk_plan pl) {
     }
     long long *table = static_cast<long long *>(tab);
     unsigned *words = reinterpret_cast<unsigned *>(table + spk::kCodeSlots);
-    unsigned h[2] = {0, 0};
+    unsigned h[3] = {0, 0, 0};
     // a sample of the tiles first (every 8th and the last: structured
     // patterns repeat their offsets); if an entry's offset was missed, all
     // tiles.  Two waves of workgroups per CU for the latency-bound walks.
@@ -430,6 +433,9 @@ spk_status build_codes(spk_plan pl) {
     }
     pl->codes_buf = buf;
     A.codes = static_cast<const char *>(buf) + sizeof(int64_t) * spk::kCodeDict;
+    const char *pack = std::getenv("SPK_ROW_PACK");
+    if (h[2] == 0 && !(pack && std::strcmp(pack, "0") == 0))
+        A.rowpack = static_cast<const char *>(A.codes) + spk::code_bytes(A.nnz);
     return SPK_OK;
 }
 

@@ -84,6 +84,10 @@ struct TileIter {
     }
 };
 
+// Packed row pointers (tag type of the row-pointer argument): per tile an
+// int64 first entry, then per row a uint16 offset from it.
+struct RowPack {};
+
 // Bounds of one row tile: its first row, its entry range [s, e) and this
 // thread's row range [a, b) (empty past the last row).
 template <typename P>
@@ -100,6 +104,25 @@ struct TileMeta {
         if (row < r1) {
             a = rp[row];
             b = rp[row + 1];
+        }
+    }
+};
+
+template <>
+struct TileMeta<RowPack> {
+    int64_t r0, s, e, a, b;
+    __device__ __forceinline__ void load(const RowPack *__restrict__ rp, int64_t n, int64_t tile) {
+        const int64_t *tb = reinterpret_cast<const int64_t *>(rp);
+        const uint16_t *ro = reinterpret_cast<const uint16_t *>(tb + (n + kTileRows - 1) / kTileRows + 1);
+        r0 = tile * kTileRows;
+        const int64_t r1 = r0 + kTileRows < n ? r0 + kTileRows : n;
+        s = tb[tile];
+        e = tb[tile + 1];
+        const int64_t row = r0 + threadIdx.x;
+        a = b = 0;
+        if (row < r1) {
+            a = s + ro[row];
+            b = row + 1 < r1 ? s + ro[row + 1] : e;
         }
     }
 };

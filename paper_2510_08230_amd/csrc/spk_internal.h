@@ -86,10 +86,23 @@ struct CsrDev {
     // column offset from its row, c - i, in a table of kCodeDict int64 offsets
     // stored in the kCodeDict * 8 bytes just before the codes.
     const void *codes = nullptr;
+    // Optional packed row pointers (null when absent; only with codes): the
+    // int64 first entry of every 256-row tile (tiles + 1 values), followed
+    // directly by one uint16 per row, its first entry less its tile's.
+    const void *rowpack = nullptr;
 };
 
 constexpr int kCodeDict = 256;    // distinct column offsets a code table holds
 constexpr int kCodeSlots = 1024;  // plan-time hash table of distinct offsets (power of two)
+
+// Byte sizes of the plan's code buffer: the offset table, the codes (rounded
+// to 16 bytes), then the packed row pointers (tiles + 1 int64, n uint16).
+inline size_t code_bytes(int64_t nnz) { return (static_cast<size_t>(nnz) + 15) & ~size_t(15); }
+inline size_t code_buffer_bytes(int64_t n_rows, int64_t nnz) {
+    const size_t tiles = static_cast<size_t>((n_rows + kTileRows - 1) / kTileRows);
+    return sizeof(int64_t) * kCodeDict + code_bytes(nnz) + sizeof(int64_t) * (tiles + 1) +
+           ((sizeof(uint16_t) * static_cast<size_t>(n_rows) + 15) & ~size_t(15));
+}
 
 // Validation flag bits (set by the GPU check, order resolved on the host).
 enum : unsigned { VFLAG_BAD_FIRST = 1u, VFLAG_DECREASING = 2u, VFLAG_BAD_LAST = 4u, VFLAG_BAD_COLUMN = 8u,

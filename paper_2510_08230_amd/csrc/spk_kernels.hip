@@ -669,7 +669,7 @@ __device__ __forceinline__ unsigned code_hash(long long d, int bits) {
 
 __global__ __launch_bounds__(kBlock) void k_code_clear(long long *table, unsigned *words) {
     for (int i = threadIdx.x; i < kCodeSlots; i += kBlock) table[i] = kCodeEmpty;
-    if (threadIdx.x < 2) words[threadIdx.x] = 0;
+    if (threadIdx.x < 4) words[threadIdx.x] = 0;
 }
 
 // Inserts d into an open-addressing set of 2^bits slots; returns 1 if this
@@ -863,6 +863,28 @@ __global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, const P 
     if (bad) atomicOr(&words[1], 2u);
 }
 
+// Packed row pointers (with the codes only): tb[t] = the first entry of tile
+// t (t <= T, tb[T] = nnz), ro[i] = row i's first entry less its tile's; an
+// offset past 65535 sets words[2] and the plan keeps the plain row pointers.
+template <typename P>
+__global__ __launch_bounds__(kBlock) void k_rowpack(int64_t n_rows, const P *__restrict__ rp, int64_t *tb,
+                                                    uint16_t *ro, unsigned *words) {
+    if (words[1] != 0) return;   // no codes: uniform
+    const int64_t T = (n_rows + kTileRows - 1) / kTileRows;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    unsigned bad = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n_rows; i += stride) {
+        const int64_t r0 = (i / kTileRows) * kTileRows;
+        const int64_t base = static_cast<int64_t>(rp[r0]);
+        const int64_t off = static_cast<int64_t>(rp[i]) - base;
+        if (off > 65535) bad = 1;
+        ro[i] = static_cast<uint16_t>(off);
+        if (i == r0) tb[i / kTileRows] = base;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) tb[T] = static_cast<int64_t>(rp[n_rows]);
+    if (bad) atomicOr(&words[2], 1u);
+}
+
 // COO structure: row and column indices in range, rows non-decreasing.
 template <typename I>
 __global__ __launch_bounds__(kBlock) void k_coo_validate(int64_t n_rows, int64_t n_cols, int64_t nnz,
@@ -950,6 +972,7 @@ hipError_t launch_code_build(const CsrDev &A, int step, long long *table, unsign
                              int grid, hipStream_t s) {
     int64_t *dict = static_cast<int64_t *>(codes_base);
     uint8_t *codes = static_cast<uint8_t *>(codes_base) + kCodeDict * sizeof(int64_t);
+    int64_t *tb = reinterpret_cast<int64_t *>(codes + code_bytes(A.nnz));
     if (step < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_code_clear, dim3(1), dim3(kBlock), 0, s, table, words);
     if (A.n_rows == 0) return hipGetLastError();
@@ -961,6 +984,8 @@ hipError_t launch_code_build(const CsrDev &A, int step, long long *table, unsign
         hipLaunchKernelGGL(k_code_table, dim3(1), dim3(kBlock), 0, s, table, words, dict);
         hipLaunchKernelGGL((k_code_encode<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, ci, dict, codes,
                            words);
+        hipLaunchKernelGGL((k_rowpack<P>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, tb,
+                           reinterpret_cast<uint16_t *>(tb + (A.n_rows + kTileRows - 1) / kTileRows + 1), words);
         return hipGetLastError();
     });
 }

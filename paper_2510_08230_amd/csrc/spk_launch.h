@@ -14,9 +14,12 @@ hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipS
 // every step-th row tile (and the last) into table (kCodeSlots int64 words),
 // then, when there are at most kCodeDict of them, writes the ascending offset
 // table into the first kCodeDict * 8 bytes of codes_base and one code byte
-// per entry after it.  Afterwards words[0] = distinct offsets collected;
+// per entry after it, then (codes usable) the packed row pointers.  words
+// holds 4 unsigned; afterwards words[0] = distinct offsets collected;
 // words[1] = 0: codes usable, bit 0: more than kCodeDict offsets, bit 1: an
-// entry's offset was not collected (sampled collection incomplete).
+// entry's offset was not collected (sampled collection incomplete);
+// words[2] != 0: a row offset within its tile exceeds 65535 (no packing).
+// codes_base holds code_buffer_bytes(n_rows, nnz) bytes.
 hipError_t launch_code_build(const CsrDev &A, int step, long long *table, unsigned *words, void *codes_base,
                              int grid, hipStream_t s);
 // COO (idx_t 0 = int32, 1 = int64): flags gets VFLAG_BAD_FIRST for a row

@@ -4,7 +4,8 @@ from its row through a per-matrix table of at most 256 offsets).
 A coded product sums every row in the same order as the plain-index kernel,
 so its result must equal that kernel's bit for bit, on every value type,
 index type, ragged tail and tile size; solves with and without codes must
-give identical iterates.  The plan takes codes exactly when the pattern has
+give identical iterates, with packed row pointers (an int64 per 256-row
+tile and a uint16 offset per row) and without.  The plan takes codes exactly when the pattern has
 at most 256 distinct offsets c - i (checked at 256 and 257, and with an
 offset that occurs in one row only, which a sampled collection misses) and
 the matrix has 2^22 entries or more (SPK_COL_CODES=1, set here, builds them
@@ -93,16 +94,18 @@ def test_coded_product_equals_plain_indices(spk, ctx, monkeypatch, name, ptr, id
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,codes=0")
     y0, i0 = spmv(spk, ctx, M, x, A.n_rows, vt)
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
-    y1, i1 = spmv(spk, ctx, M, x, A.n_rows, vt)
-    assert i0["col_codes"] == 0 and i1["col_codes"] == 1
-    assert np.array_equal(y0, y1)
+    y1, i1 = spmv(spk, ctx, M, x, A.n_rows, vt)          # codes and packed row pointers
+    monkeypatch.setenv("SPK_ROW_PACK", "0")
+    y2, i2 = spmv(spk, ctx, M, x, A.n_rows, vt)          # codes, plain row pointers
+    assert i0["col_codes"] == 0 and i1["col_codes"] == 3 and i2["col_codes"] == 1
+    assert np.array_equal(y0, y1) and np.array_equal(y0, y2)
     if vt == torch.float64:
         xh = inputs.vec(A.n_cols, 7, 5)
         m = np.maximum(np.diff(A.row_ptr), 1)
         assert np.all(np.abs(y1 - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
 
 
-@pytest.mark.parametrize("k,coded", [(256, 1), (257, 0)])
+@pytest.mark.parametrize("k,coded", [(256, 3), (257, 0)])
 def test_codes_taken_up_to_256_offsets(spk, ctx, monkeypatch, k, coded):
     # offsets -128 .. k-129: rows hold up to k entries, so tiles exceed the LDS
     # stage and the product takes the direct-load path
@@ -117,6 +120,29 @@ def test_codes_taken_up_to_256_offsets(spk, ctx, monkeypatch, k, coded):
     assert np.array_equal(y, y0)
 
 
+def test_long_tile_keeps_plain_row_pointers(spk, ctx, monkeypatch):
+    # row 5 holds 70,000 duplicate entries on the diagonal (3 distinct offsets
+    # overall), so later rows of its tile start past 65535 entries in: codes
+    # but no packed row pointers
+    A = banded(600, [-1, 0, 1], 7, extra=None)
+    rows = [list(A.col[A.row_ptr[i]:A.row_ptr[i + 1]]) for i in range(A.n_rows)]
+    rows[5] = rows[5] + [5] * 70000
+    col = np.asarray([c for r in rows for c in r], np.int32)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    val = np.random.default_rng(8).uniform(-1.0, 1.0, col.size)
+    A = inputs.CSR(600, 600, rp, col, val)
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
+    M = dev_csr(spk, A)
+    xh = inputs.vec(A.n_cols, 9, 5)
+    y, info = spmv(spk, ctx, M, to_dev(xh), A.n_rows)
+    assert info["col_codes"] == 1
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,codes=0")
+    y0, _ = spmv(spk, ctx, M, to_dev(xh), A.n_rows)
+    assert np.array_equal(y, y0)
+    m = np.maximum(np.diff(A.row_ptr), 1)
+    assert np.all(np.abs(y - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
+
+
 def test_random_pattern_keeps_indices(spk, ctx):
     A = inputs.randsym(20000, 6)   # offsets spread over +-20000
     M = dev_csr(spk, A)
@@ -127,7 +153,7 @@ def test_random_pattern_keeps_indices(spk, ctx):
     assert np.all(np.abs(y - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
 
 
-@pytest.mark.parametrize("env,coded", [("0", 0), (None, 0), ("1", 1)])
+@pytest.mark.parametrize("env,coded", [("0", 0), (None, 0), ("1", 3)])
 def test_codes_by_environment_and_size(spk, ctx, monkeypatch, env, coded):
     A = inputs.stencil7(20, 0)   # 54,400 entries: below the default size for codes
     if env is None:
@@ -170,7 +196,7 @@ def test_solves_identical_with_and_without_codes(spk, ctx, monkeypatch, case):
     x0, l0, _ = solve(spk, ctx, A, b, prec, solver, precond)
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
     x1, l1, i1 = solve(spk, ctx, A, b, prec, solver, precond)
-    assert i1["col_codes"] == 1
+    assert i1["col_codes"] == 3
     assert l0.iterations == l1.iterations and l0.outer_iterations == l1.outer_iterations
     assert np.array_equal(x0, x1)
     assert l1.converged
