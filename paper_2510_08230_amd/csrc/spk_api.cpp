@@ -196,8 +196,11 @@ bool stream_ok(const CsrDev &A) {
 
 // bpc <= 0: as many workgroups per CU as the occupancy calculator allows;
 // otherwise bpc per CU (extra workgroups queue until a slot frees).
-SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap, int nt, int pf, int bpc) {
+SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap, int nt, int pf, int bpc,
+                   int codes = 0, int pack = 0) {
     SpmvTune t{kind, lanes_log2, 1, remap, nt, pf, 0};
+    t.codes = kind == 0 && codes && A.codes;
+    t.pack = t.codes && pack && A.rowpack;
     const int occ = spk::spmv_blocks_per_cu(A, t);
     const int use = (bpc <= 0) ? occ : std::min(bpc, 32);   // a forced count may oversubscribe
     t.bpc = use;
@@ -210,11 +213,7 @@ SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int r
 
 SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
-    if (mean <= 16.0 && stream_ok(A)) {
-        SpmvTune t = make_tune(ctx, A, 0, 0, 0, 0, 1, 0);
-        t.codes = A.codes != nullptr;
-        return t;
-    }
+    if (mean <= 16.0 && stream_ok(A)) return make_tune(ctx, A, 0, 0, 0, 0, 1, 0, 1, 1);
     int l2 = 0;
     while ((1 << l2) < mean && l2 < 6) ++l2;
     return make_tune(ctx, A, 1, l2, 1, 0, 0, 0);
@@ -284,23 +283,26 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
         if (per < 0.97 * best.ms) best = TuneResult{t, per};
     }
     if (A.codes && best.tune.kind == 0) {
-        // the same tiling on one-byte column codes (nnz (S_i - 1) fewer bytes
-        // per product); the plain indices must be 3% faster to be kept
-        SpmvTune t = best.tune;
-        t.codes = 1;
-        double per = 0.0;
-        SPK_HIP(ctx, time_one(t, &per));
-        if (!(best.ms < 0.97 * per)) best = TuneResult{t, per};
-        if (best.tune.codes) {
-            // the coded kernel holds fewer registers and less LDS: one more
-            // workgroup per CU can fit
-            SpmvTune t1 = make_tune(ctx, A, 0, 0, t.xcd_remap, t.nt, t.pf, t.bpc + 1);
-            t1.codes = 1;
-            if (t1.grid != t.grid) {
-                SPK_HIP(ctx, time_one(t1, &per));
-                if (per < 0.97 * best.ms) best = TuneResult{t1, per};
+        // the best tile order and cache policy on one-byte column codes, with
+        // packed row pointers (when built) and without, each at the coded
+        // kernel's own occupancy figure and one more workgroup per CU (in
+        // order of preference: fewer bytes first, a later candidate must be
+        // 3% faster); the plain indices must be 3% faster than the best coded
+        // candidate to be kept
+        const SpmvTune b = best.tune;
+        TuneResult coded{b, 1e30};
+        for (int pack : {1, 0}) {
+            if (pack && !A.rowpack) continue;
+            const SpmvTune t = make_tune(ctx, A, 0, 0, b.xcd_remap, b.nt, b.pf, 0, 1, pack);
+            const SpmvTune t1 = make_tune(ctx, A, 0, 0, b.xcd_remap, b.nt, b.pf, t.bpc + 1, 1, pack);
+            for (int k = 0; k < (t1.grid != t.grid ? 2 : 1); ++k) {
+                const SpmvTune &c = k ? t1 : t;
+                double per = 0.0;
+                SPK_HIP(ctx, time_one(c, &per));
+                if (per < 0.97 * coded.ms) coded = TuneResult{c, per};
             }
         }
+        if (!(best.ms < 0.97 * coded.ms)) best = coded;
     }
     ctx->tune_cache[key] = best;
     *out = best;
@@ -309,13 +311,13 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
 
 // SPK_SPMV_KERNEL forces a tiling (tests and sweeps use it): "stream" or
 // "vector:<lanes>", optionally followed by ",key=value" with keys remap, nt,
-// pf, bpc, codes (e.g. "stream,pf=1,nt=1,remap=0,bpc=4,codes=0"; codes
-// defaults to 1 when the matrix has column codes).
+// pf, bpc, codes, pack (e.g. "stream,pf=1,nt=1,remap=0,bpc=4,codes=0";
+// codes and pack default to 1 when the matrix has codes / packed rows).
 bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     const char *env = std::getenv("SPK_SPMV_KERNEL");
     if (!env || !*env) return false;
     std::string v(env);
-    int kind = -1, l2 = 0, remap = -1, nt = 0, pf = 1, bpc = 0, codes = 1;
+    int kind = -1, l2 = 0, remap = -1, nt = 0, pf = 1, bpc = 0, codes = 1, pack = 1;
     size_t pos = 0;
     bool first = true;
     while (pos <= v.size()) {
@@ -341,6 +343,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
                 else if (k == "pf") pf = val;
                 else if (k == "bpc") bpc = val;
                 else if (k == "codes") codes = val;
+                else if (k == "pack") pack = val;
             }
         }
         pos = comma + 1;
@@ -348,8 +351,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     if (kind < 0) return false;
     if (kind == 0 && !stream_ok(A)) kind = 1;
     if (remap < 0) remap = 1;
-    *t = make_tune(ctx, A, kind, l2, remap, nt, pf, bpc);
-    t->codes = kind == 0 && codes != 0 && A.codes != nullptr;
+    *t = make_tune(ctx, A, kind, l2, remap, nt, pf, bpc, codes, pack);
     return true;
 }
 
@@ -378,7 +380,8 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN
     pl->info.lanes = 1 << pl->tune.lanes_log2;
     pl->info.grid = pl->tune.grid;
     pl->info.xcd_remap = pl->tune.xcd_remap;
-    pl->info.col_codes = (pl->tune.kind == 0 && pl->tune.codes && A.codes) ? (A.rowpack ? 3 : 1) : 0;
+    pl->info.col_codes =
+        (pl->tune.kind == 0 && pl->tune.codes && A.codes) ? ((pl->tune.pack && A.rowpack) ? 3 : 1) : 0;
     return SPK_OK;
 }
 

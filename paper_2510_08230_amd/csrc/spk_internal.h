@@ -75,6 +75,7 @@ struct SpmvTune {
     int pf;          // LDS tiles: 1 = the next tile's row pointers load while this tile's entries stream in
     int bpc;         // workgroups per CU the grid was sized for
     int codes = 0;   // LDS tiles: 1 = read the matrix's one-byte column codes (CsrDev::codes)
+    int pack = 0;    // with codes: 1 = read the packed row pointers (CsrDev::rowpack)
 };
 
 // Device CSR view with runtime-typed arrays.

@@ -1200,7 +1200,24 @@ int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t) {
         lo = blocks < lo ? blocks : lo;
     };
     const bool i64 = A.idx_t != 0;
-    if (A.val_t == 0) {
+    if (t.kind == 0 && t.codes && A.codes) {   // the coded instances the launch will use
+        const bool pack = t.pack && A.rowpack;
+        if (A.val_t == 0) {
+            if (pack) {
+                q(k_spmv_stream<double, RowPack, Code8, double, double, EpiPq<double>>);
+                q(k_spmv_stream<double, RowPack, Code8, double, double, EpiPlain<double>>);
+            } else {
+                q(k_spmv_stream<double, int64_t, Code8, double, double, EpiPq<double>>);
+                q(k_spmv_stream<double, int64_t, Code8, double, double, EpiPlain<double>>);
+            }
+        } else if (pack) {
+            q(k_spmv_stream<float, RowPack, Code8, float, float, EpiPq<float>>);
+            q(k_spmv_stream<float, RowPack, Code8, float, float, EpiPlain<float>>);
+        } else {
+            q(k_spmv_stream<float, int64_t, Code8, float, float, EpiPq<float>>);
+            q(k_spmv_stream<float, int64_t, Code8, float, float, EpiPlain<float>>);
+        }
+    } else if (A.val_t == 0) {
         if (t.kind == 0) {
             if (i64) {
                 q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>>);

@@ -161,7 +161,7 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
         using I = pointee_t<decltype(ci)>;
         const V *va = static_cast<const V *>(A.va);
         const dim3 grid(t.grid), block(kBlock);
-        if (t.kind == 0 && t.codes && A.codes && A.rowpack) {
+        if (t.kind == 0 && t.codes && A.codes && t.pack && A.rowpack) {
             hipLaunchKernelGGL((k_spmv_stream<V, RowPack, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz,
                                static_cast<const RowPack *>(A.rowpack), static_cast<const Code8 *>(A.codes), va, x,
                                t.xcd_remap, t.nt, t.pf, epi);

@@ -95,10 +95,13 @@ def test_coded_product_equals_plain_indices(spk, ctx, monkeypatch, name, ptr, id
     y0, i0 = spmv(spk, ctx, M, x, A.n_rows, vt)
     monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
     y1, i1 = spmv(spk, ctx, M, x, A.n_rows, vt)          # codes and packed row pointers
-    monkeypatch.setenv("SPK_ROW_PACK", "0")
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,pack=0")
     y2, i2 = spmv(spk, ctx, M, x, A.n_rows, vt)          # codes, plain row pointers
-    assert i0["col_codes"] == 0 and i1["col_codes"] == 3 and i2["col_codes"] == 1
-    assert np.array_equal(y0, y1) and np.array_equal(y0, y2)
+    monkeypatch.setenv("SPK_ROW_PACK", "0")
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
+    y3, i3 = spmv(spk, ctx, M, x, A.n_rows, vt)          # no packed rows built
+    assert i0["col_codes"] == 0 and i1["col_codes"] == 3 and i2["col_codes"] == 1 and i3["col_codes"] == 1
+    assert np.array_equal(y0, y1) and np.array_equal(y0, y2) and np.array_equal(y0, y3)
     if vt == torch.float64:
         xh = inputs.vec(A.n_cols, 7, 5)
         m = np.maximum(np.diff(A.row_ptr), 1)
