@@ -146,6 +146,29 @@ def test_long_tile_keeps_plain_row_pointers(spk, ctx, monkeypatch):
     assert np.all(np.abs(y - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
 
 
+@pytest.mark.parametrize("idx", ["i32", "i64"])
+def test_coo_plan_with_codes_equals_plain_csr(spk, ctx, monkeypatch, idx):
+    # a COO plan runs the CSR tiles over its derived row pointer, so it takes
+    # codes and packed rows too
+    A = MATS["band9_empty_rows"]()
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+    tidx = {"i32": torch.int32, "i64": torch.int64}[idx]
+    C = spk.CooMatrix(torch.from_numpy(rows).to(tidx).to(DEV),
+                      torch.from_numpy(A.col.astype(np.int64)).to(tidx).to(DEV), to_dev(A.val), A.n_rows, A.n_cols)
+    xh = inputs.vec(A.n_cols, 10, 5)
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream")
+    pl = spk.spk_plan_spmv_coo(ctx, C)
+    info = spk.spk_plan_get_info(pl)
+    y = torch.full((A.n_rows,), float("nan"), dtype=torch.float64, device=DEV)
+    spk.spk_execute_spmv(pl, to_dev(xh), y)
+    torch.cuda.synchronize()
+    spk.spk_free(pl)
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,codes=0")
+    y0, _ = spmv(spk, ctx, dev_csr(spk, A), to_dev(xh), A.n_rows)
+    assert info["col_codes"] == 3
+    assert np.array_equal(y.cpu().numpy(), y0)
+
+
 def test_random_pattern_keeps_indices(spk, ctx):
     A = inputs.randsym(20000, 6)   # offsets spread over +-20000
     M = dev_csr(spk, A)
