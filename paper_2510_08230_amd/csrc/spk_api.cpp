@@ -416,7 +416,8 @@ spk_status build_codes(spk_plan pl) {
     unsigned h[3] = {0, 0, 0};
     // a sample of the tiles first (every 8th and the last: structured
     // patterns repeat their offsets); if an entry's offset was missed, all
-    // tiles.  Two waves of workgroups per CU for the latency-bound walks.
+    // tiles.  Eight workgroups per CU (the most that fit) for the
+    // latency-bound walks.
     const int grid = ctx->num_cu * 8;
     bool ok = true;
     for (int step : {8, 1}) {
