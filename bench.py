@@ -29,6 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HIP events bracket every PROFILE_EVERY-th launch of the dominant SpMV during
+# the timed steps (every launch cost 2.8% of a C2 step; one in four, a
+# quarter of that)
+PROFILE_EVERY = 4
 
 
 def parse():
@@ -194,7 +198,7 @@ def main():
     def step(profile):
         pl = spk.spk_plan_solve(ctx, M, cfg)
         if profile:
-            spk.spk_plan_set_profiling(pl, True)
+            spk.spk_plan_set_profiling(pl, PROFILE_EVERY)
         x.zero_()
         log = spk.spk_execute_solve(pl, b, x)
         stats = spk.spk_plan_kernel_stats(pl)
@@ -274,7 +278,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": spmv_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
-                     "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": klaunch},
+                     "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": klaunch, "timed_every": PROFILE_EVERY},
     }
     # Rates the paper and the roofline discussion also use: nonzeros and GFLOP/s
     # (2 nnz flops per SpMV) over the timed steps, and for CG the whole
@@ -388,7 +392,7 @@ def spmv_mode(args):
     info = spk.spk_plan_get_info(pl)
     for _ in range(max(args.warmup, 1)):
         spk.spk_execute_spmv(pl, x, y)
-    spk.spk_plan_set_profiling(pl, not args.no_profile)
+    spk.spk_plan_set_profiling(pl, 0 if args.no_profile else PROFILE_EVERY)
     steps = max(args.steps, 1) * 10
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -418,7 +422,7 @@ def spmv_mode(args):
                    "kernel_gflops": 2.0 * nnz / (avg_ms * 1e-3) / 1e9 if avg_ms else None},
         "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPlain>", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                     "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": cnt},
+                     "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_ms, "launches": cnt, "timed_every": PROFILE_EVERY},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -479,7 +483,7 @@ def large(args):
     def step(profile):
         pl = spk.spk_plan_solve(ctx, M, cfg)
         if profile:
-            spk.spk_plan_set_profiling(pl, True)
+            spk.spk_plan_set_profiling(pl, PROFILE_EVERY)
         x.zero_()
         log = spk.spk_execute_solve(pl, b, x)
         st = spk.spk_plan_kernel_stats(pl)
@@ -516,7 +520,7 @@ def large(args):
         "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq<float>> (inner q = A32 p fused with p.q)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": None, "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg, "launches": kl},
+                     "traffic": None, "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg, "launches": kl, "timed_every": PROFILE_EVERY},
     }
     print(json.dumps(out), flush=True)
 

@@ -254,9 +254,11 @@ spk_status spk_plan_history(spk_plan plan, double *out, int64_t cap, int64_t *co
 /* Report the plan's tuning decisions. */
 spk_status spk_plan_get_info(spk_plan plan, spk_plan_info *info);
 
-/* Per-kernel timing: when on, every launch of the plan's dominant SpMV
- * kernel is bracketed by HIP events on the context stream; stats return the
- * summed device time (ms) and launch count since the last reset. */
+/* Per-kernel timing: with on = k >= 1, every k-th launch of the plan's
+ * dominant SpMV kernel (launches 0, k, 2k, ... of each solve, counting
+ * only launches that did work) is bracketed by HIP events on the context
+ * stream; on <= 0 turns timing off.  Stats return the summed device time
+ * (ms) and the count of timed launches since the last reset. */
 spk_status spk_plan_set_profiling(spk_plan plan, int32_t on);
 spk_status spk_plan_kernel_stats(spk_plan plan, double *total_ms, int64_t *launches);
 

@@ -97,7 +97,8 @@ struct spk_plan_s {
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     SolveState *st_in = nullptr, *h_st_in = nullptr;
     double *out_dev = nullptr, *h_out = nullptr;   // refinement norms (device / pinned)
-    int profiling = 0;
+    int profiling = 0;                   // time every profiling-th dominant SpMV launch (0 = off)
+    int64_t prof_seq = 0;                // dominant SpMV launches since the last collect
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     size_t ev_used = 0;
     double prof_ms = 0.0;
@@ -447,6 +448,7 @@ spk_status build_codes(spk_plan pl) {
 spk_status prof_begin(spk_plan pl, hipEvent_t *end_ev) {
     *end_ev = nullptr;
     if (!pl->profiling) return SPK_OK;
+    if (pl->prof_seq++ % pl->profiling != 0) return SPK_OK;   // not sampled
     if (pl->ev_used == pl->ev_pool.size()) {
         hipEvent_t a, b;
         SPK_HIP(pl->ctx, hipEventCreate(&a));
@@ -464,9 +466,13 @@ spk_status prof_end(spk_plan pl, hipEvent_t end_ev) {
     return SPK_OK;
 }
 
-// Accumulate the first `useful` recorded launches (stream already synchronised).
-spk_status prof_collect(spk_plan pl, int64_t useful) {
-    const size_t n = std::min<size_t>(pl->ev_used, static_cast<size_t>(std::max<int64_t>(useful, 0)));
+// Accumulate the recorded launches among the first `useful` launches (stream
+// already synchronised): launches 0, k, 2k, ... were recorded, k = profiling.
+// A solve restarts the count; SpMV plans count across calls (keep_seq).
+spk_status prof_collect(spk_plan pl, int64_t useful, bool keep_seq = false) {
+    const int64_t k = std::max(pl->profiling, 1);
+    const int64_t sampled = (std::max<int64_t>(useful, 0) + k - 1) / k;
+    const size_t n = std::min<size_t>(pl->ev_used, static_cast<size_t>(sampled));
     for (size_t i = 0; i < n; ++i) {
         float ms = 0.f;
         SPK_HIP(pl->ctx, hipEventElapsedTime(&ms, pl->ev_pool[i].first, pl->ev_pool[i].second));
@@ -474,6 +480,7 @@ spk_status prof_collect(spk_plan pl, int64_t useful) {
         pl->prof_count += 1;
     }
     pl->ev_used = 0;
+    if (!keep_seq) pl->prof_seq = 0;
     return SPK_OK;
 }
 
@@ -1125,7 +1132,7 @@ spk_status spk_execute_spmv(spk_plan pl, const void *x, void *y) {
     s = prof_end(pl, e);
     if (s != SPK_OK) return s;
     SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return prof_collect(pl, pl->ev_used);
+    return prof_collect(pl, pl->ev_used, true);   // this call's launch, if it was timed
 }
 
 // Restarted GMRES: each cycle (restart residual, krylov_dim Arnoldi steps,
@@ -1366,10 +1373,11 @@ spk_status spk_plan_get_info(spk_plan pl, spk_plan_info *info) {
 
 spk_status spk_plan_set_profiling(spk_plan pl, int32_t on) {
     if (!pl) return SPK_ERR_INVALID_ARG;
-    pl->profiling = on ? 1 : 0;
+    pl->profiling = on > 0 ? on : 0;
     pl->prof_ms = 0.0;
     pl->prof_count = 0;
     pl->ev_used = 0;
+    pl->prof_seq = 0;
     return SPK_OK;
 }
 

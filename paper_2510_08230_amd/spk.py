@@ -300,8 +300,9 @@ def spk_plan_get_info(plan: Plan) -> dict:
     return info.as_dict()
 
 
-def spk_plan_set_profiling(plan: Plan, on: bool):
-    _check(_lib.spk_plan_set_profiling(plan.handle, 1 if on else 0), plan.ctx)
+def spk_plan_set_profiling(plan: Plan, on):
+    """on: False/0 = off, True/1 = time every launch, k > 1 = every k-th."""
+    _check(_lib.spk_plan_set_profiling(plan.handle, int(on)), plan.ctx)
 
 
 def spk_plan_kernel_stats(plan: Plan):
