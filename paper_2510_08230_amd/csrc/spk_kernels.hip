@@ -654,8 +654,8 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
 //   k_code_table: one workgroup ranks the table's offsets into an ascending
 //     kCodeDict-entry table (unused entries 0), unless the collection
 //     overflowed.
-//   k_code_encode: every entry's offset is found by binary search in that
-//     table and its position stored as one byte; an offset missing from the
+//   k_code_encode: every entry's offset is looked up (an LDS hash map built
+//     from that table) and its position stored as one byte; an offset missing from the
 //     table (possible after a sampled collection) sets the error word, and
 //     the plan collects again over every tile, or keeps the plain indices.
 // The three launch back to back; the host reads the words once at the end.
@@ -816,27 +816,47 @@ __global__ __launch_bounds__(kBlock) void k_code_table(const long long *__restri
     for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = out[i];
 }
 
-// Position of d in the ascending table t[0, n), or -1.
-__device__ __forceinline__ int code_find(const int64_t *t, int n, int64_t d) {
-    int lo = 0, hi = n;   // t[lo] <= d < t[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (t[mid] <= d) lo = mid;
-        else hi = mid;
+// Code of offset d from the LDS hash map (keys / codes) the encode pass
+// builds from the sorted table, or -1 when d is not in it.  One probe in the
+// usual case (a binary search over the table took five times longer).
+__device__ __forceinline__ int code_lookup(const long long *key, const unsigned char *code, long long d) {
+    const unsigned mask = kCodeLdsSlots - 1u;
+    unsigned h = code_hash(d, 9);
+    for (unsigned probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
+        const long long v = key[h];
+        if (v == d) return code[h];
+        if (v == kCodeEmpty) return -1;
     }
-    return t[lo] == d ? lo : -1;
+    return -1;
 }
 
 template <typename P, typename I>
 __global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const int64_t *__restrict__ dict,
                                                         uint8_t *__restrict__ codes, unsigned *words) {
-    __shared__ int64_t tab[kCodeDict];
+    __shared__ long long key[kCodeLdsSlots];
+    __shared__ unsigned char code[kCodeLdsSlots];
     __shared__ unsigned short row_of[kStreamCap];
     const unsigned nd = words[0];
     if (words[1] != 0 || nd < 1 || nd > static_cast<unsigned>(kCodeDict)) return;   // no codes: uniform
     const int ndict = static_cast<int>(nd);
-    for (int i = threadIdx.x; i < kCodeDict; i += kBlock) tab[i] = dict[i];
+    // offset -> code map: the ndict distinct table entries each claim a slot
+    for (int i = threadIdx.x; i < kCodeLdsSlots; i += kBlock) key[i] = kCodeEmpty;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ndict; i += kBlock) {
+        const long long d = dict[i];
+        const unsigned mask = kCodeLdsSlots - 1u;
+        unsigned h = code_hash(d, 9);
+        for (unsigned probe = 0; probe <= mask; ++probe, h = (h + 1u) & mask) {
+            const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(key + h),
+                                                     static_cast<unsigned long long>(kCodeEmpty),
+                                                     static_cast<unsigned long long>(d));
+            if (static_cast<long long>(old) == kCodeEmpty) {
+                code[h] = static_cast<unsigned char>(i);
+                break;
+            }
+        }
+    }
     __syncthreads();
     unsigned bad = 0;
     const int64_t T = (n_rows + kTileRows - 1) / kTileRows;
@@ -847,13 +867,13 @@ __global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, const P 
 #pragma unroll
             for (int j = 0; j < kCodeBatch; ++j) {
                 if (!t.valid(j)) continue;
-                const int c = code_find(tab, ndict, t.d[j]);
+                const int c = code_lookup(key, code, t.d[j]);
                 if (c >= 0) codes[t.entry(j)] = static_cast<uint8_t>(c);
                 else bad = 1;
             }
         } else {
             for (int64_t k = t.a; k < t.b; ++k) {
-                const int c = code_find(tab, ndict, static_cast<int64_t>(ci[k]) - t.row);
+                const int c = code_lookup(key, code, static_cast<long long>(ci[k]) - t.row);
                 if (c >= 0) codes[k] = static_cast<uint8_t>(c);
                 else bad = 1;
             }
