@@ -8,6 +8,10 @@
 //   * lanes-per-row vector kernel: 2^k lanes of a wave64 share a row.
 // Both hand each row sum to an epilogue object (row(i, s), finish()), which is
 // where the solvers fuse their elementwise work and dot-product partials.
+// The LDS tiles also read a plan's compressed index arrays: one-byte column
+// codes (I = Code8: column = row + offset table[code], the table in LDS) and
+// packed row pointers (P = RowPack: an int64 per tile, a uint16 per row);
+// row sums keep their order, so the products equal the plain ones bit for bit.
 #pragma once
 
 #include "spk_device.h"
