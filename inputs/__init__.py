@@ -119,6 +119,8 @@ def _get():
         lib.gen_randsym.argtypes = [i64, u64, f64, i32, i32, vp, vp, vp]
         lib.gen_stencil7_row.restype = i32
         lib.gen_stencil7_row.argtypes = [i64, u64, f64, i32, i64, vp, vp]
+        lib.gen_stencil7_block.restype = i64
+        lib.gen_stencil7_block.argtypes = [i64, u64, f64, i32, i64, i64, vp, vp, vp]
         lib.gen_rhs.restype = None
         lib.gen_rhs.argtypes = [i64, u64, vp]
         lib.gen_vec.restype = None
@@ -208,6 +210,24 @@ def randsym(n: int, seed: int, delta: float = 1.0, deg: int = 3, f32x: bool = Fa
     return CSR(n, n, rp, col[:nnz].copy(), val[:nnz].copy())
 
 
+def randsym_many(specs, threads: int = 0):
+    """randsym(n, seed) for every (n, seed) in specs, built on several host
+    threads (each build is one C call); returns the CSR list in order."""
+    from concurrent.futures import ThreadPoolExecutor
+    workers = threads if threads > 0 else min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda sp: randsym(int(sp[0]), int(sp[1])), specs))
+
+
+def serving_mix(count: int = 256, seed: int = 4, lo: float = 1e3, hi: float = 1e6, threads: int = 0):
+    """The serving workload: count randsym instances with log-uniform sizes in
+    [lo, hi] and per-instance seeds; returns (matrices, right-hand sides)."""
+    sizes, seeds = instances(count, seed, lo, hi)
+    specs = [(int(n), int(sd) % (1 << 31)) for n, sd in zip(sizes, seeds)]
+    mats = randsym_many(specs, threads)
+    return mats, [rhs(n, sd) for n, sd in specs]
+
+
 def stencil7_rows(N: int, seed: int, rows, delta: float = 1.0, f32x: bool = False):
     """Entries of selected rows of stencil7(N) without building the matrix:
     list of (cols int64 array, vals float64 array), from the host generator."""
@@ -218,6 +238,19 @@ def stencil7_rows(N: int, seed: int, rows, delta: float = 1.0, f32x: bool = Fals
         m = int(_get().gen_stencil7_row(N, seed, float(delta), int(f32x), int(i), _p(cols), _p(vals)))
         out.append((cols[:m].copy(), vals[:m].copy()))
     return out
+
+
+def stencil7_block(N: int, seed: int, r0: int, r1: int, delta: float = 1.0, f32x: bool = False):
+    """Rows [r0, r1) of stencil7(N) without building the matrix: (row_ptr
+    int64 starting at 0, global column indices int64, values float64)."""
+    m = r1 - r0
+    rp = np.empty(m + 1, np.int64)
+    col = np.empty(7 * max(m, 0), np.int64)
+    val = np.empty(7 * max(m, 0), np.float64)
+    k = int(_get().gen_stencil7_block(N, seed, float(delta), int(f32x), r0, r1, _p(rp), _p(col), _p(val)))
+    if k < 0:
+        raise ValueError("stencil7_block: bad row range")
+    return rp, col[:k], val[:k]
 
 
 def rhs(n: int, seed: int) -> np.ndarray:

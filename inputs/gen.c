@@ -132,6 +132,23 @@ int gen_stencil7_row(int64_t N, uint64_t seed, double delta, int f32x, int64_t i
     return m;
 }
 
+/* Rows [r0, r1) of stencil7(N) as a block: row_ptr (r1 - r0 + 1 entries,
+ * starting at 0), column indices (global, ascending per row) and values, the
+ * same entries gen_stencil7 emits for those rows.  col/val hold at least
+ * 7 (r1 - r0) entries.  Returns the block's entry count, or -1 for bad
+ * arguments. */
+int64_t gen_stencil7_block(int64_t N, uint64_t seed, double delta, int f32x, int64_t r0, int64_t r1,
+                           int64_t *row_ptr, int64_t *col, double *val) {
+    if (N < 1 || r0 < 0 || r1 < r0 || r1 > N * N * N) return -1;
+    int64_t k = 0;
+    row_ptr[0] = 0;
+    for (int64_t i = r0; i < r1; ++i) {
+        k += gen_stencil7_row(N, seed, delta, f32x, i, col + k, val + k);
+        row_ptr[i - r0 + 1] = k;
+    }
+    return k;
+}
+
 /*
  * stencil7_ns(N): the stencil7 pattern with every off-diagonal entry drawn on
  * its own (a_ij and a_ji independent, so A is nonsymmetric): entry (i, dir)

@@ -19,6 +19,7 @@ the nnz-balanced row partition and the Gershgorin condition bound.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -62,6 +63,8 @@ def load(path: str = _LIB):
     lib.orc_spmv_abs.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.orc_residual.restype = None
     lib.orc_residual.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    lib.orc_residual_sumsq.restype = f64
+    lib.orc_residual_sumsq.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.orc_cg.restype = ctypes.c_int
     lib.orc_cg.argtypes = [i64, vp, vp, vp, vp, vp, f64, i64, ctypes.POINTER(CGResult), vp]
     lib.orc_cgs.restype = ctypes.c_int
@@ -158,6 +161,39 @@ class Oracle:
         self.lib.orc_residual(A.n_rows, _p(rp), _p(ci), _p(va), _p(b), _p(x), _p(r))
         return r
 
+    def residual_norm_rows(self, blocks, make_block, b, x, threads: int = 1) -> float:
+        """||b - A x||_2 for a matrix visited block by block (never held whole).
+
+        blocks: (r0, r1) row ranges covering the matrix's rows once;
+        make_block(r0, r1) returns those rows as (row_ptr from 0, global column
+        indices, values).  Each block's squared residual is summed by
+        orc_residual_sumsq; the block totals are added in the order of
+        ``blocks`` (threads only overlap the block builds and sums), then the
+        square root is taken."""
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.ascontiguousarray(x, np.float64)
+
+        def one(rng):
+            r0, r1 = rng
+            rp, ci, va = make_block(r0, r1)
+            rp = np.ascontiguousarray(rp, np.int64)
+            ci = np.ascontiguousarray(ci, np.int64)
+            va = np.ascontiguousarray(va, np.float64)
+            bb = b[r0:r1]
+            return float(self.lib.orc_residual_sumsq(r1 - r0, _p(rp), _p(ci), _p(va), _p(bb), _p(x)))
+
+        blocks = list(blocks)
+        if threads > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                parts = list(ex.map(one, blocks))
+        else:
+            parts = [one(r) for r in blocks]
+        total = 0.0
+        for v in parts:
+            total += v
+        return math.sqrt(total)
+
     def _krylov(self, fn, A, b, x0, tau, max_iters, history):
         rp, ci, va = _csr64(A)
         n = A.n_rows
@@ -246,6 +282,19 @@ def coo_validate(n_rows, n_cols, row, col):
 
 def residual(A, b, x):
     return default().residual(A, b, x)
+
+
+def residual_norm_rows(blocks, make_block, b, x, threads=1):
+    return default().residual_norm_rows(blocks, make_block, b, x, threads)
+
+
+def cg_many(systems, tau=1e-14, max_iters=10000, threads=0):
+    """oracle CG on independent systems [(A, b), ...], several at once on host
+    threads (each solve is the single-threaded cg above); list of (x, result)."""
+    from concurrent.futures import ThreadPoolExecutor
+    workers = threads if threads > 0 else min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda s: cg(s[0], s[1], tau=tau, max_iters=max_iters)[:2], systems))
 
 
 def cg(A, b, x0=None, tau=1e-14, max_iters=10000, history=False):

@@ -134,6 +134,24 @@ void orc_residual(int64_t n, const int64_t *row_ptr, const int64_t *col, const d
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
 }
 
+/* Sum over the rows of a block of (b_i - sum_k val[k] x[col[k]])^2: the
+ * squared 2-norm of the residual b - A x that the ResidualNorm criterion
+ * measures (Section 3.5, Listing 2), restricted to the block's rows.  The
+ * block's column indices address the whole x, so a matrix too large to hold
+ * can be visited block by block; rows in order, each row's products summed
+ * in storage order, squares accumulated in row order. */
+double orc_residual_sumsq(int64_t n_rows, const int64_t *row_ptr, const int64_t *col, const double *val,
+                          const double *b, const double *x) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < n_rows; ++i) {
+        double s = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += val[k] * x[col[k]];
+        const double r = b[i] - s;
+        acc += r * r;
+    }
+    return acc;
+}
+
 /*
  * Conjugate gradient (Hestenes-Stiefel).  x holds the initial guess on entry
  * and the last iterate on exit.  hist (optional, max_iters+1 entries) receives

@@ -683,6 +683,48 @@ def pin_partition(orc):
             assert np.array_equal(s[:P], ref) and s[P] == n
 
 
+def pin_residual_norm_rows(orc):
+    """The block-by-block residual norm (for matrices too large to assemble)
+    equals ||b - A x||_2 of the assembled matrix by scipy.sparse for any split
+    of the rows into blocks; x = 0 gives ||b||; closed forms on a dyadic
+    diagonal system: 0 for the exact solution, 1 and 5 (a 3-4-5 triple) for
+    solutions off by whole units in chosen rows."""
+    import scipy.sparse as sp
+    for N, f32x, seed in ((9, False, 3), (7, True, 4)):
+        A = inputs.stencil7(N, seed, f32x=f32x)
+        n = A.n_rows
+        S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(n, n))
+        b = inputs.rhs(n, seed)
+        x = inputs.vec(n, seed, 5)
+        ref = float(np.linalg.norm(b - S @ x))
+
+        def mk(r0, r1):
+            return inputs.stencil7_block(N, seed, r0, r1, f32x=f32x)
+
+        for bs in (n, 1, 100, 97):
+            blocks = [(r, min(r + bs, n)) for r in range(0, n, bs)]
+            got = orc.residual_norm_rows(blocks, mk, b, x)
+            assert abs(got - ref) <= 1e-13 * ref, (N, bs, got, ref)
+        z = orc.residual_norm_rows([(0, n // 3), (n // 3, n)], mk, b, np.zeros(n))
+        assert abs(z - np.linalg.norm(b)) <= 1e-14 * np.linalg.norm(b)
+    d = np.array([2.0, 4.0, 0.5, 1.0, 8.0, 1.0])
+    xs = np.array([1.0, -0.5, 3.0, 0.25, 2.0, -1.0])
+    bd = d * xs                                   # exact in FP64
+
+    def mkd(r0, r1):
+        return np.arange(r1 - r0 + 1, dtype=np.int64), np.arange(r0, r1, dtype=np.int64), d[r0:r1]
+
+    blocks = [(0, 2), (2, 5), (5, 6)]
+    assert orc.residual_norm_rows(blocks, mkd, bd, xs) == 0.0
+    x1 = xs.copy()
+    x1[3] -= 1.0                                  # row 3: d = 1, residual 1
+    assert orc.residual_norm_rows(blocks, mkd, bd, x1) == 1.0
+    x2 = xs.copy()
+    x2[3] -= 3.0                                  # residual 3 in row 3 ...
+    x2[5] += 4.0                                  # ... and -4 in the last row: norm 5
+    assert orc.residual_norm_rows(blocks, mkd, bd, x2) == 5.0
+
+
 def pin_gershgorin(orc):
     d = np.array([2.0, 8.0, 0.5, 3.0])
     assert orc.gershgorin_kappa(inputs.diagonal(d)) == 16.0

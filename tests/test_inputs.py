@@ -110,3 +110,24 @@ def test_rhs_and_instances():
     lg = np.log(sizes)
     assert abs(lg.mean() - (np.log(1e3) + np.log(1e6)) / 2) < 0.4
     assert len(set(seeds.tolist())) == 256
+
+
+def test_stencil7_block_equals_whole_matrix_rows():
+    for N, f32x in ((6, False), (5, True)):
+        A = inputs.stencil7(N, 3, delta=0.5, f32x=f32x)
+        n = A.n_rows
+        for r0, r1 in ((0, n), (0, 1), (7, 60), (n - 1, n), (40, 40)):
+            rp, col, val = inputs.stencil7_block(N, 3, r0, r1, delta=0.5, f32x=f32x)
+            s, e = A.row_ptr[r0], A.row_ptr[r1]
+            assert np.array_equal(rp, A.row_ptr[r0:r1 + 1] - s)
+            assert np.array_equal(col, A.col[s:e].astype(np.int64))
+            assert np.array_equal(val.view(np.uint64), A.val[s:e].view(np.uint64))
+
+
+def test_serving_mix_matches_instance_table():
+    mats, rhs = inputs.serving_mix(12, 4, 1e3, 2e4, threads=4)
+    sizes, seeds = inputs.instances(12, 4, 1e3, 2e4)
+    for A, b, n, sd in zip(mats, rhs, sizes, seeds):
+        B = inputs.randsym(int(n), int(sd) % (1 << 31))
+        assert A.n_rows == int(n) and np.array_equal(A.col, B.col) and np.array_equal(A.val, B.val)
+        assert np.array_equal(b, inputs.rhs(int(n), int(sd) % (1 << 31)))

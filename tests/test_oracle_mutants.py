@@ -48,6 +48,11 @@ MUTANTS = [
      "while (i < n && row_ptr[i] <= target) ++i;", None),
     ("gershgorin sign", "if (d - R < lo) lo = d - R;", "if (d + R < lo) lo = d + R;", None),
     ("history index", "if (hist) hist[k] = resnorm;", "if (hist) hist[k - 1] = resnorm;", "int orc_cg("),
+    ("residual sumsq drops square", "acc += r * r;", "acc += r;", "double orc_residual_sumsq("),
+    ("residual sumsq skips last row", "for (int64_t i = 0; i < n_rows; ++i) {\n        double s",
+     "for (int64_t i = 0; i + 1 < n_rows; ++i) {\n        double s", "double orc_residual_sumsq("),
+    ("residual sumsq gathers by row", "s += val[k] * x[col[k]];\n        const double r",
+     "s += val[k] * x[i];\n        const double r", "double orc_residual_sumsq("),
     # COO
     ("coo no zero fill", "for (int64_t i = 0; i < n_rows; ++i) y[i] = 0.0;", ";", "void orc_coo_spmv("),
     ("coo gather by row", "y[row[k]] += val[k] * x[col[k]];", "y[row[k]] += val[k] * x[row[k]];",
