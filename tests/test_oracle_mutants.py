@@ -20,9 +20,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # the text inside the function whose definition starts with `scope` (the
 # whole file when scope is None); the text must occur there.
 MUTANTS = [
-    ("spmv wrong gather index", "s += val[k] * x[col[k]];", "s += val[k] * x[i];", None),
+    ("spmv wrong gather index", "s += val[k] * x[col[k]];", "s += val[k] * x[i];", "void orc_spmv("),
     ("spmv dropped last term", "for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += val[k] * x[col[k]];",
-     "for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] - 1; ++k) s += val[k] * x[col[k]];", None),
+     "for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] - 1; ++k) s += val[k] * x[col[k]];", "void orc_spmv("),
     ("spmv_abs dropped abs", "s += fabs(val[k]) * fabs(x[col[k]]);", "s += fabs(val[k]) * x[col[k]];", None),
     ("residual sign", "r[i] = b[i] - r[i];", "r[i] = r[i] - b[i];", None),
     ("alpha transposed", "const double alpha = rho / pq;", "const double alpha = pq / rho;", "int orc_cg("),
