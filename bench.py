@@ -1,21 +1,30 @@
 """Benchmark of the sparse CG hot path on one MI355X.
 
-Workload: stencil7 N=215 (n = 9,938,375 unknowns, nnz = 69,291,275), seed 1,
-delta = 1, FP64 values with int32 row_ptr/col_idx, b uniform in [-1,1),
-x0 = 0, solved to ||r|| <= 1e-14 ||b|| (the mid-size HBM-bound instance).
-A step is one whole solve: plan (GPU validation, tuned launch shape,
-workspace) + execute (initial residual, CG iterations, true residual) +
-free, with A and b already resident in HBM.
+Headline workload: stencil7 N=215 (n = 9,938,375 unknowns, nnz = 69,291,275),
+seed 1, delta = 1, FP64 values with int32 row_ptr/col_idx, b uniform in
+[-1,1), x0 = 0, solved to ||r|| <= 1e-14 ||b|| (the mid-size HBM-bound
+instance).  A step is one whole solve: plan (GPU validation, tuned launch
+shape, workspace) + execute (initial residual, CG iterations, true residual)
++ free, with A and b already resident in HBM.
 
 Prints ONE JSON line.  ``value`` is updates/s = n * iterations / step time.
 ``roofline`` covers the dominant kernel (SpMV fused with p.q): algorithmic
-bytes per launch nnz*(8+4) + (n+1)*4 + 2n*8 divided by its mean duration from
-HIP events recorded around every launch on the context stream during the
-timed steps.  ``cpu_baseline`` is the FP64 oracle (one host core) solving
-the same system to the same tolerance (capped at a bounded number of
+bytes per launch in the format the kernel reads divided by its mean duration
+from HIP events recorded around every fourth launch on the context stream
+during the timed steps.  ``cpu_baseline`` is the FP64 oracle (one host core)
+solving the same system to the same tolerance (capped at a bounded number of
 iterations); ``error_vs_oracle`` compares the GPU's solution with the
-oracle's.  Other modes: mixed precision, CGS, GMRES, Jacobi PCG, batched
-serving, the large device-generated instance and a standalone SpMV mode.
+oracle's.  The default run adds, after the timed headline steps:
+  * ``mixed``: the same system by FP32 CG inside FP64 iterative refinement to
+    the same tolerance (time per solve against the FP64 headline, error
+    against the oracle's solution, the inner SpMV's roofline);
+  * ``serving``: 256 randsym systems of log-uniform sizes through the
+    continuous-batching server (saturated rate, Poisson arrivals with p50/p99
+    latency), against plain FP64 solves one at a time with every plan made
+    beforehand, and every result's error against the oracle;
+  * ``paper_context``: the paper's own figures (other hardware), context only.
+Other modes: CGS, GMRES, Jacobi PCG, the serving block alone, the large
+device-generated instance and a standalone SpMV mode.
 """
 from __future__ import annotations
 
@@ -33,6 +42,20 @@ HBM_PEAK_GBS = 8000.0
 # the timed steps (every launch cost 2.8% of a C2 step; one in four, a
 # quarter of that)
 PROFILE_EVERY = 4
+
+# The paper's own figures (other hardware, SuiteSparse matrices): context only.
+PAPER_CONTEXT = [
+    {"what": "SpMV, best of pyGinkgo CSR/COO, y = A x", "value": 150.0, "unit": "GFLOP/s (about, peak)",
+     "hardware": "NVIDIA A100", "precision": "FP32", "source": "Section 6.1, GPU SpMV"},
+    {"what": "CG time per iteration, pyGinkgo against CuPy", "value": 2.5, "unit": "x faster (about)",
+     "hardware": "NVIDIA A100", "precision": "FP64", "source": "Section 6.2, GPU solvers"},
+    {"what": "CGS against CuPy", "value": 4.0, "unit": "x faster (up to)", "hardware": "NVIDIA A100",
+     "precision": "FP64", "source": "Section 6.2, GPU solvers"},
+    {"what": "GMRES(30) against CuPy", "value": None, "unit": "CuPy slightly faster", "hardware": "NVIDIA A100",
+     "precision": "FP64", "source": "Section 6.2, GPU solvers"},
+]
+PAPER_NOTE = ("context only: the paper measures other hardware on SuiteSparse matrices and prints no absolute "
+              "solver times (its solver results are speedups over CuPy and SciPy)")
 
 
 def parse():
@@ -69,7 +92,8 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--load", type=float, default=0.7, help="offered load / saturated throughput")
-    ap.add_argument("--oracle-sample", type=int, default=16, help="instances checked against the oracle")
+    ap.add_argument("--no-serving", action="store_true", help="default run: skip the serving block")
+    ap.add_argument("--no-mixed", action="store_true", help="default run: skip the mixed-precision block")
     ap.add_argument("--large", action="store_true",
                     help="large instance: stencil7 N=1048 generated on the device, FP32-exact values, "
                          "int64 row_ptr, FP32 CG + FP64 refinement")
@@ -80,6 +104,14 @@ def parse():
                     help="iteration driver: host loop, captured graphs, one cooperative launch (FP64 CG; "
                          "other solves fall back to graphs), or the plan's choice")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line on stderr per finished phase (the JSON line stays alone on stdout)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
 
 
 def host_info():
@@ -209,6 +241,7 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    progress("headline warm-up done")
     t0 = time.perf_counter()
     iters, kms, klaunch = 0, 0.0, 0
     logs = []
@@ -223,6 +256,7 @@ def main():
     wall = t1 - t0
     ms_per_step = wall / args.steps * 1e3
     value = n * iters / wall
+    progress("headline timed steps done: %.3f ms per step" % ms_per_step)
 
     # index bytes: int32 columns and row pointers, or the plan's column codes
     # and packed row pointers
@@ -309,7 +343,9 @@ def main():
         if achieved:
             out["roofline"]["frac_vs_copy"] = achieved / cgbs
 
+    x_orc = None
     if not args.no_cpu_baseline:
+        progress("oracle baseline")
         # The FP64 oracle on the same system with the same tolerance, capped at
         # cpu_iters iterations (a bounded sample of CPU work).  Its solution
         # also gives the GPU result's error: against the last timed solve when
@@ -349,14 +385,102 @@ def main():
                 compared += ("; the GPU side is the FP64 solve of the same solver (the mixed-precision "
                              "solve meets the FP64 criterion: rel_true_residual)")
         err = float(np.linalg.norm(x_gpu - xo) / np.linalg.norm(xo))
+        if res.stop_reason == 1:
+            x_orc = xo
         out["cpu_baseline"] = {"value": n * res.iterations / dt, "unit": "updates/s", "cores": 1,
                                "kind": "oracle", "host": host_info(),
                                "sample": "FP64 oracle %s, same system and tolerance, %d iterations (plus initial "
                                          "and true residual), %.1f s" % (label, res.iterations, dt)}
         out["error_vs_oracle"] = {"rel_2norm": err, "compared": compared,
                                   "oracle_rel_true_residual": res.true_resnorm / res.rhs_norm}
+    if avg_ms:
+        out["paper_context"] = {"paper": PAPER_CONTEXT, "note": PAPER_NOTE,
+                                "this_run": {"spmv_fp64_gflops": 2.0 * nnz / (avg_ms * 1e-3) / 1e9,
+                                             "note": "the dominant SpMV launch of this run, FP64, 2 nnz flops"}}
+    plain_cg = not (cgs or gm) and args.precond == "none" and args.precision == "fp64"
+    if plain_cg and not args.no_mixed:
+        progress("mixed-precision block")
+        try:
+            out["mixed"] = mixed_block(args, ctx, M, b, x, n, nnz, ms_per_step, last, x_orc)
+        except Exception as e:   # the headline line is printed whatever happens here
+            out["mixed"] = {"error": repr(e)}
     spk.spk_finalize(ctx)
+    if plain_cg and args.pattern == "stencil7" and not args.no_serving:
+        progress("serving block")
+        try:
+            del M, rp, ci, va, b, x
+            torch.cuda.empty_cache()
+            sctx = spk.spk_init(0, torch.cuda.current_stream(dev).cuda_stream)
+            out["serving"] = serving_block(args, sctx, with_oracle=not args.no_cpu_baseline)
+            spk.spk_finalize(sctx)
+            out["latency_s"] = out["serving"]["poisson"]["latency_s"]
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
+
+
+def mixed_block(args, ctx, M, b, x, n, nnz, fp64_ms, fp64_log, x_orc):
+    """The same system solved by FP32 CG (FP32 values and vectors, FP64 dot
+    products) inside FP64 iterative refinement to the same tolerance as the
+    FP64 headline: time per whole solve (plan + solve + free, as the
+    headline), updates/s on inner iterations, the inner SpMV's roofline, and
+    the error against the oracle's FP64 solution."""
+    import numpy as np
+    import torch
+
+    from paper_2510_08230_amd import spk
+
+    cfg = spk.spk_solver_cfg_default()
+    cfg.precision = spk.PREC_MIXED_FP32
+    cfg.reduction_factor = args.tau
+    cfg.inner_reduction = args.inner
+    cfg.max_iters = 10000
+
+    def step(profile):
+        pl = spk.spk_plan_solve(ctx, M, cfg)
+        if profile:
+            spk.spk_plan_set_profiling(pl, PROFILE_EVERY)
+        x.zero_()
+        log = spk.spk_execute_solve(pl, b, x)
+        st = spk.spk_plan_kernel_stats(pl)
+        info = spk.spk_plan_get_info(pl)
+        spk.spk_free(pl)
+        return log, st, info
+
+    step(False)
+    steps = max(3, args.steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, kms, kl = 0, 0.0, 0
+    for _ in range(steps):
+        log, (ms, cnt), info = step(True)
+        iters += log.iterations
+        kms += ms
+        kl += cnt
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / steps * 1e3
+    bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 4) + 2 * n * 4
+    avg = kms / kl if kl else None
+    ach = bytes_spmv / (avg * 1e-3) / 1e9 if avg else None
+    blk = {
+        "workload": "cg_mixed_fp32_stencil7_N%d" % args.N, "dtype": "f32+f64",
+        "steps": steps, "ms_per_step": ms_step, "tau": args.tau, "inner_reduction": args.inner,
+        "inner_iterations": log.iterations, "outer_iterations": log.outer_iterations,
+        "updates_per_s": n * iters / wall, "stop_reason": log.stop_reason,
+        "rel_true_residual": log.true_resnorm / log.rhs_norm,
+        "fp64_ms_per_step": fp64_ms, "fp64_iterations": fp64_log.iterations,
+        "fp64_rel_true_residual": fp64_log.true_resnorm / fp64_log.rhs_norm,
+        "speedup_vs_fp64": fp64_ms / ms_step,
+        "inner_spmv": {"kernel": "k_spmv_*<EpiPq<float>> (q = A32 p fused with p.q)", "bytes_per_launch": bytes_spmv,
+                       "avg_launch_ms": avg, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS if ach else None,
+                       "launches": kl, "tiling": info},
+    }
+    if x_orc is not None:
+        xm = x.cpu().numpy()
+        blk["error_vs_oracle"] = float(np.linalg.norm(xm - x_orc) / np.linalg.norm(x_orc))
+        blk["equal_final_accuracy"] = bool(blk["error_vs_oracle"] <= 1e-10)
+    return blk
 
 
 def spmv_mode(args):
@@ -525,16 +649,22 @@ def large(args):
     print(json.dumps(out), flush=True)
 
 
-def serve(args):
-    """Batched serving of uneven solves: every instance is randsym(n_i) with
-    n_i log-uniform in [1e3, 1e6] (seeded), b uniform, x0 = 0, solved to
+def serving_block(args, ctx, with_oracle=True):
+    """The batched-serving configuration: args.instances randsym(n_i) systems,
+    n_i log-uniform in [1e3, 1e6] (seed 4), b uniform, x0 = 0, solved to
     ||b - A x|| <= 1e-12 ||b|| by FP32 CG + FP64 refinement in the server.
-    A closed-loop pass (all submitted at once) measures the saturated rate;
-    the timed pass submits at Poisson arrival times with rate load * that
-    rate.  Baseline: plain FP64 GPU solves, one at a time, same tolerance."""
-    import math
-    import threading
 
+    * closed loop (every request submitted at once) twice: the first warms
+      up (graph capture, pools), the second gives the saturated rate;
+    * Poisson arrivals at args.load x the saturated rate: latency p50/p99;
+    * baseline: plain FP64 GPU CG solves one at a time, every plan (GPU
+      validation, autotuned launch) made BEFORE the timed loop, to the same
+      tolerance, saturated (back to back): the fair comparison is
+      saturated serving against saturated FP64;
+    * accuracy: every served and every FP64 solution against the oracle's
+      FP64 CG solution (tau 1e-14) of the same system, all instances, the
+      oracle solves run on host threads outside every timed region.
+    Returns a dict (the "serving" block of the JSON line)."""
     import numpy as np
     import torch
 
@@ -543,17 +673,15 @@ def serve(args):
 
     dev = torch.device("cuda:0")
     tau = 1e-12
-    sizes, seeds = inputs.instances(args.instances, 4, 1e3, 1e6)
-    mats, rhs = [], []
-    for n, sd in zip(sizes, seeds):
-        A = inputs.randsym(int(n), int(sd) % (1 << 31))
-        b = inputs.rhs(int(n), int(sd) % (1 << 31))
-        M = spk.CsrMatrix(torch.from_numpy(A.row_ptr).to(torch.int32).to(dev), torch.from_numpy(A.col).to(dev),
-                          torch.from_numpy(A.val).to(dev), A.n_rows, A.n_cols)
-        mats.append((A, M))
-        rhs.append((b, torch.from_numpy(b).to(dev)))
-    xs = [torch.zeros(int(n), dtype=torch.float64, device=dev) for n in sizes]
-    ctx = spk.spk_init(0, torch.cuda.current_stream(dev).cuda_stream)
+    t_gen = time.perf_counter()
+    hosts, rhs_h = inputs.serving_mix(args.instances, 4, 1e3, 1e6)
+    gen_s = time.perf_counter() - t_gen
+    progress("serving: %d instances generated in %.1f s" % (len(hosts), gen_s))
+    nvec = np.array([A.n_rows for A in hosts], np.int64)
+    mats = [spk.CsrMatrix(torch.from_numpy(A.row_ptr).to(torch.int32).to(dev), torch.from_numpy(A.col).to(dev),
+                          torch.from_numpy(A.val).to(dev), A.n_rows, A.n_cols) for A in hosts]
+    rhs = [torch.from_numpy(b).to(dev) for b in rhs_h]
+    xs = [torch.zeros(int(n), dtype=torch.float64, device=dev) for n in nvec]
     cfg = spk.spk_solver_cfg_default()
     cfg.precision = spk.PREC_MIXED_FP32
     cfg.reduction_factor = tau
@@ -568,102 +696,137 @@ def serve(args):
         srv = spk.spk_server_create(ctx, budget, args.slots, cfg)
         t0 = time.perf_counter()
         tickets = []
-        for i, (_, M) in enumerate(mats):
+        for i, M in enumerate(mats):
             if arrivals is not None:
                 delay = t0 + arrivals[i] - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
-            tickets.append(spk.spk_server_submit(srv, M, rhs[i][1], xs[i]))
+            tickets.append(spk.spk_server_submit(srv, M, rhs[i], xs[i]))
         spk.spk_server_drain(srv)
         makespan = time.perf_counter() - t0
-        lats, iters, stops, rres = [], [], [], []
+        lats, iters, outer, stops, rres = [], [], [], [], []
         for t in tickets:
             done, st, log, lat = spk.spk_server_poll(srv, t)
             assert done and st == spk.OK
             lats.append(lat * 1e-9)
             iters.append(log.iterations)
+            outer.append(log.outer_iterations)
             stops.append(log.stop_reason)
             rres.append(log.true_resnorm / log.rhs_norm)
         stats = spk.spk_server_get_stats(srv)
         spk.spk_server_destroy(srv)
-        return makespan, np.array(lats), np.array(iters), stops, stats, rres
+        return {"makespan": makespan, "lats": np.array(lats), "iters": np.array(iters), "outer": np.array(outer),
+                "stops": stops, "stats": stats, "rres": rres}
 
-    run_pass(None)                                   # warm-up (graph capture, pools)
-    sat_makespan, _, sat_iters, _, _, _ = run_pass(None)
-    sat_rate = len(mats) / sat_makespan              # solves/s, closed loop
+    run_pass(None)                                   # warm-up
+    sat = run_pass(None)
+    sat_rate = len(mats) / sat["makespan"]           # solves/s, closed loop
     lam = args.load * sat_rate
     u = np.array([inputs.unif(4, 5, i) for i in range(len(mats))])
     arrivals = np.cumsum(-np.log1p(-(u + 1.0) / 2.0) / lam)
     arrivals -= arrivals[0]
-    makespan, lats, iters, stops, stats, rres = run_pass(arrivals)
-    nvec = np.array([int(n) for n in sizes])
-    updates = float(np.sum(nvec * iters))
-
-    # accuracy: the FP64 residual b - A x each solve reports (computed on the GPU)
-    worst_res = float(max(rres))
-
+    poi = run_pass(arrivals)
+    progress("serving: saturated %.1f solves/s, Poisson pass done" % sat_rate)
     served = [x.cpu().numpy() for x in xs]
 
-    # baseline: plain FP64 GPU solves one at a time, same tolerance
+    # baseline: plain FP64 CG, one solve at a time, plans made beforehand
     bcfg = spk.spk_solver_cfg_default()
     bcfg.reduction_factor = tau
     bcfg.max_iters = 100000
+    t_plan = time.perf_counter()
+    plans = [spk.spk_plan_solve(ctx, M, bcfg) for M in mats]
+    plan_s = time.perf_counter() - t_plan
     for x in xs:
         x.zero_()
+    spk.spk_execute_solve(plans[0], rhs[0], xs[0])   # warm-up (first solve pays one-off costs)
+    xs[0].zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    base_updates = 0.0
-    for i, (_, M) in enumerate(mats):
-        pl = spk.spk_plan_solve(ctx, M, bcfg)
-        log = spk.spk_execute_solve(pl, rhs[i][1], xs[i])
-        spk.spk_free(pl)
-        base_updates += float(nvec[i]) * log.iterations
+    base_iters, base_rres = [], []
+    for i, pl in enumerate(plans):
+        log = spk.spk_execute_solve(pl, rhs[i], xs[i])
+        base_iters.append(log.iterations)
+        base_rres.append(log.true_resnorm / log.rhs_norm)
     torch.cuda.synchronize()
     base_time = time.perf_counter() - t0
-    spk.spk_finalize(ctx)
+    for pl in plans:
+        spk.spk_free(pl)
+    fp64_sols = [x.cpu().numpy() for x in xs]
+    progress("serving: FP64 baseline %.3f s (plans %.1f s outside timing)" % (base_time, plan_s))
+    base_iters = np.array(base_iters)
+
+    def pct(a, q):
+        return float(np.percentile(a, q))
 
     out = {
-        "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
-        "value": updates / makespan,
-        "unit": "updates/s",
-        "n_gpus": 1, "steps": 1, "warmup": 2, "ms_per_step": makespan * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic (seeded randsym instances, log-uniform sizes)",
-        "config": {"workload": "serve_randsym_%d_loguniform_1e3_1e6" % len(mats), "instances": len(mats),
-                   "sum_n": int(nvec.sum()), "tau": tau, "inner_reduction": args.inner,
-                   "budget_bytes": budget, "max_slots": args.slots, "offered_load": args.load,
-                   "arrival_rate_per_s": lam, "saturated_solves_per_s": sat_rate},
-        "latency_s": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99)),
-                      "max": float(lats.max())},
-        "solves_per_s": len(mats) / makespan,
-        "server_stats": stats,
-        "accuracy": {"max_rel_residual": worst_res, "all_converged": all(s == 1 for s in stops)},
-        "baseline_fp64_one_at_a_time": {"seconds": base_time, "updates_per_s": base_updates / base_time,
-                                        "solves_per_s": len(mats) / base_time},
-        "speedup_vs_fp64_one_at_a_time": base_time / makespan,
+        "workload": "serve_randsym_%d_loguniform_1e3_1e6" % len(mats),
+        "data": "synthetic (seeded randsym instances: 3 uniform partners per row, symmetrised, uniform[-1,1) "
+                "values, diagonally dominant SPD; sizes log-uniform in [1e3, 1e6], seed 4)",
+        "instances": len(mats), "sum_n": int(nvec.sum()), "nnz_total": int(sum(A.nnz for A in hosts)),
+        "tau": tau, "inner_reduction": args.inner, "dtype": "f32+f64",
+        "budget_bytes": budget, "max_slots": args.slots, "offered_load": args.load,
+        "arrival_rate_per_s": lam, "host_generation_s": gen_s,
+        "saturated": {"makespan_s": sat["makespan"], "solves_per_s": sat_rate,
+                      "updates_per_s": float(np.sum(nvec * sat["iters"])) / sat["makespan"],
+                      "note": "all requests submitted at once (closed loop)"},
+        "poisson": {"makespan_s": poi["makespan"], "solves_per_s": len(mats) / poi["makespan"],
+                    "updates_per_s": float(np.sum(nvec * poi["iters"])) / poi["makespan"],
+                    "latency_s": {"p50": pct(poi["lats"], 50), "p99": pct(poi["lats"], 99),
+                                  "max": float(poi["lats"].max()), "mean": float(poi["lats"].mean())},
+                    "server_stats": poi["stats"]},
+        "iterations": {"inner_total": int(poi["iters"].sum()), "outer_total": int(poi["outer"].sum()),
+                       "inner_max": int(poi["iters"].max())},
+        "fp64_one_at_a_time": {"seconds": base_time, "solves_per_s": len(mats) / base_time,
+                               "updates_per_s": float(np.sum(nvec * base_iters)) / base_time,
+                               "iterations_total": int(base_iters.sum()),
+                               "plan_seconds_outside_timing": plan_s,
+                               "note": "spk_execute_solve per instance back to back; every plan (validation, "
+                                       "autotuned launch shape, workspace) made before the timed loop"},
+        "speedup_saturated_vs_fp64": base_time / sat["makespan"],
+        "accuracy": {"served_max_rel_true_residual": float(max(poi["rres"])),
+                     "fp64_max_rel_true_residual": float(max(base_rres)),
+                     "all_converged": all(st == 1 for st in poi["stops"])},
     }
-    if not args.no_cpu_baseline:
-        # The FP64 oracle's CG on a bounded sample of the instances: its rate,
-        # and the served solutions' error against its solutions.
+    if with_oracle:
         import oracle
-        sample = list(range(0, len(mats), max(1, len(mats) // max(args.oracle_sample, 1))))[: args.oracle_sample]
-        worst_rel, o_updates = 0.0, 0.0
+        threads = min(16, os.cpu_count() or 1)
         t0 = time.perf_counter()
-        sols = {}
-        for i in sample:
-            xo, ro, _ = oracle.cg(mats[i][0], rhs[i][0], tau=tau, max_iters=5000)
-            sols[i] = xo
-            o_updates += float(nvec[i]) * ro.iterations
+        sols = oracle.cg_many(list(zip(hosts, rhs_h)), tau=1e-14, max_iters=5000, threads=threads)
         dt = time.perf_counter() - t0
-        for i in sample:
-            worst_rel = max(worst_rel, float(np.linalg.norm(served[i] - sols[i]) / np.linalg.norm(sols[i])))
-        out["cpu_baseline"] = {"value": o_updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-                               "host": host_info(),
-                               "sample": "FP64 oracle CG to the same tolerance on %d of the %d instances "
-                                         "(every %d-th), %.1f s" % (len(sample), len(mats),
-                                                                   max(1, len(mats) // max(args.oracle_sample, 1)), dt)}
-        out["accuracy"]["max_rel_err_vs_oracle_sample"] = worst_rel
-        out["accuracy"]["oracle_sample"] = len(sample)
+        e_srv = np.array([np.linalg.norm(a - xo) / np.linalg.norm(xo) for a, (xo, _) in zip(served, sols)])
+        e_64 = np.array([np.linalg.norm(a - xo) / np.linalg.norm(xo) for a, (xo, _) in zip(fp64_sols, sols)])
+        o_updates = float(sum(int(A.n_rows) * r.iterations for A, (_, r) in zip(hosts, sols)))
+        out["accuracy"]["served_err_vs_oracle"] = {"max": float(e_srv.max()), "p50": pct(e_srv, 50),
+                                                   "p99": pct(e_srv, 99), "count": int(e_srv.size),
+                                                   "within_1e-10": int(np.sum(e_srv <= 1e-10))}
+        out["accuracy"]["fp64_err_vs_oracle"] = {"max": float(e_64.max()), "p50": pct(e_64, 50),
+                                                 "p99": pct(e_64, 99), "count": int(e_64.size)}
+        out["accuracy"]["oracle"] = ("FP64 oracle CG to tau 1e-14 on every instance, %d host threads, %.1f s "
+                                     "(%.3g updates/s aggregate)" % (threads, dt, o_updates / dt))
+        out["accuracy"]["equal_final_accuracy"] = bool(e_srv.max() <= 1e-10 and e_64.max() <= 1e-10)
+    return out
+
+
+def serve(args):
+    """--serve: the serving block alone, as the line's headline (updates/s of
+    the Poisson pass; p50/p99 latency beside it)."""
+    import torch
+
+    from paper_2510_08230_amd import spk
+
+    ctx = spk.spk_init(0, torch.cuda.current_stream(torch.device("cuda:0")).cuda_stream)
+    blk = serving_block(args, ctx, with_oracle=not args.no_cpu_baseline)
+    spk.spk_finalize(ctx)
+    out = {
+        "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
+        "value": blk["poisson"]["updates_per_s"], "unit": "updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": blk["poisson"]["makespan_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": blk["data"],
+        "config": {"workload": blk["workload"]},
+        "latency_s": blk["poisson"]["latency_s"],
+        "serving": blk,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -183,7 +183,10 @@ void spk_solver_cfg_default(spk_solver_cfg *cfg);
 
 /* Create a context on HIP device device_id that enqueues on hip_stream
  * (a hipStream_t; NULL = the device's null stream).  *out receives the
- * handle.  Errors: INVALID_ARG (out NULL, bad device), DEVICE. */
+ * handle.  The context plays the part of the paper's executor: the object
+ * that names the device every operator and vector lives on and runs on
+ * (Section 4.1, the Executor; created first in Listing 1).
+ * Errors: INVALID_ARG (out NULL, bad device), DEVICE. */
 spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out);
 
 /* Destroy a context.  All its plans must have been freed.  NULL is a no-op. */
@@ -226,7 +229,12 @@ spk_status spk_coo_check(spk_ctx ctx, const spk_coo *A, int32_t *verdict, int32_
  * Results equal those of spk_plan_spmv on the corresponding CSR matrix. */
 spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
 
-/* Plan a solve of A x = b.  A must be square and valid.  FP64 precision
+/* Plan a solve of A x = b: the counterpart of generating a solver operator
+ * for a system matrix from a configured factory (the generic solver entry
+ * point of Section 5, instantiated through a LinOp factory as in Section
+ * 4.2; the factory and its stopping criteria in Listings 1-2).  A must be
+ * square and valid.
+ * FP64 precision
  * needs val_type F64; the mixed precisions accept F64 values (the plan keeps
  * an FP32, BF16 or FP16 copy for the inner solve, each value rounded once to
  * nearest even) or, for MIXED_FP32, F32 values (taken as exact).
@@ -240,10 +248,14 @@ spk_status spk_plan_spmv_coo(spk_ctx ctx, const spk_coo *A, spk_plan *out);
  * preconditioner combinations), OUT_OF_MEMORY. */
 spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg, spk_plan *out);
 
-/* y = A x with the plan's matrix; x has n_cols entries, y has n_rows. */
+/* y = A x with the plan's matrix (a matrix operator's apply is the SpMV,
+ * Section 4.2; benchmarked in Section 6.1); x has n_cols entries, y has
+ * n_rows. */
 spk_status spk_execute_spmv(spk_plan plan, const void *x, void *y);
 
-/* Solve A x = b.  b (n entries, FP64) is read; x (n entries, FP64) holds the
+/* Solve A x = b: the solver's apply(b, x), which overwrites the initial
+ * guess x with the solution and returns the logger's record (Section 3.5,
+ * Listing 1).  b (n entries, FP64) is read; x (n entries, FP64) holds the
  * initial guess on entry and the last iterate on exit.  log may be NULL. */
 spk_status spk_execute_solve(spk_plan plan, const void *b, void *x, spk_log *log);
 
@@ -290,6 +302,8 @@ typedef struct {
     int64_t peak_bytes;     /* most workspace bytes held at once */
     int64_t budget_bytes;
     int64_t max_slots;
+    int64_t peak_device_bytes; /* most device bytes the request pool held at once (blocks in use
+                                  plus cached ones); never above budget_bytes */
 } spk_server_stats;
 
 /* Workspace bytes one request of n unknowns and nnz stored entries needs
@@ -312,6 +326,15 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
  * value types), BUDGET (the request alone exceeds the budget).  A malformed
  * CSR is detected on the GPU before admission and reported by poll. */
 spk_status spk_server_submit(spk_server srv, const spk_csr *A, const void *b, void *x, uint64_t *ticket);
+
+/* As spk_server_submit, with this request's own solver configuration (its
+ * reduction_factor, inner_reduction, max_iters and max_outer; the other
+ * fields must name what the server runs: CG, MIXED_FP32, no preconditioner),
+ * so one server mixes requests with different tolerances (the per-solve
+ * stopping criteria of Listing 2).  cfg NULL = the server's configuration.
+ * Errors: as spk_server_submit, plus INVALID_ARG / UNSUPPORTED for cfg. */
+spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b, void *x, const spk_solver_cfg *cfg,
+                                 uint64_t *ticket);
 
 /* Non-blocking: *done = 1 once the request finished; then log and
  * *latency_ns (submission to completion, host steady clock) are filled and

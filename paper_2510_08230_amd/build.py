@@ -1,22 +1,26 @@
 """Build the gfx950 shared library ``libspk.so`` in-tree with hipcc.
 
 The library holds every GPU kernel of the hot path and the C ABI declared
-in ``include/spk.h``.  It is compiled for gfx950 only.
+in ``include/spk.h``.  It is compiled for gfx950 only.  Each source becomes
+an object of its own (compiled in parallel), then the objects are linked.
 """
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libspk.so")
-SOURCES = ["spk_kernels.hip", "spk_krylov.hip", "spk_gmres.hip", "spk_batch.hip", "spk_api.cpp", "spk_server.cpp"]
+OBJ = os.path.join(PKG, "_build")
+SOURCES = ["spk_kernels.hip", "spk_krylov.hip", "spk_gmres.hip", "spk_batch.hip", "spk_persist.hip",
+           "spk_noalloc.hip", "spk_api.cpp", "spk_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep hipcc from forming packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -24,13 +28,28 @@ FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, s) for s in SOURCES]
+    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile every source into libspk.so (always recompiles)."""
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    srcs = sources()
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in srcs]
+
+    def compile_one(pair):
+        src, obj = pair
+        cmd = [HIPCC, *FLAGS, *inc, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    workers = jobs if jobs > 0 else min(len(srcs), max(1, min(os.cpu_count() or 1, 8)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(compile_one, zip(srcs, objs)))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *sources(), "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

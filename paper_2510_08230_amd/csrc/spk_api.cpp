@@ -28,9 +28,10 @@ struct TuneKey {
     int pt, it, vt;
     int use;     // TUNE_PLAIN or TUNE_CG
     int codes;   // the matrix has column codes
+    int staged;  // values and columns are 16-byte aligned (the LDS tiles may run)
     bool operator<(const TuneKey &o) const {
-        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes) <
-               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes);
+        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged) <
+               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged);
     }
 };
 
@@ -225,7 +226,7 @@ SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
 // the solvers' fused SpMV with st (stop flag clear) and partials.
 spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int use, SolveState *st,
                     double *partials, TuneResult *out) {
-    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use, A.codes != nullptr};
+    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use, A.codes != nullptr, stream_ok(A)};
     auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
         *out = hit->second;

@@ -24,10 +24,11 @@ using namespace dev;
 
 // Row sum of this thread's row of the 256-row tile [r0, r1) (int32 indices),
 // values and columns staged in LDS by DMA.  has_row: this thread owns a row.
+// stage = 0 (arrays not 16-byte aligned): rows read values and columns directly.
 template <typename V, typename X, typename C>
 __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                           const V *__restrict__ va, int64_t nnz, const X *__restrict__ x, int64_t r0,
-                                          int64_t r1, u32x4 *lv, u32x4 *lc, bool &has_row) {
+                                          int64_t r1, u32x4 *lv, u32x4 *lc, bool &has_row, int stage) {
     const int64_t s = rp[r0], e = rp[r1];
     const int64_t row = r0 + threadIdx.x;
     int64_t a = 0, b = 0;
@@ -37,7 +38,7 @@ __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const 
         b = rp[row + 1];
     }
     C sum = 0;
-    if (e - s <= kStreamCap) {
+    if (stage && e - s <= kStreamCap) {
         dma_chunks<V>(va, s, e, nnz, lv, 0);
         dma_chunks<int32_t>(ci, s, e, nnz, lc, 0);
         __builtin_amdgcn_s_waitcnt(0);
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
         const int64_t row = r0 + threadIdx.x;
         bool has = false;
         if (ph == PH_INNER && S.stop_in == STOP_RUNNING) {
-            const float s = tile_row_sum<float, float, float>(D.rp, D.ci, D.va32, D.nnz, D.p, r0, r1, lv, lc, has);
+            const float s = tile_row_sum<float, float, float>(D.rp, D.ci, D.va32, D.nnz, D.p, r0, r1, lv, lc, has, D.stage);
             double v[1] = {0.0};
             if (has) {
                 D.q[row] = s;
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
             }
             block_reduce_store<1>(v, D.part + PART_PQ * D.tiles + te.y, D.tiles);
         } else if (ph == PH_OUTER) {
-            const double s = tile_row_sum<double, double, double>(D.rp, D.ci, D.va64, D.nnz, D.x, r0, r1, lv, lc, has);
+            const double s = tile_row_sum<double, double, double>(D.rp, D.ci, D.va64, D.nnz, D.x, r0, r1, lv, lc, has, D.stage);
             double v[3] = {0.0, 0.0, 0.0};
             if (has) {
                 const double bi = D.b[row];

@@ -139,6 +139,7 @@ struct SlotDesc {
     double *part;           // slot workspace: kPartSites * tiles
     double tau, tau_in;
     int64_t max_iters, max_outer;
+    int32_t stage;          // 1: values and columns 16-byte aligned, tiles staged in LDS by DMA
 };
 
 // Device-resident per-slot scalars.

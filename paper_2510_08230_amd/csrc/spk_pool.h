@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <iterator>
 #include <map>
 #include <unordered_map>
 
@@ -22,17 +23,35 @@ class CachingPool {
 
     void set_cap(size_t cap) { cap_ = cap; }
 
+    // Budget mode: blocks are reused only at their exact (rounded) size, and
+    // the cap bounds everything the pool holds (blocks in use plus cached
+    // ones), so the device memory held never exceeds the cap.  get() fails
+    // with hipErrorOutOfMemory when a request would pass it.
+    void set_budget_mode(bool on) { budget_ = on; }
+
     // A block of at least `bytes` (reusing a cached block no larger than
-    // twice the request), or a fresh allocation.
+    // twice the request; in budget mode only one of the same size), or a
+    // fresh allocation.
     hipError_t get(size_t bytes, void **out) {
         bytes = round(bytes);
         auto it = free_.lower_bound(bytes);
-        if (it != free_.end() && it->first <= 2 * bytes) {
+        if (it != free_.end() && (budget_ ? it->first == bytes : it->first <= 2 * bytes)) {
             *out = it->second;
             cached_ -= it->first;
             in_use_ += it->first;
             free_.erase(it);
             return hipSuccess;
+        }
+        if (budget_) {
+            if (in_use_ + bytes > cap_) return hipErrorOutOfMemory;
+            // give back cached blocks until the new one fits under the cap
+            while (!free_.empty() && in_use_ + cached_ + bytes > cap_) {
+                auto victim = std::prev(free_.end());   // the largest first
+                cached_ -= victim->first;
+                size_.erase(victim->second);
+                raw_free(victim->second);
+                free_.erase(victim);
+            }
         }
         void *p = nullptr;
         hipError_t e = raw_alloc(&p, bytes);
@@ -55,7 +74,7 @@ class CachingPool {
         if (s == size_.end()) return;
         const size_t bytes = s->second;
         in_use_ -= bytes;
-        if (cached_ + bytes > cap_) {
+        if (cached_ + bytes + (budget_ ? in_use_ : 0) > cap_) {
             size_.erase(s);
             raw_free(p);
             return;
@@ -75,6 +94,8 @@ class CachingPool {
 
     size_t in_use() const { return in_use_; }
     size_t cached() const { return cached_; }
+    // Size of a block get(bytes) hands out (requests are rounded up to 256 bytes).
+    static size_t block_bytes(size_t bytes) { return round(bytes); }
 
   private:
     static size_t round(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
@@ -90,6 +111,7 @@ class CachingPool {
     std::multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> size_;
     size_t in_use_ = 0, cached_ = 0, cap_;
+    bool budget_ = false;
 };
 
 using DevicePool = CachingPool<false>;

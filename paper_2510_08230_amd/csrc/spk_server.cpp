@@ -49,7 +49,22 @@ struct Request {
     const double *b = nullptr;
     double *x = nullptr;
     int64_t submit_ns = 0;
+    double tau = 0.0, tau_in = 0.0;   // this request's stop tests
+    int64_t max_iters = 0, max_outer = 0;
 };
+
+// The LDS tiles stage a tile's values and columns with 16-byte DMA loads,
+// which need 16-byte aligned arrays; other requests read them directly.
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Configuration checks shared by create (server default) and submit (per request).
+bool cfg_supported(const spk_solver_cfg &c) {
+    return c.solver == SPK_SOLVER_CG && c.precond == SPK_PRECOND_NONE && c.precision == SPK_PREC_MIXED_FP32;
+}
+bool cfg_valid(const spk_solver_cfg &c) {
+    return c.reduction_factor >= 0.0 && c.inner_reduction > 0.0 && c.inner_reduction < 1.0 && c.max_iters >= 0 &&
+           c.max_outer >= 0;
+}
 
 struct Result {
     int32_t done = 0;
@@ -202,10 +217,13 @@ bool admit(spk_server srv) {
         D.part = reinterpret_cast<double *>(carve(sizeof(double) * spk::kPartSites * static_cast<size_t>(std::max<int64_t>(t, 1))));
         D.b = req.b;
         D.x = req.x;
-        D.tau = srv->cfg.reduction_factor;
-        D.tau_in = srv->cfg.inner_reduction;
-        D.max_iters = srv->cfg.max_iters;
-        D.max_outer = srv->cfg.max_outer;
+        D.tau = req.tau;
+        D.tau_in = req.tau_in;
+        D.max_iters = req.max_iters;
+        D.max_outer = req.max_outer;
+        // the slot's FP32 values are carved 256-byte aligned; the caller's
+        // FP64 values and columns decide whether tiles are DMA-staged
+        D.stage = (aligned16(D.ci) && aligned16(D.va64)) ? 1 : 0;
         spk::SlotState &S = srv->h_state[free_slot];
         std::memset(&S, 0, sizeof(S));
         S.phase = spk::PH_OUTER;
@@ -235,6 +253,8 @@ bool admit(spk_server srv) {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stats.admitted += 1;
         srv->stats.peak_bytes = std::max<int64_t>(srv->stats.peak_bytes, static_cast<int64_t>(srv->bytes_in_use));
+        srv->stats.peak_device_bytes = std::max<int64_t>(
+            srv->stats.peak_device_bytes, static_cast<int64_t>(srv->pool.in_use() + srv->pool.cached()));
     }
     return changed;
 }
@@ -379,11 +399,8 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
     spk_solver_cfg c;
     if (cfg) c = *cfg;
     else spk_solver_cfg_default(&c);
-    if (c.solver != SPK_SOLVER_CG || c.precond != SPK_PRECOND_NONE) return SPK_ERR_UNSUPPORTED;
-    if (c.precision != SPK_PREC_MIXED_FP32) return SPK_ERR_UNSUPPORTED;
-    if (!(c.reduction_factor >= 0.0) || !(c.inner_reduction > 0.0) || c.inner_reduction >= 1.0 || c.max_iters < 0 ||
-        c.max_outer < 0)
-        return SPK_ERR_INVALID_ARG;
+    if (!cfg_supported(c)) return SPK_ERR_UNSUPPORTED;
+    if (!cfg_valid(c)) return SPK_ERR_INVALID_ARG;
     const int dev = spk::ctx_device(ctx);
     if (hipSetDevice(dev) != hipSuccess) return SPK_ERR_DEVICE;
     spk_server srv = new spk_server_s();
@@ -391,6 +408,9 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
     srv->budget = hbm_budget_bytes;
     srv->max_slots = max_slots;
     srv->cfg = c;
+    // the budget bounds the device memory the request pool holds, cached
+    // blocks included (exact-size reuse, so a request's charge is its block)
+    srv->pool.set_budget_mode(true);
     srv->pool.set_cap(hbm_budget_bytes);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -439,7 +459,15 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
 }
 
 spk_status spk_server_submit(spk_server srv, const spk_csr *A, const void *b, void *x, uint64_t *ticket) {
+    return spk_server_submit_cfg(srv, A, b, x, nullptr, ticket);
+}
+
+spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b, void *x, const spk_solver_cfg *cfg,
+                                 uint64_t *ticket) {
     if (!srv || !A || !ticket) return SPK_ERR_INVALID_ARG;
+    const spk_solver_cfg &c = cfg ? *cfg : srv->cfg;
+    if (cfg && !cfg_supported(c)) return SPK_ERR_UNSUPPORTED;
+    if (cfg && !cfg_valid(c)) return SPK_ERR_INVALID_ARG;
     if (A->n_rows != A->n_cols || A->n_rows < 1 || A->nnz < 0) return SPK_ERR_INVALID_ARG;
     if (A->ptr_type != SPK_I32 || A->idx_type != SPK_I32 || A->val_type != SPK_F64) return SPK_ERR_UNSUPPORTED;
     if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values)) || !b || !x) return SPK_ERR_INVALID_ARG;
@@ -451,6 +479,10 @@ spk_status spk_server_submit(spk_server srv, const spk_csr *A, const void *b, vo
     r.b = static_cast<const double *>(b);
     r.x = static_cast<double *>(x);
     r.submit_ns = now_ns();
+    r.tau = c.reduction_factor;
+    r.tau_in = c.inner_reduction;
+    r.max_iters = c.max_iters;
+    r.max_outer = c.max_outer;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stopping) return SPK_ERR_INVALID_ARG;

@@ -165,7 +165,15 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
         using I = pointee_t<decltype(ci)>;
         const V *va = static_cast<const V *>(A.va);
         const dim3 grid(t.grid), block(kBlock);
-        if (t.kind == 0 && t.codes && A.codes && t.pack && A.rowpack) {
+        // the LDS tiles DMA the values (and the plain column indices) in
+        // 16-byte chunks; arrays without that alignment take one lane per
+        // row, which sums each row in the same order
+        auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+        const bool coded = t.kind == 0 && t.codes && A.codes;
+        if (t.kind == 0 && !(al16(A.va) && (coded || al16(A.ci)))) {
+            hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x, 0,
+                               t.xcd_remap, t.nt, epi);
+        } else if (t.kind == 0 && t.codes && A.codes && t.pack && A.rowpack) {
             hipLaunchKernelGGL((k_spmv_stream<V, RowPack, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz,
                                static_cast<const RowPack *>(A.rowpack), static_cast<const Code8 *>(A.codes), va, x,
                                t.xcd_remap, t.nt, t.pf, epi);

@@ -82,7 +82,8 @@ class PlanInfo(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("failed", ctypes.c_int64), ("ticks", ctypes.c_int64), ("peak_slots", ctypes.c_int64),
-                ("peak_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int64)]
+                ("peak_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int64),
+                ("peak_device_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +114,7 @@ _SIGS = {
     "spk_server_request_bytes": (_sz, [_i64, _i64]),
     "spk_server_create": (ctypes.c_int, [_vp, _sz, _i32, _P(SolverCfg), _P(_vp)]),
     "spk_server_submit": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(ctypes.c_uint64)]),
+    "spk_server_submit_cfg": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(SolverCfg), _P(ctypes.c_uint64)]),
     "spk_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(_i32), _P(Log), _P(_i64)]),
     "spk_server_drain": (ctypes.c_int, [_vp]),
     "spk_server_get_stats": (ctypes.c_int, [_vp, _P(ServerStats)]),
@@ -348,14 +350,20 @@ def spk_server_create(ctx: Context, hbm_budget_bytes: int, max_slots: int, cfg: 
     return Server(h)
 
 
-def spk_server_submit(srv: Server, A: CsrMatrix, b, x) -> int:
+def spk_server_submit(srv: Server, A: CsrMatrix, b, x, cfg: SolverCfg | None = None) -> int:
+    """Queue a solve; cfg (optional) is this request's own configuration (spk_server_submit_cfg)."""
     if b.numel() != A.desc.n_rows or x.numel() != A.desc.n_rows:
         raise ValueError("b and x must have n entries")
     if str(b.dtype) != "torch.float64" or str(x.dtype) != "torch.float64":
         raise ValueError("b and x must be float64")
     t = ctypes.c_uint64()
-    _server_check(_lib.spk_server_submit(srv.handle, ctypes.byref(A.desc), _dev_ptr(b, "b"), _dev_ptr(x, "x"),
-                                         ctypes.byref(t)), srv)
+    if cfg is None:
+        st = _lib.spk_server_submit(srv.handle, ctypes.byref(A.desc), _dev_ptr(b, "b"), _dev_ptr(x, "x"),
+                                    ctypes.byref(t))
+    else:
+        st = _lib.spk_server_submit_cfg(srv.handle, ctypes.byref(A.desc), _dev_ptr(b, "b"), _dev_ptr(x, "x"),
+                                        ctypes.byref(cfg), ctypes.byref(t))
+    _server_check(st, srv)
     srv.keep[t.value] = (A, b, x)
     return t.value
 

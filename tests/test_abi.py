@@ -52,6 +52,8 @@ int main(void) {
   printf("SPK_SOLVER_CGS %d\nSPK_PRECOND_JACOBI %d\nSPK_EXEC_PERSISTENT %d\nSPK_PREC_MIXED_BF16 %d\n",
          (int)SPK_SOLVER_CGS, (int)SPK_PRECOND_JACOBI, (int)SPK_EXEC_PERSISTENT, (int)SPK_PREC_MIXED_BF16);
   printf("SPK_PREC_MIXED_FP16 %d\n", (int)SPK_PREC_MIXED_FP16);
+  printf("spk_server_stats %zu\n", sizeof(spk_server_stats));
+  P(spk_server_stats, peak_device_bytes)
   return 0;
 }
 """
@@ -69,6 +71,8 @@ def test_struct_layouts_match_header(tmp_path):
     assert int(got["spk_log"]) == ctypes.sizeof(spk.Log)
     assert int(got["spk_plan_info"]) == ctypes.sizeof(spk.PlanInfo)
     assert int(got["spk_coo"]) == ctypes.sizeof(spk.Coo)
+    assert int(got["spk_server_stats"]) == ctypes.sizeof(spk.ServerStats)
+    assert int(got["spk_server_stats.peak_device_bytes"]) == spk.ServerStats.peak_device_bytes.offset
     pairs = [("spk_csr.values", spk.Csr.values), ("spk_csr.ptr_type", spk.Csr.ptr_type),
              ("spk_solver_cfg.max_iters", spk.SolverCfg.max_iters),
              ("spk_solver_cfg.reduction_factor", spk.SolverCfg.reduction_factor),

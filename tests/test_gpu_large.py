@@ -6,11 +6,15 @@ refinement reading the same FP32 values.
 * C5' (N = 256, n = 16.8M): full solution parity with the FP64 oracle,
   1e-10 relative (kappa_G <= 13 and tau = 1e-12, as for the mixed solve).
 * C5 (N = 1048, n = 1.15e9, nnz = 8.05e9, ~110 GB of HBM): the oracle cannot
-  hold the system, so parity is checked on sampled rows: the device matrix
-  rows and b equal the host generator's, and the residual of each sampled row,
-  recomputed on the host in FP64 from the generator's row and the GPU's x,
-  is within tau ||b||, as the global FP64 stop test requires (parity
-  partially pinned at this size)."""
+  hold the assembled system, so it visits the matrix block by block, taking
+  each block's rows from the host generator (oracle.residual_norm_rows): the
+  FP64 residual norm ||b - A x|| of the GPU's x over all 1.15e9 rows must
+  meet the stop test (<= tau ||b||, 1% slack for the order the two sides
+  sum in) and agree with the true residual the GPU reports to 1e-3 relative
+  (the residual is ~1e-12 of ||b||, so each row's b_i - (A x)_i cancels to
+  ~1% and the two summation orders differ there).  Sampled device rows and b
+  also equal the host generator's bit for bit.  No oracle solution exists
+  at this size: x itself is compared with the oracle only at N = 256."""
 import numpy as np
 import pytest
 import torch
@@ -107,3 +111,21 @@ def test_c5_full_size_sampled_rows(spk, ctx):
         xv = x[torch.from_numpy(hc).to(DEV)].cpu().numpy()
         ri = bi - float(np.dot(hv, xv))
         assert abs(ri) <= TAU * bnorm
+    # the whole residual, matrix-free on the host
+    del rp, col, val
+    import time
+    t0 = time.time()
+    xh = x.cpu().numpy()
+    del x, b
+    torch.cuda.empty_cache()
+    bh = inputs.rhs(n, seed)
+    print("x and b on the host, %.1f s" % (time.time() - t0), flush=True)
+    step = 1 << 22
+    blocks = [(r, min(r + step, n)) for r in range(0, n, step)]
+    res = oracle.residual_norm_rows(blocks, lambda r0, r1: inputs.stencil7_block(N, seed, r0, r1, f32x=True),
+                                    bh, xh, threads=16)
+    print("oracle residual %.6e, GPU %.6e, tau*||b|| %.6e (%.1f s)" %
+          (res, log.true_resnorm, TAU * np.linalg.norm(bh), time.time() - t0), flush=True)
+    assert abs(np.linalg.norm(bh) - bnorm) <= 1e-10 * bnorm
+    assert res <= TAU * bnorm * 1.01
+    assert abs(res - log.true_resnorm) <= 1e-3 * res

@@ -104,6 +104,7 @@ def test_budget_and_slot_limits(spk, ctx):
     stats = spk.spk_server_get_stats(srv)
     spk.spk_server_destroy(srv)
     assert stats["peak_bytes"] <= budget and stats["completed"] == len(sizes)
+    assert 0 < stats["peak_device_bytes"] <= budget   # cached blocks included
     assert 2 <= stats["peak_slots"] <= budget // least < len(sizes)
     for (A, b, _, _, x), tk in zip(reqs, tickets):
         assert res[tk][0] == spk.OK
@@ -162,3 +163,107 @@ def test_log_uniform_mix(spk, ctx):
     for (A, b, _, _, x), tk in zip(reqs, tickets):
         assert res[tk][0] == spk.OK and res[tk][1].stop_reason == spk.STOP_CONVERGED
         check_oracle(A, b, x.cpu().numpy())
+
+
+def offset_view(t):
+    """The same entries in a buffer one element longer, starting at its second element."""
+    buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=DEV)
+    v = buf[1:]
+    v.copy_(t)
+    assert v.data_ptr() % 16 != 0
+    return v
+
+
+def test_misaligned_request_equals_aligned(spk, ctx):
+    """Column and value arrays off 16-byte alignment skip the LDS DMA; each
+    row is summed in the same order, so the result is the same bit for bit."""
+    A, b, M, bd, x = make_request(spk, 30000, 77)
+    rp, ci, va = M.tensors
+    Mm = spk.CsrMatrix(rp, offset_view(ci), offset_view(va), A.n_rows, A.n_cols)
+    xm = torch.zeros_like(x)
+    srv = server(spk, ctx)
+    t1 = spk.spk_server_submit(srv, M, bd, x)
+    t2 = spk.spk_server_submit(srv, Mm, bd, xm)
+    res = wait_all(spk, srv, [t1, t2])
+    spk.spk_server_destroy(srv)
+    assert res[t1][0] == spk.OK and res[t2][0] == spk.OK
+    assert res[t1][1].iterations == res[t2][1].iterations
+    assert np.array_equal(x.cpu().numpy().view(np.uint64), xm.cpu().numpy().view(np.uint64))
+    check_oracle(A, b, x.cpu().numpy())
+
+
+def test_per_request_configuration(spk, ctx):
+    """One server, one system, three requests: the server's tolerance, a
+    looser one and a tighter cap; each meets its own stop test."""
+    A, b, M, bd, x = make_request(spk, 50000, 78)
+    x_loose, x_cap = torch.zeros_like(x), torch.zeros_like(x)
+    srv = server(spk, ctx)
+    loose = spk.spk_solver_cfg_default()
+    loose.precision = spk.PREC_MIXED_FP32
+    loose.reduction_factor = 1e-6
+    loose.inner_reduction = 1e-3
+    loose.max_iters = 20000
+    cap = spk.spk_solver_cfg_default()
+    cap.precision = spk.PREC_MIXED_FP32
+    cap.reduction_factor = TAU
+    cap.max_iters = 20000
+    cap.max_outer = 1
+    t0 = spk.spk_server_submit(srv, M, bd, x)
+    t1 = spk.spk_server_submit(srv, M, bd, x_loose, loose)
+    t2 = spk.spk_server_submit(srv, M, bd, x_cap, cap)
+    bad = spk.spk_solver_cfg_default()       # FP64 precision: not what the server runs
+    with pytest.raises(spk.SpkError) as e:
+        spk.spk_server_submit(srv, M, bd, torch.zeros_like(x), bad)
+    assert e.value.status == spk.ERR_UNSUPPORTED
+    res = wait_all(spk, srv, [t0, t1, t2])
+    spk.spk_server_destroy(srv)
+    nb = np.linalg.norm(b)
+    r0 = np.linalg.norm(oracle.residual(A, b, x.cpu().numpy()))
+    r1 = np.linalg.norm(oracle.residual(A, b, x_loose.cpu().numpy()))
+    assert res[t0][1].stop_reason == spk.STOP_CONVERGED and r0 <= TAU * nb * 1.01
+    assert res[t1][1].stop_reason == spk.STOP_CONVERGED and r1 <= 1e-6 * nb * 1.01
+    assert res[t1][1].iterations < res[t0][1].iterations
+    assert res[t2][1].stop_reason == spk.STOP_MAX_ITERS and res[t2][1].outer_iterations == 1
+
+
+def test_full_serving_mix(spk, ctx):
+    """The full serving configuration: 256 randsym instances, n log-uniform in
+    [1e3, 1e6] (seed 4), all submitted at once under a 64 GB budget, every
+    result within 1e-10 of the oracle's FP64 solution (tau 1e-14); then the
+    same 256 requests under a 256 MB budget, which admits only a few large
+    ones at a time, must give the same solutions bit for bit."""
+    t0 = time.time()
+    mats, rhs = inputs.serving_mix(256, 4, 1e3, 1e6)
+    print("generated %d instances (sum n %d) in %.1f s" % (len(mats), sum(A.n_rows for A in mats), time.time() - t0),
+          flush=True)
+    reqs = []
+    for A, b in zip(mats, rhs):
+        M = spk.CsrMatrix(torch.from_numpy(A.row_ptr).to(torch.int32).to(DEV), torch.from_numpy(A.col).to(DEV),
+                          torch.from_numpy(A.val).to(DEV), A.n_rows, A.n_cols)
+        reqs.append((M, to_dev(b)))
+    outs = []
+    for budget, slots in ((64 << 30, 256), (256 << 20, 256)):
+        xs = [torch.zeros(A.n_rows, dtype=torch.float64, device=DEV) for A in mats]
+        srv = server(spk, ctx, budget=budget, slots=slots)
+        tickets = [spk.spk_server_submit(srv, M, bd, x) for (M, bd), x in zip(reqs, xs)]
+        res = wait_all(spk, srv, tickets, timeout=120.0)
+        stats = spk.spk_server_get_stats(srv)
+        spk.spk_server_destroy(srv)
+        print("budget %d MB: peak slots %d, peak device bytes %d, ticks %d, %.1f s" %
+              (budget >> 20, stats["peak_slots"], stats["peak_device_bytes"], stats["ticks"], time.time() - t0),
+              flush=True)
+        assert stats["completed"] == 256 and stats["peak_device_bytes"] <= budget
+        for tk in tickets:
+            assert res[tk][0] == spk.OK and res[tk][1].stop_reason == spk.STOP_CONVERGED
+        outs.append([x.cpu().numpy() for x in xs])
+        if budget == 256 << 20:
+            assert stats["peak_slots"] < 256
+    for a, b2 in zip(outs[0], outs[1]):
+        assert np.array_equal(a.view(np.uint64), b2.view(np.uint64))
+    sols = oracle.cg_many(list(zip(mats, rhs)), tau=1e-14, max_iters=5000)
+    print("oracle solves done, %.1f s" % (time.time() - t0), flush=True)
+    errs = [rel(x, xo) for x, (xo, _) in zip(outs[0], sols)]
+    print("max error vs oracle %.3g" % max(errs), flush=True)
+    assert max(errs) <= 1e-10
+    for A, b, x in zip(mats, rhs, outs[0]):
+        assert np.linalg.norm(oracle.residual(A, b, x)) <= TAU * np.linalg.norm(b) * 1.01
