@@ -277,6 +277,31 @@ spk_status spk_plan_kernel_stats(spk_plan plan, double *total_ms, int64_t *launc
 /* Release a plan and everything it derived.  NULL is a no-op. */
 spk_status spk_free(spk_plan plan);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one FP64
+ * CG solve of A x = b (plan + execute + free in one call) whose workspace is
+ * a fixed scratch array the library holds on each GPU until the process
+ * ends, so the call makes no hipMalloc, hipFree or other allocating call.
+ * cfg (NULL = defaults) must ask for CG, FP64, no preconditioner, AUTO or
+ * HOST_LOOP execution and no history.  A: square, F64 values, at most
+ * spk_noalloc_max_rows() rows (the scratch holds the solve state, the
+ * reduction partials and three vectors of n doubles); the caller's arrays
+ * are borrowed for the call only.  b and x as for spk_execute_solve.  The
+ * launch shape is one an earlier plan of the same shape tuned on this
+ * context (never tuned here), else the heuristic one, so a solve after such
+ * a plan runs the same kernels and gives the same result.  Every call on one
+ * GPU shares that GPU's scratch, which keeps the last call's contents (the
+ * call clears what must start at zero): calls that overlap on one GPU, from
+ * any context or stream, race and must not be issued.  Synchronises the
+ * context stream before returning.
+ * Errors: INVALID_ARG (malformed or non-square A, too many rows, null
+ * vectors), UNSUPPORTED (other configurations), DEVICE. */
+spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg, const void *b, void *x,
+                             spk_log *log);
+
+/* Largest n_rows spk_solve_noalloc accepts (its scratch is 64 MiB per GPU). */
+int64_t spk_noalloc_max_rows(void);
+
 /* Plain device-to-device copy of bytes (multiple of 16, 16-byte aligned
  * pointers) with the library's streaming copy kernel; *ms receives its
  * device time.  Used to measure the achievable HBM bandwidth. */

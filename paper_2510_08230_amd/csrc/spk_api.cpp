@@ -61,6 +61,11 @@ struct spk_ctx_s {
     spk::DevicePool dpool;              // plan workspace cache
     spk::PinnedPool hpool;              // pinned status mirrors
     int live_plans = 0;
+    // allocation-free solves: this device's scratch array (address looked up
+    // at spk_init) and a pinned status mirror made at spk_init
+    void *scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
+    SolveState *h_noalloc_st = nullptr;
 };
 
 struct spk_plan_s {
@@ -744,10 +749,15 @@ spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&ctx->d_flags, sizeof(unsigned)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->h_noalloc_st), sizeof(SolveState), hipHostMallocDefault) !=
+            hipSuccess) {
         spk_finalize(ctx);
         return SPK_ERR_DEVICE;
     }
+    // the scratch array's device address on this device (kept per device); a
+    // failed lookup only disables spk_solve_noalloc
+    ctx->scratch_err = spk::noalloc_scratch_setup(device_id, &ctx->scratch);
     *out = ctx;
     return SPK_OK;
 }
@@ -762,6 +772,7 @@ spk_status spk_finalize(spk_ctx ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    if (ctx->h_noalloc_st) (void)hipHostFree(ctx->h_noalloc_st);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -1343,6 +1354,105 @@ spk_status spk_execute_solve(spk_plan pl, const void *b_in, void *x_in, spk_log 
                        ? execute_fp64(pl, static_cast<const double *>(b_in), static_cast<double *>(x_in), &L, graph)
                        : execute_mixed(pl, static_cast<const double *>(b_in), static_cast<double *>(x_in), &L, graph);
     if (s != SPK_OK) return s;
+    SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    SPK_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    L.converged = L.stop_reason == SPK_STOP_CONVERGED;
+    L.elapsed_ms = ms;
+    if (log) *log = L;
+    return SPK_OK;
+}
+
+// Scratch layout of an allocation-free solve: the solve state, the reduction
+// partials, then r, p and q (each 256-byte aligned).
+static constexpr size_t kNaPartialBytes = sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid;
+static constexpr size_t na_align(size_t v) { return (v + 255) & ~size_t(255); }
+static constexpr size_t kNaVecBase = na_align(sizeof(SolveState)) + na_align(kNaPartialBytes);
+
+int64_t spk_noalloc_max_rows(void) {
+    // three vectors of n doubles, each rounded up to 256 bytes
+    return static_cast<int64_t>((spk::kNoallocScratchBytes - kNaVecBase) / (3 * sizeof(double))) - 32;
+}
+
+spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg_in, const void *b_in,
+                             void *x_in, spk_log *log) {
+    if (!ctx) return SPK_ERR_INVALID_ARG;
+    spk_solver_cfg cfg;
+    if (cfg_in) cfg = *cfg_in;
+    else spk_solver_cfg_default(&cfg);
+    if (cfg.solver != SPK_SOLVER_CG || cfg.precond != SPK_PRECOND_NONE || cfg.precision != SPK_PREC_FP64)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "allocation-free solve: FP64 CG without a preconditioner only");
+    if (cfg.exec_mode != SPK_EXEC_AUTO && cfg.exec_mode != SPK_EXEC_HOST_LOOP)
+        return fail(ctx, SPK_ERR_UNSUPPORTED, "allocation-free solve: host-loop execution only");
+    if (cfg.record_history) return fail(ctx, SPK_ERR_UNSUPPORTED, "allocation-free solve keeps no history");
+    if (cfg.baseline != SPK_BASELINE_RHS_NORM) return fail(ctx, SPK_ERR_UNSUPPORTED, "only the rhs_norm baseline");
+    if (cfg.max_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_iters < 0");
+    if (!(cfg.reduction_factor >= 0.0)) return fail(ctx, SPK_ERR_INVALID_ARG, "reduction_factor must be >= 0");
+    if (cfg.chunk_iters < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "chunk_iters < 0");
+    spk_status s = check_csr_args(ctx, A);
+    if (s != SPK_OK) return s;
+    if (A->n_rows != A->n_cols) return fail(ctx, SPK_ERR_INVALID_ARG, "solve needs a square matrix");
+    if (A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
+    const int64_t n = A->n_rows;
+    if (n > spk_noalloc_max_rows())
+        return fail(ctx, SPK_ERR_INVALID_ARG,
+                    "allocation-free solve: " + std::to_string(n) + " rows exceed the scratch limit of " +
+                        std::to_string(spk_noalloc_max_rows()));
+    if (n > 0 && (!b_in || !x_in)) return fail(ctx, SPK_ERR_INVALID_ARG, "null vector");
+    if (!ctx->scratch)
+        return fail(ctx, SPK_ERR_DEVICE,
+                    std::string("allocation-free solve: scratch address lookup failed: ") +
+                        hipGetErrorString(ctx->scratch_err));
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    int32_t verdict = 0;
+    if ((s = gpu_verdict(ctx, A, &verdict)) != SPK_OK) return s;
+    if (verdict != SPK_CSR_OK) return fail(ctx, SPK_ERR_INVALID_ARG, std::string("malformed CSR: ") + verdict_name(verdict));
+    spk_log L;
+    std::memset(&L, 0, sizeof(L));
+    if (n == 0) {
+        L.converged = 1;
+        L.stop_reason = SPK_STOP_CONVERGED;
+        if (log) *log = L;
+        return SPK_OK;
+    }
+    // a plan on the stack whose workspace is the scratch array (its maps and
+    // vectors stay empty: no graphs, no profiling events)
+    spk_plan_s pl;
+    pl.ctx = ctx;
+    pl.kind = 1;
+    pl.A = to_dev(A);
+    pl.cfg = cfg;
+    pl.algo = ALGO_CG;
+    char *base = static_cast<char *>(ctx->scratch);
+    const size_t vb = na_align(sizeof(double) * static_cast<size_t>(n));
+    pl.st = reinterpret_cast<SolveState *>(base);
+    pl.partials = reinterpret_cast<double *>(base + na_align(sizeof(SolveState)));
+    pl.r = reinterpret_cast<double *>(base + kNaVecBase);
+    pl.p = reinterpret_cast<double *>(base + kNaVecBase + vb);
+    pl.q = reinterpret_cast<double *>(base + kNaVecBase + 2 * vb);
+    pl.h_st = ctx->h_noalloc_st;
+    std::memset(pl.h_st, 0, sizeof(SolveState));
+    const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
+    pl.vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 4));
+    // the launch shape an earlier plan of this shape tuned (read from the
+    // context's cache, never added to it), else the heuristic one
+    const TuneKey key{pl.A.n_rows, pl.A.n_cols, pl.A.nnz, pl.A.ptr_t, pl.A.idx_t, pl.A.val_t, TUNE_CG, false,
+                      stream_ok(pl.A)};
+    if (!forced_tune(ctx, pl.A, &pl.tune)) {
+        auto hit = ctx->tune_cache.find(key);
+        pl.tune = hit != ctx->tune_cache.end() && pl.A.nnz >= 100000 ? hit->second.tune : heuristic_tune(ctx, pl.A);
+    }
+    pl.info.exec_mode = SPK_EXEC_HOST_LOOP;
+    // the scratch keeps the last call's contents: clear the state and p by kernel
+    SPK_HIP(ctx, spk::launch_fill_zero(pl.st, na_align(sizeof(SolveState)), ctx->num_cu, ctx->stream));
+    SPK_HIP(ctx, spk::launch_fill_zero(pl.p, vb, ctx->num_cu * 4, ctx->stream));
+    SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    s = execute_fp64(&pl, static_cast<const double *>(b_in), static_cast<double *>(x_in), &L, false);
+    if (s != SPK_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        return s;
+    }
     SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
     float ms = 0.f;

@@ -16,6 +16,9 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
 constexpr int kTileRows = 256;     // rows per SpMV tile
 constexpr int kMaxGrid = 8192;     // cap on workgroups of any grid-stride launch
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, workgroups dispatched round-robin
+// Device scratch of the allocation-free solve (one array per GPU, held until
+// the process ends): solve state, reduction partials and three FP64 vectors.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
 
 enum Stop : int32_t {
     STOP_RUNNING = 0,

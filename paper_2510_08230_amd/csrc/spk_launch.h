@@ -71,6 +71,14 @@ hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s);
 
+// Allocation-free solves (spk_noalloc.hip).  noalloc_scratch_setup: device
+// address of this device's scratch array (kNoallocScratchBytes), looked up
+// once per device with the device current; later calls return the kept
+// address (and the first lookup's error).  launch_fill_zero: bytes (a
+// multiple of 16, 16-byte aligned) set to zero by a kernel.
+hipError_t noalloc_scratch_setup(int device, void **addr);
+hipError_t launch_fill_zero(void *p, size_t bytes, int grid, hipStream_t s);
+
 // CGS (FP64; spk_krylov.hip).  Iteration j of a chunk = dir(j), spmv_v,
 // update(j), spmv_r; a chunk of c iterations ends with check(c).  The initial
 // residual is launch_cg_init with the shadow residual rt in place of p.

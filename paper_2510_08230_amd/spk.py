@@ -111,6 +111,8 @@ _SIGS = {
     "spk_plan_kernel_stats": (ctypes.c_int, [_vp, _P(_f64), _P(_i64)]),
     "spk_free": (ctypes.c_int, [_vp]),
     "spk_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, _sz, _P(_f64)]),
+    "spk_solve_noalloc": (ctypes.c_int, [_vp, _P(Csr), _P(SolverCfg), _vp, _vp, _P(Log)]),
+    "spk_noalloc_max_rows": (_i64, []),
     "spk_server_request_bytes": (_sz, [_i64, _i64]),
     "spk_server_create": (ctypes.c_int, [_vp, _sz, _i32, _P(SolverCfg), _P(_vp)]),
     "spk_server_submit": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(ctypes.c_uint64)]),
@@ -285,6 +287,24 @@ def spk_execute_solve(plan: Plan, b, x) -> Log:
     log = Log()
     _check(_lib.spk_execute_solve(plan.handle, _dev_ptr(b, "b"), _dev_ptr(x, "x"), ctypes.byref(log)), plan.ctx)
     return log
+
+
+def spk_solve_noalloc(ctx: Context, A: CsrMatrix, b, x, cfg: SolverCfg | None = None) -> Log:
+    """One FP64 CG solve whose workspace is the library's fixed scratch array
+    (no device allocation in the call)."""
+    if b.numel() != A.desc.n_rows or x.numel() != A.desc.n_rows:
+        raise ValueError("b and x must have n entries")
+    if str(b.dtype) != "torch.float64" or str(x.dtype) != "torch.float64":
+        raise ValueError("b and x must be float64")
+    log = Log()
+    c = ctypes.byref(cfg) if cfg is not None else None
+    _check(_lib.spk_solve_noalloc(ctx.handle, ctypes.byref(A.desc), c, _dev_ptr(b, "b"), _dev_ptr(x, "x"),
+                                  ctypes.byref(log)), ctx)
+    return log
+
+
+def spk_noalloc_max_rows() -> int:
+    return int(_lib.spk_noalloc_max_rows())
 
 
 def spk_plan_history(plan: Plan) -> np.ndarray:
