@@ -127,6 +127,12 @@ def _get():
         lib.gen_vec.argtypes = [i64, u64, u64, vp]
         lib.gen_instances.restype = None
         lib.gen_instances.argtypes = [i64, u64, f64, f64, vp, vp]
+        lib.gen_powerlaw_max_nnz.restype = i64
+        lib.gen_powerlaw_max_nnz.argtypes = [i64, i32, i64, i64]
+        lib.gen_powerlaw.restype = i64
+        lib.gen_powerlaw.argtypes = [i64, u64, f64, i32, i64, i64, i64, i32, vp, vp, vp]
+        lib.gen_powerlaw_hub.restype = None
+        lib.gen_powerlaw_hub.argtypes = [i64, u64, i64, i64, i64, vp, vp]
         _lib = lib
     return _lib
 
@@ -208,6 +214,31 @@ def randsym(n: int, seed: int, delta: float = 1.0, deg: int = 3, f32x: bool = Fa
     if nnz < 0:
         raise ValueError("randsym: bad arguments or out of memory (%d)" % nnz)
     return CSR(n, n, rp, col[:nnz].copy(), val[:nnz].copy())
+
+
+def powerlaw(n: int, seed: int, hubs: int = 16, lo: int = 1000, hi: int = 10000, delta: float = 1.0,
+             deg: int = 3, f32x: bool = False) -> CSR:
+    """randsym(n) plus `hubs` hub rows of lo..hi partners (log-uniform): a
+    heavy-tailed row-length mix (symmetric, diagonally dominant, SPD)."""
+    cap = int(_get().gen_powerlaw_max_nnz(n, deg, hubs, hi))
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(cap, np.int32)
+    val = np.empty(cap, np.float64)
+    nnz = int(_get().gen_powerlaw(n, seed, float(delta), deg, hubs, lo, hi, int(f32x), _p(rp), _p(col), _p(val)))
+    if nnz < 0:
+        raise ValueError("powerlaw: bad arguments or out of memory (%d)" % nnz)
+    return CSR(n, n, rp, col[:nnz].copy(), val[:nnz].copy())
+
+
+def powerlaw_hubs(n: int, seed: int, hubs: int = 16, lo: int = 1000, hi: int = 10000):
+    """(row, partner draws) of every hub of powerlaw(n, seed, hubs, lo, hi)."""
+    out = []
+    r = ctypes.c_int64()
+    d = ctypes.c_int64()
+    for h in range(hubs):
+        _get().gen_powerlaw_hub(n, seed, h, lo, hi, ctypes.byref(r), ctypes.byref(d))
+        out.append((r.value, d.value))
+    return out
 
 
 def randsym_many(specs, threads: int = 0):

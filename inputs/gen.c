@@ -15,7 +15,8 @@
  *   uniform in [-1,1), FP32-exact: v = (h >> 40) * 2^-23 - 1    (exact in FP32)
  *
  * Streams: 0 off-diagonal matrix values, 1 randsym partner draws, 2 right-hand
- * side, 3 per-instance seeds, 4 per-instance sizes.
+ * side, 3 per-instance seeds, 4 per-instance sizes, 5 hub rows and their
+ * lengths, 6 hub partner draws.
  *
  * Matrix patterns (the paper's test sets are SuiteSparse matrices with
  * dimension up to 1e6, density below 1%, and 0.6-41 nonzeros per row,
@@ -25,6 +26,12 @@
  *     between i and its + neighbour in direction d (0:x,1:y,2:z) has id 3*i+d.
  *   randsym(n): row i draws 3 partners j uniform over [0,n) \ {i}; the pattern
  *     is symmetrised, sorted and merged.  Edge {i,j} has id min*n + max.
+ *   powerlaw(n, hubs, lo, hi): randsym(n) plus `hubs` hub rows: hub h sits at
+ *     row v(5, 2h) mod n and draws m_h partners (m_h log-uniform in [lo, hi]
+ *     from v(5, 2h+1)), partner t uniform over [0,n) \ {hub} from stream 6,
+ *     counter h * 2^32 + t; symmetrised and merged like randsym, so each hub
+ *     row holds up to m_h + 7 entries and its partners one more each (the
+ *     heavy-tailed row lengths of Table 2's circuit and mesh matrices).
  * Values: a_ij = a_ji = v(seed, 0, edge id); a_ii = sum_{j != i} |a_ij| + delta
  * accumulated in ascending column order in FP64, so A is symmetric and
  * strictly diagonally dominant with positive diagonal, hence SPD.
@@ -199,33 +206,24 @@ static int cmp_i64(const void *a, const void *b) {
  */
 int64_t gen_randsym_max_nnz(int64_t n, int deg) { return n + 2 * (int64_t)deg * n; }
 
-int64_t gen_randsym(int64_t n, uint64_t seed, double delta, int deg, int f32x,
-                    int64_t *row_ptr, int32_t *col, double *val) {
-    if (n < 1 || deg < 0) return -1;
-    const int64_t m = (n >= 2) ? (int64_t)deg * n : 0; /* directed draws */
+/* Symmetric pattern from m directed draws (src[k], dst_of[k]) (both owned by
+ * the caller); values and diagonal as described at the top. */
+static int64_t build_sym(int64_t n, uint64_t seed, double delta, int f32x, int64_t m, const int64_t *src,
+                         const int64_t *tgt, int64_t *row_ptr, int32_t *col, double *val) {
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     int64_t *dst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
-    int64_t *partner = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
-    if (!cnt || !dst || !partner) { free(cnt); free(dst); free(partner); return -2; }
-    for (int64_t i = 0; i < n && m > 0; ++i)
-        for (int t = 0; t < deg; ++t) {
-            uint64_t r = gen_hash(seed, 1, (uint64_t)deg * (uint64_t)i + (uint64_t)t);
-            int64_t j = (int64_t)(r % (uint64_t)(n - 1));
-            if (j >= i) j += 1;
-            partner[(int64_t)deg * i + t] = j;
-            cnt[i + 1]++; cnt[j + 1]++;
-        }
+    if (!cnt || !dst) { free(cnt); free(dst); return -2; }
+    for (int64_t k = 0; k < m; ++k) { cnt[src[k] + 1]++; cnt[tgt[k] + 1]++; }
     for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];          /* exclusive scan */
     int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    if (!fill) { free(cnt); free(dst); free(partner); return -2; }
+    if (!fill) { free(cnt); free(dst); return -2; }
     memcpy(fill, cnt, sizeof(int64_t) * (size_t)n);
-    for (int64_t i = 0; i < n && m > 0; ++i)
-        for (int t = 0; t < deg; ++t) {
-            int64_t j = partner[(int64_t)deg * i + t];
-            dst[fill[i]++] = j;
-            dst[fill[j]++] = i;
-        }
-    free(fill); free(partner);
+    for (int64_t k = 0; k < m; ++k) {
+        const int64_t i = src[k], j = tgt[k];
+        dst[fill[i]++] = j;
+        dst[fill[j]++] = i;
+    }
+    free(fill);
     int64_t k = 0;
     row_ptr[0] = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -252,6 +250,78 @@ int64_t gen_randsym(int64_t n, uint64_t seed, double delta, int deg, int f32x,
     }
     free(cnt); free(dst);
     return k;
+}
+
+/* the deg * n partner draws of randsym(n) into src/tgt[0 .. deg*n) */
+static void randsym_draws(int64_t n, uint64_t seed, int deg, int64_t *src, int64_t *tgt) {
+    for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < deg; ++t) {
+            uint64_t r = gen_hash(seed, 1, (uint64_t)deg * (uint64_t)i + (uint64_t)t);
+            int64_t j = (int64_t)(r % (uint64_t)(n - 1));
+            if (j >= i) j += 1;
+            src[(int64_t)deg * i + t] = i;
+            tgt[(int64_t)deg * i + t] = j;
+        }
+}
+
+int64_t gen_randsym(int64_t n, uint64_t seed, double delta, int deg, int f32x,
+                    int64_t *row_ptr, int32_t *col, double *val) {
+    if (n < 1 || deg < 0) return -1;
+    const int64_t m = (n >= 2) ? (int64_t)deg * n : 0; /* directed draws */
+    int64_t *src = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int64_t *tgt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    if (!src || !tgt) { free(src); free(tgt); return -2; }
+    if (m > 0) randsym_draws(n, seed, deg, src, tgt);
+    const int64_t k = build_sym(n, seed, delta, f32x, m, src, tgt, row_ptr, col, val);
+    free(src); free(tgt);
+    return k;
+}
+
+/* Hub h of powerlaw(n, ...): its row and its number of partner draws. */
+void gen_powerlaw_hub(int64_t n, uint64_t seed, int64_t h, int64_t lo, int64_t hi, int64_t *row, int64_t *draws) {
+    *row = (int64_t)(gen_hash(seed, 5, 2 * (uint64_t)h) % (uint64_t)n);
+    const double u = 0.5 * (gen_unif_f64(seed, 5, 2 * (uint64_t)h + 1) + 1.0);   /* [0, 1) */
+    int64_t m = (int64_t)llround(exp(log((double)lo) + u * (log((double)hi) - log((double)lo))));
+    if (m < lo) m = lo;
+    if (m > hi) m = hi;
+    *draws = m;
+}
+
+int64_t gen_powerlaw_max_nnz(int64_t n, int deg, int64_t hubs, int64_t hi) {
+    return n + 2 * (int64_t)deg * n + 2 * hubs * hi;
+}
+
+/* powerlaw(n, hubs, lo, hi): returns nnz, or -1 on bad arguments / -2 on
+ * allocation failure; col/val must hold gen_powerlaw_max_nnz entries. */
+int64_t gen_powerlaw(int64_t n, uint64_t seed, double delta, int deg, int64_t hubs, int64_t lo, int64_t hi, int f32x,
+                     int64_t *row_ptr, int32_t *col, double *val) {
+    if (n < 2 || deg < 0 || hubs < 0 || lo < 1 || hi < lo || hi > ((int64_t)1 << 32)) return -1;
+    int64_t m = (int64_t)deg * n;
+    for (int64_t h = 0; h < hubs; ++h) {
+        int64_t r, d;
+        gen_powerlaw_hub(n, seed, h, lo, hi, &r, &d);
+        m += d;
+    }
+    int64_t *src = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int64_t *tgt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    if (!src || !tgt) { free(src); free(tgt); return -2; }
+    randsym_draws(n, seed, deg, src, tgt);
+    int64_t k = (int64_t)deg * n;
+    for (int64_t h = 0; h < hubs; ++h) {
+        int64_t r, d;
+        gen_powerlaw_hub(n, seed, h, lo, hi, &r, &d);
+        for (int64_t t = 0; t < d; ++t) {
+            uint64_t x = gen_hash(seed, 6, ((uint64_t)h << 32) + (uint64_t)t);
+            int64_t j = (int64_t)(x % (uint64_t)(n - 1));
+            if (j >= r) j += 1;
+            src[k] = r;
+            tgt[k] = j;
+            ++k;
+        }
+    }
+    const int64_t nnz = build_sym(n, seed, delta, f32x, m, src, tgt, row_ptr, col, val);
+    free(src); free(tgt);
+    return nnz;
 }
 
 /* Right-hand side: b_i = v(seed, 2, i) in [-1,1). */

@@ -101,6 +101,29 @@ def test_randsym_degree_distribution():
     assert abs(deg.mean() - 7.0) < 0.05 and deg.min() >= 2
 
 
+def test_powerlaw_structure_and_hubs():
+    """randsym plus hub rows: symmetric, strictly dominant (SPD), the hub rows
+    hold their drawn partners (minus duplicates) and every other row stays
+    randsym-like; the randsym part is the same pattern as randsym(n)."""
+    n, seed = 20000, 3
+    A = inputs.powerlaw(n, seed, hubs=8, lo=500, hi=4000)
+    _check_spd_structure(A, 1.0)
+    deg = np.diff(A.row_ptr)
+    hubs = inputs.powerlaw_hubs(n, seed, hubs=8, lo=500, hi=4000)
+    rows = {r for r, _ in hubs}
+    for r, d in hubs:
+        assert 500 <= d <= 4000
+        assert deg[r] >= 0.9 * d          # duplicates among the draws are merged
+    others = np.array([i for i in range(n) if i not in rows])
+    assert deg[others].max() < 60 and abs(deg[others].mean() - 7.0) < 0.6
+    # removing the hub draws leaves randsym: every randsym entry is present
+    R = inputs.randsym(n, seed)
+    for i in range(0, n, 997):
+        assert set(R.col[R.row_ptr[i]:R.row_ptr[i + 1]]) <= set(A.col[A.row_ptr[i]:A.row_ptr[i + 1]])
+    B = inputs.powerlaw(n, seed, hubs=8, lo=500, hi=4000)
+    assert np.array_equal(A.col, B.col) and np.array_equal(A.val.view(np.uint64), B.val.view(np.uint64))
+
+
 def test_rhs_and_instances():
     b = inputs.rhs(1000, 4)
     assert np.all((b >= -1) & (b < 1)) and abs(b.mean()) < 0.1
