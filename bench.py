@@ -64,8 +64,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=215, help="stencil7 grid edge (n = N^3)")
-    ap.add_argument("--pattern", choices=["stencil7", "randsym"], default="stencil7",
-                    help="solve-mode matrix: stencil7 N (default) or randsym n (CG only)")
+    ap.add_argument("--pattern", choices=["stencil7", "randsym", "powerlaw"], default="stencil7",
+                    help="solve-mode matrix: stencil7 N (default), randsym n or powerlaw n (randsym plus 16 hub "
+                         "rows of 1e3..1e4 entries; CG only)")
     ap.add_argument("--n", type=int, default=10_000_000, help="randsym dimension")
     ap.add_argument("--delta", type=float, default=1.0,
                     help="diagonal margin: a_ii = sum |a_ij| + delta (1e-2 gives the harder system)")
@@ -194,11 +195,12 @@ def main():
     if (cgs or args.precond != "none") and args.precision != "fp64":
         print("CGS and the Jacobi preconditioner run in FP64 only", file=sys.stderr)
         sys.exit(2)
-    if args.pattern == "randsym":
+    if args.pattern in ("randsym", "powerlaw"):
         if cgs or gm:
-            print("the randsym pattern is symmetric: use it with CG", file=sys.stderr)
+            print("the randsym and powerlaw patterns are symmetric: use them with CG", file=sys.stderr)
             sys.exit(2)
-        A = inputs.randsym(args.n, args.seed, delta=args.delta)
+        A = (inputs.randsym(args.n, args.seed, delta=args.delta) if args.pattern == "randsym" else
+             inputs.powerlaw(args.n, args.seed, delta=args.delta))
     elif cgs or gm:
         A = inputs.stencil7_ns(N, args.seed, delta=args.delta)
     else:
@@ -261,19 +263,22 @@ def main():
     # index bytes: int32 columns and row pointers, or the plan's column codes
     # and packed row pointers
     idx = index_bytes(info, n, nnz, 4)
+    # vectors of the dominant kernel: the SpMV reads p and writes q (2n); the
+    # fused CG step reads r, q, p (gathered) and x and writes x, r, p, q (8n)
+    nvec = 8 if info.get("fused_loop") else 2
     if args.precision == "fp64":
-        bytes_spmv = nnz * 8 + idx + 2 * n * 8
+        bytes_spmv = nnz * 8 + idx + nvec * n * 8
     else:   # inner SpMV: FP32/BF16 values, int32 columns, FP32 vectors
         vb = 4 if args.precision == "mixed_fp32" else 2
-        bytes_spmv = nnz * vb + idx + 2 * n * 4
+        bytes_spmv = nnz * vb + idx + nvec * n * 4
     avg_ms = kms / klaunch if klaunch else None
     achieved = bytes_spmv / (avg_ms * 1e-3) / 1e9 if avg_ms else None
     last = logs[-1]
     traffic = measured_traffic(args, N, info)
     jname = "_jacobi" if args.precond == "jacobi" else ""
     dname = "" if args.delta == 1.0 else "_delta%g" % args.delta
-    mname = ("randsym_n%d" % n) if args.pattern == "randsym" else ("stencil7ns_N%d" if (cgs or gm) else
-                                                                 "stencil7_N%d") % N
+    mname = ("%s_n%d" % (args.pattern, n)) if args.pattern in ("randsym", "powerlaw") else (
+        "stencil7ns_N%d" if (cgs or gm) else "stencil7_N%d") % N
     if cgs:
         workload = "cgs%s_fp64_%s" % (jname, mname)
         spmv_kernel = "k_spmv_*<EpiCgsV>, k_spmv_*<EpiCgsR> (two SpMVs per CGS iteration)"
@@ -283,7 +288,9 @@ def main():
             "" if args.precision == "fp64" else "; inner GMRES of the refinement")
     else:
         workload = "%s_%s_%s" % ("pcg_jacobi" if args.precond == "jacobi" else "cg", args.precision, mname)
-        spmv_kernel = "k_spmv_*<EpiPq> (q = A p fused with p.q)"
+        spmv_kernel = ("k_spmv_*<EpiFcg> (one CG step: p formed from r, q, p at every gathered column, q = A p, "
+                       "x, r, p, q stored, four dot products)" if info.get("fused_loop") else
+                       "k_spmv_*<EpiPq> (q = A p fused with p.q)")
     workload += dname
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
@@ -300,6 +307,8 @@ def main():
                   "mixed_fp16": "f16+f32+f64"}[args.precision],
         "data": ("synthetic (seeded randsym: 3 uniform partners per row, symmetrised, uniform[-1,1) values, "
                  "diagonally dominant SPD, delta %g)" % args.delta if args.pattern == "randsym" else
+                 "synthetic (seeded powerlaw: randsym plus 16 hub rows of 1e3..1e4 partners, symmetrised, "
+                 "uniform[-1,1) values, diagonally dominant SPD, delta %g)" % args.delta if args.pattern == "powerlaw" else
                  "synthetic (seeded nonsymmetric stencil7, independent uniform[-1,1) off-diagonals, "
                  "row diagonally dominant, delta %g)" % args.delta if (cgs or gm) else
                  "synthetic (seeded stencil7, uniform[-1,1) off-diagonals, diagonally dominant SPD, "
@@ -318,14 +327,15 @@ def main():
     # (2 nnz flops per SpMV) over the timed steps, and for CG the whole
     # iteration's bytes against the floor nnz (S_v + S_i) + (n+1) S_p + 7 n S_x
     # (A once; p gathered once; x, r, p read and written once) and against the
-    # 10 n S_x of vectors the three launches move, over the last solve's device time.
+    # vectors the loop moves (10 n S_x in three launches per iteration, 8 n S_x
+    # in the one-launch fused step), over the last solve's device time.
     spmv_per_iter = 2 if cgs else 1
     spmvs = iters * spmv_per_iter
     derived = {"nnz_per_s": nnz * spmvs / wall, "gflop_per_s": 2.0 * nnz * spmvs / wall / 1e9}
     if not (cgs or gm) and last.iterations > 0:
         sv, sx = (8, 8) if args.precision == "fp64" else ((4 if args.precision == "mixed_fp32" else 2), 4)
         mat = nnz * sv + idx
-        floor_b, moved_b = mat + 7 * n * sx, mat + 10 * n * sx
+        floor_b, moved_b = mat + 7 * n * sx, mat + (8 if info.get("fused_loop") else 10) * n * sx
         t_it = last.elapsed_ms * 1e-3 / last.iterations
         derived["iteration"] = {
             "floor_bytes": floor_b, "moved_bytes": moved_b, "ms": t_it * 1e3,
@@ -460,9 +470,12 @@ def mixed_block(args, ctx, M, b, x, n, nnz, fp64_ms, fp64_log, x_orc):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall / steps * 1e3
-    bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 4) + 2 * n * 4
+    nvec = 8 if info.get("fused_loop") else 2
+    bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 4) + nvec * n * 4
     avg = kms / kl if kl else None
     ach = bytes_spmv / (avg * 1e-3) / 1e9 if avg else None
+    inner_kernel = ("k_spmv_*<EpiFcg<float>> (one inner CG step on A32, FP32 vectors)" if info.get("fused_loop")
+                    else "k_spmv_*<EpiPq<float>> (q = A32 p fused with p.q)")
     blk = {
         "workload": "cg_mixed_fp32_stencil7_N%d" % args.N, "dtype": "f32+f64",
         "steps": steps, "ms_per_step": ms_step, "tau": args.tau, "inner_reduction": args.inner,
@@ -472,7 +485,7 @@ def mixed_block(args, ctx, M, b, x, n, nnz, fp64_ms, fp64_log, x_orc):
         "fp64_ms_per_step": fp64_ms, "fp64_iterations": fp64_log.iterations,
         "fp64_rel_true_residual": fp64_log.true_resnorm / fp64_log.rhs_norm,
         "speedup_vs_fp64": fp64_ms / ms_step,
-        "inner_spmv": {"kernel": "k_spmv_*<EpiPq<float>> (q = A32 p fused with p.q)", "bytes_per_launch": bytes_spmv,
+        "inner_spmv": {"kernel": inner_kernel, "bytes_per_launch": bytes_spmv,
                        "avg_launch_ms": avg, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS if ach else None,
                        "launches": kl, "tiling": info},
     }
@@ -627,10 +640,23 @@ def large(args):
         kl += cnt
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    copy_calib = None
+    if not args.no_copy_calib:
+        # the plain copy kernel over 1 GiB each way (also the counter scale of
+        # FETCH_SIZE / WRITE_SIZE runs of this mode)
+        nb = 1 << 30
+        src = torch.empty(nb // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        best = min(spk.spk_stream_copy(ctx, src, dst, nb) for _ in range(5))
+        copy_calib = {"bytes": 2 * nb, "ms": best, "GBs": 2 * nb / (best * 1e-3) / 1e9}
+        del src, dst
     spk.spk_finalize(ctx)
-    bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 8) + 2 * n * 4
+    nvec = 8 if info.get("fused_loop") else 2
+    bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 8) + nvec * n * 4
     avg = kms / kl if kl else None
     achieved = bytes_spmv / (avg * 1e-3) / 1e9 if avg else None
+    inner_kernel = ("k_spmv_*<EpiFcg<float>> (one inner CG step on A32, FP32 vectors)" if info.get("fused_loop")
+                    else "k_spmv_*<EpiPq<float>> (inner q = A32 p fused with p.q)")
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
         "value": n * iters / wall, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -640,12 +666,17 @@ def large(args):
                    "tau": 1e-12, "index_types": "int64/int32", "iterations_per_solve": log.iterations,
                    "outer_iterations": log.outer_iterations, "stop_reason": log.stop_reason,
                    "rel_true_residual": log.true_resnorm / log.rhs_norm, "solve_device_ms": log.elapsed_ms,
-                   "spmv_tiling": info, "hbm_bytes_resident_est": (n + 1) * 8 + nnz * 8 + 2 * n * 8 + 4 * n * 4},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_*<EpiPq<float>> (inner q = A32 p fused with p.q)",
+                   "spmv_tiling": info,
+                   "hbm_bytes_resident_est": (n + 1) * 8 + nnz * 8 + 2 * n * 8 + (7 if info.get("fused_loop") else 4) * n * 4},
+        "roofline": {"bound": "hbm", "kernel": inner_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": None, "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg, "launches": kl, "timed_every": PROFILE_EVERY},
     }
+    if copy_calib:
+        out["copy_calib"] = copy_calib
+        if achieved:
+            out["roofline"]["frac_vs_copy"] = achieved / copy_calib["GBs"]
     print(json.dumps(out), flush=True)
 
 

@@ -166,7 +166,8 @@ typedef struct {
     int32_t spmv_kernel;       /* 0 = LDS-staged row tiles, 1 = lanes-per-row vector kernel */
     int32_t lanes;             /* lanes per row of the vector kernel */
     int32_t grid;              /* SpMV workgroups */
-    int32_t xcd_remap;         /* 1 = tiles grouped per XCD */
+    int32_t xcd_remap;         /* tile order: 0 round-robin, 1 XCD eighths, k >= 2 XCD blocks of k tiles,
+                                  -D per-XCD slabs of each D-row period of the pattern */
     int32_t exec_mode;         /* resolved spk_exec_mode */
     int32_t chunk_iters;       /* resolved chunk size */
     int32_t tuned;             /* 1 = chosen by timing candidates, 0 = heuristic/cached */
@@ -176,6 +177,10 @@ typedef struct {
                                   bit 1: it also reads packed row pointers (an int64 per
                                   256-row tile, a uint16 offset per row) in place of row_ptr */
     double spmv_ms;            /* measured time of the chosen SpMV (0 if not tuned) */
+    int32_t fused_loop;        /* 1 = CG runs one launch per iteration: the SpMV step also forms
+                                  the direction from the previous r, q and p at every gathered
+                                  column and updates x, r and p (0 = three launches) */
+    int32_t reserved;
 } spk_plan_info;
 
 /* Fill cfg with the defaults documented in spk_solver_cfg. */
@@ -285,11 +290,15 @@ spk_status spk_free(spk_plan plan);
  * cfg (NULL = defaults) must ask for CG, FP64, no preconditioner, AUTO or
  * HOST_LOOP execution and no history.  A: square, F64 values, at most
  * spk_noalloc_max_rows() rows (the scratch holds the solve state, the
- * reduction partials and three vectors of n doubles); the caller's arrays
+ * reduction partials and the vectors of n doubles: r, p, q, and their second
+ * buffers when the solve runs one launch per iteration, as systems of up to
+ * 2^20 rows do); the caller's arrays
  * are borrowed for the call only.  b and x as for spk_execute_solve.  The
  * launch shape is one an earlier plan of the same shape tuned on this
  * context (never tuned here), else the heuristic one, so a solve after such
- * a plan runs the same kernels and gives the same result.  Every call on one
+ * a plan runs the same kernels and gives the same result (for matrices of
+ * fewer than 2^22 entries: larger plans also derive column codes, which this
+ * solve does not, so its launch shape and rounding can differ there).  Every call on one
  * GPU shares that GPU's scratch, which keeps the last call's contents (the
  * call clears what must start at zero): calls that overlap on one GPU, from
  * any context or stream, race and must not be issued.  Synchronises the
@@ -306,6 +315,18 @@ int64_t spk_noalloc_max_rows(void);
  * pointers) with the library's streaming copy kernel; *ms receives its
  * device time.  Used to measure the achievable HBM bandwidth. */
 spk_status spk_stream_copy(spk_ctx ctx, const void *src, void *dst, size_t bytes, double *ms);
+
+/* Random-gather calibration: dst[i] = src[idx[i]] for i < m (device arrays:
+ * n_src doubles, m int32 indices in [0, n_src), m doubles) with the
+ * library's gather kernel, indices and results streamed, the source read at
+ * the given positions; *ms receives its device time.  With uniform random
+ * indices it measures the rate of the scattered 8-byte reads an SpMV of an
+ * irregular pattern makes of its input vector (a ceiling beside the HBM
+ * bandwidth spk_stream_copy measures).  The indices are range-checked on the
+ * GPU first.  Errors: INVALID_ARG (null pointers, sizes, an index out of
+ * range), OUT_OF_MEMORY, DEVICE. */
+spk_status spk_gather_probe(spk_ctx ctx, const double *src, int64_t n_src, const int32_t *idx, int64_t m,
+                            double *dst, double *ms);
 
 /* ---------------------------------------------------------------- serving
  * A continuous-batching solve server.  Requests of uneven sizes arrive from

@@ -8,6 +8,8 @@
 #include "spk_pool.h"
 
 #include <algorithm>
+#include <cstddef>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -29,16 +31,17 @@ struct TuneKey {
     int use;     // TUNE_PLAIN or TUNE_CG
     int codes;   // the matrix has column codes
     int staged;  // values and columns are 16-byte aligned (the LDS tiles may run)
+    int64_t period;   // the pattern's period in rows (0 = none known)
     bool operator<(const TuneKey &o) const {
-        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged) <
-               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged);
+        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged, period) <
+               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged, o.period);
     }
 };
 
 // What a tuning run times: the plain product y = A x, or the solvers' SpMV
 // fused with the p.q partials (its register count, and so its residency,
 // differs).
-enum { TUNE_PLAIN = 0, TUNE_CG = 1 };
+enum { TUNE_PLAIN = 0, TUNE_CG = 1, TUNE_FCG = 2 };
 
 struct TuneResult {
     SpmvTune tune;
@@ -77,6 +80,7 @@ struct spk_plan_s {
     int vec_grid = 1;
     int persist_grid = 0;                // cooperative grid of the persistent solve (0 = not used)
     unsigned *bar = nullptr;             // persistent grid-barrier words
+    spk::PersistResult *persist_res = nullptr;   // persistent mixed solve: its result (device)
     spk_plan_info info{};
     double *r = nullptr, *p = nullptr, *q = nullptr, *partials = nullptr, *hist = nullptr;
     int algo = 0;                        // ALGO_CG / ALGO_CGS / ALGO_PCG
@@ -103,6 +107,11 @@ struct spk_plan_s {
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     SolveState *st_in = nullptr, *h_st_in = nullptr;
     double *out_dev = nullptr, *h_out = nullptr;   // refinement norms (device / pinned)
+    // fused CG loop (one launch per iteration): second buffers of r, p, q
+    // (FP64, or FP32 for the inner solve), paired with r, p, q / r32, p32, q32
+    bool fused = false;
+    double *r_b = nullptr, *p_b = nullptr, *q_b = nullptr;
+    float *r32_b = nullptr, *p32_b = nullptr, *q32_b = nullptr;
     int profiling = 0;                   // time every profiling-th dominant SpMV launch (0 = off)
     int64_t prof_seq = 0;                // dominant SpMV launches since the last collect
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -161,17 +170,19 @@ CsrDev to_dev(const spk_csr *A) {
 
 size_t vec_bytes(int val_t) { return val_t == SPK_F64 ? 8 : 4; }
 
-spk_status gpu_verdict(spk_ctx ctx, const spk_csr *A, int32_t *verdict) {
+// max_row (optional): the longest row's entry count (valid for a valid A).
+spk_status gpu_verdict(spk_ctx ctx, const spk_csr *A, int32_t *verdict, int64_t *max_row = nullptr) {
     if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) {
         *verdict = SPK_CSR_BAD_SIZE;
         return SPK_OK;
     }
     const CsrDev d = to_dev(A);
-    SPK_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(unsigned), ctx->stream));
+    SPK_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, 2 * sizeof(unsigned), ctx->stream));
     SPK_HIP(ctx, spk::launch_validate(d, ctx->d_flags, ctx->num_cu * 4, ctx->stream));
-    SPK_HIP(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    SPK_HIP(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
     SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const unsigned f = *ctx->h_flags;
+    const unsigned f = ctx->h_flags[0];
+    if (max_row) *max_row = ctx->h_flags[1];
     int32_t v = SPK_CSR_OK;
     if (f & spk::VFLAG_BAD_FIRST) v = SPK_CSR_BAD_FIRST;
     else if (f & spk::VFLAG_DECREASING) v = SPK_CSR_DECREASING;
@@ -199,6 +210,16 @@ int64_t num_tiles(int64_t n) { return (n + spk::kTileRows - 1) / spk::kTileRows;
 // The LDS tiling stages with 16-byte loads: values and col_idx must be 16-byte aligned.
 bool stream_ok(const CsrDev &A) {
     return (reinterpret_cast<uintptr_t>(A.va) & 15) == 0 && (reinterpret_cast<uintptr_t>(A.ci) & 15) == 0;
+}
+
+// Tile order of the pattern's period (TileIter remap = -D): D rows, the
+// largest column offset of a coded pattern (N^2 for a 3-D 7-point stencil),
+// when every XCD slab of a period spans at least two tiles; else fallback.
+int period_remap(const CsrDev &A, int fallback) {
+    const int64_t D = A.period;
+    if (D >= int64_t(spk::kNumXcd) * spk::kTileRows * 2 && D <= INT32_MAX && D < A.n_rows)
+        return -static_cast<int>(D);
+    return fallback;
 }
 
 // bpc <= 0: as many workgroups per CU as the occupancy calculator allows;
@@ -230,8 +251,9 @@ SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
 // plan's vector type (contents irrelevant for timing).  use = TUNE_CG times
 // the solvers' fused SpMV with st (stop flag clear) and partials.
 spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int use, SolveState *st,
-                    double *partials, TuneResult *out) {
-    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use, A.codes != nullptr, stream_ok(A)};
+                    double *partials, TuneResult *out, const void *fcg = nullptr) {
+    const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use, A.codes != nullptr, stream_ok(A),
+                      A.period};
     auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
         *out = hit->second;
@@ -247,6 +269,9 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
         // they move fewer bytes: stencil7 N=215, 1.20 GB per product against
         // 1.36 GB round-robin), non-temporal matrix loads, one workgroup per
         // CU above the calculator's figure (all measured best in the CG loop).
+        // (the pattern-period slab order, remap = -D, is not a candidate: on
+        // stencil7 it measured 13% slower at N = 215 and 6% at N = 1048 than
+        // XCD-blocked runs of 64 tiles; SPK_SPMV_KERNEL=...,remap=period forces it)
         for (int remap : {64, 256, 1, 0})
             for (int nt : {1, 0}) {
                 const SpmvTune t = make_tune(ctx, A, 0, 0, remap, nt, 1, 0);
@@ -262,6 +287,16 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
     }
     auto launch = [&](const SpmvTune &t) -> hipError_t {
         if (use == TUNE_PLAIN) return spk::launch_spmv(A, t, x, y, ctx->stream);
+        if (use == TUNE_FCG) {
+            // step 0 of the fused loop (st->base = 0, the stop flag clear and
+            // st->x set by the caller): the same gathers, stores and partials
+            // as every later step
+            if (A.val_t == SPK_F64)
+                return spk::launch_fcg_step(A, t, 0, *static_cast<const spk::FcgBufs<double> *>(fcg), st, partials,
+                                            ctx->stream);
+            return spk::launch_fcg_step32(A, t, 0, *static_cast<const spk::FcgBufs<float> *>(fcg), st, partials,
+                                          ctx->stream);
+        }
         if (A.val_t == SPK_F64)
             return spk::launch_cg_spmv_pq(A, t, static_cast<const double *>(x), static_cast<double *>(y), st,
                                           partials, ctx->stream);
@@ -320,11 +355,13 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
 // "vector:<lanes>", optionally followed by ",key=value" with keys remap, nt,
 // pf, bpc, codes, pack (e.g. "stream,pf=1,nt=1,remap=0,bpc=4,codes=0";
 // codes and pack default to 1 when the matrix has codes / packed rows).
+// remap=period takes the period slabs of the matrix's pattern period (plain
+// XCD eighths when it has none); remap=-D forces a period of D rows.
 bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     const char *env = std::getenv("SPK_SPMV_KERNEL");
     if (!env || !*env) return false;
     std::string v(env);
-    int kind = -1, l2 = 0, remap = -1, nt = 0, pf = 1, bpc = 0, codes = 1, pack = 1;
+    int kind = -1, l2 = 0, remap = INT_MIN, nt = 0, pf = 1, bpc = 0, codes = 1, pack = 1;
     size_t pos = 0;
     bool first = true;
     while (pos <= v.size()) {
@@ -345,7 +382,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
             if (eq != std::string::npos) {
                 const std::string k = tok.substr(0, eq);
                 const int val = std::atoi(tok.c_str() + eq + 1);
-                if (k == "remap") remap = val;
+                if (k == "remap") remap = tok.substr(eq + 1) == "period" ? period_remap(A, 1) : val;
                 else if (k == "nt") nt = val;
                 else if (k == "pf") pf = val;
                 else if (k == "bpc") bpc = val;
@@ -357,12 +394,13 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     }
     if (kind < 0) return false;
     if (kind == 0 && !stream_ok(A)) kind = 1;
-    if (remap < 0) remap = 1;
+    if (remap == INT_MIN || remap == -1) remap = 1;
     *t = make_tune(ctx, A, kind, l2, remap, nt, pf, bpc, codes, pack);
     return true;
 }
 
-spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN, SolveState *st = nullptr) {
+spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN, SolveState *st = nullptr,
+                       const void *fcg = nullptr) {
     spk_ctx ctx = pl->ctx;
     const CsrDev &A = pl->A;
     if (A.n_rows == 0) {
@@ -374,7 +412,7 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN
         pl->info.tuned = 0;
     } else if (A.nnz >= 100000) {
         TuneResult tr;
-        spk_status s = autotune(ctx, A, x, y, use, st, pl->partials, &tr);
+        spk_status s = autotune(ctx, A, x, y, use, st, pl->partials, &tr, fcg);
         if (s != SPK_OK) return s;
         pl->tune = tr.tune;
         pl->info.tuned = 1;
@@ -442,6 +480,17 @@ spk_status build_codes(spk_plan pl) {
         ctx->dpool.put(buf);
         return SPK_OK;
     }
+    // the pattern's period: the largest offset magnitude in the ascending table
+    int64_t ends[2] = {0, 0};
+    const int64_t *dtab = static_cast<const int64_t *>(buf);
+    if (hipMemcpyAsync(&ends[0], dtab, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(&ends[1], dtab + (h[0] - 1), sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->dpool.put(buf);
+        return fail(ctx, SPK_ERR_DEVICE, "column code table");
+    }
+    A.period = std::max(-ends[0], ends[1]);
     pl->codes_buf = buf;
     A.codes = static_cast<const char *>(buf) + sizeof(int64_t) * spk::kCodeDict;
     const char *pack = std::getenv("SPK_ROW_PACK");
@@ -496,6 +545,40 @@ spk_status prof_collect(spk_plan pl, int64_t useful, bool keep_seq = false) {
 enum { LOOP_FP64 = 0, LOOP_FP32 = 1, LOOP_CGS = 2, LOOP_PCG = 3 };
 enum { ALGO_CG = 0, ALGO_CGS = 1, ALGO_PCG = 2, ALGO_GMRES = 3 };
 
+// The fused loop (one launch per CG iteration, or one grid barrier per
+// iteration in the persistent mode) runs CG in FP64 and the CG inner solve of
+// the mixed precisions for systems of at most kFusedMaxRows rows, and always
+// in the persistent mode.  Measured on stencil7: at n = 97,336 one launch per
+// iteration is 13% faster than three (launch-bound); from n = 343,000 up the
+// three vectors the fused step gathers per entry cost more than the two
+// launches it saves (3% slower there, 16% at n = 9.9e6), and on random
+// patterns each gathered vector is a random read of its own (15% slower at
+// n = 1e5).  SPK_CG_FUSED=1 / 0 forces it on / off (0 also rules out the
+// persistent mode).
+constexpr int64_t kFusedMaxRows = int64_t(1) << 17;
+
+bool fused_loop(const spk_solver_cfg &cfg, int64_t n) {
+    if (cfg.solver != SPK_SOLVER_CG || cfg.precond != SPK_PRECOND_NONE) return false;
+    const char *env = std::getenv("SPK_CG_FUSED");
+    if (env && std::strcmp(env, "0") == 0) return false;
+    if (env && std::strcmp(env, "1") == 0) return true;
+    return n <= kFusedMaxRows || cfg.exec_mode == SPK_EXEC_PERSISTENT;
+}
+
+// st->x := ptr (the tuner's runs of the fused step write through st->x).
+spk_status set_state_x(spk_ctx ctx, SolveState *st, void *ptr) {
+    void *v = ptr;
+    SPK_HIP(ctx, hipMemcpyAsync(reinterpret_cast<char *>(st) + offsetof(SolveState, x), &v, sizeof(v),
+                                hipMemcpyHostToDevice, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return SPK_OK;
+}
+
+spk::FcgBufs<double> fcg64(const spk_plan_s *pl) { return {{pl->r, pl->r_b}, {pl->p, pl->p_b}, {pl->q, pl->q_b}}; }
+spk::FcgBufs<float> fcg32(const spk_plan_s *pl) {
+    return {{pl->r32, pl->r32_b}, {pl->p32, pl->p32_b}, {pl->q32, pl->q32_b}};
+}
+
 // Iteration j of a chunk: q = A p with p.q partials; alpha and r -= alpha q
 // with r.r partials; x += alpha p, the stop test and p = r + beta p.  A chunk
 // of `count` iterations ends by advancing the base.
@@ -517,6 +600,15 @@ spk_status launch_iterations(spk_plan pl, int kind, int count, hipStream_t s, bo
                                                 pl->st, pl->partials, s));
             if ((st = pb()) != SPK_OK) return st;
             SPK_HIP(ctx, spk::launch_cgs_spmv_r(pl->A, pl->tune, pl->uh, pl->r, pl->rt, pl->st, pl->partials, s));
+            if ((st = pe()) != SPK_OK) return st;
+            continue;
+        }
+        if (pl->fused && (kind == LOOP_FP64 || kind == LOOP_FP32)) {
+            if ((st = pb()) != SPK_OK) return st;
+            if (kind == LOOP_FP64)
+                SPK_HIP(ctx, spk::launch_fcg_step(pl->A, pl->tune, i, fcg64(pl), pl->st, pl->partials, s));
+            else
+                SPK_HIP(ctx, spk::launch_fcg_step32(pl->A32, pl->tune32, i, fcg32(pl), pl->st_in, pl->partials, s));
             if ((st = pe()) != SPK_OK) return st;
             continue;
         }
@@ -655,6 +747,8 @@ void release_workspace(spk_plan pl) {
     ctx->dpool.put(pl->out_dev);
     ctx->hpool.put(pl->h_out);
     ctx->dpool.put(pl->bar);
+    ctx->dpool.put(pl->persist_res);
+    pl->persist_res = nullptr;
     ctx->dpool.put(pl->rt);
     ctx->dpool.put(pl->u);
     ctx->dpool.put(pl->v);
@@ -670,6 +764,14 @@ void release_workspace(spk_plan pl) {
     ctx->dpool.put(pl->gm_w);
     ctx->dpool.put(pl->gm_part);
     ctx->dpool.put(pl->gm_st);
+    ctx->dpool.put(pl->r_b);
+    ctx->dpool.put(pl->p_b);
+    ctx->dpool.put(pl->q_b);
+    ctx->dpool.put(pl->r32_b);
+    ctx->dpool.put(pl->p32_b);
+    ctx->dpool.put(pl->q32_b);
+    pl->r_b = pl->p_b = pl->q_b = nullptr;
+    pl->r32_b = pl->p32_b = pl->q32_b = nullptr;
     pl->coo_rp = nullptr;
     pl->gm_V = pl->gm_w = pl->gm_part = nullptr;
     pl->gm_st = nullptr;
@@ -747,8 +849,9 @@ spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) ctx->dpool.set_cap(total_b / 4);
     ctx->hpool.set_cap(size_t(16) << 20);
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipMalloc(&ctx->d_flags, sizeof(unsigned)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), sizeof(unsigned), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&ctx->d_flags, 2 * sizeof(unsigned)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), 2 * sizeof(unsigned), hipHostMallocDefault) !=
+            hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&ctx->h_noalloc_st), sizeof(SolveState), hipHostMallocDefault) !=
             hipSuccess) {
@@ -799,15 +902,18 @@ spk_status spk_partition(spk_ctx ctx, const spk_csr *A, int64_t parts, int64_t *
     return SPK_OK;
 }
 
-static spk_status plan_common(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
+static spk_status plan_common(spk_ctx ctx, const spk_csr *A, spk_plan *out, int64_t *max_row) {
     if (!ctx || !out) return SPK_ERR_INVALID_ARG;
     *out = nullptr;
     SPK_HIP(ctx, hipSetDevice(ctx->device));
     spk_status s = check_csr_args(ctx, A);
     if (s != SPK_OK) return s;
     int32_t verdict = 0;
-    s = gpu_verdict(ctx, A, &verdict);
+    s = gpu_verdict(ctx, A, &verdict, max_row);
     if (s != SPK_OK) return s;
+    // SPK_LONG_ROWS=0: every row summed by one lane, however long (comparisons)
+    const char *lr = std::getenv("SPK_LONG_ROWS");
+    if (max_row && lr && std::strcmp(lr, "0") == 0) *max_row = 0;
     if (verdict != SPK_CSR_OK) return fail(ctx, SPK_ERR_INVALID_ARG, std::string("malformed CSR: ") + verdict_name(verdict));
     return SPK_OK;
 }
@@ -816,12 +922,14 @@ static spk_status plan_common(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
 static spk_status finish_spmv_plan(spk_ctx ctx, spk_plan pl, const spk_csr *A, spk_plan *out);
 
 spk_status spk_plan_spmv(spk_ctx ctx, const spk_csr *A, spk_plan *out) {
-    spk_status s = plan_common(ctx, A, out);
+    int64_t max_row = 0;
+    spk_status s = plan_common(ctx, A, out, &max_row);
     if (s != SPK_OK) return s;
     spk_plan pl = new spk_plan_s();
     pl->ctx = ctx;
     pl->kind = 0;
     pl->A = to_dev(A);
+    pl->A.max_row = max_row;
     return finish_spmv_plan(ctx, pl, A, out);
 }
 
@@ -960,7 +1068,8 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     if (mixed && (!(cfg.inner_reduction > 0.0) || cfg.inner_reduction >= 1.0))
         return fail(ctx, SPK_ERR_INVALID_ARG, "inner_reduction must be in (0, 1)");
     if (mixed && cfg.max_outer < 0) return fail(ctx, SPK_ERR_INVALID_ARG, "max_outer < 0");
-    spk_status s = plan_common(ctx, A, out);
+    int64_t max_row = 0;
+    spk_status s = plan_common(ctx, A, out, &max_row);
     if (s != SPK_OK) return s;
     if (A->n_rows != A->n_cols) return fail(ctx, SPK_ERR_INVALID_ARG, "solve needs a square matrix");
     if (!mixed && A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
@@ -973,6 +1082,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     pl->ctx = ctx;
     pl->kind = 1;
     pl->A = to_dev(A);
+    pl->A.max_row = max_row;
     pl->cfg = cfg;
     pl->algo = cfg.solver == SPK_SOLVER_CGS     ? ALGO_CGS
                : cfg.solver == SPK_SOLVER_GMRES ? ALGO_GMRES
@@ -1015,6 +1125,9 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             pl->hist_cap = cfg.max_iters + 1;
             if (!dget(sizeof(double) * pl->hist_cap, &pl->hist)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "history");
         }
+        pl->fused = pl->algo == ALGO_CG && fused_loop(cfg, n);
+        if (pl->fused && (!dget(nb, &pl->r_b) || !dget(nb, &pl->p_b) || !dget(nb, &pl->q_b)))
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "fused CG workspace");
         if (hipMemsetAsync(pl->st, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
             hipMemsetAsync(pl->p, 0, nb, ctx->stream) != hipSuccess)
             return cleanup(SPK_ERR_DEVICE, "workspace init");
@@ -1055,7 +1168,12 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
                 spk::launch_diag_inv(pl->A, pl->dinv, pl->diag_flag, ctx->stream) != hipSuccess)
                 return cleanup(SPK_ERR_DEVICE, "Jacobi diagonal");
         }
-        s = choose_tune(pl, pl->p, pl->q, TUNE_CG, pl->st);
+        if (pl->fused) {
+            const spk::FcgBufs<double> f = fcg64(pl);
+            if ((s = set_state_x(ctx, pl->st, pl->q)) == SPK_OK) s = choose_tune(pl, pl->p, pl->q, TUNE_FCG, pl->st, &f);
+        } else {
+            s = choose_tune(pl, pl->p, pl->q, TUNE_CG, pl->st);
+        }
         if (s != SPK_OK) return cleanup(s, ctx->err);
     } else {
         if (!dget(nf, &pl->r32) || !dget(nf, &pl->p32) || !dget(nf, &pl->q32) || !dget(nf, &pl->d32) ||
@@ -1079,6 +1197,9 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             pl->A32.va = dst;
             pl->A32.val_t = to;
         }
+        pl->fused = pl->algo == ALGO_CG && fused_loop(cfg, n);
+        if (pl->fused && (!dget(nf, &pl->r32_b) || !dget(nf, &pl->p32_b) || !dget(nf, &pl->q32_b)))
+            return cleanup(SPK_ERR_OUT_OF_MEMORY, "fused CG workspace");
         if (pl->algo == ALGO_GMRES) {   // GMRES-IR: FP32 basis
             const size_t vbytes =
                 sizeof(float) * static_cast<size_t>(spk::gm_ld(std::max<int64_t>(n, 1))) * (cfg.krylov_dim + 1);
@@ -1094,7 +1215,13 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
         // (a few launches): launch-shape heuristic on A.
         const CsrDev outer = pl->A;
         pl->A = pl->A32;
-        s = choose_tune(pl, pl->p32, pl->q32, TUNE_CG, pl->st_in);
+        if (pl->fused) {
+            const spk::FcgBufs<float> f = fcg32(pl);
+            if ((s = set_state_x(ctx, pl->st_in, pl->q32)) == SPK_OK)
+                s = choose_tune(pl, pl->p32, pl->q32, TUNE_FCG, pl->st_in, &f);
+        } else {
+            s = choose_tune(pl, pl->p32, pl->q32, TUNE_CG, pl->st_in);
+        }
         pl->A = outer;
         if (s != SPK_OK) return cleanup(s, ctx->err);
         pl->tune32 = pl->tune;
@@ -1106,19 +1233,32 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     // measured faster than replaying captured chunks or one cooperative
     // launch with grid barriers.
     if (mode == SPK_EXEC_AUTO) mode = SPK_EXEC_HOST_LOOP;
-    if (mode == SPK_EXEC_PERSISTENT && (mixed || pl->algo != ALGO_CG)) mode = SPK_EXEC_GRAPH;
+    if (mode == SPK_EXEC_PERSISTENT && !pl->fused) mode = SPK_EXEC_GRAPH;
     if (pl->algo == ALGO_GMRES) mode = SPK_EXEC_HOST_LOOP;   // cycles read b and x directly
     if (mode == SPK_EXEC_PERSISTENT) {
-        const int occ = spk::persistent_blocks_per_cu(pl->A);
+        // the iterations' matrix and, for a mixed solve, the refinement's
+        const CsrDev &Ait = mixed ? pl->A32 : pl->A;
+        const int occ = stream_ok(pl->A) && stream_ok(Ait) ? spk::persistent_blocks_per_cu(Ait, mixed ? &pl->A : nullptr)
+                                                            : 0;
         const int64_t tiles = std::max<int64_t>((n + spk::kTileRows - 1) / spk::kTileRows, 1);
-        const int64_t g = std::min<int64_t>({tiles, int64_t(occ) * ctx->num_cu, int64_t(spk::kMaxGrid)});
-        void *bv = nullptr;
+        // a grid barrier costs about 2 us plus 25-50 ns per workgroup (one
+        // agent-scope release and acquire each): at least 8 tiles per
+        // workgroup, no fewer than 64 workgroups, at most the resident count
+        int64_t g = std::min<int64_t>({std::max<int64_t>(tiles / 8, 64), tiles, int64_t(occ) * ctx->num_cu,
+                                       int64_t(spk::kMaxGrid)});
+        if (const char *eg = std::getenv("SPK_PERSIST_GRID"))
+            if (std::atoi(eg) > 0) g = std::min<int64_t>({int64_t(std::atoi(eg)), int64_t(occ) * ctx->num_cu,
+                                                          int64_t(spk::kMaxGrid)});
+        void *bv = nullptr, *rv = nullptr;
         if (occ <= 0 || g < 1) {
             mode = SPK_EXEC_GRAPH;
-        } else if (ctx->dpool.get(4 * sizeof(unsigned), &bv) != hipSuccess) {
+        } else if (ctx->dpool.get(4 * sizeof(unsigned), &bv) != hipSuccess ||
+                   (mixed && ctx->dpool.get(sizeof(spk::PersistResult), &rv) != hipSuccess)) {
+            if (bv) ctx->dpool.put(bv);
             return cleanup(SPK_ERR_OUT_OF_MEMORY, "barrier words");
         } else {
             pl->bar = static_cast<unsigned *>(bv);
+            pl->persist_res = static_cast<spk::PersistResult *>(rv);
             pl->persist_grid = static_cast<int>(g);
             if (hipMemsetAsync(pl->bar, 0, 4 * sizeof(unsigned), ctx->stream) != hipSuccess)
                 return cleanup(SPK_ERR_DEVICE, "barrier init");
@@ -1126,6 +1266,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     }
     pl->info.exec_mode = mode;
     pl->info.chunk_iters = cfg.chunk_iters;
+    pl->info.fused_loop = pl->fused ? 1 : 0;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(SPK_ERR_DEVICE, "plan sync");
     ctx->live_plans++;
     *out = pl;
@@ -1191,6 +1332,47 @@ static spk_status run_gmres(spk_plan pl, const void *b, void *x, bool inner, int
     return fail(ctx, SPK_ERR_INTERNAL, "GMRES cycle cap passed without stop");
 }
 
+// One cooperative launch for the whole solve (FP64 CG, or the mixed solve
+// with its refinement); the barrier gives up after 2 s of waiting.
+static spk_status run_persistent(spk_plan pl, const double *b, double *x) {
+    spk_ctx ctx = pl->ctx;
+    const spk_solver_cfg &cfg = pl->cfg;
+    const bool mixed = cfg.precision != SPK_PREC_FP64;
+    spk::PersistSolve a{};
+    a.b = b;
+    a.x = x;
+    a.partials = pl->partials;
+    a.bar = pl->bar;
+    a.spin_ticks = static_cast<uint64_t>(ctx->wall_khz) * 2000ull;
+    a.tau = cfg.reduction_factor;
+    a.tau_in = cfg.inner_reduction;
+    a.max_iters = cfg.max_iters;
+    a.max_outer = cfg.max_outer;
+    a.remap = pl->tune.xcd_remap;
+    a.nt = pl->tune.nt;
+    a.true_residual = cfg.true_residual;
+    if (mixed) {
+        a.f32 = fcg32(pl);
+        a.d32 = pl->d32;
+        a.res = pl->persist_res;
+        a.remap = pl->tune32.xcd_remap;
+        a.nt = pl->tune32.nt;
+    } else {
+        a.f64 = fcg64(pl);
+        a.st = pl->st;
+        a.hist = pl->hist;
+        a.hist_cap = pl->hist_cap;
+    }
+    SPK_HIP(ctx, hipMemsetAsync(pl->bar, 0, 4 * sizeof(unsigned), ctx->stream));
+    SPK_HIP(ctx, spk::launch_persistent(mixed ? pl->A32 : pl->A, mixed ? &pl->A : nullptr, a, pl->persist_grid,
+                                        ctx->stream));
+    unsigned flags[4] = {0, 0, 0, 0};
+    SPK_HIP(ctx, hipMemcpyAsync(flags, pl->bar, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (flags[2] != 0) return fail(ctx, SPK_ERR_DEVICE, "persistent solve: a grid barrier timed out");
+    return SPK_OK;
+}
+
 static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log *L, bool graph) {
     spk_ctx ctx = pl->ctx;
     const spk_solver_cfg &cfg = pl->cfg;
@@ -1220,16 +1402,8 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
         SPK_HIP(ctx, spk::launch_jacobi_vec(n, x, pl->dinv, 0, ctx->stream));
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
     } else if (pl->persist_grid > 0) {
-        // one cooperative launch; the barrier gives up after 2 s of waiting
-        const uint64_t spin = static_cast<uint64_t>(ctx->wall_khz) * 2000ull;
-        SPK_HIP(ctx, hipMemsetAsync(pl->bar, 0, 4 * sizeof(unsigned), ctx->stream));
-        SPK_HIP(ctx, spk::launch_cg_persistent(pl->A, pl->persist_grid, pl->tune.xcd_remap, b, x, pl->r, pl->p, pl->q,
-                                               pl->st, pl->partials, pl->bar, spin, cfg.reduction_factor,
-                                               cfg.max_iters, pl->hist, pl->hist_cap, cfg.true_residual, ctx->stream));
-        unsigned flags[4] = {0, 0, 0, 0};
-        SPK_HIP(ctx, hipMemcpyAsync(flags, pl->bar, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream));
+        if ((s = run_persistent(pl, b, x)) != SPK_OK) return s;
         if ((s = pull(ctx, pl->h_st, pl->st, sizeof(SolveState))) != SPK_OK) return s;
-        if (flags[2] != 0) return fail(ctx, SPK_ERR_DEVICE, "persistent solve: a grid barrier timed out");
     } else if (pl->algo == ALGO_GMRES) {
         if ((s = run_gmres(pl, b, x, false, cfg.max_iters)) != SPK_OK) return s;
         SPK_HIP(ctx, spk::launch_cg_finalize(pl->A, pl->tune, b, x, pl->st, pl->partials, cfg.true_residual,
@@ -1243,10 +1417,16 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
                                               pl->hist_cap, ctx->stream));
             kind = LOOP_PCG;
         } else {
-            // CGS: the same initial residual, with the shadow residual rt = r_0 in place of p
-            SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->algo == ALGO_CGS ? pl->rt : pl->p,
-                                             pl->st, pl->partials, cfg.reduction_factor, cfg.max_iters, pl->hist,
-                                             pl->hist_cap, ctx->stream));
+            if (pl->fused) {
+                SPK_HIP(ctx, spk::launch_fcg_init(pl->A, pl->tune, b, x, fcg64(pl), pl->st, pl->partials,
+                                                  cfg.reduction_factor, cfg.max_iters, pl->hist, pl->hist_cap,
+                                                  ctx->stream));
+            } else {
+                // CGS: the same initial residual, with the shadow residual rt = r_0 in place of p
+                SPK_HIP(ctx, spk::launch_cg_init(pl->A, pl->tune, b, x, pl->r, pl->algo == ALGO_CGS ? pl->rt : pl->p,
+                                                 pl->st, pl->partials, cfg.reduction_factor, cfg.max_iters, pl->hist,
+                                                 pl->hist_cap, ctx->stream));
+            }
             if (pl->algo == ALGO_CGS) kind = LOOP_CGS;
         }
         s = run_loop(pl, kind, cfg.max_iters, graph);
@@ -1258,7 +1438,8 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
     const SolveState &h = *pl->h_st;
     if (pl->profiling) {   // SpMV launches that did work (two per CGS iteration)
         const int64_t per = pl->algo == ALGO_CGS ? 2 : 1;
-        const int64_t useful = per * h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+        // the fused loop: steps 0 .. iterations did work, the next one found the stop
+        const int64_t useful = pl->fused ? h.iter + 1 : per * h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
         if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
     }
     L->iterations = h.iter;
@@ -1279,14 +1460,32 @@ static spk_status execute_mixed(spk_plan pl, const double *b, double *x, spk_log
     spk_ctx ctx = pl->ctx;
     const spk_solver_cfg &cfg = pl->cfg;
     const int64_t n = pl->A.n_rows;
+    if (pl->persist_grid > 0) {
+        spk_status s = run_persistent(pl, b, x);
+        if (s != SPK_OK) return s;
+        spk::PersistResult r{};
+        if ((s = pull(ctx, &r, pl->persist_res, sizeof(r))) != SPK_OK) return s;
+        L->iterations = r.inner;
+        L->outer_iterations = r.outer;
+        L->implicit_resnorm = r.rnorm;
+        L->true_resnorm = r.rnorm;
+        L->rhs_norm = r.bnorm;
+        L->stop_reason = r.stop;
+        return SPK_OK;
+    }
     int64_t inner_total = 0, outer = 0;
     double bnorm = 0.0, rnorm = 0.0;
     int stop = spk::STOP_RUNNING;
     spk_status s = SPK_OK;
     while (true) {
-        SPK_HIP(ctx, spk::launch_ir_residual(pl->A, pl->tune, b, x, pl->r32, pl->p32, pl->d32, pl->st_in,
-                                             pl->partials, cfg.inner_reduction, cfg.max_iters - inner_total,
-                                             pl->out_dev, ctx->stream));
+        if (pl->fused)
+            SPK_HIP(ctx, spk::launch_fcg_ir_residual(pl->A, pl->tune, b, x, fcg32(pl), pl->d32, pl->st_in,
+                                                     pl->partials, cfg.inner_reduction, cfg.max_iters - inner_total,
+                                                     pl->out_dev, ctx->stream));
+        else
+            SPK_HIP(ctx, spk::launch_ir_residual(pl->A, pl->tune, b, x, pl->r32, pl->p32, pl->d32, pl->st_in,
+                                                 pl->partials, cfg.inner_reduction, cfg.max_iters - inner_total,
+                                                 pl->out_dev, ctx->stream));
         if ((s = pull(ctx, pl->h_out, pl->out_dev, 3 * sizeof(double))) != SPK_OK) return s;
         rnorm = pl->h_out[0];
         bnorm = pl->h_out[2];
@@ -1316,7 +1515,8 @@ static spk_status execute_mixed(spk_plan pl, const double *b, double *x, spk_log
         const SolveState &h = *pl->h_st_in;
         inner_total += h.iter;
         if (pl->profiling) {   // this inner solve's SpMV launches that did work
-            if ((s = prof_collect(pl, h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0))) != SPK_OK) return s;
+            const int64_t useful = pl->fused ? h.iter + 1 : h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+            if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
         }
         if ((h.stop == spk::STOP_BREAKDOWN || h.stop == spk::STOP_NON_FINITE) && h.iter == 0) {
             stop = h.stop;
@@ -1370,9 +1570,25 @@ static constexpr size_t kNaPartialBytes = sizeof(double) * spk::SITE_COUNT * spk
 static constexpr size_t na_align(size_t v) { return (v + 255) & ~size_t(255); }
 static constexpr size_t kNaVecBase = na_align(sizeof(SolveState)) + na_align(kNaPartialBytes);
 
+// Rows the scratch holds with v vectors of n doubles (each rounded up to 256 bytes).
+static int64_t na_rows(int v) {
+    return static_cast<int64_t>((spk::kNoallocScratchBytes - kNaVecBase) / (v * sizeof(double))) - 32;
+}
+
+// Vectors of n doubles a solve of n rows keeps in the scratch: r, p, q, and
+// their second buffers when it runs the fused loop (as a plan of the same
+// configuration and size does).
+static int na_vectors(const spk_solver_cfg &cfg, int64_t n) { return fused_loop(cfg, n) ? 6 : 3; }
+
+// Whether a solve of n rows fits the scratch.
+static bool na_fits(const spk_solver_cfg &cfg, int64_t n) { return n <= na_rows(na_vectors(cfg, n)); }
+
 int64_t spk_noalloc_max_rows(void) {
-    // three vectors of n doubles, each rounded up to 256 bytes
-    return static_cast<int64_t>((spk::kNoallocScratchBytes - kNaVecBase) / (3 * sizeof(double))) - 32;
+    // the fused loop (six vectors) runs up to kFusedMaxRows rows, which six
+    // vectors hold; above that three vectors (unless the fused loop is forced)
+    spk_solver_cfg cfg;
+    spk_solver_cfg_default(&cfg);
+    return na_fits(cfg, na_rows(3)) ? na_rows(3) : na_rows(6);
 }
 
 spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *cfg_in, const void *b_in,
@@ -1395,10 +1611,10 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
     if (A->n_rows != A->n_cols) return fail(ctx, SPK_ERR_INVALID_ARG, "solve needs a square matrix");
     if (A->val_type != SPK_F64) return fail(ctx, SPK_ERR_INVALID_ARG, "FP64 precision needs F64 values");
     const int64_t n = A->n_rows;
-    if (n > spk_noalloc_max_rows())
+    if (!na_fits(cfg, n))
         return fail(ctx, SPK_ERR_INVALID_ARG,
                     "allocation-free solve: " + std::to_string(n) + " rows exceed the scratch limit of " +
-                        std::to_string(spk_noalloc_max_rows()));
+                        std::to_string(na_rows(na_vectors(cfg, n))));
     if (n > 0 && (!b_in || !x_in)) return fail(ctx, SPK_ERR_INVALID_ARG, "null vector");
     if (!ctx->scratch)
         return fail(ctx, SPK_ERR_DEVICE,
@@ -1406,7 +1622,8 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
                         hipGetErrorString(ctx->scratch_err));
     SPK_HIP(ctx, hipSetDevice(ctx->device));
     int32_t verdict = 0;
-    if ((s = gpu_verdict(ctx, A, &verdict)) != SPK_OK) return s;
+    int64_t max_row = 0;
+    if ((s = gpu_verdict(ctx, A, &verdict, &max_row)) != SPK_OK) return s;
     if (verdict != SPK_CSR_OK) return fail(ctx, SPK_ERR_INVALID_ARG, std::string("malformed CSR: ") + verdict_name(verdict));
     spk_log L;
     std::memset(&L, 0, sizeof(L));
@@ -1422,6 +1639,7 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
     pl.ctx = ctx;
     pl.kind = 1;
     pl.A = to_dev(A);
+    pl.A.max_row = max_row;
     pl.cfg = cfg;
     pl.algo = ALGO_CG;
     char *base = static_cast<char *>(ctx->scratch);
@@ -1431,14 +1649,21 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
     pl.r = reinterpret_cast<double *>(base + kNaVecBase);
     pl.p = reinterpret_cast<double *>(base + kNaVecBase + vb);
     pl.q = reinterpret_cast<double *>(base + kNaVecBase + 2 * vb);
+    pl.fused = fused_loop(cfg, n);
+    if (pl.fused) {
+        pl.r_b = reinterpret_cast<double *>(base + kNaVecBase + 3 * vb);
+        pl.p_b = reinterpret_cast<double *>(base + kNaVecBase + 4 * vb);
+        pl.q_b = reinterpret_cast<double *>(base + kNaVecBase + 5 * vb);
+    }
     pl.h_st = ctx->h_noalloc_st;
     std::memset(pl.h_st, 0, sizeof(SolveState));
     const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
     pl.vec_grid = static_cast<int>(std::clamp<int64_t>(want, 1, int64_t(ctx->num_cu) * 4));
     // the launch shape an earlier plan of this shape tuned (read from the
     // context's cache, never added to it), else the heuristic one
-    const TuneKey key{pl.A.n_rows, pl.A.n_cols, pl.A.nnz, pl.A.ptr_t, pl.A.idx_t, pl.A.val_t, TUNE_CG, false,
-                      stream_ok(pl.A)};
+    const TuneKey key{pl.A.n_rows, pl.A.n_cols, pl.A.nnz, pl.A.ptr_t, pl.A.idx_t, pl.A.val_t,
+                      pl.fused ? TUNE_FCG : TUNE_CG, false,
+                      stream_ok(pl.A), 0};
     if (!forced_tune(ctx, pl.A, &pl.tune)) {
         auto hit = ctx->tune_cache.find(key);
         pl.tune = hit != ctx->tune_cache.end() && pl.A.nnz >= 100000 ? hit->second.tune : heuristic_tune(ctx, pl.A);
@@ -1512,6 +1737,46 @@ spk_status spk_free(spk_plan pl) {
     release_workspace(pl);
     ctx->live_plans--;
     delete pl;
+    return SPK_OK;
+}
+
+spk_status spk_gather_probe(spk_ctx ctx, const double *src, int64_t n_src, const int32_t *idx, int64_t m,
+                            double *dst, double *ms) {
+    if (!ctx) return SPK_ERR_INVALID_ARG;
+    if (n_src < 1 || m < 0 || n_src > INT32_MAX || !src || (m > 0 && (!idx || !dst)))
+        return fail(ctx, SPK_ERR_INVALID_ARG, "gather probe: bad sizes or null pointers");
+    SPK_HIP(ctx, hipSetDevice(ctx->device));
+    // the indices must stay in range: checked on the GPU first (the CSR
+    // validation kernel on a one-row matrix whose columns are idx)
+    spk_csr probe{};
+    probe.n_rows = 1;
+    probe.n_cols = n_src;
+    probe.nnz = m;
+    probe.ptr_type = SPK_I64;
+    probe.idx_type = SPK_I32;
+    probe.val_type = SPK_F64;
+    int64_t rp_h[2] = {0, m};
+    void *rp_d = nullptr;
+    if (ctx->dpool.get(sizeof(rp_h), &rp_d) != hipSuccess) return fail(ctx, SPK_ERR_OUT_OF_MEMORY, "gather probe");
+    probe.row_ptr = rp_d;
+    probe.col_idx = idx;
+    probe.values = dst;
+    int32_t verdict = 0;
+    spk_status s = SPK_OK;
+    if (hipMemcpyAsync(rp_d, rp_h, sizeof(rp_h), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+        s = fail(ctx, SPK_ERR_DEVICE, "gather probe: upload");
+    if (s == SPK_OK) s = gpu_verdict(ctx, &probe, &verdict);
+    ctx->dpool.put(rp_d);
+    if (s != SPK_OK) return s;
+    if (verdict != SPK_CSR_OK) return fail(ctx, SPK_ERR_INVALID_ARG, "gather probe: an index is out of range");
+    const int grid = std::min(ctx->num_cu * 8, spk::kMaxGrid);
+    SPK_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (m > 0) SPK_HIP(ctx, spk::launch_gather(src, idx, dst, m, grid, ctx->stream));
+    SPK_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    SPK_HIP(ctx, hipEventSynchronize(ctx->ev1));
+    float t = 0.f;
+    SPK_HIP(ctx, hipEventElapsedTime(&t, ctx->ev0, ctx->ev1));
+    if (ms) *ms = t;
     return SPK_OK;
 }
 

@@ -29,7 +29,9 @@ enum Stop : int32_t {
 };
 
 // Reduction sites: each owns an arrival counter and a partials slab.
-enum Site : int { SITE_INIT = 0, SITE_PQ = 1, SITE_RR = 2, SITE_TRUE = 3, SITE_COUNT = 4 };
+// SITE_FCG: the fused CG step's two partial sets (p.q, r.q, q.q, r.r; one set
+// per iteration parity), slabs 4 * parity + j from the site's start.
+enum Site : int { SITE_INIT = 0, SITE_PQ = 1, SITE_RR = 2, SITE_TRUE = 3, SITE_FCG = 4, SITE_COUNT = 7 };
 constexpr int kSiteWidth = 3;      // values reduced at once per site (max)
 
 // Device-resident scalars of one CG solve.  Loop kernels read only fields
@@ -49,6 +51,41 @@ struct SolveState {
     void *x;              // solution vector of this solve (FP64 x, or FP32 d of an inner solve)
     double *hist;         // optional ||r_k|| history
     int64_t hist_cap;
+};
+
+// Vector pairs of the fused CG loop: step k reads buffer (k + 1) & 1 of each
+// pair and writes buffer k & 1; the initial residual goes to buffer 1.
+template <typename T>
+struct FcgBufs {
+    T *r[2], *p[2], *q[2];
+};
+
+// Result of a persistent mixed-precision solve (written by workgroup 0).
+struct PersistResult {
+    int64_t inner, outer;   // inner iterations in all, refinement steps
+    double rnorm, bnorm;    // last ||b - A x|| (FP64) and ||b||
+    int32_t stop;
+};
+
+// Arguments of a persistent solve (matrix fields filled by the launcher).
+struct PersistSolve {
+    int64_t n, nnz;
+    const void *rp, *ci, *va, *va64;
+    const double *b;
+    double *x;
+    FcgBufs<double> f64;   // FP64 solve
+    FcgBufs<float> f32;    // mixed: inner vectors
+    float *d32;            // mixed: inner correction
+    SolveState *st;        // FP64 solve: the state the host reads
+    PersistResult *res;    // mixed: the result
+    double *partials;
+    unsigned *bar;
+    uint64_t spin_ticks;
+    double tau, tau_in;
+    int64_t max_iters, max_outer;
+    double *hist;
+    int64_t hist_cap;
+    int remap, nt, true_residual, long_row;
 };
 
 // Restarted GMRES: the small per-solve arrays (device memory, one per plan).
@@ -94,7 +131,17 @@ struct CsrDev {
     // int64 first entry of every 256-row tile (tiles + 1 values), followed
     // directly by one uint16 per row, its first entry less its tile's.
     const void *rowpack = nullptr;
+    // The pattern's period in rows when known (with codes: the largest column
+    // offset magnitude, N^2 for a 3-D 7-point stencil), else 0; picks the
+    // period-slab tile order (host side only).
+    int64_t period = 0;
+    // The longest row's entry count (measured when the plan validates A; 0 =
+    // unknown).  Above kLongRow the row tiles sum such rows with the whole
+    // workgroup (host side only: it sets the kernels' long-row argument).
+    int64_t max_row = 0;
 };
+
+constexpr int kLongRow = 256;   // rows longer than this are summed by a whole workgroup
 
 constexpr int kCodeDict = 256;    // distinct column offsets a code table holds
 constexpr int kCodeSlots = 1024;  // plan-time hash table of distinct offsets (power of two)

@@ -25,6 +25,7 @@
 // iteration (chunk base + index within the chunk), so no launch reads a
 // location that it writes.  Kernels return at once when the stop flag is
 // set, so iterations enqueued past convergence cost only empty launches.
+#include "spk_fcg.h"
 #include "spk_launch.h"
 #include "spk_spmv.h"
 
@@ -131,6 +132,47 @@ struct EpiTrue {
         double v[1] = {acc};
         block_partial<1>(v, part);
     }
+};
+
+// ------------------------------------------------------------------ fused CG step
+// One launch per CG iteration (the step and its decisions are described in
+// spk_fcg.h).  The prologue runs in skip(): every workgroup sums the partials
+// the previous step left and takes the same stop decision.
+template <typename T>
+struct EpiFcg : fcg::Rows<T> {
+    FcgBufs<T> buf;
+    SolveState *st;
+    double *part;   // two sets of 4 slabs of kMaxGrid: set s at part + 4 s kMaxGrid
+    int G;          // workgroups of every step (partials per slab)
+    int j;          // step index within the chunk
+    int w;
+    __device__ bool skip() {
+        // one read of the flag per workgroup: workgroup 0 may set it during
+        // this launch, and all waves of a workgroup must take the same branch
+        __shared__ int s_stop;
+        if (threadIdx.x == 0) s_stop = st->stop;
+        __syncthreads();
+        if (s_stop != STOP_RUNNING) return true;
+        const int64_t k = st->base + j;
+        w = static_cast<int>(k & 1);
+        this->bind(buf, static_cast<T *>(st->x), k);
+        if (k == 0) return false;
+        double tot[4];
+        sum_partials<4>(part + (w ? 0 : static_cast<size_t>(4) * kMaxGrid), G, tot);
+        const int64_t done = k - 1;   // x holds x_{k-1}
+        double a = 0.0, b = 0.0;
+        const int stop = fcg::decide(tot, done, st->thresh, st->max_iters, a, b);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            fcg::record(st, tot, done);
+            if (stop == STOP_RUNNING) st->alpha = a;
+            else st->stop = stop;   // every workgroup took the same decision
+        }
+        if (stop != STOP_RUNNING) return true;
+        this->alpha = static_cast<T>(a);
+        this->beta = static_cast<T>(b);
+        return false;
+    }
+    __device__ void finish() { block_partial<4>(this->acc, part + (w ? static_cast<size_t>(4) * kMaxGrid : 0)); }
 };
 
 // ------------------------------------------------------------------ CG scalar + vector kernels
@@ -404,205 +446,6 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, const SolveState *
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0;
 }
 
-// ------------------------------------------------------------------ persistent CG
-// The whole FP64 CG solve in one cooperative launch (all workgroups resident):
-// init, then per iteration SpMV+p.q | update+r.r | p-update, each phase
-// followed by a grid barrier.  After a barrier every workgroup sums the same
-// partials in the same order, so all take identical decisions (alpha, beta,
-// stop) and leave the loop together.  Workgroup 0 mirrors the results into
-// the SolveState for the host.  The barrier's release/acquire at agent scope
-// makes each phase's vector writes visible to every XCD before the next phase.
-// A barrier that waits longer than a wall-clock limit sets the error flag;
-// every workgroup then leaves, so the launch always ends.
-
-struct PersistArgs {
-    int64_t n, nnz;
-    const void *rp, *ci;
-    const double *va, *b;
-    double *x, *r, *p, *q;
-    SolveState *st;
-    double *part;          // 5 disjoint slabs of kMaxGrid doubles
-    unsigned *bar;         // [0] arrivals, [1] generation, [2] error flag
-    uint64_t spin_ticks;   // barrier wait limit in wall_clock64() ticks
-    double tau;
-    int64_t max_iters;
-    double *hist;
-    int64_t hist_cap;
-    int remap, true_residual;
-};
-
-// Grid-wide barrier; returns false once any workgroup has timed out.
-__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned &gen, uint64_t spin_ticks) {
-    __shared__ int s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-        if (ok) {
-            const unsigned g0 = gen;
-            const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == gridDim.x - 1) {
-                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&bar[1], g0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                const uint64_t t0 = wall_clock64();
-                // relaxed polling (an acquiring load would invalidate the caches on every
-                // poll); one acquire fence once the generation has moved
-                while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                    if (wall_clock64() - t0 > spin_ticks) {
-                        __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ok = 0;
-                        break;
-                    }
-                }
-            }
-            gen = g0 + 1;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
-
-template <typename P, typename I>
-__global__ __launch_bounds__(kBlock) void k_cg_persistent(PersistArgs a) {
-    __shared__ u32x4 lv[Chunks<double>::LDS];
-    __shared__ u32x4 lc[Chunks<I>::LDS];
-    __shared__ unsigned s_gen0;
-    const P *rp = static_cast<const P *>(a.rp);
-    const I *ci = static_cast<const I *>(a.ci);
-    const int64_t n = a.n;
-    const int G = gridDim.x;
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (threadIdx.x == 0) s_gen0 = __hip_atomic_load(&a.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    unsigned gen = s_gen0;
-    // disjoint slabs: init (2), p.q, r.r; the init slabs are reused by the true residual
-    double *part_a = a.part, *part_b = a.part + 2 * kMaxGrid, *part_c = a.part + 3 * kMaxGrid;
-    // this workgroup's contiguous, even-aligned row chunk for the vector phases
-    int64_t chunk = (n + G - 1) / G;
-    chunk += chunk & 1;
-    const int64_t v0 = min(static_cast<int64_t>(blockIdx.x) * chunk, n);
-    const int64_t v1 = min(v0 + chunk, n);
-
-    // ---- init: r = b - A x, p = r; ||b||, rho_0
-    {
-        EpiInit e{a.b, a.r, a.p, part_a, 0.0, 0.0};
-        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, 1, e, lv, lc);
-        e.finish();   // partials of r.r, b.b into part_a[0..G), part_a[kMaxGrid..)
-    }
-    if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
-    double tot2[2];
-    sum_partials<2>(part_a, G, tot2);
-    const double bn = sqrt(tot2[1]);
-    double rho = tot2[0];
-    int stop = STOP_RUNNING, zero_x = 0;
-    double res = sqrt(rho);
-    if (!isfinite(bn)) {
-        stop = STOP_NON_FINITE;
-        res = bn;
-    } else if (bn == 0.0) {
-        stop = STOP_CONVERGED;
-        zero_x = 1;
-        res = 0.0;
-    } else if (!isfinite(rho)) stop = STOP_NON_FINITE;
-    else if (res <= a.tau * bn) stop = STOP_CONVERGED;
-    else if (a.max_iters <= 0) stop = STOP_MAX_ITERS;
-    if (lead) {
-        SolveState *S = a.st;
-        S->x = a.x;
-        S->hist = a.hist;
-        S->hist_cap = a.hist_cap;
-        S->max_iters = a.max_iters;
-        S->base = 0;
-        S->iter = 0;
-        S->zero_x = zero_x;
-        S->bnorm = bn;
-        S->thresh = a.tau * bn;
-        S->rho[0] = zero_x ? 0.0 : rho;
-        S->resnorm = res;
-        S->true_resnorm = zero_x ? 0.0 : __builtin_nan("");
-        S->stop = stop;
-        if (a.hist && a.hist_cap > 0) a.hist[0] = res;
-    }
-    int64_t k = 0;
-    while (stop == STOP_RUNNING) {
-        // q = A p, partials of p.q
-        {
-            EpiPq<double> e{a.q, a.p, a.st, part_b, 0.0};
-            spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.p}, a.remap, 0, 1,
-                                                 e, lv, lc);
-            e.finish();
-        }
-        if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
-        double t1[1];
-        sum_partials<1>(part_b, G, t1);
-        const double pq = t1[0];
-        if (!isfinite(pq) || pq <= 0.0) {
-            stop = isfinite(pq) ? STOP_BREAKDOWN : STOP_NON_FINITE;
-            if (lead) {
-                a.st->pq = pq;
-                a.st->stop = stop;
-            }
-            break;
-        }
-        const double alpha = rho / pq;
-        double acc = 0.0;
-        for (int64_t i = v0 + threadIdx.x; i < v1; i += kBlock) {
-            a.x[i] = fma(alpha, a.p[i], a.x[i]);
-            const double ri = fma(-alpha, a.q[i], a.r[i]);
-            a.r[i] = ri;
-            acc = fma(ri, ri, acc);
-        }
-        {
-            double v[1] = {acc};
-            block_partial<1>(v, part_c);
-        }
-        if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
-        sum_partials<1>(part_c, G, t1);
-        const double rho_new = t1[0];
-        k += 1;
-        res = sqrt(rho_new);
-        if (!isfinite(rho_new)) stop = STOP_NON_FINITE;
-        else if (res <= a.tau * bn) stop = STOP_CONVERGED;
-        else if (k >= a.max_iters) stop = STOP_MAX_ITERS;
-        if (lead) {
-            a.st->iter = k;
-            a.st->resnorm = res;
-            a.st->pq = pq;
-            a.st->alpha = alpha;
-            a.st->rho[k & 3] = rho_new;
-            if (a.hist && k < a.hist_cap) a.hist[k] = res;
-            if (stop != STOP_RUNNING) a.st->stop = stop;
-        }
-        if (stop != STOP_RUNNING) break;
-        const double beta = rho_new / rho;
-        rho = rho_new;
-        for (int64_t i = v0 + threadIdx.x; i < v1; i += kBlock) a.p[i] = fma(beta, a.p[i], a.r[i]);
-        if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
-    }
-    if (zero_x) {
-        for (int64_t i = v0 + threadIdx.x; i < v1; i += kBlock) a.x[i] = 0.0;
-        return;
-    }
-    if (!a.true_residual || stop == STOP_NON_FINITE) return;
-    if (!grid_sync(a.bar, gen, a.spin_ticks)) return;   // x complete everywhere
-    {
-        EpiTrue e{a.b, a.st, part_a, 0.0};
-        spmv_tiles_lds<double, P, I, double>(n, a.nnz, rp, ci, a.va, PlainGather<double, double>{a.x}, a.remap, 0, 1, e, lv, lc);
-        e.finish();
-    }
-    if (!grid_sync(a.bar, gen, a.spin_ticks)) return;
-    double t1[1];
-    sum_partials<1>(part_a, G, t1);
-    if (lead) a.st->true_resnorm = sqrt(t1[0]);
-}
-
 // ------------------------------------------------------------------ structure kernels
 template <typename P, typename I>
 __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_cols, int64_t nnz,
@@ -615,8 +458,15 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
         if (rp[0] != 0) f |= VFLAG_BAD_FIRST;
         if (static_cast<int64_t>(rp[n_rows]) != nnz) f |= VFLAG_BAD_LAST;
     }
-    for (int64_t i = gid; i < n_rows; i += stride)
-        if (rp[i + 1] < rp[i]) f |= VFLAG_DECREASING;
+    unsigned longest = 0;   // longest row (entries, clamped to 2^32 - 1), for the long-row path of the SpMV
+    for (int64_t i = gid; i < n_rows; i += stride) {
+        const int64_t len = static_cast<int64_t>(rp[i + 1]) - static_cast<int64_t>(rp[i]);
+        if (len < 0) f |= VFLAG_DECREASING;
+        else longest = max(longest, len > 0xffffffffll ? 0xffffffffu : static_cast<unsigned>(len));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) longest = max(longest, static_cast<unsigned>(__shfl_xor(longest, off, 64)));
+    if ((threadIdx.x & 63) == 0 && longest > 0) atomicMax(flags + 1, longest);
     // column indices: 16-byte loads when aligned, element loads for the tail
     constexpr int EPC = 16 / sizeof(I);
     int64_t done = 0;
@@ -969,6 +819,15 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
 }
 
+// Random-gather probe: dst[i] = src[idx[i]] (indices and results streamed
+// coalesced, the source read at random 8-byte positions).
+__global__ __launch_bounds__(kBlock) void k_gather(const double *__restrict__ src, const int32_t *__restrict__ idx,
+                                                   double *__restrict__ dst, int64_t m) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < m; i += stride)
+        dst[i] = src[idx[i]];
+}
+
 int grid_for(int64_t n, int per_thread, int cap) {
     const int64_t want = (n + static_cast<int64_t>(kBlock) * per_thread - 1) / (static_cast<int64_t>(kBlock) * per_thread);
     return static_cast<int>(want < 1 ? 1 : (want > cap ? cap : want));
@@ -1083,6 +942,56 @@ hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, d
     return hipGetLastError();
 }
 
+hipError_t launch_fcg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, const FcgBufs<double> &f,
+                           SolveState *st, double *partials, double tau, int64_t max_iters, double *hist,
+                           int64_t hist_cap, hipStream_t s) {
+    fcg::EpiInit e{b, f.r[1], f.p[1], f.q[1], site(partials, SITE_INIT), 0.0, 0.0};
+    hipError_t err = launch_family<double, double, double>(A, t, x, e, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kBlock), 0, s, st, site(partials, SITE_INIT), t.grid, tau,
+                       max_iters, x, hist, hist_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_step(const CsrDev &A, const SpmvTune &t, int j, const FcgBufs<double> &f, SolveState *st,
+                           double *partials, hipStream_t s) {
+    EpiFcg<double> e{};
+    e.buf = f;
+    e.st = st;
+    e.part = site(partials, SITE_FCG);
+    e.G = t.grid;
+    e.j = j;
+    return launch_family<double, double, double>(A, t, f.p[0], e, s);
+}
+
+hipError_t launch_fcg_step32(const CsrDev &A32, const SpmvTune &t, int j, const FcgBufs<float> &f, SolveState *st,
+                             double *partials, hipStream_t s) {
+    EpiFcg<float> e{};
+    e.buf = f;
+    e.st = st;
+    e.part = site(partials, SITE_FCG);
+    e.G = t.grid;
+    e.j = j;
+    if (A32.val_t == 1) return launch_family<float, float, float>(A32, t, f.p[0], e, s);
+    if (A32.val_t == 3) return launch_family<bf16s, float, float>(A32, t, f.p[0], e, s);
+    if (A32.val_t == 2) return launch_family<_Float16, float, float>(A32, t, f.p[0], e, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fcg_ir_residual(const CsrDev &A, const SpmvTune &t, const double *b, const double *x,
+                                  const FcgBufs<float> &f, float *d32, SolveState *in, double *partials,
+                                  double tau_in, int64_t max_inner, double *out, hipStream_t s) {
+    fcg::EpiIrResidual e{b, f.r[1], f.p[1], f.q[1], d32, site(partials, SITE_INIT), 0.0, 0.0, 0.0};
+    hipError_t err = hipSuccess;
+    if (A.val_t == 0) err = launch_family<double, double, double>(A, t, x, e, s);
+    else if (A.val_t == 1) err = launch_family<float, double, double>(A, t, x, e, s);
+    else return hipErrorInvalidValue;
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, in, site(partials, SITE_INIT), t.grid, tau_in,
+                       max_inner, d32, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q, SolveState *st,
                              double *partials, hipStream_t s) {
     EpiPq<double> e{q, p, st, site(partials, SITE_PQ), 0.0};
@@ -1175,33 +1084,9 @@ hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *
     return hipGetLastError();
 }
 
-template <typename P, typename I>
-static hipError_t launch_persist_t(const PersistArgs &a, int grid, hipStream_t s) {
-    void *args[] = {const_cast<PersistArgs *>(&a)};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_persistent<P, I>), dim3(grid), dim3(kBlock),
-                                      args, 0, s);
-}
-
-hipError_t launch_cg_persistent(const CsrDev &A, int grid, int remap, const double *b, double *x, double *r, double *p,
-                                double *q, SolveState *st, double *partials, unsigned *bar, uint64_t spin_ticks,
-                                double tau, int64_t max_iters, double *hist, int64_t hist_cap, int true_residual,
-                                hipStream_t s) {
-    PersistArgs a{A.n_rows, A.nnz, A.rp, A.ci, static_cast<const double *>(A.va), b, x, r, p, q, st, partials, bar,
-                  spin_ticks, tau, max_iters, hist, hist_cap, remap, true_residual};
-    if (A.ptr_t == 0 && A.idx_t == 0) return launch_persist_t<int32_t, int32_t>(a, grid, s);
-    if (A.ptr_t == 0) return launch_persist_t<int32_t, int64_t>(a, grid, s);
-    if (A.idx_t == 0) return launch_persist_t<int64_t, int32_t>(a, grid, s);
-    return launch_persist_t<int64_t, int64_t>(a, grid, s);
-}
-
-int persistent_blocks_per_cu(const CsrDev &A) {
-    int blocks = 0;
-    hipError_t e;
-    if (A.ptr_t == 0 && A.idx_t == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int32_t, int32_t>, kBlock, 0);
-    else if (A.ptr_t == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int32_t, int64_t>, kBlock, 0);
-    else if (A.idx_t == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int64_t, int32_t>, kBlock, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_cg_persistent<int64_t, int64_t>, kBlock, 0);
-    return (e == hipSuccess && blocks > 0) ? blocks : 0;
+hipError_t launch_gather(const double *src, const int32_t *idx, double *dst, int64_t m, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3(grid), dim3(kBlock), 0, s, src, idx, dst, m);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s) {

@@ -8,6 +8,8 @@
 namespace spk {
 
 // ---- launchers (spk_kernels.hip) -------------------------------------------------
+// CSR checks: flags[0] |= VFLAG_* bits, flags[1] = max(flags[1], the longest
+// row's entry count, clamped to 2^32 - 1); both words zero before the launch.
 hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
 // Column codes (plan time): collects the distinct column offsets c - i of
@@ -42,6 +44,21 @@ hipError_t launch_cg_init(const CsrDev &A, const SpmvTune &t, const double *b, d
                           double *hist, int64_t hist_cap, hipStream_t s);
 hipError_t launch_cg_spmv_pq(const CsrDev &A, const SpmvTune &t, const double *p, double *q,
                              SolveState *st, double *partials, hipStream_t s);
+// Fused CG loop (one launch per iteration): the initial residual into
+// f.r[1] with f.p[1] = f.q[1] = 0 (then the state as launch_cg_init), step j
+// of a chunk (iteration st->base + j; x is the state's), and the FP32 inner
+// step of the mixed solve (its x is the correction d); the refinement
+// residual before a fused inner loop.
+hipError_t launch_fcg_init(const CsrDev &A, const SpmvTune &t, const double *b, double *x, const FcgBufs<double> &f,
+                           SolveState *st, double *partials, double tau, int64_t max_iters, double *hist,
+                           int64_t hist_cap, hipStream_t s);
+hipError_t launch_fcg_step(const CsrDev &A, const SpmvTune &t, int j, const FcgBufs<double> &f, SolveState *st,
+                           double *partials, hipStream_t s);
+hipError_t launch_fcg_step32(const CsrDev &A32, const SpmvTune &t, int j, const FcgBufs<float> &f, SolveState *st,
+                             double *partials, hipStream_t s);
+hipError_t launch_fcg_ir_residual(const CsrDev &A, const SpmvTune &t, const double *b, const double *x,
+                                  const FcgBufs<float> &f, float *d32, SolveState *in, double *partials,
+                                  double tau_in, int64_t max_inner, double *out, hipStream_t s);
 hipError_t launch_cg_update(int64_t n, int grid, int spmv_grid, int j, double *r, const double *q, SolveState *st,
                             double *partials, hipStream_t s);
 hipError_t launch_cg_pupdate(int64_t n, int grid, int j, const double *r, double *p, SolveState *st,
@@ -70,6 +87,8 @@ hipError_t launch_cg_finalize(const CsrDev &A, const SpmvTune &t, const double *
                               SolveState *st, double *partials, int true_residual, hipStream_t s);
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, int grid, hipStream_t s);
+// dst[i] = src[idx[i]], i < m (idx in range).
+hipError_t launch_gather(const double *src, const int32_t *idx, double *dst, int64_t m, int grid, hipStream_t s);
 
 // Allocation-free solves (spk_noalloc.hip).  noalloc_scratch_setup: device
 // address of this device's scratch array (kNoallocScratchBytes), looked up
@@ -132,15 +151,20 @@ hipError_t launch_pcg_update(int64_t n, int grid, int spmv_grid, int j, double *
 hipError_t launch_pcg_pupdate(int64_t n, int grid, int j, const double *r, const double *dinv, double *p,
                               SolveState *st, double *partials, hipStream_t s);
 
-// Whole FP64 CG solve in one cooperative launch (grid must be co-resident:
-// grid <= persistent_blocks_per_cu * CUs).  partials: at least 5 * kMaxGrid
-// doubles.  bar: 3 unsigned, [0] and [2] zero at launch.  Afterwards
-// bar[2] != 0 means a barrier waited longer than spin_ticks (wall clock).
-hipError_t launch_cg_persistent(const CsrDev &A, int grid, int remap, const double *b, double *x, double *r, double *p,
-                                double *q, SolveState *st, double *partials, unsigned *bar, uint64_t spin_ticks,
-                                double tau, int64_t max_iters, double *hist, int64_t hist_cap, int true_residual,
-                                hipStream_t s);
-int persistent_blocks_per_cu(const CsrDev &A);
+// Persistent solves (spk_persist.hip): the whole CG solve in one
+// cooperative launch, one grid barrier per fused iteration.  A: the matrix of
+// the iterations (FP64 values for an FP64 solve; the FP32/BF16/FP16 inner
+// values of a mixed solve); outer: the refinement's matrix of a mixed solve
+// (same index arrays, FP64 or FP32-exact values), nullptr for FP64.  The
+// grid must be co-resident: grid <= persistent_blocks_per_cu(A, outer) * CUs
+// (0: no persistent kernel for these types; then use the host loop).  The
+// launcher fills the matrix fields of a.  bar: 3 unsigned, [0] and [2] zero
+// at launch; afterwards bar[2] != 0 means a barrier waited longer than
+// spin_ticks (wall clock) and the solve was abandoned.  An FP64 solve leaves
+// its state in a.st as the host loop does (true residual included); a mixed
+// solve writes a.res.
+hipError_t launch_persistent(const CsrDev &A, const CsrDev *outer, PersistSolve a, int grid, hipStream_t s);
+int persistent_blocks_per_cu(const CsrDev &A, const CsrDev *outer);
 
 // Workgroups of the SpMV kernel resident per CU for this tune/type (occupancy API).
 int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t);

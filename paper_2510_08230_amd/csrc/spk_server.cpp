@@ -157,7 +157,7 @@ bool hip_ok(spk_server srv, hipError_t e, const char *what) {
 bool request_valid(spk_server srv, const Request &r) {
     spk::CsrDev d{r.A.n_rows, r.A.n_cols, r.A.nnz, r.A.ptr_type, r.A.idx_type, r.A.val_type,
                   r.A.row_ptr, r.A.col_idx, r.A.values};
-    if (!hip_ok(srv, hipMemsetAsync(srv->d_flags, 0, sizeof(unsigned), srv->stream), "flags")) return false;
+    if (!hip_ok(srv, hipMemsetAsync(srv->d_flags, 0, 2 * sizeof(unsigned), srv->stream), "flags")) return false;
     if (!hip_ok(srv, spk::launch_validate(d, srv->d_flags, srv->num_cu * 4, srv->stream), "validate")) return false;
     if (!hip_ok(srv, hipMemcpyAsync(srv->h_flags, srv->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, srv->stream),
                 "flags copy"))
@@ -428,14 +428,14 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
               hipMalloc(&srv->d_desc, sizeof(spk::SlotDesc) * ms) == hipSuccess &&
               hipMalloc(&srv->d_state, sizeof(spk::SlotState) * ms) == hipSuccess &&
               hipMalloc(&srv->d_status, sizeof(spk::SlotStatus) * ms) == hipSuccess &&
-              hipMalloc(&srv->d_flags, sizeof(unsigned)) == hipSuccess &&
+              hipMalloc(&srv->d_flags, 2 * sizeof(unsigned)) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&srv->h_counts), 2 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&srv->h_tiles), sizeof(int2) * srv->cap_tiles, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&srv->h_slots), sizeof(int32_t) * ms, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&srv->h_desc), sizeof(spk::SlotDesc) * ms, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&srv->h_state), sizeof(spk::SlotState) * ms, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&srv->h_status), sizeof(spk::SlotStatus) * ms, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(reinterpret_cast<void **>(&srv->h_flags), sizeof(unsigned), hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc(reinterpret_cast<void **>(&srv->h_flags), 2 * sizeof(unsigned), hipHostMallocDefault) == hipSuccess;
     if (ok) {
         std::memset(srv->h_status, 0, sizeof(spk::SlotStatus) * ms);
         srv->h_counts[0] = srv->h_counts[1] = 0;

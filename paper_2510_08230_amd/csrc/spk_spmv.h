@@ -17,6 +17,7 @@
 #include "spk_device.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace spk {
 namespace tile {
@@ -32,17 +33,64 @@ struct Vec16 {
     typedef T type __attribute__((ext_vector_type(W)));
 };
 
+// Rows of the tile at r0 longer than `lim` entries (this thread's row when
+// lng; its entries [a, b)): summed one at a time by the whole workgroup --
+// each thread a strided share in storage order, then the wave sums and the
+// four wave totals in a fixed order -- and handed to epi.row by the row's own
+// thread.  Every thread of the workgroup calls this (it synchronises).
+// val(k) / cix(k): entry k's value and stored column (from LDS or global).
+template <typename C, class Gx, class D, class Epi, class Val, class Cix>
+__device__ __forceinline__ void long_rows(bool lng, int64_t a, int64_t b, int64_t r0, const Gx &gx, const D &col,
+                                          Epi &epi, const Val &val, const Cix &cix) {
+    __shared__ int s_next;
+    __shared__ int64_t s_ab[2];
+    __shared__ C s_red[kBlock / 64];
+    if (!__syncthreads_or(lng)) return;
+    int done = -1;
+    while (true) {
+        if (threadIdx.x == 0) s_next = kTileRows;
+        __syncthreads();
+        if (lng && static_cast<int>(threadIdx.x) > done) atomicMin(&s_next, static_cast<int>(threadIdx.x));
+        __syncthreads();
+        const int i = s_next;
+        if (i >= kTileRows) break;   // the same in every thread
+        if (static_cast<int>(threadIdx.x) == i) {
+            s_ab[0] = a;
+            s_ab[1] = b;
+        }
+        __syncthreads();
+        const int64_t ra = s_ab[0], rb = s_ab[1], row = r0 + i;
+        C acc = 0;
+        for (int64_t k = ra + threadIdx.x; k < rb; k += kBlock)
+            acc = fma(static_cast<C>(widen(val(k))), static_cast<C>(gx(col(cix(k), row))), acc);
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (static_cast<int>(threadIdx.x) == i) {
+            C t = s_red[0];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) t += s_red[w];
+            epi.row(row, t);
+        }
+        done = i;
+        __syncthreads();   // s_ab and s_red are reused by the next long row
+    }
+}
+
 // LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
 // thread per row reduces from LDS while gathering x.  Occupancy (several
 // workgroups per CU) overlaps one workgroup's DMA with another's gathers.
 // The tile loop of the LDS-staged SpMV, shared by the per-launch kernel and the
 // persistent CG kernel: calls epi.row(row, sum) for every row of the tiles
 // this workgroup visits.  lv / lc: the workgroup's LDS staging buffers.
+// long_row > 0 (the matrix has rows longer than that): rows of more than
+// long_row entries are summed by the whole workgroup (long_rows), so a hub
+// row does not serialise its tile on one lane.
 template <typename V, typename P, typename I, typename C, class Gx, class Epi, class D = ColPlain>
 __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
                                                int remap, int nt, int pf, Epi &epi, u32x4 *lv, u32x4 *lc,
-                                               const D &col = D{}) {
+                                               const D &col = D{}, int long_row = 0) {
     const V *sv = reinterpret_cast<const V *>(lv);
     const I *sc = reinterpret_cast<const I *>(lc);
     const int64_t T = (n + kTileRows - 1) / kTileRows;
@@ -60,21 +108,26 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
         const int64_t row = cur.r0 + threadIdx.x;
         const int64_t s = static_cast<int64_t>(cur.s), e = static_cast<int64_t>(cur.e);
         const int64_t a = static_cast<int64_t>(cur.a), b = static_cast<int64_t>(cur.b);
+        const bool lng = long_row > 0 && row < r1 && b - a > long_row;
         if (e - s <= kStreamCap) {
             dma_chunks<V>(va, s, e, nnz, lv, nt);
             dma_chunks<I>(ci, s, e, nnz, lc, nt);
             if (more && pf) nxt.load(rp, n, after.tile());
             __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA (and the prefetch) has landed
             __syncthreads();                 // ... and every other wave's
-            if (row < r1) {
-                const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
-                const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
-                epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row));
-            }
+            const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
+            const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
+            if (row < r1 && !lng) epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row));
+            if (long_row > 0)
+                long_rows<C>(lng, a, b, cur.r0, gx, col, epi, [&](int64_t k) { return sv[k - s0v]; },
+                             [&](int64_t k) { return sc[k - s0c]; });
             __syncthreads();                 // LDS free for the next tile
         } else {
             if (more && pf) nxt.load(rp, n, after.tile());
-            if (row < r1) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt, col, row));
+            if (row < r1 && !lng) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt, col, row));
+            if (long_row > 0)
+                long_rows<C>(lng, a, b, cur.r0, gx, col, epi, [&](int64_t k) { return ldv(va + k, nt); },
+                             [&](int64_t k) { return ci[k]; });
         }
         if (!more) break;
         if (!pf) nxt.load(rp, n, after.tile());
@@ -83,11 +136,26 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
     }
 }
 
+// The gather of the product's input vector: x[c] itself, unless the epilogue
+// forms the vector on the fly (it then provides gather(), e.g. the fused CG
+// step, whose direction p_k = r_{k-1} - alpha q_{k-1} + beta p_{k-1} is
+// formed at every gathered column).
+template <class Epi, class = void>
+struct HasGather : std::false_type {};
+template <class Epi>
+struct HasGather<Epi, std::void_t<decltype(std::declval<const Epi &>().gather())>> : std::true_type {};
+
+template <typename X, typename C, class Epi>
+__device__ __forceinline__ auto gather_of(const Epi &epi, const X *x) {
+    if constexpr (HasGather<Epi>::value) return epi.gather();
+    else return PlainGather<X, C>{x};
+}
+
 template <typename V, typename P, typename I, typename X, typename C, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const V *__restrict__ va,
                                                         const X *__restrict__ x, int remap, int nt, int pf,
-                                                        Epi epi_in) {
+                                                        int long_row, Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
     __shared__ u32x4 lv[Chunks<V>::LDS];
@@ -98,10 +166,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, 
         const int64_t *g = reinterpret_cast<const int64_t *>(ci) - kCodeDict;
         for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = g[i];
         __syncthreads();
-        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, pf, epi, lv, lc,
-                                   ColCoded{dict});
+        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
+                                   ColCoded{dict}, long_row);
     } else {
-        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, PlainGather<X, C>{x}, remap, nt, pf, epi, lv, lc);
+        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
+                                   ColPlain{}, long_row);
     }
     epi.finish();
 }
@@ -140,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int64_t n, const P *__re
                                                         int nt, Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
-    spmv_tiles_vector<V, P, I, C>(n, rp, ci, va, PlainGather<X, C>{x}, lanes_log2, remap, nt, epi);
+    spmv_tiles_vector<V, P, I, C>(n, rp, ci, va, gather_of<X, C>(epi, x), lanes_log2, remap, nt, epi);
     epi.finish();
 }
 
@@ -170,19 +239,20 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
         // row, which sums each row in the same order
         auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
         const bool coded = t.kind == 0 && t.codes && A.codes;
+        const int lr = A.max_row > kLongRow ? kLongRow : 0;
         if (t.kind == 0 && !(al16(A.va) && (coded || al16(A.ci)))) {
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x, 0,
                                t.xcd_remap, t.nt, epi);
         } else if (t.kind == 0 && t.codes && A.codes && t.pack && A.rowpack) {
             hipLaunchKernelGGL((k_spmv_stream<V, RowPack, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz,
                                static_cast<const RowPack *>(A.rowpack), static_cast<const Code8 *>(A.codes), va, x,
-                               t.xcd_remap, t.nt, t.pf, epi);
+                               t.xcd_remap, t.nt, t.pf, lr, epi);
         } else if (t.kind == 0 && t.codes && A.codes) {
             hipLaunchKernelGGL((k_spmv_stream<V, P, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp,
-                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, epi);
+                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, lr, epi);
         } else if (t.kind == 0) {
             hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
-                               t.xcd_remap, t.nt, t.pf, epi);
+                               t.xcd_remap, t.nt, t.pf, lr, epi);
         } else {
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
                                t.lanes_log2, t.xcd_remap, t.nt, epi);

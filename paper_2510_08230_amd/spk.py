@@ -73,7 +73,8 @@ class Log(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("spmv_kernel", ctypes.c_int32), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("exec_mode", ctypes.c_int32), ("chunk_iters", ctypes.c_int32),
-                ("tuned", ctypes.c_int32), ("col_codes", ctypes.c_int32), ("spmv_ms", ctypes.c_double)]
+                ("tuned", ctypes.c_int32), ("col_codes", ctypes.c_int32), ("spmv_ms", ctypes.c_double),
+                ("fused_loop", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +112,7 @@ _SIGS = {
     "spk_plan_kernel_stats": (ctypes.c_int, [_vp, _P(_f64), _P(_i64)]),
     "spk_free": (ctypes.c_int, [_vp]),
     "spk_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, _sz, _P(_f64)]),
+    "spk_gather_probe": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _P(_f64)]),
     "spk_solve_noalloc": (ctypes.c_int, [_vp, _P(Csr), _P(SolverCfg), _vp, _vp, _P(Log)]),
     "spk_noalloc_max_rows": (_i64, []),
     "spk_server_request_bytes": (_sz, [_i64, _i64]),
@@ -343,6 +345,18 @@ def spk_stream_copy(ctx: Context, src, dst, nbytes: int) -> float:
     ms = ctypes.c_double()
     _check(_lib.spk_stream_copy(ctx.handle, _dev_ptr(src, "src"), _dev_ptr(dst, "dst"), int(nbytes),
                                 ctypes.byref(ms)), ctx)
+    return ms.value
+
+
+def spk_gather_probe(ctx: Context, src, idx, dst) -> float:
+    """dst[i] = src[idx[i]] with the library's gather kernel; its device time (ms)."""
+    if str(src.dtype) != "torch.float64" or str(dst.dtype) != "torch.float64" or str(idx.dtype) != "torch.int32":
+        raise ValueError("src and dst must be float64, idx int32")
+    if dst.numel() < idx.numel():
+        raise ValueError("dst shorter than idx")
+    ms = ctypes.c_double()
+    _check(_lib.spk_gather_probe(ctx.handle, _dev_ptr(src, "src"), int(src.numel()), _dev_ptr(idx, "idx"),
+                                 int(idx.numel()), _dev_ptr(dst, "dst"), ctypes.byref(ms)), ctx)
     return ms.value
 
 

@@ -46,7 +46,7 @@ int main(void) {
   P(spk_coo, idx_type) P(spk_coo, row_idx) P(spk_coo, values)
   P(spk_csr, values) P(spk_csr, ptr_type) P(spk_solver_cfg, max_iters) P(spk_solver_cfg, reduction_factor)
   P(spk_solver_cfg, inner_reduction) P(spk_solver_cfg, max_outer) P(spk_log, elapsed_ms) P(spk_log, stop_reason)
-  P(spk_plan_info, spmv_ms)
+  P(spk_plan_info, spmv_ms) P(spk_plan_info, fused_loop)
   printf("SPK_SOLVER_GMRES %d\n", (int)SPK_SOLVER_GMRES);
   P(spk_solver_cfg, krylov_dim)
   printf("SPK_SOLVER_CGS %d\nSPK_PRECOND_JACOBI %d\nSPK_EXEC_PERSISTENT %d\nSPK_PREC_MIXED_BF16 %d\n",
@@ -79,7 +79,8 @@ def test_struct_layouts_match_header(tmp_path):
              ("spk_solver_cfg.inner_reduction", spk.SolverCfg.inner_reduction),
              ("spk_solver_cfg.max_outer", spk.SolverCfg.max_outer),
              ("spk_log.elapsed_ms", spk.Log.elapsed_ms), ("spk_log.stop_reason", spk.Log.stop_reason),
-             ("spk_plan_info.spmv_ms", spk.PlanInfo.spmv_ms), ("spk_coo.idx_type", spk.Coo.idx_type),
+             ("spk_plan_info.spmv_ms", spk.PlanInfo.spmv_ms),
+             ("spk_plan_info.fused_loop", spk.PlanInfo.fused_loop), ("spk_coo.idx_type", spk.Coo.idx_type),
              ("spk_coo.row_idx", spk.Coo.row_idx), ("spk_coo.values", spk.Coo.values)]
     for key, field in pairs:
         assert int(got[key]) == field.offset, key

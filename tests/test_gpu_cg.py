@@ -84,8 +84,11 @@ def test_fixed_k_iterates(spk, ctx, name, K):
 
 
 @pytest.mark.parametrize("name", sorted(MATS))
-@pytest.mark.parametrize("mode", [1, 2, 3])
-def test_converged_parity(spk, ctx, name, mode):
+@pytest.mark.parametrize("mode,fused", [(1, "1"), (2, "1"), (3, "1"), (1, "0"), (2, "0")])
+def test_converged_parity(spk, ctx, monkeypatch, name, mode, fused):
+    """Host loop, graphs and the persistent launch; the fused loop (one launch
+    per iteration) and, with SPK_CG_FUSED=0, three launches per iteration."""
+    monkeypatch.setenv("SPK_CG_FUSED", fused)
     A = MATS[name]()
     b = inputs.rhs(A.n_rows, 0)
     x, log, hist = solve(spk, ctx, A, b, mode=mode, history=True)
@@ -139,7 +142,7 @@ def test_stop_semantics_modes(spk, ctx, mode):
 
 
 def test_persistent_full_size(spk, ctx):
-    """The persistent launch at stencil7 N=215 (all workgroups of the device, 3 barriers per iteration)."""
+    """The persistent launch at stencil7 N=215 (one grid barrier per fused iteration)."""
     A = inputs.stencil7(215, 1)
     b = inputs.rhs(A.n_rows, 1)
     x, log, _ = solve(spk, ctx, A, b, mode=3)

@@ -56,7 +56,7 @@ PRECS = {"fp32": "PREC_MIXED_FP32", "bf16": "PREC_MIXED_BF16", "fp16": "PREC_MIX
 
 @pytest.mark.parametrize("name", sorted(MATS))
 @pytest.mark.parametrize("prec", sorted(PRECS))
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_refined_solution_matches_fp64_oracle(spk, ctx, name, prec, mode):
     A = MATS[name]()
     b = inputs.rhs(A.n_rows, 0)
@@ -71,29 +71,50 @@ def test_refined_solution_matches_fp64_oracle(spk, ctx, name, prec, mode):
     assert abs(log.true_resnorm - np.linalg.norm(r)) <= 1e-3 * np.linalg.norm(r) + 1e-16 * np.linalg.norm(b)
 
 
-def test_fp32_values_taken_as_exact(spk, ctx):
+@pytest.mark.parametrize("mode", [1, 3])
+def test_fp32_values_taken_as_exact(spk, ctx, mode):
     """FP32-exact matrix passed with F32 values: refinement reads the same FP32 values."""
     A = inputs.stencil7(30, 5, f32x=True)
     b = inputs.rhs(A.n_rows, 5)
-    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, val=torch.float32)
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, val=torch.float32, mode=mode)
     xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=2000)
     assert log.stop_reason == spk.STOP_CONVERGED and rel(x, xo) <= 1e-10
 
 
-def test_mixed_stop_semantics(spk, ctx):
+@pytest.mark.parametrize("fused", ["0", "1"])
+@pytest.mark.parametrize("mode", [1, 3])
+def test_persistent_equals_host_loop_counts(spk, ctx, monkeypatch, fused, mode):
+    """The mixed solve in the host loop (one launch per inner iteration, or
+    three with SPK_CG_FUSED=0) and in one persistent launch: the same outer
+    and inner iteration counts (within one per inner solve: the loops sum
+    their dot products in different orders) and the oracle's solution."""
+    monkeypatch.setenv("SPK_CG_FUSED", fused)
+    A = inputs.stencil7(40, 6)
+    b = inputs.rhs(A.n_rows, 6)
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, mode=mode)
+    monkeypatch.delenv("SPK_CG_FUSED")
+    x1, log1 = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, mode=1)
+    assert log.outer_iterations == log1.outer_iterations
+    assert abs(log.iterations - log1.iterations) <= log.outer_iterations
+    xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=2000)
+    assert rel(x, xo) <= 1e-10 and rel(x1, xo) <= 1e-10
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_mixed_stop_semantics(spk, ctx, mode):
     A = inputs.stencil7(10, 1)
     b = inputs.rhs(A.n_rows, 1)
     x0 = inputs.vec(A.n_rows, 1, 6)
-    x, log = solve_mixed(spk, ctx, A, np.zeros(A.n_rows), spk.PREC_MIXED_FP32, x0=x0)
+    x, log = solve_mixed(spk, ctx, A, np.zeros(A.n_rows), spk.PREC_MIXED_FP32, x0=x0, mode=mode)
     assert log.stop_reason == spk.STOP_CONVERGED and not x.any() and log.iterations == 0
-    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, x0=x0, max_outer=0)
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, x0=x0, max_outer=0, mode=mode)
     assert log.stop_reason == spk.STOP_MAX_ITERS and np.array_equal(x, x0) and log.outer_iterations == 0
     bn = b.copy()
     bn[7] = np.nan
-    _, log = solve_mixed(spk, ctx, A, bn, spk.PREC_MIXED_FP32)
+    _, log = solve_mixed(spk, ctx, A, bn, spk.PREC_MIXED_FP32, mode=mode)
     assert log.stop_reason == spk.STOP_NON_FINITE
     # one refinement step with a loose inner tolerance does not reach 1e-12
-    _, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, max_outer=1, inner=1e-2)
+    _, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, max_outer=1, inner=1e-2, mode=mode)
     assert log.stop_reason == spk.STOP_MAX_ITERS and log.outer_iterations == 1
 
 
@@ -124,13 +145,16 @@ def test_mixed_plan_errors(spk, ctx):
     assert e.value.status == spk.ERR_INVALID_ARG
 
 
-def test_c3_full_size(spk, ctx):
-    """stencil7 N=215 (n = 9,938,375), seed 1: FP32 inner + FP64 refinement within 1e-10 of the oracle."""
+@pytest.mark.parametrize("mode", [1, 3])
+def test_c3_full_size(spk, ctx, mode):
+    """stencil7 N=215 (n = 9,938,375), seed 1: FP32 inner + FP64 refinement within 1e-10 of the oracle
+    (host loop and one persistent launch)."""
     A = inputs.stencil7(215, 1)
     b = inputs.rhs(A.n_rows, 1)
-    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32)
+    x, log = solve_mixed(spk, ctx, A, b, spk.PREC_MIXED_FP32, mode=mode)
     xo, _, _ = oracle.cg(A, b, tau=1e-14, max_iters=1000)
-    print("mixed: %d inner its, %d outer, %.1f ms" % (log.iterations, log.outer_iterations, log.elapsed_ms))
+    print("mixed mode %d: %d inner its, %d outer, %.1f ms" % (mode, log.iterations, log.outer_iterations,
+                                                             log.elapsed_ms))
     assert log.stop_reason == spk.STOP_CONVERGED and rel(x, xo) <= 1e-10
 
 

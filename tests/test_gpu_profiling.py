@@ -1,7 +1,10 @@
 """Per-launch timing of the dominant SpMV (spk_plan_set_profiling): with
 stride k the launches 0, k, 2k, ... that did work are timed, per solve for
 solve plans and across calls for SpMV plans; the timed launches' mean
-duration does not depend on the stride beyond timing noise."""
+duration does not depend on the stride beyond timing noise.  A CG solve of
+K iterations has K working SpMV launches in three-launch iterations and
+K + 1 working steps in the fused loop (the step after the last iteration
+learns of the stop before its product)."""
 import math
 
 import numpy as np
@@ -27,12 +30,15 @@ def ctx(spk):
     spk.spk_finalize(c)
 
 
+@pytest.mark.parametrize("fused", ["1", "0"])
 @pytest.mark.parametrize("every", [1, 3, 4])
-def test_solve_times_every_kth_working_launch(spk, ctx, every):
+def test_solve_times_every_kth_working_launch(spk, ctx, monkeypatch, every, fused):
+    monkeypatch.setenv("SPK_CG_FUSED", fused)
     A = inputs.stencil7(40, 2)
     cfg = spk.spk_solver_cfg_default()
     cfg.reduction_factor = 1e-10
     pl = spk.spk_plan_solve(ctx, dev_csr(spk, A), cfg)
+    assert spk.spk_plan_get_info(pl)["fused_loop"] == int(fused)
     spk.spk_plan_set_profiling(pl, every)
     iters = []
     for _ in range(2):
@@ -41,7 +47,8 @@ def test_solve_times_every_kth_working_launch(spk, ctx, every):
     ms, count = spk.spk_plan_kernel_stats(pl)
     spk.spk_free(pl)
     assert iters[0] == iters[1] > 0
-    assert count == 2 * math.ceil(iters[0] / every)
+    working = iters[0] + (1 if fused == "1" else 0)
+    assert count == 2 * math.ceil(working / every)
     assert ms > 0.0
 
 
