@@ -352,6 +352,22 @@ def main():
         out["copy_calib"] = {"bytes": 2 * nbytes, "ms": best, "GBs": cgbs}
         if achieved:
             out["roofline"]["frac_vs_copy"] = achieved / cgbs
+        del src, dst
+    if args.pattern in ("randsym", "powerlaw") and args.precision == "fp64":
+        # The gathers of this matrix's SpMV without its arithmetic: dst[e] =
+        # v[col[e]] over the column array in storage order (4 bytes of index
+        # streamed and 8 written per gather, as the SpMV streams 4 of index and
+        # 8 of value).  Its time is the ceiling the random-gather SpMV is
+        # compared with, beside the HBM peak.
+        src = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty(nnz, dtype=torch.float64, device=dev)
+        best = min(spk.spk_gather_probe(ctx, src, ci, dst) for _ in range(5))
+        out["gather_calib"] = {"gathers": nnz, "ms": best, "gathers_per_s": nnz / (best * 1e-3),
+                               "note": "dst[e] = v[col[e]] over this matrix's column array (library gather "
+                                       "kernel, best of 5)"}
+        if avg_ms:
+            out["roofline"]["frac_vs_gather"] = best / avg_ms
+        del src, dst
 
     x_orc = None
     if not args.no_cpu_baseline:

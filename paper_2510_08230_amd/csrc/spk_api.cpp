@@ -32,9 +32,11 @@ struct TuneKey {
     int codes;   // the matrix has column codes
     int staged;  // values and columns are 16-byte aligned (the LDS tiles may run)
     int64_t period;   // the pattern's period in rows (0 = none known)
+    int long_rows;    // rows longer than kLongRow (the kernels with the long-row pass run)
     bool operator<(const TuneKey &o) const {
-        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged, period) <
-               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged, o.period);
+        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged, period, long_rows) <
+               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged, o.period,
+                        o.long_rows);
     }
 };
 
@@ -253,7 +255,7 @@ SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
 spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int use, SolveState *st,
                     double *partials, TuneResult *out, const void *fcg = nullptr) {
     const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use, A.codes != nullptr, stream_ok(A),
-                      A.period};
+                      A.period, A.max_row > spk::kLongRow};
     auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
         *out = hit->second;
@@ -447,6 +449,10 @@ spk_status build_codes(spk_plan pl) {
     CsrDev &A = pl->A;
     const char *env = std::getenv("SPK_COL_CODES");
     if ((env && std::strcmp(env, "0") == 0) || A.nnz == 0 || A.n_rows == 0 || !stream_ok(A)) return SPK_OK;
+    // a row longer than kLongRow entries holds more than 256 distinct
+    // offsets unless it repeats a column; such matrices keep their indices,
+    // so the coded kernels never need the long-row pass
+    if (A.max_row > spk::kLongRow) return SPK_OK;
     if (!(env && std::strcmp(env, "1") == 0) && A.nnz < kCodeMinNnz) return SPK_OK;
     void *tab = nullptr, *buf = nullptr;
     const size_t bytes = spk::code_buffer_bytes(A.n_rows, A.nnz);
@@ -1663,7 +1669,7 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
     // context's cache, never added to it), else the heuristic one
     const TuneKey key{pl.A.n_rows, pl.A.n_cols, pl.A.nnz, pl.A.ptr_t, pl.A.idx_t, pl.A.val_t,
                       pl.fused ? TUNE_FCG : TUNE_CG, false,
-                      stream_ok(pl.A), 0};
+                      stream_ok(pl.A), 0, pl.A.max_row > spk::kLongRow};
     if (!forced_tune(ctx, pl.A, &pl.tune)) {
         auto hit = ctx->tune_cache.find(key);
         pl.tune = hit != ctx->tune_cache.end() && pl.A.nnz >= 100000 ? hit->second.tune : heuristic_tune(ctx, pl.A);

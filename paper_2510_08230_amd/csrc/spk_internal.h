@@ -85,7 +85,7 @@ struct PersistSolve {
     int64_t max_iters, max_outer;
     double *hist;
     int64_t hist_cap;
-    int remap, nt, true_residual, long_row;
+    int remap, nt, true_residual;
 };
 
 // Restarted GMRES: the small per-solve arrays (device memory, one per plan).

@@ -820,12 +820,32 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src
 }
 
 // Random-gather probe: dst[i] = src[idx[i]] (indices and results streamed
-// coalesced, the source read at random 8-byte positions).
+// coalesced, the source read at random 8-byte positions).  Each thread keeps
+// kGatherDepth gathers in flight (a row of an irregular SpMV keeps its row
+// length), so the probe measures the memory system's rate, not one load's
+// latency.
+constexpr int kGatherDepth = 8;
+
 __global__ __launch_bounds__(kBlock) void k_gather(const double *__restrict__ src, const int32_t *__restrict__ idx,
                                                    double *__restrict__ dst, int64_t m) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < m; i += stride)
-        dst[i] = src[idx[i]];
+    const int64_t span = static_cast<int64_t>(kBlock) * kGatherDepth;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * span;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * span + threadIdx.x; base < m; base += stride) {
+        int32_t j[kGatherDepth];
+        double v[kGatherDepth];
+#pragma unroll
+        for (int u = 0; u < kGatherDepth; ++u) {
+            const int64_t e = base + static_cast<int64_t>(u) * kBlock;
+            j[u] = e < m ? idx[e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherDepth; ++u) v[u] = j[u] >= 0 ? src[j[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kGatherDepth; ++u) {
+            const int64_t e = base + static_cast<int64_t>(u) * kBlock;
+            if (e < m) dst[e] = v[u];
+        }
+    }
 }
 
 int grid_for(int64_t n, int per_thread, int cap) {
@@ -1105,6 +1125,11 @@ int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t) {
         lo = blocks < lo ? blocks : lo;
     };
     const bool i64 = A.idx_t != 0;
+    const bool lr = A.max_row > kLongRow;   // plain-index kernels with the long-row pass
+    auto q2 = [&](auto without, auto with) {
+        if (lr) q(with);
+        else q(without);
+    };
     if (t.kind == 0 && t.codes && A.codes) {   // the coded instances the launch will use
         const bool pack = t.pack && A.rowpack;
         if (A.val_t == 0) {
@@ -1125,11 +1150,15 @@ int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t) {
     } else if (A.val_t == 0) {
         if (t.kind == 0) {
             if (i64) {
-                q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>>);
-                q(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPlain<double>>);
+                q2(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>>,
+                   k_spmv_stream<double, int64_t, int64_t, double, double, EpiPq<double>, true>);
+                q2(k_spmv_stream<double, int64_t, int64_t, double, double, EpiPlain<double>>,
+                   k_spmv_stream<double, int64_t, int64_t, double, double, EpiPlain<double>, true>);
             } else {
-                q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq<double>>);
-                q(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPlain<double>>);
+                q2(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq<double>>,
+                   k_spmv_stream<double, int64_t, int32_t, double, double, EpiPq<double>, true>);
+                q2(k_spmv_stream<double, int64_t, int32_t, double, double, EpiPlain<double>>,
+                   k_spmv_stream<double, int64_t, int32_t, double, double, EpiPlain<double>, true>);
             }
         } else {
             if (i64) {
@@ -1142,8 +1171,10 @@ int spmv_blocks_per_cu(const CsrDev &A, const SpmvTune &t) {
         }
     } else {
         if (t.kind == 0) {
-            q(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPlain<float>>);
-            q(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPq<float>>);
+            q2(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPlain<float>>,
+               k_spmv_stream<float, int64_t, int32_t, float, float, EpiPlain<float>, true>);
+            q2(k_spmv_stream<float, int64_t, int32_t, float, float, EpiPq<float>>,
+               k_spmv_stream<float, int64_t, int32_t, float, float, EpiPq<float>, true>);
         } else {
             q(k_spmv_vector<float, int64_t, int32_t, float, float, EpiPlain<float>>);
             q(k_spmv_vector<float, int64_t, int32_t, float, float, EpiPq<float>>);

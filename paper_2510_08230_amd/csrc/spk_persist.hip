@@ -92,7 +92,7 @@ struct EpiResid {
     }
 };
 
-template <typename V, typename V64, typename P, typename I, typename T>
+template <typename V, typename V64, typename P, typename I, typename T, bool LR>
 __global__ __launch_bounds__(kBlock) void k_persist(PersistSolve a) {
     __shared__ u32x4 lv[Chunks<double>::LDS];   // staging for the widest value type
     __shared__ u32x4 lc[Chunks<I>::LDS];
@@ -117,11 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistSolve a) {
         using W = std::remove_const_t<std::remove_pointer_t<decltype(va)>>;
         using C = decltype(ctag);
         if constexpr (std::is_same_v<I, Code8>)
-            spmv_tiles_lds<W, P, I, C>(n, a.nnz, rp, ci, va, gx, a.remap, a.nt, 1, epi, lv, lc, ColCoded{dict},
-                                       a.long_row);
+            spmv_tiles_lds<W, P, I, C, LR>(n, a.nnz, rp, ci, va, gx, a.remap, a.nt, 1, epi, lv, lc, ColCoded{dict});
         else
-            spmv_tiles_lds<W, P, I, C>(n, a.nnz, rp, ci, va, gx, a.remap, a.nt, 1, epi, lv, lc, ColPlain{},
-                                       a.long_row);
+            spmv_tiles_lds<W, P, I, C, LR>(n, a.nnz, rp, ci, va, gx, a.remap, a.nt, 1, epi, lv, lc, ColPlain{});
         epi.finish();
     };
     double *part_init = a.partials + static_cast<size_t>(SITE_INIT) * kSiteWidth * kMaxGrid;
@@ -281,36 +279,39 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistSolve a) {
     }
 }
 
-template <typename V, typename V64, typename P, typename I, typename T>
+template <typename V, typename V64, typename P, typename I, typename T, bool LR>
 const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&k_persist<V, V64, P, I, T>);
+    return reinterpret_cast<const void *>(&k_persist<V, V64, P, I, T, LR>);
 }
 
 // The kernel for the solve's types (nullptr: no persistent kernel for them).
 // outer: the refinement's matrix of a mixed solve (same index arrays as A),
-// nullptr for an FP64 solve on A.
-template <typename P, typename I>
+// nullptr for an FP64 solve on A.  LR: with the long-row pass.
+template <typename P, typename I, bool LR>
 const void *kernel_values(const CsrDev &A, const CsrDev *outer) {
-    if (!outer) return A.val_t == 0 ? kernel_ptr<double, double, P, I, double>() : nullptr;
-    if (A.val_t == 1 && outer->val_t == 0) return kernel_ptr<float, double, P, I, float>();
-    if (A.val_t == 1 && outer->val_t == 1) return kernel_ptr<float, float, P, I, float>();
-    if (A.val_t == 3 && outer->val_t == 0) return kernel_ptr<bf16s, double, P, I, float>();
-    if (A.val_t == 2 && outer->val_t == 0) return kernel_ptr<_Float16, double, P, I, float>();
+    if (!outer) return A.val_t == 0 ? kernel_ptr<double, double, P, I, double, LR>() : nullptr;
+    if (A.val_t == 1 && outer->val_t == 0) return kernel_ptr<float, double, P, I, float, LR>();
+    if (A.val_t == 1 && outer->val_t == 1) return kernel_ptr<float, float, P, I, float, LR>();
+    if (A.val_t == 3 && outer->val_t == 0) return kernel_ptr<bf16s, double, P, I, float, LR>();
+    if (A.val_t == 2 && outer->val_t == 0) return kernel_ptr<_Float16, double, P, I, float, LR>();
     return nullptr;
 }
 
 // Index combinations with a persistent kernel: int32 columns with int32 or
-// int64 row pointers, and one-byte column codes with packed, int32 or int64
-// row pointers.
+// int64 row pointers (with the long-row pass when the matrix has rows longer
+// than kLongRow), and one-byte column codes with packed, int32 or int64 row
+// pointers (coded matrices have no such rows).
 const void *kernel_for(const CsrDev &A, const CsrDev *outer) {
     if (A.codes) {
-        if (A.rowpack) return kernel_values<RowPack, Code8>(A, outer);
-        if (A.ptr_t == 0) return kernel_values<int32_t, Code8>(A, outer);
-        return kernel_values<int64_t, Code8>(A, outer);
+        if (A.rowpack) return kernel_values<RowPack, Code8, false>(A, outer);
+        if (A.ptr_t == 0) return kernel_values<int32_t, Code8, false>(A, outer);
+        return kernel_values<int64_t, Code8, false>(A, outer);
     }
     if (A.idx_t != 0) return nullptr;
-    if (A.ptr_t == 0) return kernel_values<int32_t, int32_t>(A, outer);
-    return kernel_values<int64_t, int32_t>(A, outer);
+    const bool lr = A.max_row > kLongRow;
+    if (A.ptr_t == 0)
+        return lr ? kernel_values<int32_t, int32_t, true>(A, outer) : kernel_values<int32_t, int32_t, false>(A, outer);
+    return lr ? kernel_values<int64_t, int32_t, true>(A, outer) : kernel_values<int64_t, int32_t, false>(A, outer);
 }
 
 }  // namespace
@@ -332,7 +333,6 @@ hipError_t launch_persistent(const CsrDev &A, const CsrDev *outer, PersistSolve 
     a.ci = A.codes ? A.codes : A.ci;
     a.va = A.va;
     a.va64 = outer ? outer->va : A.va;
-    a.long_row = A.max_row > kLongRow ? kLongRow : 0;
     void *args[] = {&a};
     return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kBlock), args, 0, s);
 }

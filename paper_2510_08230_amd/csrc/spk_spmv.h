@@ -33,48 +33,68 @@ struct Vec16 {
     typedef T type __attribute__((ext_vector_type(W)));
 };
 
-// Rows of the tile at r0 longer than `lim` entries (this thread's row when
-// lng; its entries [a, b)): summed one at a time by the whole workgroup --
-// each thread a strided share in storage order, then the wave sums and the
-// four wave totals in a fixed order -- and handed to epi.row by the row's own
-// thread.  Every thread of the workgroup calls this (it synchronises).
-// val(k) / cix(k): entry k's value and stored column (from LDS or global).
-template <typename C, class Gx, class D, class Epi, class Val, class Cix>
-__device__ __forceinline__ void long_rows(bool lng, int64_t a, int64_t b, int64_t r0, const Gx &gx, const D &col,
-                                          Epi &epi, const Val &val, const Cix &cix) {
-    __shared__ int s_next;
-    __shared__ int64_t s_ab[2];
+// Entry range [a, b) of one row (long-row pass: the bounds are loaded again
+// rather than kept live through the per-lane row loop).
+template <typename P>
+__device__ __forceinline__ void row_range(const P *__restrict__ rp, int64_t n, int64_t row, int64_t &a, int64_t &b) {
+    a = static_cast<int64_t>(rp[row]);
+    b = static_cast<int64_t>(rp[row + 1]);
+}
+
+template <>
+__device__ __forceinline__ void row_range<RowPack>(const RowPack *__restrict__ rp, int64_t n, int64_t row, int64_t &a,
+                                                   int64_t &b) {
+    const int64_t *tb = reinterpret_cast<const int64_t *>(rp);
+    const uint16_t *ro = reinterpret_cast<const uint16_t *>(tb + (n + kTileRows - 1) / kTileRows + 1);
+    const int64_t tile = row / kTileRows;
+    const int64_t r1 = min((tile + 1) * static_cast<int64_t>(kTileRows), n);
+    a = tb[tile] + ro[row];
+    b = row + 1 < r1 ? tb[tile] + ro[row + 1] : tb[tile + 1];
+}
+
+// The rows of the tile at r0 whose flag lng is set (rows longer than the
+// long-row limit), summed one at a time by the whole workgroup in ascending
+// row order -- each thread a strided share in storage order, then the wave
+// sums and the four wave totals in a fixed order -- and handed to epi.row by
+// the row's own thread.  Every thread of the workgroup calls this (it
+// synchronises); the flags go through LDS as one ballot per wave, so nothing
+// of the per-lane row loop stays live for it.  val(k) / cix(k): entry k's
+// value and stored column (read from global memory, also for a tile staged
+// in LDS: one call site keeps the kernel's register count down).
+template <typename C, typename P, class Gx, class D, class Epi, class Val, class Cix>
+__device__ __forceinline__ void long_rows(bool lng, const P *__restrict__ rp, int64_t n, int64_t r0, const Gx &gx,
+                                          const D &col, Epi &epi, const Val &val, const Cix &cix) {
+    __shared__ unsigned long long s_mask[kBlock / 64];
     __shared__ C s_red[kBlock / 64];
-    if (!__syncthreads_or(lng)) return;
-    int done = -1;
-    while (true) {
-        if (threadIdx.x == 0) s_next = kTileRows;
-        __syncthreads();
-        if (lng && static_cast<int>(threadIdx.x) > done) atomicMin(&s_next, static_cast<int>(threadIdx.x));
-        __syncthreads();
-        const int i = s_next;
-        if (i >= kTileRows) break;   // the same in every thread
-        if (static_cast<int>(threadIdx.x) == i) {
-            s_ab[0] = a;
-            s_ab[1] = b;
-        }
-        __syncthreads();
-        const int64_t ra = s_ab[0], rb = s_ab[1], row = r0 + i;
-        C acc = 0;
-        for (int64_t k = ra + threadIdx.x; k < rb; k += kBlock)
-            acc = fma(static_cast<C>(widen(val(k))), static_cast<C>(gx(col(cix(k), row))), acc);
-        acc = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (static_cast<int>(threadIdx.x) == i) {
-            C t = s_red[0];
+    const unsigned long long m = __ballot(lng);
+    if ((threadIdx.x & 63) == 0) s_mask[threadIdx.x >> 6] = m;
+    __syncthreads();
+#pragma unroll 1
+    for (int w = 0; w < kBlock / 64; ++w) {
+        unsigned long long left = s_mask[w];
+        while (left != 0) {   // the same in every thread
+            const int i = w * 64 + __builtin_ctzll(left);
+            left &= left - 1;
+            const int64_t row = r0 + i;
+            int64_t ra, rb;
+            row_range(rp, n, row, ra, rb);
+            C acc = 0;
+#pragma unroll 1
+            for (int64_t k = ra + threadIdx.x; k < rb; k += kBlock)
+                acc = fma(static_cast<C>(widen(val(k))), static_cast<C>(gx(col(cix(k), row))), acc);
+            acc = wave_sum(acc);
+            if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+            __syncthreads();
+            if (static_cast<int>(threadIdx.x) == i) {
+                C t = s_red[0];
 #pragma unroll
-            for (int w = 1; w < kBlock / 64; ++w) t += s_red[w];
-            epi.row(row, t);
+                for (int v = 1; v < kBlock / 64; ++v) t += s_red[v];
+                epi.row(row, t);
+            }
+            __syncthreads();   // s_red is reused by the next long row
         }
-        done = i;
-        __syncthreads();   // s_ab and s_red are reused by the next long row
     }
+    __syncthreads();           // s_mask is rewritten by the next tile
 }
 
 // LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
@@ -83,14 +103,16 @@ __device__ __forceinline__ void long_rows(bool lng, int64_t a, int64_t b, int64_
 // The tile loop of the LDS-staged SpMV, shared by the per-launch kernel and the
 // persistent CG kernel: calls epi.row(row, sum) for every row of the tiles
 // this workgroup visits.  lv / lc: the workgroup's LDS staging buffers.
-// long_row > 0 (the matrix has rows longer than that): rows of more than
-// long_row entries are summed by the whole workgroup (long_rows), so a hub
-// row does not serialise its tile on one lane.
-template <typename V, typename P, typename I, typename C, class Gx, class Epi, class D = ColPlain>
+// LR (the matrix has rows longer than kLongRow entries): those rows are
+// summed by the whole workgroup (long_rows), so a hub row does not serialise
+// its tile on one lane.  A compile-time switch: the pass costs registers, and
+// with it in every instance the kernels without hub rows lost a workgroup per
+// CU.
+template <typename V, typename P, typename I, typename C, bool LR, class Gx, class Epi, class D = ColPlain>
 __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
                                                int remap, int nt, int pf, Epi &epi, u32x4 *lv, u32x4 *lc,
-                                               const D &col = D{}, int long_row = 0) {
+                                               const D &col = D{}) {
     const V *sv = reinterpret_cast<const V *>(lv);
     const I *sc = reinterpret_cast<const I *>(lc);
     const int64_t T = (n + kTileRows - 1) / kTileRows;
@@ -108,7 +130,7 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
         const int64_t row = cur.r0 + threadIdx.x;
         const int64_t s = static_cast<int64_t>(cur.s), e = static_cast<int64_t>(cur.e);
         const int64_t a = static_cast<int64_t>(cur.a), b = static_cast<int64_t>(cur.b);
-        const bool lng = long_row > 0 && row < r1 && b - a > long_row;
+        const bool lng = LR && row < r1 && b - a > kLongRow;
         if (e - s <= kStreamCap) {
             dma_chunks<V>(va, s, e, nnz, lv, nt);
             dma_chunks<I>(ci, s, e, nnz, lc, nt);
@@ -118,17 +140,14 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
             const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
             const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
             if (row < r1 && !lng) epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row));
-            if (long_row > 0)
-                long_rows<C>(lng, a, b, cur.r0, gx, col, epi, [&](int64_t k) { return sv[k - s0v]; },
-                             [&](int64_t k) { return sc[k - s0c]; });
             __syncthreads();                 // LDS free for the next tile
         } else {
             if (more && pf) nxt.load(rp, n, after.tile());
             if (row < r1 && !lng) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt, col, row));
-            if (long_row > 0)
-                long_rows<C>(lng, a, b, cur.r0, gx, col, epi, [&](int64_t k) { return ldv(va + k, nt); },
-                             [&](int64_t k) { return ci[k]; });
         }
+        if constexpr (LR)
+            long_rows<C>(lng, rp, n, cur.r0, gx, col, epi, [&](int64_t k) { return ldv(va + k, nt); },
+                         [&](int64_t k) { return ci[k]; });
         if (!more) break;
         if (!pf) nxt.load(rp, n, after.tile());
         it = after;
@@ -151,11 +170,11 @@ __device__ __forceinline__ auto gather_of(const Epi &epi, const X *x) {
     else return PlainGather<X, C>{x};
 }
 
-template <typename V, typename P, typename I, typename X, typename C, class Epi>
+template <typename V, typename P, typename I, typename X, typename C, class Epi, bool LR = false>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const V *__restrict__ va,
                                                         const X *__restrict__ x, int remap, int nt, int pf,
-                                                        int long_row, Epi epi_in) {
+                                                        Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
     __shared__ u32x4 lv[Chunks<V>::LDS];
@@ -166,11 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, 
         const int64_t *g = reinterpret_cast<const int64_t *>(ci) - kCodeDict;
         for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = g[i];
         __syncthreads();
-        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
-                                   ColCoded{dict}, long_row);
+        spmv_tiles_lds<V, P, I, C, LR>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
+                                       ColCoded{dict});
     } else {
-        spmv_tiles_lds<V, P, I, C>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
-                                   ColPlain{}, long_row);
+        spmv_tiles_lds<V, P, I, C, LR>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
+                                       ColPlain{});
     }
     epi.finish();
 }
@@ -238,21 +257,27 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
         // 16-byte chunks; arrays without that alignment take one lane per
         // row, which sums each row in the same order
         auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+        // column codes exist only for matrices without rows longer than
+        // kLongRow (the plan's rule), so only the plain-index kernel has a
+        // long-row instance
         const bool coded = t.kind == 0 && t.codes && A.codes;
-        const int lr = A.max_row > kLongRow ? kLongRow : 0;
+        const bool lr = A.max_row > kLongRow;
         if (t.kind == 0 && !(al16(A.va) && (coded || al16(A.ci)))) {
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x, 0,
                                t.xcd_remap, t.nt, epi);
-        } else if (t.kind == 0 && t.codes && A.codes && t.pack && A.rowpack) {
+        } else if (coded && t.pack && A.rowpack) {
             hipLaunchKernelGGL((k_spmv_stream<V, RowPack, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz,
                                static_cast<const RowPack *>(A.rowpack), static_cast<const Code8 *>(A.codes), va, x,
-                               t.xcd_remap, t.nt, t.pf, lr, epi);
-        } else if (t.kind == 0 && t.codes && A.codes) {
+                               t.xcd_remap, t.nt, t.pf, epi);
+        } else if (coded) {
             hipLaunchKernelGGL((k_spmv_stream<V, P, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp,
-                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, lr, epi);
+                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, epi);
+        } else if (t.kind == 0 && lr) {
+            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi, true>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci,
+                               va, x, t.xcd_remap, t.nt, t.pf, epi);
         } else if (t.kind == 0) {
             hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
-                               t.xcd_remap, t.nt, t.pf, lr, epi);
+                               t.xcd_remap, t.nt, t.pf, epi);
         } else {
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
                                t.lanes_log2, t.xcd_remap, t.nt, epi);

@@ -21,7 +21,8 @@ import os
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_spmv.h", "csrc/spk_device.h", "csrc/spk_internal.h"]
+KERNEL_SOURCES = ["csrc/spk_kernels.hip", "csrc/spk_spmv.h", "csrc/spk_device.h", "csrc/spk_internal.h",
+                  "csrc/spk_fcg.h"]
 
 
 def kernel_digest() -> str:

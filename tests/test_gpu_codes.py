@@ -124,6 +124,29 @@ def test_period_tile_order(spk, ctx, monkeypatch, N):
     assert np.array_equal(y0, y1)
 
 
+def test_pencil_tile_order(spk, ctx, monkeypatch):
+    """A period of 150,000 rows is cut into two bands per XCD (pencils of
+    about 8192 rows walked through every period); every tile is still
+    visited once, so the product equals the plain order's bit for bit, and
+    the ragged last period is covered."""
+    n, D = 700_001, 150_000
+    offs = np.array([-D, -1, 0, 1, D], np.int64)
+    C = np.arange(n, dtype=np.int64)[:, None] + offs[None, :]
+    keep = (C >= 0) & (C < n)
+    rp = np.concatenate([[0], np.cumsum(keep.sum(axis=1))]).astype(np.int64)
+    col = C[keep].astype(np.int32)
+    val = np.random.default_rng(11).uniform(-1.0, 1.0, col.size)
+    A = inputs.CSR(n, n, rp, col, val)
+    M = dev_csr(spk, A, ptr="i32", idx="i32")
+    x = to_dev(inputs.vec(n, 7, 5))
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,remap=period")
+    y1, i1 = spmv(spk, ctx, M, x, n)
+    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,remap=1,codes=0")
+    y0, i0 = spmv(spk, ctx, M, x, n)
+    assert i1["xcd_remap"] == -D and i1["col_codes"] == 3 and i0["xcd_remap"] == 1
+    assert np.array_equal(y0, y1)
+
+
 @pytest.mark.parametrize("k,coded", [(256, 3), (257, 0)])
 def test_codes_taken_up_to_256_offsets(spk, ctx, monkeypatch, k, coded):
     # offsets -128 .. k-129: rows hold up to k entries, so tiles exceed the LDS
@@ -139,10 +162,11 @@ def test_codes_taken_up_to_256_offsets(spk, ctx, monkeypatch, k, coded):
     assert np.array_equal(y, y0)
 
 
-def test_long_tile_keeps_plain_row_pointers(spk, ctx, monkeypatch):
+def test_long_duplicate_row_keeps_plain_indices(spk, ctx, monkeypatch):
     # row 5 holds 70,000 duplicate entries on the diagonal (3 distinct offsets
-    # overall), so later rows of its tile start past 65535 entries in: codes
-    # but no packed row pointers
+    # overall): a row longer than 256 entries, so the plan keeps the plain
+    # indices (coded kernels carry no long-row pass) and the product sums that
+    # row with the whole workgroup; within the oracle's summation bound
     A = banded(600, [-1, 0, 1], 7, extra=None)
     rows = [list(A.col[A.row_ptr[i]:A.row_ptr[i + 1]]) for i in range(A.n_rows)]
     rows[5] = rows[5] + [5] * 70000
@@ -154,10 +178,10 @@ def test_long_tile_keeps_plain_row_pointers(spk, ctx, monkeypatch):
     M = dev_csr(spk, A)
     xh = inputs.vec(A.n_cols, 9, 5)
     y, info = spmv(spk, ctx, M, to_dev(xh), A.n_rows)
-    assert info["col_codes"] == 1
-    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,codes=0")
-    y0, _ = spmv(spk, ctx, M, to_dev(xh), A.n_rows)
-    assert np.array_equal(y, y0)
+    assert info["col_codes"] == 0
+    m = np.maximum(np.diff(A.row_ptr), 1)
+    bound = 2 * gamma(m, U64) * oracle.spmv_abs(A, xh)
+    assert np.all(np.abs(y - oracle.spmv(A, xh)) <= bound)
     m = np.maximum(np.diff(A.row_ptr), 1)
     assert np.all(np.abs(y - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
 
