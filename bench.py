@@ -805,6 +805,11 @@ def serving_block(args, ctx, with_oracle=True):
     def pct(a, q):
         return float(np.percentile(a, q))
 
+    # algorithmic bytes the tick SpMV moves for one pass of all requests
+    nnzv = np.array([A.nnz for A in hosts], np.int64)
+    tick_bytes = int(np.sum(sat["iters"] * (nnzv * 8 + (nvec + 1) * 4 + 8 * nvec)
+                            + (sat["outer"] + 1) * (nnzv * 12 + (nvec + 1) * 4 + 28 * nvec)))
+
     out = {
         "workload": "serve_randsym_%d_loguniform_1e3_1e6" % len(mats),
         "data": "synthetic (seeded randsym instances: 3 uniform partners per row, symmetrised, uniform[-1,1) "
@@ -823,6 +828,11 @@ def serving_block(args, ctx, with_oracle=True):
                     "server_stats": poi["stats"]},
         "iterations": {"inner_total": int(poi["iters"].sum()), "outer_total": int(poi["outer"].sum()),
                        "inner_max": int(poi["iters"].max())},
+        "tick_spmv": {"kernel": "k_b_spmv (batched tile SpMV of a tick: FP32 inner q = A32 p, FP64 refinement "
+                                "residual)",
+                      "algorithmic_bytes_per_pass": tick_bytes,
+                      "note": "sum over requests of inner iterations x (nnz (4+4) + (n+1) 4 + 8n) plus residual "
+                              "evaluations x (nnz (8+4) + (n+1) 4 + 28n); one pass of all requests"},
         "fp64_one_at_a_time": {"seconds": base_time, "solves_per_s": len(mats) / base_time,
                                "updates_per_s": float(np.sum(nvec * base_iters)) / base_time,
                                "iterations_total": int(base_iters.sum()),
@@ -861,8 +871,19 @@ def serve(args):
 
     from paper_2510_08230_amd import spk
 
-    ctx = spk.spk_init(0, torch.cuda.current_stream(torch.device("cuda:0")).cuda_stream)
+    dev = torch.device("cuda:0")
+    ctx = spk.spk_init(0, torch.cuda.current_stream(dev).cuda_stream)
     blk = serving_block(args, ctx, with_oracle=not args.no_cpu_baseline)
+    copy_calib = None
+    if not args.no_copy_calib:
+        # the plain copy kernel over 1 GiB each way (also the counter scale of
+        # FETCH_SIZE / WRITE_SIZE runs of this mode)
+        nb = 1 << 30
+        src = torch.empty(nb // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        best = min(spk.spk_stream_copy(ctx, src, dst, nb) for _ in range(5))
+        copy_calib = {"bytes": 2 * nb, "ms": best, "GBs": 2 * nb / (best * 1e-3) / 1e9}
+        del src, dst
     spk.spk_finalize(ctx)
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
@@ -874,6 +895,8 @@ def serve(args):
         "latency_s": blk["poisson"]["latency_s"],
         "serving": blk,
     }
+    if copy_calib:
+        out["copy_calib"] = copy_calib
     print(json.dumps(out), flush=True)
 
 

@@ -28,7 +28,7 @@ using namespace dev;
 template <typename V, typename X, typename C>
 __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                           const V *__restrict__ va, int64_t nnz, const X *__restrict__ x, int64_t r0,
-                                          int64_t r1, u32x4 *lv, u32x4 *lc, bool &has_row, int stage) {
+                                          int64_t r1, u32x4 *lv, u32x4 *lc, bool &has_row, int stage, int nt) {
     const int64_t s = rp[r0], e = rp[r1];
     const int64_t row = r0 + threadIdx.x;
     int64_t a = 0, b = 0;
@@ -39,8 +39,8 @@ __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const 
     }
     C sum = 0;
     if (stage && e - s <= kStreamCap) {
-        dma_chunks<V>(va, s, e, nnz, lv, 0);
-        dma_chunks<int32_t>(ci, s, e, nnz, lc, 0);
+        dma_chunks<V>(va, s, e, nnz, lv, nt);
+        dma_chunks<int32_t>(ci, s, e, nnz, lc, nt);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (has_row)
@@ -50,7 +50,7 @@ __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const 
                                               PlainGather<X, C>{x});
         __syncthreads();
     } else if (has_row) {
-        sum = row_from_global<V, int32_t, C>(va, ci, a, b, PlainGather<X, C>{x}, 0);
+        sum = row_from_global<V, int32_t, C>(va, ci, a, b, PlainGather<X, C>{x}, nt);
     }
     return sum;
 }
@@ -58,9 +58,8 @@ __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const 
 __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
     __shared__ u32x4 lv[Chunks<double>::LDS];
     __shared__ u32x4 lc[Chunks<int32_t>::LDS];
-    const int T = B.counts[0];
-    for (int g = blockIdx.x; g < T; g += gridDim.x) {
-        const int2 te = B.tiles[g];
+    for (TileIter it(B.counts[0], B.remap); it.valid(); it.next()) {
+        const int2 te = B.tiles[it.tile()];
         const SlotDesc &D = B.desc[te.x];
         const SlotState &S = B.state[te.x];
         const int ph = S.phase;
@@ -69,7 +68,8 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
         const int64_t row = r0 + threadIdx.x;
         bool has = false;
         if (ph == PH_INNER && S.stop_in == STOP_RUNNING) {
-            const float s = tile_row_sum<float, float, float>(D.rp, D.ci, D.va32, D.nnz, D.p, r0, r1, lv, lc, has, D.stage);
+            const float s = tile_row_sum<float, float, float>(D.rp, D.ci, D.va32, D.nnz, D.p, r0, r1, lv, lc, has, D.stage,
+                                                              B.nt);
             double v[1] = {0.0};
             if (has) {
                 D.q[row] = s;
@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
             }
             block_reduce_store<1>(v, D.part + PART_PQ * D.tiles + te.y, D.tiles);
         } else if (ph == PH_OUTER) {
-            const double s = tile_row_sum<double, double, double>(D.rp, D.ci, D.va64, D.nnz, D.x, r0, r1, lv, lc, has, D.stage);
+            const double s = tile_row_sum<double, double, double>(D.rp, D.ci, D.va64, D.nnz, D.x, r0, r1, lv, lc, has,
+                                                                  D.stage, B.nt);
             double v[3] = {0.0, 0.0, 0.0};
             if (has) {
                 const double bi = D.b[row];
@@ -148,9 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_b_reduce_a(BatchDev B) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_update(BatchDev B) {
-    const int T = B.counts[0];
-    for (int g = blockIdx.x; g < T; g += gridDim.x) {
-        const int2 te = B.tiles[g];
+    for (TileIter it(B.counts[0], B.remap); it.valid(); it.next()) {
+        const int2 te = B.tiles[it.tile()];
         const SlotDesc &D = B.desc[te.x];
         const SlotState &S = B.state[te.x];
         const int ph = S.phase;
@@ -222,9 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_b_reduce_b(BatchDev B) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_pupdate(BatchDev B) {
-    const int T = B.counts[0];
-    for (int g = blockIdx.x; g < T; g += gridDim.x) {
-        const int2 te = B.tiles[g];
+    for (TileIter it(B.counts[0], B.remap); it.valid(); it.next()) {
+        const int2 te = B.tiles[it.tile()];
         const SlotDesc &D = B.desc[te.x];
         const SlotState &S = B.state[te.x];
         if (S.phase != PH_INNER || S.stop_in != STOP_RUNNING) continue;

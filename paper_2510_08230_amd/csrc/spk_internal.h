@@ -216,6 +216,8 @@ struct BatchDev {
     SlotState *state;
     SlotStatus *status;
     int tile_grid, slot_grid;
+    int remap;   // tile order of the tile launches (TileIter: 0 round-robin, 1 contiguous eighths per XCD)
+    int nt;      // 1: non-temporal loads of the matrix stream
 };
 
 }  // namespace spk

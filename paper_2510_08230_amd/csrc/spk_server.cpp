@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -449,8 +450,18 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
         return SPK_ERR_OUT_OF_MEMORY;
     }
     const int occ = spk::batch_tile_blocks_per_cu();
+    // tile launches: each XCD walks a contiguous eighth of the tick's tile
+    // list (which is ordered request by request), so a request's gathered
+    // vector is read into few L2s; the matrix streams non-temporally.
+    // SPK_BATCH_TILES="remap=R,nt=T" overrides either.
+    int remap = 1, nt = 1;
+    if (const char *e = std::getenv("SPK_BATCH_TILES")) {
+        if (const char *r = std::strstr(e, "remap=")) remap = std::atoi(r + 6);
+        if (const char *t = std::strstr(e, "nt=")) nt = std::atoi(t + 3);
+    }
     srv->B = spk::BatchDev{srv->d_counts, srv->d_tiles, srv->d_slots, srv->d_desc, srv->d_state, srv->d_status,
-                           std::min(srv->num_cu * occ, spk::kMaxGrid), std::min(srv->num_cu * 4, max_slots)};
+                           std::min(srv->num_cu * occ, spk::kMaxGrid), std::min(srv->num_cu * 4, max_slots),
+                           remap, nt};
     srv->stats.budget_bytes = static_cast<int64_t>(hbm_budget_bytes);
     srv->stats.max_slots = max_slots;
     srv->worker = std::thread(worker_main, srv);

@@ -3,6 +3,8 @@
   python -m paper_2510_08230_amd.profsum stats  KERNEL_STATS_CSV [--trace KERNEL_TRACE_CSV] --cmd "..."
   python -m paper_2510_08230_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B [--last N]
       [--logs FETCH_LOG WRITE_LOG] --cmd "..."
+  python -m paper_2510_08230_amd.profsum traffic-total FETCH_CSV WRITE_CSV --kernel SUBSTR --copy-bytes B
+      --algorithmic BYTES --cmd "..."
 
 ``stats`` renders the per-kernel duration table.  ``traffic`` reports the
 median FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dispatches of one
@@ -116,6 +118,31 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, last: 
             "traffic_bytes": kf * 1024.0 * scale_f + kw * 1024.0 * scale_w, "kernel_digest": kernel_digest()}
 
 
+def traffic_total(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, algorithmic: float) -> dict:
+    """Counter totals over every dispatch of a kernel whose work differs from
+    dispatch to dispatch (the serving tick's SpMV), copy-scaled, against the
+    algorithmic bytes of the whole run."""
+    f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    w = _per_kernel(write_csv, "WRITE_SIZE")
+
+    def one(d, sub):
+        got = [v for k, v in d.items() if sub in k]
+        if len(got) != 1:
+            raise SystemExit("%r matches %d kernels" % (sub, len(got)))
+        return got[0]
+
+    copy_f = statistics.median(one(f, "k_copy16"))
+    copy_w = statistics.median(one(w, "k_copy16"))
+    kf, kw = one(f, kernel), one(w, kernel)
+    rb = sum(kf) * 1024.0 * copy_bytes / (copy_f * 1024.0)
+    wb = sum(kw) * 1024.0 * copy_bytes / (copy_w * 1024.0)
+    return {"kernel": kernel, "dispatches": [len(kf), len(kw)], "fetch_kib_total": sum(kf),
+            "write_kib_total": sum(kw), "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+            "copy_bytes_each_way": copy_bytes, "read_bytes": rb, "write_bytes": wb, "traffic_bytes": rb + wb,
+            "algorithmic_bytes": algorithmic, "traffic_over_algorithmic": (rb + wb) / algorithmic,
+            "kernel_digest": kernel_digest()}
+
+
 TILING_KEYS = ("spmv_kernel", "lanes", "grid", "xcd_remap", "col_codes")
 
 
@@ -144,7 +171,19 @@ def main():
     t.add_argument("--cmd", required=True)
     t.add_argument("--logs", nargs=2, metavar=("FETCH_LOG", "WRITE_LOG"),
                    help="the two runs' benchmark output: their SpMV tiling (which must agree) is recorded")
+    u = sub.add_parser("traffic-total")
+    u.add_argument("fetch_csv")
+    u.add_argument("write_csv")
+    u.add_argument("--kernel", required=True)
+    u.add_argument("--copy-bytes", type=int, required=True)
+    u.add_argument("--algorithmic", type=float, required=True, help="algorithmic bytes of all dispatches")
+    u.add_argument("--cmd", required=True)
     a = ap.parse_args()
+    if a.what == "traffic-total":
+        d = traffic_total(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.algorithmic)
+        d["command"] = a.cmd
+        print(json.dumps(d, indent=1))
+        return
     if a.what == "stats":
         print(stats_md(a.csv, a.cmd), end="")
         if a.trace:
