@@ -117,6 +117,7 @@ struct spk_plan_s {
     int profiling = 0;                   // time every profiling-th dominant SpMV launch (0 = off)
     int64_t prof_seq = 0;                // dominant SpMV launches since the last collect
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<char> ev_ok;             // 0: the recorded launch found nothing to do (left out)
     size_t ev_used = 0;
     double prof_ms = 0.0;
     int64_t prof_count = 0;
@@ -265,21 +266,23 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
     const double mean = A.n_rows > 0 ? static_cast<double>(A.nnz) / A.n_rows : 0.0;
     if (stream_ok(A) && mean <= 64.0) {
         // tile-to-XCD maps (XCD-blocked runs of k tiles, contiguous eighths,
-        // round-robin) x matrix loads cached or non-temporal x the occupancy
-        // calculator's workgroups per CU or one more (its figure can be low).
-        // Ordered by prior preference: XCD-blocked tile orders (at equal time
-        // they move fewer bytes: stencil7 N=215, 1.20 GB per product against
-        // 1.36 GB round-robin), non-temporal matrix loads, one workgroup per
-        // CU above the calculator's figure (all measured best in the CG loop).
+        // round-robin) x matrix loads cached or non-temporal, at the
+        // occupancy calculator's workgroups per CU.  Ordered by prior
+        // preference: XCD-blocked tile orders (at equal time they move fewer
+        // bytes: stencil7 N=215, 1.20 GB per product against 1.36 GB
+        // round-robin), non-temporal matrix loads (both measured best in the
+        // CG loop).  One workgroup per CU above the calculator's figure is
+        // not a candidate: those workgroups queue behind the resident ones,
+        // and although back-to-back timings (which find the matrix partly in
+        // the Infinity Cache) sometimes favour it, in the CG loop it measured
+        // 16% slower at C2 (190 against 164 us) and 33% slower for the FP32
+        // inner product at C3 (129 against 97 us).
         // (the pattern-period slab order, remap = -D, is not a candidate: on
         // stencil7 it measured 13% slower at N = 215 and 6% at N = 1048 than
         // XCD-blocked runs of 64 tiles; SPK_SPMV_KERNEL=...,remap=period forces it)
         for (int remap : {64, 256, 1, 0})
             for (int nt : {1, 0}) {
-                const SpmvTune t = make_tune(ctx, A, 0, 0, remap, nt, 1, 0);
-                const SpmvTune t1 = make_tune(ctx, A, 0, 0, remap, nt, 1, t.bpc + 1);
-                if (t1.grid != t.grid) cands.push_back(t1);
-                cands.push_back(t);
+                cands.push_back(make_tune(ctx, A, 0, 0, remap, nt, 1, 0));
             }
     }
     for (int l2 = 0; l2 <= 6; ++l2) {
@@ -329,22 +332,17 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
     if (A.codes && best.tune.kind == 0) {
         // the best tile order and cache policy on one-byte column codes, with
         // packed row pointers (when built) and without, each at the coded
-        // kernel's own occupancy figure and one more workgroup per CU (in
-        // order of preference: fewer bytes first, a later candidate must be
-        // 3% faster); the plain indices must be 3% faster than the best coded
-        // candidate to be kept
+        // kernel's own occupancy figure (in order of preference: fewer bytes
+        // first, a later candidate must be 3% faster); the plain indices must
+        // be 3% faster than the best coded candidate to be kept
         const SpmvTune b = best.tune;
         TuneResult coded{b, 1e30};
         for (int pack : {1, 0}) {
             if (pack && !A.rowpack) continue;
-            const SpmvTune t = make_tune(ctx, A, 0, 0, b.xcd_remap, b.nt, b.pf, 0, 1, pack);
-            const SpmvTune t1 = make_tune(ctx, A, 0, 0, b.xcd_remap, b.nt, b.pf, t.bpc + 1, 1, pack);
-            for (int k = 0; k < (t1.grid != t.grid ? 2 : 1); ++k) {
-                const SpmvTune &c = k ? t1 : t;
-                double per = 0.0;
-                SPK_HIP(ctx, time_one(c, &per));
-                if (per < 0.97 * coded.ms) coded = TuneResult{c, per};
-            }
+            const SpmvTune c = make_tune(ctx, A, 0, 0, b.xcd_remap, b.nt, b.pf, 0, 1, pack);
+            double per = 0.0;
+            SPK_HIP(ctx, time_one(c, &per));
+            if (per < 0.97 * coded.ms) coded = TuneResult{c, per};
         }
         if (!(best.ms < 0.97 * coded.ms)) best = coded;
     }
@@ -506,8 +504,10 @@ spk_status build_codes(spk_plan pl) {
 }
 
 // ------------------------------------------------------------------ profiling events
-spk_status prof_begin(spk_plan pl, hipEvent_t *end_ev) {
+// idx (optional): the recorded launch's event index, -1 when not sampled.
+spk_status prof_begin(spk_plan pl, hipEvent_t *end_ev, int64_t *idx = nullptr) {
     *end_ev = nullptr;
+    if (idx) *idx = -1;
     if (!pl->profiling) return SPK_OK;
     if (pl->prof_seq++ % pl->profiling != 0) return SPK_OK;   // not sampled
     if (pl->ev_used == pl->ev_pool.size()) {
@@ -515,7 +515,10 @@ spk_status prof_begin(spk_plan pl, hipEvent_t *end_ev) {
         SPK_HIP(pl->ctx, hipEventCreate(&a));
         SPK_HIP(pl->ctx, hipEventCreate(&b));
         pl->ev_pool.emplace_back(a, b);
+        pl->ev_ok.push_back(1);
     }
+    if (idx) *idx = static_cast<int64_t>(pl->ev_used);
+    pl->ev_ok[pl->ev_used] = 1;
     auto &pr = pl->ev_pool[pl->ev_used++];
     SPK_HIP(pl->ctx, hipEventRecord(pr.first, pl->ctx->stream));
     *end_ev = pr.second;
@@ -528,13 +531,15 @@ spk_status prof_end(spk_plan pl, hipEvent_t end_ev) {
 }
 
 // Accumulate the recorded launches among the first `useful` launches (stream
-// already synchronised): launches 0, k, 2k, ... were recorded, k = profiling.
-// A solve restarts the count; SpMV plans count across calls (keep_seq).
+// already synchronised): launches 0, k, 2k, ... were recorded, k = profiling;
+// recorded launches marked as having found nothing to do are left out.  A
+// solve restarts the count; SpMV plans count across calls (keep_seq).
 spk_status prof_collect(spk_plan pl, int64_t useful, bool keep_seq = false) {
     const int64_t k = std::max(pl->profiling, 1);
-    const int64_t sampled = (std::max<int64_t>(useful, 0) + k - 1) / k;
+    const int64_t sampled = useful <= 0 ? 0 : 1 + (useful - 1) / k;
     const size_t n = std::min<size_t>(pl->ev_used, static_cast<size_t>(sampled));
     for (size_t i = 0; i < n; ++i) {
+        if (!pl->ev_ok[i]) continue;
         float ms = 0.f;
         SPK_HIP(pl->ctx, hipEventElapsedTime(&ms, pl->ev_pool[i].first, pl->ev_pool[i].second));
         pl->prof_ms += ms;
@@ -1314,7 +1319,13 @@ static spk_status run_gmres(spk_plan pl, const void *b, void *x, bool inner, int
                                       max_iters, s));
     // every cycle but the last completes at least one step
     const int64_t max_cycles = max_iters + 2;
+    // profiling: the recorded Arnoldi launches of the current cycle and their
+    // step; after the cycle, those past the steps it completed (a cycle that
+    // stopped or broke down early) are marked as having done nothing
+    std::vector<std::pair<int64_t, int>> recorded;
+    int64_t iter_before = 0;
     for (int64_t c = 0; c < max_cycles; ++c) {
+        recorded.clear();
         if (inner && c == 0)   // the inner solve starts from d = 0: r = b needs no product
             SPK_HIP(ctx, spk::launch_gm_cycle_start_zero(n, pl->vec_grid, b, pl->gm_V, st, pl->gm_st, pl->partials,
                                                          tau, m, inner, s));
@@ -1323,8 +1334,10 @@ static spk_status run_gmres(spk_plan pl, const void *b, void *x, bool inner, int
                                                     inner, s));
         for (int j = 0; j < m; ++j) {
             hipEvent_t e = nullptr;
-            spk_status ps = prof_begin(pl, &e);
+            int64_t idx = -1;
+            spk_status ps = prof_begin(pl, &e, &idx);
             if (ps != SPK_OK) return ps;
+            if (idx >= 0) recorded.emplace_back(idx, j);
             SPK_HIP(ctx, spk::launch_gm_step_spmv(A, tune, pl->gm_V, pl->gm_w, j, st, pl->gm_st, inner, s));
             if ((ps = prof_end(pl, e)) != SPK_OK) return ps;
             SPK_HIP(ctx, spk::launch_gm_step_rest(n, pl->vec_grid, pl->gm_V, pl->gm_w, j, m, st, pl->gm_st,
@@ -1333,6 +1346,10 @@ static spk_status run_gmres(spk_plan pl, const void *b, void *x, bool inner, int
         SPK_HIP(ctx, spk::launch_gm_cycle_end(n, pl->vec_grid, m, pl->gm_V, st, pl->gm_st, inner, s));
         spk_status ps = pull(ctx, h_st, st, sizeof(SolveState));
         if (ps != SPK_OK) return ps;
+        const int64_t done = h_st->iter - iter_before;   // steps this cycle completed
+        for (const auto &r : recorded)
+            if (r.second >= done) pl->ev_ok[static_cast<size_t>(r.first)] = 0;
+        iter_before = h_st->iter;
         if (h_st->stop != spk::STOP_RUNNING) return SPK_OK;
     }
     return fail(ctx, SPK_ERR_INTERNAL, "GMRES cycle cap passed without stop");
@@ -1444,8 +1461,12 @@ static spk_status execute_fp64(spk_plan pl, const double *b, double *x, spk_log 
     const SolveState &h = *pl->h_st;
     if (pl->profiling) {   // SpMV launches that did work (two per CGS iteration)
         const int64_t per = pl->algo == ALGO_CGS ? 2 : 1;
-        // the fused loop: steps 0 .. iterations did work, the next one found the stop
-        const int64_t useful = pl->fused ? h.iter + 1 : per * h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+        // the fused loop: steps 0 .. iterations did work, the next one found
+        // the stop; GMRES marks its idle Arnoldi launches itself (every
+        // recorded launch is considered)
+        const int64_t useful = pl->algo == ALGO_GMRES ? INT64_MAX
+                               : pl->fused            ? h.iter + 1
+                                                      : per * h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
         if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
     }
     L->iterations = h.iter;
@@ -1521,7 +1542,9 @@ static spk_status execute_mixed(spk_plan pl, const double *b, double *x, spk_log
         const SolveState &h = *pl->h_st_in;
         inner_total += h.iter;
         if (pl->profiling) {   // this inner solve's SpMV launches that did work
-            const int64_t useful = pl->fused ? h.iter + 1 : h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
+            const int64_t useful = pl->algo == ALGO_GMRES ? INT64_MAX
+                                   : pl->fused            ? h.iter + 1
+                                                          : h.iter + (h.stop == spk::STOP_BREAKDOWN ? 1 : 0);
             if ((s = prof_collect(pl, useful)) != SPK_OK) return s;
         }
         if ((h.stop == spk::STOP_BREAKDOWN || h.stop == spk::STOP_NON_FINITE) && h.iter == 0) {

@@ -52,6 +52,27 @@ def test_solve_times_every_kth_working_launch(spk, ctx, monkeypatch, every, fuse
     assert ms > 0.0
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_gmres_times_only_working_arnoldi_steps(spk, ctx, every):
+    """GMRES(10) over several restarts: its last cycle stops early and the
+    Arnoldi launches enqueued after the stop find nothing to do; only the
+    working ones are timed (ceil(steps / k) of them)."""
+    A = inputs.stencil7_ns(24, 3)
+    cfg = spk.spk_solver_cfg_default()
+    cfg.solver = spk.SOLVER_GMRES
+    cfg.krylov_dim = 10
+    cfg.reduction_factor = 1e-10
+    pl = spk.spk_plan_solve(ctx, dev_csr(spk, A), cfg)
+    spk.spk_plan_set_profiling(pl, every)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    log = spk.spk_execute_solve(pl, to_dev(inputs.vec(A.n_rows, 2, 2)), x)
+    ms, count = spk.spk_plan_kernel_stats(pl)
+    spk.spk_free(pl)
+    assert log.stop_reason == spk.STOP_CONVERGED and log.iterations > 10 and log.iterations % 10 != 0
+    assert count == math.ceil(log.iterations / every)
+    assert ms > 0.0
+
+
 def test_spmv_plan_counts_across_calls(spk, ctx):
     A = inputs.stencil7(30, 1)
     pl = spk.spk_plan_spmv(ctx, dev_csr(spk, A))
