@@ -170,9 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, Gmres
 //    with NV * K * B <= 256, B = sizeof(T) up to NV = 16, else 8 (the
 //    compiler holds FP32 values converted to FP64).
 // passB keeps every finished vector's pack until u_{j+1} is formed (its dot
-// products need it), so it runs at lower occupancy than passA.  Measured on
-// stencil7_ns N=215 (FP64, J = 17..32): passA 343 us, passB 515 us, where
-// the three passes of the undelayed scheme took 400 + 381 + 383 us.
+// products need it); it splits the basis over several lanes per pack to keep
+// that footprint small (see k_gm_passB).
 // Basis columns sit ld = gm_ld(n) elements apart (16-byte aligned); the last
 // pack of a vector is loaded element by element when n is not a multiple
 // of K.
@@ -310,83 +309,135 @@ __global__ void k_gm_coef(const SolveState *st, GmresState *gs, int j) {
 // a'_t = q_t . u_{j+1} (t <= j, rows 0..NV-1) and of ||u_{j+1}||^2 (row NV).
 // uj (slot j, read and written) and un (slot j + 1) do not overlap the
 // finished vectors read through V.
+//
+// The dot products need every finished vector's pack until u_{j+1} is known,
+// so one lane holding all J of them ran at one or two waves per SIMD.  Here S
+// lanes share a pack: lane group g of a wave (64 / S lanes) holds the vectors
+// t = u S + g only; the groups' partial combinations sum_t a_t q_t and
+// sum_t d_t q_t are added across the S lanes of a pack (the same sum in
+// every lane: the exchange adds in one fixed pattern), group 0 stores the
+// pack's q_j and u_{j+1}, and every lane accumulates the dot products of its
+// own vectors.
+// Lanes per pack in passB by value type and basis bucket, measured on
+// stencil7_ns N=215 (us per launch, one lane / two / four): FP64 NV = 8:
+// 106 / 110 / 143, NV = 16: - / 242 / 266, NV = 32: - / 347 / 267 (the
+// single-lane form that held all packs took 165, 248 and 308); FP32 (the
+// GMRES-IR basis) NV = 8: two lanes 61 (old form 107), NV = 16: 112 (140).
 template <typename T, int NV>
+constexpr int passb_split() {
+    return NV <= 8 ? (sizeof(T) == 4 ? 2 : 1) : (NV <= 16 ? 2 : 4);
+}
+
+template <typename T, int NV, int S>
+constexpr int passb_pack() {
+    int k = 16 / static_cast<int>(sizeof(T));
+    while (k > 1 && (NV / S) * k * static_cast<int>(sizeof(T)) > 128) k /= 2;
+    return k;
+}
+
+template <typename T, int NV, int S>
 __global__ __launch_bounds__(kBlock) void k_gm_passB(int64_t n, int64_t ld, const T *__restrict__ V,
                                                      T *__restrict__ uj, T *__restrict__ un,
                                                      const T *__restrict__ w, int j, const SolveState *st,
                                                      const GmresState *gs, double *part) {
     if (gm_idle(st, gs)) return;
-    constexpr bool stream = NV <= 8;
-    constexpr int K = stream ? 16 / static_cast<int>(sizeof(T)) : pack_len<T, NV, (NV >= 32 ? 8 : sizeof(T))>();
+    static_assert(NV % S == 0 && (S == 1 || S == 2 || S == 4), "lane split");
+    constexpr int NS = NV / S;    // vectors per lane
+    constexpr int LP = 64 / S;    // packs per wave and round
+    constexpr int K = passb_pack<T, NV, S>();
     __shared__ double ca[NV], cd[NV + 1];
+    __shared__ double sh[NV + 1][kBlock / 64];
     if (threadIdx.x < NV) ca[threadIdx.x] = static_cast<int>(threadIdx.x) < j ? gs->a[threadIdx.x] : 0.0;
     if (threadIdx.x <= NV) cd[threadIdx.x] = static_cast<int>(threadIdx.x) <= j ? gs->d[threadIdx.x] : 0.0;
     __syncthreads();
     const double inv = 1.0 / gs->nu;
     const double dj = cd[j];
-    double acc[NV + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int g = lane / LP, pl = lane % LP;
+    double acc[NS], accn = 0.0;
 #pragma unroll
-    for (int t = 0; t <= NV; ++t) acc[t] = 0.0;
+    for (int u = 0; u < NS; ++u) acc[u] = 0.0;
     const int64_t np = (n + K - 1) / K;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < np; q += stride) {
+    const int64_t per_block = static_cast<int64_t>(kBlock / 64) * LP;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * per_block;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * per_block + wid * LP + pl; q < np; q += stride) {
         const int64_t i0 = q * K;
-        T wv[K], uv[K], vt[NV][K];
+        T vt[NS][K];
+        double pq[K], pn[K];
+#pragma unroll
+        for (int e = 0; e < K; ++e) pq[e] = pn[e] = 0.0;
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int t = u * S + g;
+            if (t < j) {
+                ld_pack<T, K>(vec(V, ld, t), i0, n, vt[u]);
+#pragma unroll
+                for (int e = 0; e < K; ++e) {
+                    const double v = static_cast<double>(vt[u][e]);
+                    pq[e] = fma(ca[t], v, pq[e]);
+                    pn[e] = fma(cd[t], v, pn[e]);
+                }
+            }
+        }
+        if constexpr (S > 1) {
+#pragma unroll
+            for (int off = LP; off < 64; off <<= 1) {
+#pragma unroll
+                for (int e = 0; e < K; ++e) {
+                    pq[e] += __shfl_xor(pq[e], off, 64);
+                    pn[e] += __shfl_xor(pn[e], off, 64);
+                }
+            }
+        }
+        T wv[K], uv[K], qv[K], nv[K];
         ld_pack<T, K>(w, i0, n, wv);
         ld_pack<T, K>(uj, i0, n, uv);
-        double qd[K], nd[K];
 #pragma unroll
         for (int e = 0; e < K; ++e) {
-            qd[e] = static_cast<double>(uv[e]);
-            nd[e] = static_cast<double>(wv[e]) * inv;
+            const double qd = static_cast<double>(uv[e]) - pq[e];
+            const double nd = fma(static_cast<double>(wv[e]), inv, -pn[e]);
+            qv[e] = static_cast<T>(qd * inv);
+            nv[e] = static_cast<T>(fma(-dj, static_cast<double>(qv[e]), nd));
         }
-#pragma unroll
-        for (int t = 0; t < NV; ++t) {
-            if (t < j) {
-                ld_pack<T, K>(vec(V, ld, t), i0, n, vt[t]);
-                if constexpr (stream) {
-#pragma unroll
-                    for (int e = 0; e < K; ++e) {
-                        const double v = static_cast<double>(vt[t][e]);
-                        qd[e] = fma(-ca[t], v, qd[e]);
-                        nd[e] = fma(-cd[t], v, nd[e]);
-                    }
-                }
-            }
+        if (g == 0) {
+            st_pack<T, K>(uj, i0, n, qv);
+            st_pack<T, K>(un, i0, n, nv);
         }
-        if constexpr (!stream) {
-#pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                if (t < j) {
-#pragma unroll
-                    for (int e = 0; e < K; ++e) {
-                        const double v = static_cast<double>(vt[t][e]);
-                        qd[e] = fma(-ca[t], v, qd[e]);
-                        nd[e] = fma(-cd[t], v, nd[e]);
-                    }
-                }
-            }
-        }
-        T qv[K], nv[K];
-#pragma unroll
-        for (int e = 0; e < K; ++e) {
-            qv[e] = static_cast<T>(qd[e] * inv);
-            nv[e] = static_cast<T>(fma(-dj, static_cast<double>(qv[e]), nd[e]));
-        }
-        st_pack<T, K>(uj, i0, n, qv);
-        st_pack<T, K>(un, i0, n, nv);
 #pragma unroll
         for (int e = 0; e < K; ++e) {
             const double u1 = static_cast<double>(nv[e]);
 #pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                if (t < j) acc[t] = fma(static_cast<double>(vt[t][e]), u1, acc[t]);
-                else if (t == j) acc[t] = fma(static_cast<double>(qv[e]), u1, acc[t]);
+            for (int u = 0; u < NS; ++u) {
+                const int t = u * S + g;
+                if (t < j) acc[u] = fma(static_cast<double>(vt[u][e]), u1, acc[u]);
+                else if (t == j) acc[u] = fma(static_cast<double>(qv[e]), u1, acc[u]);
             }
-            acc[NV] = fma(u1, u1, acc[NV]);
+            if (g == 0) accn = fma(u1, u1, accn);
         }
     }
-    block_partial<NV + 1>(acc, part);
+    // workgroup partials: per vector t = u S + g the sum over its lane group,
+    // then the four waves in order; row NV: ||u_{j+1}||^2 from group 0
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        double v = acc[u];
+#pragma unroll
+        for (int off = LP / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (pl == 0) sh[u * S + g][wid] = v;
+    }
+    {
+        double v = accn;
+#pragma unroll
+        for (int off = LP / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sh[NV][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x <= NV) {
+        const int t = threadIdx.x;
+        double v = sh[t][0];
+#pragma unroll
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) v += sh[t][w2];
+        part[static_cast<size_t>(t) * kMaxGrid + blockIdx.x] = v;
+    }
 }
 
 // End of step j (one workgroup; thread 0 does the scalar work): nu' from
@@ -592,7 +643,16 @@ static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, Sol
     SPK_GM_NV(k_gm_passA, n, ld, V, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->b[0], st, gs);
     hipLaunchKernelGGL(k_gm_coef, dim3(1), dim3(64), 0, s, st, gs, j);
-    SPK_GM_NV(k_gm_passB, n, ld, V, uj, un, w, j, st, gs, gpart);
+    // passB: lanes per pack by basis bucket
+    if (nv == 8)
+        hipLaunchKernelGGL((k_gm_passB<T, 8, passb_split<T, 8>()>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, uj, un,
+                           w, j, st, gs, gpart);
+    else if (nv == 16)
+        hipLaunchKernelGGL((k_gm_passB<T, 16, passb_split<T, 16>()>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, uj,
+                           un, w, j, st, gs, gpart);
+    else
+        hipLaunchKernelGGL((k_gm_passB<T, 32, passb_split<T, 32>()>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, uj,
+                           un, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->a[0], st, gs);
     hipLaunchKernelGGL(k_gm_final, dim3(1), dim3(kBlock), 0, s, st, gs, gpart, grid, nv, j, m);
 #undef SPK_GM_NV
