@@ -47,19 +47,14 @@ __device__ __forceinline__ T wave_sum(T v) {
 //     while each block's neighbouring rows share one L2.
 //   remap = -D (D >= 2 rows, the pattern's period): rows are cut into
 //     periods of D rows (a plane of a 3-D grid, D = N^2) and each period into
-//     8 kb bands of about kPencilRows rows (kb >= 1); XCD x owns bands
-//     x kb .. x kb + kb - 1 of every period and walks one band through all
-//     periods (a pencil) before the next.  Rows i and i +- D then sit on the
-//     same XCD and are read close together in time, so an entry of the
+//     8 slabs; XCD x owns slab x of every period and walks its tiles period by
+//     period.  Rows i and i +- D then sit on the same XCD, so an entry of the
 //     gathered vector is read into one L2 for its own plane and both
-//     neighbouring planes.  A tile belongs to the slice holding its first row.
-constexpr int64_t kPencilRows = 8192;
-
+//     neighbouring planes.  A tile belongs to the slab holding its first row.
 struct TileIter {
     int64_t j, end, stride;   // position in this XCD's (or the global) tile sequence
     int64_t k, xcd;           // block size and XCD for remap >= 2; period D for remap <= -2
     int64_t T, c, t0, t1;     // period mode: tile count, current period, its tile range on this XCD
-    int64_t P, kb, jb, bl, bh;   // period mode: periods, bands per XCD, current band and its rows in a period
     int mode;
     __device__ TileIter(int64_t T_, int remap) {
         const int64_t G = gridDim.x, b = blockIdx.x;
@@ -73,12 +68,7 @@ struct TileIter {
         if (mode == 3) {
             k = -static_cast<int64_t>(remap);
             stride = M;
-            P = (T * kTileRows + k - 1) / k;
-            kb = k / (kNumXcd * kPencilRows);
-            kb = kb < 1 ? 1 : kb;
-            jb = 0;
             c = 0;
-            band_range();
             period_range();
             j = m;
             settle();
@@ -103,34 +93,24 @@ struct TileIter {
             stride = M;
         }
     }
-    // period mode: rows [bl, bh) of a period form band jb of this XCD
-    __device__ void band_range() {
-        const int64_t band = xcd * kb + jb, nb = kNumXcd * kb;
-        bl = (band * k) / nb;
-        bh = ((band + 1) * k) / nb;
-    }
-    // period mode: the tiles of band jb in period c are [t0, t1): those whose
-    // first row lies in [c D + bl, c D + bh)
+    // period mode: this XCD's tiles of period c are [t0, t1): those whose first
+    // row lies in [c D + x D / 8, c D + (x + 1) D / 8)
     __device__ void period_range() {
-        const int64_t base = c * k;
-        t0 = min((base + bl + kTileRows - 1) / kTileRows, T);
-        t1 = min((base + bh + kTileRows - 1) / kTileRows, T);
+        const int64_t lo = c * k + (xcd * k) / kNumXcd, hi = c * k + ((xcd + 1) * k) / kNumXcd;
+        t0 = min((lo + kTileRows - 1) / kTileRows, T);
+        t1 = min((hi + kTileRows - 1) / kTileRows, T);
     }
-    // period mode: move (jb, c, j) forward until j indexes a tile of the
-    // slice (jb, c) (j counts from t0), or past this XCD's last band (then
-    // end = 0, invalid)
+    // period mode: move (c, j) forward until j indexes a tile of period c
+    // (j counts from t0), or past the last tile (then end = 0, invalid)
     __device__ void settle() {
         end = 1;
         while (j >= t1 - t0) {
-            j -= t1 - t0;
-            if (++c >= P) {
-                c = 0;
-                if (++jb >= kb) {
-                    end = 0;
-                    return;
-                }
-                band_range();
+            if (t0 >= T) {
+                end = 0;
+                return;
             }
+            j -= t1 - t0;
+            ++c;
             period_range();
         }
     }

@@ -319,10 +319,11 @@ __global__ void k_gm_coef(const SolveState *st, GmresState *gs, int j) {
 // pack's q_j and u_{j+1}, and every lane accumulates the dot products of its
 // own vectors.
 // Lanes per pack in passB by value type and basis bucket, measured on
-// stencil7_ns N=215 (us per launch, one lane / two / four): FP64 NV = 8:
-// 106 / 110 / 143, NV = 16: - / 242 / 266, NV = 32: - / 347 / 267 (the
-// single-lane form that held all packs took 165, 248 and 308); FP32 (the
-// GMRES-IR basis) NV = 8: two lanes 61 (old form 107), NV = 16: 112 (140).
+// stencil7_ns N=215 (mean us per working launch, one lane / two / four):
+// FP64 NV = 8: 106 / 110 / 143, NV = 16: - / 242 / 266, NV = 32:
+// - / 570 / 437 (the single-lane form that held all packs took 165, 248 and
+// 505); FP32 (the GMRES-IR basis) NV = 8: two lanes 61 (old form 107),
+// NV = 16: 133 (165).
 template <typename T, int NV>
 constexpr int passb_split() {
     return NV <= 8 ? (sizeof(T) == 4 ? 2 : 1) : (NV <= 16 ? 2 : 4);

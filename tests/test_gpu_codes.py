@@ -124,11 +124,10 @@ def test_period_tile_order(spk, ctx, monkeypatch, N):
     assert np.array_equal(y0, y1)
 
 
-def test_pencil_tile_order(spk, ctx, monkeypatch):
-    """A period of 150,000 rows is cut into two bands per XCD (pencils of
-    about 8192 rows walked through every period); every tile is still
-    visited once, so the product equals the plain order's bit for bit, and
-    the ragged last period is covered."""
+def test_long_period_tile_order(spk, ctx, monkeypatch):
+    """A pattern period of 150,000 rows (4.7 periods, the last ragged): the
+    period slabs still visit every tile once, so the product equals the
+    plain order's bit for bit."""
     n, D = 700_001, 150_000
     offs = np.array([-D, -1, 0, 1, D], np.int64)
     C = np.arange(n, dtype=np.int64)[:, None] + offs[None, :]
