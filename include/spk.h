@@ -166,8 +166,7 @@ typedef struct {
     int32_t spmv_kernel;       /* 0 = LDS-staged row tiles, 1 = lanes-per-row vector kernel */
     int32_t lanes;             /* lanes per row of the vector kernel */
     int32_t grid;              /* SpMV workgroups */
-    int32_t xcd_remap;         /* tile order: 0 round-robin, 1 XCD eighths, k >= 2 XCD blocks of k tiles,
-                                  -D per-XCD slabs of each D-row period of the pattern */
+    int32_t xcd_remap;         /* tile order: 0 round-robin, 1 XCD eighths, k >= 2 XCD blocks of k tiles */
     int32_t exec_mode;         /* resolved spk_exec_mode */
     int32_t chunk_iters;       /* resolved chunk size */
     int32_t tuned;             /* 1 = chosen by timing candidates, 0 = heuristic/cached */

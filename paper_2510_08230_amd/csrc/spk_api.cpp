@@ -31,12 +31,10 @@ struct TuneKey {
     int use;     // TUNE_PLAIN or TUNE_CG
     int codes;   // the matrix has column codes
     int staged;  // values and columns are 16-byte aligned (the LDS tiles may run)
-    int64_t period;   // the pattern's period in rows (0 = none known)
     int long_rows;    // rows longer than kLongRow (the kernels with the long-row pass run)
     bool operator<(const TuneKey &o) const {
-        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged, period, long_rows) <
-               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged, o.period,
-                        o.long_rows);
+        return std::tie(n_rows, n_cols, nnz, pt, it, vt, use, codes, staged, long_rows) <
+               std::tie(o.n_rows, o.n_cols, o.nnz, o.pt, o.it, o.vt, o.use, o.codes, o.staged, o.long_rows);
     }
 };
 
@@ -215,16 +213,6 @@ bool stream_ok(const CsrDev &A) {
     return (reinterpret_cast<uintptr_t>(A.va) & 15) == 0 && (reinterpret_cast<uintptr_t>(A.ci) & 15) == 0;
 }
 
-// Tile order of the pattern's period (TileIter remap = -D): D rows, the
-// largest column offset of a coded pattern (N^2 for a 3-D 7-point stencil),
-// when every XCD slab of a period spans at least two tiles; else fallback.
-int period_remap(const CsrDev &A, int fallback) {
-    const int64_t D = A.period;
-    if (D >= int64_t(spk::kNumXcd) * spk::kTileRows * 2 && D <= INT32_MAX && D < A.n_rows)
-        return -static_cast<int>(D);
-    return fallback;
-}
-
 // bpc <= 0: as many workgroups per CU as the occupancy calculator allows;
 // otherwise bpc per CU (extra workgroups queue until a slot frees).
 SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap, int nt, int pf, int bpc,
@@ -256,7 +244,7 @@ SpmvTune heuristic_tune(spk_ctx ctx, const CsrDev &A) {
 spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int use, SolveState *st,
                     double *partials, TuneResult *out, const void *fcg = nullptr) {
     const TuneKey key{A.n_rows, A.n_cols, A.nnz, A.ptr_t, A.idx_t, A.val_t, use, A.codes != nullptr, stream_ok(A),
-                      A.period, A.max_row > spk::kLongRow};
+                      A.max_row > spk::kLongRow};
     auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
         *out = hit->second;
@@ -277,9 +265,6 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
         // the Infinity Cache) sometimes favour it, in the CG loop it measured
         // 16% slower at C2 (190 against 164 us) and 33% slower for the FP32
         // inner product at C3 (129 against 97 us).
-        // (the pattern-period slab order, remap = -D, is not a candidate: on
-        // stencil7 it measured 13% slower at N = 215 and 6% at N = 1048 than
-        // XCD-blocked runs of 64 tiles; SPK_SPMV_KERNEL=...,remap=period forces it)
         for (int remap : {64, 256, 1, 0})
             for (int nt : {1, 0}) {
                 cands.push_back(make_tune(ctx, A, 0, 0, remap, nt, 1, 0));
@@ -355,8 +340,6 @@ spk_status autotune(spk_ctx ctx, const CsrDev &A, const void *x, void *y, int us
 // "vector:<lanes>", optionally followed by ",key=value" with keys remap, nt,
 // pf, bpc, codes, pack (e.g. "stream,pf=1,nt=1,remap=0,bpc=4,codes=0";
 // codes and pack default to 1 when the matrix has codes / packed rows).
-// remap=period takes the period slabs of the matrix's pattern period (plain
-// XCD eighths when it has none); remap=-D forces a period of D rows.
 bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     const char *env = std::getenv("SPK_SPMV_KERNEL");
     if (!env || !*env) return false;
@@ -382,7 +365,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
             if (eq != std::string::npos) {
                 const std::string k = tok.substr(0, eq);
                 const int val = std::atoi(tok.c_str() + eq + 1);
-                if (k == "remap") remap = tok.substr(eq + 1) == "period" ? period_remap(A, 1) : val;
+                if (k == "remap") remap = val;
                 else if (k == "nt") nt = val;
                 else if (k == "pf") pf = val;
                 else if (k == "bpc") bpc = val;
@@ -394,7 +377,7 @@ bool forced_tune(spk_ctx ctx, const CsrDev &A, SpmvTune *t) {
     }
     if (kind < 0) return false;
     if (kind == 0 && !stream_ok(A)) kind = 1;
-    if (remap == INT_MIN || remap == -1) remap = 1;
+    if (remap < 0) remap = 1;   // unset (or negative): contiguous XCD eighths
     *t = make_tune(ctx, A, kind, l2, remap, nt, pf, bpc, codes, pack);
     return true;
 }
@@ -484,17 +467,6 @@ spk_status build_codes(spk_plan pl) {
         ctx->dpool.put(buf);
         return SPK_OK;
     }
-    // the pattern's period: the largest offset magnitude in the ascending table
-    int64_t ends[2] = {0, 0};
-    const int64_t *dtab = static_cast<const int64_t *>(buf);
-    if (hipMemcpyAsync(&ends[0], dtab, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(&ends[1], dtab + (h[0] - 1), sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-        ctx->dpool.put(buf);
-        return fail(ctx, SPK_ERR_DEVICE, "column code table");
-    }
-    A.period = std::max(-ends[0], ends[1]);
     pl->codes_buf = buf;
     A.codes = static_cast<const char *>(buf) + sizeof(int64_t) * spk::kCodeDict;
     const char *pack = std::getenv("SPK_ROW_PACK");
@@ -1692,7 +1664,7 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
     // context's cache, never added to it), else the heuristic one
     const TuneKey key{pl.A.n_rows, pl.A.n_cols, pl.A.nnz, pl.A.ptr_t, pl.A.idx_t, pl.A.val_t,
                       pl.fused ? TUNE_FCG : TUNE_CG, false,
-                      stream_ok(pl.A), 0, pl.A.max_row > spk::kLongRow};
+                      stream_ok(pl.A), pl.A.max_row > spk::kLongRow};
     if (!forced_tune(ctx, pl.A, &pl.tune)) {
         auto hit = ctx->tune_cache.find(key);
         pl.tune = hit != ctx->tune_cache.end() && pl.A.nnz >= 100000 ? hit->second.tune : heuristic_tune(ctx, pl.A);

@@ -131,10 +131,6 @@ struct CsrDev {
     // int64 first entry of every 256-row tile (tiles + 1 values), followed
     // directly by one uint16 per row, its first entry less its tile's.
     const void *rowpack = nullptr;
-    // The pattern's period in rows when known (with codes: the largest column
-    // offset magnitude, N^2 for a 3-D 7-point stencil), else 0; picks the
-    // period-slab tile order (host side only).
-    int64_t period = 0;
     // The longest row's entry count (measured when the plan validates A; 0 =
     // unknown).  Above kLongRow the row tiles sum such rows with the whole
     // workgroup (host side only: it sets the kernels' long-row argument).

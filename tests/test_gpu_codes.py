@@ -108,44 +108,6 @@ def test_coded_product_equals_plain_indices(spk, ctx, monkeypatch, name, ptr, id
         assert np.all(np.abs(y1 - oracle.spmv(A, xh)) <= 2 * gamma(m, U64) * oracle.spmv_abs(A, xh))
 
 
-@pytest.mark.parametrize("N", [70, 97])
-def test_period_tile_order(spk, ctx, monkeypatch, N):
-    """The coded stencil's period (its largest column offset, N^2) orders the
-    tiles in per-XCD slabs of each plane; every tile is still visited once,
-    so the product equals the plain order's bit for bit."""
-    A = inputs.stencil7(N, 2)
-    M = dev_csr(spk, A, ptr="i32", idx="i32")
-    x = to_dev(inputs.vec(A.n_cols, 7, 5))
-    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,remap=period")
-    y1, i1 = spmv(spk, ctx, M, x, A.n_rows)
-    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,remap=1,codes=0")
-    y0, i0 = spmv(spk, ctx, M, x, A.n_rows)
-    assert i1["xcd_remap"] == -N * N and i1["col_codes"] == 3 and i0["xcd_remap"] == 1
-    assert np.array_equal(y0, y1)
-
-
-def test_long_period_tile_order(spk, ctx, monkeypatch):
-    """A pattern period of 150,000 rows (4.7 periods, the last ragged): the
-    period slabs still visit every tile once, so the product equals the
-    plain order's bit for bit."""
-    n, D = 700_001, 150_000
-    offs = np.array([-D, -1, 0, 1, D], np.int64)
-    C = np.arange(n, dtype=np.int64)[:, None] + offs[None, :]
-    keep = (C >= 0) & (C < n)
-    rp = np.concatenate([[0], np.cumsum(keep.sum(axis=1))]).astype(np.int64)
-    col = C[keep].astype(np.int32)
-    val = np.random.default_rng(11).uniform(-1.0, 1.0, col.size)
-    A = inputs.CSR(n, n, rp, col, val)
-    M = dev_csr(spk, A, ptr="i32", idx="i32")
-    x = to_dev(inputs.vec(n, 7, 5))
-    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,remap=period")
-    y1, i1 = spmv(spk, ctx, M, x, n)
-    monkeypatch.setenv("SPK_SPMV_KERNEL", "stream,remap=1,codes=0")
-    y0, i0 = spmv(spk, ctx, M, x, n)
-    assert i1["xcd_remap"] == -D and i1["col_codes"] == 3 and i0["xcd_remap"] == 1
-    assert np.array_equal(y0, y1)
-
-
 @pytest.mark.parametrize("k,coded", [(256, 3), (257, 0)])
 def test_codes_taken_up_to_256_offsets(spk, ctx, monkeypatch, k, coded):
     # offsets -128 .. k-129: rows hold up to k entries, so tiles exceed the LDS
