@@ -58,7 +58,8 @@ struct spk_ctx_s {
     int wall_khz = 0;                   // wall_clock64() rate
     std::string err;
     unsigned *d_flags = nullptr;
-    unsigned *h_flags = nullptr;        // pinned
+    unsigned *h_flags = nullptr;        // pinned; [2], [3]: the pattern probe's words
+    long long *d_probe = nullptr;       // pattern probe: offset table (kCodeSlots) and 4 words
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::map<TuneKey, TuneResult> tune_cache;
     spk::DevicePool dpool;              // plan workspace cache
@@ -530,22 +531,45 @@ enum { ALGO_CG = 0, ALGO_CGS = 1, ALGO_PCG = 2, ALGO_GMRES = 3 };
 
 // The fused loop (one launch per CG iteration, or one grid barrier per
 // iteration in the persistent mode) runs CG in FP64 and the CG inner solve of
-// the mixed precisions for systems of at most kFusedMaxRows rows, and always
-// in the persistent mode.  Measured on stencil7: at n = 97,336 one launch per
-// iteration is 13% faster than three (launch-bound); from n = 343,000 up the
-// three vectors the fused step gathers per entry cost more than the two
-// launches it saves (3% slower there, 16% at n = 9.9e6), and on random
-// patterns each gathered vector is a random read of its own (15% slower at
-// n = 1e5).  SPK_CG_FUSED=1 / 0 forces it on / off (0 also rules out the
-// persistent mode).
+// the mixed precisions for small systems, and always in the persistent mode.
+// Measured (ms per solve, fused / three launches): stencil7 n = 97,336:
+// 0.65 / 0.74; n = 343,000: 1.18 / 1.14 (the three vectors the fused step
+// gathers per entry cost more than the two launches it saves; 16% slower at
+// n = 9.9e6); randsym n = 16,000: 0.62 / 0.66, n = 50,000: 0.67 / 0.68,
+// n = 131,072: 1.09 / 0.84 (on a random pattern each gathered vector is a
+// random read of its own).  So: up to kFusedMaxRowsAny rows always; up to
+// kFusedMaxRows when the pattern is banded (pattern_regular); never above.
+// SPK_CG_FUSED=1 / 0 forces it on / off (0 also rules out the persistent
+// mode).
 constexpr int64_t kFusedMaxRows = int64_t(1) << 17;
+constexpr int64_t kFusedMaxRowsAny = int64_t(1) << 16;
 
-bool fused_loop(const spk_solver_cfg &cfg, int64_t n) {
+// Whether the choice depends on the pattern (pattern_regular must be asked).
+bool fused_needs_pattern(const spk_solver_cfg &cfg, int64_t n) {
+    if (cfg.solver != SPK_SOLVER_CG || cfg.precond != SPK_PRECOND_NONE || std::getenv("SPK_CG_FUSED")) return false;
+    return cfg.exec_mode != SPK_EXEC_PERSISTENT && n > kFusedMaxRowsAny && n <= kFusedMaxRows;
+}
+
+bool fused_loop(const spk_solver_cfg &cfg, int64_t n, bool regular) {
     if (cfg.solver != SPK_SOLVER_CG || cfg.precond != SPK_PRECOND_NONE) return false;
     const char *env = std::getenv("SPK_CG_FUSED");
     if (env && std::strcmp(env, "0") == 0) return false;
     if (env && std::strcmp(env, "1") == 0) return true;
-    return n <= kFusedMaxRows || cfg.exec_mode == SPK_EXEC_PERSISTENT;
+    return n <= kFusedMaxRowsAny || (n <= kFusedMaxRows && regular) || cfg.exec_mode == SPK_EXEC_PERSISTENT;
+}
+
+// Whether valid A's pattern is banded: the row tiles sampled (every eighth
+// and the last) hold at most kCodeDict distinct column offsets c - i.
+spk_status pattern_regular(spk_ctx ctx, const CsrDev &A, bool *regular) {
+    *regular = true;
+    if (A.n_rows == 0 || A.nnz == 0) return SPK_OK;
+    long long *table = ctx->d_probe;
+    unsigned *words = reinterpret_cast<unsigned *>(table + spk::kCodeSlots);
+    SPK_HIP(ctx, spk::launch_pattern_probe(A, 8, table, words, ctx->num_cu * 8, ctx->stream));
+    SPK_HIP(ctx, hipMemcpyAsync(ctx->h_flags + 2, words, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    SPK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *regular = ctx->h_flags[3] == 0 && ctx->h_flags[2] <= static_cast<unsigned>(spk::kCodeDict);
+    return SPK_OK;
 }
 
 // st->x := ptr (the tuner's runs of the fused step write through st->x).
@@ -833,8 +857,9 @@ spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
     ctx->hpool.set_cap(size_t(16) << 20);
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&ctx->d_flags, 2 * sizeof(unsigned)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), 2 * sizeof(unsigned), hipHostMallocDefault) !=
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->h_flags), 4 * sizeof(unsigned), hipHostMallocDefault) !=
             hipSuccess ||
+        hipMalloc(&ctx->d_probe, sizeof(long long) * spk::kCodeSlots + 4 * sizeof(unsigned)) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&ctx->h_noalloc_st), sizeof(SolveState), hipHostMallocDefault) !=
             hipSuccess) {
@@ -858,6 +883,7 @@ spk_status spk_finalize(spk_ctx ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    if (ctx->d_probe) (void)hipFree(ctx->d_probe);
     if (ctx->h_noalloc_st) (void)hipHostFree(ctx->h_noalloc_st);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -1094,6 +1120,9 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
     };
     const size_t partial_bytes = sizeof(double) * spk::SITE_COUNT * spk::kSiteWidth * spk::kMaxGrid;
     if (!dget(partial_bytes, &pl->partials)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "partials");
+    bool regular = true;   // the pattern decides the loop kind only in the size band between the limits
+    if (fused_needs_pattern(cfg, n) && (s = pattern_regular(ctx, pl->A, &regular)) != SPK_OK)
+        return cleanup(s, ctx->err);
     s = build_codes(pl);
     if (s != SPK_OK) return cleanup(s, ctx->err);
     const int64_t want = (n + int64_t(spk::kBlock) * 8 - 1) / (int64_t(spk::kBlock) * 8);
@@ -1108,7 +1137,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             pl->hist_cap = cfg.max_iters + 1;
             if (!dget(sizeof(double) * pl->hist_cap, &pl->hist)) return cleanup(SPK_ERR_OUT_OF_MEMORY, "history");
         }
-        pl->fused = pl->algo == ALGO_CG && fused_loop(cfg, n);
+        pl->fused = pl->algo == ALGO_CG && fused_loop(cfg, n, regular);
         if (pl->fused && (!dget(nb, &pl->r_b) || !dget(nb, &pl->p_b) || !dget(nb, &pl->q_b)))
             return cleanup(SPK_ERR_OUT_OF_MEMORY, "fused CG workspace");
         if (hipMemsetAsync(pl->st, 0, sizeof(SolveState), ctx->stream) != hipSuccess ||
@@ -1180,7 +1209,7 @@ spk_status spk_plan_solve(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg *c
             pl->A32.va = dst;
             pl->A32.val_t = to;
         }
-        pl->fused = pl->algo == ALGO_CG && fused_loop(cfg, n);
+        pl->fused = pl->algo == ALGO_CG && fused_loop(cfg, n, regular);
         if (pl->fused && (!dget(nf, &pl->r32_b) || !dget(nf, &pl->p32_b) || !dget(nf, &pl->q32_b)))
             return cleanup(SPK_ERR_OUT_OF_MEMORY, "fused CG workspace");
         if (pl->algo == ALGO_GMRES) {   // GMRES-IR: FP32 basis
@@ -1579,7 +1608,7 @@ static int64_t na_rows(int v) {
 // Vectors of n doubles a solve of n rows keeps in the scratch: r, p, q, and
 // their second buffers when it runs the fused loop (as a plan of the same
 // configuration and size does).
-static int na_vectors(const spk_solver_cfg &cfg, int64_t n) { return fused_loop(cfg, n) ? 6 : 3; }
+static int na_vectors(const spk_solver_cfg &cfg, int64_t n) { return fused_loop(cfg, n, true) ? 6 : 3; }
 
 // Whether a solve of n rows fits the scratch.
 static bool na_fits(const spk_solver_cfg &cfg, int64_t n) { return n <= na_rows(na_vectors(cfg, n)); }
@@ -1650,7 +1679,9 @@ spk_status spk_solve_noalloc(spk_ctx ctx, const spk_csr *A, const spk_solver_cfg
     pl.r = reinterpret_cast<double *>(base + kNaVecBase);
     pl.p = reinterpret_cast<double *>(base + kNaVecBase + vb);
     pl.q = reinterpret_cast<double *>(base + kNaVecBase + 2 * vb);
-    pl.fused = fused_loop(cfg, n);
+    bool regular = true;
+    if (fused_needs_pattern(cfg, n) && (s = pattern_regular(ctx, pl.A, &regular)) != SPK_OK) return s;
+    pl.fused = fused_loop(cfg, n, regular);
     if (pl.fused) {
         pl.r_b = reinterpret_cast<double *>(base + kNaVecBase + 3 * vb);
         pl.p_b = reinterpret_cast<double *>(base + kNaVecBase + 4 * vb);

@@ -867,6 +867,20 @@ hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipSt
     });
 }
 
+hipError_t launch_pattern_probe(const CsrDev &A, int step, long long *table, unsigned *words, int grid,
+                                hipStream_t s) {
+    if (step < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_code_clear, dim3(1), dim3(kBlock), 0, s, table, words);
+    if (A.n_rows == 0) return hipGetLastError();
+    return dispatch_idx(A, [&](auto rp, auto ci) {
+        using P = pointee_t<decltype(rp)>;
+        using I = pointee_t<decltype(ci)>;
+        hipLaunchKernelGGL((k_code_collect<P, I>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, rp, ci, step, table,
+                           words);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_code_build(const CsrDev &A, int step, long long *table, unsigned *words, void *codes_base,
                              int grid, hipStream_t s) {
     int64_t *dict = static_cast<int64_t *>(codes_base);

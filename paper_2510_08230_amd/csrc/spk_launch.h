@@ -12,6 +12,11 @@ namespace spk {
 // row's entry count, clamped to 2^32 - 1); both words zero before the launch.
 hipError_t launch_validate(const CsrDev &A, unsigned *flags, int max_grid, hipStream_t s);
 hipError_t launch_partition(const CsrDev &A, int64_t parts, int64_t *split, hipStream_t s);
+// The distinct column offsets c - i of every step-th row tile (and the last)
+// collected into table (kCodeSlots slots); words[0] counts them, words[1] is
+// set when there are more than kCodeDict.  A must be valid.
+hipError_t launch_pattern_probe(const CsrDev &A, int step, long long *table, unsigned *words, int grid,
+                                hipStream_t s);
 // Column codes (plan time): collects the distinct column offsets c - i of
 // every step-th row tile (and the last) into table (kCodeSlots int64 words),
 // then, when there are at most kCodeDict of them, writes the ascending offset

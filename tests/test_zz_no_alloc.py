@@ -51,12 +51,16 @@ def planned(spk, ctx, M, b, cfg):
 # 512,000 rows) run three launches per iteration, the others one (the scratch
 # layouts differ); all stay below the 2^22 entries from which plans build
 # column codes (the allocation-free solve builds none)
-@pytest.mark.parametrize("mats", [((46, 0), (23, 3)), ((60, 1), (9, 2)), ((80, 5), (50, 1))])
+@pytest.mark.parametrize("mats", [(("stencil7", 46, 0), ("stencil7", 23, 3)), (("stencil7", 60, 1), ("stencil7", 9, 2)),
+                                  (("stencil7", 80, 5), ("stencil7", 50, 1)),
+                                  (("randsym", 100000, 2), ("randsym", 40000, 3))])
 def test_noalloc_equals_planned_twice(spk, ctx, mats):
+    # randsym 100,000 lies in the size band where the pattern picks the loop
+    # (three launches for a random pattern), randsym 40,000 below it (fused)
     cfg = cfg_for(spk)
-    for N, seed in mats:   # the second system is the smaller one
-        print("noalloc: stencil7 N=%d seed=%d" % (N, seed), flush=True)
-        A = inputs.stencil7(N, seed)
+    for kind, N, seed in mats:   # the second system is the smaller one
+        print("noalloc: %s %d seed=%d" % (kind, N, seed), flush=True)
+        A = inputs.stencil7(N, seed) if kind == "stencil7" else inputs.randsym(N, seed)
         bh = inputs.rhs(A.n_rows, seed)
         M = dev_csr(spk, A, ptr="i32", idx="i32")
         b = to_dev(bh)
