@@ -171,7 +171,8 @@ __global__ __launch_bounds__(kBlock) void k_gm_cycle_start(SolveState *st, Gmres
 //    compiler holds FP32 values converted to FP64).
 // passB keeps every finished vector's pack until u_{j+1} is formed (its dot
 // products need it); it splits the basis over several lanes per pack to keep
-// that footprint small (see k_gm_passB).
+// that footprint small (see k_gm_passB), and passA takes the same split for
+// all but the FP64 small-basis bucket (k_gm_passA_split).
 // Basis columns sit ld = gm_ld(n) elements apart (16-byte aligned); the last
 // pack of a vector is loaded element by element when n is not a multiple
 // of K.
@@ -320,13 +321,14 @@ __global__ void k_gm_coef(const SolveState *st, GmresState *gs, int j) {
 // own vectors.
 // Lanes per pack in passB by value type and basis bucket, measured on
 // stencil7_ns N=215 (mean us per working launch, one lane / two / four):
-// FP64 NV = 8: 106 / 110 / 143, NV = 16: - / 242 / 266, NV = 32:
-// - / 570 / 437 (the single-lane form that held all packs took 165, 248 and
-// 505); FP32 (the GMRES-IR basis) NV = 8: two lanes 61 (old form 107),
-// NV = 16: 133 (165).
+// FP64 NV = 8: 116 / 107 / 115, NV = 16: - / 246 / 235, NV = 32: - / - /
+// 404; FP32 (the GMRES-IR basis) NV = 8: - / 55 / 80, NV = 16: - / 133 /
+// 120.  (Combining each vector's pack as it arrived, which kept one load in
+// flight per lane, took 106, 241 and 436 for FP64 and 61 and 132 for FP32
+// at the best split.)
 template <typename T, int NV>
 constexpr int passb_split() {
-    return NV <= 8 ? (sizeof(T) == 4 ? 2 : 1) : (NV <= 16 ? 2 : 4);
+    return NV <= 8 ? 2 : 4;
 }
 
 template <typename T, int NV, int S>
@@ -334,6 +336,60 @@ constexpr int passb_pack() {
     int k = 16 / static_cast<int>(sizeof(T));
     while (k > 1 && (NV / S) * k * static_cast<int>(sizeof(T)) > 128) k /= 2;
     return k;
+}
+
+// passA with the basis split over S lanes per pack, as passB: lane group g
+// of a wave holds the vectors t = u S + g (t <= j), each lane sums its
+// vectors' products with w over its pack, and the workgroup partial of
+// vector t is its group's sum followed by the four waves in order.
+template <typename T, int NV, int S>
+__global__ __launch_bounds__(kBlock) void k_gm_passA_split(int64_t n, int64_t ld, const T *__restrict__ V,
+                                                           const T *__restrict__ w, int j, const SolveState *st,
+                                                           const GmresState *gs, double *part) {
+    if (gm_idle(st, gs)) return;
+    static_assert(NV % S == 0 && (S == 1 || S == 2 || S == 4), "lane split");
+    constexpr int NS = NV / S;
+    constexpr int LP = 64 / S;
+    constexpr int K = passb_pack<T, NV, S>();
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int g = lane / LP, pl = lane % LP;
+    double acc[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) acc[u] = 0.0;
+    const int64_t np = (n + K - 1) / K;
+    const int64_t per_block = static_cast<int64_t>(kBlock / 64) * LP;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * per_block;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * per_block + wid * LP + pl; q < np; q += stride) {
+        const int64_t i0 = q * K;
+        T wv[K], vt[NS][K];
+        ld_pack<T, K>(w, i0, n, wv);
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            if (u * S + g <= j) ld_pack<T, K>(vec(V, ld, u * S + g), i0, n, vt[u]);
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            if (u * S + g <= j) {
+#pragma unroll
+                for (int e = 0; e < K; ++e)
+                    acc[u] = fma(static_cast<double>(wv[e]), static_cast<double>(vt[u][e]), acc[u]);
+            }
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        double v = acc[u];
+#pragma unroll
+        for (int off = LP / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (pl == 0) sh[u * S + g][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int t = threadIdx.x;
+        double v = sh[t][0];
+#pragma unroll
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) v += sh[t][w2];
+        part[static_cast<size_t>(t) * kMaxGrid + blockIdx.x] = v;
+    }
 }
 
 template <typename T, int NV, int S>
@@ -363,7 +419,14 @@ __global__ __launch_bounds__(kBlock) void k_gm_passB(int64_t n, int64_t ld, cons
     const int64_t stride = static_cast<int64_t>(gridDim.x) * per_block;
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * per_block + wid * LP + pl; q < np; q += stride) {
         const int64_t i0 = q * K;
-        T vt[NS][K];
+        // every load of the round is issued before the first use, so the
+        // lane's packs are in flight together
+        T vt[NS][K], wv[K], uv[K];
+        ld_pack<T, K>(w, i0, n, wv);
+        ld_pack<T, K>(uj, i0, n, uv);
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            if (u * S + g < j) ld_pack<T, K>(vec(V, ld, u * S + g), i0, n, vt[u]);
         double pq[K], pn[K];
 #pragma unroll
         for (int e = 0; e < K; ++e) pq[e] = pn[e] = 0.0;
@@ -371,7 +434,6 @@ __global__ __launch_bounds__(kBlock) void k_gm_passB(int64_t n, int64_t ld, cons
         for (int u = 0; u < NS; ++u) {
             const int t = u * S + g;
             if (t < j) {
-                ld_pack<T, K>(vec(V, ld, t), i0, n, vt[u]);
 #pragma unroll
                 for (int e = 0; e < K; ++e) {
                     const double v = static_cast<double>(vt[u][e]);
@@ -390,9 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_passB(int64_t n, int64_t ld, cons
                 }
             }
         }
-        T wv[K], uv[K], qv[K], nv[K];
-        ld_pack<T, K>(w, i0, n, wv);
-        ld_pack<T, K>(uj, i0, n, uv);
+        T qv[K], nv[K];
 #pragma unroll
         for (int e = 0; e < K; ++e) {
             const double qd = static_cast<double>(uv[e]) - pq[e];
@@ -627,6 +687,26 @@ hipError_t launch_gm_step_spmv(const CsrDev &A, const SpmvTune &t, const void *V
     return fp32 ? step_spmv_t<float>(A, t, V, w, j, st, gs, s) : step_spmv_t<double>(A, t, V, w, j, st, gs, s);
 }
 
+// passA form by value type and basis bucket: 0 = one lane per pack
+// (k_gm_passA), S > 0 = S lanes per pack (k_gm_passA_split).  Measured on
+// stencil7_ns N=215 (mean us per working launch; one lane per pack, then
+// the split form with one / two / four lanes): FP64 NV = 8: 81 / 89 / 85 /
+// 82, NV = 16: 199 / 198 / 195 / 186, NV = 32: 331 / 330 / 321 / 322; FP32
+// NV = 8: 38 / 37 / 35 / 35, NV = 16: 153 / 100 / 96 / 90, NV = 32: 143 /
+// 142 / 136 / 128.
+template <typename T, int NV>
+constexpr int passa_split() { return sizeof(T) == 8 && NV <= 8 ? 0 : 4; }
+
+template <typename T, int NV>
+static void launch_passA(int grid, int64_t n, int64_t ld, const T *V, const T *w, int j, const SolveState *st,
+                         const GmresState *gs, double *gpart, hipStream_t s) {
+    if constexpr (passa_split<T, NV>() == 0)
+        hipLaunchKernelGGL((k_gm_passA<T, NV>), dim3(grid), dim3(kBlock), 0, s, n, ld, V, w, j, st, gs, gpart);
+    else
+        hipLaunchKernelGGL((k_gm_passA_split<T, NV, passa_split<T, NV>()>), dim3(grid), dim3(kBlock), 0, s, n, ld, V,
+                           w, j, st, gs, gpart);
+}
+
 template <typename T>
 static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, SolveState *st, GmresState *gs,
                               double *gpart, hipStream_t s) {
@@ -635,13 +715,9 @@ static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, Sol
     const int64_t ld = gm_ld(n);
     T *uj = V + static_cast<int64_t>(j) * ld;
     T *un = V + static_cast<int64_t>(j + 1) * ld;
-#define SPK_GM_NV(K, ...)                                                                                   \
-    do {                                                                                                    \
-        if (nv == 8) hipLaunchKernelGGL((K<T, 8>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);            \
-        else if (nv == 16) hipLaunchKernelGGL((K<T, 16>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);     \
-        else hipLaunchKernelGGL((K<T, 32>), dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
-    } while (0)
-    SPK_GM_NV(k_gm_passA, n, ld, V, w, j, st, gs, gpart);
+    if (nv == 8) launch_passA<T, 8>(grid, n, ld, V, w, j, st, gs, gpart, s);
+    else if (nv == 16) launch_passA<T, 16>(grid, n, ld, V, w, j, st, gs, gpart, s);
+    else launch_passA<T, 32>(grid, n, ld, V, w, j, st, gs, gpart, s);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->b[0], st, gs);
     hipLaunchKernelGGL(k_gm_coef, dim3(1), dim3(64), 0, s, st, gs, j);
     // passB: lanes per pack by basis bucket
@@ -656,7 +732,6 @@ static hipError_t step_rest_t(int64_t n, int grid, T *V, T *w, int j, int m, Sol
                            un, w, j, st, gs, gpart);
     hipLaunchKernelGGL(k_gm_reduce, dim3(J), dim3(kBlock), 0, s, gpart, grid, &gs->a[0], st, gs);
     hipLaunchKernelGGL(k_gm_final, dim3(1), dim3(kBlock), 0, s, st, gs, gpart, grid, nv, j, m);
-#undef SPK_GM_NV
     return hipGetLastError();
 }
 
