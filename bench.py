@@ -708,6 +708,8 @@ def serving_block(args, ctx, with_oracle=True):
       validation, autotuned launch) made BEFORE the timed loop, to the same
       tolerance, saturated (back to back): the fair comparison is
       saturated serving against saturated FP64;
+    * batched FP64: the same requests as FP64 CG in the server (closed loop,
+      after a warm-up pass): mixed against FP64 precision, both batched;
     * accuracy: every served and every FP64 solution against the oracle's
       FP64 CG solution (tau 1e-14) of the same system, all instances, the
       oracle solves run on host threads outside every timed region.
@@ -736,11 +738,11 @@ def serving_block(args, ctx, with_oracle=True):
     cfg.max_iters = 100000
     budget = int(args.budget_gb * (1 << 30))
 
-    def run_pass(arrivals):
+    def run_pass(arrivals, pcfg=cfg):
         for x in xs:
             x.zero_()
         torch.cuda.synchronize()
-        srv = spk.spk_server_create(ctx, budget, args.slots, cfg)
+        srv = spk.spk_server_create(ctx, budget, args.slots, pcfg)
         t0 = time.perf_counter()
         tickets = []
         for i, M in enumerate(mats):
@@ -775,6 +777,16 @@ def serving_block(args, ctx, with_oracle=True):
     poi = run_pass(arrivals)
     progress("serving: saturated %.1f solves/s, Poisson pass done" % sat_rate)
     served = [x.cpu().numpy() for x in xs]
+
+    # the same requests as FP64 CG in the server
+    cfg64 = spk.spk_solver_cfg_default()
+    cfg64.precision = spk.PREC_FP64
+    cfg64.reduction_factor = tau
+    cfg64.max_iters = 100000
+    run_pass(None, cfg64)                            # warm-up
+    sat64 = run_pass(None, cfg64)
+    served64 = [x.cpu().numpy() for x in xs]
+    progress("serving: batched FP64 %.1f solves/s" % (len(mats) / sat64["makespan"]))
 
     # baseline: plain FP64 CG, one solve at a time, plans made beforehand
     bcfg = spk.spk_solver_cfg_default()
@@ -840,9 +852,16 @@ def serving_block(args, ctx, with_oracle=True):
                                "note": "spk_execute_solve per instance back to back; every plan (validation, "
                                        "autotuned launch shape, workspace) made before the timed loop"},
         "speedup_saturated_vs_fp64": base_time / sat["makespan"],
+        "fp64_batched": {"makespan_s": sat64["makespan"], "solves_per_s": len(mats) / sat64["makespan"],
+                         "updates_per_s": float(np.sum(nvec * sat64["iters"])) / sat64["makespan"],
+                         "iterations_total": int(sat64["iters"].sum()),
+                         "outer_total": int(sat64["outer"].sum()),
+                         "note": "the same requests as FP64 CG in the server, all submitted at once"},
+        "speedup_saturated_vs_fp64_batched": sat64["makespan"] / sat["makespan"],
         "accuracy": {"served_max_rel_true_residual": float(max(poi["rres"])),
                      "fp64_max_rel_true_residual": float(max(base_rres)),
-                     "all_converged": all(st == 1 for st in poi["stops"])},
+                     "fp64_batched_max_rel_true_residual": float(max(sat64["rres"])),
+                     "all_converged": all(st == 1 for st in poi["stops"] + sat64["stops"])},
     }
     if with_oracle:
         import oracle
@@ -852,15 +871,19 @@ def serving_block(args, ctx, with_oracle=True):
         dt = time.perf_counter() - t0
         e_srv = np.array([np.linalg.norm(a - xo) / np.linalg.norm(xo) for a, (xo, _) in zip(served, sols)])
         e_64 = np.array([np.linalg.norm(a - xo) / np.linalg.norm(xo) for a, (xo, _) in zip(fp64_sols, sols)])
+        e_b64 = np.array([np.linalg.norm(a - xo) / np.linalg.norm(xo) for a, (xo, _) in zip(served64, sols)])
         o_updates = float(sum(int(A.n_rows) * r.iterations for A, (_, r) in zip(hosts, sols)))
         out["accuracy"]["served_err_vs_oracle"] = {"max": float(e_srv.max()), "p50": pct(e_srv, 50),
                                                    "p99": pct(e_srv, 99), "count": int(e_srv.size),
                                                    "within_1e-10": int(np.sum(e_srv <= 1e-10))}
         out["accuracy"]["fp64_err_vs_oracle"] = {"max": float(e_64.max()), "p50": pct(e_64, 50),
                                                  "p99": pct(e_64, 99), "count": int(e_64.size)}
+        out["accuracy"]["fp64_batched_err_vs_oracle"] = {"max": float(e_b64.max()), "p50": pct(e_b64, 50),
+                                                         "p99": pct(e_b64, 99), "count": int(e_b64.size)}
         out["accuracy"]["oracle"] = ("FP64 oracle CG to tau 1e-14 on every instance, %d host threads, %.1f s "
                                      "(%.3g updates/s aggregate)" % (threads, dt, o_updates / dt))
-        out["accuracy"]["equal_final_accuracy"] = bool(e_srv.max() <= 1e-10 and e_64.max() <= 1e-10)
+        out["accuracy"]["equal_final_accuracy"] = bool(e_srv.max() <= 1e-10 and e_64.max() <= 1e-10 and
+                                                       e_b64.max() <= 1e-10)
     return out
 
 

@@ -331,9 +331,12 @@ spk_status spk_gather_probe(spk_ctx ctx, const double *src, int64_t n_src, const
  * A continuous-batching solve server.  Requests of uneven sizes arrive from
  * any host thread; a worker thread admits each into a free slot once its
  * workspace fits the HBM budget, and every live request advances in the same
- * batched launches (per-request FP32 CG with FP64 dot products and FP64
- * iterative refinement: the mixed-precision solve above, on per-request
- * 256-row tiles).  Requests that arrive while others run join between tick
+ * batched launches, on per-request 256-row tiles: a SPK_PREC_MIXED_FP32
+ * request by FP32 CG with FP64 dot products and FP64 iterative refinement
+ * (the mixed-precision solve above), a SPK_PREC_FP64 request by FP64 CG
+ * (Algorithm 1) to ||r|| <= reduction_factor ||b|| on the recurrence
+ * residual, then confirmed on the true residual b - A x (a restart from it
+ * if the test fails there).  Requests that arrive while others run join between tick
  * batches.  A request's result is bitwise independent of which other
  * requests share the batch.  Small systems being overhead-bound is the
  * paper's observation (Sections 6.1-6.2); batching many of them into one
@@ -351,15 +354,22 @@ typedef struct {
                                   plus cached ones); never above budget_bytes */
 } spk_server_stats;
 
-/* Workspace bytes one request of n unknowns and nnz stored entries needs
- * (counted against the budget).  Pure host computation. */
+/* Workspace bytes one SPK_PREC_MIXED_FP32 request of n unknowns and nnz
+ * stored entries needs (counted against the budget).  Pure host computation. */
 size_t spk_server_request_bytes(int64_t n, int64_t nnz);
 
+/* As spk_server_request_bytes for a request of the given precision
+ * (SPK_PREC_MIXED_FP32, or SPK_PREC_FP64: four FP64 vectors and no value
+ * copy); 0 for a precision the server does not run. */
+size_t spk_server_request_bytes_prec(int32_t precision, int64_t n, int64_t nnz);
+
 /* Create a server on the context's device with an HBM budget for request
- * workspace and at most max_slots live requests.  cfg: precision must be
- * SPK_PREC_MIXED_FP32; reduction_factor is the FP64 stop test
- * ||b - A x|| <= reduction_factor ||b||, inner_reduction the inner CG's,
- * max_iters caps inner iterations per request, max_outer refinement steps.
+ * workspace and at most max_slots live requests.  cfg (the default of every
+ * request): solver CG, no preconditioner, precision SPK_PREC_MIXED_FP32 or
+ * SPK_PREC_FP64; reduction_factor is the FP64 stop test
+ * ||b - A x|| <= reduction_factor ||b||, inner_reduction the mixed inner
+ * CG's, max_iters caps inner iterations per request, max_outer refinement
+ * steps (restarts of an FP64 request).
  * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY. */
 spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_slots, const spk_solver_cfg *cfg,
                              spk_server *out);
@@ -373,10 +383,10 @@ spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_s
 spk_status spk_server_submit(spk_server srv, const spk_csr *A, const void *b, void *x, uint64_t *ticket);
 
 /* As spk_server_submit, with this request's own solver configuration (its
- * reduction_factor, inner_reduction, max_iters and max_outer; the other
- * fields must name what the server runs: CG, MIXED_FP32, no preconditioner),
- * so one server mixes requests with different tolerances (the per-solve
- * stopping criteria of Listing 2).  cfg NULL = the server's configuration.
+ * reduction_factor, inner_reduction, max_iters, max_outer and precision
+ * (MIXED_FP32 or FP64); solver CG and no preconditioner), so one
+ * server mixes requests with different tolerances and precisions (the
+ * per-solve stopping criteria of Listing 2).  cfg NULL = the server's configuration.
  * Errors: as spk_server_submit, plus INVALID_ARG / UNSUPPORTED for cfg. */
 spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b, void *x, const spk_solver_cfg *cfg,
                                  uint64_t *ticket);

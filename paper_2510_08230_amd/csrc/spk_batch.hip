@@ -1,8 +1,11 @@
 // Batched serving kernels: every live slot (one solve request) advances by one
 // step of its phase per tick, all slots in the same six launches.
 //
-// Each request is solved by FP32 CG (FP64 dot products) with FP64 iterative
-// refinement, exactly as the single-solve mixed path does, but on per-slot
+// A mixed request is solved by FP32 CG (FP64 dot products) with FP64
+// iterative refinement, exactly as the single-solve mixed path does; an
+// FP64 request runs the same phases with an FP64 inner CG whose stop test
+// is the final one (||r|| <= tau ||b||), so with x0 = 0 it is plain CG and
+// the outer step only confirms the true residual.  Both run on per-slot
 // 256-row tiles: the launch walks a global tile list (slot, local tile), and
 // every per-slot reduction is over per-TILE partials summed in a fixed order
 // by one workgroup per slot.  Tile boundaries and reduction trees depend only
@@ -10,7 +13,8 @@
 // in any mix of other requests.
 //
 // Phases: OUTER (r = b - A x in FP64; r32 = p32 = fl32(r), d = 0) ->
-// INNER (CG on A32 d = r32 until ||r_in|| <= tau_in ||r32||) -> CORRECT
+// INNER (CG on A32 d = r32 until ||r_in|| <= tau_in ||r32||; FP64 requests:
+// CG on A d = r until ||r_in|| <= tau ||b||) -> CORRECT
 // (x += d) -> OUTER ... -> DONE when ||b - A x|| <= tau ||b|| (or a cap).
 // Scalars a launch writes are read only by later launches; the phase a tick
 // acts on is committed by the last launch of the tick.
@@ -67,7 +71,8 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
         const int64_t r1 = min(r0 + static_cast<int64_t>(kTileRows), D.n);
         const int64_t row = r0 + threadIdx.x;
         bool has = false;
-        if (ph == PH_INNER && S.stop_in == STOP_RUNNING) {
+        const bool inner = ph == PH_INNER && S.stop_in == STOP_RUNNING;
+        if (inner && !D.fp64) {
             const float s = tile_row_sum<float, float, float>(D.rp, D.ci, D.va32, D.nnz, D.p, r0, r1, lv, lc, has, D.stage,
                                                               B.nt);
             double v[1] = {0.0};
@@ -76,22 +81,39 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(BatchDev B) {
                 v[0] = static_cast<double>(D.p[row]) * static_cast<double>(s);
             }
             block_reduce_store<1>(v, D.part + PART_PQ * D.tiles + te.y, D.tiles);
-        } else if (ph == PH_OUTER) {
-            const double s = tile_row_sum<double, double, double>(D.rp, D.ci, D.va64, D.nnz, D.x, r0, r1, lv, lc, has,
-                                                                  D.stage, B.nt);
-            double v[3] = {0.0, 0.0, 0.0};
-            if (has) {
-                const double bi = D.b[row];
-                const double ri = bi - s;
-                const float r32 = static_cast<float>(ri);
-                D.r[row] = r32;
-                D.p[row] = r32;
-                D.d[row] = 0.0f;
-                v[0] = ri * ri;
-                v[1] = static_cast<double>(r32) * static_cast<double>(r32);
-                v[2] = bi * bi;
+        } else if (inner || ph == PH_OUTER) {
+            // FP64 products: an FP64 request's q = A p, or any request's A x
+            const double s = tile_row_sum<double, double, double>(D.rp, D.ci, D.va64, D.nnz, inner ? D.p64 : D.x, r0,
+                                                                  r1, lv, lc, has, D.stage, B.nt);
+            if (inner) {
+                double v[1] = {0.0};
+                if (has) {
+                    D.q64[row] = s;
+                    v[0] = D.p64[row] * s;
+                }
+                block_reduce_store<1>(v, D.part + PART_PQ * D.tiles + te.y, D.tiles);
+            } else {
+                double v[3] = {0.0, 0.0, 0.0};
+                if (has) {
+                    const double bi = D.b[row];
+                    const double ri = bi - s;
+                    if (D.fp64) {
+                        D.r64[row] = ri;
+                        D.p64[row] = ri;
+                        D.d64[row] = 0.0;
+                        v[1] = ri * ri;
+                    } else {
+                        const float r32 = static_cast<float>(ri);
+                        D.r[row] = r32;
+                        D.p[row] = r32;
+                        D.d[row] = 0.0f;
+                        v[1] = static_cast<double>(r32) * static_cast<double>(r32);
+                    }
+                    v[0] = ri * ri;
+                    v[2] = bi * bi;
+                }
+                block_reduce_store<3>(v, D.part + PART_OUT * D.tiles + te.y, D.tiles);
             }
-            block_reduce_store<3>(v, D.part + PART_OUT * D.tiles + te.y, D.tiles);
         }
     }
 }
@@ -137,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_b_reduce_a(BatchDev B) {
                     S.next_phase = PH_DONE;
                 } else {
                     S.rho[0] = tot[1];
-                    S.thresh_in = D.tau_in * r32;
+                    S.thresh_in = D.fp64 ? D.tau * bn : D.tau_in * r32;
                     S.iter_in = 0;
                     S.stop_in = STOP_RUNNING;
                     S.next_phase = PH_INNER;
@@ -158,17 +180,25 @@ __global__ __launch_bounds__(kBlock) void k_b_update(BatchDev B) {
         const int64_t row = r0 + threadIdx.x;
         const bool has = row < D.n;
         if (ph == PH_INNER && S.stop_in == STOP_RUNNING) {
-            const float alpha = static_cast<float>(S.alpha);
             double v[1] = {0.0};
             if (has) {
-                D.d[row] = fmaf(alpha, D.p[row], D.d[row]);
-                const float ri = fmaf(-alpha, D.q[row], D.r[row]);
-                D.r[row] = ri;
-                v[0] = static_cast<double>(ri) * static_cast<double>(ri);
+                if (D.fp64) {
+                    const double alpha = S.alpha;
+                    D.d64[row] = fma(alpha, D.p64[row], D.d64[row]);
+                    const double ri = fma(-alpha, D.q64[row], D.r64[row]);
+                    D.r64[row] = ri;
+                    v[0] = ri * ri;
+                } else {
+                    const float alpha = static_cast<float>(S.alpha);
+                    D.d[row] = fmaf(alpha, D.p[row], D.d[row]);
+                    const float ri = fmaf(-alpha, D.q[row], D.r[row]);
+                    D.r[row] = ri;
+                    v[0] = static_cast<double>(ri) * static_cast<double>(ri);
+                }
             }
             block_reduce_store<1>(v, D.part + PART_RR * D.tiles + te.y, D.tiles);
         } else if (ph == PH_CORRECT) {
-            if (has) D.x[row] += static_cast<double>(D.d[row]);
+            if (has) D.x[row] += D.fp64 ? D.d64[row] : static_cast<double>(D.d[row]);
         } else if (ph == PH_ZEROX) {
             if (has) D.x[row] = 0.0;
         }
@@ -228,7 +258,9 @@ __global__ __launch_bounds__(kBlock) void k_b_pupdate(BatchDev B) {
         const SlotState &S = B.state[te.x];
         if (S.phase != PH_INNER || S.stop_in != STOP_RUNNING) continue;
         const int64_t row = static_cast<int64_t>(te.y) * kTileRows + threadIdx.x;
-        if (row < D.n) D.p[row] = fmaf(static_cast<float>(S.beta), D.p[row], D.r[row]);
+        if (row >= D.n) continue;
+        if (D.fp64) D.p64[row] = fma(S.beta, D.p64[row], D.r64[row]);
+        else D.p[row] = fmaf(static_cast<float>(S.beta), D.p[row], D.r[row]);
     }
 }
 

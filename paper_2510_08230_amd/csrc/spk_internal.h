@@ -164,7 +164,7 @@ namespace spk {
 enum Phase : int32_t {
     PH_FREE = 0,     // slot unused
     PH_OUTER = 1,    // refinement residual r = b - A x (FP64) this tick
-    PH_INNER = 2,    // FP32 CG iterations on A32 d = r32
+    PH_INNER = 2,    // CG iterations on A d = r (FP32 with FP64 dots, or FP64)
     PH_CORRECT = 3,  // x += d this tick
     PH_ZEROX = 4,    // b == 0: x = 0 this tick
     PH_DONE = 5      // finished; waiting for the host to retire it
@@ -181,11 +181,13 @@ struct SlotDesc {
     const float *va32;      // rounded copy (slot workspace)
     const double *b;
     double *x;
-    float *r, *p, *q, *d;   // slot workspace
-    double *part;           // slot workspace: kPartSites * tiles
+    float *r, *p, *q, *d;          // slot workspace of an FP32-inner request
+    double *r64, *p64, *q64, *d64; // slot workspace of an FP64 request
+    double *part;                  // slot workspace: kPartSites * tiles
     double tau, tau_in;
     int64_t max_iters, max_outer;
     int32_t stage;          // 1: values and columns 16-byte aligned, tiles staged in LDS by DMA
+    int32_t fp64;           // 1: the inner CG runs in FP64 on the caller's values (no FP32 copy)
 };
 
 // Device-resident per-slot scalars.

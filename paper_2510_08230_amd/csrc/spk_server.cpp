@@ -36,11 +36,14 @@ int64_t tiles_of(int64_t n) { return (n + spk::kTileRows - 1) / spk::kTileRows; 
 
 size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
-// Workspace one request needs: r, p, q, d (FP32, n each), the FP32 value copy
-// (nnz) and the per-tile partial sums.
-size_t request_bytes(int64_t n, int64_t nnz) {
-    const size_t vec = align256(sizeof(float) * static_cast<size_t>(std::max<int64_t>(n, 1)));
-    return 4 * vec + align256(sizeof(float) * static_cast<size_t>(std::max<int64_t>(nnz, 1))) +
+// Workspace one request needs: r, p, q, d (n each; FP32 for a mixed
+// request, FP64 for an FP64 one), the FP32 value copy (nnz; mixed only) and
+// the per-tile partial sums.
+size_t request_bytes(int64_t n, int64_t nnz, bool fp64) {
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const size_t vec = align256(es * static_cast<size_t>(std::max<int64_t>(n, 1)));
+    const size_t copy = fp64 ? 0 : align256(sizeof(float) * static_cast<size_t>(std::max<int64_t>(nnz, 1)));
+    return 4 * vec + copy +
            align256(sizeof(double) * spk::kPartSites * static_cast<size_t>(std::max<int64_t>(tiles_of(n), 1)));
 }
 
@@ -52,6 +55,7 @@ struct Request {
     int64_t submit_ns = 0;
     double tau = 0.0, tau_in = 0.0;   // this request's stop tests
     int64_t max_iters = 0, max_outer = 0;
+    bool fp64 = false;                 // SPK_PREC_FP64 (else SPK_PREC_MIXED_FP32)
 };
 
 // The LDS tiles stage a tile's values and columns with 16-byte DMA loads,
@@ -60,7 +64,8 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 // Configuration checks shared by create (server default) and submit (per request).
 bool cfg_supported(const spk_solver_cfg &c) {
-    return c.solver == SPK_SOLVER_CG && c.precond == SPK_PRECOND_NONE && c.precision == SPK_PREC_MIXED_FP32;
+    return c.solver == SPK_SOLVER_CG && c.precond == SPK_PRECOND_NONE &&
+           (c.precision == SPK_PREC_MIXED_FP32 || c.precision == SPK_PREC_FP64);
 }
 bool cfg_valid(const spk_solver_cfg &c) {
     return c.reduction_factor >= 0.0 && c.inner_reduction > 0.0 && c.inner_reduction < 1.0 && c.max_iters >= 0 &&
@@ -174,7 +179,7 @@ bool admit(spk_server srv) {
     while (!srv->waiting.empty()) {
         Request &r = srv->waiting.front();
         const int64_t n = r.A.n_rows;
-        const size_t bytes = request_bytes(n, r.A.nnz);
+        const size_t bytes = request_bytes(n, r.A.nnz, r.fp64);
         const int64_t t = tiles_of(n);
         int free_slot = -1;
         for (int i = 0; i < srv->max_slots; ++i)
@@ -201,19 +206,29 @@ bool admit(spk_server srv) {
             cur += align256(b);
             return p;
         };
-        const size_t vb = sizeof(float) * static_cast<size_t>(std::max<int64_t>(n, 1));
+        const size_t nn = static_cast<size_t>(std::max<int64_t>(n, 1));
         spk::SlotDesc &D = srv->h_desc[free_slot];
+        std::memset(&D, 0, sizeof(D));
         D.n = n;
         D.nnz = req.A.nnz;
         D.tiles = t;
         D.rp = static_cast<const int32_t *>(req.A.row_ptr);
         D.ci = static_cast<const int32_t *>(req.A.col_idx);
         D.va64 = static_cast<const double *>(req.A.values);
-        D.r = reinterpret_cast<float *>(carve(vb));
-        D.p = reinterpret_cast<float *>(carve(vb));
-        D.q = reinterpret_cast<float *>(carve(vb));
-        D.d = reinterpret_cast<float *>(carve(vb));
-        float *va32 = reinterpret_cast<float *>(carve(sizeof(float) * static_cast<size_t>(std::max<int64_t>(req.A.nnz, 1))));
+        D.fp64 = req.fp64 ? 1 : 0;
+        float *va32 = nullptr;
+        if (req.fp64) {
+            D.r64 = reinterpret_cast<double *>(carve(sizeof(double) * nn));
+            D.p64 = reinterpret_cast<double *>(carve(sizeof(double) * nn));
+            D.q64 = reinterpret_cast<double *>(carve(sizeof(double) * nn));
+            D.d64 = reinterpret_cast<double *>(carve(sizeof(double) * nn));
+        } else {
+            D.r = reinterpret_cast<float *>(carve(sizeof(float) * nn));
+            D.p = reinterpret_cast<float *>(carve(sizeof(float) * nn));
+            D.q = reinterpret_cast<float *>(carve(sizeof(float) * nn));
+            D.d = reinterpret_cast<float *>(carve(sizeof(float) * nn));
+            va32 = reinterpret_cast<float *>(carve(sizeof(float) * static_cast<size_t>(std::max<int64_t>(req.A.nnz, 1))));
+        }
         D.va32 = va32;
         D.part = reinterpret_cast<double *>(carve(sizeof(double) * spk::kPartSites * static_cast<size_t>(std::max<int64_t>(t, 1))));
         D.b = req.b;
@@ -230,7 +245,7 @@ bool admit(spk_server srv) {
         S.phase = spk::PH_OUTER;
         S.next_phase = spk::PH_OUTER;
         bool ok = true;
-        if (req.A.nnz > 0)
+        if (req.A.nnz > 0 && !req.fp64)
             ok = hip_ok(srv, spk::launch_round_f32(req.A.nnz, D.va64, va32, srv->num_cu * 4, srv->stream), "round");
         ok = ok && hip_ok(srv, hipMemcpyAsync(srv->d_desc + free_slot, &D, sizeof(D), hipMemcpyHostToDevice, srv->stream),
                           "desc upload");
@@ -391,7 +406,13 @@ void worker_main(spk_server srv) {
 
 extern "C" {
 
-size_t spk_server_request_bytes(int64_t n, int64_t nnz) { return request_bytes(n, nnz); }
+size_t spk_server_request_bytes(int64_t n, int64_t nnz) { return request_bytes(n, nnz, false); }
+
+size_t spk_server_request_bytes_prec(int32_t precision, int64_t n, int64_t nnz) {
+    if (precision == SPK_PREC_FP64) return request_bytes(n, nnz, true);
+    if (precision == SPK_PREC_MIXED_FP32) return request_bytes(n, nnz, false);
+    return 0;
+}
 
 spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_slots, const spk_solver_cfg *cfg,
                              spk_server *out) {
@@ -482,7 +503,8 @@ spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b
     if (A->n_rows != A->n_cols || A->n_rows < 1 || A->nnz < 0) return SPK_ERR_INVALID_ARG;
     if (A->ptr_type != SPK_I32 || A->idx_type != SPK_I32 || A->val_type != SPK_F64) return SPK_ERR_UNSUPPORTED;
     if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values)) || !b || !x) return SPK_ERR_INVALID_ARG;
-    if (request_bytes(A->n_rows, A->nnz) > srv->budget || tiles_of(A->n_rows) > srv->cap_tiles)
+    const bool fp64 = c.precision == SPK_PREC_FP64;
+    if (request_bytes(A->n_rows, A->nnz, fp64) > srv->budget || tiles_of(A->n_rows) > srv->cap_tiles)
         return SPK_ERR_BUDGET;
     if (tiles_of(A->n_rows) > INT32_MAX) return SPK_ERR_UNSUPPORTED;
     Request r;
@@ -494,6 +516,7 @@ spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b
     r.tau_in = c.inner_reduction;
     r.max_iters = c.max_iters;
     r.max_outer = c.max_outer;
+    r.fp64 = fp64;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stopping) return SPK_ERR_INVALID_ARG;

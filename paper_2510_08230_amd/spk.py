@@ -116,6 +116,7 @@ _SIGS = {
     "spk_solve_noalloc": (ctypes.c_int, [_vp, _P(Csr), _P(SolverCfg), _vp, _vp, _P(Log)]),
     "spk_noalloc_max_rows": (_i64, []),
     "spk_server_request_bytes": (_sz, [_i64, _i64]),
+    "spk_server_request_bytes_prec": (_sz, [_i32, _i64, _i64]),
     "spk_server_create": (ctypes.c_int, [_vp, _sz, _i32, _P(SolverCfg), _P(_vp)]),
     "spk_server_submit": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(ctypes.c_uint64)]),
     "spk_server_submit_cfg": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(SolverCfg), _P(ctypes.c_uint64)]),
@@ -369,6 +370,10 @@ class Server:
 
 def spk_server_request_bytes(n: int, nnz: int) -> int:
     return int(_lib.spk_server_request_bytes(int(n), int(nnz)))
+
+
+def spk_server_request_bytes_prec(precision: int, n: int, nnz: int) -> int:
+    return int(_lib.spk_server_request_bytes_prec(int(precision), int(n), int(nnz)))
 
 
 def _server_check(status, srv):

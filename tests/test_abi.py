@@ -132,3 +132,18 @@ def test_server_request_bytes_formula():
         tiles = (n + 255) // 256
         want = 4 * al(4 * n) + al(4 * max(nnz, 1)) + al(8 * 5 * max(tiles, 1))
         assert spk.spk_server_request_bytes(n, nnz) == want
+
+
+def test_server_request_bytes_by_precision():
+    """FP64 requests: 4 FP64 vectors and the partials, no value copy; the
+    mixed figure is spk_server_request_bytes'; other precisions: 0."""
+    from paper_2510_08230_amd import spk
+
+    def al(b):
+        return (b + 255) // 256 * 256
+    for n, nnz in [(1, 1), (1000, 7000), (256, 1792), (257, 0), (1_000_000, 7_000_000)]:
+        tiles = (n + 255) // 256
+        want = 4 * al(8 * n) + al(8 * 5 * max(tiles, 1))
+        assert spk.spk_server_request_bytes_prec(spk.PREC_FP64, n, nnz) == want
+        assert spk.spk_server_request_bytes_prec(spk.PREC_MIXED_FP32, n, nnz) == spk.spk_server_request_bytes(n, nnz)
+        assert spk.spk_server_request_bytes_prec(spk.PREC_MIXED_BF16, n, nnz) == 0

@@ -4,7 +4,10 @@ Each request is a randsym system solved by FP32 CG with FP64 dot products
 and FP64 iterative refinement to ||b - A x|| <= 1e-12 ||b||; every result is
 checked against the FP64 oracle's solution (1e-10 relative, the serving
 configuration's bound; derivation as for the single mixed solve: kappa_G <= 13),
-and a request's solution is bitwise the same alone and in a mix."""
+and a request's solution is bitwise the same alone and in a mix.  FP64
+requests (plain CG per request, the true residual confirmed at the end) are
+held to the single FP64 solve's bar: the oracle's iteration count +-1 and
+x within 1e-12 of its x at tau = 1e-14."""
 import time
 
 import numpy as np
@@ -41,13 +44,17 @@ def make_request(spk, n, seed):
     return A, b, M, to_dev(b), torch.zeros(n, dtype=torch.float64, device=DEV)
 
 
-def server(spk, ctx, budget=1 << 30, slots=64):
+def server_cfg(spk, precision=None, tau=TAU):
     cfg = spk.spk_solver_cfg_default()
-    cfg.precision = spk.PREC_MIXED_FP32
-    cfg.reduction_factor = TAU
+    cfg.precision = spk.PREC_MIXED_FP32 if precision is None else precision
+    cfg.reduction_factor = tau
     cfg.inner_reduction = 1e-4
     cfg.max_iters = 20000
-    return spk.spk_server_create(ctx, budget, slots, cfg)
+    return cfg
+
+
+def server(spk, ctx, budget=1 << 30, slots=64, precision=None, tau=TAU):
+    return spk.spk_server_create(ctx, budget, slots, server_cfg(spk, precision, tau))
 
 
 def wait_all(spk, srv, tickets, timeout=60.0):
@@ -211,7 +218,8 @@ def test_per_request_configuration(spk, ctx):
     t0 = spk.spk_server_submit(srv, M, bd, x)
     t1 = spk.spk_server_submit(srv, M, bd, x_loose, loose)
     t2 = spk.spk_server_submit(srv, M, bd, x_cap, cap)
-    bad = spk.spk_solver_cfg_default()       # FP64 precision: not what the server runs
+    bad = spk.spk_solver_cfg_default()       # BF16 inner precision: not what the server runs
+    bad.precision = spk.PREC_MIXED_BF16
     with pytest.raises(spk.SpkError) as e:
         spk.spk_server_submit(srv, M, bd, torch.zeros_like(x), bad)
     assert e.value.status == spk.ERR_UNSUPPORTED
@@ -224,6 +232,82 @@ def test_per_request_configuration(spk, ctx):
     assert res[t1][1].stop_reason == spk.STOP_CONVERGED and r1 <= 1e-6 * nb * 1.01
     assert res[t1][1].iterations < res[t0][1].iterations
     assert res[t2][1].stop_reason == spk.STOP_MAX_ITERS and res[t2][1].outer_iterations == 1
+
+
+def test_fp64_requests_match_plain_cg(spk, ctx):
+    """FP64 requests from x0 = 0 at tau = 1e-14 (the C2 stop test): each is
+    plain CG, so its iteration count is the oracle's +-1 and x is within
+    1e-12 of the oracle's; a restart from the true residual (outer
+    iterations 2) may add iterations."""
+    sizes = [3000, 777, 40000, 200000]
+    reqs = [make_request(spk, n, 400 + i) for i, n in enumerate(sizes)]
+    srv = server(spk, ctx, precision=spk.PREC_FP64, tau=1e-14)
+    tickets = [spk.spk_server_submit(srv, M, bd, x) for (_, _, M, bd, x) in reqs]
+    res = wait_all(spk, srv, tickets)
+    stats = spk.spk_server_get_stats(srv)
+    spk.spk_server_destroy(srv)
+    assert stats["completed"] == len(sizes)
+    for (A, b, _, _, x), tk in zip(reqs, tickets):
+        st, log, _ = res[tk]
+        xo, ro, _ = oracle.cg(A, b, tau=1e-14, max_iters=5000)
+        print("n %d: %d iterations, %d outer (oracle %d)" % (A.n_rows, log.iterations, log.outer_iterations,
+                                                            ro.iterations))
+        assert st == spk.OK and log.stop_reason == spk.STOP_CONVERGED
+        assert log.outer_iterations in (1, 2)
+        if log.outer_iterations == 1:
+            assert abs(log.iterations - ro.iterations) <= 1
+        xg = x.cpu().numpy()
+        assert rel(xg, xo) <= 1e-12
+        assert np.linalg.norm(oracle.residual(A, b, xg)) <= 1e-14 * np.linalg.norm(b) * 1.01
+        assert log.true_resnorm <= 1e-14 * np.linalg.norm(b) * 1.01
+
+
+def test_precisions_share_a_server(spk, ctx):
+    """FP64 and mixed requests in one server (per-request precision): each
+    result is bitwise the one the same request gets alone."""
+    sizes = [3000, 40000, 12345, 65536]
+    fp64 = server_cfg(spk, spk.PREC_FP64)
+    mixed = server_cfg(spk)
+    plan = [(n, 500 + i, fp64 if i % 2 == 0 else mixed) for i, n in enumerate(sizes)]
+    plan += [(n, 600 + i, mixed if i % 2 == 0 else fp64) for i, n in enumerate(sizes)]
+    reqs = [make_request(spk, n, seed) for n, seed, _ in plan]
+    alone = []
+    for (_, _, M, bd, x), (_, _, cfg) in zip(reqs, plan):
+        srv = server(spk, ctx)
+        t = spk.spk_server_submit(srv, M, bd, x, cfg)
+        r = wait_all(spk, srv, [t])
+        spk.spk_server_destroy(srv)
+        assert r[t][0] == spk.OK and r[t][1].stop_reason == spk.STOP_CONVERGED
+        alone.append(x.cpu().numpy().copy())
+        x.zero_()
+    srv = server(spk, ctx)
+    tickets = [spk.spk_server_submit(srv, M, bd, x, cfg) for (_, _, M, bd, x), (_, _, cfg) in zip(reqs, plan)]
+    res = wait_all(spk, srv, tickets)
+    spk.spk_server_destroy(srv)
+    for (A, b, _, _, x), tk, xa in zip(reqs, tickets, alone):
+        assert res[tk][0] == spk.OK and res[tk][1].stop_reason == spk.STOP_CONVERGED
+        xg = x.cpu().numpy()
+        assert np.array_equal(xg.view(np.uint64), xa.view(np.uint64))
+        check_oracle(A, b, xg)
+
+
+def test_fp64_budget_accounting(spk, ctx):
+    """FP64 requests are charged their own workspace (4 FP64 vectors, no
+    value copy) against the budget."""
+    sizes = [20000, 30000, 25000, 22000]
+    reqs = [make_request(spk, n, 700 + i) for i, n in enumerate(sizes)]
+    per = [spk.spk_server_request_bytes_prec(spk.PREC_FP64, n, int(r[0].nnz)) for n, r in zip(sizes, reqs)]
+    budget = max(per) + min(per) // 2       # one request at a time
+    srv = server(spk, ctx, budget=budget, slots=8, precision=spk.PREC_FP64)
+    tickets = [spk.spk_server_submit(srv, M, bd, x) for (_, _, M, bd, x) in reqs]
+    res = wait_all(spk, srv, tickets)
+    stats = spk.spk_server_get_stats(srv)
+    spk.spk_server_destroy(srv)
+    assert stats["completed"] == len(sizes) and stats["peak_slots"] == 1
+    assert stats["peak_bytes"] == max(per) and stats["peak_device_bytes"] <= budget
+    for (A, b, _, _, x), tk in zip(reqs, tickets):
+        assert res[tk][0] == spk.OK
+        check_oracle(A, b, x.cpu().numpy())
 
 
 def test_full_serving_mix(spk, ctx):
