@@ -447,6 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, const SolveState *
 }
 
 // ------------------------------------------------------------------ structure kernels
+constexpr int kValidateUnroll = 4;
+
 template <typename P, typename I>
 __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                                      const P *__restrict__ rp, const I *__restrict__ ci,
@@ -458,29 +460,64 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n_rows, int64_t n_c
         if (rp[0] != 0) f |= VFLAG_BAD_FIRST;
         if (static_cast<int64_t>(rp[n_rows]) != nnz) f |= VFLAG_BAD_LAST;
     }
+    // Both walks take kValidateUnroll strides per round with every load of
+    // the round issued before the first check, so each lane keeps that many
+    // loads in flight (one at a time left the pass latency-bound).
     unsigned longest = 0;   // longest row (entries, clamped to 2^32 - 1), for the long-row path of the SpMV
-    for (int64_t i = gid; i < n_rows; i += stride) {
-        const int64_t len = static_cast<int64_t>(rp[i + 1]) - static_cast<int64_t>(rp[i]);
-        if (len < 0) f |= VFLAG_DECREASING;
-        else longest = max(longest, len > 0xffffffffll ? 0xffffffffu : static_cast<unsigned>(len));
+    for (int64_t i0 = gid; i0 < n_rows; i0 += kValidateUnroll * stride) {
+        int64_t lo[kValidateUnroll], hi[kValidateUnroll];
+#pragma unroll
+        for (int u = 0; u < kValidateUnroll; ++u) {
+            const int64_t i = i0 + u * stride < n_rows ? i0 + u * stride : n_rows - 1;
+            lo[u] = static_cast<int64_t>(rp[i]);
+            hi[u] = static_cast<int64_t>(rp[i + 1]);
+        }
+#pragma unroll
+        for (int u = 0; u < kValidateUnroll; ++u) {
+            if (i0 + u * stride >= n_rows) continue;
+            const int64_t len = hi[u] - lo[u];
+            if (len < 0) f |= VFLAG_DECREASING;
+            else longest = max(longest, len > 0xffffffffll ? 0xffffffffu : static_cast<unsigned>(len));
+        }
     }
+    // one atomic per workgroup at most: every wave's maximum goes through LDS,
+    // and a maximum the flag word already holds (it only grows) is not sent
+    // (same-address atomics from every wave serialised the pass)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) longest = max(longest, static_cast<unsigned>(__shfl_xor(longest, off, 64)));
-    if ((threadIdx.x & 63) == 0 && longest > 0) atomicMax(flags + 1, longest);
+    __shared__ unsigned wave_longest[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wave_longest[threadIdx.x >> 6] = longest;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = wave_longest[0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, wave_longest[w]);
+        if (m > __hip_atomic_load(flags + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(flags + 1, m);
+    }
     // column indices: 16-byte loads when aligned, element loads for the tail
     constexpr int EPC = 16 / sizeof(I);
     int64_t done = 0;
     if ((reinterpret_cast<uintptr_t>(ci) & 15) == 0) {
         const int64_t nch = nnz / EPC;
         const u32x4 *c16 = reinterpret_cast<const u32x4 *>(ci);
-        for (int64_t g = gid; g < nch; g += stride) {
-            const u32x4 v = c16[g];
-            I e[EPC];
-            __builtin_memcpy(e, &v, 16);
+        for (int64_t g0 = gid; g0 < nch; g0 += kValidateUnroll * stride) {
+            // chunks past the end re-read the last one (checked, not used)
+            u32x4 v[kValidateUnroll];
 #pragma unroll
-            for (int j = 0; j < EPC; ++j) {
-                const int64_t c = static_cast<int64_t>(e[j]);
-                if (c < 0 || c >= n_cols) f |= VFLAG_BAD_COLUMN;
+            for (int u = 0; u < kValidateUnroll; ++u) {
+                const int64_t g = g0 + u * stride;
+                v[u] = c16[g < nch ? g : nch - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kValidateUnroll; ++u) {
+                if (g0 + u * stride >= nch) continue;
+                I e[EPC];
+                __builtin_memcpy(e, &v[u], 16);
+#pragma unroll
+                for (int j = 0; j < EPC; ++j) {
+                    const int64_t c = static_cast<int64_t>(e[j]);
+                    if (c < 0 || c >= n_cols) f |= VFLAG_BAD_COLUMN;
+                }
             }
         }
         done = nch * EPC;
@@ -541,50 +578,85 @@ __device__ __forceinline__ int code_insert(long long *set, int bits, long long d
     return -1;
 }
 
-// The entries of the 256-row tile at row r0, for the code kernels.  When the
-// tile's entries fit the LDS row map (the usual case), load() maps each entry
-// to its row and gives this thread the offsets of entries s + threadIdx.x +
-// j * kBlock (j < kCodeBatch; invalid past e), all loads issued before any
-// is used; otherwise mapped is false and each thread walks its own row
-// [a, b).  Every thread of the workgroup must call load() and done().
+// The entries of the 256-row tile at row r0, for the code kernels.
+// CodeRows::load() reads the tile's row pointers (no LDS, no barrier: a walk
+// issues it for its next tile before it works on the current one).
+// CodeTile::cols() then, when the tile's entries fit the LDS row map (the
+// usual case), issues the loads of entries s + threadIdx.x + j * kBlock
+// (j < kCodeBatch; invalid past e), maps each entry to its row while they
+// are in flight, and gives this thread those entries' offsets; otherwise
+// mapped is false and each thread walks its own row [a, b).  Every thread
+// of the workgroup must call cols() and done().  (Keeping the next tile's
+// indices in flight as well cost a wave per SIMD and was slower.)
 constexpr int kCodeBatch = kStreamCap / kBlock;
+
+// Workgroup barrier for LDS only: LDS writes before it are seen by LDS
+// reads after it, and global loads and stores still in flight stay in
+// flight (__syncthreads waits for those too, which would drain the next
+// tile's prefetched row pointers and this tile's code stores every tile).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The row pointers stay in their stored type until cols() (a widening right
+// after the load would wait for it there).
+template <typename P>
+struct CodeRows {
+    P s, e, a, b;
+    int64_t r0;
+    bool has;   // this thread's row is in the tile (else cols() clears a and b)
+    __device__ __forceinline__ void load(int64_t n_rows, const P *__restrict__ rp, int64_t tile_r0) {
+        r0 = tile_r0;
+        const int64_t r1 = r0 + kTileRows < n_rows ? r0 + kTileRows : n_rows;
+        s = rp[r0];
+        e = rp[r1];
+        const int64_t row = r0 + threadIdx.x;
+        has = row < r1;
+        const int64_t rr = has ? row : r1 - 1;   // unconditional loads (see cols())
+        a = rp[rr];
+        b = rp[rr + 1];
+    }
+};
 
 template <typename P, typename I>
 struct CodeTile {
-    int64_t s, e, a, b, row;
+    int64_t s, e, a, b, row, r0;
     bool mapped;
     int64_t d[kCodeBatch];
-    __device__ __forceinline__ void load(int64_t n_rows, const P *__restrict__ rp, const I *__restrict__ ci,
-                                         int64_t r0, unsigned short *row_of) {
-        const int64_t r1 = r0 + kTileRows < n_rows ? r0 + kTileRows : n_rows;
-        s = static_cast<int64_t>(rp[r0]);
-        e = static_cast<int64_t>(rp[r1]);
+    __device__ __forceinline__ void cols(const CodeRows<P> &r, const I *__restrict__ ci, unsigned short *row_of) {
+        r0 = r.r0;
         row = r0 + threadIdx.x;
-        a = b = 0;
-        if (row < r1) {
-            a = static_cast<int64_t>(rp[row]);
-            b = static_cast<int64_t>(rp[row + 1]);
-        }
+        s = static_cast<int64_t>(r.s);
+        e = static_cast<int64_t>(r.e);
+        a = r.has ? static_cast<int64_t>(r.a) : 0;
+        b = r.has ? static_cast<int64_t>(r.b) : 0;
         mapped = e - s <= kStreamCap;   // uniform
         if (!mapped) return;
-        for (int64_t k = a; k < b; ++k) row_of[k - s] = static_cast<unsigned short>(threadIdx.x);
-        __syncthreads();
-        int64_t c[kCodeBatch];
+        // every lane loads (entries past e re-read the tile's last one and
+        // are not used): a load under a branch is waited for at the join
+        I c[kCodeBatch];
+        const int64_t last = e > s ? e - 1 : s;
+        if (e > s) {   // uniform
 #pragma unroll
-        for (int j = 0; j < kCodeBatch; ++j) {
-            const int64_t k = s + threadIdx.x + j * kBlock;
-            c[j] = k < e ? static_cast<int64_t>(ci[k]) : 0;
+            for (int j = 0; j < kCodeBatch; ++j) {
+                const int64_t k = s + threadIdx.x + j * kBlock;
+                c[j] = ci[k < last ? k : last];
+            }
         }
+        for (int64_t k = a; k < b; ++k) row_of[k - s] = static_cast<unsigned short>(threadIdx.x);
+        lds_barrier();
 #pragma unroll
         for (int j = 0; j < kCodeBatch; ++j) {
             const int64_t k = s + threadIdx.x + j * kBlock;
-            d[j] = k < e ? c[j] - (r0 + row_of[k - s]) : 0;
+            d[j] = k < e ? static_cast<int64_t>(c[j]) - (r0 + row_of[k - s]) : 0;
         }
     }
     __device__ __forceinline__ bool valid(int j) const { return s + threadIdx.x + j * kBlock < e; }
     __device__ __forceinline__ int64_t entry(int j) const { return s + threadIdx.x + j * kBlock; }
     __device__ __forceinline__ void done() const {
-        if (mapped) __syncthreads();   // row map free for the next tile
+        if (mapped) lds_barrier();   // row map free for the next tile
     }
 };
 
@@ -612,9 +684,12 @@ __global__ __launch_bounds__(kBlock) void k_code_collect(int64_t n_rows, const P
         const int r = code_insert(set, 9, d);
         if (r < 0 || (r > 0 && atomicAdd(&used, 1u) >= static_cast<unsigned>(kCodeDict))) over = 1;
     };
+    CodeRows<P> nx;   // the next tile's row pointers, in flight while this one is worked on
+    if (blockIdx.x < U) nx.load(n_rows, rp, code_tile(blockIdx.x, T, step) * kTileRows);
     for (int64_t u = blockIdx.x; u < U; u += gridDim.x) {
         CodeTile<P, I> t;
-        t.load(n_rows, rp, ci, code_tile(u, T, step) * kTileRows, row_of);
+        t.cols(nx, ci, row_of);
+        if (u + gridDim.x < U) nx.load(n_rows, rp, code_tile(u + gridDim.x, T, step) * kTileRows);
         if (t.mapped) {
 #pragma unroll
             for (int j = 0; j < kCodeBatch; ++j)
@@ -623,9 +698,9 @@ __global__ __launch_bounds__(kBlock) void k_code_collect(int64_t n_rows, const P
             for (int64_t k = t.a; k < t.b && !over; ++k) add(static_cast<long long>(ci[k]) - t.row);
         }
         t.done();
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x == 0 && words[1]) over = 1;   // another workgroup already overflowed
-        __syncthreads();
+        lds_barrier();
         if (over) break;                               // uniform: read after the barrier
     }
     if (over) {
@@ -710,9 +785,12 @@ __global__ __launch_bounds__(kBlock) void k_code_encode(int64_t n_rows, const P 
     __syncthreads();
     unsigned bad = 0;
     const int64_t T = (n_rows + kTileRows - 1) / kTileRows;
+    CodeRows<P> nx;   // the next tile's row pointers, in flight while this one is worked on
+    if (blockIdx.x < T) nx.load(n_rows, rp, static_cast<int64_t>(blockIdx.x) * kTileRows);
     for (int64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
         CodeTile<P, I> t;
-        t.load(n_rows, rp, ci, tile * kTileRows, row_of);
+        t.cols(nx, ci, row_of);
+        if (tile + gridDim.x < T) nx.load(n_rows, rp, (tile + gridDim.x) * kTileRows);
         if (t.mapped) {
 #pragma unroll
             for (int j = 0; j < kCodeBatch; ++j) {
