@@ -95,29 +95,40 @@ struct TileIter {
 // int64 first entry, then per row a uint16 offset from it.
 struct RowPack {};
 
-// Bounds of one row tile: its first row, its entry range [s, e) and this
-// thread's row range [a, b) (empty past the last row).
+// Bounds of one row tile: its first row, its entry range [first(), end())
+// and this thread's row range [lo(), hi()) (empty past the last row).
+// load() issues every load unconditionally (a thread past the tile's last
+// row re-reads that row's bounds) and keeps the loaded values as stored, so
+// a load for the next tile stays in flight until the bounds are used: a
+// load under a branch, or a value combined right after its load, is waited
+// for at once.
 template <typename P>
 struct TileMeta {
     int64_t r0;
     P s, e, a, b;
+    bool has;
     __device__ __forceinline__ void load(const P *__restrict__ rp, int64_t n, int64_t tile) {
         r0 = tile * kTileRows;
         const int64_t r1 = r0 + kTileRows < n ? r0 + kTileRows : n;
         s = rp[r0];
         e = rp[r1];
         const int64_t row = r0 + threadIdx.x;
-        a = b = 0;
-        if (row < r1) {
-            a = rp[row];
-            b = rp[row + 1];
-        }
+        has = row < r1;
+        const int64_t rr = has ? row : r1 - 1;
+        a = rp[rr];
+        b = rp[rr + 1];
     }
+    __device__ __forceinline__ int64_t first() const { return static_cast<int64_t>(s); }
+    __device__ __forceinline__ int64_t end() const { return static_cast<int64_t>(e); }
+    __device__ __forceinline__ int64_t lo() const { return has ? static_cast<int64_t>(a) : 0; }
+    __device__ __forceinline__ int64_t hi() const { return has ? static_cast<int64_t>(b) : 0; }
 };
 
 template <>
 struct TileMeta<RowPack> {
-    int64_t r0, s, e, a, b;
+    int64_t r0, s, e;
+    uint16_t ra, rb;
+    bool has, tail;   // tail: this thread's row is the tile's last (its end is e)
     __device__ __forceinline__ void load(const RowPack *__restrict__ rp, int64_t n, int64_t tile) {
         const int64_t *tb = reinterpret_cast<const int64_t *>(rp);
         const uint16_t *ro = reinterpret_cast<const uint16_t *>(tb + (n + kTileRows - 1) / kTileRows + 1);
@@ -126,13 +137,27 @@ struct TileMeta<RowPack> {
         s = tb[tile];
         e = tb[tile + 1];
         const int64_t row = r0 + threadIdx.x;
-        a = b = 0;
-        if (row < r1) {
-            a = s + ro[row];
-            b = row + 1 < r1 ? s + ro[row + 1] : e;
-        }
+        has = row < r1;
+        const int64_t rr = has ? row : r1 - 1;
+        tail = rr + 1 >= r1;
+        ra = ro[rr];
+        rb = ro[tail ? rr : rr + 1];
     }
+    __device__ __forceinline__ int64_t first() const { return s; }
+    __device__ __forceinline__ int64_t end() const { return e; }
+    __device__ __forceinline__ int64_t lo() const { return has ? s + ra : 0; }
+    __device__ __forceinline__ int64_t hi() const { return has ? (tail ? e : s + rb) : 0; }
 };
+
+// Workgroup barrier for LDS only: LDS writes before it are seen by LDS
+// reads after it, and global loads and stores still in flight stay in
+// flight (__syncthreads also waits for those: a tile's result stores or the
+// next tile's prefetched loads would then be drained at every tile).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Block-level fixed-order reduction of NV doubles; thread 0 stores the
 // workgroup's partials at partials[j * kMaxGrid + blockIdx.x].

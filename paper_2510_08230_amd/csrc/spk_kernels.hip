@@ -79,12 +79,15 @@ struct EpiPq {
     double *part;
     double acc;
     __device__ bool skip() const { return st->stop != STOP_RUNNING; }
+    __device__ T pre(int64_t i) const { return p[i]; }
     template <class C>
-    __device__ void row(int64_t i, C s) {
+    __device__ void row(int64_t i, C s, T pi) {
         const T qi = static_cast<T>(s);
         q[i] = qi;
-        acc = fma(static_cast<double>(p[i]), static_cast<double>(qi), acc);
+        acc = fma(static_cast<double>(pi), static_cast<double>(qi), acc);
     }
+    template <class C>
+    __device__ void row(int64_t i, C s) { row(i, s, p[i]); }
     __device__ void finish() {
         double v[1] = {acc};
         block_partial<1>(v, part);
@@ -589,16 +592,6 @@ __device__ __forceinline__ int code_insert(long long *set, int bits, long long d
 // of the workgroup must call cols() and done().  (Keeping the next tile's
 // indices in flight as well cost a wave per SIMD and was slower.)
 constexpr int kCodeBatch = kStreamCap / kBlock;
-
-// Workgroup barrier for LDS only: LDS writes before it are seen by LDS
-// reads after it, and global loads and stores still in flight stay in
-// flight (__syncthreads waits for those too, which would drain the next
-// tile's prefetched row pointers and this tile's code stores every tile).
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // The row pointers stay in their stored type until cols() (a widening right
 // after the load would wait for it there).

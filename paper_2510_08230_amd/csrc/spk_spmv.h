@@ -97,6 +97,30 @@ __device__ __forceinline__ void long_rows(bool lng, const P *__restrict__ rp, in
     __syncthreads();           // s_mask is rewritten by the next tile
 }
 
+// Epilogue operands loaded with the tile: an epilogue that reads a vector at
+// its row (p_i for p.q, b_i for a residual) may provide pre(i), returning
+// that value, and row(i, sum, value).  The tile loop then issues the load
+// beside the tile's DMA, whose wait covers it, instead of after the row sum,
+// where it would add a memory round trip to every tile.
+template <class Epi, class = void>
+struct HasPre : std::false_type {};
+template <class Epi>
+struct HasPre<Epi, std::void_t<decltype(std::declval<const Epi &>().pre(int64_t(0)))>> : std::true_type {};
+
+struct NoPre {};
+
+template <class Epi>
+__device__ __forceinline__ auto pre_of(const Epi &epi, int64_t i) {
+    if constexpr (HasPre<Epi>::value) return epi.pre(i);
+    else return NoPre{};
+}
+
+template <class Epi, class C, class Pv>
+__device__ __forceinline__ void emit_row(Epi &epi, int64_t i, C sum, const Pv &pv) {
+    if constexpr (std::is_same_v<Pv, NoPre>) epi.row(i, sum);
+    else epi.row(i, sum, pv);
+}
+
 // LDS-staged row tiles: DMA the tile's values and columns into LDS, then one
 // thread per row reduces from LDS while gathering x.  Occupancy (several
 // workgroups per CU) overlaps one workgroup's DMA with another's gathers.
@@ -128,22 +152,24 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
         const bool more = after.valid();
         const int64_t r1 = min(cur.r0 + static_cast<int64_t>(kTileRows), n);
         const int64_t row = cur.r0 + threadIdx.x;
-        const int64_t s = static_cast<int64_t>(cur.s), e = static_cast<int64_t>(cur.e);
-        const int64_t a = static_cast<int64_t>(cur.a), b = static_cast<int64_t>(cur.b);
+        const int64_t s = cur.first(), e = cur.end();
+        const int64_t a = cur.lo(), b = cur.hi();
         const bool lng = LR && row < r1 && b - a > kLongRow;
         if (e - s <= kStreamCap) {
             dma_chunks<V>(va, s, e, nnz, lv, nt);
             dma_chunks<I>(ci, s, e, nnz, lc, nt);
             if (more && pf) nxt.load(rp, n, after.tile());
-            __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA (and the prefetch) has landed
+            const auto pv = pre_of(epi, row < r1 ? row : r1 - 1);   // every lane loads
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA (and the prefetches) has landed
             __syncthreads();                 // ... and every other wave's
             const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
             const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
-            if (row < r1 && !lng) epi.row(row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row));
-            __syncthreads();                 // LDS free for the next tile
+            if (row < r1 && !lng) emit_row(epi, row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row), pv);
+            lds_barrier();                   // LDS free for the next tile (the row's stores stay in flight)
         } else {
             if (more && pf) nxt.load(rp, n, after.tile());
-            if (row < r1 && !lng) epi.row(row, row_from_global<V, I, C>(va, ci, a, b, gx, nt, col, row));
+            const auto pv = pre_of(epi, row < r1 ? row : r1 - 1);
+            if (row < r1 && !lng) emit_row(epi, row, row_from_global<V, I, C>(va, ci, a, b, gx, nt, col, row), pv);
         }
         if constexpr (LR)
             long_rows<C>(lng, rp, n, cur.r0, gx, col, epi, [&](int64_t k) { return ldv(va + k, nt); },

@@ -262,6 +262,32 @@ def test_fp64_requests_match_plain_cg(spk, ctx):
         assert log.true_resnorm <= 1e-14 * np.linalg.norm(b) * 1.01
 
 
+def test_fp64_edge_requests(spk, ctx):
+    """FP64 requests: b = 0 gives x = 0 (converged, whatever x0 held); a
+    nonzero initial guess is refined from its own residual and meets the
+    stop test; max_iters = 0 stops at once with x0 untouched."""
+    srv = server(spk, ctx, precision=spk.PREC_FP64)
+    A, b, M, bd, x = make_request(spk, 5000, 801)
+    x.fill_(3.0)
+    tz = spk.spk_server_submit(srv, M, to_dev(np.zeros(5000)), x)
+    A2, b2, M2, bd2, x2 = make_request(spk, 20000, 802)
+    x0 = inputs.vec(20000, 802, 9)
+    x2.copy_(to_dev(x0))
+    tg = spk.spk_server_submit(srv, M2, bd2, x2)
+    cap = server_cfg(spk, spk.PREC_FP64)
+    cap.max_iters = 0
+    A3, b3, M3, bd3, x3 = make_request(spk, 3000, 803)
+    x3.fill_(0.5)
+    tc = spk.spk_server_submit(srv, M3, bd3, x3, cap)
+    res = wait_all(spk, srv, [tz, tg, tc])
+    spk.spk_server_destroy(srv)
+    assert res[tz][0] == spk.OK and res[tz][1].stop_reason == spk.STOP_CONVERGED and not x.cpu().numpy().any()
+    assert res[tg][0] == spk.OK and res[tg][1].stop_reason == spk.STOP_CONVERGED
+    check_oracle(A2, b2, x2.cpu().numpy())
+    assert res[tc][0] == spk.OK and res[tc][1].stop_reason == spk.STOP_MAX_ITERS
+    assert res[tc][1].iterations == 0 and np.all(x3.cpu().numpy() == 0.5)
+
+
 def test_precisions_share_a_server(spk, ctx):
     """FP64 and mixed requests in one server (per-request precision): each
     result is bitwise the one the same request gets alone."""
