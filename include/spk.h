@@ -179,7 +179,7 @@ typedef struct {
     int32_t fused_loop;        /* 1 = CG runs one launch per iteration: the SpMV step also forms
                                   the direction from the previous r, q and p at every gathered
                                   column and updates x, r and p (0 = three launches) */
-    int32_t reserved;
+    int32_t nontemporal;       /* 1 = the row-tile SpMV streams the matrix with non-temporal loads */
 } spk_plan_info;
 
 /* Fill cfg with the defaults documented in spk_solver_cfg. */

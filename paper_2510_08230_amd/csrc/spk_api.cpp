@@ -219,6 +219,7 @@ bool stream_ok(const CsrDev &A) {
 SpmvTune make_tune(spk_ctx ctx, const CsrDev &A, int kind, int lanes_log2, int remap, int nt, int pf, int bpc,
                    int codes = 0, int pack = 0) {
     SpmvTune t{kind, lanes_log2, 1, remap, nt, pf, 0};
+    t.cus = ctx->num_cu;
     t.codes = kind == 0 && codes && A.codes;
     t.pack = t.codes && pack && A.rowpack;
     const int occ = spk::spmv_blocks_per_cu(A, t);
@@ -409,6 +410,7 @@ spk_status choose_tune(spk_plan pl, const void *x, void *y, int use = TUNE_PLAIN
     pl->info.lanes = 1 << pl->tune.lanes_log2;
     pl->info.grid = pl->tune.grid;
     pl->info.xcd_remap = pl->tune.xcd_remap;
+    pl->info.nontemporal = pl->tune.nt;
     pl->info.col_codes =
         (pl->tune.kind == 0 && pl->tune.codes && A.codes) ? ((pl->tune.pack && A.rowpack) ? 3 : 1) : 0;
     return SPK_OK;

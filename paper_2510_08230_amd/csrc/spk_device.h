@@ -54,8 +54,10 @@ struct TileIter {
     uint32_t k, xcd;           // block size and XCD (remap >= 2)
     int shift;                 // log2 k when k is a power of two, else -1
     int mode;
-    __device__ TileIter(int64_t T64, int remap) {
-        const uint32_t G = gridDim.x, b = blockIdx.x, T = static_cast<uint32_t>(T64);
+    __device__ TileIter(int64_t T64, int remap) : TileIter(T64, remap, gridDim.x) {}
+    // G: the workgroups that walk the tiles (the first G of the grid)
+    __device__ TileIter(int64_t T64, int remap, uint32_t G) {
+        const uint32_t b = blockIdx.x, T = static_cast<uint32_t>(T64);
         mode = (G >= kNumXcd && remap >= 1) ? (remap == 1 ? 1 : 2) : 0;
         k = remap >= 2 ? static_cast<uint32_t>(remap) : 1u;
         shift = (k & (k - 1)) == 0 ? __builtin_ctz(k) : -1;

@@ -116,6 +116,7 @@ struct SpmvTune {
     int bpc;         // workgroups per CU the grid was sized for
     int codes = 0;   // LDS tiles: 1 = read the matrix's one-byte column codes (CsrDev::codes)
     int pack = 0;    // with codes: 1 = read the packed row pointers (CsrDev::rowpack)
+    int cus = 0;     // compute units of the device (0 = unknown: every workgroup walks tiles)
 };
 
 // Device CSR view with runtime-typed arrays.

@@ -16,6 +16,7 @@
 
 #include "spk_device.h"
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -136,11 +137,11 @@ template <typename V, typename P, typename I, typename C, bool LR, class Gx, cla
 __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                const I *__restrict__ ci, const V *__restrict__ va, const Gx &gx,
                                                int remap, int nt, int pf, Epi &epi, u32x4 *lv, u32x4 *lc,
-                                               const D &col = D{}) {
+                                               const D &col = D{}, uint32_t walkers = 0) {
     const V *sv = reinterpret_cast<const V *>(lv);
     const I *sc = reinterpret_cast<const I *>(lc);
     const int64_t T = (n + kTileRows - 1) / kTileRows;
-    TileIter it(T, remap);
+    TileIter it(T, remap, walkers ? walkers : gridDim.x);
     if (!it.valid()) return;
     // pf = 1: the row pointers of the next tile are loaded while the current
     // tile's entries stream in, so each tile starts with its bounds at hand.
@@ -196,13 +197,24 @@ __device__ __forceinline__ auto gather_of(const Epi &epi, const X *x) {
     else return PlainGather<X, C>{x};
 }
 
+// walkers: the workgroups that walk the tiles (0 = all).  A grid sized for
+// the autotuned kernel can exceed what another epilogue's kernel holds
+// resident; the workgroups past the resident count would then start only
+// when the first ones finish and walk their tiles alone.  They take no
+// tiles instead and store zero partials, so a consumer still sums one
+// partial per launched workgroup and gets the same total.
 template <typename V, typename P, typename I, typename X, typename C, class Epi, bool LR = false>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const V *__restrict__ va,
                                                         const X *__restrict__ x, int remap, int nt, int pf,
-                                                        Epi epi_in) {
+                                                        int walkers, Epi epi_in) {
     Epi epi = epi_in;
     if (epi.skip()) return;
+    const uint32_t W = walkers > 0 && static_cast<uint32_t>(walkers) < gridDim.x ? walkers : gridDim.x;
+    if (blockIdx.x >= W) {   // uniform
+        epi.finish();
+        return;
+    }
     __shared__ u32x4 lv[Chunks<V>::LDS];
     __shared__ u32x4 lc[Chunks<I>::LDS];
     if constexpr (std::is_same_v<I, Code8>) {
@@ -212,10 +224,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, 
         for (int i = threadIdx.x; i < kCodeDict; i += kBlock) dict[i] = g[i];
         __syncthreads();
         spmv_tiles_lds<V, P, I, C, LR>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
-                                       ColCoded{dict});
+                                       ColCoded{dict}, W);
     } else {
         spmv_tiles_lds<V, P, I, C, LR>(n, nnz, rp, ci, va, gather_of<X, C>(epi, x), remap, nt, pf, epi, lv, lc,
-                                       ColPlain{});
+                                       ColPlain{}, W);
     }
     epi.finish();
 }
@@ -271,9 +283,23 @@ hipError_t dispatch_idx(const CsrDev &A, F &&f) {
 template <class Ptr>
 using pointee_t = std::remove_const_t<std::remove_pointer_t<Ptr>>;
 
+// Workgroups of kernel Kern resident on one CU at once (asked once per
+// kernel; 0 if the runtime cannot tell).
+template <auto Kern>
+int resident_per_cu() {
+    static const int blocks = [] {
+        int b = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, Kern, kBlock, 0) == hipSuccess ? b : 0;
+    }();
+    return blocks;
+}
+
 template <typename V, typename X, typename C, class Epi>
 hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const Epi &epi, hipStream_t s) {
     if (A.n_rows == 0) return hipSuccess;
+    // tile walkers of a row-tile kernel: the grid, or as many workgroups as
+    // that kernel holds resident on the device if fewer
+    auto walkers = [&](int per_cu) { return t.cus > 0 && per_cu > 0 ? std::min(t.grid, t.cus * per_cu) : 0; };
     return dispatch_idx(A, [&](auto rp, auto ci) {
         using P = pointee_t<decltype(rp)>;
         using I = pointee_t<decltype(ci)>;
@@ -292,18 +318,21 @@ hipError_t launch_family(const CsrDev &A, const SpmvTune &t, const X *x, const E
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x, 0,
                                t.xcd_remap, t.nt, epi);
         } else if (coded && t.pack && A.rowpack) {
-            hipLaunchKernelGGL((k_spmv_stream<V, RowPack, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz,
-                               static_cast<const RowPack *>(A.rowpack), static_cast<const Code8 *>(A.codes), va, x,
-                               t.xcd_remap, t.nt, t.pf, epi);
+            constexpr auto K = k_spmv_stream<V, RowPack, Code8, X, C, Epi>;
+            hipLaunchKernelGGL(K, grid, block, 0, s, A.n_rows, A.nnz, static_cast<const RowPack *>(A.rowpack),
+                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, walkers(resident_per_cu<K>()), epi);
         } else if (coded) {
-            hipLaunchKernelGGL((k_spmv_stream<V, P, Code8, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp,
-                               static_cast<const Code8 *>(A.codes), va, x, t.xcd_remap, t.nt, t.pf, epi);
+            constexpr auto K = k_spmv_stream<V, P, Code8, X, C, Epi>;
+            hipLaunchKernelGGL(K, grid, block, 0, s, A.n_rows, A.nnz, rp, static_cast<const Code8 *>(A.codes), va, x,
+                               t.xcd_remap, t.nt, t.pf, walkers(resident_per_cu<K>()), epi);
         } else if (t.kind == 0 && lr) {
-            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi, true>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci,
-                               va, x, t.xcd_remap, t.nt, t.pf, epi);
+            constexpr auto K = k_spmv_stream<V, P, I, X, C, Epi, true>;
+            hipLaunchKernelGGL(K, grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x, t.xcd_remap, t.nt, t.pf,
+                               walkers(resident_per_cu<K>()), epi);
         } else if (t.kind == 0) {
-            hipLaunchKernelGGL((k_spmv_stream<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x,
-                               t.xcd_remap, t.nt, t.pf, epi);
+            constexpr auto K = k_spmv_stream<V, P, I, X, C, Epi>;
+            hipLaunchKernelGGL(K, grid, block, 0, s, A.n_rows, A.nnz, rp, ci, va, x, t.xcd_remap, t.nt, t.pf,
+                               walkers(resident_per_cu<K>()), epi);
         } else {
             hipLaunchKernelGGL((k_spmv_vector<V, P, I, X, C, Epi>), grid, block, 0, s, A.n_rows, rp, ci, va, x,
                                t.lanes_log2, t.xcd_remap, t.nt, epi);

@@ -74,7 +74,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("spmv_kernel", ctypes.c_int32), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("exec_mode", ctypes.c_int32), ("chunk_iters", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("col_codes", ctypes.c_int32), ("spmv_ms", ctypes.c_double),
-                ("fused_loop", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fused_loop", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
