@@ -73,6 +73,7 @@ struct EpiInit {
 // q = A p (stored in T); partials of p.q accumulated in FP64 from the stored values.
 template <typename T>
 struct EpiPq {
+    static constexpr bool kHotLoop = true;   // the CG loop's product (register budget of its kernel)
     T *q;
     const T *p;
     const SolveState *st;

@@ -197,6 +197,21 @@ __device__ __forceinline__ auto gather_of(const Epi &epi, const X *x) {
     else return PlainGather<X, C>{x};
 }
 
+// Register budget of the row-tile kernel, as waves per SIMD it must fit: the
+// CG loop's product on coded FP64 tiles with packed rows (an epilogue that
+// declares kHotLoop) is held to seven, where it otherwise lands one
+// register above the budget and loses a workgroup per CU to it; every other
+// instance is left to the compiler.
+template <class Epi, class = void>
+struct HotLoop : std::false_type {};
+template <class Epi>
+struct HotLoop<Epi, std::void_t<decltype(Epi::kHotLoop)>> : std::bool_constant<Epi::kHotLoop> {};
+
+template <typename V, typename P, class Epi>
+constexpr int spmv_min_waves() {
+    return std::is_same_v<V, double> && std::is_same_v<P, RowPack> && HotLoop<Epi>::value ? 7 : 1;
+}
+
 // walkers: the workgroups that walk the tiles (0 = all).  A grid sized for
 // the autotuned kernel can exceed what another epilogue's kernel holds
 // resident; the workgroups past the resident count would then start only
@@ -204,7 +219,7 @@ __device__ __forceinline__ auto gather_of(const Epi &epi, const X *x) {
 // tiles instead and store zero partials, so a consumer still sums one
 // partial per launched workgroup and gets the same total.
 template <typename V, typename P, typename I, typename X, typename C, class Epi, bool LR = false>
-__global__ __launch_bounds__(kBlock) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spmv_min_waves<V, P, Epi>()))) void k_spmv_stream(int64_t n, int64_t nnz, const P *__restrict__ rp,
                                                         const I *__restrict__ ci, const V *__restrict__ va,
                                                         const X *__restrict__ x, int remap, int nt, int pf,
                                                         int walkers, Epi epi_in) {
