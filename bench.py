@@ -666,6 +666,14 @@ def large(args):
         best = min(spk.spk_stream_copy(ctx, src, dst, nb) for _ in range(5))
         copy_calib = {"bytes": 2 * nb, "ms": best, "GBs": 2 * nb / (best * 1e-3) / 1e9}
         del src, dst
+        # and over one FP32 vector of this size each way: the copy rate falls
+        # with the buffer size (address translation over tens of GB)
+        nv = n * 4 // 16 * 16
+        src = torch.empty(nv // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        best = min(spk.spk_stream_copy(ctx, src, dst, nv) for _ in range(3))
+        copy_calib["vector_size"] = {"bytes": 2 * nv, "ms": best, "GBs": 2 * nv / (best * 1e-3) / 1e9}
+        del src, dst
     spk.spk_finalize(ctx)
     nvec = 8 if info.get("fused_loop") else 2
     bytes_spmv = nnz * 4 + index_bytes(info, n, nnz, 8) + nvec * n * 4
@@ -693,7 +701,26 @@ def large(args):
         out["copy_calib"] = copy_calib
         if achieved:
             out["roofline"]["frac_vs_copy"] = achieved / copy_calib["GBs"]
+            out["roofline"]["frac_vs_copy_vector_size"] = achieved / copy_calib["vector_size"]["GBs"]
+    out["roofline"]["traffic"] = large_traffic(N, info)
     print(json.dumps(out), flush=True)
+
+
+def large_traffic(N, tiling):
+    """Counter traffic (bytes per inner product) of the large instance from
+    its rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when that summary is
+    for other kernel sources, another size or another launch shape."""
+    path = os.path.join(ROOT, "profiles", "spmv_pq32_cg_mixed_fp32_stencil7_N1048_traffic.json")
+    if N != 1048 or not os.path.exists(path):
+        return None
+    from paper_2510_08230_amd import profsum
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_digest") != profsum.kernel_digest():
+        return None
+    if d.get("tiling") is not None and any(d["tiling"][k] != tiling.get(k) for k in profsum.TILING_KEYS):
+        return None
+    return d["traffic_bytes"]
 
 
 def serving_block(args, ctx, with_oracle=True):
@@ -906,6 +933,14 @@ def serve(args):
         dst = torch.empty_like(src)
         best = min(spk.spk_stream_copy(ctx, src, dst, nb) for _ in range(5))
         copy_calib = {"bytes": 2 * nb, "ms": best, "GBs": 2 * nb / (best * 1e-3) / 1e9}
+        del src, dst
+        # and over one FP32 vector of this size each way: the copy rate falls
+        # with the buffer size (address translation over tens of GB)
+        nv = n * 4 // 16 * 16
+        src = torch.empty(nv // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        best = min(spk.spk_stream_copy(ctx, src, dst, nv) for _ in range(3))
+        copy_calib["vector_size"] = {"bytes": 2 * nv, "ms": best, "GBs": 2 * nv / (best * 1e-3) / 1e9}
         del src, dst
     spk.spk_finalize(ctx)
     out = {
