@@ -360,8 +360,15 @@ size_t spk_server_request_bytes(int64_t n, int64_t nnz);
 
 /* As spk_server_request_bytes for a request of the given precision
  * (SPK_PREC_MIXED_FP32, or SPK_PREC_FP64: four FP64 vectors and no value
- * copy); 0 for a precision the server does not run. */
+ * copy) on 32-bit indices; 0 for a precision the server does not run. */
 size_t spk_server_request_bytes_prec(int32_t precision, int64_t n, int64_t nnz);
+
+/* Workspace bytes of a request of matrix A (its sizes and index types; the
+ * pointers are not read) at the given precision: as
+ * spk_server_request_bytes_prec, plus 32-bit copies of 64-bit row pointers
+ * (n + 1) and columns (nnz), each rounded up to 256 bytes.  0 for index
+ * types or a precision the server does not take. */
+size_t spk_server_request_bytes_csr(const spk_csr *A, int32_t precision);
 
 /* Create a server on the context's device with an HBM budget for request
  * workspace and at most max_slots live requests.  cfg (the default of every
@@ -374,12 +381,15 @@ size_t spk_server_request_bytes_prec(int32_t precision, int64_t n, int64_t nnz);
 spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_slots, const spk_solver_cfg *cfg,
                              spk_server *out);
 
-/* Queue a solve of A x = b (device pointers; A square with int32 row_ptr and
- * col_idx and F64 values; x holds the initial guess and receives the
- * solution).  The caller keeps A, b, x alive and untouched until the request
- * is done.  *ticket identifies it.  Errors: INVALID_ARG, UNSUPPORTED (index or
- * value types), BUDGET (the request alone exceeds the budget).  A malformed
- * CSR is detected on the GPU before admission and reported by poll. */
+/* Queue a solve of A x = b (device pointers; A square with int32 or int64
+ * row_ptr and col_idx and F64 values; x holds the initial guess and
+ * receives the solution).  64-bit indices are narrowed into the request's
+ * workspace at admission, so n and nnz must stay below 2^31 - 1.  The caller
+ * keeps A, b, x alive and untouched until the request is done.  *ticket
+ * identifies it.  Errors: INVALID_ARG, UNSUPPORTED (index or value types,
+ * 64-bit indices past 2^31 - 1), BUDGET (the request alone exceeds the
+ * budget).  A malformed CSR is detected on the GPU before admission and
+ * reported by poll. */
 spk_status spk_server_submit(spk_server srv, const spk_csr *A, const void *b, void *x, uint64_t *ticket);
 
 /* As spk_server_submit, with this request's own solver configuration (its

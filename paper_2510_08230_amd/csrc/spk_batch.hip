@@ -287,7 +287,22 @@ __global__ __launch_bounds__(kBlock) void k_round_f32(int64_t nnz, const double 
         dst[i] = static_cast<float>(src[i]);
 }
 
+// dst[i] = src[i] for 64-bit indices known to fit 32 bits (a validated
+// request's row pointers or columns, below 2^31).
+__global__ __launch_bounds__(kBlock) void k_narrow_i32(int64_t count, const int64_t *__restrict__ src,
+                                                       int32_t *__restrict__ dst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < count; i += stride)
+        dst[i] = static_cast<int32_t>(src[i]);
+}
+
 }  // namespace
+
+hipError_t launch_narrow_i32(int64_t count, const int64_t *src, int32_t *dst, int grid, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_narrow_i32, dim3(grid), dim3(kBlock), 0, s, count, src, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_tick(const BatchDev &B, hipStream_t s) {
     hipLaunchKernelGGL(k_b_spmv, dim3(B.tile_grid), dim3(kBlock), 0, s, B);

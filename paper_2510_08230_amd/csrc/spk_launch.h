@@ -185,6 +185,7 @@ namespace spk {
 hipError_t launch_batch_tick(const BatchDev &B, hipStream_t s);
 // FP64 -> FP32 values of a newly admitted request.
 hipError_t launch_round_f32(int64_t nnz, const double *src, float *dst, int grid, hipStream_t s);
+hipError_t launch_narrow_i32(int64_t count, const int64_t *src, int32_t *dst, int grid, hipStream_t s);
 int batch_tile_blocks_per_cu();
 
 }  // namespace spk

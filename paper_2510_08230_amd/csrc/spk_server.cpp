@@ -37,13 +37,16 @@ int64_t tiles_of(int64_t n) { return (n + spk::kTileRows - 1) / spk::kTileRows; 
 size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Workspace one request needs: r, p, q, d (n each; FP32 for a mixed
-// request, FP64 for an FP64 one), the FP32 value copy (nnz; mixed only) and
-// the per-tile partial sums.
-size_t request_bytes(int64_t n, int64_t nnz, bool fp64) {
+// request, FP64 for an FP64 one), the FP32 value copy (nnz; mixed only), the
+// per-tile partial sums, and 32-bit copies of 64-bit row pointers (n + 1)
+// and columns (nnz): the tick kernels read 32-bit indices.
+size_t request_bytes(int64_t n, int64_t nnz, bool fp64, bool ptr64 = false, bool idx64 = false) {
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const size_t vec = align256(es * static_cast<size_t>(std::max<int64_t>(n, 1)));
     const size_t copy = fp64 ? 0 : align256(sizeof(float) * static_cast<size_t>(std::max<int64_t>(nnz, 1)));
-    return 4 * vec + copy +
+    const size_t rp32 = ptr64 ? align256(sizeof(int32_t) * static_cast<size_t>(n + 1)) : 0;
+    const size_t ci32 = idx64 ? align256(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(nnz, 1))) : 0;
+    return 4 * vec + copy + rp32 + ci32 +
            align256(sizeof(double) * spk::kPartSites * static_cast<size_t>(std::max<int64_t>(tiles_of(n), 1)));
 }
 
@@ -56,6 +59,7 @@ struct Request {
     double tau = 0.0, tau_in = 0.0;   // this request's stop tests
     int64_t max_iters = 0, max_outer = 0;
     bool fp64 = false;                 // SPK_PREC_FP64 (else SPK_PREC_MIXED_FP32)
+    bool ptr64 = false, idx64 = false; // 64-bit row pointers / columns (narrowed at admission)
 };
 
 // The LDS tiles stage a tile's values and columns with 16-byte DMA loads,
@@ -179,7 +183,7 @@ bool admit(spk_server srv) {
     while (!srv->waiting.empty()) {
         Request &r = srv->waiting.front();
         const int64_t n = r.A.n_rows;
-        const size_t bytes = request_bytes(n, r.A.nnz, r.fp64);
+        const size_t bytes = request_bytes(n, r.A.nnz, r.fp64, r.ptr64, r.idx64);
         const int64_t t = tiles_of(n);
         int free_slot = -1;
         for (int i = 0; i < srv->max_slots; ++i)
@@ -214,6 +218,7 @@ bool admit(spk_server srv) {
         D.tiles = t;
         D.rp = static_cast<const int32_t *>(req.A.row_ptr);
         D.ci = static_cast<const int32_t *>(req.A.col_idx);
+        int32_t *rp32 = nullptr, *ci32 = nullptr;
         D.va64 = static_cast<const double *>(req.A.values);
         D.fp64 = req.fp64 ? 1 : 0;
         float *va32 = nullptr;
@@ -230,6 +235,10 @@ bool admit(spk_server srv) {
             va32 = reinterpret_cast<float *>(carve(sizeof(float) * static_cast<size_t>(std::max<int64_t>(req.A.nnz, 1))));
         }
         D.va32 = va32;
+        if (req.ptr64) D.rp = rp32 = reinterpret_cast<int32_t *>(carve(sizeof(int32_t) * static_cast<size_t>(n + 1)));
+        if (req.idx64)
+            D.ci = ci32 = reinterpret_cast<int32_t *>(
+                carve(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(req.A.nnz, 1))));
         D.part = reinterpret_cast<double *>(carve(sizeof(double) * spk::kPartSites * static_cast<size_t>(std::max<int64_t>(t, 1))));
         D.b = req.b;
         D.x = req.x;
@@ -245,7 +254,13 @@ bool admit(spk_server srv) {
         S.phase = spk::PH_OUTER;
         S.next_phase = spk::PH_OUTER;
         bool ok = true;
-        if (req.A.nnz > 0 && !req.fp64)
+        if (rp32)
+            ok = hip_ok(srv, spk::launch_narrow_i32(n + 1, static_cast<const int64_t *>(req.A.row_ptr), rp32,
+                                                    srv->num_cu * 4, srv->stream), "row pointers");
+        if (ok && ci32)
+            ok = hip_ok(srv, spk::launch_narrow_i32(req.A.nnz, static_cast<const int64_t *>(req.A.col_idx), ci32,
+                                                    srv->num_cu * 4, srv->stream), "columns");
+        if (ok && req.A.nnz > 0 && !req.fp64)
             ok = hip_ok(srv, spk::launch_round_f32(req.A.nnz, D.va64, va32, srv->num_cu * 4, srv->stream), "round");
         ok = ok && hip_ok(srv, hipMemcpyAsync(srv->d_desc + free_slot, &D, sizeof(D), hipMemcpyHostToDevice, srv->stream),
                           "desc upload");
@@ -414,6 +429,15 @@ size_t spk_server_request_bytes_prec(int32_t precision, int64_t n, int64_t nnz) 
     return 0;
 }
 
+size_t spk_server_request_bytes_csr(const spk_csr *A, int32_t precision) {
+    if (!A || A->n_rows < 0 || A->nnz < 0) return 0;
+    if ((A->ptr_type != SPK_I32 && A->ptr_type != SPK_I64) || (A->idx_type != SPK_I32 && A->idx_type != SPK_I64))
+        return 0;
+    if (precision != SPK_PREC_FP64 && precision != SPK_PREC_MIXED_FP32) return 0;
+    return request_bytes(A->n_rows, A->nnz, precision == SPK_PREC_FP64, A->ptr_type == SPK_I64,
+                         A->idx_type == SPK_I64);
+}
+
 spk_status spk_server_create(spk_ctx ctx, size_t hbm_budget_bytes, int32_t max_slots, const spk_solver_cfg *cfg,
                              spk_server *out) {
     if (!ctx || !out || max_slots < 1 || max_slots > 65536 || hbm_budget_bytes == 0) return SPK_ERR_INVALID_ARG;
@@ -501,10 +525,17 @@ spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b
     if (cfg && !cfg_supported(c)) return SPK_ERR_UNSUPPORTED;
     if (cfg && !cfg_valid(c)) return SPK_ERR_INVALID_ARG;
     if (A->n_rows != A->n_cols || A->n_rows < 1 || A->nnz < 0) return SPK_ERR_INVALID_ARG;
-    if (A->ptr_type != SPK_I32 || A->idx_type != SPK_I32 || A->val_type != SPK_F64) return SPK_ERR_UNSUPPORTED;
+    if ((A->ptr_type != SPK_I32 && A->ptr_type != SPK_I64) || (A->idx_type != SPK_I32 && A->idx_type != SPK_I64) ||
+        A->val_type != SPK_F64)
+        return SPK_ERR_UNSUPPORTED;
+    // the tick kernels read 32-bit indices: 64-bit ones are narrowed, so
+    // their values (at most n and nnz) must fit
+    if ((A->ptr_type == SPK_I64 || A->idx_type == SPK_I64) && (A->n_rows >= INT32_MAX || A->nnz >= INT32_MAX))
+        return SPK_ERR_UNSUPPORTED;
     if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values)) || !b || !x) return SPK_ERR_INVALID_ARG;
     const bool fp64 = c.precision == SPK_PREC_FP64;
-    if (request_bytes(A->n_rows, A->nnz, fp64) > srv->budget || tiles_of(A->n_rows) > srv->cap_tiles)
+    const bool ptr64 = A->ptr_type == SPK_I64, idx64 = A->idx_type == SPK_I64;
+    if (request_bytes(A->n_rows, A->nnz, fp64, ptr64, idx64) > srv->budget || tiles_of(A->n_rows) > srv->cap_tiles)
         return SPK_ERR_BUDGET;
     if (tiles_of(A->n_rows) > INT32_MAX) return SPK_ERR_UNSUPPORTED;
     Request r;
@@ -517,6 +548,8 @@ spk_status spk_server_submit_cfg(spk_server srv, const spk_csr *A, const void *b
     r.max_iters = c.max_iters;
     r.max_outer = c.max_outer;
     r.fp64 = fp64;
+    r.ptr64 = ptr64;
+    r.idx64 = idx64;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stopping) return SPK_ERR_INVALID_ARG;

@@ -117,6 +117,7 @@ _SIGS = {
     "spk_noalloc_max_rows": (_i64, []),
     "spk_server_request_bytes": (_sz, [_i64, _i64]),
     "spk_server_request_bytes_prec": (_sz, [_i32, _i64, _i64]),
+    "spk_server_request_bytes_csr": (_sz, [_P(Csr), _i32]),
     "spk_server_create": (ctypes.c_int, [_vp, _sz, _i32, _P(SolverCfg), _P(_vp)]),
     "spk_server_submit": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(ctypes.c_uint64)]),
     "spk_server_submit_cfg": (ctypes.c_int, [_vp, _P(Csr), _vp, _vp, _P(SolverCfg), _P(ctypes.c_uint64)]),
@@ -374,6 +375,13 @@ def spk_server_request_bytes(n: int, nnz: int) -> int:
 
 def spk_server_request_bytes_prec(precision: int, n: int, nnz: int) -> int:
     return int(_lib.spk_server_request_bytes_prec(int(precision), int(n), int(nnz)))
+
+
+def spk_server_request_bytes_csr(A, precision: int) -> int:
+    """Workspace bytes of a request of matrix A (a CsrMatrix, or a Csr
+    descriptor: only its sizes and index types are read)."""
+    desc = A.desc if hasattr(A, "desc") else A
+    return int(_lib.spk_server_request_bytes_csr(ctypes.byref(desc), int(precision)))
 
 
 def _server_check(status, srv):

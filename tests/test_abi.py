@@ -147,3 +147,24 @@ def test_server_request_bytes_by_precision():
         assert spk.spk_server_request_bytes_prec(spk.PREC_FP64, n, nnz) == want
         assert spk.spk_server_request_bytes_prec(spk.PREC_MIXED_FP32, n, nnz) == spk.spk_server_request_bytes(n, nnz)
         assert spk.spk_server_request_bytes_prec(spk.PREC_MIXED_BF16, n, nnz) == 0
+
+
+def test_server_request_bytes_by_index_types():
+    """64-bit row pointers and columns add their 32-bit copies (n + 1 and nnz
+    int32, each rounded up to 256 bytes); types the server does not take: 0."""
+    from paper_2510_08230_amd import spk
+
+    def al(b):
+        return (b + 255) // 256 * 256
+    for n, nnz in [(1, 1), (1000, 7000), (257, 0)]:
+        for ptr in (spk.I32, spk.I64):
+            for idx in (spk.I32, spk.I64):
+                d = spk.Csr(n_rows=n, n_cols=n, nnz=nnz, ptr_type=ptr, idx_type=idx, val_type=spk.F64)
+                for prec in (spk.PREC_FP64, spk.PREC_MIXED_FP32):
+                    want = spk.spk_server_request_bytes_prec(prec, n, nnz)
+                    want += al(4 * (n + 1)) if ptr == spk.I64 else 0
+                    want += al(4 * max(nnz, 1)) if idx == spk.I64 else 0
+                    assert spk.spk_server_request_bytes_csr(d, prec) == want
+                assert spk.spk_server_request_bytes_csr(d, spk.PREC_MIXED_BF16) == 0
+    bad = spk.Csr(n_rows=10, n_cols=10, nnz=5, ptr_type=7, idx_type=spk.I32, val_type=spk.F64)
+    assert spk.spk_server_request_bytes_csr(bad, spk.PREC_FP64) == 0

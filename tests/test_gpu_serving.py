@@ -317,6 +317,48 @@ def test_precisions_share_a_server(spk, ctx):
         check_oracle(A, b, xg)
 
 
+def test_index_types_give_the_same_solution(spk, ctx):
+    """64-bit row pointers and columns are narrowed into the request's
+    workspace at admission: every index-type combination gives the int32
+    request's solution bit for bit, in both precisions, in one server; the
+    budget is charged the copies (spk_server_request_bytes_csr)."""
+    sizes = [3000, 40000, 12345]
+    combos = [(torch.int32, torch.int32), (torch.int64, torch.int64), (torch.int64, torch.int32),
+              (torch.int32, torch.int64)]
+    srv = server(spk, ctx)
+    jobs = []
+    for i, n in enumerate(sizes):
+        A = inputs.randsym(n, 900 + i)
+        b = inputs.rhs(n, 900 + i)
+        bd = to_dev(b)
+        for prec in (spk.PREC_MIXED_FP32, spk.PREC_FP64):
+            for pt, it in combos:
+                M = spk.CsrMatrix(torch.from_numpy(A.row_ptr).to(pt).to(DEV),
+                                  torch.from_numpy(A.col.astype(np.int64)).to(it).to(DEV),
+                                  torch.from_numpy(A.val).to(DEV), n, n)
+                want = spk.spk_server_request_bytes_prec(prec, n, int(A.nnz))
+                want += (4 * (n + 1) + 255) // 256 * 256 if pt == torch.int64 else 0
+                want += (4 * max(int(A.nnz), 1) + 255) // 256 * 256 if it == torch.int64 else 0
+                assert spk.spk_server_request_bytes_csr(M, prec) == want
+                x = torch.zeros(n, dtype=torch.float64, device=DEV)
+                t = spk.spk_server_submit(srv, M, bd, x, server_cfg(spk, prec))
+                jobs.append((i, prec, (pt, it), A, b, M, x, t))
+    res = wait_all(spk, srv, [j[-1] for j in jobs])
+    stats = spk.spk_server_get_stats(srv)
+    spk.spk_server_destroy(srv)
+    assert stats["completed"] == len(jobs) and stats["failed"] == 0
+    first = {}
+    for i, prec, types, A, b, M, x, t in jobs:
+        assert res[t][0] == spk.OK and res[t][1].stop_reason == spk.STOP_CONVERGED
+        xg = x.cpu().numpy()
+        key = (i, prec)
+        if key not in first:
+            first[key] = xg
+            check_oracle(A, b, xg)
+        else:
+            assert np.array_equal(xg.view(np.uint64), first[key].view(np.uint64)), (key, types)
+
+
 def test_fp64_budget_accounting(spk, ctx):
     """FP64 requests are charged their own workspace (4 FP64 vectors, no
     value copy) against the budget."""
