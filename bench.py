@@ -934,14 +934,6 @@ def serve(args):
         best = min(spk.spk_stream_copy(ctx, src, dst, nb) for _ in range(5))
         copy_calib = {"bytes": 2 * nb, "ms": best, "GBs": 2 * nb / (best * 1e-3) / 1e9}
         del src, dst
-        # and over one FP32 vector of this size each way: the copy rate falls
-        # with the buffer size (address translation over tens of GB)
-        nv = n * 4 // 16 * 16
-        src = torch.empty(nv // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        best = min(spk.spk_stream_copy(ctx, src, dst, nv) for _ in range(3))
-        copy_calib["vector_size"] = {"bytes": 2 * nv, "ms": best, "GBs": 2 * nv / (best * 1e-3) / 1e9}
-        del src, dst
     spk.spk_finalize(ctx)
     out = {
         "metric": "hot-path updates/sec and % HBM roofline, 1 MI355X; batched p50/p99 latency",
