@@ -61,6 +61,7 @@ struct spk_ctx_s {
     unsigned *h_flags = nullptr;        // pinned; [2], [3]: the pattern probe's words
     long long *d_probe = nullptr;       // pattern probe: offset table (kCodeSlots) and 4 words
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_snap = nullptr;       // marks a state snapshot copy in the solve loops
     std::map<TuneKey, TuneResult> tune_cache;
     spk::DevicePool dpool;              // plan workspace cache
     spk::PinnedPool hpool;              // pinned status mirrors
@@ -710,28 +711,59 @@ int next_chunk(int prev, int64_t k0, double r0, int64_t k1, double r1, double th
 }
 
 // Run CG iterations of one loop kind until the device-side state stops.
-// The state must already be initialised (init / refinement kernels).
+// The state must already be initialised (init / refinement kernels).  The
+// host reads the state from a snapshot copy queued after the chunks launched
+// so far, and queues the next chunk before waiting for it, so the device is
+// never idle while the host decides: chunk lengths follow the observed
+// residual decay, less the chunk already in flight, and launches past
+// convergence return at once.
 spk_status run_loop(spk_plan pl, int kind, int64_t max_iters, bool graph) {
     spk_ctx ctx = pl->ctx;
     SolveState *st = kind == LOOP_FP32 ? pl->st_in : pl->st;
     SolveState *h = kind == LOOP_FP32 ? pl->h_st_in : pl->h_st;
     const int cfg_chunk = pl->cfg.chunk_iters;
-    spk_status s = pull(ctx, h, st, sizeof(SolveState));
+    auto snapshot = [&]() -> spk_status {
+        SPK_HIP(ctx, hipMemcpyAsync(h, st, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->stream));
+        SPK_HIP(ctx, hipEventRecord(ctx->ev_snap, ctx->stream));
+        return SPK_OK;
+    };
+    auto wait = [&]() -> spk_status {
+        SPK_HIP(ctx, hipEventSynchronize(ctx->ev_snap));
+        return SPK_OK;
+    };
+    spk_status s = snapshot();   // the state before the first chunk
     if (s != SPK_OK) return s;
-    int chunk = cfg_chunk > 0 ? cfg_chunk : 8;
-    int64_t launched = 0, k_prev = 0;
+    int inflight = static_cast<int>(std::max<int64_t>(0, std::min<int64_t>(cfg_chunk > 0 ? cfg_chunk : 8, max_iters)));
+    if (inflight > 0 && (s = run_chunk(pl, kind, inflight, graph)) != SPK_OK) return s;
+    if ((s = wait()) != SPK_OK) return s;
+    if (h->stop != spk::STOP_RUNNING) return SPK_OK;   // the queued chunk's launches return at once
+    int64_t covered = 0;   // iterations the next snapshot follows
+    int64_t k_prev = h->iter;
     double r_prev = h->resnorm > 0.0 ? h->resnorm : 1.0;
-    while (h->stop == spk::STOP_RUNNING) {
-        const int64_t left = max_iters - launched;
-        const int c = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(chunk, left)));
-        if ((s = run_chunk(pl, kind, c, graph)) != SPK_OK) return s;
-        launched += c;
-        if ((s = pull(ctx, h, st, sizeof(SolveState))) != SPK_OK) return s;
+    // before the first rate is known the speculative chunk is short: it only
+    // has to outlast the host's read of the first snapshot
+    int guess = cfg_chunk > 0 ? cfg_chunk : 2;
+    while (true) {
+        covered += inflight;
+        if ((s = snapshot()) != SPK_OK) return s;
+        // launches past max_iters: the fused loop decides its stop one
+        // launch late, and the decision itself takes a launch
+        const int64_t left = max_iters + 2 - covered;
+        const int next = left > 0 ? static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(guess, left))) : 0;
+        if (next > 0 && (s = run_chunk(pl, kind, next, graph)) != SPK_OK) return s;
+        if ((s = wait()) != SPK_OK) return s;
         if (h->stop != spk::STOP_RUNNING) break;
-        if (launched > max_iters + 1) return fail(ctx, SPK_ERR_INTERNAL, "iteration cap passed without stop");
-        if (cfg_chunk <= 0) chunk = next_chunk(chunk, k_prev, r_prev, h->iter, h->resnorm, h->thresh, max_iters - h->iter);
+        if (next == 0) return fail(ctx, SPK_ERR_INTERNAL, "iteration cap passed without stop");
+        if (cfg_chunk > 0) {
+            guess = cfg_chunk;
+        } else {
+            const int rem = next_chunk(std::max(inflight, 1), k_prev, r_prev, h->iter, h->resnorm, h->thresh,
+                                       max_iters - h->iter);
+            guess = std::max(rem - next, 1);
+        }
         k_prev = h->iter;
         r_prev = h->resnorm;
+        inflight = next;
     }
     return SPK_OK;
 }
@@ -863,6 +895,7 @@ spk_status spk_init(int device_id, void *hip_stream, spk_ctx *out) {
             hipSuccess ||
         hipMalloc(&ctx->d_probe, sizeof(long long) * spk::kCodeSlots + 4 * sizeof(unsigned)) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_snap, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&ctx->h_noalloc_st), sizeof(SolveState), hipHostMallocDefault) !=
             hipSuccess) {
         spk_finalize(ctx);
@@ -889,6 +922,7 @@ spk_status spk_finalize(spk_ctx ctx) {
     if (ctx->h_noalloc_st) (void)hipHostFree(ctx->h_noalloc_st);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->ev_snap) (void)hipEventDestroy(ctx->ev_snap);
     delete ctx;
     return SPK_OK;
 }
