@@ -90,13 +90,21 @@ struct Rows {
         acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
     }
     __device__ Gather<T> gather() const { return Gather<T>{ro, qo, po, alpha, beta}; }
+    // the row's own entries of the previous vectors and of x, loaded with
+    // the tile (the tile loop issues pre() beside its DMA)
+    struct Own {
+        T p, q, r, x;
+    };
+    __device__ __forceinline__ Own pre(int64_t i) const { return Own{po[i], qo[i], ro[i], x[i]}; }
     template <class C>
-    __device__ __forceinline__ void row(int64_t i, C s) {
+    __device__ __forceinline__ void row(int64_t i, C s) { row(i, s, pre(i)); }
+    template <class C>
+    __device__ __forceinline__ void row(int64_t i, C s, const Own &o) {
         const T qk = static_cast<T>(s);
-        const T pold = po[i];
-        const T rk = fma(-alpha, qo[i], ro[i]);
+        const T pold = o.p;
+        const T rk = fma(-alpha, o.q, o.r);
         const T pk = fma(beta, pold, rk);
-        x[i] = fma(alpha, pold, x[i]);
+        x[i] = fma(alpha, pold, o.x);
         rn[i] = rk;
         pn[i] = pk;
         qn[i] = qk;
