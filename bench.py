@@ -848,6 +848,10 @@ def serving_block(args, ctx, with_oracle=True):
     nnzv = np.array([A.nnz for A in hosts], np.int64)
     tick_bytes = int(np.sum(sat["iters"] * (nnzv * 8 + (nvec + 1) * 4 + 8 * nvec)
                             + (sat["outer"] + 1) * (nnzv * 12 + (nvec + 1) * 4 + 28 * nvec)))
+    # ... and for the same requests in FP64 (inner products on the FP64 values
+    # and vectors; the residual writes FP64 r, p, d)
+    tick_bytes64 = int(np.sum(sat64["iters"] * (nnzv * 12 + (nvec + 1) * 4 + 16 * nvec)
+                              + (sat64["outer"] + 1) * (nnzv * 12 + (nvec + 1) * 4 + 40 * nvec)))
 
     out = {
         "workload": "serve_randsym_%d_loguniform_1e3_1e6" % len(mats),
@@ -883,6 +887,7 @@ def serving_block(args, ctx, with_oracle=True):
                          "updates_per_s": float(np.sum(nvec * sat64["iters"])) / sat64["makespan"],
                          "iterations_total": int(sat64["iters"].sum()),
                          "outer_total": int(sat64["outer"].sum()),
+                         "tick_spmv_algorithmic_bytes_per_pass": tick_bytes64,
                          "note": "the same requests as FP64 CG in the server, all submitted at once"},
         "speedup_saturated_vs_fp64_batched": sat64["makespan"] / sat["makespan"],
         "accuracy": {"served_max_rel_true_residual": float(max(poi["rres"])),
