@@ -186,17 +186,40 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], double *partials)
 
 // Every thread of the calling workgroup receives the fixed-order sums of the
 // G partials partials[j * stride + b] (b < G) a previous launch stored
-// (identical in every workgroup that calls it).
+// (identical in every workgroup that calls it).  Each thread adds its
+// strided share b = tid, tid + kBlock, ... in increasing b; the loads of up
+// to 8 / NV strides (for every j) are issued before any of them is added, so
+// a thread waits for one round trip per batch rather than per partial.
+// Strides past G load a valid partial (the batch's first) and are not added.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double *partials, int64_t G, int64_t stride, double (&tot)[NV]) {
     __shared__ double sh[NV][kBlock / 64];
+    constexpr int U = NV >= 8 ? 1 : 8 / NV;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double t[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) t[j] = 0.0;
+    for (int64_t b0 = threadIdx.x; b0 < G; b0 += static_cast<int64_t>(U) * kBlock) {
+        double v[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t b = b0 + static_cast<int64_t>(u) * kBlock;
+            const int64_t bc = b < G ? b : b0;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) v[u][j] = partials[static_cast<size_t>(j) * stride + bc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + static_cast<int64_t>(u) * kBlock < G) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) t[j] += v[u][j];
+            }
+        }
+    }
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        double t = 0.0;
-        for (int64_t b = threadIdx.x; b < G; b += kBlock) t += partials[static_cast<size_t>(j) * stride + b];
-        t = wave_sum(t);
-        if (lane == 0) sh[j][wid] = t;
+        const double w = wave_sum(t[j]);
+        if (lane == 0) sh[j][wid] = w;
     }
     __syncthreads();
 #pragma unroll
