@@ -47,11 +47,13 @@ __device__ __forceinline__ C tile_row_sum(const int32_t *__restrict__ rp, const 
         dma_chunks<int32_t>(ci, s, e, nnz, lc, nt);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        __builtin_amdgcn_s_setprio(2);   // row sums ahead of other workgroups' DMA issue
         if (has_row)
             sum = row_from_lds<V, int32_t, C>(reinterpret_cast<const V *>(lv), reinterpret_cast<const int32_t *>(lc), a,
                                               b, s & ~static_cast<int64_t>(Chunks<V>::EPC - 1),
                                               s & ~static_cast<int64_t>(Chunks<int32_t>::EPC - 1),
                                               PlainGather<X, C>{x});
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     } else if (has_row) {
         sum = row_from_global<V, int32_t, C>(va, ci, a, b, PlainGather<X, C>{x}, nt);

@@ -163,9 +163,14 @@ __device__ __forceinline__ void spmv_tiles_lds(int64_t n, int64_t nnz, const P *
             const auto pv = pre_of(epi, row < r1 ? row : r1 - 1);   // every lane loads
             __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA (and the prefetches) has landed
             __syncthreads();                 // ... and every other wave's
+            // The row sums run at raised wave priority, so on a SIMD shared
+            // with workgroups that are issuing or awaiting their next tile's
+            // DMA they finish first and free their LDS sooner.
+            __builtin_amdgcn_s_setprio(2);
             const int64_t s0v = s & ~static_cast<int64_t>(Chunks<V>::EPC - 1);
             const int64_t s0c = s & ~static_cast<int64_t>(Chunks<I>::EPC - 1);
             if (row < r1 && !lng) emit_row(epi, row, row_from_lds<V, I, C>(sv, sc, a, b, s0v, s0c, gx, col, row), pv);
+            __builtin_amdgcn_s_setprio(0);
             lds_barrier();                   // LDS free for the next tile (the row's stores stay in flight)
         } else {
             if (more && pf) nxt.load(rp, n, after.tile());
